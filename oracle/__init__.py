@@ -1,0 +1,165 @@
+"""FP64 CPU oracle for the batched fRG loop integrals -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
+import this package.  The product library (``paper_2412_13043_amd``) never imports, links or
+calls it, and the two share no code: the oracle is plain C (``frg_oracle.c``: long-double
+Newton Gauss-Legendre, libm transcendentals, Neumaier sums), wrapped here with ctypes.
+
+What each function computes, and the passage of arXiv 2412.13043 it follows, is documented
+in ``frg_oracle.h``.  Every function here is pinned by ``tests/test_oracle_*.py`` to closed
+forms, library routines, high-precision (mpmath) evaluations, brute-force Cartesian sums and
+invariances; none is "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "frg_oracle.c")
+_LIB = os.path.join(_HERE, "libfrg_oracle.so")
+
+REG_EXP = 0
+REG_LITIM = 1
+LPA = 1
+TWO_POINT = 2
+THREE_POINT = 3
+
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math) into oracle/libfrg_oracle.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build()
+            lib = ctypes.CDLL(_LIB)
+            D, I, P = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
+            lib.frgo_gauss_legendre.argtypes = [I, D, D, P, P]
+            lib.frgo_regulator.argtypes = [I, D, D]
+            lib.frgo_regulator.restype = D
+            lib.frgo_regulator_dot.argtypes = [I, D, D]
+            lib.frgo_regulator_dot.restype = D
+            lib.frgo_dressing.argtypes = [P, I, D, D, D]
+            lib.frgo_dressing.restype = D
+            lib.frgo_propagator.argtypes = [I, P, I, D, D, D, D, D]
+            lib.frgo_propagator.restype = D
+            lib.frgo_integrate.argtypes = [I, I, I, I, I, D, D, I, P, P, D, P, I, D, D, I, P]
+            lib.frgo_vertex_hyperspherical.argtypes = [I, I, I, I, I, D, D, I, P, P, D, P, I, D, D, P]
+            lib.frgo_lpa_flow_rhs.argtypes = [I, I, D, D, I, I, D, P, P, I, P]
+            lib.frgo_fd_derivatives.argtypes = [P, P, I, P, P]
+            _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def gauss_legendre(n: int, a: float, b: float):
+    lib = _load()
+    x = np.empty(n)
+    w = np.empty(n)
+    if lib.frgo_gauss_legendre(n, a, b, _ptr(x), _ptr(w)) != 0:
+        raise ValueError("invalid Gauss-Legendre request")
+    return x, w
+
+
+def regulator(l2: float, k: float = 1.0, kind: int = REG_EXP) -> float:
+    return _load().frgo_regulator(kind, l2, k)
+
+
+def regulator_dot(l2: float, k: float = 1.0, kind: int = REG_EXP) -> float:
+    return _load().frgo_regulator_dot(kind, l2, k)
+
+
+def dressing(Z, x_min: float, x_max: float, l2: float) -> float:
+    Z = _f64(Z)
+    return _load().frgo_dressing(_ptr(Z), 0 if Z is None else len(Z), x_min, x_max, l2)
+
+
+def propagator(l2, m2, k=1.0, Z=None, x_min=1e-3, x_max=1e3, kind=REG_EXP) -> float:
+    Z = _f64(Z)
+    return _load().frgo_propagator(kind, _ptr(Z), 0 if Z is None else len(Z), x_min, x_max, l2, m2, k)
+
+
+def integrate(family, n_q, q_max, *, d=None, n_x=0, n_phi=0, k=1.0, regulator=REG_EXP, ext=None,
+              m2=None, m2_scalar=0.0, Z=None, x_min=1e-3, x_max=1e3, n_ext=None):
+    """Loop integrals I_e (see frg_oracle.h).  ext: None | p[n] | (p[n], alpha[n])."""
+    if d is None:
+        d = 3 if family == LPA else 4
+    if family == THREE_POINT and ext is not None:
+        p, alpha = ext
+        ext_arr = np.concatenate([_f64(p), _f64(alpha)])
+        n = len(p)
+    elif ext is not None:
+        ext_arr = _f64(ext)
+        n = len(ext_arr)
+    else:
+        ext_arr = None
+        n = None
+    m2a = _f64(m2)
+    if n is None:
+        n = len(m2a) if m2a is not None else int(n_ext)
+    Za = _f64(Z)
+    out = np.empty(n)
+    rc = _load().frgo_integrate(family, d, n_q, n_x, n_phi, q_max, k, regulator, _ptr(ext_arr),
+                                _ptr(m2a), m2_scalar, _ptr(Za), 0 if Za is None else len(Za),
+                                x_min, x_max, n, _ptr(out))
+    if rc != 0:
+        raise ValueError(f"frgo_integrate rejected the arguments (rc={rc})")
+    return out
+
+
+def vertex_hyperspherical(n_legs, n_q, n_t1, n_t2, n_t3, q_max, p1, p2, m2, *, k=1.0,
+                          regulator=REG_EXP, Z=None, x_min=1e-3, x_max=1e3) -> float:
+    p1a = _f64(p1)
+    p2a = _f64(p2)
+    Za = _f64(Z)
+    out = np.empty(1)
+    rc = _load().frgo_vertex_hyperspherical(n_legs, n_q, n_t1, n_t2, n_t3, q_max, k, regulator,
+                                            _ptr(p1a), _ptr(p2a), m2, _ptr(Za),
+                                            0 if Za is None else len(Za), x_min, x_max, _ptr(out))
+    if rc != 0:
+        raise ValueError("frgo_vertex_hyperspherical rejected the arguments")
+    return float(out[0])
+
+
+def fd_derivatives(x, f):
+    xa, fa = _f64(x), _f64(f)
+    d1 = np.empty(len(xa))
+    d2 = np.empty(len(xa))
+    if _load().frgo_fd_derivatives(_ptr(xa), _ptr(fa), len(xa), _ptr(d1), _ptr(d2)) != 0:
+        raise ValueError("fd_derivatives needs n >= 3")
+    return d1, d2
+
+
+def lpa_flow_rhs(rho, u, n_q, q_max, *, d=3, k=1.0, regulator=REG_EXP, n_comp=4, m2_floor=-0.9):
+    rho_a, u_a = _f64(rho), _f64(u)
+    out = np.empty(len(rho_a))
+    rc = _load().frgo_lpa_flow_rhs(d, n_q, q_max, k, regulator, n_comp, m2_floor, _ptr(rho_a),
+                                   _ptr(u_a), len(rho_a), _ptr(out))
+    if rc != 0:
+        raise ValueError("frgo_lpa_flow_rhs rejected the arguments")
+    return out

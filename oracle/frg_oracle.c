@@ -1,0 +1,339 @@
+/*
+ * frg_oracle.c -- plain FP64 CPU oracle for the batched fRG loop integrals.
+ *
+ * TEST INFRASTRUCTURE ONLY (see frg_oracle.h).  Deliberately simple: every node term is
+ * evaluated in full from the definitions, in nested loops, with libm math and
+ * Neumaier-compensated sums.  No hoisting, no blocking, no reordering beyond the sum order.
+ */
+#include "frg_oracle.h"
+
+#include <math.h>
+#include <stddef.h>
+
+#define PI 3.14159265358979323846264338327950288
+
+/* ---------------------------------------------------------------------------------------- */
+/* Neumaier (improved Kahan-Babuska) compensated summation.                                  */
+/* ---------------------------------------------------------------------------------------- */
+typedef struct {
+    double s, c;
+} nsum;
+
+static void nsum_add(nsum *acc, double v) {
+    double t = acc->s + v;
+    if (fabs(acc->s) >= fabs(v))
+        acc->c += (acc->s - t) + v;
+    else
+        acc->c += (v - t) + acc->s;
+    acc->s = t;
+}
+
+static double nsum_get(const nsum *acc) { return acc->s + acc->c; }
+
+/* ---------------------------------------------------------------------------------------- */
+/* Gauss-Legendre: nodes are the roots of P_n, found by Newton's method on the three-term    */
+/* recurrence (n+1) P_{n+1} = (2n+1) x P_n - n P_{n-1}; weights 2/((1-x^2) P_n'(x)^2).       */
+/* Computed in long double, mapped affinely to [a, b].                                      */
+/* ---------------------------------------------------------------------------------------- */
+static void legendre_eval(int n, long double x, long double *pn, long double *dpn) {
+    long double p0 = 1.0L, p1 = x;
+    if (n == 0) {
+        *pn = 1.0L;
+        *dpn = 0.0L;
+        return;
+    }
+    for (int j = 1; j < n; ++j) {
+        long double p2 = ((2.0L * j + 1.0L) * x * p1 - (long double)j * p0) / (j + 1.0L);
+        p0 = p1;
+        p1 = p2;
+    }
+    *pn = p1;
+    /* P_n'(x) = n (x P_n - P_{n-1}) / (x^2 - 1) */
+    *dpn = (long double)n * (x * p1 - p0) / (x * x - 1.0L);
+}
+
+int frgo_gauss_legendre(int n, double a, double b, double *nodes, double *weights) {
+    if (n < 1 || !(b > a) || nodes == NULL || weights == NULL) return -1;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    long double half = 0.5L * ((long double)b - (long double)a);
+    long double mid = 0.5L * ((long double)b + (long double)a);
+    for (int i = 0; i < n; ++i) {
+        /* i-th root from the largest down; Tricomi-type starting value */
+        long double x = cosl(pi * (i + 0.75L) / (n + 0.5L));
+        long double pn = 0, dpn = 1;
+        for (int it = 0; it < 40; ++it) {
+            legendre_eval(n, x, &pn, &dpn);
+            long double dx = pn / dpn;
+            x -= dx;
+            /* quadratic convergence: once a step is this small the next error is negligible */
+            if (fabsl(dx) < 1e-18L) break;
+        }
+        legendre_eval(n, x, &pn, &dpn);
+        long double w = 2.0L / ((1.0L - x * x) * dpn * dpn);
+        /* store ascending: root i (descending order) goes to slot n-1-i */
+        nodes[n - 1 - i] = (double)(mid + half * x);
+        weights[n - 1 - i] = (double)(half * w);
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* Regulators.                                                                               */
+/*   exponential:  R = l2/(exp(y) - 1), y = l2/k^2.  At fixed l2, k dy/dk = -2 y, so         */
+/*   k dR/dk = l2 e^y 2y/(e^y - 1)^2 = 2 k^2 y^2 e^y/(e^y - 1)^2 (> 0).  Both are written     */
+/*   with E = expm1(-y), e = exp(-y): R = k^2 y e/(-E), Rdot = 2 k^2 y^2 e/E^2, so that no   */
+/*   cancellation (small y) or overflow (large y) occurs.                                    */
+/*   flat (Litim):  R = (k^2 - l2) Theta(k^2 - l2), k dR/dk = 2 k^2 Theta(k^2 - l2).         */
+/* ---------------------------------------------------------------------------------------- */
+static void exp_pair(double y, double *e, double *E) {
+    /* e = exp(-y), E = exp(-y) - 1, each to full relative precision */
+    if (y < 0.69314718055994530942) {
+        *E = expm1(-y);
+        *e = 1.0 + *E;
+    } else {
+        *e = exp(-y);
+        *E = *e - 1.0;
+    }
+}
+
+double frgo_regulator(int kind, double l2, double k) {
+    double k2 = k * k;
+    if (l2 < 0.0) l2 = 0.0;
+    if (kind == FRGO_REG_LITIM) return (l2 < k2) ? (k2 - l2) : 0.0;
+    double y = l2 / k2;
+    if (y == 0.0) return k2;
+    double e, E;
+    exp_pair(y, &e, &E);
+    return k2 * y * e / (-E);
+}
+
+double frgo_regulator_dot(int kind, double l2, double k) {
+    double k2 = k * k;
+    if (l2 < 0.0) l2 = 0.0;
+    if (kind == FRGO_REG_LITIM) return (l2 < k2) ? 2.0 * k2 : 0.0;
+    double y = l2 / k2;
+    if (y == 0.0) return 2.0 * k2;
+    double e, E;
+    exp_pair(y, &e, &E);
+    return 2.0 * k2 * y * y * e / (E * E);
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* Dressing: linear interpolation in u = log|l| on a log-uniform grid, clamped at the ends.  */
+/* ---------------------------------------------------------------------------------------- */
+double frgo_dressing(const double *Z, int nZ, double x_min, double x_max, double l2) {
+    if (Z == NULL) return 1.0;
+    if (nZ == 1) return Z[0];
+    double u = (l2 > 0.0) ? 0.5 * log(l2) : -INFINITY;
+    double lmin = log(x_min), lmax = log(x_max);
+    double delta = (lmax - lmin) / (double)(nZ - 1);
+    double s = (u - lmin) / delta;
+    if (!(s > 0.0)) s = 0.0; /* also catches -inf */
+    if (s > (double)(nZ - 1)) s = (double)(nZ - 1);
+    int i = (int)floor(s);
+    if (i > nZ - 2) i = nZ - 2;
+    double f = s - (double)i;
+    return Z[i] + f * (Z[i + 1] - Z[i]);
+}
+
+double frgo_propagator(int reg, const double *Z, int nZ, double x_min, double x_max, double l2,
+                       double m2, double k) {
+    if (l2 < 0.0) l2 = 0.0;
+    double z = frgo_dressing(Z, nZ, x_min, x_max, l2);
+    return 1.0 / (z * l2 + frgo_regulator(reg, l2, k) + m2);
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* Loop integrals.                                                                           */
+/* ---------------------------------------------------------------------------------------- */
+static double omega(int d) {
+    /* surface of the unit sphere in d dimensions: 2 pi^(d/2) / Gamma(d/2) */
+    return 2.0 * pow(PI, 0.5 * d) / tgamma(0.5 * d);
+}
+
+#define MAXN 4096
+
+int frgo_integrate(int family, int d, int n_q, int n_x, int n_phi, double q_max, double k,
+                   int regulator, const double *ext, const double *m2, double m2_scalar,
+                   const double *Z, int nZ, double x_min, double x_max, int n_ext, double *out) {
+    if (n_ext < 0 || out == NULL) return -1;
+    if (n_q < 1 || n_q > MAXN || !(q_max > 0.0) || !(k > 0.0)) return -1;
+    if (Z != NULL && (nZ < 1 || !(x_min > 0.0) || !(x_max > x_min))) return -1;
+    if (family == FRGO_LPA) {
+        if (d < 1) return -1;
+    } else if (family == FRGO_TWO_POINT || family == FRGO_THREE_POINT) {
+        if (d != 4 || n_x < 1 || n_x > MAXN || ext == NULL) return -1;
+        if (family == FRGO_THREE_POINT && (n_phi < 1 || n_phi > MAXN)) return -1;
+    } else {
+        return -1;
+    }
+
+    static __thread double qn[MAXN], qw[MAXN], xn[MAXN], xw[MAXN], fn[MAXN], fw[MAXN];
+    frgo_gauss_legendre(n_q, 0.0, q_max * k, qn, qw);
+    if (family != FRGO_LPA) frgo_gauss_legendre(n_x, -1.0, 1.0, xn, xw);
+    if (family == FRGO_THREE_POINT) frgo_gauss_legendre(n_phi, 0.0, PI, fn, fw);
+
+    for (int e = 0; e < n_ext; ++e) {
+        double mass = m2 ? m2[e] : m2_scalar;
+        nsum total = {0.0, 0.0};
+        if (family == FRGO_LPA) {
+            double pref = omega(d) / pow(2.0 * PI, (double)d);
+            for (int a = 0; a < n_q; ++a) {
+                double q = qn[a], q2 = q * q;
+                double den = q2 + frgo_regulator(regulator, q2, k) + mass;
+                double term = pref * qw[a] * pow(q, (double)(d - 1)) *
+                              frgo_regulator_dot(regulator, q2, k) / (den * den);
+                nsum_add(&total, term);
+            }
+        } else if (family == FRGO_TWO_POINT) {
+            double p = ext[e];
+            double pref = 4.0 * PI / pow(2.0 * PI, 4.0);
+            for (int a = 0; a < n_q; ++a) {
+                nsum inner = {0.0, 0.0};
+                double q = qn[a], q2 = q * q;
+                for (int b = 0; b < n_x; ++b) {
+                    double x = xn[b];
+                    double l2 = q2 + p * p + 2.0 * q * p * x;
+                    double gq = frgo_propagator(regulator, Z, nZ, x_min, x_max, q2, mass, k);
+                    double gl = frgo_propagator(regulator, Z, nZ, x_min, x_max, l2, mass, k);
+                    double term = pref * qw[a] * xw[b] * sqrt(1.0 - x * x) * q2 * q *
+                                  frgo_regulator_dot(regulator, q2, k) * gq * gq * gl;
+                    nsum_add(&inner, term);
+                }
+                nsum_add(&total, nsum_get(&inner));
+            }
+        } else {
+            double p = ext[e], alpha = ext[n_ext + e];
+            double ca = cos(alpha), sa = sin(alpha);
+            double pref = 2.0 * PI / pow(2.0 * PI, 4.0);
+            for (int a = 0; a < n_q; ++a) {
+                nsum mid = {0.0, 0.0};
+                double q = qn[a], q2 = q * q;
+                for (int b = 0; b < n_x; ++b) {
+                    nsum inner = {0.0, 0.0};
+                    double x = xn[b], sx = sqrt(1.0 - x * x);
+                    for (int c = 0; c < n_phi; ++c) {
+                        double phi = fn[c];
+                        double l1 = q2 + p * p + 2.0 * q * p * x;
+                        double l2 = q2 + p * p - 2.0 * q * p * (x * ca + sx * cos(phi) * sa);
+                        double gq = frgo_propagator(regulator, Z, nZ, x_min, x_max, q2, mass, k);
+                        double g1 = frgo_propagator(regulator, Z, nZ, x_min, x_max, l1, mass, k);
+                        double g2 = frgo_propagator(regulator, Z, nZ, x_min, x_max, l2, mass, k);
+                        double term = pref * qw[a] * xw[b] * fw[c] * sx * sin(phi) * q2 * q *
+                                      frgo_regulator_dot(regulator, q2, k) * gq * gq * g1 * g2;
+                        nsum_add(&inner, term);
+                    }
+                    nsum_add(&mid, nsum_get(&inner));
+                }
+                nsum_add(&total, nsum_get(&mid));
+            }
+        }
+        out[e] = nsum_get(&total);
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* Hyperspherical reference rule (rotation-invariance pin).                                  */
+/* q = |q| (cos t1, sin t1 cos t2, sin t1 sin t2 cos t3, sin t1 sin t2 sin t3),              */
+/* d^4q = q^3 sin^2 t1 sin t2 dq dt1 dt2 dt3.                                                */
+/* ---------------------------------------------------------------------------------------- */
+static double dot4(const double *a, const double *b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
+}
+
+int frgo_vertex_hyperspherical(int n_legs, int n_q, int n_t1, int n_t2, int n_t3, double q_max,
+                               double k, int regulator, const double p1[4], const double p2[4],
+                               double m2, const double *Z, int nZ, double x_min, double x_max,
+                               double *out) {
+    if ((n_legs != 2 && n_legs != 3) || n_q < 1 || n_t1 < 1 || n_t2 < 1 || n_t3 < 1) return -1;
+    if (n_q > MAXN || n_t1 > MAXN || n_t2 > MAXN || n_t3 > MAXN || out == NULL) return -1;
+    static __thread double qn[MAXN], qw[MAXN], t1n[MAXN], t1w[MAXN], t2n[MAXN], t2w[MAXN],
+        t3n[MAXN], t3w[MAXN];
+    frgo_gauss_legendre(n_q, 0.0, q_max * k, qn, qw);
+    frgo_gauss_legendre(n_t1, 0.0, PI, t1n, t1w);
+    frgo_gauss_legendre(n_t2, 0.0, PI, t2n, t2w);
+    frgo_gauss_legendre(n_t3, 0.0, 2.0 * PI, t3n, t3w);
+    double pref = 1.0 / pow(2.0 * PI, 4.0);
+    nsum total = {0.0, 0.0};
+    for (int a = 0; a < n_q; ++a) {
+        double q = qn[a], q2 = q * q;
+        double gq = frgo_propagator(regulator, Z, nZ, x_min, x_max, q2, m2, k);
+        double rad = pref * qw[a] * q2 * q * frgo_regulator_dot(regulator, q2, k) * gq * gq;
+        nsum s1 = {0.0, 0.0};
+        for (int i = 0; i < n_t1; ++i) {
+            double t1 = t1n[i];
+            nsum s2 = {0.0, 0.0};
+            for (int j = 0; j < n_t2; ++j) {
+                double t2 = t2n[j];
+                nsum s3 = {0.0, 0.0};
+                for (int c = 0; c < n_t3; ++c) {
+                    double t3 = t3n[c];
+                    double v[4] = {q * cos(t1), q * sin(t1) * cos(t2),
+                                   q * sin(t1) * sin(t2) * cos(t3), q * sin(t1) * sin(t2) * sin(t3)};
+                    double a1[4], a2[4];
+                    for (int m = 0; m < 4; ++m) {
+                        a1[m] = v[m] + p1[m];
+                        a2[m] = v[m] - p2[m];
+                    }
+                    double g = frgo_propagator(regulator, Z, nZ, x_min, x_max, dot4(a1, a1), m2, k);
+                    if (n_legs == 3)
+                        g *= frgo_propagator(regulator, Z, nZ, x_min, x_max, dot4(a2, a2), m2, k);
+                    nsum_add(&s3, t3w[c] * g);
+                }
+                nsum_add(&s2, t2w[j] * sin(t2) * nsum_get(&s3));
+            }
+            nsum_add(&s1, t1w[i] * sin(t1) * sin(t1) * nsum_get(&s2));
+        }
+        nsum_add(&total, rad * nsum_get(&s1));
+    }
+    *out = nsum_get(&total);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* LPA flow right-hand side.                                                                 */
+/* ---------------------------------------------------------------------------------------- */
+int frgo_fd_derivatives(const double *x, const double *f, int n, double *d1, double *d2) {
+    /* derivatives of the quadratic through three neighbouring points (Lagrange form) */
+    if (n < 3 || x == NULL || f == NULL || d1 == NULL || d2 == NULL) return -1;
+    for (int i = 0; i < n; ++i) {
+        int c = (i == 0) ? 1 : (i == n - 1 ? n - 2 : i); /* centre of the stencil */
+        double x0 = x[c - 1], x1 = x[c], x2 = x[c + 1];
+        double f0 = f[c - 1], f1 = f[c], f2 = f[c + 1];
+        double xe = x[i];
+        /* L_j'(xe) and L_j'' for the three Lagrange basis polynomials */
+        double l0d = ((xe - x1) + (xe - x2)) / ((x0 - x1) * (x0 - x2));
+        double l1d = ((xe - x0) + (xe - x2)) / ((x1 - x0) * (x1 - x2));
+        double l2d = ((xe - x0) + (xe - x1)) / ((x2 - x0) * (x2 - x1));
+        double l0s = 2.0 / ((x0 - x1) * (x0 - x2));
+        double l1s = 2.0 / ((x1 - x0) * (x1 - x2));
+        double l2s = 2.0 / ((x2 - x0) * (x2 - x1));
+        d1[i] = f0 * l0d + f1 * l1d + f2 * l2d;
+        d2[i] = f0 * l0s + f1 * l1s + f2 * l2s;
+    }
+    return 0;
+}
+
+int frgo_lpa_flow_rhs(int d, int n_q, double q_max, double k, int regulator, int n_comp,
+                      double m2_floor, const double *rho, const double *u, int n, double *dudt) {
+    if (n < 3 || n > MAXN || n_comp < 1 || rho == NULL || u == NULL || dudt == NULL) return -1;
+    static __thread double d1[MAXN], d2[MAXN], ms[MAXN], mp[MAXN], Is[MAXN], Ip[MAXN];
+    if (frgo_fd_derivatives(rho, u, n, d1, d2) != 0) return -1;
+    for (int i = 0; i < n; ++i) {
+        ms[i] = u[i] + 2.0 * rho[i] * d1[i];
+        mp[i] = u[i];
+        if (ms[i] < m2_floor) ms[i] = m2_floor;
+        if (mp[i] < m2_floor) mp[i] = m2_floor;
+    }
+    int rc = frgo_integrate(FRGO_LPA, d, n_q, 0, 0, q_max, k, regulator, NULL, ms, 0.0, NULL, 0,
+                            0.0, 0.0, n, Is);
+    if (rc != 0) return rc;
+    rc = frgo_integrate(FRGO_LPA, d, n_q, 0, 0, q_max, k, regulator, NULL, mp, 0.0, NULL, 0, 0.0,
+                        0.0, n, Ip);
+    if (rc != 0) return rc;
+    for (int i = 0; i < n; ++i)
+        dudt[i] = 0.5 * (Is[i] * (3.0 * d1[i] + 2.0 * rho[i] * d2[i]) +
+                         (double)(n_comp - 1) * Ip[i] * d1[i]);
+    return 0;
+}

@@ -1,0 +1,93 @@
+/*
+ * frg_oracle.h -- plain, slow, FP64 CPU oracle for the batched fRG loop integrals.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or calls this code;
+ * only the test suite, the smoke check and the CPU-baseline leg of the benchmark do.  It shares
+ * no source with the HIP library: its own Gauss-Legendre generator (Newton on the Legendre
+ * three-term recurrence in long double), libm transcendentals, Neumaier-compensated sums.
+ *
+ * Everything follows the paper (Sattler & Pawlowski, "DiFfRG: A Discretisation Framework for
+ * functional Renormalisation Group flows", arXiv 2412.13043):
+ *   - RG-time convention t = log(Lambda/k), k d/dk = -d/dt                     (Sec. 2.1)
+ *   - k d/dk = -2 x d/dx for x = p^2/k^2, used for the regulator derivative    (Sec. 3.1)
+ *   - flat (Litim) regulator r(x) = (1/x - 1) Theta(1 - x)                      (Sec. 3.1, fig. polyExpReg)
+ *   - vacuum "Quadrature" integrator: tensor-product quadrature over |q| and
+ *     the loop angles, d = 4 angle names cos1, cos2, phi                      (Sec. 5.3, App. F)
+ *   - log-coordinate linear interpolation of dressing functions               (App. F, FunctionTex1D)
+ * and the exponential regulator R_k(q) = q^2/(exp(q^2/k^2) - 1) of the benchmark workloads.
+ *
+ * All arrays are host memory owned by the caller.  Functions return 0 on success and a negative
+ * value on invalid arguments (nothing is written then).
+ */
+#ifndef FRG_ORACLE_H
+#define FRG_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { FRGO_REG_EXP = 0, FRGO_REG_LITIM = 1 };
+enum { FRGO_LPA = 1, FRGO_TWO_POINT = 2, FRGO_THREE_POINT = 3 };
+
+/* n-point Gauss-Legendre rule on [a, b]; nodes ascending. */
+int frgo_gauss_legendre(int n, double a, double b, double *nodes, double *weights);
+
+/* Regulator R_k(l2) and its scale derivative k dR_k/dk at momentum squared l2 (>= 0). */
+double frgo_regulator(int kind, double l2, double k);
+double frgo_regulator_dot(int kind, double l2, double k);
+
+/* Dressing Z(l2) from a table on a grid log-uniform in |l| over [x_min, x_max] (n >= 2 points),
+ * linear in log|l|, constant outside.  Z == NULL means Z == 1. */
+double frgo_dressing(const double *Z, int nZ, double x_min, double x_max, double l2);
+
+/* Propagator G(l2) = 1/(Z(l2) l2 + R_k(l2) + m2). */
+double frgo_propagator(int reg, const double *Z, int nZ, double x_min, double x_max,
+                       double l2, double m2, double k);
+
+/*
+ * Loop integral I_e for every external point e in [0, n_ext):
+ *   family 1 (LPA, any d >= 1, no angles):
+ *       I = Omega_d/(2pi)^d  sum_a w_a q_a^(d-1) Rdot(q_a^2) / (q_a^2 + R(q_a^2) + m2_e)^2      (Z == 1)
+ *   family 2 (two-point, d = 4, angle cos1 = x):
+ *       I = 4pi/(2pi)^4 sum_ab w_a w_b sqrt(1-x_b^2) q^3 Rdot(q^2) G(q^2)^2 G((q+p)^2)
+ *   family 3 (three-point, d = 4, angles cos1 = x and phi in [0, pi]):
+ *       I = 2pi/(2pi)^4 sum_abc w_a w_b w_c sqrt(1-x^2) sin(phi) q^3 Rdot G(q^2)^2 G((q+p1)^2) G((q-p2)^2)
+ *       with p1 = p e1, p2 = p (cos(alpha) e1 + sin(alpha) e2).
+ * Radial GL(n_q) on [0, q_max*k], x GL(n_x) on [-1, 1], phi GL(n_phi) on [0, pi].
+ * ext: family 1 unused (may be NULL); family 2 p[n_ext]; family 3 p[n_ext] followed by alpha[n_ext].
+ * m2: per-point masses [n_ext] (NULL -> m2_scalar).
+ */
+int frgo_integrate(int family, int d, int n_q, int n_x, int n_phi, double q_max, double k,
+                   int regulator, const double *ext, const double *m2, double m2_scalar,
+                   const double *Z, int nZ, double x_min, double x_max, int n_ext, double *out);
+
+/*
+ * General d = 4 one-loop integral with explicit external 4-vectors, on a full hyperspherical
+ * product rule (GL in the polar angles theta1, theta2 in [0, pi] with the sin^2/sin Jacobian
+ * and GL in the azimuth theta3 in [0, 2pi]):
+ *   I = 1/(2pi)^4 \int d^4q Rdot(q^2) G(q^2)^2 G((q+p1)^2) [G((q-p2)^2) if n_legs == 3]
+ * Used only to pin the reduced angle forms of families 2 and 3 (rotation invariance).
+ */
+int frgo_vertex_hyperspherical(int n_legs, int n_q, int n_t1, int n_t2, int n_t3, double q_max,
+                               double k, int regulator, const double p1[4], const double p2[4],
+                               double m2, const double *Z, int nZ, double x_min, double x_max,
+                               double *out);
+
+/*
+ * Right-hand side of the LPA flow of u(rho) = U'(rho) for the O(N) model on a rho grid (Sec. 3.1
+ * flux form, vacuum, d dimensions, radial and N-1 Goldstone modes):
+ *   m_s^2 = u + 2 rho u',  m_p^2 = u   (each floored at m2_floor)
+ *   du/dt = +1/2 [ I(m_s^2) (3 u' + 2 rho u'') + (N-1) I(m_p^2) u' ]
+ * where I is the family-1 integral and t = log(Lambda/k).  u', u'' are second-order finite
+ * differences on the (possibly non-uniform) grid, one-sided at the two ends.  n >= 3.
+ */
+int frgo_lpa_flow_rhs(int d, int n_q, double q_max, double k, int regulator, int n_comp,
+                      double m2_floor, const double *rho, const double *u, int n, double *dudt);
+
+/* Second-order finite-difference first and second derivatives used by frgo_lpa_flow_rhs. */
+int frgo_fd_derivatives(const double *x, const double *f, int n, double *d1, double *d2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
