@@ -1,0 +1,269 @@
+"""Benchmark of the batched loop-integral hot path on one MI355X.
+
+Step = one flow right-hand side batch of the two-point vertex workload: 256 right-hand sides,
+each 256 external momenta p in [1e-3, 1e2] (log-spaced) x (64 radial x 32 cos1 Gauss-Legendre
+nodes) with its own tabulated dressing Z (256-point log grid), m^2 = 0.5, float64 -- evaluated by
+one fused frg_integrate_multi launch (134,217,728 integrand nodes).  Inputs are resident in HBM
+before the timed region.
+
+Printed (one JSON line): Gnodes/s, ms per step, the roofline of the dominant kernel (algorithmic
+FP64 FLOPs per node x nodes per launch / average kernel time from HIP events on the launch
+stream, against the MI355X FP64 vector peak), the FP64 oracle timed on the host cores on a
+bounded sample, and secondary figures for the other workloads (LPA batch, three-point batch, the
+float32 precision form, right-hand-side latency percentiles).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_PEAK_TFLOPS = 157.3  # packed FP32 (v_pk_fma_f32); unpacked float32 tops out at half
+# Algorithmic FP64 work per integrand node (FLOP-equivalents, transcendentals included), per
+# family, as derived in DESIGN.md (section "Roofline and FLOP accounting").
+FLOP_PER_NODE = {1: 15.0, 2: 74.0, 3: 83.0}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _dev(torch, a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), dtype=torch.float64,
+                        device="cuda")
+
+
+def time_kernel(torch, fn, steps, warmup):
+    """Run fn warmup + steps times; return (wall seconds for the steps, per-launch event ms)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return t1 - t0, [a.elapsed_time(b) for a, b in evs]
+
+
+def two_point_batch_setup(torch, frg, B=256, precision=0, seed_m2=None):
+    from paper_2412_13043_amd import workloads as wl
+
+    if seed_m2 is None:
+        p, m2, Zs = wl.two_point_batch(B)
+        m2a = None
+    else:
+        p, m2a, Zs = wl.near_pole_batch(B)
+        m2 = 0.0
+    tp = _dev(torch, p)
+    tZ = _dev(torch, Zs)
+    tm = _dev(torch, m2a) if m2a is not None else None
+    out = torch.empty((B, p.size), dtype=torch.float64, device="cuda")
+    err = torch.empty((B, p.size), dtype=torch.float64, device="cuda") if precision else None
+    desc = frg.make_desc(2, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX, precision=precision,
+                         near_pole_tau=0.1 if precision else 0.0)
+    batches = [frg.make_batch(p.size, out[b], ext=tp, m2=None if tm is None else tm[b],
+                              m2_scalar=m2, Z=tZ[b], x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
+                              err_out=None if err is None else err[b]) for b in range(B)]
+    keep = (tp, tZ, tm, out, err)
+    nodes = B * p.size * wl.TWO_NQ * wl.TWO_NX
+    return [desc] * B, batches, out, err, nodes, keep
+
+
+def cpu_baseline(target_seconds=12.0):
+    """FP64 oracle on the host cores: disjoint external-point ranges in parallel threads."""
+    import oracle
+    from paper_2412_13043_amd import workloads as wl
+
+    p, m2, Zs = wl.two_point_batch(64)
+    threads = min(os.cpu_count() or 1, 16)
+    nodes_done = 0
+    rhs_done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < target_seconds:
+        Z = Zs[rhs_done % Zs.shape[0]]
+        chunks = np.array_split(np.arange(p.size), threads)
+        ths = [threading.Thread(target=oracle.integrate,
+                                args=(oracle.TWO_POINT, wl.TWO_NQ, wl.TWO_QMAX),
+                                kwargs=dict(n_x=wl.TWO_NX, ext=p[c], m2_scalar=m2, Z=Z))
+               for c in chunks if c.size]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        rhs_done += 1
+        nodes_done += p.size * wl.TWO_NQ * wl.TWO_NX
+    el = time.perf_counter() - t0
+    return {"value": round(nodes_done / el / 1e9, 6), "unit": "Gnodes/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{rhs_done} two-point right-hand sides (256 momenta x 64x32 nodes each, "
+                      f"float64, C -O2 libm), {threads} threads over disjoint momentum ranges, "
+                      f"{el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the loop-integral "
+              "path is measured on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2412_13043_amd import frg
+    from paper_2412_13043_amd import workloads as wl
+
+    ctx = frg.Context(0)
+    log("bench: two-point batch setup")
+    descs, batches, out, _, nodes, keep = two_point_batch_setup(torch, frg)
+
+    def step():
+        ctx.integrate_multi(descs, batches)
+
+    log(f"bench: timing {args.steps} steps after {args.warmup} warmup")
+    wall, ev_ms = time_kernel(torch, step, args.steps, args.warmup)
+    ms_per_step = wall / args.steps * 1e3
+    value = nodes * args.steps / wall / 1e9
+    avg_ms = float(np.mean(ev_ms))
+    flops = FLOP_PER_NODE[2] * nodes
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    res = {
+        "metric": "integrand Gnodes/s + % FP64/FP32 vector peak; p50/p99 RHS latency",
+        "value": round(value, 3),
+        "unit": "Gnodes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "two-point vertex flow d=4: 256 right-hand sides x 256 momenta "
+                               "x 64x32 GL nodes, per-RHS tabulated Z, m2=0.5, float64, one "
+                               "fused frg_integrate_multi launch",
+                   "nodes_per_step": nodes, "rhs_per_step": 256},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                     "traffic": None, "kernel": "frg::multi_kernel",
+                     "avg_kernel_ms": round(avg_ms, 4),
+                     "flop_per_node": FLOP_PER_NODE[2]},
+    }
+    extra = {}
+    if not args.no_extra:
+        extra = secondary(torch, frg, wl, ctx)
+    if extra:
+        res["extra"] = extra
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline")
+        res["cpu_baseline"] = cpu_baseline()
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+def secondary(torch, frg, wl, ctx):
+    """Other workloads, timed the same way (fewer steps)."""
+    ex = {}
+    # LPA batch: 4096 right-hand sides x 64 rho points x GL32
+    log("bench: LPA batch")
+    rho, u, m2 = wl.lpa_batch()
+    tm = _dev(torch, m2.reshape(-1))
+    o1 = torch.empty(tm.numel(), dtype=torch.float64, device="cuda")
+    d1 = frg.make_desc(1, wl.LPA_NQ, wl.LPA_QMAX)
+    wall, ev = time_kernel(torch, lambda: ctx.integrate(d1, o1, m2=tm), 20, 3)
+    n1 = tm.numel() * wl.LPA_NQ
+    ex["lpa_batch_4096"] = {"gnodes_per_s": round(n1 / (np.mean(ev) * 1e-3) / 1e9, 2),
+                            "avg_kernel_ms": round(float(np.mean(ev)), 4)}
+    # three-point batch: 8 right-hand sides x 1024 external pairs x 64x32x16
+    log("bench: three-point batch")
+    P, A, m3, Z3 = wl.three_point_batch()
+    text = _dev(torch, np.concatenate([P, A]))
+    tm3 = _dev(torch, m3)
+    tZ3 = _dev(torch, Z3)
+    o3 = torch.empty((8, P.size), dtype=torch.float64, device="cuda")
+    d3 = frg.make_desc(3, wl.THREE_NQ, wl.THREE_QMAX, n_x=wl.THREE_NX, n_phi=wl.THREE_NPHI)
+    b3 = [frg.make_batch(P.size, o3[b], ext=text, m2=tm3[b], Z=tZ3[b], x_min=wl.Z_XMIN,
+                         x_max=wl.Z_XMAX) for b in range(8)]
+    wall, ev = time_kernel(torch, lambda: ctx.integrate_multi([d3] * 8, b3), 3, 1)
+    n3 = 8 * P.size * wl.THREE_NQ * wl.THREE_NX * wl.THREE_NPHI
+    ms3 = float(np.mean(ev))
+    ex["three_point_batch_8"] = {
+        "gnodes_per_s": round(n3 / (ms3 * 1e-3) / 1e9, 2), "avg_kernel_ms": round(ms3, 3),
+        "fp64_tflops": round(FLOP_PER_NODE[3] * n3 / (ms3 * 1e-3) / 1e12, 3),
+        "frac_fp64_peak": round(FLOP_PER_NODE[3] * n3 / (ms3 * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                                4)}
+    # precision form on the near-pole workload vs float64 on identical inputs
+    log("bench: float32 precision form")
+    res = {}
+    for prec in (0, 1):
+        descs, batches, out, err, nodes, keep = two_point_batch_setup(torch, frg, precision=prec,
+                                                                      seed_m2=4)
+        wall, ev = time_kernel(torch, lambda: ctx.integrate_multi(descs, batches), 5, 1)
+        res[prec] = (float(np.mean(ev)), out.clone(), None if err is None else err.clone(), nodes)
+    ms64, o64, _, nodes = res[0]
+    ms32, o32, e32, _ = res[1]
+    rel = ((o32 - o64).abs() / o64.abs()).cpu().numpy()
+    ex["fp32_form_near_pole"] = {
+        "speedup_vs_fp64": round(ms64 / ms32, 3),
+        "gnodes_per_s": round(nodes / (ms32 * 1e-3) / 1e9, 2),
+        "max_rel_err_vs_fp64": float(rel.max()), "median_rel_err_vs_fp64": float(np.median(rel)),
+        "max_stated_bound": float(e32.max().item()), "near_pole_tau": 0.1}
+    # right-hand-side latency (graph replays): one LPA RHS and one two-point RHS
+    log("bench: RHS latency")
+    lat = {}
+    rho = wl.lpa_rho_grid()
+    trho = _dev(torch, rho)
+    st = _dev(torch, -0.3 + rho)
+    du = torch.empty_like(st)
+    dl = frg.make_desc(1, wl.LPA_NQ, wl.LPA_QMAX)
+    lat["lpa_rhs"] = _latency(torch, lambda: ctx.flow_rhs(dl, st, trho, du, n_comp=4,
+                                                           m2_floor=-0.9))
+    p, m2, Z = wl.two_point()
+    tp, tZ = _dev(torch, p), _dev(torch, Z)
+    s2 = torch.full((p.size,), m2, dtype=torch.float64, device="cuda")
+    d2 = torch.empty_like(s2)
+    dd = frg.make_desc(2, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX)
+    lat["two_point_rhs"] = _latency(torch, lambda: ctx.flow_rhs(dd, s2, tp, d2, Z=tZ,
+                                                                m2_floor=-0.9, coef=1.0))
+    ex["rhs_latency_us"] = lat
+    return ex
+
+
+def _latency(torch, fn, n=2000):
+    for _ in range(20):
+        fn()
+    torch.cuda.synchronize()
+    ts = np.empty(n)
+    for i in range(n):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts[i] = time.perf_counter() - t0
+    return {"p50": round(float(np.percentile(ts, 50)) * 1e6, 2),
+            "p99": round(float(np.percentile(ts, 99)) * 1e6, 2), "calls": n}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,229 @@
+/*
+ * frg.h -- C ABI of the MI355X (gfx950) batched loop-integral library for functional
+ * renormalisation group flows.
+ *
+ * What the library computes follows Sattler & Pawlowski, "DiFfRG: A Discretisation Framework
+ * for functional Renormalisation Group flows" (arXiv 2412.13043):
+ *   - a flow right-hand side is a set of loop-momentum integrals, one per external point, whose
+ *     integrands carry the regulator insertion k dR_k/dk (Sec. 2.1, generalised flow equation and
+ *     the tower of n-point flows; t = log(Lambda/k), k d/dk = -d/dt);
+ *   - each integral is evaluated by a "Quadrature" integrator, a tensor-product quadrature that
+ *     treats all vacuum dimensions alike, over |q| and the loop angles; in d = 4 the angle
+ *     variables are cos1 and (for two angles beyond it) phi (Sec. 5.3 "Momentum integrations",
+ *     App. F "Kernel definitions");
+ *   - an integration kernel is described by its type, number of angles, dimension d and compute
+ *     type ctype in {double, float} (App. F), and receives constants, per-point variables and
+ *     tabulated functions interpolated on logarithmic coordinates (App. F "Parameter
+ *     definitions", FunctionTex1D);
+ *   - the model's right-hand side fills one residual entry per integral call (App. G listing;
+ *     Sec. 5.2 dt_variables), batched here over all external points of a flow.
+ * The quadrature family is Gauss-Legendre: radial nodes on [0, q_max k], x = cos1 on [-1, 1]
+ * with the d = 4 measure factor sqrt(1 - x^2), phi on [0, pi] with measure sin(phi).
+ *
+ * Conventions for every call:
+ *   - Every entry point returns frg_status; nothing throws across the ABI.  On any error the
+ *     output buffers are left unspecified and frg_last_error() (thread-local) names the cause.
+ *   - Argument and shape errors are reported synchronously with FRG_E_INVAL before anything is
+ *     enqueued.  HIP runtime failures are FRG_E_DEVICE.
+ *   - "device" pointers are HIP device memory (for example torch CUDA/HIP tensors); the caller
+ *     owns them and keeps them alive until the stream reaches the work (for sessions: until the
+ *     ticket completes).  "host" pointers are ordinary host memory.
+ *   - Work is enqueued on the caller's stream (NULL = the default stream) and is asynchronous
+ *     unless stated otherwise; results are visible after the stream is synchronised.
+ *   - All arrays are float64, structure-of-arrays, contiguous.
+ *   - The library owns its quadrature-rule cache, scratch, tile lists, autotune cache and the
+ *     session-resident dressing tables.
+ */
+#ifndef FRG_H
+#define FRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct frg_context frg_context; /* device, rule cache, scratch pools, autotune cache */
+typedef struct frg_session frg_session; /* serving loop over one context */
+
+typedef enum {
+    FRG_OK = 0,
+    FRG_E_INVAL = 1,       /* bad argument, descriptor or shape; nothing was enqueued */
+    FRG_E_NOMEM = 2,       /* allocation failed or request exceeds the HBM budget */
+    FRG_E_DEVICE = 3,      /* HIP runtime error; see frg_last_error() */
+    FRG_E_NOTREADY = 4,    /* ticket not finished (poll) */
+    FRG_E_TIMEOUT = 5,     /* wait timed out */
+    FRG_E_CANCELLED = 6,   /* ticket was cancelled */
+    FRG_E_UNSUPPORTED = 7  /* valid but not implemented combination */
+} frg_status;
+
+typedef enum {
+    FRG_FP64 = 0,       /* integrand and all sums in float64 */
+    FRG_FP32_KAHAN = 1  /* float32 integrand, compensated float32 inner sums, float64 outer sums;
+                           propagators near the pole evaluated in float64 (see near_pole_tau) */
+} frg_precision;
+
+typedef enum {
+    FRG_FAMILY_LPA = 1,         /* radial only, any d >= 1 (local potential approximation) */
+    FRG_FAMILY_TWO_POINT = 2,   /* d = 4, one angle (cos1) */
+    FRG_FAMILY_THREE_POINT = 3  /* d = 4, cos1 and phi (third angle trivial: factor 2 pi) */
+} frg_family;
+
+/*
+ * Integral descriptor ("integration kernel" in the paper's App. F terms).
+ *
+ *   family 1:  I_e = Omega_d/(2pi)^d sum_a w_a q_a^(d-1) Rdot(q_a^2)/(q_a^2 + R(q_a^2) + m2_e)^2
+ *   family 2:  I_e = 4pi/(2pi)^4 sum_ab w_a w_b sqrt(1-x_b^2) q_a^3 Rdot(q_a^2) G(q_a^2)^2
+ *                    G(q_a^2 + p_e^2 + 2 q_a p_e x_b)
+ *   family 3:  I_e = 2pi/(2pi)^4 sum_abc w_a w_b w_c sqrt(1-x_b^2) sin(phi_c) q_a^3 Rdot G(q_a^2)^2
+ *                    G(l1^2) G(l2^2),   l1 = q + p1, l2 = q - p2,
+ *                    p1 = p e1, p2 = p (cos(alpha) e1 + sin(alpha) e2):
+ *                    l1^2 = q^2 + p^2 + 2 q p x,
+ *                    l2^2 = q^2 + p^2 - 2 q p (x cos(alpha) + sqrt(1-x^2) cos(phi) sin(alpha))
+ * with the exponential regulator R(l2) = l2/(exp(l2/k^2) - 1), its scale derivative
+ * Rdot = k dR/dk = 2 k^2 y^2 e^y/(e^y - 1)^2 (y = l2/k^2) and the propagator
+ * G(l2) = 1/(Z(l2) l2 + R(l2) + m2).  Radial GL(n_q) on [0, q_max*k]; x GL(n_x) on [-1, 1];
+ * phi GL(n_phi) on [0, pi].  Momenta squared below zero from rounding are clamped to 0.
+ */
+typedef struct {
+    int family;            /* frg_family */
+    int d;                 /* 1..8 for LPA; must be 4 for families 2 and 3 */
+    int n_q;               /* radial nodes, 1..FRG_MAX_NODES */
+    int n_x;               /* cos1 nodes (families 2, 3), 1..FRG_MAX_NODES; ignored for LPA */
+    int n_phi;             /* phi nodes (family 3), 1..FRG_MAX_NODES; ignored otherwise */
+    int precision;         /* frg_precision */
+    double q_max;          /* radial upper limit in units of k, > 0 */
+    double k;              /* RG scale, > 0 */
+    double near_pole_tau;  /* FP32 form only: a propagator whose denominator D satisfies
+                              D < tau (|Z l2 + R| + |m2|) is evaluated in float64; 0 = never */
+} frg_integral_desc;
+
+#define FRG_MAX_NODES 1024
+#define FRG_MAX_TABLE 4096
+
+/* Dressing Z tabulated on n points log-uniform in |l| over [x_min, x_max] (device pointer),
+ * linear in log|l| between points, constant outside.  values == NULL means Z == 1.
+ * Ignored by family 1 (Z == 1 there). */
+typedef struct {
+    const double *values;
+    int n;                 /* 2..FRG_MAX_TABLE */
+    double x_min, x_max;   /* 0 < x_min < x_max */
+} frg_log_table;
+
+/* One batch of n_ext external points sharing one descriptor and one dressing table. */
+typedef struct {
+    int n_ext;             /* >= 0; 0 is a valid no-op */
+    const double *ext;     /* device. family 1: unused (may be NULL); family 2: p[n_ext];
+                              family 3: p[n_ext] followed by alpha[n_ext] (2 n_ext values) */
+    const double *m2;      /* device [n_ext] per-point m^2, or NULL to use m2_scalar */
+    double m2_scalar;
+    frg_log_table Z;
+    double *out;           /* device [n_ext]: I_e */
+    double *err_out;       /* device [n_ext] or NULL: FP32 form's stated relative error bound per
+                              result (0 for FP64); see DESIGN notes in the implementation */
+} frg_batch;
+
+/* ---- context ------------------------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the library's own device
+ * allocations for sessions (0 = 90% of free memory).  *out receives the handle. */
+frg_status frg_context_create(int device, size_t hbm_budget_bytes, frg_context **out);
+/* Waits for the context's work, frees everything it owns. NULL is a no-op. */
+frg_status frg_context_destroy(frg_context *ctx);
+/* Message of the last failing call on this thread ("" if none). Valid until the next call. */
+const char *frg_last_error(void);
+
+/* ---- batched integration ------------------------------------------------------------------- */
+
+/* Evaluate I_e for all points of one batch (paper Sec. 5.3: the integrator's get(k, args...),
+ * batched over external points).  One kernel launch on `stream`. */
+frg_status frg_integrate_batch(frg_context *ctx, const frg_integral_desc *desc,
+                               const frg_batch *batch, hipStream_t stream);
+
+/* Evaluate n batches with independent descriptors (any mix of families, node counts and
+ * precisions) in one fused persistent launch: the work is cut into tiles, ordered largest
+ * first, and consumed by a grid sized to the device.  Each result is bitwise identical to the
+ * same batch submitted alone through frg_integrate_batch with the same descriptor. */
+frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc *descs,
+                               const frg_batch *batches, hipStream_t stream);
+
+/* ---- flow right-hand side ------------------------------------------------------------------- */
+
+/*
+ * State of a flow whose right-hand side is assembled from one family of loop integrals.
+ *   family 1 (LPA of the O(N) model, paper Sec. 3.1 in its flux form):
+ *       state = u_i = U'(rho_i) on the grid rho_i (n_ext >= 3, strictly increasing);
+ *       m_s^2 = u + 2 rho u', m_p^2 = u (both floored at m2_floor), u', u'' from the quadratic
+ *       through three neighbouring grid points (one-sided at the ends), and
+ *       du_i/dt = 1/2 [ I(m_s^2) (3 u' + 2 rho u'') + (n_comp - 1) I(m_p^2) u' ]
+ *       with t = log(Lambda/k) (Sec. 2.1).  Needs 2 n_ext integrals per call.
+ *   families 2 and 3 (vertex expansion): state = m2_e per external point (floored at m2_floor),
+ *       grid = the batch's ext array, and dstate_e/dt = coef * I_e.
+ */
+typedef struct {
+    int family;
+    int n_ext;
+    const double *state;   /* device [n_ext] */
+    const double *grid;    /* device: family 1 rho[n_ext]; 2 p[n_ext]; 3 p, alpha [2 n_ext] */
+    frg_log_table Z;       /* families 2, 3 */
+    int n_comp;            /* family 1: N of O(N) (>= 1) */
+    double m2_floor;       /* mass floor (-0.9 k^2 in the LPA workload) */
+    double coef;           /* families 2, 3: dstate/dt = coef * I */
+} frg_flow_state;
+
+/* dstate_dt (device [n_ext]) = RHS(state) for one flow (see frg_flow_state).  The whole chain
+ * state -> masses -> integrals -> assembly runs on the device.  The first call for a shape
+ * captures it as a HIP graph on `stream`; later calls with the same shape, pointers and stream
+ * replay the graph (pointer or shape changes re-capture). */
+frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
+                        const frg_flow_state *state, double *dstate_dt, hipStream_t stream);
+
+/* ---- serving -------------------------------------------------------------------------------- */
+
+typedef struct {
+    int max_inflight;          /* launches in flight at once (>= 1) */
+    size_t hbm_budget_bytes;   /* device bytes the session may hold for admitted requests;
+                                  0 = the context budget */
+    int poll_us;               /* scheduler sleep when idle */
+    int watchdog_ms;           /* a launch outstanding longer than this fails its tickets */
+} frg_session_config;
+
+typedef struct {
+    double p50_us, p99_us;     /* submit -> result visible on the host, completed requests */
+    double gnodes_per_s;       /* integrand evaluations / busy wall time */
+    uint64_t admitted, queued, rejected, completed, failed, cancelled;
+    uint64_t nodes;            /* integrand evaluations completed */
+    uint64_t launches;         /* fused launches issued */
+} frg_stats;
+
+/* Requests submitted to a session hold HOST pointers (ext, m2, out, err_out); the session
+ * stages them into device memory it owns, admitted against the HBM budget, evaluates them in
+ * fused launches that new arrivals join while earlier launches run (continuous batching), and
+ * copies results back before the ticket completes. */
+frg_status frg_session_open(frg_context *ctx, const frg_session_config *cfg, frg_session **out);
+/* Copy a dressing table (host values) into device memory for the session's lifetime.
+ * A request whose batch.Z.values is NULL and whose table_id >= 0 uses the resident table. */
+frg_status frg_session_register_table(frg_session *s, const double *Z_host, int n, double x_min,
+                                      double x_max, int *table_id);
+/* Queue one request; returns immediately with a ticket.  FRG_E_NOMEM if the request alone
+ * exceeds the session budget; FRG_E_INVAL on a bad descriptor or batch. */
+frg_status frg_session_submit(frg_session *s, const frg_integral_desc *desc,
+                              const frg_batch *batch_host, int table_id, uint64_t *ticket);
+/* *done = 1 when the ticket's results are in the host output buffers. */
+frg_status frg_session_poll(frg_session *s, uint64_t ticket, int *done);
+/* Block until the ticket completes (FRG_OK), fails, is cancelled, or timeout_ms passes
+ * (FRG_E_TIMEOUT; timeout_ms < 0 waits forever). */
+frg_status frg_session_wait(frg_session *s, uint64_t ticket, int timeout_ms);
+/* Cancel a ticket that has not been launched yet (FRG_E_NOTREADY if already running). */
+frg_status frg_session_cancel(frg_session *s, uint64_t ticket);
+frg_status frg_session_stats(frg_session *s, frg_stats *out);
+/* Drain in-flight work, fail queued tickets with FRG_E_CANCELLED, free the session. */
+frg_status frg_session_close(frg_session *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRG_H */

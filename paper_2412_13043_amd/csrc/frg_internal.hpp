@@ -1,0 +1,84 @@
+// Internal structures shared by the host runtime and the HIP kernels.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace frg {
+
+constexpr int kWave = 64;          // CDNA wavefront width; one workgroup = one wavefront
+constexpr int kMaxRule = 1024;     // FRG_MAX_NODES
+constexpr int kMaxTable = 4096;    // FRG_MAX_TABLE
+
+// Quadrature rules computed on the device once and cached by the context.
+//  radial (k = 1): q^_a, W^_a = w^_a q^_a^(d-1) Rdot^(q^_a^2), R^_a = R(q^_a^2)
+//  cos1:           x_b, xw_b = w_b sqrt(1 - x_b^2), xs_b = sqrt(1 - x_b^2)      (+ float copies)
+//  phi:            fc_c = cos(phi_c), fw_c = w_c sin(phi_c)                      (+ float copies)
+struct RadialRule {
+    const double *q, *W, *R;
+    const float *qf, *Wf, *Rf;
+};
+struct AngleRule {
+    const double *x, *xw, *xs;
+    const float *xf, *xwf, *xsf;
+};
+struct PhiRule {
+    const double *c, *w;
+    const float *cf, *wf;
+};
+
+// One request ("batch" of external points under one descriptor), as the kernels see it.
+struct ReqDev {
+    int family, d, n_q, n_x, n_phi, precision;
+    int n_ext;
+    int lq_log2;      // lanes per external point = 1 << lq_log2 (families 2, 3)
+    int chunks;       // radial chunks per external tile
+    int ext_tiles;    // ceil(n_ext / (64 >> lq_log2))
+    int nZ;           // 0 => Z == 1
+    int m2_mode;      // 0 scalar, 1 array, 2 array floored at m2_floor (flow states)
+    int ctr_base;     // first counter of this request in the counter array
+    int pad0;
+    long long contrib_base;  // first double of this request's [n_q][n_ext] contribution block
+    double k, k2;
+    double pref;      // final multiplier: Omega-factor * k^(d+2) (and flow coef, if any)
+    double m2s;       // scalar m2
+    double m2_floor;
+    double za, zb;    // dressing coordinate s = za * log(l2) + zb
+    double tau;       // near-pole threshold (FP32 form)
+    RadialRule rad;
+    AngleRule ang;
+    PhiRule phi;
+    const double *ext;    // family 2: p; family 3: p then alpha
+    const double *m2;
+    const double *Z;
+    double *out;
+    double *err;
+};
+
+// A unit of work: external tile `et` of request `req`, radial chunk `chunk`.
+struct TileDev {
+    int req;
+    int et;
+    int chunk;
+    int pad;
+};
+
+// Kernel entry points (defined in frg_kernels.hip).
+hipError_t launch_rules(int n_q, double q_max, int d, int n_x, int n_phi, double *q, double *W,
+                        double *R, float *qf, float *Wf, float *Rf, double *x, double *xw,
+                        double *xs, float *xf, float *xwf, float *xsf, double *fc, double *fw,
+                        float *fcf, float *fwf, hipStream_t s);
+hipError_t launch_batch(const ReqDev *req_dev_host, const ReqDev *req_dev_ptr, int n_tiles,
+                        int lds_bytes, double *contrib, unsigned *counters, hipStream_t s);
+hipError_t launch_multi(const ReqDev *reqs_dev, int n_reqs, const TileDev *tiles_dev,
+                        int n_tiles, int grid, int lds_bytes, double *contrib,
+                        unsigned *counters, unsigned *work_ctr, hipStream_t s);
+hipError_t launch_lpa_state(int n, const double *rho, const double *u, double m2_floor,
+                            double *m2_out, double *fac_out, hipStream_t s);
+hipError_t launch_lpa_assemble(int n, int n_comp, const double *I, const double *fac,
+                               double *dudt, hipStream_t s);
+hipError_t launch_fill_zero_u32(unsigned *p, size_t n, hipStream_t s);
+
+}  // namespace frg

@@ -1,0 +1,648 @@
+// HIP kernels for gfx950 (CDNA4): quadrature rules, the per-tile loop-integral bodies of the
+// three integrand families in float64 and in the float32 precision form, the fused multi-request
+// consumer, and the LPA flow-state / assembly kernels.
+//
+// Work decomposition.  A workgroup is one 64-lane wavefront.  A tile is (request, external tile,
+// radial chunk).  For the LPA family one lane owns one external point and the whole radial sum.
+// For the vertex families a lane owns one (external point, radial node) pair at a time and
+// evaluates its whole inner angle sum in a fixed order; the resulting contribution is stored in a
+// [n_q][n_ext] scratch block and the last tile of an external tile adds the contributions in
+// radial order.  Each result therefore depends only on its own request, never on the tiling,
+// batch composition or launch shape.
+//
+// All device code is built with -ffp-contract=off: every fused multiply-add is written out with
+// fma(), so the operation sequence (and so the rounding) is fixed by the source.
+#include <hip/hip_runtime.h>
+
+#include "frg_internal.hpp"
+
+namespace frg {
+
+// --------------------------------------------------------------------------------------------
+// Quadrature rules
+// --------------------------------------------------------------------------------------------
+// Gauss-Legendre roots written as x = cos(theta): Newton's method in theta on P_n(cos theta),
+// with P_n and P_n' from the three-term recurrence and the derivative recurrence
+// P'_{j+1} = P'_{j-1} + (2j+1) P_j.  Working in theta keeps 1 +- x = 2 cos^2(theta/2),
+// 2 sin^2(theta/2) and sqrt(1 - x^2) = sin(theta) accurate at the ends of the interval.
+__device__ static void legendre_pd(int n, double x, double &p, double &dp) {
+    double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0;
+    for (int j = 1; j < n; ++j) {
+        double p2 = ((2.0 * j + 1.0) * x * p1 - (double)j * p0) / (double)(j + 1);
+        double d2 = d0 + (2.0 * j + 1.0) * p1;
+        p0 = p1;
+        p1 = p2;
+        d0 = d1;
+        d1 = d2;
+    }
+    p = p1;
+    dp = d1;
+}
+
+// i-th root in increasing theta (decreasing x); returns theta and the [-1, 1] weight.
+__device__ static void gl_root(int n, int i, double &theta, double &w) {
+    const double pi = 3.141592653589793238462643383279502884;
+    double t = pi * (4.0 * i + 3.0) / (4.0 * n + 2.0);
+    double p = 0.0, dp = 1.0;
+    for (int it = 0; it < 30; ++it) {
+        legendre_pd(n, cos(t), p, dp);
+        // d/dtheta P_n(cos theta) = -sin(theta) P_n'(cos theta)
+        double step = p / (sin(t) * dp);
+        t += step;
+        if (fabs(step) < 1e-15 * t) {
+            legendre_pd(n, cos(t), p, dp);
+            t += p / (sin(t) * dp);
+            break;
+        }
+    }
+    legendre_pd(n, cos(t), p, dp);
+    double s = sin(t);
+    theta = t;
+    w = 2.0 / (s * s * dp * dp);
+}
+
+// e = exp(-y) and E = expm1(-y) for y >= 0, both to full relative precision (the regulator
+// derivative at the radial nodes multiplies e directly, so e must stay accurate when tiny).
+__device__ __forceinline__ void exp_pair64(double y, double &e, double &E) {
+    if (y < 0.69314718055994530942) {
+        E = expm1(-y);
+        e = 1.0 + E;
+    } else {
+        e = exp(-y);
+        E = e - 1.0;
+    }
+}
+
+// Propagator variant: E = expm1(-y) to full relative precision and e = 1 + E.  e is accurate to
+// 1e-16 absolute, which is all the propagator needs: where e is tiny its term l2 e is below
+// 1e-16 of the denominator.
+__device__ __forceinline__ void exp_pair64_prop(double y, double &e, double &E) {
+    E = expm1(-y);
+    e = 1.0 + E;
+}
+
+__global__ void __launch_bounds__(64) rules_kernel(
+    int n_q, double q_max, int d, int n_x, int n_phi, double *q, double *W, double *R, float *qf,
+    float *Wf, float *Rf, double *x, double *xw, double *xs, float *xf, float *xwf, float *xsf,
+    double *fc, double *fw, float *fcf, float *fwf) {
+    const double pi = 3.141592653589793238462643383279502884;
+    int which = blockIdx.y;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (which == 0 && i < n_q) {
+        double th, w;
+        gl_root(n_q, i, th, w);
+        double c = cos(0.5 * th);
+        double qh = q_max * c * c;  // (q_max/2)(1 + cos theta)
+        double wh = 0.5 * q_max * w;
+        double y = qh * qh;          // k = 1
+        double Rh, Rd;
+        if (y > 0.0) {
+            double e, E;
+            exp_pair64(y, e, E);
+            Rh = y * e / (-E);
+            Rd = 2.0 * y * y * e / (E * E);
+        } else {
+            Rh = 1.0;
+            Rd = 2.0;
+        }
+        double qp = 1.0;
+        for (int j = 0; j < d - 1; ++j) qp *= qh;
+        int slot = n_q - 1 - i;  // ascending q
+        q[slot] = qh;
+        W[slot] = wh * qp * Rd;
+        R[slot] = Rh;
+        qf[slot] = (float)qh;
+        Wf[slot] = (float)(wh * qp * Rd);
+        Rf[slot] = (float)Rh;
+    } else if (which == 1 && i < n_x) {
+        double th, w;
+        gl_root(n_x, i, th, w);
+        double xv = cos(th), sv = sin(th);
+        int slot = n_x - 1 - i;  // ascending x
+        x[slot] = xv;
+        xs[slot] = sv;
+        xw[slot] = w * sv;
+        xf[slot] = (float)xv;
+        xsf[slot] = (float)sv;
+        xwf[slot] = (float)(w * sv);
+    } else if (which == 2 && i < n_phi) {
+        double th, w;
+        gl_root(n_phi, i, th, w);
+        double c = cos(0.5 * th);
+        double ph = pi * c * c;  // (pi/2)(1 + cos theta), ascending in slot order
+        double wp = 0.5 * pi * w;
+        int slot = n_phi - 1 - i;
+        double sp, cp;
+        sincos(ph, &sp, &cp);
+        fc[slot] = cp;
+        fw[slot] = wp * sp;
+        fcf[slot] = (float)cp;
+        fwf[slot] = (float)(wp * sp);
+    }
+}
+
+hipError_t launch_rules(int n_q, double q_max, int d, int n_x, int n_phi, double *q, double *W,
+                        double *R, float *qf, float *Wf, float *Rf, double *x, double *xw,
+                        double *xs, float *xf, float *xwf, float *xsf, double *fc, double *fw,
+                        float *fcf, float *fwf, hipStream_t s) {
+    int nmax = n_q > n_x ? n_q : n_x;
+    nmax = nmax > n_phi ? nmax : n_phi;
+    dim3 grid((nmax + 63) / 64, 3);
+    hipLaunchKernelGGL(rules_kernel, grid, dim3(64), 0, s, n_q, q_max, d, n_x, n_phi, q, W, R,
+                       qf, Wf, Rf, x, xw, xs, xf, xwf, xsf, fc, fw, fcf, fwf);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------------------------
+// Float64 integrand pieces
+// --------------------------------------------------------------------------------------------
+// Smallest momentum squared fed to the propagator.  l2 <= 0 only arises from rounding; with
+// l2 = 1e-300 the propagator equals its l2 = 0 limit 1/(k^2 + m2) to within 1e-300 relative, the
+// dressing clamps to its first entry, and no 0/0 occurs in the single-division form below.
+#define FRG_L2_TINY 1e-300
+
+// Dressing lookup: s = (log|l| - log x_min)/Delta = za*log(l2) + zb, clamped to [0, n-1]; the
+// staged table holds (Z_i, Z_{i+1} - Z_i) with a zero slope in the last entry.
+__device__ __forceinline__ double dressing64(const double2 *__restrict__ Zs, int nZ, double za,
+                                             double zb, double l2) {
+    double s = fma(log(l2), za, zb);
+    s = fmin(fmax(s, 0.0), (double)(nZ - 1));
+    int i = (int)s;
+    double f = s - (double)i;
+    double2 z = Zs[i];
+    return fma(f, z.y, z.x);
+}
+
+// G(l2) = 1/(Z l2 + R(l2) + m2) with R = l2 e/(-E), e = exp(-y), E = expm1(-y), y = l2/k^2,
+// as one division: G = (-E)/((-E)(Z l2 + m2) + l2 e).  l2 > 0.
+__device__ __forceinline__ double prop64(double l2, double z, double m2, double inv_k2) {
+    double y = l2 * inv_k2;
+    double e, E;
+    exp_pair64_prop(y, e, E);
+    double num = -E;
+    double den = fma(num, fma(z, l2, m2), l2 * e);
+    return num / den;
+}
+
+struct Smem {
+    double2 *Z64;
+    float2 *Z32;
+};
+
+__device__ __forceinline__ double lane_m2(const ReqDev &r, int e) {
+    if (r.m2_mode == 0) return r.m2s;
+    double v = r.m2[e];
+    if (r.m2_mode == 2) v = fmax(v, r.m2_floor);
+    return v;
+}
+
+// Radial prologue for (external point, radial node a): q, G(q^2)^2 W^_a and the angle
+// coefficients c0 = q^2 + p^2, c1 = 2 q p.
+struct RadialTerm {
+    double q2, wg, c0, c1;
+};
+
+__device__ __forceinline__ RadialTerm radial64(const ReqDev &r, const Smem &sm, int a, double p,
+                                               double m2, double inv_k2) {
+    RadialTerm t;
+    double q = r.k * r.rad.q[a];
+    t.q2 = q * q;
+    double zq = r.nZ ? dressing64(sm.Z64, r.nZ, r.za, r.zb, fmax(t.q2, FRG_L2_TINY)) : 1.0;
+    double A = fma(zq, t.q2, r.k2 * r.rad.R[a]);
+    double G = 1.0 / (A + m2);
+    t.wg = r.rad.W[a] * (G * G);
+    t.c0 = fma(p, p, t.q2);
+    t.c1 = 2.0 * q * p;
+    (void)inv_k2;
+    return t;
+}
+
+// Contribution of (e, a) to the two-point integral (without the global prefactor).
+__device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm, int a, double p,
+                                                double m2, double inv_k2) {
+    RadialTerm t = radial64(r, sm, a, p, m2, inv_k2);
+    double inner = 0.0;
+    const int nx = r.n_x;
+    for (int b = 0; b < nx; ++b) {
+        double l2 = fmax(fma(t.c1, r.ang.x[b], t.c0), FRG_L2_TINY);
+        double z = r.nZ ? dressing64(sm.Z64, r.nZ, r.za, r.zb, l2) : 1.0;
+        inner = fma(r.ang.xw[b], prop64(l2, z, m2, inv_k2), inner);
+    }
+    return t.wg * inner;
+}
+
+// Contribution of (e, a) to the three-point integral.  l1 does not depend on phi, so G(l1^2) is
+// evaluated once per (a, b); l2^2 = (c0 - c1 x cos a) - c1 sqrt(1-x^2) sin a cos phi.
+__device__ __forceinline__ double contrib_three64(const ReqDev &r, const Smem &sm, int a, double p,
+                                                  double ca, double sa, double m2,
+                                                  double inv_k2) {
+    RadialTerm t = radial64(r, sm, a, p, m2, inv_k2);
+    double mid = 0.0;
+    const int nx = r.n_x, nphi = r.n_phi;
+    for (int b = 0; b < nx; ++b) {
+        double xb = r.ang.x[b];
+        double l1 = fmax(fma(t.c1, xb, t.c0), FRG_L2_TINY);
+        double z1 = r.nZ ? dressing64(sm.Z64, r.nZ, r.za, r.zb, l1) : 1.0;
+        double g1 = prop64(l1, z1, m2, inv_k2);
+        double A2 = fma(-t.c1, xb * ca, t.c0);
+        double B2 = -t.c1 * (r.ang.xs[b] * sa);
+        double inner = 0.0;
+        for (int c = 0; c < nphi; ++c) {
+            double l2 = fmax(fma(B2, r.phi.c[c], A2), FRG_L2_TINY);
+            double z2 = r.nZ ? dressing64(sm.Z64, r.nZ, r.za, r.zb, l2) : 1.0;
+            inner = fma(r.phi.w[c], prop64(l2, z2, m2, inv_k2), inner);
+        }
+        mid = fma(r.ang.xw[b] * g1, inner, mid);
+    }
+    return t.wg * mid;
+}
+
+// --------------------------------------------------------------------------------------------
+// Float32 precision form
+// --------------------------------------------------------------------------------------------
+// float32 integrand with compensated (Kahan) float32 inner sums; the per-(e, a) contribution is
+// widened to float64 before the radial weight, and every sum across radial nodes is float64.
+// A propagator whose float32 denominator is small against its parts (D < tau (|Z l2 + R| + |m2|),
+// i.e. near the pole m2 -> -(Z l2 + R)) is re-evaluated in float64.
+struct Kahan32 {
+    float s, c;
+    __device__ __forceinline__ void add(float v) {
+        float y = v - c;
+        float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+};
+
+__device__ __forceinline__ float dressing32(const float2 *__restrict__ Zs, int nZ, float za,
+                                            float zb, float l2) {
+    float s = fmaf(__logf(l2), za, zb);
+    s = fminf(fmaxf(s, 0.0f), (float)(nZ - 1));
+    int i = (int)s;
+    float f = s - (float)i;
+    float2 z = Zs[i];
+    return fmaf(f, z.y, z.x);
+}
+
+// Returns G(l2) and the amplification factor kappa = (|Z l2 + R| + |m2|)/D of the float32
+// evaluation (1 when evaluated in float64).
+__device__ __forceinline__ float prop32(float l2, float z, float m2f, double m2, double inv_k2,
+                                        float inv_k2f, float tau, const ReqDev &r, const Smem &sm,
+                                        float &kappa) {
+    float y = l2 * inv_k2f;
+    float E = expm1f(-y);
+    float e = 1.0f + E;
+    float num = -E;
+    float zl = z * l2;
+    float Rn = l2 * e;  // R * num
+    float den = fmaf(num, zl + m2f, Rn);
+    float parts = fmaf(num, zl, Rn) + num * fabsf(m2f);  // num * (|Z l2 + R| + |m2|)
+    if (den < tau * parts) {
+        double l2d = (double)l2;
+        double zd = r.nZ ? dressing64(sm.Z64, r.nZ, r.za, r.zb, l2d) : 1.0;
+        kappa = 1.0f;
+        return (float)prop64(l2d, zd, m2, inv_k2);
+    }
+    kappa = parts / den;
+    return num / den;
+}
+
+__device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm, int a, double p,
+                                                double m2, double inv_k2, float &kmax) {
+    RadialTerm t = radial64(r, sm, a, p, m2, inv_k2);
+    const float c0 = (float)t.c0, c1 = (float)t.c1, m2f = (float)m2, ik = (float)inv_k2;
+    const float za = (float)r.za, zb = (float)r.zb, tau = (float)r.tau;
+    Kahan32 acc{0.0f, 0.0f};
+    const int nx = r.n_x;
+    for (int b = 0; b < nx; ++b) {
+        float l2 = fmaxf(fmaf(c1, r.ang.xf[b], c0), 1e-30f);
+        float z = r.nZ ? dressing32(sm.Z32, r.nZ, za, zb, l2) : 1.0f;
+        float kap;
+        float g = prop32(l2, z, m2f, m2, inv_k2, ik, tau, r, sm, kap);
+        kmax = fmaxf(kmax, kap);
+        acc.add(r.ang.xwf[b] * g);
+    }
+    return t.wg * ((double)acc.s - (double)acc.c);
+}
+
+__device__ __forceinline__ double contrib_three32(const ReqDev &r, const Smem &sm, int a, double p,
+                                                  double ca, double sa, double m2,
+                                                  double inv_k2, float &kmax) {
+    RadialTerm t = radial64(r, sm, a, p, m2, inv_k2);
+    const float c0 = (float)t.c0, c1 = (float)t.c1, m2f = (float)m2, ik = (float)inv_k2;
+    const float za = (float)r.za, zb = (float)r.zb, tau = (float)r.tau;
+    const float caf = (float)ca, saf = (float)sa;
+    double mid = 0.0;
+    const int nx = r.n_x, nphi = r.n_phi;
+    for (int b = 0; b < nx; ++b) {
+        float xb = r.ang.xf[b];
+        float l1 = fmaxf(fmaf(c1, xb, c0), 1e-30f);
+        float z1 = r.nZ ? dressing32(sm.Z32, r.nZ, za, zb, l1) : 1.0f;
+        float kap;
+        float g1 = prop32(l1, z1, m2f, m2, inv_k2, ik, tau, r, sm, kap);
+        kmax = fmaxf(kmax, kap);
+        float A2 = fmaf(-c1, xb * caf, c0);
+        float B2 = -c1 * (r.ang.xsf[b] * saf);
+        Kahan32 acc{0.0f, 0.0f};
+        for (int c = 0; c < nphi; ++c) {
+            float l2 = fmaxf(fmaf(B2, r.phi.cf[c], A2), 1e-30f);
+            float z2 = r.nZ ? dressing32(sm.Z32, r.nZ, za, zb, l2) : 1.0f;
+            float g2 = prop32(l2, z2, m2f, m2, inv_k2, ik, tau, r, sm, kap);
+            kmax = fmaxf(kmax, kap);
+            acc.add(r.phi.wf[c] * g2);
+        }
+        double inner = (double)acc.s - (double)acc.c;
+        mid = fma((double)r.ang.xw[b] * (double)g1, inner, mid);
+    }
+    return t.wg * mid;
+}
+
+// --------------------------------------------------------------------------------------------
+// Tile bodies
+// --------------------------------------------------------------------------------------------
+__device__ __forceinline__ void stage_tables(const ReqDev &r, Smem &sm) {
+    // (Z_i, Z_{i+1} - Z_i) pairs, zero slope in the last entry; float32 copies for that form
+    for (int i = threadIdx.x; i < r.nZ; i += blockDim.x) {
+        double zi = r.Z[i];
+        double dz = (i + 1 < r.nZ) ? (r.Z[i + 1] - zi) : 0.0;
+        sm.Z64[i] = make_double2(zi, dz);
+        if (r.precision == 1) sm.Z32[i] = make_float2((float)zi, (float)dz);
+    }
+}
+
+// LPA: one lane per external point, the whole radial sum in one lane, no scratch.
+__device__ __forceinline__ void tile_lpa(const ReqDev &r, int et) {
+    int e = et * kWave + (int)threadIdx.x;
+    if (e >= r.n_ext) return;
+    double m2 = lane_m2(r, e);
+    const int nq = r.n_q;
+    if (r.precision == 0) {
+        double acc = 0.0;
+        for (int a = 0; a < nq; ++a) {
+            double qh = r.rad.q[a];
+            double t = fma(r.k2, fma(qh, qh, r.rad.R[a]), m2);
+            double g = 1.0 / t;
+            acc = fma(r.rad.W[a], g * g, acc);
+        }
+        r.out[e] = r.pref * acc;
+        if (r.err) r.err[e] = 0.0;
+    } else {
+        // float32 terms, compensated float32 sum; near-pole denominators in float64
+        const float k2f = (float)r.k2, m2f = (float)m2, tau = (float)r.tau;
+        Kahan32 acc{0.0f, 0.0f};
+        float kmax = 1.0f;
+        for (int a = 0; a < nq; ++a) {
+            float qh = r.rad.qf[a];
+            float A = k2f * fmaf(qh, qh, r.rad.Rf[a]);
+            float t = A + m2f;
+            float g;
+            if (t < tau * (A + fabsf(m2f))) {
+                double qd = r.rad.q[a];
+                g = (float)(1.0 / fma(r.k2, fma(qd, qd, r.rad.R[a]), m2));
+            } else {
+                g = 1.0f / t;
+                kmax = fmaxf(kmax, (A + fabsf(m2f)) / t);
+            }
+            acc.add(r.rad.Wf[a] * (g * g));
+        }
+        r.out[e] = r.pref * ((double)acc.s - (double)acc.c);
+        if (r.err) r.err[e] = (double)(40.0f + 2.0f * kmax) * 5.9604644775390625e-8;
+    }
+}
+
+// Vertex families: lanes = (external point, radial sub-lane); contributions to scratch; the last
+// chunk of an external tile reduces in radial order.
+template <int FAM>
+__device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int et, int chunk,
+                                            double *__restrict__ contrib,
+                                            unsigned *__restrict__ counters) {
+    const int lq = 1 << r.lq_log2;
+    const int le = kWave >> r.lq_log2;
+    const int lane = (int)threadIdx.x;
+    const int el = lane >> r.lq_log2;
+    const int sub = lane & (lq - 1);
+    const int e = et * le + el;
+    const bool valid = e < r.n_ext;
+    const int a0 = (int)(((long long)r.n_q * chunk) / r.chunks);
+    const int a1 = (int)(((long long)r.n_q * (chunk + 1)) / r.chunks);
+    const double inv_k2 = 1.0 / r.k2;
+    double *blk = contrib + r.contrib_base;
+    float kmax = 1.0f;
+    if (valid) {
+        double p = r.ext[e];
+        double m2 = lane_m2(r, e);
+        double ca = 1.0, sa = 0.0;
+        if (FAM == 3) sincos(r.ext[r.n_ext + e], &sa, &ca);
+        for (int a = a0 + sub; a < a1; a += lq) {
+            double v;
+            if (r.precision == 0) {
+                v = (FAM == 2) ? contrib_two64(r, sm, a, p, m2, inv_k2)
+                               : contrib_three64(r, sm, a, p, ca, sa, m2, inv_k2);
+            } else {
+                v = (FAM == 2) ? contrib_two32(r, sm, a, p, m2, inv_k2, kmax)
+                               : contrib_three32(r, sm, a, p, ca, sa, m2, inv_k2, kmax);
+            }
+            blk[(long long)a * r.n_ext + e] = v;
+        }
+    }
+    // per-point slots after the tile counters (zero at rest): largest float32 amplification
+    unsigned *kslot = counters + r.ctr_base + r.ext_tiles;
+    if (r.precision == 1 && valid) atomicMax(&kslot[e], __float_as_uint(kmax));
+    // publish the contributions, then count this chunk
+    __threadfence();
+    __syncthreads();
+    __shared__ unsigned last;
+    if (lane == 0) {
+        unsigned old = atomicAdd(&counters[r.ctr_base + et], 1u);
+        last = (old == (unsigned)(r.chunks - 1)) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (lane < le) {
+        int ef = et * le + lane;
+        if (ef < r.n_ext) {
+            double s = 0.0;
+            for (int a = 0; a < r.n_q; ++a) {
+                unsigned long long bits = __hip_atomic_load(
+                    (unsigned long long *)(blk + (long long)a * r.n_ext + ef), __ATOMIC_RELAXED,
+                    __HIP_MEMORY_SCOPE_AGENT);
+                s += __longlong_as_double((long long)bits);
+            }
+            r.out[ef] = r.pref * s;
+            if (r.err) {
+                if (r.precision == 1) {
+                    unsigned kb = __hip_atomic_load(&kslot[ef], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+                    float km = __uint_as_float(kb);
+                    r.err[ef] = (double)(40.0f + 2.0f * km) * 5.9604644775390625e-8;
+                } else {
+                    r.err[ef] = 0.0;
+                }
+            }
+            if (r.precision == 1)
+                __hip_atomic_store(&kslot[ef], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    if (lane == 0) atomicExch(&counters[r.ctr_base + et], 0u);
+}
+
+__device__ __forceinline__ void run_tile(const ReqDev &r, Smem &sm, int et, int chunk,
+                                         double *contrib, unsigned *counters) {
+    if (r.family == 1)
+        tile_lpa(r, et);
+    else if (r.family == 2)
+        tile_vertex<2>(r, sm, et, chunk, contrib, counters);
+    else
+        tile_vertex<3>(r, sm, et, chunk, contrib, counters);
+}
+
+// One request: tile = blockIdx.x -> (external tile, chunk).
+template <int FAM>
+__global__ void __launch_bounds__(64) batch_kernel(ReqDev r, double *contrib, unsigned *counters) {
+    extern __shared__ double2 lds_z[];
+    Smem sm;
+    sm.Z64 = lds_z;
+    sm.Z32 = (float2 *)(lds_z + (r.nZ > 0 ? r.nZ : 0));
+    int et = blockIdx.x / r.chunks;
+    int chunk = blockIdx.x - et * r.chunks;
+    if (FAM != 1 && r.nZ > 0) {
+        stage_tables(r, sm);
+        __syncthreads();
+    }
+    if (FAM == 1)
+        tile_lpa(r, et);
+    else
+        tile_vertex<FAM>(r, sm, et, chunk, contrib, counters);
+}
+
+hipError_t launch_batch(const ReqDev *req_host, const ReqDev *req_dev_ptr, int n_tiles,
+                        int lds_bytes, double *contrib, unsigned *counters, hipStream_t s) {
+    (void)req_dev_ptr;
+    const ReqDev &r = *req_host;
+    if (n_tiles <= 0) return hipSuccess;
+    if (r.family == 1)
+        hipLaunchKernelGGL(batch_kernel<1>, dim3(n_tiles), dim3(kWave), 0, s, r, contrib,
+                           counters);
+    else if (r.family == 2)
+        hipLaunchKernelGGL(batch_kernel<2>, dim3(n_tiles), dim3(kWave), lds_bytes, s, r,
+                           contrib, counters);
+    else
+        hipLaunchKernelGGL(batch_kernel<3>, dim3(n_tiles), dim3(kWave), lds_bytes, s, r,
+                           contrib, counters);
+    return hipGetLastError();
+}
+
+// Many requests in one launch.  A grid sized to the device pulls tiles (ordered largest first by
+// the host) from a global counter until the list is empty; the last workgroup to leave resets the
+// counters, so the kernel can be relaunched (or replayed in a graph) without a memset.
+__global__ void __launch_bounds__(64) multi_kernel(const ReqDev *__restrict__ reqs,
+                                                   const TileDev *__restrict__ tiles, int n_tiles,
+                                                   double *contrib, unsigned *counters,
+                                                   unsigned *work) {
+    extern __shared__ double2 lds_z[];
+    __shared__ int tile_s;
+    Smem sm;
+    int staged = -1;
+    for (;;) {
+        if (threadIdx.x == 0) tile_s = (int)atomicAdd(&work[0], 1u);
+        __syncthreads();
+        int t = tile_s;
+        __syncthreads();
+        if (t >= n_tiles) break;
+        TileDev td = tiles[t];
+        const ReqDev &r = reqs[td.req];
+        sm.Z64 = lds_z;
+        sm.Z32 = (float2 *)(lds_z + r.nZ);
+        if (r.family != 1 && r.nZ > 0 && staged != td.req) {
+            stage_tables(r, sm);
+            __syncthreads();
+            staged = td.req;
+        }
+        run_tile(r, sm, td.et, td.chunk, contrib, counters);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned done = atomicAdd(&work[1], 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(&work[0], 0u);
+            atomicExch(&work[1], 0u);
+        }
+    }
+}
+
+hipError_t launch_multi(const ReqDev *reqs_dev, int n_reqs, const TileDev *tiles_dev,
+                        int n_tiles, int grid, int lds_bytes, double *contrib,
+                        unsigned *counters, unsigned *work_ctr, hipStream_t s) {
+    (void)n_reqs;
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(multi_kernel, dim3(grid), dim3(kWave), lds_bytes, s, reqs_dev, tiles_dev,
+                       n_tiles, contrib, counters, work_ctr);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------------------------
+// LPA flow state and assembly
+// --------------------------------------------------------------------------------------------
+// u', u'' at grid point i from the quadratic through three neighbouring points (Newton divided
+// differences; the stencil is shifted inwards at the two ends).
+__global__ void __launch_bounds__(64) lpa_state_kernel(int n, const double *__restrict__ rho,
+                                                       const double *__restrict__ u,
+                                                       double m2_floor, double *m2_out,
+                                                       double *fac_out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = i == 0 ? 1 : (i == n - 1 ? n - 2 : i);
+    double x0 = rho[c - 1], x1 = rho[c], x2 = rho[c + 1];
+    double f0 = u[c - 1], f1 = u[c], f2 = u[c + 1];
+    double d01 = (f1 - f0) / (x1 - x0);
+    double d12 = (f2 - f1) / (x2 - x1);
+    double d012 = (d12 - d01) / (x2 - x0);
+    double xi = rho[i];
+    double up = d01 + d012 * ((xi - x0) + (xi - x1));
+    double upp = 2.0 * d012;
+    double ms = u[i] + 2.0 * xi * up;
+    double mp = u[i];
+    m2_out[i] = fmax(ms, m2_floor);
+    m2_out[n + i] = fmax(mp, m2_floor);
+    fac_out[i] = 3.0 * up + 2.0 * xi * upp;
+    fac_out[n + i] = up;
+}
+
+__global__ void __launch_bounds__(64) lpa_assemble_kernel(int n, int n_comp,
+                                                          const double *__restrict__ I,
+                                                          const double *__restrict__ fac,
+                                                          double *dudt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dudt[i] = 0.5 * (I[i] * fac[i] + (double)(n_comp - 1) * I[n + i] * fac[n + i]);
+}
+
+hipError_t launch_lpa_state(int n, const double *rho, const double *u, double m2_floor,
+                            double *m2_out, double *fac_out, hipStream_t s) {
+    hipLaunchKernelGGL(lpa_state_kernel, dim3((n + 63) / 64), dim3(64), 0, s, n, rho, u,
+                       m2_floor, m2_out, fac_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_lpa_assemble(int n, int n_comp, const double *I, const double *fac,
+                               double *dudt, hipStream_t s) {
+    hipLaunchKernelGGL(lpa_assemble_kernel, dim3((n + 63) / 64), dim3(64), 0, s, n, n_comp, I,
+                       fac, dudt);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) fill_zero_u32_kernel(unsigned *p, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_fill_zero_u32(unsigned *p, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_zero_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       p, n);
+    return hipGetLastError();
+}
+
+}  // namespace frg

@@ -1,0 +1,659 @@
+// Host runtime of the loop-integral library: context, device-built quadrature-rule cache,
+// argument validation, tile planning, per-stream scratch, and the C-ABI entry points for batched
+// integration and flow right-hand sides.
+#include "frg_runtime.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+namespace frg {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_ptrs) {
+    if (!d || !b) {
+        set_error("null descriptor or batch");
+        return FRG_E_INVAL;
+    }
+    if (d->family < 1 || d->family > 3) {
+        set_error("family must be 1 (LPA), 2 (two-point) or 3 (three-point), got %d", d->family);
+        return FRG_E_INVAL;
+    }
+    if (d->precision != FRG_FP64 && d->precision != FRG_FP32_KAHAN) {
+        set_error("precision must be FRG_FP64 or FRG_FP32_KAHAN, got %d", d->precision);
+        return FRG_E_INVAL;
+    }
+    if (d->family == FRG_FAMILY_LPA) {
+        if (d->d < 1 || d->d > 8) {
+            set_error("LPA family needs 1 <= d <= 8, got %d", d->d);
+            return FRG_E_INVAL;
+        }
+    } else if (d->d != 4) {
+        set_error("vertex families are implemented for d = 4 only, got d = %d", d->d);
+        return FRG_E_UNSUPPORTED;
+    }
+    if (d->n_q < 1 || d->n_q > FRG_MAX_NODES) {
+        set_error("n_q must be in [1, %d], got %d", FRG_MAX_NODES, d->n_q);
+        return FRG_E_INVAL;
+    }
+    if (d->family >= 2 && (d->n_x < 1 || d->n_x > FRG_MAX_NODES)) {
+        set_error("n_x must be in [1, %d], got %d", FRG_MAX_NODES, d->n_x);
+        return FRG_E_INVAL;
+    }
+    if (d->family == 3 && (d->n_phi < 1 || d->n_phi > FRG_MAX_NODES)) {
+        set_error("n_phi must be in [1, %d], got %d", FRG_MAX_NODES, d->n_phi);
+        return FRG_E_INVAL;
+    }
+    if (!finite_pos(d->q_max) || !finite_pos(d->k)) {
+        set_error("q_max and k must be finite and > 0");
+        return FRG_E_INVAL;
+    }
+    if (!std::isfinite(d->near_pole_tau) || d->near_pole_tau < 0.0 || d->near_pole_tau >= 1.0) {
+        set_error("near_pole_tau must be in [0, 1)");
+        return FRG_E_INVAL;
+    }
+    if (b->n_ext < 0 || b->n_ext > (1 << 24)) {
+        set_error("n_ext must be in [0, 2^24], got %d", b->n_ext);
+        return FRG_E_INVAL;
+    }
+    if (b->n_ext == 0) return FRG_OK;
+    if (!b->out) {
+        set_error("out is NULL");
+        return FRG_E_INVAL;
+    }
+    if (d->family >= 2 && !b->ext) {
+        set_error("ext is NULL for a vertex family");
+        return FRG_E_INVAL;
+    }
+    if (!b->m2 && !std::isfinite(b->m2_scalar)) {
+        set_error("m2_scalar is not finite");
+        return FRG_E_INVAL;
+    }
+    if (d->family >= 2 && b->Z.values) {
+        if (b->Z.n < 2 || b->Z.n > FRG_MAX_TABLE) {
+            set_error("dressing table size must be in [2, %d], got %d", FRG_MAX_TABLE, b->Z.n);
+            return FRG_E_INVAL;
+        }
+        if (!finite_pos(b->Z.x_min) || !finite_pos(b->Z.x_max) || !(b->Z.x_max > b->Z.x_min)) {
+            set_error("dressing grid needs 0 < x_min < x_max");
+            return FRG_E_INVAL;
+        }
+    }
+    if ((double)d->n_q * (double)b->n_ext > 2.0e9) {
+        set_error("n_q * n_ext too large for one batch");
+        return FRG_E_INVAL;
+    }
+    if (device_ptrs) {
+        // every pointer the kernels dereference must be device-accessible memory
+        const void *ptrs[4] = {b->ext, b->m2, b->out, b->err_out};
+        for (const void *p : ptrs) {
+            if (!p) continue;
+            hipPointerAttribute_t attr;
+            if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+                (void)hipGetLastError();
+                set_error("pointer %p is not HIP device memory", p);
+                return FRG_E_INVAL;
+            }
+            if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) {
+                set_error("pointer %p is not HIP device memory", p);
+                return FRG_E_INVAL;
+            }
+        }
+        if (d->family >= 2 && b->Z.values) {
+            hipPointerAttribute_t attr;
+            if (hipPointerGetAttributes(&attr, b->Z.values) != hipSuccess ||
+                (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)) {
+                (void)hipGetLastError();
+                set_error("dressing table is not HIP device memory");
+                return FRG_E_INVAL;
+            }
+        }
+    }
+    return FRG_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Rule cache
+// ---------------------------------------------------------------------------------------------
+static frg_status get_radial(frg_context *ctx, int n, double q_max, int d, RadialRule *out) {
+    auto key = std::make_tuple(n, q_max, d);
+    auto it = ctx->radial.find(key);
+    if (it == ctx->radial.end()) {
+        auto e = std::make_unique<RadialEntry>();
+        size_t nb = (size_t)n * (3 * sizeof(double) + 3 * sizeof(float)) + 64;
+        FRG_HIP_CHECK(e->buf.alloc(nb));
+        double *q = (double *)e->buf.ptr, *W = q + n, *R = W + n;
+        float *qf = (float *)(R + n), *Wf = qf + n, *Rf = Wf + n;
+        FRG_HIP_CHECK(launch_rules(n, q_max, d, 0, 0, q, W, R, qf, Wf, Rf, nullptr, nullptr,
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   nullptr, ctx->aux));
+        FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
+        e->rule = RadialRule{q, W, R, qf, Wf, Rf};
+        it = ctx->radial.emplace(key, std::move(e)).first;
+    }
+    *out = it->second->rule;
+    return FRG_OK;
+}
+
+static frg_status get_cos1(frg_context *ctx, int n, AngleRule *out) {
+    auto it = ctx->cos1.find(n);
+    if (it == ctx->cos1.end()) {
+        auto e = std::make_unique<AngleEntry>();
+        FRG_HIP_CHECK(e->buf.alloc((size_t)n * (3 * sizeof(double) + 3 * sizeof(float)) + 64));
+        double *x = (double *)e->buf.ptr, *xw = x + n, *xs = xw + n;
+        float *xf = (float *)(xs + n), *xwf = xf + n, *xsf = xwf + n;
+        FRG_HIP_CHECK(launch_rules(0, 1.0, 1, n, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   nullptr, x, xw, xs, xf, xwf, xsf, nullptr, nullptr, nullptr,
+                                   nullptr, ctx->aux));
+        FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
+        e->rule = AngleRule{x, xw, xs, xf, xwf, xsf};
+        it = ctx->cos1.emplace(n, std::move(e)).first;
+    }
+    *out = it->second->rule;
+    return FRG_OK;
+}
+
+static frg_status get_phi(frg_context *ctx, int n, PhiRule *out) {
+    auto it = ctx->phi.find(n);
+    if (it == ctx->phi.end()) {
+        auto e = std::make_unique<PhiEntry>();
+        FRG_HIP_CHECK(e->buf.alloc((size_t)n * (2 * sizeof(double) + 2 * sizeof(float)) + 64));
+        double *c = (double *)e->buf.ptr, *w = c + n;
+        float *cf = (float *)(w + n), *wf = cf + n;
+        FRG_HIP_CHECK(launch_rules(0, 1.0, 1, 0, n, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c,
+                                   w, cf, wf, ctx->aux));
+        FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
+        e->rule = PhiRule{c, w, cf, wf};
+        it = ctx->phi.emplace(n, std::move(e)).first;
+    }
+    *out = it->second->rule;
+    return FRG_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Planning
+// ---------------------------------------------------------------------------------------------
+static int ilog2(int v) {
+    int r = 0;
+    while ((1 << (r + 1)) <= v) ++r;
+    return r;
+}
+
+TileShape heuristic_shape(const frg_integral_desc &d, int n_ext, int target_waves) {
+    TileShape s;
+    if (d.family == 1) return s;
+    // external points per wavefront: the smallest power of two >= n_ext, at least 4
+    int le = kWave;
+    while (le > 4 && le / 2 >= n_ext) le /= 2;
+    s.lq_log2 = ilog2(kWave / le);
+    int lq = 1 << s.lq_log2;
+    int ext_tiles = (n_ext + le - 1) / le;
+    int max_chunks = (d.n_q + lq - 1) / lq;  // at least one radial node per lane and chunk
+    int want = (target_waves + ext_tiles - 1) / std::max(ext_tiles, 1);
+    s.chunks = std::max(1, std::min(max_chunks, want));
+    return s;
+}
+
+TileShape choose_shape(frg_context *ctx, const frg_integral_desc &d, int n_ext, int target_waves) {
+    std::vector<int> key = {d.family, d.precision, d.n_q, d.n_x, d.n_phi, n_ext, target_waves};
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) return it->second;
+    return heuristic_shape(d, n_ext, target_waves);
+}
+
+size_t contrib_doubles(const ReqDev &r) {
+    if (r.family == 1) return 0;
+    return (size_t)r.n_q * (size_t)r.n_ext;  // [n_q][n_ext] contributions
+}
+
+int counter_count(const ReqDev &r) {
+    // one counter per external tile, then (float32 form) one amplification slot per point
+    if (r.family == 1) return 0;
+    return r.ext_tiles + (r.precision == 1 ? r.n_ext : 0);
+}
+
+int tile_count(const ReqDev &r) { return r.ext_tiles * r.chunks; }
+
+int lds_bytes_for(const ReqDev &r) {
+    if (r.family == 1 || r.nZ == 0) return 0;
+    return r.nZ * (int)sizeof(double2) + (r.precision == 1 ? r.nZ * (int)sizeof(float2) : 0);
+}
+
+frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_batch &b,
+                        const TileShape &shape, int m2_mode, double m2_floor, double coef,
+                        ReqDev *out) {
+    ReqDev r;
+    std::memset(&r, 0, sizeof r);
+    r.family = d.family;
+    r.d = d.d;
+    r.n_q = d.n_q;
+    r.n_x = d.family >= 2 ? d.n_x : 0;
+    r.n_phi = d.family == 3 ? d.n_phi : 0;
+    r.precision = d.precision;
+    r.n_ext = b.n_ext;
+    r.lq_log2 = d.family == 1 ? 0 : shape.lq_log2;
+    r.chunks = d.family == 1 ? 1 : shape.chunks;
+    int le = kWave >> r.lq_log2;
+    r.ext_tiles = (b.n_ext + le - 1) / le;
+    r.k = d.k;
+    r.k2 = d.k * d.k;
+    const double pi = 3.141592653589793238462643383279502884;
+    double omega;
+    if (d.family == 1)
+        omega = 2.0 * std::pow(pi, 0.5 * d.d) / std::tgamma(0.5 * d.d) / std::pow(2.0 * pi, d.d);
+    else if (d.family == 2)
+        omega = 4.0 * pi / std::pow(2.0 * pi, 4);
+    else
+        omega = 2.0 * pi / std::pow(2.0 * pi, 4);
+    r.pref = omega * std::pow(d.k, d.d + 2) * coef;
+    r.m2_mode = b.m2 ? m2_mode : 0;
+    r.m2s = b.m2_scalar;
+    r.m2_floor = m2_floor;
+    r.tau = d.precision == 1 ? d.near_pole_tau : 0.0;
+    if (d.family >= 2 && b.Z.values) {
+        r.nZ = b.Z.n;
+        double lmin = std::log(b.Z.x_min), lmax = std::log(b.Z.x_max);
+        double delta = (lmax - lmin) / (double)(b.Z.n - 1);
+        r.za = 0.5 / delta;
+        r.zb = -lmin / delta;
+        r.Z = b.Z.values;
+    }
+    frg_status st = get_radial(ctx, d.n_q, d.q_max, d.d, &r.rad);
+    if (st != FRG_OK) return st;
+    if (d.family >= 2) {
+        st = get_cos1(ctx, d.n_x, &r.ang);
+        if (st != FRG_OK) return st;
+    }
+    if (d.family == 3) {
+        st = get_phi(ctx, d.n_phi, &r.phi);
+        if (st != FRG_OK) return st;
+    }
+    r.ext = b.ext;
+    r.m2 = b.m2;
+    r.out = b.out;
+    r.err = b.err_out;
+    *out = r;
+    return FRG_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Scratch and launches
+// ---------------------------------------------------------------------------------------------
+static frg_status grow(DeviceBuffer &buf, size_t bytes, hipStream_t s, bool zero_u32) {
+    if (buf.bytes >= bytes && buf.ptr) return FRG_OK;
+    if (buf.ptr) {
+        // queued work on this stream may still use the old buffer
+        FRG_HIP_CHECK(hipStreamSynchronize(s));
+        FRG_HIP_CHECK(hipFree(buf.ptr));
+        buf.ptr = nullptr;
+        buf.bytes = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 4096);
+    want = want + want / 2;
+    FRG_HIP_CHECK(buf.alloc(want));
+    if (zero_u32) FRG_HIP_CHECK(launch_fill_zero_u32((unsigned *)buf.ptr, want / 4, s));
+    return FRG_OK;
+}
+
+frg_status get_scratch(frg_context *ctx, hipStream_t s, size_t n_contrib, size_t n_counters,
+                       size_t n_reqs, size_t n_tiles, Scratch **out) {
+    auto &slot = ctx->scratch[s];
+    if (!slot) slot = std::make_unique<Scratch>();
+    Scratch *sc = slot.get();
+    frg_status st;
+    if ((st = grow(sc->contrib, n_contrib * sizeof(double), s, false)) != FRG_OK) return st;
+    if ((st = grow(sc->counters, n_counters * sizeof(unsigned), s, true)) != FRG_OK) return st;
+    if ((st = grow(sc->work, 2 * sizeof(unsigned), s, true)) != FRG_OK) return st;
+    sc->last_key.clear();
+    if ((st = grow(sc->reqs, n_reqs * sizeof(ReqDev), s, false)) != FRG_OK) return st;
+    if ((st = grow(sc->tiles, n_tiles * sizeof(TileDev), s, false)) != FRG_OK) return st;
+    *out = sc;
+    return FRG_OK;
+}
+
+frg_status run_batch(frg_context *ctx, ReqDev &r, hipStream_t s, Scratch *sc) {
+    (void)ctx;
+    r.contrib_base = 0;
+    r.ctr_base = 0;
+    FRG_HIP_CHECK(launch_batch(&r, nullptr, tile_count(r), lds_bytes_for(r),
+                               (double *)sc->contrib.ptr, (unsigned *)sc->counters.ptr, s));
+    return FRG_OK;
+}
+
+frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s, Scratch *sc,
+                     int grid_waves) {
+    (void)ctx;
+    std::vector<TileDev> tiles;
+    std::vector<double> cost;
+    long long cb = 0;
+    int ctr = 0, lds = 0;
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        ReqDev &r = reqs[i];
+        r.contrib_base = cb;
+        r.ctr_base = ctr;
+        cb += (long long)contrib_doubles(r);
+        ctr += counter_count(r);
+        lds = std::max(lds, lds_bytes_for(r));
+        int lq = 1 << r.lq_log2;
+        double inner = r.family == 1 ? 1.0 : (double)r.n_x * (r.family == 3 ? r.n_phi : 1);
+        for (int et = 0; et < r.ext_tiles; ++et)
+            for (int ch = 0; ch < r.chunks; ++ch) {
+                int a0 = (int)(((long long)r.n_q * ch) / r.chunks);
+                int a1 = (int)(((long long)r.n_q * (ch + 1)) / r.chunks);
+                double c = r.family == 1 ? (double)r.n_q : std::ceil((double)(a1 - a0) / lq) * inner;
+                tiles.push_back(TileDev{(int)i, et, ch, 0});
+                cost.push_back(c);
+            }
+    }
+    if (tiles.empty()) return FRG_OK;
+    // longest-processing-time-first order; ties keep request/tile order
+    std::vector<int> order(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<TileDev> sorted(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) sorted[i] = tiles[order[i]];
+    size_t rb = reqs.size() * sizeof(ReqDev), tb = sorted.size() * sizeof(TileDev);
+    if (!sc->staged) FRG_HIP_CHECK(hipEventCreateWithFlags(&sc->staged, hipEventDisableTiming));
+    // the previous upload from the staging area must have finished before it is rewritten
+    FRG_HIP_CHECK(hipEventSynchronize(sc->staged));
+    if (sc->host_bytes < rb + tb) {
+        if (sc->host_stage) FRG_HIP_CHECK(hipHostFree(sc->host_stage));
+        sc->host_stage = nullptr;
+        sc->host_bytes = 0;
+        size_t want = (rb + tb) + (rb + tb) / 2 + 4096;
+        FRG_HIP_CHECK(hipHostMalloc(&sc->host_stage, want, hipHostMallocDefault));
+        sc->host_bytes = want;
+    }
+    std::memcpy(sc->host_stage, reqs.data(), rb);
+    std::memcpy((char *)sc->host_stage + rb, sorted.data(), tb);
+    FRG_HIP_CHECK(hipMemcpyAsync(sc->reqs.ptr, sc->host_stage, rb, hipMemcpyHostToDevice, s));
+    FRG_HIP_CHECK(hipMemcpyAsync(sc->tiles.ptr, (char *)sc->host_stage + rb, tb,
+                                 hipMemcpyHostToDevice, s));
+    FRG_HIP_CHECK(hipEventRecord(sc->staged, s));
+    sc->last_tiles = (int)sorted.size();
+    sc->last_grid = std::min<int>((int)sorted.size(), std::max(grid_waves, 1));
+    sc->last_lds = lds;
+    sc->last_nreqs = (int)reqs.size();
+    return relaunch_multi(sc, s);
+}
+
+frg_status relaunch_multi(Scratch *sc, hipStream_t s) {
+    FRG_HIP_CHECK(launch_multi((const ReqDev *)sc->reqs.ptr, sc->last_nreqs,
+                               (const TileDev *)sc->tiles.ptr, sc->last_tiles, sc->last_grid,
+                               sc->last_lds, (double *)sc->contrib.ptr,
+                               (unsigned *)sc->counters.ptr, (unsigned *)sc->work.ptr, s));
+    return FRG_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Flow right-hand sides, captured as HIP graphs
+// ---------------------------------------------------------------------------------------------
+struct FlowGraph {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    DeviceBuffer work;      // LPA: m2 [2n], fac [2n], I [2n]
+    DeviceBuffer contrib;
+    DeviceBuffer counters;
+    ~FlowGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+}  // namespace frg
+
+using namespace frg;
+
+extern "C" {
+
+const char *frg_last_error(void) { return g_last_error.c_str(); }
+
+frg_status frg_context_create(int device, size_t hbm_budget_bytes, frg_context **out) {
+    clear_error();
+    if (!out) {
+        set_error("out is NULL");
+        return FRG_E_INVAL;
+    }
+    int n = 0;
+    FRG_HIP_CHECK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) {
+        set_error("device %d out of range (%d devices)", device, n);
+        return FRG_E_INVAL;
+    }
+    FRG_HIP_CHECK(hipSetDevice(device));
+    auto ctx = std::make_unique<frg_context>();
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    FRG_HIP_CHECK(hipGetDeviceProperties(&prop, device));
+    ctx->num_cus = prop.multiProcessorCount;
+    size_t free_b = 0, total_b = 0;
+    FRG_HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
+    ctx->hbm_budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
+    FRG_HIP_CHECK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    const char *tp = std::getenv("FRG_AUTOTUNE_CACHE");
+    if (tp) ctx->tune_path = tp;
+    *out = ctx.release();
+    return FRG_OK;
+}
+
+frg_status frg_context_destroy(frg_context *ctx) {
+    clear_error();
+    if (!ctx) return FRG_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->graphs.clear();
+    ctx->scratch.clear();
+    ctx->radial.clear();
+    ctx->cos1.clear();
+    ctx->phi.clear();
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+    delete ctx;
+    return FRG_OK;
+}
+
+frg_status frg_integrate_batch(frg_context *ctx, const frg_integral_desc *desc,
+                               const frg_batch *batch, hipStream_t stream) {
+    clear_error();
+    if (!ctx) {
+        set_error("context is NULL");
+        return FRG_E_INVAL;
+    }
+    frg_status st = validate(desc, batch, true);
+    if (st != FRG_OK) return st;
+    if (batch->n_ext == 0) return FRG_OK;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    FRG_HIP_CHECK(hipSetDevice(ctx->device));
+    TileShape shape = choose_shape(ctx, *desc, batch->n_ext, 16 * ctx->num_cus);
+    ReqDev r;
+    if ((st = make_request(ctx, *desc, *batch, shape, 1, 0.0, 1.0, &r)) != FRG_OK) return st;
+    Scratch *sc;
+    if ((st = get_scratch(ctx, stream, contrib_doubles(r), counter_count(r), 1, 1, &sc)) != FRG_OK)
+        return st;
+    return run_batch(ctx, r, stream, sc);
+}
+
+frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc *descs,
+                               const frg_batch *batches, hipStream_t stream) {
+    clear_error();
+    if (!ctx || n < 0 || (n > 0 && (!descs || !batches))) {
+        set_error("invalid arguments to frg_integrate_multi");
+        return FRG_E_INVAL;
+    }
+    frg_status st;
+    // plan cache: the same arguments as the previous fused call on this stream relaunch the
+    // uploaded plan directly (flows re-evaluate the same batches every stage)
+    std::vector<char> key((size_t)n * (sizeof(frg_integral_desc) + sizeof(frg_batch)));
+    if (n > 0) {
+        std::memcpy(key.data(), descs, (size_t)n * sizeof(frg_integral_desc));
+        std::memcpy(key.data() + (size_t)n * sizeof(frg_integral_desc), batches,
+                    (size_t)n * sizeof(frg_batch));
+    }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->scratch.find(stream);
+        if (n > 0 && it != ctx->scratch.end() && it->second->last_key == key &&
+            it->second->last_tiles > 0) {
+            FRG_HIP_CHECK(hipSetDevice(ctx->device));
+            return relaunch_multi(it->second.get(), stream);
+        }
+    }
+    double total_nodes = 0.0;
+    std::vector<double> nodes(n);
+    for (int i = 0; i < n; ++i) {
+        if ((st = validate(&descs[i], &batches[i], true)) != FRG_OK) {
+            std::string m = g_last_error;
+            set_error("batch %d: %s", i, m.c_str());
+            return st;
+        }
+        const frg_integral_desc &d = descs[i];
+        double per = (double)d.n_q * (d.family >= 2 ? d.n_x : 1) * (d.family == 3 ? d.n_phi : 1);
+        nodes[i] = per * batches[i].n_ext;
+        total_nodes += nodes[i];
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    FRG_HIP_CHECK(hipSetDevice(ctx->device));
+    std::vector<ReqDev> reqs;
+    size_t n_contrib = 0, n_ctr = 0, n_tiles = 0;
+    const int target_total = 16 * ctx->num_cus;
+    for (int i = 0; i < n; ++i) {
+        if (batches[i].n_ext == 0) continue;
+        int target = std::max(1, (int)std::lround(target_total * nodes[i] / total_nodes));
+        TileShape shape = choose_shape(ctx, descs[i], batches[i].n_ext, target);
+        ReqDev r;
+        if ((st = make_request(ctx, descs[i], batches[i], shape, 1, 0.0, 1.0, &r)) != FRG_OK)
+            return st;
+        n_contrib += contrib_doubles(r);
+        n_ctr += counter_count(r);
+        n_tiles += tile_count(r);
+        reqs.push_back(r);
+    }
+    if (reqs.empty()) return FRG_OK;
+    Scratch *sc;
+    if ((st = get_scratch(ctx, stream, n_contrib, n_ctr, reqs.size(), n_tiles, &sc)) != FRG_OK)
+        return st;
+    sc->last_key.clear();
+    if ((st = run_multi(ctx, reqs, stream, sc, 8 * ctx->num_cus)) != FRG_OK) return st;
+    sc->last_key = std::move(key);
+    return FRG_OK;
+}
+
+frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
+                        const frg_flow_state *state, double *dstate_dt, hipStream_t stream) {
+    clear_error();
+    if (!ctx || !desc || !state || !dstate_dt) {
+        set_error("null argument to frg_flow_rhs");
+        return FRG_E_INVAL;
+    }
+    if (state->family != desc->family) {
+        set_error("flow state family %d does not match descriptor family %d", state->family,
+                  desc->family);
+        return FRG_E_INVAL;
+    }
+    const int n = state->n_ext;
+    if (!state->state || !state->grid || n < (desc->family == 1 ? 3 : 1)) {
+        set_error("flow state needs state and grid pointers and n_ext >= %d",
+                  desc->family == 1 ? 3 : 1);
+        return FRG_E_INVAL;
+    }
+    if (desc->family == 1 && state->n_comp < 1) {
+        set_error("n_comp must be >= 1");
+        return FRG_E_INVAL;
+    }
+    if (!std::isfinite(state->m2_floor) || !std::isfinite(state->coef)) {
+        set_error("m2_floor and coef must be finite");
+        return FRG_E_INVAL;
+    }
+    // the batch the integrals run on (pointers filled below)
+    frg_batch b;
+    std::memset(&b, 0, sizeof b);
+    b.n_ext = desc->family == 1 ? 2 * n : n;
+    b.ext = desc->family == 1 ? nullptr : state->grid;
+    b.m2 = state->state;
+    b.Z = state->Z;
+    b.out = dstate_dt;
+    frg_status st = validate(desc, &b, true);
+    if (st != FRG_OK) return st;
+
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    FRG_HIP_CHECK(hipSetDevice(ctx->device));
+    std::vector<long long> key = {desc->family, desc->d, desc->n_q, desc->n_x, desc->n_phi,
+                                  desc->precision, n, state->n_comp, (long long)stream,
+                                  (long long)state->state, (long long)state->grid,
+                                  (long long)state->Z.values, state->Z.n, (long long)dstate_dt};
+    double dk[7] = {desc->q_max, desc->k, desc->near_pole_tau, state->m2_floor, state->coef,
+                    state->Z.x_min, state->Z.x_max};
+    for (double v : dk) {
+        long long bits;
+        std::memcpy(&bits, &v, sizeof bits);
+        key.push_back(bits);
+    }
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        auto g = std::make_unique<FlowGraph>();
+        TileShape shape = choose_shape(ctx, *desc, b.n_ext, 16 * ctx->num_cus);
+        ReqDev r;
+        double *m2buf = nullptr, *fac = nullptr, *Ibuf = nullptr;
+        if (desc->family == 1) {
+            FRG_HIP_CHECK(g->work.alloc(6 * (size_t)n * sizeof(double)));
+            m2buf = (double *)g->work.ptr;
+            fac = m2buf + 2 * n;
+            Ibuf = fac + 2 * n;
+            b.m2 = m2buf;
+            b.out = Ibuf;
+            if ((st = make_request(ctx, *desc, b, shape, 1, 0.0, 1.0, &r)) != FRG_OK) return st;
+        } else {
+            if ((st = make_request(ctx, *desc, b, shape, 2, state->m2_floor, state->coef, &r)) !=
+                FRG_OK)
+                return st;
+        }
+        FRG_HIP_CHECK(g->contrib.alloc(std::max<size_t>(contrib_doubles(r), 1) * sizeof(double)));
+        FRG_HIP_CHECK(
+            g->counters.alloc(std::max<size_t>(counter_count(r), 1) * sizeof(unsigned)));
+        FRG_HIP_CHECK(launch_fill_zero_u32((unsigned *)g->counters.ptr,
+                                           std::max<size_t>(counter_count(r), 1), ctx->aux));
+        FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
+        r.contrib_base = 0;
+        r.ctr_base = 0;
+        FRG_HIP_CHECK(hipStreamBeginCapture(ctx->aux, hipStreamCaptureModeThreadLocal));
+        hipError_t e1 = hipSuccess;
+        if (desc->family == 1)
+            e1 = launch_lpa_state(n, state->grid, state->state, state->m2_floor, m2buf, fac,
+                                  ctx->aux);
+        if (e1 == hipSuccess)
+            e1 = launch_batch(&r, nullptr, tile_count(r), lds_bytes_for(r),
+                              (double *)g->contrib.ptr, (unsigned *)g->counters.ptr, ctx->aux);
+        if (e1 == hipSuccess && desc->family == 1)
+            e1 = launch_lpa_assemble(n, state->n_comp, Ibuf, fac, dstate_dt, ctx->aux);
+        hipError_t e2 = hipStreamEndCapture(ctx->aux, &g->graph);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            set_error("graph capture failed: %s / %s", hipGetErrorString(e1),
+                      hipGetErrorString(e2));
+            return FRG_E_DEVICE;
+        }
+        FRG_HIP_CHECK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+        it = ctx->graphs.emplace(key, std::move(g)).first;
+    }
+    FRG_HIP_CHECK(hipGraphLaunch(it->second->exec, stream));
+    return FRG_OK;
+}
+
+}  // extern "C"

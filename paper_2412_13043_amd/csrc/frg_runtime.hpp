@@ -1,0 +1,138 @@
+// Host runtime internals shared by the C-ABI entry points and the serving loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/frg.h"
+#include "frg_internal.hpp"
+
+namespace frg {
+
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define FRG_HIP_CHECK(expr)                                                                   \
+    do {                                                                                      \
+        hipError_t _e = (expr);                                                               \
+        if (_e != hipSuccess) {                                                               \
+            ::frg::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                             __LINE__);                                                       \
+            return FRG_E_DEVICE;                                                              \
+        }                                                                                     \
+    } while (0)
+
+struct DeviceBuffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DeviceBuffer() = default;
+    DeviceBuffer(const DeviceBuffer &) = delete;
+    DeviceBuffer &operator=(const DeviceBuffer &) = delete;
+    ~DeviceBuffer() {
+        if (ptr) (void)hipFree(ptr);
+    }
+    hipError_t alloc(size_t n) {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, n > 0 ? n : 1);
+        if (e == hipSuccess) {
+            ptr = p;
+            bytes = n;
+        }
+        return e;
+    }
+};
+
+struct RadialEntry {
+    DeviceBuffer buf;
+    RadialRule rule;
+};
+struct AngleEntry {
+    DeviceBuffer buf;
+    AngleRule rule;
+};
+struct PhiEntry {
+    DeviceBuffer buf;
+    PhiRule rule;
+};
+
+// Per-stream scratch: contribution blocks, per-external-tile counters, work counters, and the
+// request/tile tables of fused launches.  Counters are zero at rest (kernels reset them).
+struct Scratch {
+    DeviceBuffer contrib;   // doubles
+    DeviceBuffer counters;  // u32, zero at rest
+    DeviceBuffer work;      // 2 x u32, zero at rest
+    DeviceBuffer reqs;      // ReqDev[]
+    DeviceBuffer tiles;     // TileDev[]
+    // pinned staging for the request/tile tables of fused launches; `staged` is recorded after
+    // the upload so the staging area is not rewritten while a copy may still read it
+    void *host_stage = nullptr;
+    size_t host_bytes = 0;
+    hipEvent_t staged = nullptr;
+    // last fused call on this stream: its argument bytes and launch shape (plan cache)
+    std::vector<char> last_key;
+    int last_tiles = 0, last_grid = 0, last_lds = 0, last_nreqs = 0;
+    ~Scratch() {
+        if (host_stage) (void)hipHostFree(host_stage);
+        if (staged) (void)hipEventDestroy(staged);
+    }
+};
+
+// Tile shape of one request for the vertex families (the LPA family always uses lanes = points).
+struct TileShape {
+    int lq_log2 = 0;
+    int chunks = 1;
+};
+
+struct FlowGraph;
+
+}  // namespace frg
+
+struct frg_context {
+    int device = 0;
+    size_t hbm_budget = 0;
+    int num_cus = 256;
+    std::mutex mu;
+    hipStream_t aux = nullptr;  // rule construction and graph capture
+    std::map<std::tuple<int, double, int>, std::unique_ptr<frg::RadialEntry>> radial;
+    std::map<int, std::unique_ptr<frg::AngleEntry>> cos1;
+    std::map<int, std::unique_ptr<frg::PhiEntry>> phi;
+    std::map<hipStream_t, std::unique_ptr<frg::Scratch>> scratch;
+    std::map<std::vector<long long>, std::unique_ptr<frg::FlowGraph>> graphs;
+    std::map<std::vector<int>, frg::TileShape> tuned;  // autotuned shapes (loaded/saved on disk)
+    std::string tune_path;
+};
+
+namespace frg {
+
+// Validate a descriptor/batch pair; FRG_E_INVAL with a message on failure.
+frg_status validate(const frg_integral_desc *desc, const frg_batch *batch, bool device_ptrs);
+// Fill a ReqDev for a validated request (rules resolved through the context cache).
+frg_status make_request(frg_context *ctx, const frg_integral_desc &desc, const frg_batch &b,
+                        const TileShape &shape, int m2_mode, double m2_floor, double coef,
+                        ReqDev *out);
+// Tile shape for a request: autotuned entry if one exists, else the heuristic.
+TileShape choose_shape(frg_context *ctx, const frg_integral_desc &desc, int n_ext,
+                       int target_waves);
+TileShape heuristic_shape(const frg_integral_desc &desc, int n_ext, int target_waves);
+// Doubles of contribution scratch and counters a request needs.
+size_t contrib_doubles(const ReqDev &r);
+int counter_count(const ReqDev &r);
+int tile_count(const ReqDev &r);
+// Scratch for a stream, grown to at least the given sizes.
+frg_status get_scratch(frg_context *ctx, hipStream_t s, size_t contrib_doubles, size_t counters,
+                       size_t n_reqs, size_t n_tiles, Scratch **out);
+// Launch helpers (caller holds ctx->mu).
+frg_status run_batch(frg_context *ctx, ReqDev &r, hipStream_t s, Scratch *sc);
+frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s, Scratch *sc,
+                     int grid_waves);
+frg_status relaunch_multi(Scratch *sc, hipStream_t s);
+int lds_bytes_for(const ReqDev &r);
+
+}  // namespace frg

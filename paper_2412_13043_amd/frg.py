@@ -1,0 +1,266 @@
+"""Thin ctypes binding of the C ABI in include/frg.h (argument marshalling only).
+
+Every computation runs in libfrg.so's HIP kernels.  torch is used for device memory (tensors
+whose data_ptr() are handed to the library) and for streams.  There is no CPU fallback: if the
+built library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_size_t, c_uint64, c_void_p
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfrg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it first (python -m paper_2412_13043_amd.build, or "
+        "__graft_entry__.build()); there is no fallback path")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- enums (frg.h) --------------------------------------------------------------------------
+FRG_OK, FRG_E_INVAL, FRG_E_NOMEM, FRG_E_DEVICE, FRG_E_NOTREADY, FRG_E_TIMEOUT, \
+    FRG_E_CANCELLED, FRG_E_UNSUPPORTED = range(8)
+FRG_FP64, FRG_FP32_KAHAN = 0, 1
+FRG_FAMILY_LPA, FRG_FAMILY_TWO_POINT, FRG_FAMILY_THREE_POINT = 1, 2, 3
+FRG_MAX_NODES = 1024
+FRG_MAX_TABLE = 4096
+
+STATUS_NAMES = {0: "FRG_OK", 1: "FRG_E_INVAL", 2: "FRG_E_NOMEM", 3: "FRG_E_DEVICE",
+                4: "FRG_E_NOTREADY", 5: "FRG_E_TIMEOUT", 6: "FRG_E_CANCELLED",
+                7: "FRG_E_UNSUPPORTED"}
+
+
+class FrgError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+# ---- structs (frg.h) ------------------------------------------------------------------------
+class frg_integral_desc(ctypes.Structure):
+    _fields_ = [("family", c_int), ("d", c_int), ("n_q", c_int), ("n_x", c_int),
+                ("n_phi", c_int), ("precision", c_int), ("q_max", c_double), ("k", c_double),
+                ("near_pole_tau", c_double)]
+
+
+class frg_log_table(ctypes.Structure):
+    _fields_ = [("values", c_void_p), ("n", c_int), ("x_min", c_double), ("x_max", c_double)]
+
+
+class frg_batch(ctypes.Structure):
+    _fields_ = [("n_ext", c_int), ("ext", c_void_p), ("m2", c_void_p), ("m2_scalar", c_double),
+                ("Z", frg_log_table), ("out", c_void_p), ("err_out", c_void_p)]
+
+
+class frg_flow_state(ctypes.Structure):
+    _fields_ = [("family", c_int), ("n_ext", c_int), ("state", c_void_p), ("grid", c_void_p),
+                ("Z", frg_log_table), ("n_comp", c_int), ("m2_floor", c_double),
+                ("coef", c_double)]
+
+
+class frg_session_config(ctypes.Structure):
+    _fields_ = [("max_inflight", c_int), ("hbm_budget_bytes", c_size_t), ("poll_us", c_int),
+                ("watchdog_ms", c_int)]
+
+
+class frg_stats(ctypes.Structure):
+    _fields_ = [("p50_us", c_double), ("p99_us", c_double), ("gnodes_per_s", c_double),
+                ("admitted", c_uint64), ("queued", c_uint64), ("rejected", c_uint64),
+                ("completed", c_uint64), ("failed", c_uint64), ("cancelled", c_uint64),
+                ("nodes", c_uint64), ("launches", c_uint64)]
+
+
+_P = c_void_p
+_sig = {
+    "frg_context_create": ([c_int, c_size_t, POINTER(c_void_p)], c_int),
+    "frg_context_destroy": ([_P], c_int),
+    "frg_last_error": ([], c_char_p),
+    "frg_integrate_batch": ([_P, POINTER(frg_integral_desc), POINTER(frg_batch), _P], c_int),
+    "frg_integrate_multi": ([_P, c_int, POINTER(frg_integral_desc), POINTER(frg_batch), _P],
+                            c_int),
+    "frg_flow_rhs": ([_P, POINTER(frg_integral_desc), POINTER(frg_flow_state), _P, _P], c_int),
+    "frg_session_open": ([_P, POINTER(frg_session_config), POINTER(c_void_p)], c_int),
+    "frg_session_register_table": ([_P, _P, c_int, c_double, c_double, POINTER(c_int)], c_int),
+    "frg_session_submit": ([_P, POINTER(frg_integral_desc), POINTER(frg_batch), c_int,
+                            POINTER(c_uint64)], c_int),
+    "frg_session_poll": ([_P, c_uint64, POINTER(c_int)], c_int),
+    "frg_session_wait": ([_P, c_uint64, c_int], c_int),
+    "frg_session_cancel": ([_P, c_uint64], c_int),
+    "frg_session_stats": ([_P, POINTER(frg_stats)], c_int),
+    "frg_session_close": ([_P], c_int),
+}
+EXPORTED = tuple(_sig)
+for _name, (_args, _res) in _sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+
+def frg_last_error() -> str:
+    m = _lib.frg_last_error()
+    return m.decode() if m else ""
+
+
+def _check(status: int, where: str, ok=(FRG_OK,)) -> int:
+    if status not in ok:
+        raise FrgError(status, where, frg_last_error())
+    return status
+
+
+# ---- direct wrappers with the ABI's names -----------------------------------------------------
+def frg_context_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
+    h = c_void_p()
+    _check(_lib.frg_context_create(device, hbm_budget_bytes, byref(h)), "frg_context_create")
+    return h.value
+
+
+def frg_context_destroy(ctx: int) -> None:
+    _check(_lib.frg_context_destroy(ctx), "frg_context_destroy")
+
+
+def frg_integrate_batch(ctx: int, desc: frg_integral_desc, batch: frg_batch, stream: int) -> None:
+    _check(_lib.frg_integrate_batch(ctx, byref(desc), byref(batch), stream), "frg_integrate_batch")
+
+
+def frg_integrate_multi(ctx: int, descs, batches, stream: int) -> None:
+    n = len(descs)
+    D = (frg_integral_desc * n)(*descs)
+    B = (frg_batch * n)(*batches)
+    _check(_lib.frg_integrate_multi(ctx, n, D, B, stream), "frg_integrate_multi")
+
+
+def frg_flow_rhs(ctx: int, desc: frg_integral_desc, state: frg_flow_state, dstate_dt: int,
+                 stream: int) -> None:
+    _check(_lib.frg_flow_rhs(ctx, byref(desc), byref(state), dstate_dt, stream), "frg_flow_rhs")
+
+
+def frg_session_open(ctx: int, cfg: frg_session_config) -> int:
+    h = c_void_p()
+    _check(_lib.frg_session_open(ctx, byref(cfg), byref(h)), "frg_session_open")
+    return h.value
+
+
+def frg_session_register_table(s: int, Z_host_ptr: int, n: int, x_min: float,
+                               x_max: float) -> int:
+    tid = c_int()
+    _check(_lib.frg_session_register_table(s, Z_host_ptr, n, x_min, x_max, byref(tid)),
+           "frg_session_register_table")
+    return tid.value
+
+
+def frg_session_submit(s: int, desc: frg_integral_desc, batch: frg_batch, table_id: int) -> int:
+    t = c_uint64()
+    _check(_lib.frg_session_submit(s, byref(desc), byref(batch), table_id, byref(t)),
+           "frg_session_submit")
+    return t.value
+
+
+def frg_session_poll(s: int, ticket: int) -> bool:
+    done = c_int()
+    _check(_lib.frg_session_poll(s, ticket, byref(done)), "frg_session_poll")
+    return bool(done.value)
+
+
+def frg_session_wait(s: int, ticket: int, timeout_ms: int = -1) -> int:
+    return _check(_lib.frg_session_wait(s, ticket, timeout_ms), "frg_session_wait",
+                  ok=(FRG_OK, FRG_E_TIMEOUT))
+
+
+def frg_session_cancel(s: int, ticket: int) -> int:
+    return _check(_lib.frg_session_cancel(s, ticket), "frg_session_cancel",
+                  ok=(FRG_OK, FRG_E_NOTREADY))
+
+
+def frg_session_stats(s: int) -> frg_stats:
+    st = frg_stats()
+    _check(_lib.frg_session_stats(s, byref(st)), "frg_session_stats")
+    return st
+
+
+def frg_session_close(s: int) -> None:
+    _check(_lib.frg_session_close(s), "frg_session_close")
+
+
+def raw_status(name: str, *args) -> int:
+    """Call an ABI function and return its status without raising (for error-path tests)."""
+    return getattr(_lib, name)(*args)
+
+
+# ---- torch-tensor conveniences (marshalling only) ---------------------------------------------
+def _dptr(t) -> int | None:
+    if t is None:
+        return None
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError("expected a contiguous float64 tensor on a HIP (cuda) device")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def make_desc(family: int, n_q: int, q_max: float, *, n_x: int = 0, n_phi: int = 0, d: int = 0,
+              k: float = 1.0, precision: int = FRG_FP64, near_pole_tau: float = 0.0):
+    if d == 0:
+        d = 3 if family == FRG_FAMILY_LPA else 4
+    return frg_integral_desc(family, d, n_q, n_x, n_phi, precision, q_max, k, near_pole_tau)
+
+
+def make_batch(n_ext: int, out, *, ext=None, m2=None, m2_scalar: float = 0.0, Z=None,
+               x_min: float = 1e-3, x_max: float = 1e3, err_out=None) -> frg_batch:
+    zt = frg_log_table(_dptr(Z), 0 if Z is None else int(Z.numel()), x_min, x_max)
+    return frg_batch(n_ext, _dptr(ext), _dptr(m2), m2_scalar, zt, _dptr(out), _dptr(err_out))
+
+
+class Context:
+    """Owns one frg_context on a HIP device."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.device = device
+        self.handle = frg_context_create(device, hbm_budget_bytes)
+
+    def close(self):
+        if self.handle:
+            frg_context_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):  # pragma: no cover - best effort
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def integrate(self, desc, out, *, ext=None, m2=None, m2_scalar=0.0, Z=None, x_min=1e-3,
+                  x_max=1e3, err_out=None, stream=None):
+        b = make_batch(int(out.numel()), out, ext=ext, m2=m2, m2_scalar=m2_scalar, Z=Z,
+                       x_min=x_min, x_max=x_max, err_out=err_out)
+        frg_integrate_batch(self.handle, desc, b, _stream(stream))
+        return out
+
+    def integrate_multi(self, descs, batches, stream=None):
+        frg_integrate_multi(self.handle, list(descs), list(batches), _stream(stream))
+
+    def flow_rhs(self, desc, state, grid, dstate_dt, *, Z=None, x_min=1e-3, x_max=1e3,
+                 n_comp=4, m2_floor=-0.9, coef=1.0, stream=None):
+        zt = frg_log_table(_dptr(Z), 0 if Z is None else int(Z.numel()), x_min, x_max)
+        st = frg_flow_state(desc.family, int(dstate_dt.numel()), _dptr(state), _dptr(grid), zt,
+                            n_comp, m2_floor, coef)
+        frg_flow_rhs(self.handle, desc, st, _dptr(dstate_dt), _stream(stream))
+        return dstate_dt

@@ -1,0 +1,399 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by element.
+
+Tolerance: 1e-12 relative per external point in float64 (every integrand is positive, so the
+relative error is well defined).  The float32 precision form is held to the error bound it
+states per result (err_out).  Fused multi-request launches must reproduce single-batch results
+bitwise.
+"""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_13043_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2412_13043_amd import frg
+
+    ctx = frg.Context(0)
+    yield frg, ctx, torch
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _d(torch, a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), dtype=torch.float64,
+                        device="cuda")
+
+
+def _rel(got, ref):
+    return float(np.max(np.abs(got - ref) / np.abs(ref)))
+
+
+def _run(env, family, n_q, q_max, *, n_x=0, n_phi=0, d=0, k=1.0, ext=None, m2=None,
+         m2_scalar=0.0, Z=None, n_ext=None, precision=0, tau=0.0, err=False):
+    frg, ctx, torch = env
+    desc = frg.make_desc(family, n_q, q_max, n_x=n_x, n_phi=n_phi, d=d, k=k,
+                         precision=precision, near_pole_tau=tau)
+    if n_ext is None:
+        n_ext = len(m2) if m2 is not None else (len(ext) if family != 3 else len(ext) // 2)
+    out = torch.full((n_ext,), float("nan"), dtype=torch.float64, device="cuda")
+    eo = torch.full((n_ext,), float("nan"), dtype=torch.float64, device="cuda") if err else None
+    ctx.integrate(desc, out, ext=None if ext is None else _d(torch, ext),
+                  m2=None if m2 is None else _d(torch, m2), m2_scalar=m2_scalar,
+                  Z=None if Z is None else _d(torch, Z), x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
+                  err_out=eo)
+    torch.cuda.synchronize()
+    if err:
+        return out.cpu().numpy(), eo.cpu().numpy()
+    return out.cpu().numpy()
+
+
+# ------------------------------------------------------------------------------------------
+# Workload 1: LPA d = 3
+# ------------------------------------------------------------------------------------------
+def test_lpa_single_rhs(env):
+    rho, u, m2 = wl.lpa_potential()
+    got = _run(env, 1, wl.LPA_NQ, wl.LPA_QMAX, m2=m2)
+    ref = oracle.integrate(oracle.LPA, wl.LPA_NQ, wl.LPA_QMAX, m2=m2)
+    assert _rel(got, ref) <= TOL
+
+
+def test_lpa_batch_4096(env):
+    rho, u, m2 = wl.lpa_batch()
+    m2 = m2.reshape(-1)
+    got = _run(env, 1, wl.LPA_NQ, wl.LPA_QMAX, m2=m2)
+    ref = oracle.integrate(oracle.LPA, wl.LPA_NQ, wl.LPA_QMAX, m2=m2)
+    assert _rel(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("d,n_q,k,n_ext", [(1, 1, 1.0, 1), (2, 7, 0.37, 65), (4, 128, 2.5, 130),
+                                           (5, 33, 1.0, 64), (3, 1024, 1.0, 3)])
+def test_lpa_shapes(env, d, n_q, k, n_ext):
+    m2 = np.random.default_rng(n_q).uniform(-0.8, 3.0, n_ext) * k * k
+    got = _run(env, 1, n_q, 6.0, d=d, k=k, m2=m2)
+    ref = oracle.integrate(oracle.LPA, n_q, 6.0, d=d, k=k, m2=m2)
+    assert _rel(got, ref) <= TOL
+
+
+def test_lpa_scalar_mass(env):
+    got = _run(env, 1, 32, 6.0, m2_scalar=0.5, n_ext=70)
+    ref = oracle.integrate(oracle.LPA, 32, 6.0, m2_scalar=0.5, n_ext=70)
+    assert _rel(got, ref) <= TOL
+
+
+# ------------------------------------------------------------------------------------------
+# Workload 2: two-point d = 4
+# ------------------------------------------------------------------------------------------
+def test_two_point_single_rhs(env):
+    p, m2, Z = wl.two_point()
+    got = _run(env, 2, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX, ext=p, m2_scalar=m2, Z=Z)
+    ref = oracle.integrate(oracle.TWO_POINT, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX, ext=p,
+                           m2_scalar=m2, Z=Z)
+    assert _rel(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("n_ext,n_q,n_x,k,useZ,arr", [
+    (1, 1, 1, 1.0, True, False), (3, 5, 7, 1.0, True, True), (17, 24, 16, 0.37, True, True),
+    (65, 9, 3, 1.0, False, True), (100, 16, 8, 2.0, True, False), (300, 40, 20, 1.0, True, True)])
+def test_two_point_shapes(env, n_ext, n_q, n_x, k, useZ, arr):
+    rng = np.random.default_rng(n_ext)
+    p = 10 ** rng.uniform(-3, 2, n_ext) * k
+    m2 = rng.uniform(-0.9, 2.0, n_ext) * k * k if arr else None
+    Z = wl.dressing_table(n_ext) if useZ else None
+    got = _run(env, 2, n_q, 10.0, n_x=n_x, k=k, ext=p, m2=m2, m2_scalar=0.5 * k * k, Z=Z)
+    ref = oracle.integrate(oracle.TWO_POINT, n_q, 10.0, n_x=n_x, k=k, ext=p, m2=m2,
+                           m2_scalar=0.5 * k * k, Z=Z)
+    assert _rel(got, ref) <= TOL
+
+
+def test_two_point_zero_momentum_and_edges(env):
+    p = np.array([0.0, 1e-300, 1e-3, 5.0, 100.0, 1e3])
+    Z = wl.dressing_table(2)
+    got = _run(env, 2, 32, 10.0, n_x=16, ext=p, m2_scalar=0.5, Z=Z)
+    ref = oracle.integrate(oracle.TWO_POINT, 32, 10.0, n_x=16, ext=p, m2_scalar=0.5, Z=Z)
+    assert _rel(got, ref) <= TOL
+
+
+def test_two_point_big_table_and_rule(env):
+    # largest dressing table and a 1024-node cos1 rule
+    n = 4096
+    Z = 0.8 + 0.7 * (0.5 + 0.5 * np.sin(np.linspace(0, 40, n)))
+    p = np.array([0.01, 0.7, 3.0])
+    got = _run(env, 2, 16, 10.0, n_x=1024, ext=p, m2_scalar=0.3, Z=Z)
+    ref = oracle.integrate(oracle.TWO_POINT, 16, 10.0, n_x=1024, ext=p, m2_scalar=0.3, Z=Z)
+    assert _rel(got, ref) <= TOL
+
+
+# ------------------------------------------------------------------------------------------
+# Workload 3: three-point d = 4 (full launch shape, sampled outputs) and small full cases
+# ------------------------------------------------------------------------------------------
+def test_three_point_full_size_sampled(env):
+    P, A, m2, Z = wl.three_point()
+    ext = np.concatenate([P, A])
+    got = _run(env, 3, wl.THREE_NQ, wl.THREE_QMAX, n_x=wl.THREE_NX, n_phi=wl.THREE_NPHI,
+               ext=ext, m2=m2, Z=Z)
+    rng = np.random.default_rng(33)
+    idx = np.unique(np.concatenate([[0, 15, 16 * 32, 16 * 32 + 15, 1023],
+                                    rng.choice(1024, 27, replace=False)]))
+    ref = oracle.integrate(oracle.THREE_POINT, wl.THREE_NQ, wl.THREE_QMAX, n_x=wl.THREE_NX,
+                           n_phi=wl.THREE_NPHI, ext=(P[idx], A[idx]), m2=m2[idx], Z=Z)
+    assert _rel(got[idx], ref) <= TOL
+    assert np.all(np.isfinite(got)) and np.all(got > 0)
+
+
+@pytest.mark.parametrize("n_ext,n_q,n_x,n_phi,useZ", [(1, 1, 1, 1, True), (100, 16, 8, 6, True),
+                                                      (70, 9, 5, 3, False)])
+def test_three_point_small_full(env, n_ext, n_q, n_x, n_phi, useZ):
+    rng = np.random.default_rng(n_ext + n_phi)
+    p = 10 ** rng.uniform(-3, 2, n_ext)
+    a = rng.uniform(0, math.pi, n_ext)
+    a[:2] = [0.0, math.pi][: min(2, n_ext)]
+    m2 = rng.uniform(0.1, 2.0, n_ext)
+    Z = wl.dressing_table(9) if useZ else None
+    got = _run(env, 3, n_q, 10.0, n_x=n_x, n_phi=n_phi, ext=np.concatenate([p, a]), m2=m2, Z=Z)
+    ref = oracle.integrate(oracle.THREE_POINT, n_q, 10.0, n_x=n_x, n_phi=n_phi, ext=(p, a), m2=m2,
+                           Z=Z)
+    assert _rel(got, ref) <= TOL
+
+
+# ------------------------------------------------------------------------------------------
+# Workload 4: near-pole masses, float64 parity and the float32 form's stated bound
+# ------------------------------------------------------------------------------------------
+def test_near_pole_fp64(env):
+    p, m2, Z = wl.near_pole()
+    got = _run(env, 2, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX, ext=p, m2=m2, Z=Z)
+    ref = oracle.integrate(oracle.TWO_POINT, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX, ext=p, m2=m2,
+                           Z=Z)
+    assert _rel(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("tau", [0.0, 0.1, 0.25])
+def test_fp32_form_within_stated_bound(env, tau):
+    p, m2, Z = wl.near_pole()
+    got, bound = _run(env, 2, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX, ext=p, m2=m2, Z=Z,
+                      precision=1, tau=tau, err=True)
+    ref = oracle.integrate(oracle.TWO_POINT, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX, ext=p, m2=m2,
+                           Z=Z)
+    rel = np.abs(got - ref) / ref
+    print(f"fp32 form tau={tau}: max rel err {rel.max():.3e}, median {np.median(rel):.3e}, "
+          f"max stated bound {bound.max():.3e}")
+    assert np.all(rel <= bound)
+    assert np.all(bound < 1e-4)
+
+
+def test_fp32_form_lpa_and_three_point(env):
+    rho, u, m2 = wl.lpa_potential()
+    got, bound = _run(env, 1, 32, 6.0, m2=m2, precision=1, tau=0.1, err=True)
+    ref = oracle.integrate(oracle.LPA, 32, 6.0, m2=m2)
+    assert np.all(np.abs(got - ref) / ref <= bound)
+    P, A, m2, Z = wl.three_point()
+    sel = np.arange(0, 1024, 37)
+    ext = np.concatenate([P[sel], A[sel]])
+    got, bound = _run(env, 3, 24, 10.0, n_x=12, n_phi=8, ext=ext, m2=m2[sel], Z=Z, precision=1,
+                      tau=0.1, err=True)
+    ref = oracle.integrate(oracle.THREE_POINT, 24, 10.0, n_x=12, n_phi=8, ext=(P[sel], A[sel]),
+                           m2=m2[sel], Z=Z)
+    assert np.all(np.abs(got - ref) / ref <= bound)
+
+
+# ------------------------------------------------------------------------------------------
+# Fused multi-request launches
+# ------------------------------------------------------------------------------------------
+def _mixed_requests():
+    reqs = []
+    rho, u, m2 = wl.lpa_batch(B=3)
+    for b in range(3):
+        reqs.append(dict(family=1, n_q=32 + 8 * b, q_max=6.0, m2=m2[b], prec=b % 2))
+    p, _, Z = wl.two_point()
+    reqs.append(dict(family=2, n_q=64, q_max=10.0, n_x=32, ext=p, m2s=0.5, Z=Z, prec=0))
+    reqs.append(dict(family=2, n_q=20, q_max=10.0, n_x=12, ext=p[:37], m2s=0.9, Z=Z, prec=1,
+                     tau=0.1))
+    P, A, m3, Z3 = wl.three_point()
+    sel = np.arange(0, 1024, 11)
+    reqs.append(dict(family=3, n_q=16, q_max=10.0, n_x=8, n_phi=6,
+                     ext=np.concatenate([P[sel], A[sel]]), m2=m3[sel], Z=Z3, prec=0))
+    reqs.append(dict(family=3, n_q=12, q_max=10.0, n_x=6, n_phi=4,
+                     ext=np.concatenate([P[:20], A[:20]]), m2=m3[:20], Z=None, prec=1, tau=0.2))
+    return reqs
+
+
+def test_multi_matches_single_bitwise(env):
+    frg, ctx, torch = env
+    reqs = _mixed_requests()
+    descs, batches, outs, keep = [], [], [], []
+    singles = []
+    for r in reqs:
+        n = len(r["m2"]) if "m2" in r else (len(r["ext"]) if r["family"] == 2 else
+                                            len(r["ext"]) // 2)
+        desc = frg.make_desc(r["family"], r["n_q"], r["q_max"], n_x=r.get("n_x", 0),
+                             n_phi=r.get("n_phi", 0), precision=r["prec"],
+                             near_pole_tau=r.get("tau", 0.0))
+        ext = _d(torch, r["ext"]) if "ext" in r else None
+        m2 = _d(torch, r["m2"]) if "m2" in r else None
+        Z = _d(torch, r["Z"]) if r.get("Z") is not None else None
+        out = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        keep += [ext, m2, Z]
+        batches.append(frg.make_batch(n, out, ext=ext, m2=m2, m2_scalar=r.get("m2s", 0.0), Z=Z,
+                                      x_min=wl.Z_XMIN, x_max=wl.Z_XMAX))
+        descs.append(desc)
+        outs.append(out)
+        single = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        ctx.integrate(desc, single, ext=ext, m2=m2, m2_scalar=r.get("m2s", 0.0), Z=Z,
+                      x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)
+        singles.append(single)
+    for rep in range(2):
+        for o in outs:
+            o.fill_(float("nan"))
+        ctx.integrate_multi(descs, batches)
+        torch.cuda.synchronize()
+        for o, s in zip(outs, singles):
+            assert torch.equal(o, s), f"replay {rep}: multi result differs from single batch"
+    # and the float64 ones agree with the oracle
+    r = reqs[3]
+    ref = oracle.integrate(oracle.TWO_POINT, 64, 10.0, n_x=32, ext=r["ext"], m2_scalar=0.5,
+                           Z=r["Z"])
+    assert _rel(outs[3].cpu().numpy(), ref) <= TOL
+
+
+def test_two_point_batch_256_multi_sampled(env):
+    frg, ctx, torch = env
+    p, m2, Zs = wl.two_point_batch()
+    B = Zs.shape[0]
+    tp = _d(torch, p)
+    tZ = _d(torch, Zs)
+    out = torch.full((B, p.size), float("nan"), dtype=torch.float64, device="cuda")
+    desc = frg.make_desc(2, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX)
+    batches = [frg.make_batch(p.size, out[b], ext=tp, m2_scalar=m2, Z=tZ[b], x_min=wl.Z_XMIN,
+                              x_max=wl.Z_XMAX) for b in range(B)]
+    ctx.integrate_multi([desc] * B, batches)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    rng = np.random.default_rng(256)
+    for b in list(range(0, B, 17)) + [B - 1]:
+        idx = rng.choice(p.size, 6, replace=False)
+        ref = oracle.integrate(oracle.TWO_POINT, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX,
+                               ext=p[idx], m2_scalar=m2, Z=Zs[b])
+        assert _rel(got[b, idx], ref) <= TOL, b
+    assert np.all(np.isfinite(got))
+
+
+# ------------------------------------------------------------------------------------------
+# Flow right-hand sides (graph-captured), replayed with eager work in between
+# ------------------------------------------------------------------------------------------
+def test_flow_rhs_lpa_and_graph_replays(env):
+    frg, ctx, torch = env
+    rho = wl.lpa_rho_grid()
+    trho = _d(torch, rho)
+    desc = frg.make_desc(1, wl.LPA_NQ, wl.LPA_QMAX)
+    state = _d(torch, -0.3 + rho)
+    dudt = torch.empty_like(state)
+    for rep, (a, b, c) in enumerate([(0.3, 1.0, 0.0), (0.1, 0.7, 0.4), (0.45, 1.3, -0.2),
+                                     (0.3, 1.0, 0.0)]):
+        u = -a + b * rho + c * rho ** 2
+        state.copy_(torch.from_numpy(u))
+        _ = (state * 2.0).sum()  # unrelated eager work between replays
+        ctx.flow_rhs(desc, state, trho, dudt, n_comp=4, m2_floor=-0.9)
+        torch.cuda.synchronize()
+        ref = oracle.lpa_flow_rhs(rho, u, wl.LPA_NQ, wl.LPA_QMAX, n_comp=4, m2_floor=-0.9)
+        got = dudt.cpu().numpy()
+        # u' and u'' come from finite differences, whose rounding (independent formulas on the
+        # two sides) is amplified by ~|u|/(h |u'|) and |u|/(h^2 |u''|) with h = 1/63
+        assert np.max(np.abs(got - ref) / (np.abs(ref) + 1e-3 * np.max(np.abs(ref)))) <= 1e-11, rep
+
+
+@pytest.mark.parametrize("family", [2, 3])
+def test_flow_rhs_vertex(env, family):
+    frg, ctx, torch = env
+    rng = np.random.default_rng(family)
+    n = 96
+    p = 10 ** rng.uniform(-3, 2, n)
+    Z = wl.dressing_table(5)
+    if family == 2:
+        grid = p
+        desc = frg.make_desc(2, 24, 10.0, n_x=12)
+    else:
+        grid = np.concatenate([p, rng.uniform(0, math.pi, n)])
+        desc = frg.make_desc(3, 12, 10.0, n_x=8, n_phi=6)
+    tgrid, tZ = _d(torch, grid), _d(torch, Z)
+    state = _d(torch, rng.uniform(-1.2, 2.0, n))
+    out = torch.empty_like(state)
+    for rep in range(3):
+        s = state.cpu().numpy()
+        ctx.flow_rhs(desc, state, tgrid, out, Z=tZ, m2_floor=-0.5, coef=-0.25)
+        torch.cuda.synchronize()
+        m2 = np.maximum(s, -0.5)
+        if family == 2:
+            ref = oracle.integrate(2, 24, 10.0, n_x=12, ext=p, m2=m2, Z=Z)
+        else:
+            ref = oracle.integrate(3, 12, 10.0, n_x=8, n_phi=6, ext=(grid[:n], grid[n:]), m2=m2,
+                                   Z=Z)
+        assert _rel(out.cpu().numpy(), -0.25 * ref) <= TOL
+        state.mul_(0.9).add_(0.05)
+
+
+# ------------------------------------------------------------------------------------------
+# Error paths and no-ops (validation happens before any launch)
+# ------------------------------------------------------------------------------------------
+def test_invalid_arguments_rejected(env):
+    frg, ctx, torch = env
+    out = torch.zeros(8, dtype=torch.float64, device="cuda")
+    ext = torch.ones(8, dtype=torch.float64, device="cuda")
+    cases = [
+        frg.make_desc(4, 8, 6.0),                         # family
+        frg.make_desc(1, 0, 6.0),                         # n_q
+        frg.make_desc(1, 2000, 6.0),                      # n_q too large
+        frg.make_desc(2, 8, 10.0, n_x=0),                 # n_x
+        frg.make_desc(2, 8, -1.0, n_x=4),                 # q_max
+        frg.make_desc(3, 8, 10.0, n_x=4, n_phi=0),        # n_phi
+        frg.make_desc(1, 8, 6.0, k=0.0),                  # k
+        frg.make_desc(1, 8, 6.0, precision=7),            # precision
+        frg.make_desc(1, 8, 6.0, precision=1, near_pole_tau=1.5),
+    ]
+    for desc in cases:
+        b = frg.make_batch(8, out, ext=ext, m2_scalar=0.5)
+        st = frg.raw_status("frg_integrate_batch", ctx.handle, ctypes.byref(desc),
+                            ctypes.byref(b), None)
+        assert st == frg.FRG_E_INVAL, (desc.family, desc.n_q, frg.frg_last_error())
+    desc = frg.make_desc(2, 8, 10.0, n_x=4, d=3)
+    b = frg.make_batch(8, out, ext=ext, m2_scalar=0.5)
+    assert frg.raw_status("frg_integrate_batch", ctx.handle, ctypes.byref(desc), ctypes.byref(b),
+                          None) == frg.FRG_E_UNSUPPORTED
+    # a host pointer where device memory is required
+    host = np.zeros(8)
+    desc = frg.make_desc(1, 8, 6.0)
+    b = frg.make_batch(8, out, m2_scalar=0.5)
+    b.out = host.ctypes.data
+    assert frg.raw_status("frg_integrate_batch", ctx.handle, ctypes.byref(desc), ctypes.byref(b),
+                          None) == frg.FRG_E_INVAL
+    # vertex family without ext, bad table
+    desc = frg.make_desc(2, 8, 10.0, n_x=4)
+    b = frg.make_batch(8, out, m2_scalar=0.5)
+    assert frg.raw_status("frg_integrate_batch", ctx.handle, ctypes.byref(desc), ctypes.byref(b),
+                          None) == frg.FRG_E_INVAL
+    Zbad = torch.ones(1, dtype=torch.float64, device="cuda")
+    b = frg.make_batch(8, out, ext=ext, m2_scalar=0.5, Z=Zbad)
+    assert frg.raw_status("frg_integrate_batch", ctx.handle, ctypes.byref(desc), ctypes.byref(b),
+                          None) == frg.FRG_E_INVAL
+    # out untouched by rejected calls
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(out).item() == 0
+
+
+def test_empty_batch_is_noop(env):
+    frg, ctx, torch = env
+    desc = frg.make_desc(2, 8, 10.0, n_x=4)
+    b = frg.frg_batch()
+    b.n_ext = 0
+    assert frg.raw_status("frg_integrate_batch", ctx.handle, ctypes.byref(desc), ctypes.byref(b),
+                          None) == frg.FRG_OK
+    ctx.integrate_multi([], [])
