@@ -248,7 +248,140 @@ def secondary(torch, frg, wl, ctx):
     lat["two_point_rhs"] = _latency(torch, lambda: ctx.flow_rhs(dd, s2, tp, d2, Z=tZ,
                                                                 m2_floor=-0.9, coef=1.0))
     ex["rhs_latency_us"] = lat
+    log("bench: serving")
+    ex["serving"] = serving(torch, frg, wl, ctx)
     return ex
+
+
+def serving(torch, frg, wl, ctx, n_steppers=200, seconds=6.0, load=0.8, seed=12345):
+    """Workload 5: synthetic RK4 time-steppers submitting right-hand-side requests to a session.
+
+    Each stepper (workloads.stepper_spec) owns a request shape (family, n_ext, nodes per
+    dimension, float64 or float32) and a state; every RK4 stage submits one request built from the
+    stage state, waits for it, and sleeps an exponential think time before the next, so arrivals
+    are close to Poisson.  The think time is set for an offered load of `load` times the
+    capacity implied by the per-shape service times measured beforehand.  Reported: requests,
+    Gnodes/s, p50/p99 latency (submit -> result in the host buffer), and the same arrival trace
+    served FIFO on one stream by the plain per-batch float64 path (one frg_integrate_batch per
+    request, service times measured per shape).
+    """
+    import math
+    import random
+
+    specs = [wl.stepper_spec(i) for i in range(n_steppers)]
+
+    def host_request(sp, state):
+        n = sp.n_ext
+        if sp.family == 1:
+            g = np.gradient(state, sp.ext)
+            m2 = np.maximum(state + 2.0 * sp.ext * g, -0.9)
+            ext = None
+        else:
+            m2 = np.clip(state, 0.05, 4.0)
+            ext = np.ascontiguousarray(sp.ext)
+        return ext, np.ascontiguousarray(m2)
+
+    def desc_of(sp, fp64=False):
+        prec = 0 if (fp64 or not sp.fp32) else 1
+        return frg.make_desc(sp.family, sp.n_q, sp.q_max, n_x=sp.n_x, n_phi=sp.n_phi,
+                             precision=prec, near_pole_tau=0.1 if prec else 0.0)
+
+    # per-shape service time of the plain float64 path (inputs to HBM, integrate, result back)
+    svc = []
+    for sp in specs:
+        ext, m2 = host_request(sp, sp.state0)
+        d = desc_of(sp, fp64=True)
+        tz = None if sp.Z is None else _dev(torch, sp.Z)
+        best = 1e9
+        for _ in range(2):
+            t0 = time.perf_counter()
+            te = None if ext is None else _dev(torch, ext)
+            tm = _dev(torch, m2)
+            out = torch.empty(sp.n_ext, dtype=torch.float64, device="cuda")
+            ctx.integrate(d, out, ext=te, m2=tm, Z=tz, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)
+            out.cpu()
+            best = min(best, time.perf_counter() - t0)
+        svc.append(best)
+    svc = np.array(svc)
+    mean_svc = float(svc.mean())
+    think = max(mean_svc * (n_steppers / load - 1.0), 0.0)
+
+    cfg = frg.frg_session_config(4, 4 << 30, 20, 0)  # 4 GiB arena
+    sess = frg.frg_session_open(ctx.handle, cfg)
+    tables = {}
+    for sp in specs:
+        if sp.Z is not None:
+            tables[sp.index] = frg.frg_session_register_table(sess, sp.Z.ctypes.data, sp.Z.size,
+                                                              wl.Z_XMIN, wl.Z_XMAX)
+    trace = []  # (arrival, stepper, latency)
+    lock = threading.Lock()
+    t_start = time.perf_counter()
+    t_end = t_start + seconds
+
+    def stepper(sp):
+        rnd = random.Random(seed + sp.index)
+        u = sp.state0.copy()
+        h, eta = 0.05, 0.02
+        d = desc_of(sp)
+        tid = tables.get(sp.index, -1)
+        out = np.empty(sp.n_ext)
+        err = np.empty(sp.n_ext)
+        while time.perf_counter() < t_end:
+            ks = []
+            for stage in range(4):
+                us = u if stage == 0 else u + (h if stage == 3 else h / 2) * ks[-1]
+                ext, m2 = host_request(sp, us)
+                zt = frg.frg_log_table(None, 0, wl.Z_XMIN, wl.Z_XMAX)
+                b = frg.frg_batch(sp.n_ext, None if ext is None else ext.ctypes.data,
+                                  m2.ctypes.data, 0.0, zt, out.ctypes.data, err.ctypes.data)
+                t0 = time.perf_counter()
+                tk = frg.frg_session_submit(sess, d, b, tid)
+                frg.frg_session_wait(sess, tk, -1)
+                t1 = time.perf_counter()
+                with lock:
+                    trace.append((t0 - t_start, sp.index, t1 - t0))
+                ks.append(-eta * out)
+                time.sleep(rnd.expovariate(1.0 / think) if think > 0 else 0.0)
+                if time.perf_counter() >= t_end:
+                    break
+            if len(ks) == 4:
+                u = u + h / 6.0 * (ks[0] + 2 * ks[1] + 2 * ks[2] + ks[3])
+
+    ths = [threading.Thread(target=stepper, args=(sp,)) for sp in specs]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    st = frg.frg_session_stats(sess)
+    frg.frg_session_close(sess)
+    nodes = np.array([wl.request_nodes(specs[i]) for _, i, _ in trace], dtype=np.float64)
+    lat = np.array([l for _, _, l in trace])
+    arr = np.array([a for a, _, _ in trace])
+    span = max(a + l for a, _, l in trace) - min(arr)
+    # the same arrivals served FIFO, one request at a time, by the plain float64 path
+    order = np.argsort(arr)
+    free_at = 0.0
+    base_lat = np.empty(len(trace))
+    for k in order:
+        a, i, _ = trace[k]
+        start = max(a, free_at)
+        free_at = start + svc[i]
+        base_lat[k] = free_at - a
+    base_span = free_at - float(arr.min())
+    n32 = sum(1 for _, i, _ in trace if specs[i].fp32)
+    return {
+        "steppers": n_steppers, "seconds": seconds, "offered_load": load,
+        "requests": len(trace), "fp32_requests": n32,
+        "gnodes_per_s": round(float(nodes.sum()) / span / 1e9, 2),
+        "p50_us": round(float(np.percentile(lat, 50)) * 1e6, 1),
+        "p99_us": round(float(np.percentile(lat, 99)) * 1e6, 1),
+        "session_p50_us": round(st.p50_us, 1), "session_p99_us": round(st.p99_us, 1),
+        "launches": int(st.launches),
+        "baseline_fp64_per_batch": {
+            "gnodes_per_s": round(float(nodes.sum()) / base_span / 1e9, 2),
+            "p50_us": round(float(np.percentile(base_lat, 50)) * 1e6, 1),
+            "p99_us": round(float(np.percentile(base_lat, 99)) * 1e6, 1)},
+    }
 
 
 def _latency(torch, fn, n=2000):

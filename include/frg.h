@@ -122,8 +122,10 @@ typedef struct {
     double m2_scalar;
     frg_log_table Z;
     double *out;           /* device [n_ext]: I_e */
-    double *err_out;       /* device [n_ext] or NULL: FP32 form's stated relative error bound per
-                              result (0 for FP64); see DESIGN notes in the implementation */
+    double *err_out;       /* device [n_ext] or NULL: stated relative error bound per result of
+                              the FP32 form, (40 + 2 kappa) 2^-24 with kappa the largest
+                              amplification (|Z l2 + R| + |m2|)/D of a float32 propagator of
+                              that point (0 for FP64) */
 } frg_batch;
 
 /* ---- context ------------------------------------------------------------------------------- */
@@ -149,6 +151,15 @@ frg_status frg_integrate_batch(frg_context *ctx, const frg_integral_desc *desc,
  * same batch submitted alone through frg_integrate_batch with the same descriptor. */
 frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc *descs,
                                const frg_batch *batches, hipStream_t stream);
+
+/* Pick the tile shape (lanes per external point x radial chunks) of frg_integrate_batch and
+ * frg_flow_rhs for this descriptor and batch size by timing the candidate shapes on the given
+ * batch (its out buffer is overwritten with the integrals), and keep the fastest in the context.
+ * If the environment variable FRG_AUTOTUNE_CACHE names a file, tuned shapes are loaded from it
+ * when the context is created and appended to it here.  Results do not depend on the shape, only
+ * speed does.  Synchronises `stream`.  *best_us (optional) receives the best time per launch. */
+frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const frg_batch *batch,
+                        hipStream_t stream, int reps, double *best_us);
 
 /* ---- flow right-hand side ------------------------------------------------------------------- */
 
@@ -212,7 +223,9 @@ frg_status frg_session_register_table(frg_session *s, const double *Z_host, int 
  * exceeds the session budget; FRG_E_INVAL on a bad descriptor or batch. */
 frg_status frg_session_submit(frg_session *s, const frg_integral_desc *desc,
                               const frg_batch *batch_host, int table_id, uint64_t *ticket);
-/* *done = 1 when the ticket's results are in the host output buffers. */
+/* *done = 1 when the ticket's results are in the host output buffers.  A ticket that failed
+ * returns its failure status: FRG_E_TIMEOUT if the watchdog gave up on its launch, FRG_E_DEVICE
+ * on a HIP error, FRG_E_CANCELLED if cancelled. */
 frg_status frg_session_poll(frg_session *s, uint64_t ticket, int *done);
 /* Block until the ticket completes (FRG_OK), fails, is cancelled, or timeout_ms passes
  * (FRG_E_TIMEOUT; timeout_ms < 0 waits forever). */

@@ -29,25 +29,31 @@ def _run(cmd):
     subprocess.check_call(cmd)
 
 
-def build(verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = True, out: str = LIB, defines=()) -> str:
+    """Compile and link libfrg.so; `defines` are extra -D tuning macros for the device code."""
+    build_dir = BUILD if out == LIB else out + ".build"
+    os.makedirs(build_dir, exist_ok=True)
     objs = []
     for src, is_device in SOURCES:
-        obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
+        obj = os.path.join(build_dir, src.rsplit(".", 1)[0] + ".o")
         cmd = ["hipcc", "-c"] + COMMON
         if is_device:
-            cmd += DEVICE
+            cmd += DEVICE + ["-D" + d for d in defines]
         else:
             cmd += ["-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-x", "c++"]
         cmd += [os.path.join(CSRC, src), "-o", obj]
         _run(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     _run(["hipcc", "-shared", "-o", tmp] + objs + ["--offload-arch=" + ARCH, "-lpthread"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    build()
+    # python build.py [OUT.so [MACRO=VALUE ...]]
+    if len(sys.argv) > 1:
+        build(out=os.path.abspath(sys.argv[1]), defines=sys.argv[2:])
+    else:
+        build()
     sys.exit(0)

@@ -38,8 +38,7 @@ struct ReqDev {
     int ext_tiles;    // ceil(n_ext / (64 >> lq_log2))
     int nZ;           // 0 => Z == 1
     int m2_mode;      // 0 scalar, 1 array, 2 array floored at m2_floor (flow states)
-    int ctr_base;     // first counter of this request in the counter array
-    int pad0;
+    long long ctr_base;      // first counter of this request in the counter array
     long long contrib_base;  // first double of this request's [n_q][n_ext] contribution block
     double k, k2;
     double pref;      // final multiplier: Omega-factor * k^(d+2) (and flow coef, if any)
@@ -50,6 +49,7 @@ struct ReqDev {
     RadialRule rad;
     AngleRule ang;
     PhiRule phi;
+    const double2 *logt;  // 256-entry table of the float64 logarithm (c_j, ln(1/c_j))
     const double *ext;    // family 2: p; family 3: p then alpha
     const double *m2;
     const double *Z;
@@ -80,5 +80,7 @@ hipError_t launch_lpa_state(int n, const double *rho, const double *u, double m2
 hipError_t launch_lpa_assemble(int n, int n_comp, const double *I, const double *fac,
                                double *dudt, hipStream_t s);
 hipError_t launch_fill_zero_u32(unsigned *p, size_t n, hipStream_t s);
+hipError_t launch_log_table(double2 *out, hipStream_t s);
+constexpr int kLogTable = 256;
 
 }  // namespace frg

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include "frg_internal.hpp"
+#include "frg_math.hpp"
 
 namespace frg {
 
@@ -161,33 +162,94 @@ hipError_t launch_rules(int n_q, double q_max, int d, int n_x, int n_phi, double
 // dressing clamps to its first entry, and no 0/0 occurs in the single-division form below.
 #define FRG_L2_TINY 1e-300
 
-// Dressing lookup: s = (log|l| - log x_min)/Delta = za*log(l2) + zb, clamped to [0, n-1]; the
-// staged table holds (Z_i, Z_{i+1} - Z_i) with a zero slope in the last entry.
-__device__ __forceinline__ double dressing64(const double2 *__restrict__ Zs, int nZ, double za,
-                                             double zb, double l2) {
-    double s = fma(log(l2), za, zb);
-    s = fmin(fmax(s, 0.0), (double)(nZ - 1));
-    int i = (int)s;
-    double f = s - (double)i;
-    double2 z = Zs[i];
+// Occupancy target of the integrand kernels (waves per SIMD); bounds the VGPR budget so that the
+// loop-invariant constants of the inner loops stay resident in registers.
+#ifndef FRG_WAVES_PER_EU
+#define FRG_WAVES_PER_EU 4
+#endif
+// Propagators evaluated together per inner-loop step (instruction-level parallelism).
+#ifndef FRG_ILP
+#define FRG_ILP 4
+#endif
+
+// Tables staged in LDS for one request: the logarithm table, then the dressing as n + 1 entries
+// (Z_0, 0), (Z_0, Z_1 - Z_0), ..., (Z_{n-2}, Z_{n-1} - Z_{n-2}), (Z_{n-1}, 0) addressed by
+// s + 1, s = (log|l| - log x_min)/Delta: the constant first and last entries absorb every s
+// outside [0, n-1], so one integer clamp of the cell index replaces clamping s; then
+// (float32 form) the same entries in float32.
+struct Smem {
+    double2 *logt;
+    double2 *Z64;
+    float2 *Z32;
+};
+
+// Cell index and fraction of the padded dressing table for coordinate sp = s + 1.
+__device__ __forceinline__ void zcell64(double sp, int nZ, int &i, double &f) {
+    i = min(max((int)sp, 0), nZ);
+    f = __builtin_amdgcn_fract(sp);
+}
+
+// Dressing Z(l2) (l2 > 0): s + 1 = za*log(l2) + zb1.
+__device__ __forceinline__ double dressing64(const Smem &sm, int nZ, double za, double zb1,
+                                             double l2) {
+    int i;
+    double f;
+    zcell64(fma(fm::log_tab(l2, sm.logt), za, zb1), nZ, i, f);
+    const double2 z = sm.Z64[i];
     return fma(f, z.y, z.x);
 }
 
 // G(l2) = 1/(Z l2 + R(l2) + m2) with R = l2 e/(-E), e = exp(-y), E = expm1(-y), y = l2/k^2,
-// as one division: G = (-E)/((-E)(Z l2 + m2) + l2 e).  l2 > 0.
+// written with one reciprocal: G = (-E)/((-E)(Z l2 + m2) + l2 e), and l2 e = l2 + l2 E.
+// l2 e carries an absolute error of ~1e-16 l2 where e is tiny, which is below 1e-16 of the
+// denominator.  l2 > 0.
 __device__ __forceinline__ double prop64(double l2, double z, double m2, double inv_k2) {
-    double y = l2 * inv_k2;
-    double e, E;
-    exp_pair64_prop(y, e, E);
-    double num = -E;
-    double den = fma(num, fma(z, l2, m2), l2 * e);
-    return num / den;
+    const double E = fm::expm1_neg(l2 * inv_k2);
+    const double den = fma(-E, fma(z, l2, m2), fma(l2, E, l2));
+    return -E * fm::rcp_nr(den);
 }
 
-struct Smem {
-    double2 *Z64;
-    float2 *Z32;
-};
+// W propagators at once, G[w] = G(l2[w]) with the tabulated dressing, ordered by phase so that the
+// LDS gathers of all W points are in flight while the regulator (which does not depend on the
+// dressing) is evaluated, and the W dependency chains interleave.
+template <int W>
+__device__ __forceinline__ void propagators64(const double (&l2)[W], double (&G)[W],
+                                              const Smem &sm, int nZ, double za, double zb1,
+                                              double m2, double inv_k2) {
+    double2 t[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) t[w] = sm.logt[(__double2hiint(l2[w]) >> 12) & 0xff];
+    double E[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) E[w] = fm::expm1_neg(l2[w] * inv_k2);
+    int iz[W];
+    double fz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const double f = __builtin_amdgcn_frexp_mant(l2[w]);
+        const int k = __builtin_amdgcn_frexp_exp(l2[w]);
+        const double r = fma(f, t[w].x, -1.0);
+        double p = fma(r, 0.2, -0.25);
+        p = fma(r, p, 0.3333333333333333);
+        p = fma(r, p, -0.5);
+        p = fma(r, p, 1.0);
+        p = r * p;
+        const double ln = fma((double)k, fm::LN2_HI, t[w].y + p);
+        zcell64(fma(ln, za, zb1), nZ, iz[w], fz[w]);
+    }
+    double2 z[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) z[w] = sm.Z64[iz[w]];
+    double le[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) le[w] = fma(l2[w], E[w], l2[w]);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const double zv = fma(fz[w], z[w].y, z[w].x);
+        const double den = fma(-E[w], fma(zv, l2[w], m2), le[w]);
+        G[w] = -E[w] * fm::rcp_nr(den);
+    }
+}
 
 __device__ __forceinline__ double lane_m2(const ReqDev &r, int e) {
     if (r.m2_mode == 0) return r.m2s;
@@ -196,37 +258,46 @@ __device__ __forceinline__ double lane_m2(const ReqDev &r, int e) {
     return v;
 }
 
-// Radial prologue for (external point, radial node a): q, G(q^2)^2 W^_a and the angle
-// coefficients c0 = q^2 + p^2, c1 = 2 q p.
+// Radial prologue for (external point, radial node a): W^_a G(q^2)^2 and the angle coefficients
+// c0 = q^2 + p^2, c1 = 2 q p.
 struct RadialTerm {
-    double q2, wg, c0, c1;
+    double wg, c0, c1;
 };
 
 __device__ __forceinline__ RadialTerm radial64(const ReqDev &r, const Smem &sm, int a, double p,
-                                               double m2, double inv_k2) {
+                                               double m2) {
     RadialTerm t;
-    double q = r.k * r.rad.q[a];
-    t.q2 = q * q;
-    double zq = r.nZ ? dressing64(sm.Z64, r.nZ, r.za, r.zb, fmax(t.q2, FRG_L2_TINY)) : 1.0;
-    double A = fma(zq, t.q2, r.k2 * r.rad.R[a]);
-    double G = 1.0 / (A + m2);
+    const double q = r.k * r.rad.q[a];
+    const double q2 = q * q;
+    const double zq = dressing64(sm, r.nZ, r.za, r.zb + 1.0, fmax(q2, FRG_L2_TINY));
+    const double A = fma(zq, q2, r.k2 * r.rad.R[a]);
+    const double G = fm::rcp_nr(A + m2);
     t.wg = r.rad.W[a] * (G * G);
-    t.c0 = fma(p, p, t.q2);
+    t.c0 = fma(p, p, q2);
     t.c1 = 2.0 * q * p;
-    (void)inv_k2;
     return t;
 }
 
 // Contribution of (e, a) to the two-point integral (without the global prefactor).
 __device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm, int a, double p,
                                                 double m2, double inv_k2) {
-    RadialTerm t = radial64(r, sm, a, p, m2, inv_k2);
+    const RadialTerm t = radial64(r, sm, a, p, m2);
+    const int nx = r.n_x, nZ = r.nZ;
+    const double za = r.za, zb1 = r.zb + 1.0;
     double inner = 0.0;
-    const int nx = r.n_x;
-    for (int b = 0; b < nx; ++b) {
-        double l2 = fmax(fma(t.c1, r.ang.x[b], t.c0), FRG_L2_TINY);
-        double z = r.nZ ? dressing64(sm.Z64, r.nZ, r.za, r.zb, l2) : 1.0;
-        inner = fma(r.ang.xw[b], prop64(l2, z, m2, inv_k2), inner);
+    int b = 0;
+    for (; b + FRG_ILP <= nx; b += FRG_ILP) {
+        double l2[FRG_ILP], G[FRG_ILP];
+#pragma unroll
+        for (int w = 0; w < FRG_ILP; ++w) l2[w] = fmax(fma(t.c1, r.ang.x[b + w], t.c0), FRG_L2_TINY);
+        propagators64<FRG_ILP>(l2, G, sm, nZ, za, zb1, m2, inv_k2);
+#pragma unroll
+        for (int w = 0; w < FRG_ILP; ++w) inner = fma(r.ang.xw[b + w], G[w], inner);
+    }
+    for (; b < nx; ++b) {
+        double l2[1] = {fmax(fma(t.c1, r.ang.x[b], t.c0), FRG_L2_TINY)}, G[1];
+        propagators64<1>(l2, G, sm, nZ, za, zb1, m2, inv_k2);
+        inner = fma(r.ang.xw[b], G[0], inner);
     }
     return t.wg * inner;
 }
@@ -236,23 +307,33 @@ __device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm,
 __device__ __forceinline__ double contrib_three64(const ReqDev &r, const Smem &sm, int a, double p,
                                                   double ca, double sa, double m2,
                                                   double inv_k2) {
-    RadialTerm t = radial64(r, sm, a, p, m2, inv_k2);
+    const RadialTerm t = radial64(r, sm, a, p, m2);
+    const int nx = r.n_x, nphi = r.n_phi, nZ = r.nZ;
+    const double za = r.za, zb1 = r.zb + 1.0;
     double mid = 0.0;
-    const int nx = r.n_x, nphi = r.n_phi;
     for (int b = 0; b < nx; ++b) {
-        double xb = r.ang.x[b];
-        double l1 = fmax(fma(t.c1, xb, t.c0), FRG_L2_TINY);
-        double z1 = r.nZ ? dressing64(sm.Z64, r.nZ, r.za, r.zb, l1) : 1.0;
-        double g1 = prop64(l1, z1, m2, inv_k2);
-        double A2 = fma(-t.c1, xb * ca, t.c0);
-        double B2 = -t.c1 * (r.ang.xs[b] * sa);
+        const double xb = r.ang.x[b];
+        double l1[1] = {fmax(fma(t.c1, xb, t.c0), FRG_L2_TINY)}, g1[1];
+        propagators64<1>(l1, g1, sm, nZ, za, zb1, m2, inv_k2);
+        const double A2 = fma(-t.c1, xb * ca, t.c0);
+        const double B2 = -t.c1 * (r.ang.xs[b] * sa);
         double inner = 0.0;
-        for (int c = 0; c < nphi; ++c) {
-            double l2 = fmax(fma(B2, r.phi.c[c], A2), FRG_L2_TINY);
-            double z2 = r.nZ ? dressing64(sm.Z64, r.nZ, r.za, r.zb, l2) : 1.0;
-            inner = fma(r.phi.w[c], prop64(l2, z2, m2, inv_k2), inner);
+        int c = 0;
+        for (; c + FRG_ILP <= nphi; c += FRG_ILP) {
+            double l2[FRG_ILP], G[FRG_ILP];
+#pragma unroll
+            for (int w = 0; w < FRG_ILP; ++w)
+                l2[w] = fmax(fma(B2, r.phi.c[c + w], A2), FRG_L2_TINY);
+            propagators64<FRG_ILP>(l2, G, sm, nZ, za, zb1, m2, inv_k2);
+#pragma unroll
+            for (int w = 0; w < FRG_ILP; ++w) inner = fma(r.phi.w[c + w], G[w], inner);
         }
-        mid = fma(r.ang.xw[b] * g1, inner, mid);
+        for (; c < nphi; ++c) {
+            double l2[1] = {fmax(fma(B2, r.phi.c[c], A2), FRG_L2_TINY)}, G[1];
+            propagators64<1>(l2, G, sm, nZ, za, zb1, m2, inv_k2);
+            inner = fma(r.phi.w[c], G[0], inner);
+        }
+        mid = fma(r.ang.xw[b] * g1[0], inner, mid);
     }
     return t.wg * mid;
 }
@@ -260,10 +341,11 @@ __device__ __forceinline__ double contrib_three64(const ReqDev &r, const Smem &s
 // --------------------------------------------------------------------------------------------
 // Float32 precision form
 // --------------------------------------------------------------------------------------------
-// float32 integrand with compensated (Kahan) float32 inner sums; the per-(e, a) contribution is
-// widened to float64 before the radial weight, and every sum across radial nodes is float64.
-// A propagator whose float32 denominator is small against its parts (D < tau (|Z l2 + R| + |m2|),
-// i.e. near the pole m2 -> -(Z l2 + R)) is re-evaluated in float64.
+// float32 integrand; the sum over the innermost angle is compensated (Kahan) in float32 over
+// blocks of FRG_ILP nodes; the per-(e, a) contribution is widened to float64 before the radial
+// weight, and every sum across radial nodes is float64.  A propagator whose float32 denominator
+// is small against its parts (D < tau (|Z l2 + R| + |m2|), i.e. near the pole m2 -> -(Z l2 + R))
+// is re-evaluated in float64.
 struct Kahan32 {
     float s, c;
     __device__ __forceinline__ void add(float v) {
@@ -274,53 +356,89 @@ struct Kahan32 {
     }
 };
 
-__device__ __forceinline__ float dressing32(const float2 *__restrict__ Zs, int nZ, float za,
-                                            float zb, float l2) {
-    float s = fmaf(__logf(l2), za, zb);
-    s = fminf(fmaxf(s, 0.0f), (float)(nZ - 1));
-    int i = (int)s;
-    float f = s - (float)i;
-    float2 z = Zs[i];
-    return fmaf(f, z.y, z.x);
+struct Par32 {
+    int nZ;
+    float za2, zb1;   // s + 1 = za2 * log2(l2) + zb1
+    float m2f, am2f;  // m2 and |m2|
+    float ik, tau;    // 1/k^2, near-pole threshold
+    double m2, inv_k2, za, zb1d;
+};
+
+// W float32 propagators; kmax tracks the largest amplification (|Z l2 + R| + |m2|)/D of the
+// float32 evaluations.
+template <int W>
+__device__ __forceinline__ void propagators32(const float (&l2)[W], float (&G)[W], float &kmax,
+                                              const Smem &sm, const Par32 &P) {
+    int iz[W];
+    float fz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const float sp = fmaf(__builtin_amdgcn_logf(l2[w]), P.za2, P.zb1);
+        iz[w] = min(max((int)sp, 0), P.nZ);
+        fz[w] = __builtin_amdgcn_fractf(sp);
+    }
+    float2 z[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) z[w] = sm.Z32[iz[w]];
+    float E[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) E[w] = fm::expm1_neg_f(l2[w] * P.ik);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const float zv = fmaf(fz[w], z[w].y, z[w].x);
+        const float le = fmaf(l2[w], E[w], l2[w]);
+        const float den = fmaf(-E[w], fmaf(zv, l2[w], P.m2f), le);
+        const float parts = fmaf(-E[w], fmaf(zv, l2[w], P.am2f), le);
+        if (den < P.tau * parts) {
+            const double l2d = (double)l2[w];
+            const double zd = dressing64(sm, P.nZ, P.za, P.zb1d, l2d);
+            G[w] = (float)prop64(l2d, zd, P.m2, P.inv_k2);
+        } else {
+            const float rd = __builtin_amdgcn_rcpf(den);
+            G[w] = -E[w] * rd;
+            kmax = fmaxf(kmax, parts * rd);
+        }
+    }
 }
 
-// Returns G(l2) and the amplification factor kappa = (|Z l2 + R| + |m2|)/D of the float32
-// evaluation (1 when evaluated in float64).
-__device__ __forceinline__ float prop32(float l2, float z, float m2f, double m2, double inv_k2,
-                                        float inv_k2f, float tau, const ReqDev &r, const Smem &sm,
-                                        float &kappa) {
-    float y = l2 * inv_k2f;
-    float E = expm1f(-y);
-    float e = 1.0f + E;
-    float num = -E;
-    float zl = z * l2;
-    float Rn = l2 * e;  // R * num
-    float den = fmaf(num, zl + m2f, Rn);
-    float parts = fmaf(num, zl, Rn) + num * fabsf(m2f);  // num * (|Z l2 + R| + |m2|)
-    if (den < tau * parts) {
-        double l2d = (double)l2;
-        double zd = r.nZ ? dressing64(sm.Z64, r.nZ, r.za, r.zb, l2d) : 1.0;
-        kappa = 1.0f;
-        return (float)prop64(l2d, zd, m2, inv_k2);
-    }
-    kappa = parts / den;
-    return num / den;
+__device__ __forceinline__ Par32 par32(const ReqDev &r, double m2, double inv_k2) {
+    Par32 P;
+    P.nZ = r.nZ;
+    P.za2 = (float)(r.za * 0.69314718055994530942);
+    P.zb1 = (float)(r.zb + 1.0);
+    P.m2f = (float)m2;
+    P.am2f = fabsf(P.m2f);
+    P.ik = (float)inv_k2;
+    P.tau = (float)r.tau;
+    P.m2 = m2;
+    P.inv_k2 = inv_k2;
+    P.za = r.za;
+    P.zb1d = r.zb + 1.0;
+    return P;
 }
 
 __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm, int a, double p,
                                                 double m2, double inv_k2, float &kmax) {
-    RadialTerm t = radial64(r, sm, a, p, m2, inv_k2);
-    const float c0 = (float)t.c0, c1 = (float)t.c1, m2f = (float)m2, ik = (float)inv_k2;
-    const float za = (float)r.za, zb = (float)r.zb, tau = (float)r.tau;
+    const RadialTerm t = radial64(r, sm, a, p, m2);
+    const Par32 P = par32(r, m2, inv_k2);
+    const float c0 = (float)t.c0, c1 = (float)t.c1;
     Kahan32 acc{0.0f, 0.0f};
     const int nx = r.n_x;
-    for (int b = 0; b < nx; ++b) {
-        float l2 = fmaxf(fmaf(c1, r.ang.xf[b], c0), 1e-30f);
-        float z = r.nZ ? dressing32(sm.Z32, r.nZ, za, zb, l2) : 1.0f;
-        float kap;
-        float g = prop32(l2, z, m2f, m2, inv_k2, ik, tau, r, sm, kap);
-        kmax = fmaxf(kmax, kap);
-        acc.add(r.ang.xwf[b] * g);
+    int b = 0;
+    for (; b + FRG_ILP <= nx; b += FRG_ILP) {
+        float l2[FRG_ILP], G[FRG_ILP];
+#pragma unroll
+        for (int w = 0; w < FRG_ILP; ++w) l2[w] = fmaxf(fmaf(c1, r.ang.xf[b + w], c0), 1e-30f);
+        propagators32<FRG_ILP>(l2, G, kmax, sm, P);
+        float blk = 0.0f;
+#pragma unroll
+        for (int w = 0; w < FRG_ILP; ++w) blk = fmaf(r.ang.xwf[b + w], G[w], blk);
+        acc.add(blk);
+    }
+    for (; b < nx; ++b) {
+        float l2[1] = {fmaxf(fmaf(c1, r.ang.xf[b], c0), 1e-30f)}, G[1];
+        propagators32<1>(l2, G, kmax, sm, P);
+        acc.add(r.ang.xwf[b] * G[0]);
     }
     return t.wg * ((double)acc.s - (double)acc.c);
 }
@@ -328,60 +446,84 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
 __device__ __forceinline__ double contrib_three32(const ReqDev &r, const Smem &sm, int a, double p,
                                                   double ca, double sa, double m2,
                                                   double inv_k2, float &kmax) {
-    RadialTerm t = radial64(r, sm, a, p, m2, inv_k2);
-    const float c0 = (float)t.c0, c1 = (float)t.c1, m2f = (float)m2, ik = (float)inv_k2;
-    const float za = (float)r.za, zb = (float)r.zb, tau = (float)r.tau;
+    const RadialTerm t = radial64(r, sm, a, p, m2);
+    const Par32 P = par32(r, m2, inv_k2);
+    const float c0 = (float)t.c0, c1 = (float)t.c1;
     const float caf = (float)ca, saf = (float)sa;
     double mid = 0.0;
     const int nx = r.n_x, nphi = r.n_phi;
     for (int b = 0; b < nx; ++b) {
-        float xb = r.ang.xf[b];
-        float l1 = fmaxf(fmaf(c1, xb, c0), 1e-30f);
-        float z1 = r.nZ ? dressing32(sm.Z32, r.nZ, za, zb, l1) : 1.0f;
-        float kap;
-        float g1 = prop32(l1, z1, m2f, m2, inv_k2, ik, tau, r, sm, kap);
-        kmax = fmaxf(kmax, kap);
-        float A2 = fmaf(-c1, xb * caf, c0);
-        float B2 = -c1 * (r.ang.xsf[b] * saf);
+        const float xb = r.ang.xf[b];
+        float l1[1] = {fmaxf(fmaf(c1, xb, c0), 1e-30f)}, g1[1];
+        propagators32<1>(l1, g1, kmax, sm, P);
+        const float A2 = fmaf(-c1, xb * caf, c0);
+        const float B2 = -c1 * (r.ang.xsf[b] * saf);
         Kahan32 acc{0.0f, 0.0f};
-        for (int c = 0; c < nphi; ++c) {
-            float l2 = fmaxf(fmaf(B2, r.phi.cf[c], A2), 1e-30f);
-            float z2 = r.nZ ? dressing32(sm.Z32, r.nZ, za, zb, l2) : 1.0f;
-            float g2 = prop32(l2, z2, m2f, m2, inv_k2, ik, tau, r, sm, kap);
-            kmax = fmaxf(kmax, kap);
-            acc.add(r.phi.wf[c] * g2);
+        int c = 0;
+        for (; c + FRG_ILP <= nphi; c += FRG_ILP) {
+            float l2[FRG_ILP], G[FRG_ILP];
+#pragma unroll
+            for (int w = 0; w < FRG_ILP; ++w)
+                l2[w] = fmaxf(fmaf(B2, r.phi.cf[c + w], A2), 1e-30f);
+            propagators32<FRG_ILP>(l2, G, kmax, sm, P);
+            float blk = 0.0f;
+#pragma unroll
+            for (int w = 0; w < FRG_ILP; ++w) blk = fmaf(r.phi.wf[c + w], G[w], blk);
+            acc.add(blk);
         }
-        double inner = (double)acc.s - (double)acc.c;
-        mid = fma((double)r.ang.xw[b] * (double)g1, inner, mid);
+        for (; c < nphi; ++c) {
+            float l2[1] = {fmaxf(fmaf(B2, r.phi.cf[c], A2), 1e-30f)}, G[1];
+            propagators32<1>(l2, G, kmax, sm, P);
+            acc.add(r.phi.wf[c] * G[0]);
+        }
+        const double inner = (double)acc.s - (double)acc.c;
+        mid = fma((double)r.ang.xw[b] * (double)g1[0], inner, mid);
     }
     return t.wg * mid;
 }
+
+// float32 form's stated relative error bound per result: (C0 + 2 kappa_max) u32, u32 = 2^-24
+#define FRG_FP32_BOUND(kmax) ((double)(40.0f + 2.0f * (kmax)) * 5.9604644775390625e-8)
 
 // --------------------------------------------------------------------------------------------
 // Tile bodies
 // --------------------------------------------------------------------------------------------
 __device__ __forceinline__ void stage_tables(const ReqDev &r, Smem &sm) {
-    // (Z_i, Z_{i+1} - Z_i) pairs, zero slope in the last entry; float32 copies for that form
-    for (int i = threadIdx.x; i < r.nZ; i += blockDim.x) {
-        double zi = r.Z[i];
-        double dz = (i + 1 < r.nZ) ? (r.Z[i + 1] - zi) : 0.0;
-        sm.Z64[i] = make_double2(zi, dz);
-        if (r.precision == 1) sm.Z32[i] = make_float2((float)zi, (float)dz);
+    for (int i = threadIdx.x; i < kLogTable; i += blockDim.x) sm.logt[i] = r.logt[i];
+    // padded dressing: entry j (0..n) is (Z_{j-1}, Z_j - Z_{j-1}) with constant end entries
+    const int n = r.nZ;
+    for (int j = threadIdx.x; j <= n; j += blockDim.x) {
+        double zi, dz;
+        if (j == 0) {
+            zi = r.Z[0];
+            dz = 0.0;
+        } else {
+            zi = r.Z[j - 1];
+            dz = (j < n) ? (r.Z[j] - zi) : 0.0;
+        }
+        sm.Z64[j] = make_double2(zi, dz);
+        if (r.precision == 1) sm.Z32[j] = make_float2((float)zi, (float)dz);
     }
 }
 
+__device__ __forceinline__ void bind_smem(Smem &sm, double2 *lds, int nZ) {
+    sm.logt = lds;
+    sm.Z64 = lds + kLogTable;
+    sm.Z32 = (float2 *)(lds + kLogTable + nZ + 1);
+}
+
 // LPA: one lane per external point, the whole radial sum in one lane, no scratch.
+template <int PREC>
 __device__ __forceinline__ void tile_lpa(const ReqDev &r, int et) {
-    int e = et * kWave + (int)threadIdx.x;
+    const int e = et * kWave + (int)threadIdx.x;
     if (e >= r.n_ext) return;
-    double m2 = lane_m2(r, e);
+    const double m2 = lane_m2(r, e);
     const int nq = r.n_q;
-    if (r.precision == 0) {
+    if (PREC == 0) {
         double acc = 0.0;
         for (int a = 0; a < nq; ++a) {
-            double qh = r.rad.q[a];
-            double t = fma(r.k2, fma(qh, qh, r.rad.R[a]), m2);
-            double g = 1.0 / t;
+            const double qh = r.rad.q[a];
+            const double g = fm::rcp_nr(fma(r.k2, fma(qh, qh, r.rad.R[a]), m2));
             acc = fma(r.rad.W[a], g * g, acc);
         }
         r.out[e] = r.pref * acc;
@@ -392,27 +534,27 @@ __device__ __forceinline__ void tile_lpa(const ReqDev &r, int et) {
         Kahan32 acc{0.0f, 0.0f};
         float kmax = 1.0f;
         for (int a = 0; a < nq; ++a) {
-            float qh = r.rad.qf[a];
-            float A = k2f * fmaf(qh, qh, r.rad.Rf[a]);
-            float t = A + m2f;
+            const float qh = r.rad.qf[a];
+            const float A = k2f * fmaf(qh, qh, r.rad.Rf[a]);
+            const float t = A + m2f;
             float g;
             if (t < tau * (A + fabsf(m2f))) {
-                double qd = r.rad.q[a];
-                g = (float)(1.0 / fma(r.k2, fma(qd, qd, r.rad.R[a]), m2));
+                const double qd = r.rad.q[a];
+                g = (float)fm::rcp_nr(fma(r.k2, fma(qd, qd, r.rad.R[a]), m2));
             } else {
-                g = 1.0f / t;
-                kmax = fmaxf(kmax, (A + fabsf(m2f)) / t);
+                g = __builtin_amdgcn_rcpf(t);
+                kmax = fmaxf(kmax, (A + fabsf(m2f)) * g);
             }
             acc.add(r.rad.Wf[a] * (g * g));
         }
         r.out[e] = r.pref * ((double)acc.s - (double)acc.c);
-        if (r.err) r.err[e] = (double)(40.0f + 2.0f * kmax) * 5.9604644775390625e-8;
+        if (r.err) r.err[e] = FRG_FP32_BOUND(kmax);
     }
 }
 
 // Vertex families: lanes = (external point, radial sub-lane); contributions to scratch; the last
-// chunk of an external tile reduces in radial order.
-template <int FAM>
+// chunk of an external tile adds them in radial order.
+template <int FAM, int PREC>
 __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int et, int chunk,
                                             double *__restrict__ contrib,
                                             unsigned *__restrict__ counters) {
@@ -427,27 +569,26 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
     const int a1 = (int)(((long long)r.n_q * (chunk + 1)) / r.chunks);
     const double inv_k2 = 1.0 / r.k2;
     double *blk = contrib + r.contrib_base;
+    // per-point slots after the tile counters (zero at rest): largest float32 amplification
+    unsigned *kslot = counters + r.ctr_base + r.ext_tiles;
     float kmax = 1.0f;
     if (valid) {
-        double p = r.ext[e];
-        double m2 = lane_m2(r, e);
+        const double p = r.ext[e];
+        const double m2 = lane_m2(r, e);
         double ca = 1.0, sa = 0.0;
         if (FAM == 3) sincos(r.ext[r.n_ext + e], &sa, &ca);
         for (int a = a0 + sub; a < a1; a += lq) {
             double v;
-            if (r.precision == 0) {
+            if (PREC == 0)
                 v = (FAM == 2) ? contrib_two64(r, sm, a, p, m2, inv_k2)
                                : contrib_three64(r, sm, a, p, ca, sa, m2, inv_k2);
-            } else {
+            else
                 v = (FAM == 2) ? contrib_two32(r, sm, a, p, m2, inv_k2, kmax)
                                : contrib_three32(r, sm, a, p, ca, sa, m2, inv_k2, kmax);
-            }
             blk[(long long)a * r.n_ext + e] = v;
         }
+        if (PREC == 1) atomicMax(&kslot[e], __float_as_uint(kmax));
     }
-    // per-point slots after the tile counters (zero at rest): largest float32 amplification
-    unsigned *kslot = counters + r.ctr_base + r.ext_tiles;
-    if (r.precision == 1 && valid) atomicMax(&kslot[e], __float_as_uint(kmax));
     // publish the contributions, then count this chunk
     __threadfence();
     __syncthreads();
@@ -460,7 +601,7 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
     if (!last) return;
     __threadfence();
     if (lane < le) {
-        int ef = et * le + lane;
+        const int ef = et * le + lane;
         if (ef < r.n_ext) {
             double s = 0.0;
             for (int a = 0; a < r.n_q; ++a) {
@@ -470,50 +611,35 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
                 s += __longlong_as_double((long long)bits);
             }
             r.out[ef] = r.pref * s;
-            if (r.err) {
-                if (r.precision == 1) {
-                    unsigned kb = __hip_atomic_load(&kslot[ef], __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-                    float km = __uint_as_float(kb);
-                    r.err[ef] = (double)(40.0f + 2.0f * km) * 5.9604644775390625e-8;
-                } else {
-                    r.err[ef] = 0.0;
-                }
-            }
-            if (r.precision == 1)
+            if (PREC == 1) {
+                unsigned kb = __hip_atomic_load(&kslot[ef], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+                if (r.err) r.err[ef] = FRG_FP32_BOUND(__uint_as_float(kb));
                 __hip_atomic_store(&kslot[ef], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else if (r.err) {
+                r.err[ef] = 0.0;
+            }
         }
     }
     if (lane == 0) atomicExch(&counters[r.ctr_base + et], 0u);
 }
 
-__device__ __forceinline__ void run_tile(const ReqDev &r, Smem &sm, int et, int chunk,
-                                         double *contrib, unsigned *counters) {
-    if (r.family == 1)
-        tile_lpa(r, et);
-    else if (r.family == 2)
-        tile_vertex<2>(r, sm, et, chunk, contrib, counters);
-    else
-        tile_vertex<3>(r, sm, et, chunk, contrib, counters);
-}
-
 // One request: tile = blockIdx.x -> (external tile, chunk).
-template <int FAM>
-__global__ void __launch_bounds__(64) batch_kernel(ReqDev r, double *contrib, unsigned *counters) {
-    extern __shared__ double2 lds_z[];
-    Smem sm;
-    sm.Z64 = lds_z;
-    sm.Z32 = (float2 *)(lds_z + (r.nZ > 0 ? r.nZ : 0));
-    int et = blockIdx.x / r.chunks;
-    int chunk = blockIdx.x - et * r.chunks;
-    if (FAM != 1 && r.nZ > 0) {
-        stage_tables(r, sm);
-        __syncthreads();
+template <int FAM, int PREC>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FRG_WAVES_PER_EU)))
+batch_kernel(ReqDev r, double *contrib, unsigned *counters) {
+    extern __shared__ double2 lds_dyn[];
+    if (FAM == 1) {
+        tile_lpa<PREC>(r, blockIdx.x);
+        return;
     }
-    if (FAM == 1)
-        tile_lpa(r, et);
-    else
-        tile_vertex<FAM>(r, sm, et, chunk, contrib, counters);
+    Smem sm;
+    bind_smem(sm, lds_dyn, r.nZ);
+    const int et = blockIdx.x / r.chunks;
+    const int chunk = blockIdx.x - et * r.chunks;
+    stage_tables(r, sm);
+    __syncthreads();
+    tile_vertex<FAM, PREC>(r, sm, et, chunk, contrib, counters);
 }
 
 hipError_t launch_batch(const ReqDev *req_host, const ReqDev *req_dev_ptr, int n_tiles,
@@ -521,50 +647,66 @@ hipError_t launch_batch(const ReqDev *req_host, const ReqDev *req_dev_ptr, int n
     (void)req_dev_ptr;
     const ReqDev &r = *req_host;
     if (n_tiles <= 0) return hipSuccess;
-    if (r.family == 1)
-        hipLaunchKernelGGL(batch_kernel<1>, dim3(n_tiles), dim3(kWave), 0, s, r, contrib,
-                           counters);
-    else if (r.family == 2)
-        hipLaunchKernelGGL(batch_kernel<2>, dim3(n_tiles), dim3(kWave), lds_bytes, s, r,
-                           contrib, counters);
-    else
-        hipLaunchKernelGGL(batch_kernel<3>, dim3(n_tiles), dim3(kWave), lds_bytes, s, r,
-                           contrib, counters);
+    const dim3 g(n_tiles), b(kWave);
+#define FRG_LAUNCH(F, P) \
+    hipLaunchKernelGGL((batch_kernel<F, P>), g, b, lds_bytes, s, r, contrib, counters)
+    if (r.family == 1) {
+        if (r.precision == 0) FRG_LAUNCH(1, 0); else FRG_LAUNCH(1, 1);
+    } else if (r.family == 2) {
+        if (r.precision == 0) FRG_LAUNCH(2, 0); else FRG_LAUNCH(2, 1);
+    } else {
+        if (r.precision == 0) FRG_LAUNCH(3, 0); else FRG_LAUNCH(3, 1);
+    }
+#undef FRG_LAUNCH
     return hipGetLastError();
 }
 
 // Many requests in one launch.  A grid sized to the device pulls tiles (ordered largest first by
 // the host) from a global counter until the list is empty; the last workgroup to leave resets the
 // counters, so the kernel can be relaunched (or replayed in a graph) without a memset.
-__global__ void __launch_bounds__(64) multi_kernel(const ReqDev *__restrict__ reqs,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FRG_WAVES_PER_EU)))
+multi_kernel(const ReqDev *__restrict__ reqs,
                                                    const TileDev *__restrict__ tiles, int n_tiles,
                                                    double *contrib, unsigned *counters,
                                                    unsigned *work) {
-    extern __shared__ double2 lds_z[];
+    extern __shared__ double2 lds_dyn[];
     __shared__ int tile_s;
     Smem sm;
     int staged = -1;
     for (;;) {
         if (threadIdx.x == 0) tile_s = (int)atomicAdd(&work[0], 1u);
         __syncthreads();
-        int t = tile_s;
+        const int t = tile_s;
         __syncthreads();
         if (t >= n_tiles) break;
-        TileDev td = tiles[t];
+        const TileDev td = tiles[t];
         const ReqDev &r = reqs[td.req];
-        sm.Z64 = lds_z;
-        sm.Z32 = (float2 *)(lds_z + r.nZ);
-        if (r.family != 1 && r.nZ > 0 && staged != td.req) {
+        if (r.family == 1) {
+            if (r.precision == 0) tile_lpa<0>(r, td.et); else tile_lpa<1>(r, td.et);
+            continue;
+        }
+        bind_smem(sm, lds_dyn, r.nZ);
+        if (staged != td.req) {
             stage_tables(r, sm);
             __syncthreads();
             staged = td.req;
         }
-        run_tile(r, sm, td.et, td.chunk, contrib, counters);
+        if (r.family == 2) {
+            if (r.precision == 0)
+                tile_vertex<2, 0>(r, sm, td.et, td.chunk, contrib, counters);
+            else
+                tile_vertex<2, 1>(r, sm, td.et, td.chunk, contrib, counters);
+        } else {
+            if (r.precision == 0)
+                tile_vertex<3, 0>(r, sm, td.et, td.chunk, contrib, counters);
+            else
+                tile_vertex<3, 1>(r, sm, td.et, td.chunk, contrib, counters);
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         __threadfence();
-        unsigned done = atomicAdd(&work[1], 1u);
+        const unsigned done = atomicAdd(&work[1], 1u);
         if (done == gridDim.x - 1) {
             atomicExch(&work[0], 0u);
             atomicExch(&work[1], 0u);
@@ -579,6 +721,20 @@ hipError_t launch_multi(const ReqDev *reqs_dev, int n_reqs, const TileDev *tiles
     if (n_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(multi_kernel, dim3(grid), dim3(kWave), lds_bytes, s, reqs_dev, tiles_dev,
                        n_tiles, contrib, counters, work_ctr);
+    return hipGetLastError();
+}
+
+// Logarithm table for fm::log_tab: (2 c_j, ln(1/c_j) - ln 2), c_j = 1/(1 + (j + 1/2)/256) rounded
+// to double (2 c_j is exact), ln(1/c_j) - ln 2 to a few ulp of a number below 1 in magnitude.
+__global__ void __launch_bounds__(256) log_table_kernel(double2 *out) {
+    const int j = threadIdx.x;
+    if (j >= kLogTable) return;
+    const double c = 1.0 / (1.0 + (j + 0.5) / 256.0);
+    out[j] = make_double2(2.0 * c, -log(c) - 0.69314718055994530942);
+}
+
+hipError_t launch_log_table(double2 *out, hipStream_t s) {
+    hipLaunchKernelGGL(log_table_kernel, dim3(1), dim3(kLogTable), 0, s, out);
     return hipGetLastError();
 }
 

@@ -234,8 +234,10 @@ int counter_count(const ReqDev &r) {
 int tile_count(const ReqDev &r) { return r.ext_tiles * r.chunks; }
 
 int lds_bytes_for(const ReqDev &r) {
-    if (r.family == 1 || r.nZ == 0) return 0;
-    return r.nZ * (int)sizeof(double2) + (r.precision == 1 ? r.nZ * (int)sizeof(float2) : 0);
+    // logarithm table, float64 dressing pairs, float32 dressing pairs (float32 form)
+    if (r.family == 1) return 0;
+    return (kLogTable + r.nZ + 1) * (int)sizeof(double2) +
+           (r.precision == 1 ? (r.nZ + 1) * (int)sizeof(float2) : 0);
 }
 
 frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_batch &b,
@@ -269,13 +271,17 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
     r.m2s = b.m2_scalar;
     r.m2_floor = m2_floor;
     r.tau = d.precision == 1 ? d.near_pole_tau : 0.0;
-    if (d.family >= 2 && b.Z.values) {
-        r.nZ = b.Z.n;
-        double lmin = std::log(b.Z.x_min), lmax = std::log(b.Z.x_max);
-        double delta = (lmax - lmin) / (double)(b.Z.n - 1);
+    if (d.family >= 2) {
+        // without a dressing table the kernels look up a two-entry table of ones (Z == 1 exactly),
+        // which keeps the inner loops free of branches
+        const bool has = b.Z.values != nullptr;
+        r.nZ = has ? b.Z.n : 2;
+        double xmin = has ? b.Z.x_min : 1.0, xmax = has ? b.Z.x_max : 2.0;
+        double lmin = std::log(xmin), lmax = std::log(xmax);
+        double delta = (lmax - lmin) / (double)(r.nZ - 1);
         r.za = 0.5 / delta;
         r.zb = -lmin / delta;
-        r.Z = b.Z.values;
+        r.Z = has ? b.Z.values : (const double *)ctx->ones.ptr;
     }
     frg_status st = get_radial(ctx, d.n_q, d.q_max, d.d, &r.rad);
     if (st != FRG_OK) return st;
@@ -287,6 +293,7 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
         st = get_phi(ctx, d.n_phi, &r.phi);
         if (st != FRG_OK) return st;
     }
+    r.logt = (const double2 *)ctx->logtab.ptr;
     r.ext = b.ext;
     r.m2 = b.m2;
     r.out = b.out;
@@ -339,19 +346,12 @@ frg_status run_batch(frg_context *ctx, ReqDev &r, hipStream_t s, Scratch *sc) {
     return FRG_OK;
 }
 
-frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s, Scratch *sc,
-                     int grid_waves) {
-    (void)ctx;
+std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out) {
     std::vector<TileDev> tiles;
     std::vector<double> cost;
-    long long cb = 0;
-    int ctr = 0, lds = 0;
+    int lds = 0;
     for (size_t i = 0; i < reqs.size(); ++i) {
-        ReqDev &r = reqs[i];
-        r.contrib_base = cb;
-        r.ctr_base = ctr;
-        cb += (long long)contrib_doubles(r);
-        ctr += counter_count(r);
+        const ReqDev &r = reqs[i];
         lds = std::max(lds, lds_bytes_for(r));
         int lq = 1 << r.lq_log2;
         double inner = r.family == 1 ? 1.0 : (double)r.n_x * (r.family == 3 ? r.n_phi : 1);
@@ -359,18 +359,35 @@ frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s,
             for (int ch = 0; ch < r.chunks; ++ch) {
                 int a0 = (int)(((long long)r.n_q * ch) / r.chunks);
                 int a1 = (int)(((long long)r.n_q * (ch + 1)) / r.chunks);
-                double c = r.family == 1 ? (double)r.n_q : std::ceil((double)(a1 - a0) / lq) * inner;
+                double c = r.family == 1 ? (double)r.n_q
+                                         : std::ceil((double)(a1 - a0) / lq) * inner;
                 tiles.push_back(TileDev{(int)i, et, ch, 0});
                 cost.push_back(c);
             }
     }
-    if (tiles.empty()) return FRG_OK;
     // longest-processing-time-first order; ties keep request/tile order
     std::vector<int> order(tiles.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     std::vector<TileDev> sorted(tiles.size());
     for (size_t i = 0; i < order.size(); ++i) sorted[i] = tiles[order[i]];
+    if (lds_out) *lds_out = lds;
+    return sorted;
+}
+
+frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s, Scratch *sc,
+                     int grid_waves) {
+    (void)ctx;
+    long long cb = 0, ctr = 0;
+    for (ReqDev &r : reqs) {
+        r.contrib_base = cb;
+        r.ctr_base = ctr;
+        cb += (long long)contrib_doubles(r);
+        ctr += counter_count(r);
+    }
+    int lds = 0;
+    std::vector<TileDev> sorted = make_tiles(reqs, &lds);
+    if (sorted.empty()) return FRG_OK;
     size_t rb = reqs.size() * sizeof(ReqDev), tb = sorted.size() * sizeof(TileDev);
     if (!sc->staged) FRG_HIP_CHECK(hipEventCreateWithFlags(&sc->staged, hipEventDisableTiming));
     // the previous upload from the staging area must have finished before it is rewritten
@@ -449,8 +466,25 @@ frg_status frg_context_create(int device, size_t hbm_budget_bytes, frg_context *
     FRG_HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
     ctx->hbm_budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
     FRG_HIP_CHECK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    FRG_HIP_CHECK(ctx->logtab.alloc(kLogTable * sizeof(double2)));
+    FRG_HIP_CHECK(launch_log_table((double2 *)ctx->logtab.ptr, ctx->aux));
+    {
+        const double ones[2] = {1.0, 1.0};
+        FRG_HIP_CHECK(ctx->ones.alloc(sizeof ones));
+        FRG_HIP_CHECK(hipMemcpy(ctx->ones.ptr, ones, sizeof ones, hipMemcpyHostToDevice));
+    }
+    FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
     const char *tp = std::getenv("FRG_AUTOTUNE_CACHE");
-    if (tp) ctx->tune_path = tp;
+    if (tp) {
+        // lines: family precision n_q n_x n_phi n_ext target lq_log2 chunks
+        ctx->tune_path = tp;
+        std::ifstream f(tp);
+        std::vector<int> v(9);
+        while (f && (f >> v[0] >> v[1] >> v[2] >> v[3] >> v[4] >> v[5] >> v[6] >> v[7] >> v[8])) {
+            if (v[7] < 0 || v[7] > 4 || v[8] < 1 || v[8] > FRG_MAX_NODES) continue;
+            ctx->tuned[std::vector<int>(v.begin(), v.begin() + 7)] = TileShape{v[7], v[8]};
+        }
+    }
     *out = ctx.release();
     return FRG_OK;
 }
@@ -489,6 +523,78 @@ frg_status frg_integrate_batch(frg_context *ctx, const frg_integral_desc *desc,
     if ((st = get_scratch(ctx, stream, contrib_doubles(r), counter_count(r), 1, 1, &sc)) != FRG_OK)
         return st;
     return run_batch(ctx, r, stream, sc);
+}
+
+frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const frg_batch *batch,
+                        hipStream_t stream, int reps, double *best_us) {
+    clear_error();
+    if (!ctx || reps < 1 || reps > 1000) {
+        set_error("invalid arguments to frg_autotune");
+        return FRG_E_INVAL;
+    }
+    frg_status st = validate(desc, batch, true);
+    if (st != FRG_OK) return st;
+    if (batch->n_ext == 0 || desc->family == 1) return FRG_OK;  // LPA has a single shape
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    FRG_HIP_CHECK(hipSetDevice(ctx->device));
+    const int target = 16 * ctx->num_cus;
+    std::vector<TileShape> cands;
+    for (int lq = 0; lq <= 4; ++lq) {
+        const int le = kWave >> lq;
+        if (lq > 0 && le / 2 >= batch->n_ext) continue;  // narrower than needed
+        const int max_chunks = (desc->n_q + (1 << lq) - 1) >> lq;
+        for (int ch = 1; ch <= max_chunks; ch *= 2) cands.push_back(TileShape{lq, ch});
+        if ((max_chunks & (max_chunks - 1)) != 0) cands.push_back(TileShape{lq, max_chunks});
+    }
+    cands.push_back(heuristic_shape(*desc, batch->n_ext, target));
+    hipEvent_t e0, e1;
+    FRG_HIP_CHECK(hipEventCreate(&e0));
+    FRG_HIP_CHECK(hipEventCreate(&e1));
+    double best = 1e300;
+    TileShape best_shape = cands.back();
+    frg_status res = FRG_OK;
+    for (const TileShape &c : cands) {
+        ReqDev r;
+        if ((res = make_request(ctx, *desc, *batch, c, 1, 0.0, 1.0, &r)) != FRG_OK) break;
+        Scratch *sc;
+        if ((res = get_scratch(ctx, stream, contrib_doubles(r), counter_count(r), 1, 1, &sc)) !=
+            FRG_OK)
+            break;
+        if ((res = run_batch(ctx, r, stream, sc)) != FRG_OK) break;  // warm-up
+        double t_best = 1e300;
+        for (int k = 0; k < reps && res == FRG_OK; ++k) {
+            if (hipEventRecord(e0, stream) != hipSuccess) res = FRG_E_DEVICE;
+            if (res == FRG_OK) res = run_batch(ctx, r, stream, sc);
+            if (res == FRG_OK && hipEventRecord(e1, stream) != hipSuccess) res = FRG_E_DEVICE;
+            if (res == FRG_OK && hipEventSynchronize(e1) != hipSuccess) res = FRG_E_DEVICE;
+            float ms = 0.f;
+            if (res == FRG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) res = FRG_E_DEVICE;
+            t_best = std::min(t_best, (double)ms * 1e3);
+        }
+        if (res != FRG_OK) break;
+        if (t_best < best) {
+            best = t_best;
+            best_shape = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (res != FRG_OK) {
+        if (res == FRG_E_DEVICE && g_last_error.empty()) set_error("autotune launch failed");
+        return res;
+    }
+    std::vector<int> key = {desc->family, desc->precision, desc->n_q, desc->n_x, desc->n_phi,
+                            batch->n_ext, target};
+    ctx->tuned[key] = best_shape;
+    if (best_us) *best_us = best;
+    if (!ctx->tune_path.empty()) {
+        std::ofstream f(ctx->tune_path, std::ios::app);
+        if (f) {
+            for (int v : key) f << v << ' ';
+            f << best_shape.lq_log2 << ' ' << best_shape.chunks << '\n';
+        }
+    }
+    return FRG_OK;
 }
 
 frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc *descs,

@@ -100,6 +100,8 @@ struct frg_context {
     int num_cus = 256;
     std::mutex mu;
     hipStream_t aux = nullptr;  // rule construction and graph capture
+    frg::DeviceBuffer logtab;   // float64 logarithm table (double2[256])
+    frg::DeviceBuffer ones;     // {1, 1}: dressing table of requests without one
     std::map<std::tuple<int, double, int>, std::unique_ptr<frg::RadialEntry>> radial;
     std::map<int, std::unique_ptr<frg::AngleEntry>> cos1;
     std::map<int, std::unique_ptr<frg::PhiEntry>> phi;
@@ -133,6 +135,8 @@ frg_status run_batch(frg_context *ctx, ReqDev &r, hipStream_t s, Scratch *sc);
 frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s, Scratch *sc,
                      int grid_waves);
 frg_status relaunch_multi(Scratch *sc, hipStream_t s);
+// Tiles of a fused launch in longest-first order, and the dynamic LDS bytes it needs.
+std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out);
 int lds_bytes_for(const ReqDev &r);
 
 }  // namespace frg

@@ -10,8 +10,16 @@ import ctypes
 import os
 from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_size_t, c_uint64, c_void_p
 
+# torch ships its own HIP and HSA runtimes (same sonames as the system ROCm ones).  Importing it
+# before libfrg.so makes the loader bind libfrg's libamdhip64.so.7 dependency to the copy torch
+# already loaded, so the process has one HIP runtime; loading libfrg.so first would bring in a
+# second runtime, and whichever initialises second finds no device.
+import torch  # noqa: F401  (load order matters, see above)
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfrg.so")
+# FRG_LIBRARY selects another build of the same library (for example one compiled with different
+# tuning macros); the default is the in-tree build.
+LIB_PATH = os.environ.get("FRG_LIBRARY") or os.path.join(_HERE, "libfrg.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -82,6 +90,8 @@ _sig = {
     "frg_integrate_multi": ([_P, c_int, POINTER(frg_integral_desc), POINTER(frg_batch), _P],
                             c_int),
     "frg_flow_rhs": ([_P, POINTER(frg_integral_desc), POINTER(frg_flow_state), _P, _P], c_int),
+    "frg_autotune": ([_P, POINTER(frg_integral_desc), POINTER(frg_batch), _P, c_int,
+                      POINTER(c_double)], c_int),
     "frg_session_open": ([_P, POINTER(frg_session_config), POINTER(c_void_p)], c_int),
     "frg_session_register_table": ([_P, _P, c_int, c_double, c_double, POINTER(c_int)], c_int),
     "frg_session_submit": ([_P, POINTER(frg_integral_desc), POINTER(frg_batch), c_int,
@@ -97,6 +107,11 @@ for _name, (_args, _res) in _sig.items():
     _fn = getattr(_lib, _name)
     _fn.argtypes = _args
     _fn.restype = _res
+# test double of the serving loop (include/frg_testing.h)
+_lib.frg_session_open_fake.argtypes = [POINTER(frg_session_config), c_double, c_double,
+                                       POINTER(c_void_p)]
+_lib.frg_session_open_fake.restype = c_int
+TESTING_EXPORTED = ("frg_session_open_fake",)
 
 
 def frg_last_error() -> str:
@@ -132,6 +147,14 @@ def frg_integrate_multi(ctx: int, descs, batches, stream: int) -> None:
     _check(_lib.frg_integrate_multi(ctx, n, D, B, stream), "frg_integrate_multi")
 
 
+def frg_autotune(ctx: int, desc: frg_integral_desc, batch: frg_batch, stream: int,
+                 reps: int = 3) -> float:
+    best = c_double()
+    _check(_lib.frg_autotune(ctx, byref(desc), byref(batch), stream, reps, byref(best)),
+           "frg_autotune")
+    return best.value
+
+
 def frg_flow_rhs(ctx: int, desc: frg_integral_desc, state: frg_flow_state, dstate_dt: int,
                  stream: int) -> None:
     _check(_lib.frg_flow_rhs(ctx, byref(desc), byref(state), dstate_dt, stream), "frg_flow_rhs")
@@ -140,6 +163,13 @@ def frg_flow_rhs(ctx: int, desc: frg_integral_desc, state: frg_flow_state, dstat
 def frg_session_open(ctx: int, cfg: frg_session_config) -> int:
     h = c_void_p()
     _check(_lib.frg_session_open(ctx, byref(cfg), byref(h)), "frg_session_open")
+    return h.value
+
+
+def frg_session_open_fake(cfg: frg_session_config, ns_per_node: float, base_us: float) -> int:
+    h = c_void_p()
+    _check(_lib.frg_session_open_fake(byref(cfg), ns_per_node, base_us, byref(h)),
+           "frg_session_open_fake")
     return h.value
 
 
@@ -253,6 +283,12 @@ class Context:
                        x_min=x_min, x_max=x_max, err_out=err_out)
         frg_integrate_batch(self.handle, desc, b, _stream(stream))
         return out
+
+    def autotune(self, desc, out, *, ext=None, m2=None, m2_scalar=0.0, Z=None, x_min=1e-3,
+                 x_max=1e3, reps=3, stream=None):
+        b = make_batch(int(out.numel()), out, ext=ext, m2=m2, m2_scalar=m2_scalar, Z=Z,
+                       x_min=x_min, x_max=x_max)
+        return frg_autotune(self.handle, desc, b, _stream(stream), reps)
 
     def integrate_multi(self, descs, batches, stream=None):
         frg_integrate_multi(self.handle, list(descs), list(batches), _stream(stream))

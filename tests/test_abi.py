@@ -78,3 +78,16 @@ def test_context_create_rejects_bad_arguments():
 
 def test_destroy_null_is_noop():
     assert frg.raw_status("frg_context_destroy", None) == frg.FRG_OK
+
+
+def test_binding_loads_a_single_hip_runtime():
+    # the binding imports torch first, so libfrg.so binds to torch's HIP runtime
+    import subprocess
+    import sys
+
+    code = ("from paper_2412_13043_amd import frg\n"
+            "m = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in m if 'libamdhip64' in l}))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         cwd=ROOT, check=True).stdout.split()
+    assert out[-1] == "1"

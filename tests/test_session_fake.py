@@ -1,0 +1,168 @@
+"""Serving-loop scheduling on the CPU, through the test-double executor (include/frg_testing.h):
+admission against the HBM budget, arrival order, rejection of oversized requests, cancellation,
+the watchdog, close-while-busy and the statistics.  No device work runs and nothing is computed;
+the result checks of sessions are GPU tests."""
+import ctypes
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2412_13043_amd import frg
+
+
+def _cfg(inflight=2, budget=1 << 20, poll_us=50, watchdog_ms=0):
+    return frg.frg_session_config(inflight, budget, poll_us, watchdog_ms)
+
+
+class Req:
+    """Host buffers of one two-point request (kept alive until its ticket ends)."""
+
+    def __init__(self, n_ext=64, n_q=16, n_x=8):
+        self.p = np.linspace(0.01, 5.0, n_ext)
+        self.out = np.full(n_ext, -1.0)
+        self.desc = frg.make_desc(frg.FRG_FAMILY_TWO_POINT, n_q, 10.0, n_x=n_x)
+        self.batch = frg.frg_batch(n_ext, self.p.ctypes.data, None, 0.5,
+                                   frg.frg_log_table(None, 0, 1e-3, 1e3),
+                                   self.out.ctypes.data, None)
+
+    @property
+    def nodes(self):
+        return self.batch.n_ext * self.desc.n_q * self.desc.n_x
+
+    def footprint(self):
+        # inputs, outputs and the [n_q][n_ext] contribution block, 256-byte aligned pieces
+        a = lambda v: (v + 255) // 256 * 256
+        n = self.batch.n_ext
+        return a(a(n * 8) + a(n * 8) + a(self.desc.n_q * n * 8))
+
+
+def test_fake_session_completes_in_arrival_order_with_one_slot():
+    s = frg.frg_session_open_fake(_cfg(inflight=1, budget=1 << 30), 100.0, 200.0)
+    reqs = [Req(n_ext=32 + 8 * i) for i in range(6)]
+    tickets = [frg.frg_session_submit(s, r.desc, r.batch, -1) for r in reqs]
+    for t in tickets:
+        assert frg.frg_session_wait(s, t, 5000) == frg.FRG_OK
+    st = frg.frg_session_stats(s)
+    assert st.completed == 6 and st.failed == 0 and st.rejected == 0
+    assert st.nodes == sum(r.nodes for r in reqs)
+    assert st.p50_us > 0 and st.p99_us >= st.p50_us and st.gnodes_per_s > 0
+    # the test double never writes outputs
+    assert all(np.all(r.out == -1.0) for r in reqs)
+    frg.frg_session_close(s)
+
+
+def test_admission_waits_for_memory_and_never_fails():
+    r0 = Req(n_ext=64)
+    budget = 2 * r0.footprint() + 512  # two requests fit at once
+    s = frg.frg_session_open_fake(_cfg(inflight=4, budget=budget), 2000.0, 1000.0)
+    reqs = [Req(n_ext=64) for _ in range(10)]
+    t0 = time.perf_counter()
+    tickets = [frg.frg_session_submit(s, r.desc, r.batch, -1) for r in reqs]
+    st = frg.frg_session_stats(s)
+    assert st.queued + st.admitted == 10
+    for t in tickets:
+        assert frg.frg_session_wait(s, t, 20000) == frg.FRG_OK
+    st = frg.frg_session_stats(s)
+    assert st.completed == 10 and st.failed == 0
+    # at most two requests were resident together, so at least five launches were needed
+    assert st.launches >= 5
+    assert time.perf_counter() - t0 > 5 * (1e-3 + 2000e-9 * reqs[0].nodes) * 0.9
+    frg.frg_session_close(s)
+
+
+def test_request_larger_than_budget_is_rejected_at_submit():
+    big = Req(n_ext=4096, n_q=64)
+    s = frg.frg_session_open_fake(_cfg(budget=big.footprint() // 2), 1.0, 1.0)
+    with pytest.raises(frg.FrgError) as ei:
+        frg.frg_session_submit(s, big.desc, big.batch, -1)
+    assert ei.value.status == frg.FRG_E_NOMEM
+    assert frg.frg_session_stats(s).rejected == 1
+    frg.frg_session_close(s)
+
+
+def test_cancel_queued_and_running():
+    s = frg.frg_session_open_fake(_cfg(inflight=1, budget=1 << 30), 0.0, 300000.0)  # 0.3 s/launch
+    a, b = Req(), Req()
+    ta = frg.frg_session_submit(s, a.desc, a.batch, -1)
+    time.sleep(0.05)  # a is launched, b waits for the only slot
+    tb = frg.frg_session_submit(s, b.desc, b.batch, -1)
+    assert frg.frg_session_cancel(s, tb) == frg.FRG_OK
+    assert frg.frg_session_cancel(s, ta) == frg.FRG_E_NOTREADY
+    with pytest.raises(frg.FrgError) as ei:
+        frg.frg_session_wait(s, tb, 1000)
+    assert ei.value.status == frg.FRG_E_CANCELLED
+    assert frg.frg_session_wait(s, ta, 5000) == frg.FRG_OK
+    st = frg.frg_session_stats(s)
+    assert st.cancelled == 1 and st.completed == 1
+    frg.frg_session_close(s)
+
+
+def test_wait_timeout_and_watchdog():
+    s = frg.frg_session_open_fake(_cfg(inflight=1, budget=1 << 30, watchdog_ms=50), 0.0, 400000.0)
+    a = Req()
+    t = frg.frg_session_submit(s, a.desc, a.batch, -1)
+    assert frg.frg_session_wait(s, t, 10) == frg.FRG_E_TIMEOUT  # still running
+    time.sleep(0.15)  # the watchdog fails the ticket after 50 ms
+    with pytest.raises(frg.FrgError) as ei:
+        frg.frg_session_poll(s, t)
+    assert ei.value.status == frg.FRG_E_TIMEOUT
+    assert frg.frg_session_stats(s).failed == 1
+    frg.frg_session_close(s)  # drains the still-running launch
+
+
+def test_close_while_busy_cancels_queued():
+    s = frg.frg_session_open_fake(_cfg(inflight=1, budget=1 << 30), 0.0, 200000.0)
+    reqs = [Req() for _ in range(3)]
+    tickets = [frg.frg_session_submit(s, r.desc, r.batch, -1) for r in reqs]
+    time.sleep(0.02)
+    frg.frg_session_close(s)  # the running launch finishes, the two queued ones are cancelled
+
+
+def test_many_threads_submit_concurrently():
+    # one slot and 2 ms per launch: requests arriving during a launch join the next one
+    s = frg.frg_session_open_fake(_cfg(inflight=1, budget=1 << 30), 0.0, 2000.0)
+    errors = []
+
+    def client(i):
+        try:
+            for k in range(20):
+                r = Req(n_ext=16 + (i * 7 + k) % 50)
+                t = frg.frg_session_submit(s, r.desc, r.batch, -1)
+                assert frg.frg_session_wait(s, t, 10000) == frg.FRG_OK
+        except Exception as e:  # pragma: no cover
+            errors.append(e)
+
+    th = [threading.Thread(target=client, args=(i,)) for i in range(16)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors
+    st = frg.frg_session_stats(s)
+    assert st.completed == 320 and st.failed == 0
+    # continuous batching: launches carried several requests on average
+    assert st.launches < 160
+    frg.frg_session_close(s)
+
+
+def test_invalid_session_arguments():
+    h = ctypes.c_void_p()
+    bad = [_cfg(inflight=0), _cfg(inflight=17), _cfg(budget=100)]
+    for c in bad:
+        assert frg.raw_status("frg_session_open_fake", ctypes.byref(c), 1.0, 1.0,
+                              ctypes.byref(h)) == frg.FRG_E_INVAL
+    s = frg.frg_session_open_fake(_cfg(), 1.0, 1.0)
+    r = Req()
+    with pytest.raises(frg.FrgError):
+        frg.frg_session_submit(s, r.desc, r.batch, 5)  # unknown table
+    r.desc.n_q = 0
+    with pytest.raises(frg.FrgError):
+        frg.frg_session_submit(s, r.desc, r.batch, -1)
+    with pytest.raises(frg.FrgError):
+        frg.frg_session_wait(s, 999, 10)
+    Z = np.ones(16)
+    tid = frg.frg_session_register_table(s, Z.ctypes.data, 16, 1e-3, 1e3)
+    assert tid == 0
+    frg.frg_session_close(s)
