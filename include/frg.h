@@ -123,9 +123,11 @@ typedef struct {
     frg_log_table Z;
     double *out;           /* device [n_ext]: I_e */
     double *err_out;       /* device [n_ext] or NULL: stated relative error bound per result of
-                              the FP32 form, (40 + 2 kappa) 2^-24 with kappa the largest
-                              amplification (|Z l2 + R| + |m2|)/D of a float32 propagator of
-                              that point (0 for FP64) */
+                              the FP32 form, (16 + 3 kappa) u + kappa L ds with u = 2^-24,
+                              kappa the largest amplification (|Z l2 + R| + |m2|)/D of a
+                              float32 propagator of that point, L the largest relative step
+                              of the dressing table and ds the float32 error bound of the
+                              dressing coordinate (0 for FP64) */
 } frg_batch;
 
 /* ---- context ------------------------------------------------------------------------------- */
@@ -156,8 +158,9 @@ frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc 
  * frg_flow_rhs for this descriptor and batch size by timing the candidate shapes on the given
  * batch (its out buffer is overwritten with the integrals), and keep the fastest in the context.
  * If the environment variable FRG_AUTOTUNE_CACHE names a file, tuned shapes are loaded from it
- * when the context is created and appended to it here.  Results do not depend on the shape, only
- * speed does.  Synchronises `stream`.  *best_us (optional) receives the best time per launch. */
+ * when the context is created and appended to it here; if FRG_AUTOTUNE_LOG names a file, every
+ * candidate's time is appended to it ("family precision n_q n_x n_phi n_ext lq_log2 chunks us").
+ * Results do not depend on the shape, only speed does.  Synchronises `stream`.  *best_us (optional) receives the best time per launch. */
 frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const frg_batch *batch,
                         hipStream_t stream, int reps, double *best_us);
 

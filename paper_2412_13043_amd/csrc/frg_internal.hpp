@@ -72,7 +72,8 @@ hipError_t launch_rules(int n_q, double q_max, int d, int n_x, int n_phi, double
                         float *fcf, float *fwf, hipStream_t s);
 hipError_t launch_batch(const ReqDev *req_dev_host, const ReqDev *req_dev_ptr, int n_tiles,
                         int lds_bytes, double *contrib, unsigned *counters, hipStream_t s);
-hipError_t launch_multi(const ReqDev *reqs_dev, int n_reqs, const TileDev *tiles_dev,
+// fam/prec: the family and precision shared by every request of the launch, or -1 (mixed).
+hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, const TileDev *tiles_dev,
                         int n_tiles, int grid, int lds_bytes, double *contrib,
                         unsigned *counters, unsigned *work_ctr, hipStream_t s);
 hipError_t launch_lpa_state(int n, const double *rho, const double *u, double m2_floor,
@@ -81,6 +82,7 @@ hipError_t launch_lpa_assemble(int n, int n_comp, const double *I, const double 
                                double *dudt, hipStream_t s);
 hipError_t launch_fill_zero_u32(unsigned *p, size_t n, hipStream_t s);
 hipError_t launch_log_table(double2 *out, hipStream_t s);
+int multi_blocks_per_cu(int fam, int prec, int lds_bytes);
 constexpr int kLogTable = 256;
 
 }  // namespace frg

@@ -162,14 +162,27 @@ hipError_t launch_rules(int n_q, double q_max, int d, int n_x, int n_phi, double
 // dressing clamps to its first entry, and no 0/0 occurs in the single-division form below.
 #define FRG_L2_TINY 1e-300
 
-// Occupancy target of the integrand kernels (waves per SIMD); bounds the VGPR budget so that the
-// loop-invariant constants of the inner loops stay resident in registers.
-#ifndef FRG_WAVES_PER_EU
-#define FRG_WAVES_PER_EU 4
+// Quadrature rules stay constant while an integrand kernel runs.  Reading them through the
+// constant address space lets the compiler use scalar loads for the wave-uniform rule entries
+// (batched and issued ahead of use) instead of a vector memory round trip per inner-loop step,
+// which it must otherwise assume the kernel's own stores may alias.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *kc(const T *p) {
+    return (const __attribute__((address_space(4))) T *)p;
+}
+
+// Occupancy targets (waves per SIMD) of the integrand kernels; they bound the VGPR budget.  The
+// single-request kernels and the two-point fused instances fit 5 waves without spilling; the
+// general fused kernel (every family and precision) and the three-point fused instances fit 4.
+#ifndef FRG_WAVES_PER_EU_BATCH
+#define FRG_WAVES_PER_EU_BATCH 5
+#endif
+#ifndef FRG_WAVES_PER_EU_MULTI
+#define FRG_WAVES_PER_EU_MULTI 4
 #endif
 // Propagators evaluated together per inner-loop step (instruction-level parallelism).
 #ifndef FRG_ILP
-#define FRG_ILP 4
+#define FRG_ILP 2
 #endif
 
 // Tables staged in LDS for one request: the logarithm table, then the dressing as n + 1 entries
@@ -181,6 +194,7 @@ struct Smem {
     double2 *logt;
     double2 *Z64;
     float2 *Z32;
+    float *zslope;  // max_i |Z_{i+1} - Z_i| / min_i |Z_i| of the staged table (float32 form's bound)
 };
 
 // Cell index and fraction of the padded dressing table for coordinate sp = s + 1.
@@ -267,12 +281,12 @@ struct RadialTerm {
 __device__ __forceinline__ RadialTerm radial64(const ReqDev &r, const Smem &sm, int a, double p,
                                                double m2) {
     RadialTerm t;
-    const double q = r.k * r.rad.q[a];
+    const double q = r.k * kc(r.rad.q)[a];
     const double q2 = q * q;
     const double zq = dressing64(sm, r.nZ, r.za, r.zb + 1.0, fmax(q2, FRG_L2_TINY));
-    const double A = fma(zq, q2, r.k2 * r.rad.R[a]);
+    const double A = fma(zq, q2, r.k2 * kc(r.rad.R)[a]);
     const double G = fm::rcp_nr(A + m2);
-    t.wg = r.rad.W[a] * (G * G);
+    t.wg = kc(r.rad.W)[a] * (G * G);
     t.c0 = fma(p, p, q2);
     t.c1 = 2.0 * q * p;
     return t;
@@ -289,15 +303,15 @@ __device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm,
     for (; b + FRG_ILP <= nx; b += FRG_ILP) {
         double l2[FRG_ILP], G[FRG_ILP];
 #pragma unroll
-        for (int w = 0; w < FRG_ILP; ++w) l2[w] = fmax(fma(t.c1, r.ang.x[b + w], t.c0), FRG_L2_TINY);
+        for (int w = 0; w < FRG_ILP; ++w) l2[w] = fmax(fma(t.c1, kc(r.ang.x)[b + w], t.c0), FRG_L2_TINY);
         propagators64<FRG_ILP>(l2, G, sm, nZ, za, zb1, m2, inv_k2);
 #pragma unroll
-        for (int w = 0; w < FRG_ILP; ++w) inner = fma(r.ang.xw[b + w], G[w], inner);
+        for (int w = 0; w < FRG_ILP; ++w) inner = fma(kc(r.ang.xw)[b + w], G[w], inner);
     }
     for (; b < nx; ++b) {
-        double l2[1] = {fmax(fma(t.c1, r.ang.x[b], t.c0), FRG_L2_TINY)}, G[1];
+        double l2[1] = {fmax(fma(t.c1, kc(r.ang.x)[b], t.c0), FRG_L2_TINY)}, G[1];
         propagators64<1>(l2, G, sm, nZ, za, zb1, m2, inv_k2);
-        inner = fma(r.ang.xw[b], G[0], inner);
+        inner = fma(kc(r.ang.xw)[b], G[0], inner);
     }
     return t.wg * inner;
 }
@@ -312,28 +326,28 @@ __device__ __forceinline__ double contrib_three64(const ReqDev &r, const Smem &s
     const double za = r.za, zb1 = r.zb + 1.0;
     double mid = 0.0;
     for (int b = 0; b < nx; ++b) {
-        const double xb = r.ang.x[b];
+        const double xb = kc(r.ang.x)[b];
         double l1[1] = {fmax(fma(t.c1, xb, t.c0), FRG_L2_TINY)}, g1[1];
         propagators64<1>(l1, g1, sm, nZ, za, zb1, m2, inv_k2);
         const double A2 = fma(-t.c1, xb * ca, t.c0);
-        const double B2 = -t.c1 * (r.ang.xs[b] * sa);
+        const double B2 = -t.c1 * (kc(r.ang.xs)[b] * sa);
         double inner = 0.0;
         int c = 0;
         for (; c + FRG_ILP <= nphi; c += FRG_ILP) {
             double l2[FRG_ILP], G[FRG_ILP];
 #pragma unroll
             for (int w = 0; w < FRG_ILP; ++w)
-                l2[w] = fmax(fma(B2, r.phi.c[c + w], A2), FRG_L2_TINY);
+                l2[w] = fmax(fma(B2, kc(r.phi.c)[c + w], A2), FRG_L2_TINY);
             propagators64<FRG_ILP>(l2, G, sm, nZ, za, zb1, m2, inv_k2);
 #pragma unroll
-            for (int w = 0; w < FRG_ILP; ++w) inner = fma(r.phi.w[c + w], G[w], inner);
+            for (int w = 0; w < FRG_ILP; ++w) inner = fma(kc(r.phi.w)[c + w], G[w], inner);
         }
         for (; c < nphi; ++c) {
-            double l2[1] = {fmax(fma(B2, r.phi.c[c], A2), FRG_L2_TINY)}, G[1];
+            double l2[1] = {fmax(fma(B2, kc(r.phi.c)[c], A2), FRG_L2_TINY)}, G[1];
             propagators64<1>(l2, G, sm, nZ, za, zb1, m2, inv_k2);
-            inner = fma(r.phi.w[c], G[0], inner);
+            inner = fma(kc(r.phi.w)[c], G[0], inner);
         }
-        mid = fma(r.ang.xw[b] * g1[0], inner, mid);
+        mid = fma(kc(r.ang.xw)[b] * g1[0], inner, mid);
     }
     return t.wg * mid;
 }
@@ -421,24 +435,24 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
                                                 double m2, double inv_k2, float &kmax) {
     const RadialTerm t = radial64(r, sm, a, p, m2);
     const Par32 P = par32(r, m2, inv_k2);
-    const float c0 = (float)t.c0, c1 = (float)t.c1;
     Kahan32 acc{0.0f, 0.0f};
     const int nx = r.n_x;
     int b = 0;
     for (; b + FRG_ILP <= nx; b += FRG_ILP) {
         float l2[FRG_ILP], G[FRG_ILP];
 #pragma unroll
-        for (int w = 0; w < FRG_ILP; ++w) l2[w] = fmaxf(fmaf(c1, r.ang.xf[b + w], c0), 1e-30f);
+        for (int w = 0; w < FRG_ILP; ++w)
+            l2[w] = (float)fmax(fma(t.c1, kc(r.ang.x)[b + w], t.c0), 1e-30);
         propagators32<FRG_ILP>(l2, G, kmax, sm, P);
         float blk = 0.0f;
 #pragma unroll
-        for (int w = 0; w < FRG_ILP; ++w) blk = fmaf(r.ang.xwf[b + w], G[w], blk);
+        for (int w = 0; w < FRG_ILP; ++w) blk = fmaf(kc(r.ang.xwf)[b + w], G[w], blk);
         acc.add(blk);
     }
     for (; b < nx; ++b) {
-        float l2[1] = {fmaxf(fmaf(c1, r.ang.xf[b], c0), 1e-30f)}, G[1];
+        float l2[1] = {(float)fmax(fma(t.c1, kc(r.ang.x)[b], t.c0), 1e-30)}, G[1];
         propagators32<1>(l2, G, kmax, sm, P);
-        acc.add(r.ang.xwf[b] * G[0]);
+        acc.add(kc(r.ang.xwf)[b] * G[0]);
     }
     return t.wg * ((double)acc.s - (double)acc.c);
 }
@@ -448,42 +462,57 @@ __device__ __forceinline__ double contrib_three32(const ReqDev &r, const Smem &s
                                                   double inv_k2, float &kmax) {
     const RadialTerm t = radial64(r, sm, a, p, m2);
     const Par32 P = par32(r, m2, inv_k2);
-    const float c0 = (float)t.c0, c1 = (float)t.c1;
-    const float caf = (float)ca, saf = (float)sa;
     double mid = 0.0;
     const int nx = r.n_x, nphi = r.n_phi;
     for (int b = 0; b < nx; ++b) {
-        const float xb = r.ang.xf[b];
-        float l1[1] = {fmaxf(fmaf(c1, xb, c0), 1e-30f)}, g1[1];
+        const double xb = kc(r.ang.x)[b];
+        float l1[1] = {(float)fmax(fma(t.c1, xb, t.c0), 1e-30)}, g1[1];
         propagators32<1>(l1, g1, kmax, sm, P);
-        const float A2 = fmaf(-c1, xb * caf, c0);
-        const float B2 = -c1 * (r.ang.xsf[b] * saf);
+        const double A2 = fma(-t.c1, xb * ca, t.c0);
+        const double B2 = -t.c1 * (kc(r.ang.xs)[b] * sa);
         Kahan32 acc{0.0f, 0.0f};
         int c = 0;
         for (; c + FRG_ILP <= nphi; c += FRG_ILP) {
             float l2[FRG_ILP], G[FRG_ILP];
 #pragma unroll
             for (int w = 0; w < FRG_ILP; ++w)
-                l2[w] = fmaxf(fmaf(B2, r.phi.cf[c + w], A2), 1e-30f);
+                l2[w] = (float)fmax(fma(B2, kc(r.phi.c)[c + w], A2), 1e-30);
             propagators32<FRG_ILP>(l2, G, kmax, sm, P);
             float blk = 0.0f;
 #pragma unroll
-            for (int w = 0; w < FRG_ILP; ++w) blk = fmaf(r.phi.wf[c + w], G[w], blk);
+            for (int w = 0; w < FRG_ILP; ++w) blk = fmaf(kc(r.phi.wf)[c + w], G[w], blk);
             acc.add(blk);
         }
         for (; c < nphi; ++c) {
-            float l2[1] = {fmaxf(fmaf(B2, r.phi.cf[c], A2), 1e-30f)}, G[1];
+            float l2[1] = {(float)fmax(fma(B2, kc(r.phi.c)[c], A2), 1e-30)}, G[1];
             propagators32<1>(l2, G, kmax, sm, P);
-            acc.add(r.phi.wf[c] * G[0]);
+            acc.add(kc(r.phi.wf)[c] * G[0]);
         }
         const double inner = (double)acc.s - (double)acc.c;
-        mid = fma((double)r.ang.xw[b] * (double)g1[0], inner, mid);
+        mid = fma((double)kc(r.ang.xw)[b] * (double)g1[0], inner, mid);
     }
     return t.wg * mid;
 }
 
-// float32 form's stated relative error bound per result: (C0 + 2 kappa_max) u32, u32 = 2^-24
-#define FRG_FP32_BOUND(kmax) ((double)(40.0f + 2.0f * (kmax)) * 5.9604644775390625e-8)
+// float32 form's stated relative error bound per result (u = 2^-24, kappa = largest float32
+// amplification (|Z l2 + R| + |m2|)/D of the point, L = largest relative step of the dressing
+// table, ds = bound on the float32 error of the dressing coordinate s):
+//   (16 + 3 kappa) u + kappa L ds
+// 16 u: l2 rounded once to float32, expm1 and its reconstruction, the reciprocal, the weight
+// products, the block sums and their compensated accumulation; 3 kappa u: the rounding of the
+// denominator's three terms, amplified by their cancellation; kappa L ds: the dressing lookup.
+// ds: s + 1 = fmaf(log2 l2, za2, zb1) in float32 -- the rounding of l2 (1.5 u in log2), v_log_f32
+// (1 ulp of |log2 l2|, at most Lmax = the larger |log2| of the table's end points while s is
+// inside the table; outside it the end entries are constant), and the rounding of za2, zb1 and
+// the sum (u (2 nZ + 3 |zb1| + 2)).
+__device__ __forceinline__ double fp32_bound(float kmax, float zslope, const ReqDev &r) {
+    const double u = 5.9604644775390625e-8;
+    const double ln2 = 0.69314718055994530942;
+    const double za2 = r.za * ln2, zb1 = fabs(r.zb + 1.0);
+    const double lmax = fmax(fabs(-r.zb / r.za), fabs((r.nZ - 1 - r.zb) / r.za)) / ln2;
+    const double ds = u * (2.0 * (r.nZ + 1) + 3.0 * zb1 + 2.0) + za2 * (2.0 * u * lmax + 1.5 * u);
+    return (16.0 + 3.0 * (double)kmax) * u + (double)kmax * (double)zslope * ds;
+}
 
 // --------------------------------------------------------------------------------------------
 // Tile bodies
@@ -504,12 +533,27 @@ __device__ __forceinline__ void stage_tables(const ReqDev &r, Smem &sm) {
         sm.Z64[j] = make_double2(zi, dz);
         if (r.precision == 1) sm.Z32[j] = make_float2((float)zi, (float)dz);
     }
+    if (r.precision == 1) {
+        // largest |Z_{i+1} - Z_i| over smallest |Z_i| (one wavefront per workgroup)
+        float mx = 0.0f, mn = 3.0e38f;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const double zi = r.Z[i];
+            mn = fminf(mn, (float)fabs(zi));
+            if (i + 1 < n) mx = fmaxf(mx, (float)fabs(r.Z[i + 1] - zi));
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            mx = fmaxf(mx, __shfl_xor(mx, o));
+            mn = fminf(mn, __shfl_xor(mn, o));
+        }
+        if (threadIdx.x == 0) *sm.zslope = mn > 0.0f ? mx / mn : 3.0e38f;
+    }
 }
 
-__device__ __forceinline__ void bind_smem(Smem &sm, double2 *lds, int nZ) {
+__device__ __forceinline__ void bind_smem(Smem &sm, double2 *lds, int nZ, float *zslope) {
     sm.logt = lds;
     sm.Z64 = lds + kLogTable;
     sm.Z32 = (float2 *)(lds + kLogTable + nZ + 1);
+    sm.zslope = zslope;
 }
 
 // LPA: one lane per external point, the whole radial sum in one lane, no scratch.
@@ -522,9 +566,9 @@ __device__ __forceinline__ void tile_lpa(const ReqDev &r, int et) {
     if (PREC == 0) {
         double acc = 0.0;
         for (int a = 0; a < nq; ++a) {
-            const double qh = r.rad.q[a];
-            const double g = fm::rcp_nr(fma(r.k2, fma(qh, qh, r.rad.R[a]), m2));
-            acc = fma(r.rad.W[a], g * g, acc);
+            const double qh = kc(r.rad.q)[a];
+            const double g = fm::rcp_nr(fma(r.k2, fma(qh, qh, kc(r.rad.R)[a]), m2));
+            acc = fma(kc(r.rad.W)[a], g * g, acc);
         }
         r.out[e] = r.pref * acc;
         if (r.err) r.err[e] = 0.0;
@@ -534,21 +578,21 @@ __device__ __forceinline__ void tile_lpa(const ReqDev &r, int et) {
         Kahan32 acc{0.0f, 0.0f};
         float kmax = 1.0f;
         for (int a = 0; a < nq; ++a) {
-            const float qh = r.rad.qf[a];
-            const float A = k2f * fmaf(qh, qh, r.rad.Rf[a]);
+            const float qh = kc(r.rad.qf)[a];
+            const float A = k2f * fmaf(qh, qh, kc(r.rad.Rf)[a]);
             const float t = A + m2f;
             float g;
             if (t < tau * (A + fabsf(m2f))) {
-                const double qd = r.rad.q[a];
-                g = (float)fm::rcp_nr(fma(r.k2, fma(qd, qd, r.rad.R[a]), m2));
+                const double qd = kc(r.rad.q)[a];
+                g = (float)fm::rcp_nr(fma(r.k2, fma(qd, qd, kc(r.rad.R)[a]), m2));
             } else {
                 g = __builtin_amdgcn_rcpf(t);
                 kmax = fmaxf(kmax, (A + fabsf(m2f)) * g);
             }
-            acc.add(r.rad.Wf[a] * (g * g));
+            acc.add(kc(r.rad.Wf)[a] * (g * g));
         }
         r.out[e] = r.pref * ((double)acc.s - (double)acc.c);
-        if (r.err) r.err[e] = FRG_FP32_BOUND(kmax);
+        if (r.err) r.err[e] = (16.0 + 3.0 * (double)kmax) * 5.9604644775390625e-8;
     }
 }
 
@@ -587,7 +631,24 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
                                : contrib_three32(r, sm, a, p, ca, sa, m2, inv_k2, kmax);
             blk[(long long)a * r.n_ext + e] = v;
         }
-        if (PREC == 1) atomicMax(&kslot[e], __float_as_uint(kmax));
+        if (PREC == 1 && r.chunks > 1) atomicMax(&kslot[e], __float_as_uint(kmax));
+    }
+    if (r.chunks == 1) {
+        // This wavefront evaluated every radial node of its points, so no other workgroup takes
+        // part: a workgroup barrier publishes the contributions, and the radial sum below runs
+        // in the same order as the cross-workgroup one (identical bits).  No device-scope fence
+        // (an L2 writeback and invalidate on a multi-XCD part) and no counter are needed.
+        if (PREC == 1) {
+            for (int o = 1; o < lq; o <<= 1) kmax = fmaxf(kmax, __shfl_xor(kmax, o));
+        }
+        __syncthreads();
+        if (valid && sub == 0) {
+            double s = 0.0;
+            for (int a = 0; a < r.n_q; ++a) s += blk[(long long)a * r.n_ext + e];
+            r.out[e] = r.pref * s;
+            if (r.err) r.err[e] = (PREC == 1) ? fp32_bound(kmax, *sm.zslope, r) : 0.0;
+        }
+        return;
     }
     // publish the contributions, then count this chunk
     __threadfence();
@@ -614,7 +675,7 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
             if (PREC == 1) {
                 unsigned kb = __hip_atomic_load(&kslot[ef], __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
-                if (r.err) r.err[ef] = FRG_FP32_BOUND(__uint_as_float(kb));
+                if (r.err) r.err[ef] = fp32_bound(__uint_as_float(kb), *sm.zslope, r);
                 __hip_atomic_store(&kslot[ef], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else if (r.err) {
                 r.err[ef] = 0.0;
@@ -626,15 +687,16 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
 
 // One request: tile = blockIdx.x -> (external tile, chunk).
 template <int FAM, int PREC>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FRG_WAVES_PER_EU)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FRG_WAVES_PER_EU_BATCH)))
 batch_kernel(ReqDev r, double *contrib, unsigned *counters) {
     extern __shared__ double2 lds_dyn[];
     if (FAM == 1) {
         tile_lpa<PREC>(r, blockIdx.x);
         return;
     }
+    __shared__ float zslope;
     Smem sm;
-    bind_smem(sm, lds_dyn, r.nZ);
+    bind_smem(sm, lds_dyn, r.nZ, &zslope);
     const int et = blockIdx.x / r.chunks;
     const int chunk = blockIdx.x - et * r.chunks;
     stage_tables(r, sm);
@@ -664,13 +726,35 @@ hipError_t launch_batch(const ReqDev *req_host, const ReqDev *req_dev_ptr, int n
 // Many requests in one launch.  A grid sized to the device pulls tiles (ordered largest first by
 // the host) from a global counter until the list is empty; the last workgroup to leave resets the
 // counters, so the kernel can be relaunched (or replayed in a graph) without a memset.
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FRG_WAVES_PER_EU)))
-multi_kernel(const ReqDev *__restrict__ reqs,
-                                                   const TileDev *__restrict__ tiles, int n_tiles,
-                                                   double *contrib, unsigned *counters,
-                                                   unsigned *work) {
+// FAM = PREC = -1 is the general kernel (any mix of families and precisions); a launch whose
+// requests all share one family and precision uses the instance specialised for them, which
+// carries only that path and so needs fewer registers (more resident waves).
+template <int FAM, int PREC>
+__device__ __forceinline__ void multi_tile(const ReqDev &r, Smem &sm, const TileDev &td,
+                                           double *contrib, unsigned *counters) {
+    const int fam = FAM > 0 ? FAM : r.family;
+    const int prec = PREC >= 0 ? PREC : r.precision;
+    if (fam == 2) {
+        if (prec == 0)
+            tile_vertex<2, 0>(r, sm, td.et, td.chunk, contrib, counters);
+        else
+            tile_vertex<2, 1>(r, sm, td.et, td.chunk, contrib, counters);
+    } else {
+        if (prec == 0)
+            tile_vertex<3, 0>(r, sm, td.et, td.chunk, contrib, counters);
+        else
+            tile_vertex<3, 1>(r, sm, td.et, td.chunk, contrib, counters);
+    }
+}
+
+template <int FAM, int PREC>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
+    (FAM < 0 || FAM == 3) ? FRG_WAVES_PER_EU_MULTI : FRG_WAVES_PER_EU_BATCH)))
+multi_kernel(const ReqDev *__restrict__ reqs, const TileDev *__restrict__ tiles, int n_tiles,
+             double *contrib, unsigned *counters, unsigned *work) {
     extern __shared__ double2 lds_dyn[];
     __shared__ int tile_s;
+    __shared__ float zslope;
     Smem sm;
     int staged = -1;
     for (;;) {
@@ -681,28 +765,23 @@ multi_kernel(const ReqDev *__restrict__ reqs,
         if (t >= n_tiles) break;
         const TileDev td = tiles[t];
         const ReqDev &r = reqs[td.req];
-        if (r.family == 1) {
-            if (r.precision == 0) tile_lpa<0>(r, td.et); else tile_lpa<1>(r, td.et);
+        if (FAM == 1 || (FAM < 0 && r.family == 1)) {
+            if ((PREC >= 0 ? PREC : r.precision) == 0)
+                tile_lpa<0>(r, td.et);
+            else
+                tile_lpa<1>(r, td.et);
             continue;
         }
-        bind_smem(sm, lds_dyn, r.nZ);
-        if (staged != td.req) {
-            stage_tables(r, sm);
+        if (FAM != 1) {
+            bind_smem(sm, lds_dyn, r.nZ, &zslope);
+            if (staged != td.req) {
+                stage_tables(r, sm);
+                __syncthreads();
+                staged = td.req;
+            }
+            multi_tile<FAM, PREC>(r, sm, td, contrib, counters);
             __syncthreads();
-            staged = td.req;
         }
-        if (r.family == 2) {
-            if (r.precision == 0)
-                tile_vertex<2, 0>(r, sm, td.et, td.chunk, contrib, counters);
-            else
-                tile_vertex<2, 1>(r, sm, td.et, td.chunk, contrib, counters);
-        } else {
-            if (r.precision == 0)
-                tile_vertex<3, 0>(r, sm, td.et, td.chunk, contrib, counters);
-            else
-                tile_vertex<3, 1>(r, sm, td.et, td.chunk, contrib, counters);
-        }
-        __syncthreads();
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -714,13 +793,33 @@ multi_kernel(const ReqDev *__restrict__ reqs,
     }
 }
 
-hipError_t launch_multi(const ReqDev *reqs_dev, int n_reqs, const TileDev *tiles_dev,
+typedef void (*multi_fn)(const ReqDev *, const TileDev *, int, double *, unsigned *, unsigned *);
+
+static multi_fn multi_variant(int fam, int prec) {
+    // fam/prec < 0: general kernel
+    if (fam == 1) return prec == 0 ? multi_kernel<1, 0> : multi_kernel<1, 1>;
+    if (fam == 2) return prec == 0 ? multi_kernel<2, 0> : multi_kernel<2, 1>;
+    if (fam == 3) return prec == 0 ? multi_kernel<3, 0> : multi_kernel<3, 1>;
+    return multi_kernel<-1, -1>;
+}
+
+// Workgroups of the fused kernel resident per CU with `lds_bytes` of dynamic LDS (sizes the
+// persistent grid).
+int multi_blocks_per_cu(int fam, int prec, int lds_bytes) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, multi_variant(fam, prec), kWave,
+                                                     lds_bytes) != hipSuccess ||
+        n < 1)
+        n = 4;
+    return n;
+}
+
+hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, const TileDev *tiles_dev,
                         int n_tiles, int grid, int lds_bytes, double *contrib,
                         unsigned *counters, unsigned *work_ctr, hipStream_t s) {
-    (void)n_reqs;
     if (n_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(multi_kernel, dim3(grid), dim3(kWave), lds_bytes, s, reqs_dev, tiles_dev,
-                       n_tiles, contrib, counters, work_ctr);
+    hipLaunchKernelGGL(multi_variant(fam, prec), dim3(grid), dim3(kWave), lds_bytes, s, reqs_dev,
+                       tiles_dev, n_tiles, contrib, counters, work_ctr);
     return hipGetLastError();
 }
 

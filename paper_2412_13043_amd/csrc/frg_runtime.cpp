@@ -204,11 +204,18 @@ TileShape heuristic_shape(const frg_integral_desc &d, int n_ext, int target_wave
     // external points per wavefront: the smallest power of two >= n_ext, at least 4
     int le = kWave;
     while (le > 4 && le / 2 >= n_ext) le /= 2;
+    int ext_tiles = (n_ext + le - 1) / le;
+    // Prefer more lanes per point over radial chunks: a tile that holds all radial nodes of its
+    // points finishes them itself, while chunked tiles must meet through device-scope fences.
+    while (ext_tiles < target_waves && le > 4 && 2 * (kWave / le) <= d.n_q) {
+        le /= 2;
+        ext_tiles = (n_ext + le - 1) / le;
+    }
     s.lq_log2 = ilog2(kWave / le);
     int lq = 1 << s.lq_log2;
-    int ext_tiles = (n_ext + le - 1) / le;
     int max_chunks = (d.n_q + lq - 1) / lq;  // at least one radial node per lane and chunk
-    int want = (target_waves + ext_tiles - 1) / std::max(ext_tiles, 1);
+    // chunks only when even the narrowest tiles leave the chip mostly idle
+    int want = ext_tiles * 4 >= target_waves ? 1 : (target_waves + ext_tiles - 1) / ext_tiles;
     s.chunks = std::max(1, std::min(max_chunks, want));
     return s;
 }
@@ -375,9 +382,18 @@ std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out) {
     return sorted;
 }
 
+void common_kind(const std::vector<ReqDev> &reqs, int *fam, int *prec) {
+    *fam = reqs.empty() ? -1 : reqs[0].family;
+    *prec = reqs.empty() ? -1 : reqs[0].precision;
+    for (const ReqDev &r : reqs) {
+        if (r.family != *fam) *fam = -1;
+        if (r.precision != *prec) *prec = -1;
+    }
+    if (*fam < 0 || *prec < 0) *fam = *prec = -1;
+}
+
 frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s, Scratch *sc,
                      int grid_waves) {
-    (void)ctx;
     long long cb = 0, ctr = 0;
     for (ReqDev &r : reqs) {
         r.contrib_base = cb;
@@ -407,14 +423,17 @@ frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s,
                                  hipMemcpyHostToDevice, s));
     FRG_HIP_CHECK(hipEventRecord(sc->staged, s));
     sc->last_tiles = (int)sorted.size();
-    sc->last_grid = std::min<int>((int)sorted.size(), std::max(grid_waves, 1));
+    // persistent grid: as many one-wave workgroups as the CUs hold at once
+    common_kind(reqs, &sc->last_fam, &sc->last_prec);
+    const int resident = multi_blocks_per_cu(sc->last_fam, sc->last_prec, lds) * ctx->num_cus;
+    sc->last_grid = std::min<int>((int)sorted.size(), std::max(std::min(grid_waves, resident), 1));
     sc->last_lds = lds;
     sc->last_nreqs = (int)reqs.size();
     return relaunch_multi(sc, s);
 }
 
 frg_status relaunch_multi(Scratch *sc, hipStream_t s) {
-    FRG_HIP_CHECK(launch_multi((const ReqDev *)sc->reqs.ptr, sc->last_nreqs,
+    FRG_HIP_CHECK(launch_multi((const ReqDev *)sc->reqs.ptr, sc->last_fam, sc->last_prec,
                                (const TileDev *)sc->tiles.ptr, sc->last_tiles, sc->last_grid,
                                sc->last_lds, (double *)sc->contrib.ptr,
                                (unsigned *)sc->counters.ptr, (unsigned *)sc->work.ptr, s));
@@ -572,6 +591,13 @@ frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const f
             t_best = std::min(t_best, (double)ms * 1e3);
         }
         if (res != FRG_OK) break;
+        if (const char *lp = std::getenv("FRG_AUTOTUNE_LOG")) {
+            std::ofstream lf(lp, std::ios::app);
+            if (lf)
+                lf << desc->family << ' ' << desc->precision << ' ' << desc->n_q << ' '
+                   << desc->n_x << ' ' << desc->n_phi << ' ' << batch->n_ext << ' ' << c.lq_log2
+                   << ' ' << c.chunks << ' ' << t_best << '\n';
+        }
         if (t_best < best) {
             best = t_best;
             best_shape = c;
@@ -639,7 +665,7 @@ frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc 
     FRG_HIP_CHECK(hipSetDevice(ctx->device));
     std::vector<ReqDev> reqs;
     size_t n_contrib = 0, n_ctr = 0, n_tiles = 0;
-    const int target_total = 16 * ctx->num_cus;
+    const int target_total = 32 * ctx->num_cus;  // about twice the resident waves
     for (int i = 0; i < n; ++i) {
         if (batches[i].n_ext == 0) continue;
         int target = std::max(1, (int)std::lround(target_total * nodes[i] / total_nodes));
@@ -657,7 +683,7 @@ frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc 
     if ((st = get_scratch(ctx, stream, n_contrib, n_ctr, reqs.size(), n_tiles, &sc)) != FRG_OK)
         return st;
     sc->last_key.clear();
-    if ((st = run_multi(ctx, reqs, stream, sc, 8 * ctx->num_cus)) != FRG_OK) return st;
+    if ((st = run_multi(ctx, reqs, stream, sc, 1 << 30)) != FRG_OK) return st;
     sc->last_key = std::move(key);
     return FRG_OK;
 }

@@ -192,7 +192,7 @@ class HipExecutor : public Executor {
         std::vector<ReqDev> rd;
         double total = 0.0;
         for (SessReq *r : sl.reqs) total += (double)r->nodes;
-        const int target_total = 16 * ctx->num_cus;
+        const int target_total = 32 * ctx->num_cus;
         long long ctr = 0;
         for (SessReq *r : sl.reqs) {
             frg_batch b = r->host;
@@ -270,9 +270,12 @@ class HipExecutor : public Executor {
         FRG_HIP_CHECK(launch_fill_zero_u32((unsigned *)sl.counters.ptr, nctr, sl.stream));
         const ReqDev *reqs_dev = (const ReqDev *)sl.tables.ptr;
         const TileDev *tiles_dev = (const TileDev *)((char *)sl.tables.ptr + tiles_off);
-        int grid = std::min<int>((int)tiles.size(), 8 * ctx->num_cus);
-        FRG_HIP_CHECK(launch_multi(reqs_dev, (int)rd.size(), tiles_dev, (int)tiles.size(), grid,
-                                   lds, (double *)base, (unsigned *)sl.counters.ptr,
+        int fam, prec;
+        common_kind(rd, &fam, &prec);
+        int grid = std::min<int>((int)tiles.size(),
+                                 multi_blocks_per_cu(fam, prec, lds) * ctx->num_cus);
+        FRG_HIP_CHECK(launch_multi(reqs_dev, fam, prec, tiles_dev, (int)tiles.size(), grid, lds,
+                                   (double *)base, (unsigned *)sl.counters.ptr,
                                    (unsigned *)sl.work.ptr, sl.stream));
         sl.host_out.clear();
         pos = out_start;
