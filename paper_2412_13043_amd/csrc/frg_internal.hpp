@@ -45,6 +45,7 @@ struct ReqDev {
     double m2s;       // scalar m2
     double m2_floor;
     double za, zb;    // dressing coordinate s = za * log(l2) + zb
+    double zbk;       // the same coordinate from y = l2/k^2: s = za * log(y) + zbk
     double tau;       // near-pole threshold (FP32 form)
     RadialRule rad;
     AngleRule ang;
@@ -83,6 +84,7 @@ hipError_t launch_lpa_assemble(int n, int n_comp, const double *I, const double 
 hipError_t launch_fill_zero_u32(unsigned *p, size_t n, hipStream_t s);
 hipError_t launch_log_table(double2 *out, hipStream_t s);
 int multi_blocks_per_cu(int fam, int prec, int lds_bytes);
+int multi_grid(int n_tiles, int fam, int prec, int lds_bytes, int num_cus);
 constexpr int kLogTable = 256;
 
 }  // namespace frg

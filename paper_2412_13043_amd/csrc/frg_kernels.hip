@@ -14,6 +14,8 @@
 // fma(), so the operation sequence (and so the rounding) is fixed by the source.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "frg_internal.hpp"
 #include "frg_math.hpp"
 
@@ -172,8 +174,8 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *kc(const T
 }
 
 // Occupancy targets (waves per SIMD) of the integrand kernels; they bound the VGPR budget.  The
-// single-request kernels and the two-point fused instances fit 5 waves without spilling; the
-// general fused kernel (every family and precision) and the three-point fused instances fit 4.
+// two-point kernels fit 5 waves; the three-point kernels and the general fused kernel (every
+// family and precision) are held to 4, where they keep their working set in registers.
 #ifndef FRG_WAVES_PER_EU_BATCH
 #define FRG_WAVES_PER_EU_BATCH 5
 #endif
@@ -295,25 +297,27 @@ __device__ __forceinline__ RadialTerm radial64(const ReqDev &r, const Smem &sm, 
 // Contribution of (e, a) to the two-point integral (without the global prefactor).
 __device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm, int a, double p,
                                                 double m2, double inv_k2) {
+    // inner loop in units of k^2: y = l2/k^2 with G(l2) = G^(y)/k^2, G^ = 1/(Z y + R/k^2 + m2/k^2)
     const RadialTerm t = radial64(r, sm, a, p, m2);
+    const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2, m2h = m2 * inv_k2;
     const int nx = r.n_x, nZ = r.nZ;
-    const double za = r.za, zb1 = r.zb + 1.0;
+    const double za = r.za, zb1 = r.zbk + 1.0;
     double inner = 0.0;
     int b = 0;
     for (; b + FRG_ILP <= nx; b += FRG_ILP) {
         double l2[FRG_ILP], G[FRG_ILP];
 #pragma unroll
-        for (int w = 0; w < FRG_ILP; ++w) l2[w] = fmax(fma(t.c1, kc(r.ang.x)[b + w], t.c0), FRG_L2_TINY);
-        propagators64<FRG_ILP>(l2, G, sm, nZ, za, zb1, m2, inv_k2);
+        for (int w = 0; w < FRG_ILP; ++w) l2[w] = fmax(fma(c1, kc(r.ang.x)[b + w], c0), FRG_L2_TINY);
+        propagators64<FRG_ILP>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w) inner = fma(kc(r.ang.xw)[b + w], G[w], inner);
     }
     for (; b < nx; ++b) {
-        double l2[1] = {fmax(fma(t.c1, kc(r.ang.x)[b], t.c0), FRG_L2_TINY)}, G[1];
-        propagators64<1>(l2, G, sm, nZ, za, zb1, m2, inv_k2);
+        double l2[1] = {fmax(fma(c1, kc(r.ang.x)[b], c0), FRG_L2_TINY)}, G[1];
+        propagators64<1>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
         inner = fma(kc(r.ang.xw)[b], G[0], inner);
     }
-    return t.wg * inner;
+    return t.wg * (inner * inv_k2);
 }
 
 // Contribution of (e, a) to the three-point integral.  l1 does not depend on phi, so G(l1^2) is
@@ -321,16 +325,18 @@ __device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm,
 __device__ __forceinline__ double contrib_three64(const ReqDev &r, const Smem &sm, int a, double p,
                                                   double ca, double sa, double m2,
                                                   double inv_k2) {
+    // both legs in units of k^2 (see contrib_two64): the product carries 1/k^4
     const RadialTerm t = radial64(r, sm, a, p, m2);
+    const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2, m2h = m2 * inv_k2;
     const int nx = r.n_x, nphi = r.n_phi, nZ = r.nZ;
-    const double za = r.za, zb1 = r.zb + 1.0;
+    const double za = r.za, zb1 = r.zbk + 1.0;
     double mid = 0.0;
     for (int b = 0; b < nx; ++b) {
         const double xb = kc(r.ang.x)[b];
-        double l1[1] = {fmax(fma(t.c1, xb, t.c0), FRG_L2_TINY)}, g1[1];
-        propagators64<1>(l1, g1, sm, nZ, za, zb1, m2, inv_k2);
-        const double A2 = fma(-t.c1, xb * ca, t.c0);
-        const double B2 = -t.c1 * (kc(r.ang.xs)[b] * sa);
+        double l1[1] = {fmax(fma(c1, xb, c0), FRG_L2_TINY)}, g1[1];
+        propagators64<1>(l1, g1, sm, nZ, za, zb1, m2h, 1.0);
+        const double A2 = fma(-c1, xb * ca, c0);
+        const double B2 = -c1 * (kc(r.ang.xs)[b] * sa);
         double inner = 0.0;
         int c = 0;
         for (; c + FRG_ILP <= nphi; c += FRG_ILP) {
@@ -338,18 +344,18 @@ __device__ __forceinline__ double contrib_three64(const ReqDev &r, const Smem &s
 #pragma unroll
             for (int w = 0; w < FRG_ILP; ++w)
                 l2[w] = fmax(fma(B2, kc(r.phi.c)[c + w], A2), FRG_L2_TINY);
-            propagators64<FRG_ILP>(l2, G, sm, nZ, za, zb1, m2, inv_k2);
+            propagators64<FRG_ILP>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
 #pragma unroll
             for (int w = 0; w < FRG_ILP; ++w) inner = fma(kc(r.phi.w)[c + w], G[w], inner);
         }
         for (; c < nphi; ++c) {
             double l2[1] = {fmax(fma(B2, kc(r.phi.c)[c], A2), FRG_L2_TINY)}, G[1];
-            propagators64<1>(l2, G, sm, nZ, za, zb1, m2, inv_k2);
+            propagators64<1>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
             inner = fma(kc(r.phi.w)[c], G[0], inner);
         }
         mid = fma(kc(r.ang.xw)[b] * g1[0], inner, mid);
     }
-    return t.wg * mid;
+    return t.wg * (mid * (inv_k2 * inv_k2));
 }
 
 // --------------------------------------------------------------------------------------------
@@ -517,36 +523,67 @@ __device__ __forceinline__ double fp32_bound(float kmax, float zslope, const Req
 // --------------------------------------------------------------------------------------------
 // Tile bodies
 // --------------------------------------------------------------------------------------------
-__device__ __forceinline__ void stage_tables(const ReqDev &r, Smem &sm) {
-    for (int i = threadIdx.x; i < kLogTable; i += blockDim.x) sm.logt[i] = r.logt[i];
-    // padded dressing: entry j (0..n) is (Z_{j-1}, Z_j - Z_{j-1}) with constant end entries
+// The logarithm table is the same for every request of a context: a persistent workgroup stages
+// it once.  Loads are issued together before the LDS stores (no round trip per entry).
+__device__ __forceinline__ void stage_log(Smem &sm, const double2 *logt) {
+    static_assert(kLogTable % kWave == 0, "log table staged in whole wavefront passes");
+    double2 v[kLogTable / kWave];
+#pragma unroll
+    for (int k = 0; k < kLogTable / kWave; ++k) v[k] = logt[k * kWave + threadIdx.x];
+#pragma unroll
+    for (int k = 0; k < kLogTable / kWave; ++k) sm.logt[k * kWave + threadIdx.x] = v[k];
+}
+
+// Padded dressing of one request: entry j (0..n) is (Z_{j-1}, Z_j - Z_{j-1}) with constant end
+// entries; for the float32 form also its float copy and the table's largest relative step
+// max|Z_{i+1} - Z_i| / min|Z_i| (one wavefront per workgroup).
+__device__ __forceinline__ void stage_dressing(const ReqDev &r, Smem &sm) {
+    constexpr int U = 2;  // entries per lane whose loads are in flight together
     const int n = r.nZ;
-    for (int j = threadIdx.x; j <= n; j += blockDim.x) {
-        double zi, dz;
-        if (j == 0) {
-            zi = r.Z[0];
-            dz = 0.0;
-        } else {
-            zi = r.Z[j - 1];
-            dz = (j < n) ? (r.Z[j] - zi) : 0.0;
+    float mx = 0.0f, mn = 3.0e38f;
+    for (int j0 = (int)threadIdx.x; j0 <= n; j0 += U * kWave) {
+        double lo[U], hi[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = min(j0 + u * kWave, n);
+            lo[u] = r.Z[max(j - 1, 0)];
+            hi[u] = r.Z[min(j, n - 1)];
         }
-        sm.Z64[j] = make_double2(zi, dz);
-        if (r.precision == 1) sm.Z32[j] = make_float2((float)zi, (float)dz);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u * kWave;
+            if (j > n) break;
+            const double dz = (j == 0 || j == n) ? 0.0 : hi[u] - lo[u];
+            sm.Z64[j] = make_double2(lo[u], dz);
+            if (r.precision == 1) {
+                sm.Z32[j] = make_float2((float)lo[u], (float)dz);
+                if (j >= 1) mn = fminf(mn, (float)fabs(lo[u]));
+                if (j >= 1 && j < n) mx = fmaxf(mx, (float)fabs(dz));
+            }
+        }
     }
     if (r.precision == 1) {
-        // largest |Z_{i+1} - Z_i| over smallest |Z_i| (one wavefront per workgroup)
-        float mx = 0.0f, mn = 3.0e38f;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const double zi = r.Z[i];
-            mn = fminf(mn, (float)fabs(zi));
-            if (i + 1 < n) mx = fmaxf(mx, (float)fabs(r.Z[i + 1] - zi));
-        }
         for (int o = kWave / 2; o > 0; o >>= 1) {
             mx = fmaxf(mx, __shfl_xor(mx, o));
             mn = fminf(mn, __shfl_xor(mn, o));
         }
         if (threadIdx.x == 0) *sm.zslope = mn > 0.0f ? mx / mn : 3.0e38f;
     }
+}
+
+// Radial sum of one point's contributions in radial order, with 8 loads in flight per wait.
+__device__ __forceinline__ double radial_sum(const double *blk, int n_q, long long stride, int e) {
+    double s = 0.0;
+    int a = 0;
+    for (; a + 8 <= n_q; a += 8) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = blk[(long long)(a + j) * stride + e];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += v[j];
+    }
+    for (; a < n_q; ++a) s += blk[(long long)a * stride + e];
+    return s;
 }
 
 __device__ __forceinline__ void bind_smem(Smem &sm, double2 *lds, int nZ, float *zslope) {
@@ -643,8 +680,7 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
         }
         __syncthreads();
         if (valid && sub == 0) {
-            double s = 0.0;
-            for (int a = 0; a < r.n_q; ++a) s += blk[(long long)a * r.n_ext + e];
+            const double s = radial_sum(blk, r.n_q, r.n_ext, e);
             r.out[e] = r.pref * s;
             if (r.err) r.err[e] = (PREC == 1) ? fp32_bound(kmax, *sm.zslope, r) : 0.0;
         }
@@ -664,13 +700,8 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
     if (lane < le) {
         const int ef = et * le + lane;
         if (ef < r.n_ext) {
-            double s = 0.0;
-            for (int a = 0; a < r.n_q; ++a) {
-                unsigned long long bits = __hip_atomic_load(
-                    (unsigned long long *)(blk + (long long)a * r.n_ext + ef), __ATOMIC_RELAXED,
-                    __HIP_MEMORY_SCOPE_AGENT);
-                s += __longlong_as_double((long long)bits);
-            }
+            // the fence above (acquire side) makes every chunk's contributions visible
+            const double s = radial_sum(blk, r.n_q, r.n_ext, ef);
             r.out[ef] = r.pref * s;
             if (PREC == 1) {
                 unsigned kb = __hip_atomic_load(&kslot[ef], __ATOMIC_RELAXED,
@@ -687,7 +718,8 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
 
 // One request: tile = blockIdx.x -> (external tile, chunk).
 template <int FAM, int PREC>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FRG_WAVES_PER_EU_BATCH)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
+    FAM == 3 ? FRG_WAVES_PER_EU_MULTI : FRG_WAVES_PER_EU_BATCH)))
 batch_kernel(ReqDev r, double *contrib, unsigned *counters) {
     extern __shared__ double2 lds_dyn[];
     if (FAM == 1) {
@@ -699,7 +731,8 @@ batch_kernel(ReqDev r, double *contrib, unsigned *counters) {
     bind_smem(sm, lds_dyn, r.nZ, &zslope);
     const int et = blockIdx.x / r.chunks;
     const int chunk = blockIdx.x - et * r.chunks;
-    stage_tables(r, sm);
+    stage_log(sm, r.logt);
+    stage_dressing(r, sm);
     __syncthreads();
     tile_vertex<FAM, PREC>(r, sm, et, chunk, contrib, counters);
 }
@@ -724,8 +757,9 @@ hipError_t launch_batch(const ReqDev *req_host, const ReqDev *req_dev_ptr, int n
 }
 
 // Many requests in one launch.  A grid sized to the device pulls tiles (ordered largest first by
-// the host) from a global counter until the list is empty; the last workgroup to leave resets the
-// counters, so the kernel can be relaunched (or replayed in a graph) without a memset.
+// the host) from a global counter until the list is empty.  A fill kernel ahead of every launch
+// clears the counter (relaunches and graph replays need no memset), so no workgroup has to
+// order its exit against the others with a device-scope fence.
 // FAM = PREC = -1 is the general kernel (any mix of families and precisions); a launch whose
 // requests all share one family and precision uses the instance specialised for them, which
 // carries only that path and so needs fewer registers (more resident waves).
@@ -757,6 +791,7 @@ multi_kernel(const ReqDev *__restrict__ reqs, const TileDev *__restrict__ tiles,
     __shared__ float zslope;
     Smem sm;
     int staged = -1;
+    bool log_staged = false;
     for (;;) {
         if (threadIdx.x == 0) tile_s = (int)atomicAdd(&work[0], 1u);
         __syncthreads();
@@ -775,20 +810,15 @@ multi_kernel(const ReqDev *__restrict__ reqs, const TileDev *__restrict__ tiles,
         if (FAM != 1) {
             bind_smem(sm, lds_dyn, r.nZ, &zslope);
             if (staged != td.req) {
-                stage_tables(r, sm);
+                // every request of a launch shares the context's logarithm table
+                if (!log_staged) stage_log(sm, r.logt);
+                log_staged = true;
+                stage_dressing(r, sm);
                 __syncthreads();
                 staged = td.req;
             }
             multi_tile<FAM, PREC>(r, sm, td, contrib, counters);
             __syncthreads();
-        }
-    }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned done = atomicAdd(&work[1], 1u);
-        if (done == gridDim.x - 1) {
-            atomicExch(&work[0], 0u);
-            atomicExch(&work[1], 0u);
         }
     }
 }
@@ -814,10 +844,22 @@ int multi_blocks_per_cu(int fam, int prec, int lds_bytes) {
     return n;
 }
 
+// Persistent grid: at most the workgroups the CUs hold at once, and no more than the tile list
+// needs in whole rounds -- with R = ceil(tiles / resident) rounds, ceil(tiles / R) workgroups
+// share the tiles evenly instead of leaving a last round mostly idle.
+int multi_grid(int n_tiles, int fam, int prec, int lds_bytes, int num_cus) {
+    const int resident = std::max(1, multi_blocks_per_cu(fam, prec, lds_bytes) * num_cus);
+    if (n_tiles <= resident) return std::max(n_tiles, 1);
+    const int rounds = (n_tiles + resident - 1) / resident;
+    return (n_tiles + rounds - 1) / rounds;
+}
+
 hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, const TileDev *tiles_dev,
                         int n_tiles, int grid, int lds_bytes, double *contrib,
                         unsigned *counters, unsigned *work_ctr, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
+    const hipError_t e = launch_fill_zero_u32(work_ctr, 2, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(multi_variant(fam, prec), dim3(grid), dim3(kWave), lds_bytes, s, reqs_dev,
                        tiles_dev, n_tiles, contrib, counters, work_ctr);
     return hipGetLastError();

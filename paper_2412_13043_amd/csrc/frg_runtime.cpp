@@ -207,7 +207,7 @@ TileShape heuristic_shape(const frg_integral_desc &d, int n_ext, int target_wave
     int ext_tiles = (n_ext + le - 1) / le;
     // Prefer more lanes per point over radial chunks: a tile that holds all radial nodes of its
     // points finishes them itself, while chunked tiles must meet through device-scope fences.
-    while (ext_tiles < target_waves && le > 4 && 2 * (kWave / le) <= d.n_q) {
+    while (ext_tiles < target_waves && le > 1 && 2 * (kWave / le) <= d.n_q) {
         le /= 2;
         ext_tiles = (n_ext + le - 1) / le;
     }
@@ -288,6 +288,7 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
         double delta = (lmax - lmin) / (double)(r.nZ - 1);
         r.za = 0.5 / delta;
         r.zb = -lmin / delta;
+        r.zbk = r.zb + r.za * std::log(r.k2);
         r.Z = has ? b.Z.values : (const double *)ctx->ones.ptr;
     }
     frg_status st = get_radial(ctx, d.n_q, d.q_max, d.d, &r.rad);
@@ -423,10 +424,10 @@ frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s,
                                  hipMemcpyHostToDevice, s));
     FRG_HIP_CHECK(hipEventRecord(sc->staged, s));
     sc->last_tiles = (int)sorted.size();
-    // persistent grid: as many one-wave workgroups as the CUs hold at once
     common_kind(reqs, &sc->last_fam, &sc->last_prec);
-    const int resident = multi_blocks_per_cu(sc->last_fam, sc->last_prec, lds) * ctx->num_cus;
-    sc->last_grid = std::min<int>((int)sorted.size(), std::max(std::min(grid_waves, resident), 1));
+    sc->last_grid = std::min(
+        multi_grid((int)sorted.size(), sc->last_fam, sc->last_prec, lds, ctx->num_cus),
+        std::max(grid_waves, 1));
     sc->last_lds = lds;
     sc->last_nreqs = (int)reqs.size();
     return relaunch_multi(sc, s);
@@ -558,7 +559,7 @@ frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const f
     FRG_HIP_CHECK(hipSetDevice(ctx->device));
     const int target = 16 * ctx->num_cus;
     std::vector<TileShape> cands;
-    for (int lq = 0; lq <= 4; ++lq) {
+    for (int lq = 0; lq <= 6; ++lq) {
         const int le = kWave >> lq;
         if (lq > 0 && le / 2 >= batch->n_ext) continue;  // narrower than needed
         const int max_chunks = (desc->n_q + (1 << lq) - 1) >> lq;

@@ -272,8 +272,7 @@ class HipExecutor : public Executor {
         const TileDev *tiles_dev = (const TileDev *)((char *)sl.tables.ptr + tiles_off);
         int fam, prec;
         common_kind(rd, &fam, &prec);
-        int grid = std::min<int>((int)tiles.size(),
-                                 multi_blocks_per_cu(fam, prec, lds) * ctx->num_cus);
+        const int grid = multi_grid((int)tiles.size(), fam, prec, lds, ctx->num_cus);
         FRG_HIP_CHECK(launch_multi(reqs_dev, fam, prec, tiles_dev, (int)tiles.size(), grid, lds,
                                    (double *)base, (unsigned *)sl.counters.ptr,
                                    (unsigned *)sl.work.ptr, sl.stream));
