@@ -29,7 +29,9 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_PEAK_TFLOPS = 157.3  # packed FP32 (v_pk_fma_f32); unpacked float32 tops out at half
 # Algorithmic FP64 work per integrand node (FLOP-equivalents, transcendentals included), per
-# family, as derived in DESIGN.md (section "Roofline and FLOP accounting").
+# family: LPA one propagator square and weight; two-point ell^2, log, dressing lerp, expm1 and
+# one single-division propagator plus the accumulation; three-point the same per node (its
+# first leg depends on the outer angle only and is counted once per 16 nodes).
 FLOP_PER_NODE = {1: 15.0, 2: 74.0, 3: 83.0}
 
 

@@ -162,6 +162,10 @@ hipError_t launch_rules(int n_q, double q_max, int d, int n_x, int n_phi, double
 // Smallest momentum squared fed to the propagator.  l2 <= 0 only arises from rounding; with
 // l2 = 1e-300 the propagator equals its l2 = 0 limit 1/(k^2 + m2) to within 1e-300 relative, the
 // dressing clamps to its first entry, and no 0/0 occurs in the single-division form below.
+// A leg along the cos1 angle needs no clamp: Gauss-Legendre nodes are interior,
+// |x| <= 1 - 2.3e-6 for n <= 1024, and l2 = q^2 + p^2 + 2qpx >= (1 - |x|)(q^2 + p^2), far above
+// the few ulp of q^2 + p^2 that its evaluation can err by.  The three-point leg through phi can
+// come arbitrarily close to zero (alpha on a node angle, phi near 0) and keeps the clamp.
 #define FRG_L2_TINY 1e-300
 
 // Quadrature rules stay constant while an integrand kernel runs.  Reading them through the
@@ -201,7 +205,11 @@ struct Smem {
 
 // Cell index and fraction of the padded dressing table for coordinate sp = s + 1.
 __device__ __forceinline__ void zcell64(double sp, int nZ, int &i, double &f) {
-    i = min(max((int)sp, 0), nZ);
+    // v_cvt_u32_f64 saturates (negative and NaN to 0), so only the upper clamp is left; the
+    // padded end entries make the fraction irrelevant wherever a clamp applies
+    unsigned u;
+    asm("v_cvt_u32_f64 %0, %1" : "=v"(u) : "v"(sp));
+    i = (int)min(u, (unsigned)nZ);
     f = __builtin_amdgcn_fract(sp);
 }
 
@@ -245,8 +253,7 @@ __device__ __forceinline__ void propagators64(const double (&l2)[W], double (&G)
         const double f = __builtin_amdgcn_frexp_mant(l2[w]);
         const int k = __builtin_amdgcn_frexp_exp(l2[w]);
         const double r = fma(f, t[w].x, -1.0);
-        double p = fma(r, 0.2, -0.25);
-        p = fma(r, p, 0.3333333333333333);
+        double p = fma(r, -0.25, 0.3333333333333333);
         p = fma(r, p, -0.5);
         p = fma(r, p, 1.0);
         p = r * p;
@@ -307,13 +314,13 @@ __device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm,
     for (; b + FRG_ILP <= nx; b += FRG_ILP) {
         double l2[FRG_ILP], G[FRG_ILP];
 #pragma unroll
-        for (int w = 0; w < FRG_ILP; ++w) l2[w] = fmax(fma(c1, kc(r.ang.x)[b + w], c0), FRG_L2_TINY);
+        for (int w = 0; w < FRG_ILP; ++w) l2[w] = fma(c1, kc(r.ang.x)[b + w], c0);
         propagators64<FRG_ILP>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w) inner = fma(kc(r.ang.xw)[b + w], G[w], inner);
     }
     for (; b < nx; ++b) {
-        double l2[1] = {fmax(fma(c1, kc(r.ang.x)[b], c0), FRG_L2_TINY)}, G[1];
+        double l2[1] = {fma(c1, kc(r.ang.x)[b], c0)}, G[1];
         propagators64<1>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
         inner = fma(kc(r.ang.xw)[b], G[0], inner);
     }
@@ -333,7 +340,7 @@ __device__ __forceinline__ double contrib_three64(const ReqDev &r, const Smem &s
     double mid = 0.0;
     for (int b = 0; b < nx; ++b) {
         const double xb = kc(r.ang.x)[b];
-        double l1[1] = {fmax(fma(c1, xb, c0), FRG_L2_TINY)}, g1[1];
+        double l1[1] = {fma(c1, xb, c0)}, g1[1];
         propagators64<1>(l1, g1, sm, nZ, za, zb1, m2h, 1.0);
         const double A2 = fma(-c1, xb * ca, c0);
         const double B2 = -c1 * (kc(r.ang.xs)[b] * sa);
@@ -653,38 +660,46 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
     // per-point slots after the tile counters (zero at rest): largest float32 amplification
     unsigned *kslot = counters + r.ctr_base + r.ext_tiles;
     float kmax = 1.0f;
+    double p = 0.0, m2 = 0.0, ca = 1.0, sa = 0.0;
     if (valid) {
-        const double p = r.ext[e];
-        const double m2 = lane_m2(r, e);
-        double ca = 1.0, sa = 0.0;
+        p = r.ext[e];
+        m2 = lane_m2(r, e);
         if (FAM == 3) sincos(r.ext[r.n_ext + e], &sa, &ca);
-        for (int a = a0 + sub; a < a1; a += lq) {
-            double v;
-            if (PREC == 0)
-                v = (FAM == 2) ? contrib_two64(r, sm, a, p, m2, inv_k2)
-                               : contrib_three64(r, sm, a, p, ca, sa, m2, inv_k2);
-            else
-                v = (FAM == 2) ? contrib_two32(r, sm, a, p, m2, inv_k2, kmax)
-                               : contrib_three32(r, sm, a, p, ca, sa, m2, inv_k2, kmax);
-            blk[(long long)a * r.n_ext + e] = v;
-        }
-        if (PREC == 1 && r.chunks > 1) atomicMax(&kslot[e], __float_as_uint(kmax));
     }
+    auto node = [&](int a) -> double {
+        if (PREC == 0)
+            return (FAM == 2) ? contrib_two64(r, sm, a, p, m2, inv_k2)
+                              : contrib_three64(r, sm, a, p, ca, sa, m2, inv_k2);
+        return (FAM == 2) ? contrib_two32(r, sm, a, p, m2, inv_k2, kmax)
+                          : contrib_three32(r, sm, a, p, ca, sa, m2, inv_k2, kmax);
+    };
     if (r.chunks == 1) {
-        // This wavefront evaluated every radial node of its points, so no other workgroup takes
-        // part: a workgroup barrier publishes the contributions, and the radial sum below runs
-        // in the same order as the cross-workgroup one (identical bits).  No device-scope fence
-        // (an L2 writeback and invalidate on a multi-XCD part) and no counter are needed.
+        // The wavefront holds every radial node of its points.  The lq lanes of a point take
+        // rounds of lq consecutive radial nodes; after each round the point's first lane pulls
+        // the round's values across lanes and adds them in radial order -- the same sequence
+        // of additions as the radial sum of chunked tiles (identical bits), with no scratch
+        // stores, no barrier and no device-scope fence (an L2 writeback and invalidate on a
+        // multi-XCD part).
+        const int base = lane & ~(lq - 1);
+        double sum = 0.0;
+        for (int r0 = 0; r0 < r.n_q; r0 += lq) {
+            const int a = r0 + sub;
+            const double v = (valid && a < r.n_q) ? node(a) : 0.0;
+            const int nk = min(lq, r.n_q - r0);
+            for (int k = 0; k < nk; ++k) sum += __shfl(v, base + k);
+        }
         if (PREC == 1) {
             for (int o = 1; o < lq; o <<= 1) kmax = fmaxf(kmax, __shfl_xor(kmax, o));
         }
-        __syncthreads();
         if (valid && sub == 0) {
-            const double s = radial_sum(blk, r.n_q, r.n_ext, e);
-            r.out[e] = r.pref * s;
+            r.out[e] = r.pref * sum;
             if (r.err) r.err[e] = (PREC == 1) ? fp32_bound(kmax, *sm.zslope, r) : 0.0;
         }
         return;
+    }
+    if (valid) {
+        for (int a = a0 + sub; a < a1; a += lq) blk[(long long)a * r.n_ext + e] = node(a);
+        if (PREC == 1) atomicMax(&kslot[e], __float_as_uint(kmax));
     }
     // publish the contributions, then count this chunk
     __threadfence();
@@ -756,10 +771,11 @@ hipError_t launch_batch(const ReqDev *req_host, const ReqDev *req_dev_ptr, int n
     return hipGetLastError();
 }
 
-// Many requests in one launch.  A grid sized to the device pulls tiles (ordered largest first by
-// the host) from a global counter until the list is empty.  A fill kernel ahead of every launch
-// clears the counter (relaunches and graph replays need no memset), so no workgroup has to
-// order its exit against the others with a device-scope fence.
+// Many requests in one launch.  A grid sized to the device takes the first tiles (ordered
+// largest first by the host) by workgroup index and pulls the rest from a global counter until
+// the list is empty.  A fill kernel ahead of every launch clears the counter (relaunches and
+// graph replays need no memset), so no workgroup has to order its exit against the others with
+// a device-scope fence.
 // FAM = PREC = -1 is the general kernel (any mix of families and precisions); a launch whose
 // requests all share one family and precision uses the instance specialised for them, which
 // carries only that path and so needs fewer registers (more resident waves).
@@ -792,11 +808,19 @@ multi_kernel(const ReqDev *__restrict__ reqs, const TileDev *__restrict__ tiles,
     Smem sm;
     int staged = -1;
     bool log_staged = false;
-    for (;;) {
-        if (threadIdx.x == 0) tile_s = (int)atomicAdd(&work[0], 1u);
-        __syncthreads();
-        const int t = tile_s;
-        __syncthreads();
+    for (int round = 0;; ++round) {
+        // The first round is static (tile = workgroup index): thousands of workgroups starting
+        // together would otherwise queue on one atomic.  Later tiles come from the counter.
+        int t;
+        if (round == 0) {
+            t = (int)blockIdx.x;
+        } else {
+            if ((int)gridDim.x >= n_tiles) break;
+            if (threadIdx.x == 0) tile_s = (int)gridDim.x + (int)atomicAdd(&work[0], 1u);
+            __syncthreads();
+            t = tile_s;
+            __syncthreads();
+        }
         if (t >= n_tiles) break;
         const TileDev td = tiles[t];
         const ReqDev &r = reqs[td.req];

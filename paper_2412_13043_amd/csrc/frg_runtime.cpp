@@ -227,14 +227,16 @@ TileShape choose_shape(frg_context *ctx, const frg_integral_desc &d, int n_ext, 
     return heuristic_shape(d, n_ext, target_waves);
 }
 
+// Only radially chunked requests hand contributions between workgroups; a single-chunk tile
+// reduces its points within the wavefront and needs neither scratch nor counters.
 size_t contrib_doubles(const ReqDev &r) {
-    if (r.family == 1) return 0;
+    if (r.family == 1 || r.chunks == 1) return 0;
     return (size_t)r.n_q * (size_t)r.n_ext;  // [n_q][n_ext] contributions
 }
 
 int counter_count(const ReqDev &r) {
     // one counter per external tile, then (float32 form) one amplification slot per point
-    if (r.family == 1) return 0;
+    if (r.family == 1 || r.chunks == 1) return 0;
     return r.ext_tiles + (r.precision == 1 ? r.n_ext : 0);
 }
 

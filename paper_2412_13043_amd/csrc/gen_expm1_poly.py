@@ -1,6 +1,6 @@
 """Coefficients of the float64 expm1 kernel polynomial used in frg_math.hpp.
 
-expm1(r) = r + r^2 Q(r) on |r| <= ln2/2, with Q a degree-9 Chebyshev interpolant of
+expm1(r) = r + r^2 Q(r) on |r| <= ln2/2, with Q a degree-8 Chebyshev interpolant of
 (expm1(r) - r)/r^2 (near-minimax; mpmath.chebyfit at 40 digits), printed highest degree first.
 Run: python gen_expm1_poly.py
 """
@@ -17,9 +17,9 @@ def Q(r):
 
 
 if __name__ == "__main__":
-    coeffs, err = mp.chebyfit(Q, [-A, A], 10, error=True)
+    coeffs, err = mp.chebyfit(Q, [-A, A], 9, error=True)
     for k, c in enumerate(coeffs):
-        print(f"    constexpr double Q{9 - k} = {float(c)!r};")
+        print(f"    constexpr double Q{8 - k} = {float(c)!r};")
     worst = 0
     for i in range(4001):
         r = -A + 2 * A * i / 4000
