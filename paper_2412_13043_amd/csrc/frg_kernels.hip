@@ -533,12 +533,14 @@ __device__ __forceinline__ double fp32_bound(float kmax, float zslope, const Req
 // The logarithm table is the same for every request of a context: a persistent workgroup stages
 // it once.  Loads are issued together before the LDS stores (no round trip per entry).
 __device__ __forceinline__ void stage_log(Smem &sm, const double2 *logt) {
-    static_assert(kLogTable % kWave == 0, "log table staged in whole wavefront passes");
-    double2 v[kLogTable / kWave];
-#pragma unroll
-    for (int k = 0; k < kLogTable / kWave; ++k) v[k] = logt[k * kWave + threadIdx.x];
-#pragma unroll
-    for (int k = 0; k < kLogTable / kWave; ++k) sm.logt[k * kWave + threadIdx.x] = v[k];
+    static_assert(kLogTable == 4 * kWave, "log table staged in four wavefront passes");
+    const int i = (int)threadIdx.x;
+    const double2 v0 = logt[i], v1 = logt[i + kWave], v2 = logt[i + 2 * kWave],
+                  v3 = logt[i + 3 * kWave];
+    sm.logt[i] = v0;
+    sm.logt[i + kWave] = v1;
+    sm.logt[i + 2 * kWave] = v2;
+    sm.logt[i + 3 * kWave] = v3;
 }
 
 // Padded dressing of one request: entry j (0..n) is (Z_{j-1}, Z_j - Z_{j-1}) with constant end
