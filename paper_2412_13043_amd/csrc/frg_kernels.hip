@@ -383,12 +383,14 @@ struct Kahan32 {
     }
 };
 
+// Per-point constants of the float32 form; like the float64 loops it works in units of k^2
+// (y = l2/k^2, m2/k^2, G^ = k^2 G).
 struct Par32 {
     int nZ;
-    float za2, zb1;   // s + 1 = za2 * log2(l2) + zb1
-    float m2f, am2f;  // m2 and |m2|
-    float ik, tau;    // 1/k^2, near-pole threshold
-    double m2, inv_k2, za, zb1d;
+    float za2, zb1;   // s + 1 = za2 * log2(y) + zb1
+    float m2f, am2f;  // m2/k^2 and its magnitude
+    float tau;        // near-pole threshold
+    double m2, za, zb1d;
 };
 
 // W float32 propagators; kmax tracks the largest amplification (|Z l2 + R| + |m2|)/D of the
@@ -401,7 +403,9 @@ __device__ __forceinline__ void propagators32(const float (&l2)[W], float (&G)[W
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         const float sp = fmaf(__builtin_amdgcn_logf(l2[w]), P.za2, P.zb1);
-        iz[w] = min(max((int)sp, 0), P.nZ);
+        unsigned u;  // saturating conversion: negative and NaN to 0 (see zcell64)
+        asm("v_cvt_u32_f32 %0, %1" : "=v"(u) : "v"(sp));
+        iz[w] = (int)min(u, (unsigned)P.nZ);
         fz[w] = __builtin_amdgcn_fractf(sp);
     }
     float2 z[W];
@@ -409,7 +413,7 @@ __device__ __forceinline__ void propagators32(const float (&l2)[W], float (&G)[W
     for (int w = 0; w < W; ++w) z[w] = sm.Z32[iz[w]];
     float E[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) E[w] = fm::expm1_neg_f(l2[w] * P.ik);
+    for (int w = 0; w < W; ++w) E[w] = fm::expm1_neg_f(l2[w]);
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         const float zv = fmaf(fz[w], z[w].y, z[w].x);
@@ -419,11 +423,12 @@ __device__ __forceinline__ void propagators32(const float (&l2)[W], float (&G)[W
         if (den < P.tau * parts) {
             const double l2d = (double)l2[w];
             const double zd = dressing64(sm, P.nZ, P.za, P.zb1d, l2d);
-            G[w] = (float)prop64(l2d, zd, P.m2, P.inv_k2);
+            G[w] = (float)prop64(l2d, zd, P.m2, 1.0);
         } else {
             const float rd = __builtin_amdgcn_rcpf(den);
             G[w] = -E[w] * rd;
-            kmax = fmaxf(kmax, parts * rd);
+            // both non-negative: the larger float is the larger bit pattern
+            kmax = __uint_as_float(max(__float_as_uint(kmax), __float_as_uint(parts * rd)));
         }
     }
 }
@@ -432,15 +437,13 @@ __device__ __forceinline__ Par32 par32(const ReqDev &r, double m2, double inv_k2
     Par32 P;
     P.nZ = r.nZ;
     P.za2 = (float)(r.za * 0.69314718055994530942);
-    P.zb1 = (float)(r.zb + 1.0);
-    P.m2f = (float)m2;
+    P.zb1 = (float)(r.zbk + 1.0);
+    P.m2 = m2 * inv_k2;
+    P.m2f = (float)P.m2;
     P.am2f = fabsf(P.m2f);
-    P.ik = (float)inv_k2;
     P.tau = (float)r.tau;
-    P.m2 = m2;
-    P.inv_k2 = inv_k2;
     P.za = r.za;
-    P.zb1d = r.zb + 1.0;
+    P.zb1d = r.zbk + 1.0;
     return P;
 }
 
@@ -448,6 +451,7 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
                                                 double m2, double inv_k2, float &kmax) {
     const RadialTerm t = radial64(r, sm, a, p, m2);
     const Par32 P = par32(r, m2, inv_k2);
+    const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2;  // y = l2/k^2 > 0 (see FRG_L2_TINY)
     Kahan32 acc{0.0f, 0.0f};
     const int nx = r.n_x;
     int b = 0;
@@ -455,7 +459,7 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
         float l2[FRG_ILP], G[FRG_ILP];
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w)
-            l2[w] = (float)fmax(fma(t.c1, kc(r.ang.x)[b + w], t.c0), 1e-30);
+            l2[w] = (float)fma(c1, kc(r.ang.x)[b + w], c0);
         propagators32<FRG_ILP>(l2, G, kmax, sm, P);
         float blk = 0.0f;
 #pragma unroll
@@ -463,11 +467,11 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
         acc.add(blk);
     }
     for (; b < nx; ++b) {
-        float l2[1] = {(float)fmax(fma(t.c1, kc(r.ang.x)[b], t.c0), 1e-30)}, G[1];
+        float l2[1] = {(float)fma(c1, kc(r.ang.x)[b], c0)}, G[1];
         propagators32<1>(l2, G, kmax, sm, P);
         acc.add(kc(r.ang.xwf)[b] * G[0]);
     }
-    return t.wg * ((double)acc.s - (double)acc.c);
+    return t.wg * (((double)acc.s - (double)acc.c) * inv_k2);
 }
 
 __device__ __forceinline__ double contrib_three32(const ReqDev &r, const Smem &sm, int a, double p,
@@ -475,14 +479,15 @@ __device__ __forceinline__ double contrib_three32(const ReqDev &r, const Smem &s
                                                   double inv_k2, float &kmax) {
     const RadialTerm t = radial64(r, sm, a, p, m2);
     const Par32 P = par32(r, m2, inv_k2);
+    const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2;
     double mid = 0.0;
     const int nx = r.n_x, nphi = r.n_phi;
     for (int b = 0; b < nx; ++b) {
         const double xb = kc(r.ang.x)[b];
-        float l1[1] = {(float)fmax(fma(t.c1, xb, t.c0), 1e-30)}, g1[1];
+        float l1[1] = {(float)fma(c1, xb, c0)}, g1[1];
         propagators32<1>(l1, g1, kmax, sm, P);
-        const double A2 = fma(-t.c1, xb * ca, t.c0);
-        const double B2 = -t.c1 * (kc(r.ang.xs)[b] * sa);
+        const double A2 = fma(-c1, xb * ca, c0);
+        const double B2 = -c1 * (kc(r.ang.xs)[b] * sa);
         Kahan32 acc{0.0f, 0.0f};
         int c = 0;
         for (; c + FRG_ILP <= nphi; c += FRG_ILP) {
@@ -504,25 +509,25 @@ __device__ __forceinline__ double contrib_three32(const ReqDev &r, const Smem &s
         const double inner = (double)acc.s - (double)acc.c;
         mid = fma((double)kc(r.ang.xw)[b] * (double)g1[0], inner, mid);
     }
-    return t.wg * mid;
+    return t.wg * (mid * (inv_k2 * inv_k2));
 }
 
 // float32 form's stated relative error bound per result (u = 2^-24, kappa = largest float32
 // amplification (|Z l2 + R| + |m2|)/D of the point, L = largest relative step of the dressing
 // table, ds = bound on the float32 error of the dressing coordinate s):
 //   (16 + 3 kappa) u + kappa L ds
-// 16 u: l2 rounded once to float32, expm1 and its reconstruction, the reciprocal, the weight
-// products, the block sums and their compensated accumulation; 3 kappa u: the rounding of the
-// denominator's three terms, amplified by their cancellation; kappa L ds: the dressing lookup.
-// ds: s + 1 = fmaf(log2 l2, za2, zb1) in float32 -- the rounding of l2 (1.5 u in log2), v_log_f32
-// (1 ulp of |log2 l2|, at most Lmax = the larger |log2| of the table's end points while s is
-// inside the table; outside it the end entries are constant), and the rounding of za2, zb1 and
-// the sum (u (2 nZ + 3 |zb1| + 2)).
+// 16 u: y = l2/k^2 rounded once to float32, expm1 and its reconstruction, the reciprocal, the
+// weight products, the block sums and their compensated accumulation; 3 kappa u: the rounding of
+// the denominator's three terms, amplified by their cancellation; kappa L ds: the dressing
+// lookup.  ds: s + 1 = fmaf(log2 y, za2, zb1) in float32 -- the rounding of y (1.5 u in log2),
+// v_log_f32 (1 ulp of |log2 y|, at most Lmax = the larger |log2| of the table's end points in
+// units of k^2 while s is inside the table; outside it the end entries are constant), and the
+// rounding of za2, zb1 and the sum (u (2 nZ + 3 |zb1| + 2)).
 __device__ __forceinline__ double fp32_bound(float kmax, float zslope, const ReqDev &r) {
     const double u = 5.9604644775390625e-8;
     const double ln2 = 0.69314718055994530942;
-    const double za2 = r.za * ln2, zb1 = fabs(r.zb + 1.0);
-    const double lmax = fmax(fabs(-r.zb / r.za), fabs((r.nZ - 1 - r.zb) / r.za)) / ln2;
+    const double za2 = r.za * ln2, zb1 = fabs(r.zbk + 1.0);
+    const double lmax = fmax(fabs(-r.zbk / r.za), fabs((r.nZ - 1 - r.zbk) / r.za)) / ln2;
     const double ds = u * (2.0 * (r.nZ + 1) + 3.0 * zb1 + 2.0) + za2 * (2.0 * u * lmax + 1.5 * u);
     return (16.0 + 3.0 * (double)kmax) * u + (double)kmax * (double)zslope * ds;
 }

@@ -400,6 +400,53 @@ def test_empty_batch_is_noop(env):
 
 
 # ------------------------------------------------------------------------------------------
+# Tile shapes: lanes per point 1..64, radially chunked or not, ragged radial rounds -- every
+# shape must give the same bits (the radial sum always runs in radial order)
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("family,precision", [(2, 0), (2, 1), (3, 0), (3, 1)])
+def test_tile_shapes_give_identical_bits(env, tmp_path, monkeypatch, family, precision):
+    frg, _, torch = env
+    n_q, n_x, n_phi = 13, 6, (4 if family == 3 else 0)
+    rng = np.random.default_rng(40 + family)
+    n = 37
+    p = 10 ** rng.uniform(-3, 2, n)
+    ext = np.concatenate([p, rng.uniform(0, math.pi, n)]) if family == 3 else p
+    m2 = rng.uniform(-0.9, 2.0, n) if precision == 0 else rng.uniform(-0.95, -0.5, n)
+    Z = wl.dressing_table(7)
+    desc = frg.make_desc(family, n_q, 10.0, n_x=n_x, n_phi=n_phi, precision=precision,
+                         near_pole_tau=0.1 if precision else 0.0)
+    target = 16 * torch.cuda.get_device_properties(0).multi_processor_count
+    te, tm, tz = _d(torch, ext), _d(torch, m2), _d(torch, Z)
+    results = []
+    # (lanes-per-point log2, radial chunks): one, several and the maximum number of chunks;
+    # 8, 16 and 64 lanes leave a ragged last radial round (13 nodes)
+    shapes = [(0, 1), (0, 13), (1, 3), (2, 1), (3, 1), (3, 2), (4, 1), (6, 1)]
+    for lq, ch in shapes:
+        cache = tmp_path / f"shape_{lq}_{ch}.txt"
+        cache.write_text(f"{family} {precision} {n_q} {n_x} {n_phi} {n} {target} {lq} {ch}\n")
+        monkeypatch.setenv("FRG_AUTOTUNE_CACHE", str(cache))
+        ctx = frg.Context(0)
+        try:
+            out = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+            eo = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+            ctx.integrate(desc, out, ext=te, m2=tm, Z=tz, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
+                          err_out=eo)
+            torch.cuda.synchronize()
+            results.append((out.cpu().numpy(), eo.cpu().numpy()))
+        finally:
+            ctx.close()
+    for (o, e), shape in zip(results[1:], shapes[1:]):
+        assert np.array_equal(o, results[0][0]), shape
+        assert np.array_equal(e, results[0][1]), shape
+    if precision == 0:
+        ref = oracle.integrate(family, n_q, 10.0, n_x=n_x, n_phi=n_phi,
+                               ext=(p, ext[n:]) if family == 3 else p, m2=m2, Z=Z)
+        assert _rel(results[0][0], ref) <= TOL
+    else:
+        assert np.all(np.isfinite(results[0][0])) and np.all(results[0][1] > 0)
+
+
+# ------------------------------------------------------------------------------------------
 # Autotuner: picks a tile shape by timing; results must not change, the choice is persisted
 # ------------------------------------------------------------------------------------------
 def test_autotune_keeps_results_bitwise(env, tmp_path, monkeypatch):
