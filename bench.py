@@ -147,6 +147,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--workload", default="two_point_256",
+                    choices=["two_point_256", "three_point_8", "lpa_4096"],
+                    help="workload of the timed line (default: the two-point batch); the others "
+                         "exist so that each family's kernel can be profiled on its own")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the "
                          "reference kernel for scaling FETCH_SIZE/WRITE_SIZE counters)")
@@ -172,18 +176,16 @@ def main():
     from paper_2412_13043_amd import workloads as wl
 
     ctx = frg.Context(0)
-    log("bench: two-point batch setup")
-    descs, batches, out, _, nodes, keep = two_point_batch_setup(torch, frg)
-
-    def step():
-        ctx.integrate_multi(descs, batches)
+    log(f"bench: {args.workload} setup")
+    step, nodes, family, kernel, config, keep = workload_setup(torch, frg, wl, ctx,
+                                                                args.workload)
 
     log(f"bench: timing {args.steps} steps after {args.warmup} warmup")
     wall, ev_ms = time_kernel(torch, step, args.steps, args.warmup)
     ms_per_step = wall / args.steps * 1e3
     value = nodes * args.steps / wall / 1e9
     avg_ms = float(np.mean(ev_ms))
-    flops = FLOP_PER_NODE[2] * nodes
+    flops = FLOP_PER_NODE[family] * nodes
     achieved = flops / (avg_ms * 1e-3) / 1e12
     res = {
         "metric": "integrand Gnodes/s + % FP64/FP32 vector peak; p50/p99 RHS latency",
@@ -198,15 +200,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "two-point vertex flow d=4: 256 right-hand sides x 256 momenta "
-                               "x 64x32 GL nodes, per-RHS tabulated Z, m2=0.5, float64, one "
-                               "fused frg_integrate_multi launch",
-                   "nodes_per_step": nodes, "rhs_per_step": 256},
+        "config": config,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                     "traffic": measured_traffic(), "kernel": "frg::multi_kernel<2, 0>",
-                     "avg_kernel_ms": round(avg_ms, 4),
-                     "flop_per_node": FLOP_PER_NODE[2]},
+                     "traffic": measured_traffic() if args.workload == "two_point_256" else None,
+                     "kernel": kernel, "avg_kernel_ms": round(avg_ms, 4),
+                     "flop_per_node": FLOP_PER_NODE[family]},
     }
     extra = {}
     if not args.no_extra:
@@ -219,6 +218,43 @@ def main():
     torch.cuda.synchronize()
     ctx.close()
     print(json.dumps(res), flush=True)
+
+
+def workload_setup(torch, frg, wl, ctx, name):
+    """Inputs resident in HBM and a step function for one timed workload."""
+    if name == "two_point_256":
+        descs, batches, out, _, nodes, keep = two_point_batch_setup(torch, frg)
+        config = {"workload": "two-point vertex flow d=4: 256 right-hand sides x 256 momenta x "
+                              "64x32 GL nodes, per-RHS tabulated Z, m2=0.5, float64, one fused "
+                              "frg_integrate_multi launch",
+                  "nodes_per_step": nodes, "rhs_per_step": 256}
+        return (lambda: ctx.integrate_multi(descs, batches), nodes, 2, "frg::multi_kernel<2, 0>",
+                config, keep)
+    if name == "three_point_8":
+        P, A, m3, Z3 = wl.three_point_batch()
+        text = _dev(torch, np.concatenate([P, A]))
+        tm3, tZ3 = _dev(torch, m3), _dev(torch, Z3)
+        o3 = torch.empty((8, P.size), dtype=torch.float64, device="cuda")
+        d3 = frg.make_desc(3, wl.THREE_NQ, wl.THREE_QMAX, n_x=wl.THREE_NX, n_phi=wl.THREE_NPHI)
+        b3 = [frg.make_batch(P.size, o3[b], ext=text, m2=tm3[b], Z=tZ3[b], x_min=wl.Z_XMIN,
+                             x_max=wl.Z_XMAX) for b in range(8)]
+        nodes = 8 * P.size * wl.THREE_NQ * wl.THREE_NX * wl.THREE_NPHI
+        config = {"workload": "three-point vertex flow d=4: 8 right-hand sides x 1024 external "
+                              "pairs x 64x32x16 GL nodes, per-RHS tabulated Z, m2 in U[0.1,2], "
+                              "float64, one fused frg_integrate_multi launch",
+                  "nodes_per_step": nodes, "rhs_per_step": 8}
+        return (lambda: ctx.integrate_multi([d3] * 8, b3), nodes, 3, "frg::multi_kernel<3, 0>",
+                config, (text, tm3, tZ3, o3))
+    rho, u, m2 = wl.lpa_batch()
+    tm = _dev(torch, m2.reshape(-1))
+    o1 = torch.empty(tm.numel(), dtype=torch.float64, device="cuda")
+    d1 = frg.make_desc(1, wl.LPA_NQ, wl.LPA_QMAX)
+    nodes = tm.numel() * wl.LPA_NQ
+    config = {"workload": "LPA O(4) d=3: 4096 right-hand sides x 64 rho points x 32 GL nodes, "
+                          "float64, one frg_integrate_batch launch",
+              "nodes_per_step": nodes, "rhs_per_step": 4096}
+    return (lambda: ctx.integrate(d1, o1, m2=tm), nodes, 1, "frg::batch_kernel<1, 0>", config,
+            (tm, o1))
 
 
 def secondary(torch, frg, wl, ctx):
