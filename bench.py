@@ -68,21 +68,22 @@ def _dev(torch, a):
 
 
 def time_kernel(torch, fn, steps, warmup):
-    """Run fn warmup + steps times; return (wall seconds for the steps, per-launch event ms)."""
+    """Run fn warmup + steps times; return (wall seconds for the timed steps, average ms per step
+    from one pair of HIP events around them on the launch stream).  Events between steps would
+    put their own markers into the stream, so the timed region is bracketed only once."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(steps)]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    for a, b in evs:
-        a.record(stream)
+    a.record(stream)
+    for _ in range(steps):
         fn()
-        b.record(stream)
+    b.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return t1 - t0, [a.elapsed_time(b) for a, b in evs]
+    return t1 - t0, [a.elapsed_time(b) / steps]
 
 
 def two_point_batch_setup(torch, frg, B=256, precision=0, seed_m2=None):
@@ -321,6 +322,14 @@ def secondary(torch, frg, wl, ctx):
     dd = frg.make_desc(2, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX)
     lat["two_point_rhs"] = _latency(torch, lambda: ctx.flow_rhs(dd, s2, tp, d2, Z=tZ,
                                                                 m2_floor=-0.9, coef=1.0))
+    P, A, m3, Z3 = wl.three_point()
+    tg3, tZ3 = _dev(torch, np.concatenate([P, A])), _dev(torch, Z3)
+    s3 = _dev(torch, m3)
+    d3o = torch.empty_like(s3)
+    d3 = frg.make_desc(3, wl.THREE_NQ, wl.THREE_QMAX, n_x=wl.THREE_NX, n_phi=wl.THREE_NPHI)
+    lat["three_point_rhs"] = _latency(torch, lambda: ctx.flow_rhs(d3, s3, tg3, d3o, Z=tZ3,
+                                                                  m2_floor=-0.9, coef=1.0),
+                                      n=500)
     ex["rhs_latency_us"] = lat
     log("bench: serving")
     ex["serving"] = serving(torch, frg, wl, ctx)

@@ -154,13 +154,17 @@ frg_status frg_integrate_batch(frg_context *ctx, const frg_integral_desc *desc,
 frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc *descs,
                                const frg_batch *batches, hipStream_t stream);
 
-/* Pick the tile shape (lanes per external point x radial chunks) of frg_integrate_batch and
+/* Pick the tile shape (lanes per external point over radial nodes and, for the three-point
+ * family, over cos1 nodes; radial chunks per external tile) of frg_integrate_batch and
  * frg_flow_rhs for this descriptor and batch size by timing the candidate shapes on the given
  * batch (its out buffer is overwritten with the integrals), and keep the fastest in the context.
  * If the environment variable FRG_AUTOTUNE_CACHE names a file, tuned shapes are loaded from it
- * when the context is created and appended to it here; if FRG_AUTOTUNE_LOG names a file, every
- * candidate's time is appended to it ("family precision n_q n_x n_phi n_ext lq_log2 chunks us").
- * Results do not depend on the shape, only speed does.  Synchronises `stream`.  *best_us (optional) receives the best time per launch. */
+ * when the context is created and appended to it here, one line per shape:
+ * "family precision n_q n_x n_phi n_ext target lq_log2 chunks lx_log2" (target = 16 x CUs);
+ * if FRG_AUTOTUNE_LOG names a file, every candidate's time is appended to it
+ * ("family precision n_q n_x n_phi n_ext lq_log2 chunks lx_log2 us").
+ * Results do not depend on the shape, only speed does.  Synchronises `stream`.
+ * *best_us (optional) receives the best time per launch. */
 frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const frg_batch *batch,
                         hipStream_t stream, int reps, double *best_us);
 

@@ -329,40 +329,36 @@ __device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm,
 
 // Contribution of (e, a) to the three-point integral.  l1 does not depend on phi, so G(l1^2) is
 // evaluated once per (a, b); l2^2 = (c0 - c1 x cos a) - c1 sqrt(1-x^2) sin a cos phi.
-__device__ __forceinline__ double contrib_three64(const ReqDev &r, const Smem &sm, int a, double p,
-                                                  double ca, double sa, double m2,
-                                                  double inv_k2) {
-    // both legs in units of k^2 (see contrib_two64): the product carries 1/k^4
-    const RadialTerm t = radial64(r, sm, a, p, m2);
-    const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2, m2h = m2 * inv_k2;
-    const int nx = r.n_x, nphi = r.n_phi, nZ = r.nZ;
+// One cos1 node b of the three-point contribution (units of k^2): t = xw_b G^(l1^2) and the phi
+// sum inner = sum_c w_c G^(l2^2).
+__device__ __forceinline__ void xterm64(const ReqDev &r, const Smem &sm, int b, double c0,
+                                        double c1, double ca, double sa, double m2h, double &t,
+                                        double &inner) {
+    const int nphi = r.n_phi, nZ = r.nZ;
     const double za = r.za, zb1 = r.zbk + 1.0;
-    double mid = 0.0;
-    for (int b = 0; b < nx; ++b) {
-        const double xb = kc(r.ang.x)[b];
-        double l1[1] = {fma(c1, xb, c0)}, g1[1];
-        propagators64<1>(l1, g1, sm, nZ, za, zb1, m2h, 1.0);
-        const double A2 = fma(-c1, xb * ca, c0);
-        const double B2 = -c1 * (kc(r.ang.xs)[b] * sa);
-        double inner = 0.0;
-        int c = 0;
-        for (; c + FRG_ILP <= nphi; c += FRG_ILP) {
-            double l2[FRG_ILP], G[FRG_ILP];
+    const double xb = kc(r.ang.x)[b];
+    double l1[1] = {fma(c1, xb, c0)}, g1[1];
+    propagators64<1>(l1, g1, sm, nZ, za, zb1, m2h, 1.0);
+    const double A2 = fma(-c1, xb * ca, c0);
+    const double B2 = -c1 * (kc(r.ang.xs)[b] * sa);
+    double acc = 0.0;
+    int c = 0;
+    for (; c + FRG_ILP <= nphi; c += FRG_ILP) {
+        double l2[FRG_ILP], G[FRG_ILP];
 #pragma unroll
-            for (int w = 0; w < FRG_ILP; ++w)
-                l2[w] = fmax(fma(B2, kc(r.phi.c)[c + w], A2), FRG_L2_TINY);
-            propagators64<FRG_ILP>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
+        for (int w = 0; w < FRG_ILP; ++w)
+            l2[w] = fmax(fma(B2, kc(r.phi.c)[c + w], A2), FRG_L2_TINY);
+        propagators64<FRG_ILP>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
 #pragma unroll
-            for (int w = 0; w < FRG_ILP; ++w) inner = fma(kc(r.phi.w)[c + w], G[w], inner);
-        }
-        for (; c < nphi; ++c) {
-            double l2[1] = {fmax(fma(B2, kc(r.phi.c)[c], A2), FRG_L2_TINY)}, G[1];
-            propagators64<1>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
-            inner = fma(kc(r.phi.w)[c], G[0], inner);
-        }
-        mid = fma(kc(r.ang.xw)[b] * g1[0], inner, mid);
+        for (int w = 0; w < FRG_ILP; ++w) acc = fma(kc(r.phi.w)[c + w], G[w], acc);
     }
-    return t.wg * (mid * (inv_k2 * inv_k2));
+    for (; c < nphi; ++c) {
+        double l2[1] = {fmax(fma(B2, kc(r.phi.c)[c], A2), FRG_L2_TINY)}, G[1];
+        propagators64<1>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
+        acc = fma(kc(r.phi.w)[c], G[0], acc);
+    }
+    t = kc(r.ang.xw)[b] * g1[0];
+    inner = acc;
 }
 
 // --------------------------------------------------------------------------------------------
@@ -474,42 +470,78 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
     return t.wg * (((double)acc.s - (double)acc.c) * inv_k2);
 }
 
-__device__ __forceinline__ double contrib_three32(const ReqDev &r, const Smem &sm, int a, double p,
-                                                  double ca, double sa, double m2,
-                                                  double inv_k2, float &kmax) {
-    const RadialTerm t = radial64(r, sm, a, p, m2);
-    const Par32 P = par32(r, m2, inv_k2);
-    const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2;
-    double mid = 0.0;
-    const int nx = r.n_x, nphi = r.n_phi;
-    for (int b = 0; b < nx; ++b) {
-        const double xb = kc(r.ang.x)[b];
-        float l1[1] = {(float)fma(c1, xb, c0)}, g1[1];
-        propagators32<1>(l1, g1, kmax, sm, P);
-        const double A2 = fma(-c1, xb * ca, c0);
-        const double B2 = -c1 * (kc(r.ang.xs)[b] * sa);
-        Kahan32 acc{0.0f, 0.0f};
-        int c = 0;
-        for (; c + FRG_ILP <= nphi; c += FRG_ILP) {
-            float l2[FRG_ILP], G[FRG_ILP];
+__device__ __forceinline__ void xterm32(const ReqDev &r, const Smem &sm, const Par32 &P, int b,
+                                        double c0, double c1, double ca, double sa, float &kmax,
+                                        double &t, double &inner) {
+    const int nphi = r.n_phi;
+    const double xb = kc(r.ang.x)[b];
+    float l1[1] = {(float)fma(c1, xb, c0)}, g1[1];
+    propagators32<1>(l1, g1, kmax, sm, P);
+    const double A2 = fma(-c1, xb * ca, c0);
+    const double B2 = -c1 * (kc(r.ang.xs)[b] * sa);
+    Kahan32 acc{0.0f, 0.0f};
+    int c = 0;
+    for (; c + FRG_ILP <= nphi; c += FRG_ILP) {
+        float l2[FRG_ILP], G[FRG_ILP];
 #pragma unroll
-            for (int w = 0; w < FRG_ILP; ++w)
-                l2[w] = (float)fmax(fma(B2, kc(r.phi.c)[c + w], A2), 1e-30);
-            propagators32<FRG_ILP>(l2, G, kmax, sm, P);
-            float blk = 0.0f;
+        for (int w = 0; w < FRG_ILP; ++w)
+            l2[w] = (float)fmax(fma(B2, kc(r.phi.c)[c + w], A2), 1e-30);
+        propagators32<FRG_ILP>(l2, G, kmax, sm, P);
+        float blk = 0.0f;
 #pragma unroll
-            for (int w = 0; w < FRG_ILP; ++w) blk = fmaf(kc(r.phi.wf)[c + w], G[w], blk);
-            acc.add(blk);
-        }
-        for (; c < nphi; ++c) {
-            float l2[1] = {(float)fmax(fma(B2, kc(r.phi.c)[c], A2), 1e-30)}, G[1];
-            propagators32<1>(l2, G, kmax, sm, P);
-            acc.add(kc(r.phi.wf)[c] * G[0]);
-        }
-        const double inner = (double)acc.s - (double)acc.c;
-        mid = fma((double)kc(r.ang.xw)[b] * (double)g1[0], inner, mid);
+        for (int w = 0; w < FRG_ILP; ++w) blk = fmaf(kc(r.phi.wf)[c + w], G[w], blk);
+        acc.add(blk);
     }
-    return t.wg * (mid * (inv_k2 * inv_k2));
+    for (; c < nphi; ++c) {
+        float l2[1] = {(float)fmax(fma(B2, kc(r.phi.c)[c], A2), 1e-30)}, G[1];
+        propagators32<1>(l2, G, kmax, sm, P);
+        acc.add(kc(r.phi.wf)[c] * G[0]);
+    }
+    inner = (double)acc.s - (double)acc.c;
+    t = (double)kc(r.ang.xw)[b] * (double)g1[0];
+}
+
+// Contribution of (e, a) to the three-point integral (without the global prefactor), the cos1
+// nodes shared by lx adjacent lanes (lx = 1: one lane takes them all).  In rounds of lx
+// consecutive nodes each lane evaluates one; the round's first lane pulls the (t, inner) pairs
+// across lanes and folds them into mid in cos1 order, so mid is the same sequence of fused
+// multiply-adds for every lx.  All lanes of a wavefront call this together when lx > 1 (the
+// cross-lane pulls need them); act marks the lanes with a point and radial node to evaluate.
+template <int PREC>
+__device__ __forceinline__ double contrib_three(const ReqDev &r, const Smem &sm, int a, double p,
+                                                double ca, double sa, double m2, double inv_k2,
+                                                float &kmax, bool act, int sx, int lx) {
+    double wg = 0.0, c0 = 0.0, c1 = 0.0;
+    Par32 P;
+    if (act) {
+        const RadialTerm t = radial64(r, sm, a, p, m2);
+        wg = t.wg;
+        c0 = t.c0 * inv_k2;
+        c1 = t.c1 * inv_k2;
+        if (PREC == 1) P = par32(r, m2, inv_k2);
+    }
+    const double m2h = m2 * inv_k2;
+    const int nx = r.n_x;
+    const int xbase = (int)threadIdx.x & ~(lx - 1);
+    double mid = 0.0;
+    for (int j0 = 0; j0 < nx; j0 += lx) {
+        const int b = j0 + sx;
+        double tb = 0.0, ib = 0.0;
+        if (act && b < nx) {
+            if (PREC == 0)
+                xterm64(r, sm, b, c0, c1, ca, sa, m2h, tb, ib);
+            else
+                xterm32(r, sm, P, b, c0, c1, ca, sa, kmax, tb, ib);
+        }
+        if (lx == 1) {
+            mid = fma(tb, ib, mid);
+        } else {
+            const int nk = min(lx, nx - j0);
+            for (int k = 0; k < nk; ++k)
+                mid = fma(__shfl(tb, xbase + k), __shfl(ib, xbase + k), mid);
+        }
+    }
+    return wg * (mid * (inv_k2 * inv_k2));
 }
 
 // float32 form's stated relative error bound per result (u = 2^-24, kappa = largest float32
@@ -653,11 +685,15 @@ template <int FAM, int PREC>
 __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int et, int chunk,
                                             double *__restrict__ contrib,
                                             unsigned *__restrict__ counters) {
-    const int lq = 1 << r.lq_log2;
-    const int le = kWave >> r.lq_log2;
+    // lanes per point = lq (radial) x lx (cos1, three-point only); lane = (point, sq, sx)
+    const int lxl = (FAM == 3) ? r.lx_log2 : 0;
+    const int lpl = r.lq_log2 + lxl;
+    const int lq = 1 << r.lq_log2, lx = 1 << lxl;
+    const int le = kWave >> lpl;
     const int lane = (int)threadIdx.x;
-    const int el = lane >> r.lq_log2;
-    const int sub = lane & (lq - 1);
+    const int el = lane >> lpl;
+    const int sub = lane & ((1 << lpl) - 1);
+    const int sq = sub >> lxl, sx = sub & (lx - 1);
     const int e = et * le + el;
     const bool valid = e < r.n_ext;
     const int a0 = (int)(((long long)r.n_q * chunk) / r.chunks);
@@ -673,30 +709,33 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
         m2 = lane_m2(r, e);
         if (FAM == 3) sincos(r.ext[r.n_ext + e], &sa, &ca);
     }
-    auto node = [&](int a) -> double {
-        if (PREC == 0)
-            return (FAM == 2) ? contrib_two64(r, sm, a, p, m2, inv_k2)
-                              : contrib_three64(r, sm, a, p, ca, sa, m2, inv_k2);
-        return (FAM == 2) ? contrib_two32(r, sm, a, p, m2, inv_k2, kmax)
-                          : contrib_three32(r, sm, a, p, ca, sa, m2, inv_k2, kmax);
+    // contribution of radial node a (valid in the point's sx == 0 lanes); every lane of the
+    // wavefront calls it together, lanes without work pass act = false
+    auto node = [&](int a, bool act) -> double {
+        if (FAM == 3)
+            return contrib_three<PREC>(r, sm, act ? a : 0, p, ca, sa, m2, inv_k2, kmax, act, sx,
+                                       lx);
+        if (!act) return 0.0;
+        return (PREC == 0) ? contrib_two64(r, sm, a, p, m2, inv_k2)
+                           : contrib_two32(r, sm, a, p, m2, inv_k2, kmax);
     };
     if (r.chunks == 1) {
-        // The wavefront holds every radial node of its points.  The lq lanes of a point take
-        // rounds of lq consecutive radial nodes; after each round the point's first lane pulls
-        // the round's values across lanes and adds them in radial order -- the same sequence
-        // of additions as the radial sum of chunked tiles (identical bits), with no scratch
-        // stores, no barrier and no device-scope fence (an L2 writeback and invalidate on a
-        // multi-XCD part).
-        const int base = lane & ~(lq - 1);
+        // The wavefront holds every radial node of its points.  The lq radial sub-lanes of a
+        // point take rounds of lq consecutive radial nodes; after each round the point's first
+        // lane pulls the round's values across lanes and adds them in radial order -- the same
+        // sequence of additions as the radial sum of chunked tiles (identical bits), with no
+        // scratch stores, no barrier and no device-scope fence (an L2 writeback and invalidate
+        // on a multi-XCD part).
+        const int base = lane & ~((1 << lpl) - 1);
         double sum = 0.0;
         for (int r0 = 0; r0 < r.n_q; r0 += lq) {
-            const int a = r0 + sub;
-            const double v = (valid && a < r.n_q) ? node(a) : 0.0;
+            const int a = r0 + sq;
+            const double v = node(a, valid && a < r.n_q);
             const int nk = min(lq, r.n_q - r0);
-            for (int k = 0; k < nk; ++k) sum += __shfl(v, base + k);
+            for (int k = 0; k < nk; ++k) sum += __shfl(v, base + k * lx);
         }
         if (PREC == 1) {
-            for (int o = 1; o < lq; o <<= 1) kmax = fmaxf(kmax, __shfl_xor(kmax, o));
+            for (int o = 1; o < (1 << lpl); o <<= 1) kmax = fmaxf(kmax, __shfl_xor(kmax, o));
         }
         if (valid && sub == 0) {
             r.out[e] = r.pref * sum;
@@ -704,10 +743,13 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
         }
         return;
     }
-    if (valid) {
-        for (int a = a0 + sub; a < a1; a += lq) blk[(long long)a * r.n_ext + e] = node(a);
-        if (PREC == 1) atomicMax(&kslot[e], __float_as_uint(kmax));
+    for (int r0 = a0; r0 < a1; r0 += lq) {
+        const int a = r0 + sq;
+        const bool act = valid && a < a1;
+        const double v = node(a, act);
+        if (act && sx == 0) blk[(long long)a * r.n_ext + e] = v;
     }
+    if (valid && PREC == 1) atomicMax(&kslot[e], __float_as_uint(kmax));
     // publish the contributions, then count this chunk
     __threadfence();
     __syncthreads();

@@ -212,6 +212,12 @@ TileShape heuristic_shape(const frg_integral_desc &d, int n_ext, int target_wave
         ext_tiles = (n_ext + le - 1) / le;
     }
     s.lq_log2 = ilog2(kWave / le);
+    // three-point: then share the cos1 nodes of a radial node among lanes as well
+    while (d.family == 3 && ext_tiles < target_waves && le > 1 && (2 << s.lx_log2) <= d.n_x) {
+        le /= 2;
+        ++s.lx_log2;
+        ext_tiles = (n_ext + le - 1) / le;
+    }
     int lq = 1 << s.lq_log2;
     int max_chunks = (d.n_q + lq - 1) / lq;  // at least one radial node per lane and chunk
     // chunks only when even the narrowest tiles leave the chip mostly idle
@@ -262,8 +268,9 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
     r.precision = d.precision;
     r.n_ext = b.n_ext;
     r.lq_log2 = d.family == 1 ? 0 : shape.lq_log2;
+    r.lx_log2 = d.family == 3 ? shape.lx_log2 : 0;
     r.chunks = d.family == 1 ? 1 : shape.chunks;
-    int le = kWave >> r.lq_log2;
+    int le = kWave >> (r.lq_log2 + r.lx_log2);
     r.ext_tiles = (b.n_ext + le - 1) / le;
     r.k = d.k;
     r.k2 = d.k * d.k;
@@ -364,7 +371,10 @@ std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out) {
         const ReqDev &r = reqs[i];
         lds = std::max(lds, lds_bytes_for(r));
         int lq = 1 << r.lq_log2;
-        double inner = r.family == 1 ? 1.0 : (double)r.n_x * (r.family == 3 ? r.n_phi : 1);
+        double inner = r.family == 1 ? 1.0
+                       : r.family == 2
+                           ? (double)r.n_x
+                           : std::ceil((double)r.n_x / (1 << r.lx_log2)) * r.n_phi;
         for (int et = 0; et < r.ext_tiles; ++et)
             for (int ch = 0; ch < r.chunks; ++ch) {
                 int a0 = (int)(((long long)r.n_q * ch) / r.chunks);
@@ -498,13 +508,19 @@ frg_status frg_context_create(int device, size_t hbm_budget_bytes, frg_context *
     FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
     const char *tp = std::getenv("FRG_AUTOTUNE_CACHE");
     if (tp) {
-        // lines: family precision n_q n_x n_phi n_ext target lq_log2 chunks
+        // lines: family precision n_q n_x n_phi n_ext target lq_log2 chunks [lx_log2]
         ctx->tune_path = tp;
         std::ifstream f(tp);
-        std::vector<int> v(9);
-        while (f && (f >> v[0] >> v[1] >> v[2] >> v[3] >> v[4] >> v[5] >> v[6] >> v[7] >> v[8])) {
-            if (v[7] < 0 || v[7] > 4 || v[8] < 1 || v[8] > FRG_MAX_NODES) continue;
-            ctx->tuned[std::vector<int>(v.begin(), v.begin() + 7)] = TileShape{v[7], v[8]};
+        std::string line;
+        while (std::getline(f, line)) {
+            std::istringstream ls(line);
+            std::vector<int> v;
+            int x;
+            while (ls >> x) v.push_back(x);
+            if (v.size() != 9 && v.size() != 10) continue;
+            const int lx = v.size() == 10 ? v[9] : 0;
+            if (v[7] < 0 || lx < 0 || v[7] + lx > 6 || v[8] < 1 || v[8] > FRG_MAX_NODES) continue;
+            ctx->tuned[std::vector<int>(v.begin(), v.begin() + 7)] = TileShape{v[7], v[8], lx};
         }
     }
     *out = ctx.release();
@@ -567,6 +583,11 @@ frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const f
         const int max_chunks = (desc->n_q + (1 << lq) - 1) >> lq;
         for (int ch = 1; ch <= max_chunks; ch *= 2) cands.push_back(TileShape{lq, ch});
         if ((max_chunks & (max_chunks - 1)) != 0) cands.push_back(TileShape{lq, max_chunks});
+        // three-point: cos1 nodes shared among lanes as well (single radial chunk)
+        for (int lx = 1; desc->family == 3 && lq + lx <= 6 && (1 << lx) <= desc->n_x; ++lx) {
+            if ((kWave >> (lq + lx)) / 2 >= batch->n_ext && lq + lx > 0) continue;
+            cands.push_back(TileShape{lq, 1, lx});
+        }
     }
     cands.push_back(heuristic_shape(*desc, batch->n_ext, target));
     hipEvent_t e0, e1;
@@ -599,7 +620,7 @@ frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const f
             if (lf)
                 lf << desc->family << ' ' << desc->precision << ' ' << desc->n_q << ' '
                    << desc->n_x << ' ' << desc->n_phi << ' ' << batch->n_ext << ' ' << c.lq_log2
-                   << ' ' << c.chunks << ' ' << t_best << '\n';
+                   << ' ' << c.chunks << ' ' << c.lx_log2 << ' ' << t_best << '\n';
         }
         if (t_best < best) {
             best = t_best;
@@ -620,7 +641,8 @@ frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const f
         std::ofstream f(ctx->tune_path, std::ios::app);
         if (f) {
             for (int v : key) f << v << ' ';
-            f << best_shape.lq_log2 << ' ' << best_shape.chunks << '\n';
+            f << best_shape.lq_log2 << ' ' << best_shape.chunks << ' ' << best_shape.lx_log2
+              << '\n';
         }
     }
     return FRG_OK;

@@ -86,8 +86,9 @@ struct Scratch {
 
 // Tile shape of one request for the vertex families (the LPA family always uses lanes = points).
 struct TileShape {
-    int lq_log2 = 0;
-    int chunks = 1;
+    int lq_log2 = 0;  // lanes per point over radial nodes (log2)
+    int chunks = 1;   // radial chunks (separate workgroups) per external tile
+    int lx_log2 = 0;  // lanes per point over cos1 nodes (log2; three-point only)
 };
 
 struct FlowGraph;

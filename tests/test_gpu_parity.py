@@ -418,12 +418,17 @@ def test_tile_shapes_give_identical_bits(env, tmp_path, monkeypatch, family, pre
     target = 16 * torch.cuda.get_device_properties(0).multi_processor_count
     te, tm, tz = _d(torch, ext), _d(torch, m2), _d(torch, Z)
     results = []
-    # (lanes-per-point log2, radial chunks): one, several and the maximum number of chunks;
-    # 8, 16 and 64 lanes leave a ragged last radial round (13 nodes)
-    shapes = [(0, 1), (0, 13), (1, 3), (2, 1), (3, 1), (3, 2), (4, 1), (6, 1)]
-    for lq, ch in shapes:
-        cache = tmp_path / f"shape_{lq}_{ch}.txt"
-        cache.write_text(f"{family} {precision} {n_q} {n_x} {n_phi} {n} {target} {lq} {ch}\n")
+    # (radial lanes per point log2, radial chunks, cos1 lanes log2): one, several and the
+    # maximum number of chunks; 8, 16 and 64 radial lanes leave a ragged last radial round (13
+    # nodes); three-point also shares the 6 cos1 nodes among 2, 4 and 8 lanes (ragged), up to
+    # 64 lanes per point, alone and with radial chunks
+    shapes = [(0, 1, 0), (0, 13, 0), (1, 3, 0), (2, 1, 0), (3, 1, 0), (3, 2, 0), (4, 1, 0),
+              (6, 1, 0)]
+    if family == 3:
+        shapes += [(0, 1, 1), (0, 1, 3), (2, 1, 2), (4, 1, 2), (3, 1, 3), (1, 4, 2)]
+    for lq, ch, lx in shapes:
+        cache = tmp_path / f"shape_{lq}_{ch}_{lx}.txt"
+        cache.write_text(f"{family} {precision} {n_q} {n_x} {n_phi} {n} {target} {lq} {ch} {lx}\n")
         monkeypatch.setenv("FRG_AUTOTUNE_CACHE", str(cache))
         ctx = frg.Context(0)
         try:
