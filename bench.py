@@ -305,7 +305,8 @@ def secondary(torch, frg, wl, ctx):
         "gnodes_per_s": round(nodes / (ms32 * 1e-3) / 1e9, 2),
         "max_rel_err_vs_fp64": float(rel.max()), "median_rel_err_vs_fp64": float(np.median(rel)),
         "max_stated_bound": float(e32.max().item()), "near_pole_tau": 0.1}
-    # right-hand-side latency (graph replays): one LPA RHS and one two-point RHS
+    # right-hand-side latency: one LPA, two-point and three-point RHS per call, the plan's kernels
+    # launched directly (default) and replayed as a captured HIP graph (FRG_FLOW_GRAPH=1)
     log("bench: RHS latency")
     lat = {}
     rho = wl.lpa_rho_grid()
@@ -313,23 +314,29 @@ def secondary(torch, frg, wl, ctx):
     st = _dev(torch, -0.3 + rho)
     du = torch.empty_like(st)
     dl = frg.make_desc(1, wl.LPA_NQ, wl.LPA_QMAX)
-    lat["lpa_rhs"] = _latency(torch, lambda: ctx.flow_rhs(dl, st, trho, du, n_comp=4,
-                                                           m2_floor=-0.9))
     p, m2, Z = wl.two_point()
     tp, tZ = _dev(torch, p), _dev(torch, Z)
     s2 = torch.full((p.size,), m2, dtype=torch.float64, device="cuda")
     d2 = torch.empty_like(s2)
     dd = frg.make_desc(2, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX)
-    lat["two_point_rhs"] = _latency(torch, lambda: ctx.flow_rhs(dd, s2, tp, d2, Z=tZ,
-                                                                m2_floor=-0.9, coef=1.0))
     P, A, m3, Z3 = wl.three_point()
     tg3, tZ3 = _dev(torch, np.concatenate([P, A])), _dev(torch, Z3)
     s3 = _dev(torch, m3)
     d3o = torch.empty_like(s3)
     d3 = frg.make_desc(3, wl.THREE_NQ, wl.THREE_QMAX, n_x=wl.THREE_NX, n_phi=wl.THREE_NPHI)
-    lat["three_point_rhs"] = _latency(torch, lambda: ctx.flow_rhs(d3, s3, tg3, d3o, Z=tZ3,
-                                                                  m2_floor=-0.9, coef=1.0),
-                                      n=500)
+    os.environ["FRG_FLOW_GRAPH"] = "1"
+    gctx = frg.Context(0)
+    del os.environ["FRG_FLOW_GRAPH"]
+    for mode, c in (("", ctx), ("_graph", gctx)):
+        lat["lpa_rhs" + mode] = _latency(torch, lambda: c.flow_rhs(dl, st, trho, du, n_comp=4,
+                                                                   m2_floor=-0.9), n=10000)
+        lat["two_point_rhs" + mode] = _latency(torch, lambda: c.flow_rhs(dd, s2, tp, d2, Z=tZ,
+                                                                         m2_floor=-0.9, coef=1.0),
+                                               n=10000)
+        lat["three_point_rhs" + mode] = _latency(
+            torch, lambda: c.flow_rhs(d3, s3, tg3, d3o, Z=tZ3, m2_floor=-0.9, coef=1.0), n=2000)
+    torch.cuda.synchronize()
+    gctx.close()
     ex["rhs_latency_us"] = lat
     log("bench: serving")
     ex["serving"] = serving(torch, frg, wl, ctx)

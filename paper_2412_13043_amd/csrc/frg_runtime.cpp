@@ -457,11 +457,28 @@ frg_status relaunch_multi(Scratch *sc, hipStream_t s) {
 // Flow right-hand sides, captured as HIP graphs
 // ---------------------------------------------------------------------------------------------
 struct FlowGraph {
-    hipGraphExec_t exec = nullptr;
+    hipGraphExec_t exec = nullptr;  // captured plan (graph mode), else launched directly
     hipGraph_t graph = nullptr;
     DeviceBuffer work;      // LPA: m2 [2n], fac [2n], I [2n]
     DeviceBuffer contrib;
     DeviceBuffer counters;
+    ReqDev r{};             // the integrals of the right-hand side
+    int family = 0, n = 0, n_comp = 0;
+    const double *grid = nullptr, *state = nullptr;
+    double m2_floor = 0.0;
+    double *dstate_dt = nullptr;
+    // state -> masses -> integrals -> assembly on stream s
+    hipError_t enqueue(hipStream_t s) const {
+        double *m2buf = (double *)work.ptr, *fac = m2buf ? m2buf + 2 * n : nullptr;
+        double *Ibuf = fac ? fac + 2 * n : nullptr;
+        hipError_t e = hipSuccess;
+        if (family == 1) e = launch_lpa_state(n, grid, state, m2_floor, m2buf, fac, s);
+        if (e == hipSuccess)
+            e = launch_batch(&r, nullptr, tile_count(r), lds_bytes_for(r), (double *)contrib.ptr,
+                             (unsigned *)counters.ptr, s);
+        if (e == hipSuccess && family == 1) e = launch_lpa_assemble(n, n_comp, Ibuf, fac, dstate_dt, s);
+        return e;
+    }
     ~FlowGraph() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -506,6 +523,8 @@ frg_status frg_context_create(int device, size_t hbm_budget_bytes, frg_context *
         FRG_HIP_CHECK(hipMemcpy(ctx->ones.ptr, ones, sizeof ones, hipMemcpyHostToDevice));
     }
     FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
+    const char *fg = std::getenv("FRG_FLOW_GRAPH");
+    ctx->flow_graphs = fg && fg[0] == '1';
     const char *tp = std::getenv("FRG_AUTOTUNE_CACHE");
     if (tp) {
         // lines: family precision n_q n_x n_phi n_ext target lq_log2 chunks [lx_log2]
@@ -790,26 +809,35 @@ frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
         FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
         r.contrib_base = 0;
         r.ctr_base = 0;
-        FRG_HIP_CHECK(hipStreamBeginCapture(ctx->aux, hipStreamCaptureModeThreadLocal));
-        hipError_t e1 = hipSuccess;
-        if (desc->family == 1)
-            e1 = launch_lpa_state(n, state->grid, state->state, state->m2_floor, m2buf, fac,
-                                  ctx->aux);
-        if (e1 == hipSuccess)
-            e1 = launch_batch(&r, nullptr, tile_count(r), lds_bytes_for(r),
-                              (double *)g->contrib.ptr, (unsigned *)g->counters.ptr, ctx->aux);
-        if (e1 == hipSuccess && desc->family == 1)
-            e1 = launch_lpa_assemble(n, state->n_comp, Ibuf, fac, dstate_dt, ctx->aux);
-        hipError_t e2 = hipStreamEndCapture(ctx->aux, &g->graph);
-        if (e1 != hipSuccess || e2 != hipSuccess) {
-            set_error("graph capture failed: %s / %s", hipGetErrorString(e1),
-                      hipGetErrorString(e2));
-            return FRG_E_DEVICE;
+        g->r = r;
+        g->family = desc->family;
+        g->n = n;
+        g->n_comp = state->n_comp;
+        g->grid = state->grid;
+        g->state = state->state;
+        g->m2_floor = state->m2_floor;
+        g->dstate_dt = dstate_dt;
+        (void)m2buf;
+        (void)fac;
+        (void)Ibuf;
+        if (ctx->flow_graphs) {
+            FRG_HIP_CHECK(hipStreamBeginCapture(ctx->aux, hipStreamCaptureModeThreadLocal));
+            const hipError_t e1 = g->enqueue(ctx->aux);
+            const hipError_t e2 = hipStreamEndCapture(ctx->aux, &g->graph);
+            if (e1 != hipSuccess || e2 != hipSuccess) {
+                set_error("graph capture failed: %s / %s", hipGetErrorString(e1),
+                          hipGetErrorString(e2));
+                return FRG_E_DEVICE;
+            }
+            FRG_HIP_CHECK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
         }
-        FRG_HIP_CHECK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
         it = ctx->graphs.emplace(key, std::move(g)).first;
     }
-    FRG_HIP_CHECK(hipGraphLaunch(it->second->exec, stream));
+    if (it->second->exec) {
+        FRG_HIP_CHECK(hipGraphLaunch(it->second->exec, stream));
+    } else {
+        FRG_HIP_CHECK(it->second->enqueue(stream));
+    }
     return FRG_OK;
 }
 

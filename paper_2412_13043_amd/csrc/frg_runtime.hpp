@@ -107,7 +107,8 @@ struct frg_context {
     std::map<int, std::unique_ptr<frg::AngleEntry>> cos1;
     std::map<int, std::unique_ptr<frg::PhiEntry>> phi;
     std::map<hipStream_t, std::unique_ptr<frg::Scratch>> scratch;
-    std::map<std::vector<long long>, std::unique_ptr<frg::FlowGraph>> graphs;
+    std::map<std::vector<long long>, std::unique_ptr<frg::FlowGraph>> graphs;  // flow RHS plans
+    bool flow_graphs = false;  // replay flow RHS plans as captured HIP graphs (FRG_FLOW_GRAPH=1)
     std::map<std::vector<int>, frg::TileShape> tuned;  // autotuned shapes (loaded/saved on disk)
     std::string tune_path;
 };

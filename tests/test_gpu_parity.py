@@ -290,8 +290,25 @@ def test_two_point_batch_256_multi_sampled(env):
 # ------------------------------------------------------------------------------------------
 # Flow right-hand sides (graph-captured), replayed with eager work in between
 # ------------------------------------------------------------------------------------------
-def test_flow_rhs_lpa_and_graph_replays(env):
+@pytest.fixture(params=["direct", "graph"])
+def flow_ctx(request, env, monkeypatch):
+    """The fixture's context (plans launched directly) or one that replays captured graphs."""
     frg, ctx, torch = env
+    if request.param == "direct":
+        yield ctx
+        return
+    monkeypatch.setenv("FRG_FLOW_GRAPH", "1")  # read when a context is created
+    gctx = frg.Context(0)
+    try:
+        yield gctx
+    finally:
+        torch.cuda.synchronize()
+        gctx.close()
+
+
+def test_flow_rhs_lpa_and_graph_replays(env, flow_ctx):
+    frg, _, torch = env
+    ctx = flow_ctx
     rho = wl.lpa_rho_grid()
     trho = _d(torch, rho)
     desc = frg.make_desc(1, wl.LPA_NQ, wl.LPA_QMAX)
@@ -312,8 +329,9 @@ def test_flow_rhs_lpa_and_graph_replays(env):
 
 
 @pytest.mark.parametrize("family", [2, 3])
-def test_flow_rhs_vertex(env, family):
-    frg, ctx, torch = env
+def test_flow_rhs_vertex(env, flow_ctx, family):
+    frg, _, torch = env
+    ctx = flow_ctx
     rng = np.random.default_rng(family)
     n = 96
     p = 10 ** rng.uniform(-3, 2, n)
