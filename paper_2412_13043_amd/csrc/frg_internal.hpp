@@ -78,11 +78,9 @@ hipError_t launch_batch(const ReqDev *req_dev_host, const ReqDev *req_dev_ptr, i
 hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, const TileDev *tiles_dev,
                         int n_tiles, int grid, int lds_bytes, double *contrib,
                         unsigned *counters, unsigned *work_ctr, hipStream_t s);
-hipError_t launch_lpa_state(int n, const double *rho, const double *u, double m2_floor,
-                            double *m2_out, double *fac_out, hipStream_t s);
-hipError_t launch_lpa_assemble(int n, int n_comp, const double *I, const double *fac,
-                               double *dudt, hipStream_t s);
 hipError_t launch_fill_zero_u32(unsigned *p, size_t n, hipStream_t s);
+hipError_t launch_lpa_rhs(const ReqDev &r, int n, int n_comp, const double *rho, const double *u,
+                          double m2_floor, double *dudt, hipStream_t s);
 hipError_t launch_log_table(double2 *out, hipStream_t s);
 int multi_blocks_per_cu(int fam, int prec, int lds_bytes);
 int multi_grid(int n_tiles, int fam, int prec, int lds_bytes, int num_cus);

@@ -640,11 +640,10 @@ __device__ __forceinline__ void bind_smem(Smem &sm, double2 *lds, int nZ, float 
 }
 
 // LPA: one lane per external point, the whole radial sum in one lane, no scratch.
+// One LPA integral pref * sum_a W_a / (A_a + m2)^2 with A_a = k^2 (q^_a^2 + R^_a); the float32
+// form states (16 + 3 kappa) 2^-24 in err.
 template <int PREC>
-__device__ __forceinline__ void tile_lpa(const ReqDev &r, int et) {
-    const int e = et * kWave + (int)threadIdx.x;
-    if (e >= r.n_ext) return;
-    const double m2 = lane_m2(r, e);
+__device__ __forceinline__ double lpa_integral(const ReqDev &r, double m2, double &err) {
     const int nq = r.n_q;
     if (PREC == 0) {
         double acc = 0.0;
@@ -653,30 +652,39 @@ __device__ __forceinline__ void tile_lpa(const ReqDev &r, int et) {
             const double g = fm::rcp_nr(fma(r.k2, fma(qh, qh, kc(r.rad.R)[a]), m2));
             acc = fma(kc(r.rad.W)[a], g * g, acc);
         }
-        r.out[e] = r.pref * acc;
-        if (r.err) r.err[e] = 0.0;
-    } else {
-        // float32 terms, compensated float32 sum; near-pole denominators in float64
-        const float k2f = (float)r.k2, m2f = (float)m2, tau = (float)r.tau;
-        Kahan32 acc{0.0f, 0.0f};
-        float kmax = 1.0f;
-        for (int a = 0; a < nq; ++a) {
-            const float qh = kc(r.rad.qf)[a];
-            const float A = k2f * fmaf(qh, qh, kc(r.rad.Rf)[a]);
-            const float t = A + m2f;
-            float g;
-            if (t < tau * (A + fabsf(m2f))) {
-                const double qd = kc(r.rad.q)[a];
-                g = (float)fm::rcp_nr(fma(r.k2, fma(qd, qd, kc(r.rad.R)[a]), m2));
-            } else {
-                g = __builtin_amdgcn_rcpf(t);
-                kmax = fmaxf(kmax, (A + fabsf(m2f)) * g);
-            }
-            acc.add(kc(r.rad.Wf)[a] * (g * g));
-        }
-        r.out[e] = r.pref * ((double)acc.s - (double)acc.c);
-        if (r.err) r.err[e] = (16.0 + 3.0 * (double)kmax) * 5.9604644775390625e-8;
+        err = 0.0;
+        return r.pref * acc;
     }
+    // float32 terms, compensated float32 sum; near-pole denominators in float64
+    const float k2f = (float)r.k2, m2f = (float)m2, tau = (float)r.tau;
+    Kahan32 acc{0.0f, 0.0f};
+    float kmax = 1.0f;
+    for (int a = 0; a < nq; ++a) {
+        const float qh = kc(r.rad.qf)[a];
+        const float A = k2f * fmaf(qh, qh, kc(r.rad.Rf)[a]);
+        const float t = A + m2f;
+        float g;
+        if (t < tau * (A + fabsf(m2f))) {
+            const double qd = kc(r.rad.q)[a];
+            g = (float)fm::rcp_nr(fma(r.k2, fma(qd, qd, kc(r.rad.R)[a]), m2));
+        } else {
+            g = __builtin_amdgcn_rcpf(t);
+            kmax = fmaxf(kmax, (A + fabsf(m2f)) * g);
+        }
+        acc.add(kc(r.rad.Wf)[a] * (g * g));
+    }
+    err = (16.0 + 3.0 * (double)kmax) * 5.9604644775390625e-8;
+    return r.pref * ((double)acc.s - (double)acc.c);
+}
+
+template <int PREC>
+__device__ __forceinline__ void tile_lpa(const ReqDev &r, int et) {
+    const int e = et * kWave + (int)threadIdx.x;
+    if (e >= r.n_ext) return;
+    double err;
+    const double v = lpa_integral<PREC>(r, lane_m2(r, e), err);
+    r.out[e] = v;
+    if (r.err) r.err[e] = err;
 }
 
 // Vertex families: lanes = (external point, radial sub-lane); contributions to scratch; the last
@@ -957,49 +965,44 @@ hipError_t launch_log_table(double2 *out, hipStream_t s) {
 // --------------------------------------------------------------------------------------------
 // u', u'' at grid point i from the quadratic through three neighbouring points (Newton divided
 // differences; the stencil is shifted inwards at the two ends).
-__global__ void __launch_bounds__(64) lpa_state_kernel(int n, const double *__restrict__ rho,
-                                                       const double *__restrict__ u,
-                                                       double m2_floor, double *m2_out,
-                                                       double *fac_out) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// The whole LPA right-hand side in one launch, one thread per grid point: u' and u'' from the
+// quadratic through three neighbouring grid points (one-sided at the ends), the sigma and pi
+// masses floored at m2_floor, their two integrals (the same operations as the LPA tile) and the
+// flux-form assembly du/dt = 1/2 [I(m_s^2) (3u' + 2 rho u'') + (N - 1) I(m_p^2) u'].
+template <int PREC>
+__global__ void __launch_bounds__(64) lpa_rhs_kernel(ReqDev r, int n, int n_comp,
+                                                     const double *__restrict__ rho,
+                                                     const double *__restrict__ u,
+                                                     double m2_floor, double *dudt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int c = i == 0 ? 1 : (i == n - 1 ? n - 2 : i);
-    double x0 = rho[c - 1], x1 = rho[c], x2 = rho[c + 1];
-    double f0 = u[c - 1], f1 = u[c], f2 = u[c + 1];
-    double d01 = (f1 - f0) / (x1 - x0);
-    double d12 = (f2 - f1) / (x2 - x1);
-    double d012 = (d12 - d01) / (x2 - x0);
-    double xi = rho[i];
-    double up = d01 + d012 * ((xi - x0) + (xi - x1));
-    double upp = 2.0 * d012;
-    double ms = u[i] + 2.0 * xi * up;
-    double mp = u[i];
-    m2_out[i] = fmax(ms, m2_floor);
-    m2_out[n + i] = fmax(mp, m2_floor);
-    fac_out[i] = 3.0 * up + 2.0 * xi * upp;
-    fac_out[n + i] = up;
+    const int c = i == 0 ? 1 : (i == n - 1 ? n - 2 : i);
+    const double x0 = rho[c - 1], x1 = rho[c], x2 = rho[c + 1];
+    const double f0 = u[c - 1], f1 = u[c], f2 = u[c + 1];
+    const double d01 = (f1 - f0) / (x1 - x0);
+    const double d12 = (f2 - f1) / (x2 - x1);
+    const double d012 = (d12 - d01) / (x2 - x0);
+    const double xi = rho[i];
+    const double up = d01 + d012 * ((xi - x0) + (xi - x1));
+    const double upp = 2.0 * d012;
+    const double ms = u[i] + 2.0 * xi * up;
+    const double mp = u[i];
+    const double fs = 3.0 * up + 2.0 * xi * upp;
+    const double fp = up;
+    double es, ep;
+    const double Is = lpa_integral<PREC>(r, fmax(ms, m2_floor), es);
+    const double Ip = lpa_integral<PREC>(r, fmax(mp, m2_floor), ep);
+    dudt[i] = 0.5 * (Is * fs + (double)(n_comp - 1) * Ip * fp);
 }
 
-__global__ void __launch_bounds__(64) lpa_assemble_kernel(int n, int n_comp,
-                                                          const double *__restrict__ I,
-                                                          const double *__restrict__ fac,
-                                                          double *dudt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    dudt[i] = 0.5 * (I[i] * fac[i] + (double)(n_comp - 1) * I[n + i] * fac[n + i]);
-}
-
-hipError_t launch_lpa_state(int n, const double *rho, const double *u, double m2_floor,
-                            double *m2_out, double *fac_out, hipStream_t s) {
-    hipLaunchKernelGGL(lpa_state_kernel, dim3((n + 63) / 64), dim3(64), 0, s, n, rho, u,
-                       m2_floor, m2_out, fac_out);
-    return hipGetLastError();
-}
-
-hipError_t launch_lpa_assemble(int n, int n_comp, const double *I, const double *fac,
-                               double *dudt, hipStream_t s) {
-    hipLaunchKernelGGL(lpa_assemble_kernel, dim3((n + 63) / 64), dim3(64), 0, s, n, n_comp, I,
-                       fac, dudt);
+hipError_t launch_lpa_rhs(const ReqDev &r, int n, int n_comp, const double *rho, const double *u,
+                          double m2_floor, double *dudt, hipStream_t s) {
+    if (r.precision == 0)
+        hipLaunchKernelGGL(lpa_rhs_kernel<0>, dim3((n + 63) / 64), dim3(64), 0, s, r, n, n_comp,
+                           rho, u, m2_floor, dudt);
+    else
+        hipLaunchKernelGGL(lpa_rhs_kernel<1>, dim3((n + 63) / 64), dim3(64), 0, s, r, n, n_comp,
+                           rho, u, m2_floor, dudt);
     return hipGetLastError();
 }
 

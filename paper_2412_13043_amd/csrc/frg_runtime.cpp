@@ -459,7 +459,6 @@ frg_status relaunch_multi(Scratch *sc, hipStream_t s) {
 struct FlowGraph {
     hipGraphExec_t exec = nullptr;  // captured plan (graph mode), else launched directly
     hipGraph_t graph = nullptr;
-    DeviceBuffer work;      // LPA: m2 [2n], fac [2n], I [2n]
     DeviceBuffer contrib;
     DeviceBuffer counters;
     ReqDev r{};             // the integrals of the right-hand side
@@ -467,17 +466,11 @@ struct FlowGraph {
     const double *grid = nullptr, *state = nullptr;
     double m2_floor = 0.0;
     double *dstate_dt = nullptr;
-    // state -> masses -> integrals -> assembly on stream s
+    // state -> masses -> integrals -> assembly on stream s (LPA: one fused kernel)
     hipError_t enqueue(hipStream_t s) const {
-        double *m2buf = (double *)work.ptr, *fac = m2buf ? m2buf + 2 * n : nullptr;
-        double *Ibuf = fac ? fac + 2 * n : nullptr;
-        hipError_t e = hipSuccess;
-        if (family == 1) e = launch_lpa_state(n, grid, state, m2_floor, m2buf, fac, s);
-        if (e == hipSuccess)
-            e = launch_batch(&r, nullptr, tile_count(r), lds_bytes_for(r), (double *)contrib.ptr,
-                             (unsigned *)counters.ptr, s);
-        if (e == hipSuccess && family == 1) e = launch_lpa_assemble(n, n_comp, Ibuf, fac, dstate_dt, s);
-        return e;
+        if (family == 1) return launch_lpa_rhs(r, n, n_comp, grid, state, m2_floor, dstate_dt, s);
+        return launch_batch(&r, nullptr, tile_count(r), lds_bytes_for(r), (double *)contrib.ptr,
+                            (unsigned *)counters.ptr, s);
     }
     ~FlowGraph() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -787,14 +780,9 @@ frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
         auto g = std::make_unique<FlowGraph>();
         TileShape shape = choose_shape(ctx, *desc, b.n_ext, 16 * ctx->num_cus);
         ReqDev r;
-        double *m2buf = nullptr, *fac = nullptr, *Ibuf = nullptr;
         if (desc->family == 1) {
-            FRG_HIP_CHECK(g->work.alloc(6 * (size_t)n * sizeof(double)));
-            m2buf = (double *)g->work.ptr;
-            fac = m2buf + 2 * n;
-            Ibuf = fac + 2 * n;
-            b.m2 = m2buf;
-            b.out = Ibuf;
+            // the fused kernel takes rules, prefactor and precision from r; masses come from
+            // the state inside it
             if ((st = make_request(ctx, *desc, b, shape, 1, 0.0, 1.0, &r)) != FRG_OK) return st;
         } else {
             if ((st = make_request(ctx, *desc, b, shape, 2, state->m2_floor, state->coef, &r)) !=
@@ -817,9 +805,6 @@ frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
         g->state = state->state;
         g->m2_floor = state->m2_floor;
         g->dstate_dt = dstate_dt;
-        (void)m2buf;
-        (void)fac;
-        (void)Ibuf;
         if (ctx->flow_graphs) {
             FRG_HIP_CHECK(hipStreamBeginCapture(ctx->aux, hipStreamCaptureModeThreadLocal));
             const hipError_t e1 = g->enqueue(ctx->aux);
