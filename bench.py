@@ -40,12 +40,18 @@ def log(msg):
 
 
 def kernel_source_sha():
+    """Hash of the device sources with line comments and blank lines removed (comment edits do
+    not change the kernels the traffic counters were taken on)."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in ("frg_kernels.hip", "frg_math.hpp", "frg_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2412_13043_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2412_13043_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = re.sub(r"//.*", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

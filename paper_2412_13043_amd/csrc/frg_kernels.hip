@@ -1,14 +1,15 @@
 // HIP kernels for gfx950 (CDNA4): quadrature rules, the per-tile loop-integral bodies of the
 // three integrand families in float64 and in the float32 precision form, the fused multi-request
-// consumer, and the LPA flow-state / assembly kernels.
+// consumer, and the fused LPA right-hand side.
 //
 // Work decomposition.  A workgroup is one 64-lane wavefront.  A tile is (request, external tile,
 // radial chunk).  For the LPA family one lane owns one external point and the whole radial sum.
-// For the vertex families a lane owns one (external point, radial node) pair at a time and
-// evaluates its whole inner angle sum in a fixed order; the resulting contribution is stored in a
-// [n_q][n_ext] scratch block and the last tile of an external tile adds the contributions in
-// radial order.  Each result therefore depends only on its own request, never on the tiling,
-// batch composition or launch shape.
+// For the vertex families the lanes of a point share its radial nodes (and, three-point, its
+// cos1 nodes); each (point, radial node) contribution is a fixed sequence of operations, and the
+// point's result adds the contributions in radial order -- within the wavefront by cross-lane
+// pulls when the tile holds every radial node, else through a [n_q][n_ext] scratch block summed
+// by the last chunk.  Each result therefore depends only on its own request, never on the
+// tiling, batch composition or launch shape.
 //
 // All device code is built with -ffp-contract=off: every fused multiply-add is written out with
 // fma(), so the operation sequence (and so the rounding) is fixed by the source.
@@ -708,7 +709,8 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
     const int a1 = (int)(((long long)r.n_q * (chunk + 1)) / r.chunks);
     const double inv_k2 = 1.0 / r.k2;
     double *blk = contrib + r.contrib_base;
-    // per-point slots after the tile counters (zero at rest): largest float32 amplification
+    // chunked tiles: per-point slots after the tile counters (zero at rest, reset by the last
+    // chunk): largest float32 amplification
     unsigned *kslot = counters + r.ctr_base + r.ext_tiles;
     float kmax = 1.0f;
     double p = 0.0, m2 = 0.0, ca = 1.0, sa = 0.0;

@@ -63,11 +63,13 @@ struct PhiEntry {
 };
 
 // Per-stream scratch: contribution blocks, per-external-tile counters, work counters, and the
-// request/tile tables of fused launches.  Counters are zero at rest (kernels reset them).
+// request/tile tables of fused launches.  Chunk counters are zero at rest (the last chunk of an
+// external tile resets its counter); the fused kernel's tile counter is cleared before each
+// launch.
 struct Scratch {
-    DeviceBuffer contrib;   // doubles
+    DeviceBuffer contrib;   // doubles (radially chunked requests)
     DeviceBuffer counters;  // u32, zero at rest
-    DeviceBuffer work;      // 2 x u32, zero at rest
+    DeviceBuffer work;      // 2 x u32: fused-launch tile counter
     DeviceBuffer reqs;      // ReqDev[]
     DeviceBuffer tiles;     // TileDev[]
     // pinned staging for the request/tile tables of fused launches; `staged` is recorded after

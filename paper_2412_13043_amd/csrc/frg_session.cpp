@@ -106,7 +106,7 @@ struct Slot {
     hipEvent_t done = nullptr;
     DeviceBuffer tables;    // ReqDev[] then TileDev[]
     DeviceBuffer counters;  // zeroed before each launch
-    DeviceBuffer work;      // fused-launch work counters, zero at rest
+    DeviceBuffer work;      // fused-launch tile counter (cleared ahead of each launch)
     void *host = nullptr;   // pinned staging: tables, inputs, outputs
     size_t host_bytes = 0;
     std::vector<SessReq *> reqs;
