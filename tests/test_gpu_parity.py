@@ -134,6 +134,68 @@ def test_two_point_big_table_and_rule(env):
     assert _rel(got, ref) <= TOL
 
 
+def test_maximum_node_counts(env):
+    # 1024 nodes (the largest rule) in each dimension in turn, every family
+    Z = wl.dressing_table(11)
+    m2 = np.array([0.7, -0.4, 1.9])
+    got = _run(env, 1, 1024, 6.0, m2=m2)
+    assert _rel(got, oracle.integrate(oracle.LPA, 1024, 6.0, m2=m2)) <= TOL
+    p = np.array([0.02, 1.3, 40.0])
+    got = _run(env, 2, 1024, 10.0, n_x=4, ext=p, m2=m2, Z=Z)
+    ref = oracle.integrate(oracle.TWO_POINT, 1024, 10.0, n_x=4, ext=p, m2=m2, Z=Z)
+    assert _rel(got, ref) <= TOL
+    alpha = np.array([0.0, 1.1, math.pi])
+    for n_q, n_x, n_phi in ((4, 4, 1024), (8, 1024, 2), (1024, 2, 2)):
+        got = _run(env, 3, n_q, 10.0, n_x=n_x, n_phi=n_phi, ext=np.concatenate([p, alpha]),
+                    m2=m2, Z=Z)
+        ref = oracle.integrate(oracle.THREE_POINT, n_q, 10.0, n_x=n_x, n_phi=n_phi,
+                               ext=(p, alpha), m2=m2, Z=Z)
+        assert _rel(got, ref) <= TOL, (n_q, n_x, n_phi)
+
+
+def test_multi_with_empty_and_ragged_batches(env):
+    # empty batches inside a fused launch are skipped; ragged sizes (1, 65, 130 points) match
+    # their single-batch results bitwise
+    frg, ctx, torch = env
+    rng = np.random.default_rng(77)
+    Z = _d(torch, wl.dressing_table(3))
+    descs, batches, outs, singles, keep = [], [], [], [], []
+    for fam, n in ((2, 0), (2, 1), (3, 65), (2, 0), (2, 130), (3, 0), (1, 65)):
+        if fam == 1:
+            desc = frg.make_desc(1, 32, 6.0)
+        elif fam == 2:
+            desc = frg.make_desc(2, 24, 10.0, n_x=12)
+        else:
+            desc = frg.make_desc(3, 12, 10.0, n_x=8, n_phi=6)
+        ext = None
+        if fam == 2:
+            ext = _d(torch, 10 ** rng.uniform(-3, 2, n))
+        elif fam == 3:
+            ext = _d(torch, np.concatenate([10 ** rng.uniform(-3, 2, n),
+                                            rng.uniform(0, math.pi, n)]))
+        m2 = _d(torch, rng.uniform(-0.5, 2.0, n))
+        out = torch.full((max(n, 1),), float("nan"), dtype=torch.float64, device="cuda")
+        batches.append(frg.make_batch(n, out, ext=ext, m2=m2, Z=Z if fam != 1 else None,
+                                      x_min=wl.Z_XMIN, x_max=wl.Z_XMAX))
+        descs.append(desc)
+        outs.append((out, n))
+        keep += [ext, m2]
+        if n:
+            single = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+            ctx.integrate(desc, single, ext=ext, m2=m2, Z=Z if fam != 1 else None,
+                          x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)
+            singles.append(single)
+        else:
+            singles.append(None)
+    ctx.integrate_multi(descs, batches)
+    torch.cuda.synchronize()
+    for (o, n), sgl in zip(outs, singles):
+        if n == 0:
+            assert torch.isnan(o).all()  # nothing written for an empty batch
+        else:
+            assert torch.equal(o[:n], sgl)
+
+
 # ------------------------------------------------------------------------------------------
 # Workload 3: three-point d = 4 (full launch shape, sampled outputs) and small full cases
 # ------------------------------------------------------------------------------------------
