@@ -79,6 +79,9 @@ hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, const TileDev
                         int n_tiles, int grid, int lds_bytes, double *contrib,
                         unsigned *counters, unsigned *work_ctr, hipStream_t s);
 hipError_t launch_fill_zero_u32(unsigned *p, size_t n, hipStream_t s);
+// radially chunked requests: radial sums after the integrand launch (no-op otherwise)
+hipError_t launch_finalize(const ReqDev &r, const double *contrib, unsigned *counters,
+                           hipStream_t s);
 hipError_t launch_lpa_rhs(const ReqDev &r, int n, int n_comp, const double *rho, const double *u,
                           double m2_floor, double *dudt, hipStream_t s);
 hipError_t launch_log_table(double2 *out, hipStream_t s);

@@ -709,9 +709,9 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
     const int a1 = (int)(((long long)r.n_q * (chunk + 1)) / r.chunks);
     const double inv_k2 = 1.0 / r.k2;
     double *blk = contrib + r.contrib_base;
-    // chunked tiles: per-point slots after the tile counters (zero at rest, reset by the last
-    // chunk): largest float32 amplification
-    unsigned *kslot = counters + r.ctr_base + r.ext_tiles;
+    // chunked tiles, float32 form: per-point slots of the largest amplification (zero at rest,
+    // reset by the finalize kernel), then one slot for the dressing table's relative step
+    unsigned *kslot = counters + r.ctr_base;
     float kmax = 1.0f;
     double p = 0.0, m2 = 0.0, ca = 1.0, sa = 0.0;
     if (valid) {
@@ -759,35 +759,30 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
         const double v = node(a, act);
         if (act && sx == 0) blk[(long long)a * r.n_ext + e] = v;
     }
-    if (valid && PREC == 1) atomicMax(&kslot[e], __float_as_uint(kmax));
-    // publish the contributions, then count this chunk
-    __threadfence();
-    __syncthreads();
-    __shared__ unsigned last;
-    if (lane == 0) {
-        unsigned old = atomicAdd(&counters[r.ctr_base + et], 1u);
-        last = (old == (unsigned)(r.chunks - 1)) ? 1u : 0u;
+    // the finalize kernel (a later launch on the same stream) adds the chunks in radial order
+    if (PREC == 1) {
+        if (valid) atomicMax(&kslot[e], __float_as_uint(kmax));
+        if (lane == 0) kslot[r.n_ext] = __float_as_uint(*sm.zslope);  // same value from every tile
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (lane < le) {
-        const int ef = et * le + lane;
-        if (ef < r.n_ext) {
-            // the fence above (acquire side) makes every chunk's contributions visible
-            const double s = radial_sum(blk, r.n_q, r.n_ext, ef);
-            r.out[ef] = r.pref * s;
-            if (PREC == 1) {
-                unsigned kb = __hip_atomic_load(&kslot[ef], __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-                if (r.err) r.err[ef] = fp32_bound(__uint_as_float(kb), *sm.zslope, r);
-                __hip_atomic_store(&kslot[ef], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else if (r.err) {
-                r.err[ef] = 0.0;
-            }
-        }
+}
+
+// Radially chunked requests: one thread per external point adds the [n_q][n_ext] contributions
+// in radial order (the same additions as the in-wavefront sum of single-chunk tiles) and states
+// the float32 bound from the amplification slots, which it returns to zero.
+__global__ void __launch_bounds__(64) finalize_kernel(ReqDev r, const double *contrib,
+                                                     unsigned *counters) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= r.n_ext) return;
+    const double s = radial_sum(contrib + r.contrib_base, r.n_q, r.n_ext, e);
+    r.out[e] = r.pref * s;
+    if (r.precision == 1) {
+        unsigned *kslot = counters + r.ctr_base;
+        if (r.err)
+            r.err[e] = fp32_bound(__uint_as_float(kslot[e]), __uint_as_float(kslot[r.n_ext]), r);
+        kslot[e] = 0u;
+    } else if (r.err) {
+        r.err[e] = 0.0;
     }
-    if (lane == 0) atomicExch(&counters[r.ctr_base + et], 0u);
 }
 
 // One request: tile = blockIdx.x -> (external tile, chunk).
@@ -995,6 +990,14 @@ __global__ void __launch_bounds__(64) lpa_rhs_kernel(ReqDev r, int n, int n_comp
     const double Is = lpa_integral<PREC>(r, fmax(ms, m2_floor), es);
     const double Ip = lpa_integral<PREC>(r, fmax(mp, m2_floor), ep);
     dudt[i] = 0.5 * (Is * fs + (double)(n_comp - 1) * Ip * fp);
+}
+
+hipError_t launch_finalize(const ReqDev &r, const double *contrib, unsigned *counters,
+                           hipStream_t s) {
+    if (r.family == 1 || r.chunks <= 1 || r.n_ext == 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3((r.n_ext + 63) / 64), dim3(64), 0, s, r, contrib,
+                       counters);
+    return hipGetLastError();
 }
 
 hipError_t launch_lpa_rhs(const ReqDev &r, int n, int n_comp, const double *rho, const double *u,

@@ -198,7 +198,8 @@ static int ilog2(int v) {
     return r;
 }
 
-TileShape heuristic_shape(const frg_integral_desc &d, int n_ext, int target_waves) {
+TileShape heuristic_shape(const frg_integral_desc &d, int n_ext, int target_waves,
+                          bool allow_chunks) {
     TileShape s;
     if (d.family == 1) return s;
     // external points per wavefront: the smallest power of two >= n_ext, at least 4
@@ -206,7 +207,7 @@ TileShape heuristic_shape(const frg_integral_desc &d, int n_ext, int target_wave
     while (le > 4 && le / 2 >= n_ext) le /= 2;
     int ext_tiles = (n_ext + le - 1) / le;
     // Prefer more lanes per point over radial chunks: a tile that holds all radial nodes of its
-    // points finishes them itself, while chunked tiles must meet through device-scope fences.
+    // points finishes them within the wavefront, chunked tiles need the finalize pass.
     while (ext_tiles < target_waves && le > 1 && 2 * (kWave / le) <= d.n_q) {
         le /= 2;
         ext_tiles = (n_ext + le - 1) / le;
@@ -218,6 +219,17 @@ TileShape heuristic_shape(const frg_integral_desc &d, int n_ext, int target_wave
         ++s.lx_log2;
         ext_tiles = (n_ext + le - 1) / le;
     }
+    if (!allow_chunks) return s;
+    // three-point with 64 lanes per point and still too few tiles: move radial lanes to cos1
+    // lanes and give the radial nodes freed that way to further chunks (same lanes per point,
+    // twice the tiles)
+    while (d.family == 3 && le == 1 && ext_tiles * s.chunks < target_waves && s.lq_log2 > 0 &&
+           (2 << s.lx_log2) <= d.n_x) {
+        --s.lq_log2;
+        ++s.lx_log2;
+        s.chunks *= 2;
+    }
+    if (s.chunks > 1) return s;
     int lq = 1 << s.lq_log2;
     int max_chunks = (d.n_q + lq - 1) / lq;  // at least one radial node per lane and chunk
     // chunks only when even the narrowest tiles leave the chip mostly idle
@@ -226,11 +238,12 @@ TileShape heuristic_shape(const frg_integral_desc &d, int n_ext, int target_wave
     return s;
 }
 
-TileShape choose_shape(frg_context *ctx, const frg_integral_desc &d, int n_ext, int target_waves) {
+TileShape choose_shape(frg_context *ctx, const frg_integral_desc &d, int n_ext, int target_waves,
+                       bool allow_chunks) {
     std::vector<int> key = {d.family, d.precision, d.n_q, d.n_x, d.n_phi, n_ext, target_waves};
     auto it = ctx->tuned.find(key);
-    if (it != ctx->tuned.end()) return it->second;
-    return heuristic_shape(d, n_ext, target_waves);
+    if (it != ctx->tuned.end() && (allow_chunks || it->second.chunks == 1)) return it->second;
+    return heuristic_shape(d, n_ext, target_waves, allow_chunks);
 }
 
 // Only radially chunked requests hand contributions between workgroups; a single-chunk tile
@@ -241,9 +254,9 @@ size_t contrib_doubles(const ReqDev &r) {
 }
 
 int counter_count(const ReqDev &r) {
-    // one counter per external tile, then (float32 form) one amplification slot per point
-    if (r.family == 1 || r.chunks == 1) return 0;
-    return r.ext_tiles + (r.precision == 1 ? r.n_ext : 0);
+    // float32 form: one amplification slot per point and the dressing table's relative step
+    if (r.family == 1 || r.chunks == 1 || r.precision == 0) return 0;
+    return r.n_ext + 1;
 }
 
 int tile_count(const ReqDev &r) { return r.ext_tiles * r.chunks; }
@@ -360,6 +373,8 @@ frg_status run_batch(frg_context *ctx, ReqDev &r, hipStream_t s, Scratch *sc) {
     r.ctr_base = 0;
     FRG_HIP_CHECK(launch_batch(&r, nullptr, tile_count(r), lds_bytes_for(r),
                                (double *)sc->contrib.ptr, (unsigned *)sc->counters.ptr, s));
+    FRG_HIP_CHECK(launch_finalize(r, (const double *)sc->contrib.ptr,
+                                  (unsigned *)sc->counters.ptr, s));
     return FRG_OK;
 }
 
@@ -469,8 +484,10 @@ struct FlowGraph {
     // state -> masses -> integrals -> assembly on stream s (LPA: one fused kernel)
     hipError_t enqueue(hipStream_t s) const {
         if (family == 1) return launch_lpa_rhs(r, n, n_comp, grid, state, m2_floor, dstate_dt, s);
-        return launch_batch(&r, nullptr, tile_count(r), lds_bytes_for(r), (double *)contrib.ptr,
-                            (unsigned *)counters.ptr, s);
+        const hipError_t e = launch_batch(&r, nullptr, tile_count(r), lds_bytes_for(r),
+                                          (double *)contrib.ptr, (unsigned *)counters.ptr, s);
+        if (e != hipSuccess) return e;
+        return launch_finalize(r, (const double *)contrib.ptr, (unsigned *)counters.ptr, s);
     }
     ~FlowGraph() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -601,7 +618,7 @@ frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const f
             cands.push_back(TileShape{lq, 1, lx});
         }
     }
-    cands.push_back(heuristic_shape(*desc, batch->n_ext, target));
+    cands.push_back(heuristic_shape(*desc, batch->n_ext, target, true));
     hipEvent_t e0, e1;
     FRG_HIP_CHECK(hipEventCreate(&e0));
     FRG_HIP_CHECK(hipEventCreate(&e1));
@@ -706,7 +723,8 @@ frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc 
     for (int i = 0; i < n; ++i) {
         if (batches[i].n_ext == 0) continue;
         int target = std::max(1, (int)std::lround(target_total * nodes[i] / total_nodes));
-        TileShape shape = choose_shape(ctx, descs[i], batches[i].n_ext, target);
+        // fused launches take no radial chunks (they would need a finalize pass per request)
+        TileShape shape = choose_shape(ctx, descs[i], batches[i].n_ext, target, false);
         ReqDev r;
         if ((st = make_request(ctx, descs[i], batches[i], shape, 1, 0.0, 1.0, &r)) != FRG_OK)
             return st;

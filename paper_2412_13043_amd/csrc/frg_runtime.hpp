@@ -123,10 +123,12 @@ frg_status validate(const frg_integral_desc *desc, const frg_batch *batch, bool 
 frg_status make_request(frg_context *ctx, const frg_integral_desc &desc, const frg_batch &b,
                         const TileShape &shape, int m2_mode, double m2_floor, double coef,
                         ReqDev *out);
-// Tile shape for a request: autotuned entry if one exists, else the heuristic.
+// Tile shape for a request: the autotuned one if the context has it, else the heuristic.
+// allow_chunks = false (fused launches) restricts both to single-chunk shapes.
 TileShape choose_shape(frg_context *ctx, const frg_integral_desc &desc, int n_ext,
-                       int target_waves);
-TileShape heuristic_shape(const frg_integral_desc &desc, int n_ext, int target_waves);
+                       int target_waves, bool allow_chunks = true);
+TileShape heuristic_shape(const frg_integral_desc &desc, int n_ext, int target_waves,
+                          bool allow_chunks = true);
 // Doubles of contribution scratch and counters a request needs.
 size_t contrib_doubles(const ReqDev &r);
 int counter_count(const ReqDev &r);
