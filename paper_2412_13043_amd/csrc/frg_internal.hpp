@@ -34,7 +34,7 @@ struct ReqDev {
     int family, d, n_q, n_x, n_phi, precision;
     int n_ext;
     int lq_log2;      // lanes per external point over radial nodes: 1 << lq_log2 (families 2, 3)
-    int lx_log2;      // ... times lanes over cos1 nodes: 1 << lx_log2 (three-point only, else 0)
+    int lx_log2;      // ... times lanes over cos1 nodes: 1 << lx_log2 (families 2, 3; LPA 0)
     int chunks;       // radial chunks per external tile
     int ext_tiles;    // ceil(n_ext / (64 >> (lq_log2 + lx_log2)))
     int nZ;           // 0 => Z == 1

@@ -471,6 +471,73 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
     return t.wg * (((double)acc.s - (double)acc.c) * inv_k2);
 }
 
+// Two-point contribution with the cos1 nodes shared by lx adjacent lanes (lx = 1: one lane takes
+// them all).  In rounds of lx consecutive nodes each lane evaluates one propagator; the round's
+// first lane pulls them across lanes and accumulates them in cos1 order exactly as the one-lane
+// loops do (float64: one fused multiply-add per node; float32: the same FRG_ILP-node blocks and
+// compensated additions), so the bits do not depend on lx.  Called by all lanes of a wavefront
+// together when lx > 1; act marks the lanes with a point and radial node to evaluate.
+template <int PREC>
+__device__ __forceinline__ double contrib_two(const ReqDev &r, const Smem &sm, int a, double p,
+                                              double m2, double inv_k2, float &kmax, bool act,
+                                              int sx, int lx) {
+    if (lx == 1) {
+        if (!act) return 0.0;
+        return (PREC == 0) ? contrib_two64(r, sm, a, p, m2, inv_k2)
+                           : contrib_two32(r, sm, a, p, m2, inv_k2, kmax);
+    }
+    double wg = 0.0, c0 = 0.0, c1 = 0.0;
+    Par32 P;
+    if (act) {
+        const RadialTerm t = radial64(r, sm, a, p, m2);
+        wg = t.wg;
+        c0 = t.c0 * inv_k2;
+        c1 = t.c1 * inv_k2;
+        if (PREC == 1) P = par32(r, m2, inv_k2);
+    }
+    const double m2h = m2 * inv_k2, za = r.za, zb1 = r.zbk + 1.0;
+    const int nx = r.n_x, nZ = r.nZ;
+    const int xbase = (int)threadIdx.x & ~(lx - 1);
+    const int nblk = nx - nx % FRG_ILP;  // nodes the float32 loop covers in whole blocks
+    double inner = 0.0;
+    Kahan32 acc{0.0f, 0.0f};
+    float blk = 0.0f;
+    for (int j0 = 0; j0 < nx; j0 += lx) {
+        const int b = j0 + sx;
+        double g = 0.0;
+        float gf = 0.0f;
+        if (act && b < nx) {
+            if (PREC == 0) {
+                double l2[1] = {fma(c1, kc(r.ang.x)[b], c0)}, G[1];
+                propagators64<1>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
+                g = G[0];
+            } else {
+                float l2[1] = {(float)fma(c1, kc(r.ang.x)[b], c0)}, G[1];
+                propagators32<1>(l2, G, kmax, sm, P);
+                gf = G[0];
+            }
+        }
+        const int nk = min(lx, nx - j0);
+        for (int k = 0; k < nk; ++k) {
+            const int bk = j0 + k;
+            if (PREC == 0) {
+                inner = fma(kc(r.ang.xw)[bk], __shfl(g, xbase + k), inner);
+            } else {
+                const float gk = __shfl(gf, xbase + k);
+                if (bk < nblk) {
+                    const int w = bk % FRG_ILP;
+                    blk = fmaf(kc(r.ang.xwf)[bk], gk, w == 0 ? 0.0f : blk);
+                    if (w == FRG_ILP - 1) acc.add(blk);
+                } else {
+                    acc.add(kc(r.ang.xwf)[bk] * gk);
+                }
+            }
+        }
+    }
+    if (PREC == 0) return wg * (inner * inv_k2);
+    return wg * (((double)acc.s - (double)acc.c) * inv_k2);
+}
+
 __device__ __forceinline__ void xterm32(const ReqDev &r, const Smem &sm, const Par32 &P, int b,
                                         double c0, double c1, double ca, double sa, float &kmax,
                                         double &t, double &inner) {
@@ -694,8 +761,8 @@ template <int FAM, int PREC>
 __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int et, int chunk,
                                             double *__restrict__ contrib,
                                             unsigned *__restrict__ counters) {
-    // lanes per point = lq (radial) x lx (cos1, three-point only); lane = (point, sq, sx)
-    const int lxl = (FAM == 3) ? r.lx_log2 : 0;
+    // lanes per point = lq (radial) x lx (cos1); lane = (point, sq, sx)
+    const int lxl = r.lx_log2;
     const int lpl = r.lq_log2 + lxl;
     const int lq = 1 << r.lq_log2, lx = 1 << lxl;
     const int le = kWave >> lpl;
@@ -725,9 +792,7 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
         if (FAM == 3)
             return contrib_three<PREC>(r, sm, act ? a : 0, p, ca, sa, m2, inv_k2, kmax, act, sx,
                                        lx);
-        if (!act) return 0.0;
-        return (PREC == 0) ? contrib_two64(r, sm, a, p, m2, inv_k2)
-                           : contrib_two32(r, sm, a, p, m2, inv_k2, kmax);
+        return contrib_two<PREC>(r, sm, act ? a : 0, p, m2, inv_k2, kmax, act, sx, lx);
     };
     if (r.chunks == 1) {
         // The wavefront holds every radial node of its points.  The lq radial sub-lanes of a

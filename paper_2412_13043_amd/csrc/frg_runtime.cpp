@@ -213,18 +213,31 @@ TileShape heuristic_shape(const frg_integral_desc &d, int n_ext, int target_wave
         ext_tiles = (n_ext + le - 1) / le;
     }
     s.lq_log2 = ilog2(kWave / le);
-    // three-point: then share the cos1 nodes of a radial node among lanes as well
-    while (d.family == 3 && ext_tiles < target_waves && le > 1 && (2 << s.lx_log2) <= d.n_x) {
+    // integrand nodes one lane evaluates; splitting further than kMinLaneNodes would leave the
+    // per-lane prologue and the cross-lane additions dominant
+    constexpr int kMinLaneNodes = 16;
+    auto lane_nodes = [&](int lq_log2, int lx_log2, int chunks) {
+        const long long rq = (d.n_q + ((long long)chunks << lq_log2) - 1) /
+                             ((long long)chunks << lq_log2);
+        const long long rx = (d.n_x + (1LL << lx_log2) - 1) >> lx_log2;
+        return rq * rx * (d.family == 3 ? d.n_phi : 1);
+    };
+    // then share the cos1 nodes of a radial node among lanes as well
+    while (ext_tiles < target_waves && le > 1 && (2 << s.lx_log2) <= d.n_x &&
+           lane_nodes(s.lq_log2, s.lx_log2 + 1, 1) >= kMinLaneNodes) {
         le /= 2;
         ++s.lx_log2;
         ext_tiles = (n_ext + le - 1) / le;
     }
-    if (!allow_chunks) return s;
-    // three-point with 64 lanes per point and still too few tiles: move radial lanes to cos1
-    // lanes and give the radial nodes freed that way to further chunks (same lanes per point,
-    // twice the tiles)
-    while (d.family == 3 && le == 1 && ext_tiles * s.chunks < target_waves && s.lq_log2 > 0 &&
-           (2 << s.lx_log2) <= d.n_x) {
+    // Radial chunks cost a second (finalize) launch, a few microseconds: only for requests
+    // with work enough to gain that back (about 15 us of the whole chip).
+    const double nodes = (double)n_ext * d.n_q * d.n_x * (d.family == 3 ? d.n_phi : 1);
+    if (!allow_chunks || nodes < 8.0e6) return s;
+    // 64 lanes per point and still too few tiles: move radial lanes to cos1 lanes and give the
+    // radial nodes freed that way to further chunks (same lanes per point, twice the tiles)
+    while (le == 1 && ext_tiles * s.chunks < target_waves && s.lq_log2 > 0 &&
+           (2 << s.lx_log2) <= d.n_x &&
+           lane_nodes(s.lq_log2 - 1, s.lx_log2 + 1, s.chunks * 2) >= kMinLaneNodes) {
         --s.lq_log2;
         ++s.lx_log2;
         s.chunks *= 2;
@@ -281,7 +294,7 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
     r.precision = d.precision;
     r.n_ext = b.n_ext;
     r.lq_log2 = d.family == 1 ? 0 : shape.lq_log2;
-    r.lx_log2 = d.family == 3 ? shape.lx_log2 : 0;
+    r.lx_log2 = d.family >= 2 ? shape.lx_log2 : 0;
     r.chunks = d.family == 1 ? 1 : shape.chunks;
     int le = kWave >> (r.lq_log2 + r.lx_log2);
     r.ext_tiles = (b.n_ext + le - 1) / le;
@@ -387,9 +400,8 @@ std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out) {
         lds = std::max(lds, lds_bytes_for(r));
         int lq = 1 << r.lq_log2;
         double inner = r.family == 1 ? 1.0
-                       : r.family == 2
-                           ? (double)r.n_x
-                           : std::ceil((double)r.n_x / (1 << r.lx_log2)) * r.n_phi;
+                                     : std::ceil((double)r.n_x / (1 << r.lx_log2)) *
+                                           (r.family == 3 ? r.n_phi : 1);
         for (int et = 0; et < r.ext_tiles; ++et)
             for (int ch = 0; ch < r.chunks; ++ch) {
                 int a0 = (int)(((long long)r.n_q * ch) / r.chunks);
@@ -612,8 +624,8 @@ frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const f
         const int max_chunks = (desc->n_q + (1 << lq) - 1) >> lq;
         for (int ch = 1; ch <= max_chunks; ch *= 2) cands.push_back(TileShape{lq, ch});
         if ((max_chunks & (max_chunks - 1)) != 0) cands.push_back(TileShape{lq, max_chunks});
-        // three-point: cos1 nodes shared among lanes as well (single radial chunk)
-        for (int lx = 1; desc->family == 3 && lq + lx <= 6 && (1 << lx) <= desc->n_x; ++lx) {
+        // cos1 nodes shared among lanes as well (single radial chunk)
+        for (int lx = 1; lq + lx <= 6 && (1 << lx) <= desc->n_x; ++lx) {
             if ((kWave >> (lq + lx)) / 2 >= batch->n_ext && lq + lx > 0) continue;
             cands.push_back(TileShape{lq, 1, lx});
         }

@@ -90,7 +90,7 @@ struct Scratch {
 struct TileShape {
     int lq_log2 = 0;  // lanes per point over radial nodes (log2)
     int chunks = 1;   // radial chunks (separate workgroups) per external tile
-    int lx_log2 = 0;  // lanes per point over cos1 nodes (log2; three-point only)
+    int lx_log2 = 0;  // lanes per point over cos1 nodes (log2; families 2 and 3)
 };
 
 struct FlowGraph;

@@ -362,10 +362,12 @@ static bool admit_and_launch(frg_session &s) {
             break;
         }
     if (!free_slot || s.queue.empty()) return false;
-    // arrival order; stop at the first request that does not fit (no overtaking), cap the
-    // launch so that one slot does not swallow the whole queue when others are idle
+    // Arrival order; stop at the first request that does not fit (no overtaking).  A launch
+    // completes as a whole, so it is capped at about half a millisecond of the chip: small
+    // requests are not held back by a large one launched with them, and a request above the
+    // cap runs alone in its slot while the other slots keep serving the rest of the queue.
     const size_t max_reqs = 512;
-    const double max_nodes = 4.0e9;
+    const double max_nodes = 2.5e8;
     double nodes = 0.0;
     std::vector<SessReq *> batch;
     while (!s.queue.empty() && batch.size() < max_reqs) {

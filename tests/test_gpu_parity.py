@@ -500,12 +500,10 @@ def test_tile_shapes_give_identical_bits(env, tmp_path, monkeypatch, family, pre
     results = []
     # (radial lanes per point log2, radial chunks, cos1 lanes log2): one, several and the
     # maximum number of chunks; 8, 16 and 64 radial lanes leave a ragged last radial round (13
-    # nodes); three-point also shares the 6 cos1 nodes among 2, 4 and 8 lanes (ragged), up to
-    # 64 lanes per point, alone and with radial chunks
+    # nodes); the 6 cos1 nodes shared among 2, 4 and 8 lanes (ragged), up to 64 lanes per
+    # point, alone and with radial chunks
     shapes = [(0, 1, 0), (0, 13, 0), (1, 3, 0), (2, 1, 0), (3, 1, 0), (3, 2, 0), (4, 1, 0),
-              (6, 1, 0)]
-    if family == 3:
-        shapes += [(0, 1, 1), (0, 1, 3), (2, 1, 2), (4, 1, 2), (3, 1, 3), (1, 4, 2)]
+              (6, 1, 0), (0, 1, 1), (0, 1, 3), (2, 1, 2), (4, 1, 2), (3, 1, 3), (1, 4, 2)]
     for lq, ch, lx in shapes:
         cache = tmp_path / f"shape_{lq}_{ch}_{lx}.txt"
         cache.write_text(f"{family} {precision} {n_q} {n_x} {n_phi} {n} {target} {lq} {ch} {lx}\n")
