@@ -237,10 +237,29 @@ __device__ __forceinline__ double prop64(double l2, double z, double m2, double 
 // W propagators at once, G[w] = G(l2[w]) with the tabulated dressing, ordered by phase so that the
 // LDS gathers of all W points are in flight while the regulator (which does not depend on the
 // dressing) is evaluated, and the W dependency chains interleave.
-template <int W>
+// Far field: for y = l2/k^2 >= FRG_FAR_Y, fm::expm1_neg(y) is exactly -1 (2^n < 2^-55 in its
+// reconstruction), so l2 e = l2 + l2 E = 0 and the propagator below is exactly 1/(Z l2 + m2) --
+// the same bits without evaluating the exponential.  A wavefront takes that path only when all
+// its active lanes are in the far field (a uniform branch).  Used where whole wavefronts often
+// are (two-point tiles group a few neighbouring radial nodes of neighbouring momenta); a
+// three-point wavefront spans all radial nodes of a point and would only pay for the vote.
+#define FRG_FAR_Y 38.0
+
+template <int W, bool FAR = false>
 __device__ __forceinline__ void propagators64(const double (&l2)[W], double (&G)[W],
                                               const Smem &sm, int nZ, double za, double zb1,
                                               double m2, double inv_k2) {
+    bool far = FAR;
+#pragma unroll
+    for (int w = 0; w < W; ++w) far = far && (l2[w] * inv_k2 >= FRG_FAR_Y);
+    if (FAR && __all(far)) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const double zv = dressing64(sm, nZ, za, zb1, l2[w]);
+            G[w] = fm::rcp_nr(fma(zv, l2[w], m2));
+        }
+        return;
+    }
     double2 t[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) t[w] = sm.logt[(__double2hiint(l2[w]) >> 12) & 0xff];
@@ -316,13 +335,13 @@ __device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm,
         double l2[FRG_ILP], G[FRG_ILP];
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w) l2[w] = fma(c1, kc(r.ang.x)[b + w], c0);
-        propagators64<FRG_ILP>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
+        propagators64<FRG_ILP, true>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w) inner = fma(kc(r.ang.xw)[b + w], G[w], inner);
     }
     for (; b < nx; ++b) {
         double l2[1] = {fma(c1, kc(r.ang.x)[b], c0)}, G[1];
-        propagators64<1>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
+        propagators64<1, true>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
         inner = fma(kc(r.ang.xw)[b], G[0], inner);
     }
     return t.wg * (inner * inv_k2);
@@ -392,9 +411,38 @@ struct Par32 {
 
 // W float32 propagators; kmax tracks the largest amplification (|Z l2 + R| + |m2|)/D of the
 // float32 evaluations.
-template <int W>
+// Far field of the float32 form: fm::expm1_neg_f(y) is exactly -1 for y >= 17, so E = -1,
+// l2 e = 0 and both the denominator and its parts lose the exponential exactly (see FRG_FAR_Y).
+#define FRG_FAR_Y32 18.0f
+
+template <int W, bool FAR = false>
 __device__ __forceinline__ void propagators32(const float (&l2)[W], float (&G)[W], float &kmax,
                                               const Smem &sm, const Par32 &P) {
+    bool far = FAR;
+#pragma unroll
+    for (int w = 0; w < W; ++w) far = far && (l2[w] >= FRG_FAR_Y32);
+    if (FAR && __all(far)) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const float sp = fmaf(__builtin_amdgcn_logf(l2[w]), P.za2, P.zb1);
+            unsigned u;
+            asm("v_cvt_u32_f32 %0, %1" : "=v"(u) : "v"(sp));
+            const float2 z = sm.Z32[(int)min(u, (unsigned)P.nZ)];
+            const float zv = fmaf(__builtin_amdgcn_fractf(sp), z.y, z.x);
+            const float den = fmaf(zv, l2[w], P.m2f);
+            const float parts = fmaf(zv, l2[w], P.am2f);
+            if (den < P.tau * parts) {
+                const double l2d = (double)l2[w];
+                const double zd = dressing64(sm, P.nZ, P.za, P.zb1d, l2d);
+                G[w] = (float)prop64(l2d, zd, P.m2, 1.0);
+            } else {
+                const float rd = __builtin_amdgcn_rcpf(den);
+                G[w] = rd;
+                kmax = __uint_as_float(max(__float_as_uint(kmax), __float_as_uint(parts * rd)));
+            }
+        }
+        return;
+    }
     int iz[W];
     float fz[W];
 #pragma unroll
@@ -457,7 +505,7 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w)
             l2[w] = (float)fma(c1, kc(r.ang.x)[b + w], c0);
-        propagators32<FRG_ILP>(l2, G, kmax, sm, P);
+        propagators32<FRG_ILP, true>(l2, G, kmax, sm, P);
         float blk = 0.0f;
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w) blk = fmaf(kc(r.ang.xwf)[b + w], G[w], blk);
@@ -465,7 +513,7 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
     }
     for (; b < nx; ++b) {
         float l2[1] = {(float)fma(c1, kc(r.ang.x)[b], c0)}, G[1];
-        propagators32<1>(l2, G, kmax, sm, P);
+        propagators32<1, true>(l2, G, kmax, sm, P);
         acc.add(kc(r.ang.xwf)[b] * G[0]);
     }
     return t.wg * (((double)acc.s - (double)acc.c) * inv_k2);
@@ -509,11 +557,11 @@ __device__ __forceinline__ double contrib_two(const ReqDev &r, const Smem &sm, i
         if (act && b < nx) {
             if (PREC == 0) {
                 double l2[1] = {fma(c1, kc(r.ang.x)[b], c0)}, G[1];
-                propagators64<1>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
+                propagators64<1, true>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
                 g = G[0];
             } else {
                 float l2[1] = {(float)fma(c1, kc(r.ang.x)[b], c0)}, G[1];
-                propagators32<1>(l2, G, kmax, sm, P);
+                propagators32<1, true>(l2, G, kmax, sm, P);
                 gf = G[0];
             }
         }
