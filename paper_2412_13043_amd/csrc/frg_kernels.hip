@@ -7,8 +7,8 @@
 // For the vertex families the lanes of a point share its radial nodes (and, three-point, its
 // cos1 nodes); each (point, radial node) contribution is a fixed sequence of operations, and the
 // point's result adds the contributions in radial order -- within the wavefront by cross-lane
-// pulls when the tile holds every radial node, else through a [n_q][n_ext] scratch block summed
-// by the last chunk.  Each result therefore depends only on its own request, never on the
+// pulls when the tile holds every radial node, else through a [n_q][n_ext] scratch block that a
+// finalize kernel sums in radial order.  Each result therefore depends only on its own request, never on the
 // tiling, batch composition or launch shape.
 //
 // All device code is built with -ffp-contract=off: every fused multiply-add is written out with

@@ -62,10 +62,10 @@ struct PhiEntry {
     PhiRule rule;
 };
 
-// Per-stream scratch: contribution blocks, per-external-tile counters, work counters, and the
-// request/tile tables of fused launches.  Chunk counters are zero at rest (the last chunk of an
-// external tile resets its counter); the fused kernel's tile counter is cleared before each
-// launch.
+// Per-stream scratch: contribution blocks, float32 amplification slots, work counters, and the
+// request/tile tables of fused launches.  The amplification slots are zero at rest (the finalize
+// kernel resets them after reading); the fused kernel's tile counter is cleared by a fill kernel
+// before each launch.
 struct Scratch {
     DeviceBuffer contrib;   // doubles (radially chunked requests)
     DeviceBuffer counters;  // u32, zero at rest
