@@ -164,6 +164,78 @@ def cpu_baseline(target_seconds=12.0):
                       f"{el:.1f} s"}
 
 
+def oracle_timings(threads_max=16, seconds=1.5):
+    """The FP64 oracle per workload on the host: seconds per right-hand side with one thread and
+    with `threads_max` threads over disjoint external-point ranges, plus the host description."""
+    import platform
+
+    import oracle
+    from paper_2412_13043_amd import workloads as wl
+
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    threads = min(avail, threads_max)
+
+    def rate(call, n_points, nodes_per_point, n_threads):
+        """Repeat `call(lo, hi)` over point ranges split across n_threads for >= `seconds`."""
+        chunks = np.array_split(np.arange(n_points), n_threads)
+        done = 0
+        t0 = time.perf_counter()
+        while True:
+            ths = [threading.Thread(target=call, args=(c[0], c[-1] + 1)) for c in chunks if c.size]
+            for t in ths:
+                t.start()
+            for t in ths:
+                t.join()
+            done += n_points
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                return done * nodes_per_point / el  # nodes per second
+
+    res = {"host": {"cpu_model": model, "logical_cpus": os.cpu_count(),
+                    "cpus_available": avail, "threads_used": threads}}
+    # LPA: 64 rho points x GL32 per right-hand side; the 4096-RHS batch, one point = one integral
+    rho, u, m2 = wl.lpa_batch()
+    m2f = m2.reshape(-1)
+    lpa = lambda lo, hi: oracle.integrate(oracle.LPA, wl.LPA_NQ, wl.LPA_QMAX, m2=m2f[lo:hi])
+    # two-point: 256 momenta x 64x32 per right-hand side
+    p, m2s, Z = wl.two_point()
+    two = lambda lo, hi: oracle.integrate(oracle.TWO_POINT, wl.TWO_NQ, wl.TWO_QMAX,
+                                          n_x=wl.TWO_NX, ext=p[lo:hi], m2_scalar=m2s, Z=Z)
+    # three-point: 1024 (p, alpha) pairs x 64x32x16 per right-hand side
+    P, A, m3, Z3 = wl.three_point()
+    three = lambda lo, hi: oracle.integrate(oracle.THREE_POINT, wl.THREE_NQ, wl.THREE_QMAX,
+                                            n_x=wl.THREE_NX, n_phi=wl.THREE_NPHI,
+                                            ext=(P[lo:hi], A[lo:hi]), m2=m3[lo:hi], Z=Z3)
+    cases = {
+        "lpa": (lpa, m2f.size, wl.LPA_NQ, wl.LPA_N_RHO * wl.LPA_NQ, 1.0),
+        "two_point": (two, p.size, wl.TWO_NQ * wl.TWO_NX, p.size * wl.TWO_NQ * wl.TWO_NX, 1.0),
+        # one thread: a 64-pair sample of the right-hand side
+        "three_point": (three, P.size, wl.THREE_NQ * wl.THREE_NX * wl.THREE_NPHI,
+                        P.size * wl.THREE_NQ * wl.THREE_NX * wl.THREE_NPHI, 64 / P.size),
+    }
+    for name, (call, n_pts, npp, nodes_rhs, single_frac) in cases.items():
+        out = {"nodes_per_rhs": nodes_rhs}
+        for nt in (1, threads):
+            n_use = max(int(n_pts * single_frac), nt) if nt == 1 else n_pts
+            r = rate(call, n_use, npp, nt)
+            out[f"threads_{nt}"] = {"gnodes_per_s": round(r / 1e9, 5),
+                                    "seconds_per_rhs": round(nodes_rhs / r, 6)}
+        res[name] = out
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +243,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--serving-seconds", type=float, default=4.0,
+                    help="measured seconds of the serving loop per offered load")
     ap.add_argument("--workload", default="two_point_256",
                     choices=["two_point_256", "three_point_8", "lpa_4096"],
                     help="workload of the timed line (default: the two-point batch); the others "
@@ -240,12 +314,15 @@ def main():
     }
     extra = {}
     if not args.no_extra:
-        extra = secondary(torch, frg, wl, ctx)
+        extra = secondary(torch, frg, wl, ctx, serving_seconds=args.serving_seconds)
     if extra:
         res["extra"] = extra
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         res["cpu_baseline"] = cpu_baseline()
+        if not args.no_extra:
+            log("bench: oracle per workload, one thread and all threads")
+            res.setdefault("extra", {})["oracle_cpu"] = oracle_timings()
     torch.cuda.synchronize()
     ctx.close()
     print(json.dumps(res), flush=True)
@@ -288,7 +365,7 @@ def workload_setup(torch, frg, wl, ctx, name):
             (tm, o1))
 
 
-def secondary(torch, frg, wl, ctx):
+def secondary(torch, frg, wl, ctx, serving_seconds=4.0):
     """Other workloads, timed the same way (fewer steps)."""
     ex = {}
     # LPA batch: 4096 right-hand sides x 64 rho points x GL32
@@ -334,8 +411,12 @@ def secondary(torch, frg, wl, ctx):
         ms32, o32, e32, _ = res[1]
         rel = ((o32 - o64).abs() / o64.abs()).cpu().numpy()
         within = bool(((o32 - o64).abs() / o64.abs() <= e32).all().item())
+        gn = nodes / (ms32 * 1e-3) / 1e9
         return {"speedup_vs_fp64": round(ms64 / ms32, 3),
-                "gnodes_per_s": round(nodes / (ms32 * 1e-3) / 1e9, 2),
+                "gnodes_per_s": round(gn, 2),
+                # nominal work per node against the packed float32 peak (the form issues no
+                # packed instructions, so half of it is its own ceiling)
+                "frac_fp32_peak": round(FLOP_PER_NODE[2] * gn / 1e3 / FP32_PEAK_TFLOPS, 4),
                 "max_rel_err_vs_fp64": float(rel.max()),
                 "median_rel_err_vs_fp64": float(np.median(rel)),
                 "max_stated_bound": float(e32.max().item()), "all_within_bound": within,
@@ -380,29 +461,30 @@ def secondary(torch, frg, wl, ctx):
     gctx.close()
     ex["rhs_latency_us"] = lat
     log("bench: serving")
-    ex["serving"] = serving(torch, frg, wl, ctx)
+    ex["serving"] = serving(torch, frg, wl, ctx, seconds=serving_seconds)
     return ex
 
 
-def serving(torch, frg, wl, ctx, n_steppers=200, seconds=6.0, load=0.8, seed=12345):
+def serving(torch, frg, wl, ctx, n_steppers=200, seconds=4.0, loads=(0.5, 0.8, 0.95),
+            seed=12345):
     """Workload 5: synthetic RK4 time-steppers submitting right-hand-side requests to a session.
 
     Each stepper (workloads.stepper_spec) owns a request shape (family, n_ext, nodes per
     dimension, float64 or float32) and a state; every RK4 stage submits one request built from the
     stage state, waits for it, and sleeps an exponential think time before the next, so arrivals
     are close to Poisson.  The think time is set for an offered load of `load` times the
-    capacity implied by the per-shape service times measured beforehand.  Reported: requests,
-    Gnodes/s, p50/p99 latency (submit -> result in the host buffer), and the same arrival trace
-    served FIFO on one stream by the plain per-batch float64 path (one frg_integrate_batch per
-    request, service times measured per shape).
+    capacity implied by the per-shape service times measured beforehand.  Reported per load:
+    requests, Gnodes/s, p50/p99 latency (submit -> result in the host buffer) overall and per
+    family and precision, and the same arrival trace served FIFO on one stream by the plain
+    per-batch float64 path (one frg_integrate_batch per request, service times measured per
+    shape).
     """
-    import math
     import random
 
     specs = [wl.stepper_spec(i) for i in range(n_steppers)]
+    fam_name = {1: "lpa", 2: "two_point", 3: "three_point"}
 
     def host_request(sp, state):
-        n = sp.n_ext
         if sp.family == 1:
             g = np.gradient(state, sp.ext)
             m2 = np.maximum(state + 2.0 * sp.ext * g, -0.9)
@@ -435,84 +517,104 @@ def serving(torch, frg, wl, ctx, n_steppers=200, seconds=6.0, load=0.8, seed=123
         svc.append(best)
     svc = np.array(svc)
     mean_svc = float(svc.mean())
-    think = max(mean_svc * (n_steppers / load - 1.0), 0.0)
+    req_nodes = np.array([wl.request_nodes(sp) for sp in specs], dtype=np.float64)
 
-    cfg = frg.frg_session_config(4, 4 << 30, 20, 0)  # 4 GiB arena
-    sess = frg.frg_session_open(ctx.handle, cfg)
-    tables = {}
-    for sp in specs:
-        if sp.Z is not None:
-            tables[sp.index] = frg.frg_session_register_table(sess, sp.Z.ctypes.data, sp.Z.size,
-                                                              wl.Z_XMIN, wl.Z_XMAX)
-    trace = []  # (arrival, stepper, latency)
-    lock = threading.Lock()
-    t_start = time.perf_counter()
-    t_end = t_start + seconds
+    def pct(x, q):
+        return round(float(np.percentile(x, q)) * 1e6, 1)
 
-    def stepper(sp):
-        rnd = random.Random(seed + sp.index)
-        u = sp.state0.copy()
-        h, eta = 0.05, 0.02
-        d = desc_of(sp)
-        tid = tables.get(sp.index, -1)
-        out = np.empty(sp.n_ext)
-        err = np.empty(sp.n_ext)
-        while time.perf_counter() < t_end:
-            ks = []
-            for stage in range(4):
-                us = u if stage == 0 else u + (h if stage == 3 else h / 2) * ks[-1]
-                ext, m2 = host_request(sp, us)
-                zt = frg.frg_log_table(None, 0, wl.Z_XMIN, wl.Z_XMAX)
-                b = frg.frg_batch(sp.n_ext, None if ext is None else ext.ctypes.data,
-                                  m2.ctypes.data, 0.0, zt, out.ctypes.data, err.ctypes.data)
-                t0 = time.perf_counter()
-                tk = frg.frg_session_submit(sess, d, b, tid)
-                frg.frg_session_wait(sess, tk, -1)
-                t1 = time.perf_counter()
-                with lock:
-                    trace.append((t0 - t_start, sp.index, t1 - t0))
-                ks.append(-eta * out)
-                time.sleep(rnd.expovariate(1.0 / think) if think > 0 else 0.0)
-                if time.perf_counter() >= t_end:
-                    break
-            if len(ks) == 4:
-                u = u + h / 6.0 * (ks[0] + 2 * ks[1] + 2 * ks[2] + ks[3])
+    def run(load):
+        think = max(mean_svc * (n_steppers / load - 1.0), 0.0)
+        cfg = frg.frg_session_config(4, 4 << 30, 20, 0)  # 4 GiB arena
+        sess = frg.frg_session_open(ctx.handle, cfg)
+        tables = {}
+        for sp in specs:
+            if sp.Z is not None:
+                tables[sp.index] = frg.frg_session_register_table(
+                    sess, sp.Z.ctypes.data, sp.Z.size, wl.Z_XMIN, wl.Z_XMAX)
+        trace = []  # (arrival, stepper, latency)
+        lock = threading.Lock()
+        t_start = time.perf_counter()
+        t_end = t_start + seconds
 
-    ths = [threading.Thread(target=stepper, args=(sp,)) for sp in specs]
-    for t in ths:
-        t.start()
-    for t in ths:
-        t.join()
-    st = frg.frg_session_stats(sess)
-    frg.frg_session_close(sess)
-    nodes = np.array([wl.request_nodes(specs[i]) for _, i, _ in trace], dtype=np.float64)
-    lat = np.array([l for _, _, l in trace])
-    arr = np.array([a for a, _, _ in trace])
-    span = max(a + l for a, _, l in trace) - min(arr)
-    # the same arrivals served FIFO, one request at a time, by the plain float64 path
-    order = np.argsort(arr)
-    free_at = 0.0
-    base_lat = np.empty(len(trace))
-    for k in order:
-        a, i, _ = trace[k]
-        start = max(a, free_at)
-        free_at = start + svc[i]
-        base_lat[k] = free_at - a
-    base_span = free_at - float(arr.min())
-    n32 = sum(1 for _, i, _ in trace if specs[i].fp32)
-    return {
-        "steppers": n_steppers, "seconds": seconds, "offered_load": load,
-        "requests": len(trace), "fp32_requests": n32,
-        "gnodes_per_s": round(float(nodes.sum()) / span / 1e9, 2),
-        "p50_us": round(float(np.percentile(lat, 50)) * 1e6, 1),
-        "p99_us": round(float(np.percentile(lat, 99)) * 1e6, 1),
-        "session_p50_us": round(st.p50_us, 1), "session_p99_us": round(st.p99_us, 1),
-        "launches": int(st.launches),
-        "baseline_fp64_per_batch": {
-            "gnodes_per_s": round(float(nodes.sum()) / base_span / 1e9, 2),
-            "p50_us": round(float(np.percentile(base_lat, 50)) * 1e6, 1),
-            "p99_us": round(float(np.percentile(base_lat, 99)) * 1e6, 1)},
-    }
+        def stepper(sp):
+            rnd = random.Random(seed + sp.index)
+            u = sp.state0.copy()
+            h, eta = 0.05, 0.02
+            d = desc_of(sp)
+            tid = tables.get(sp.index, -1)
+            out = np.empty(sp.n_ext)
+            err = np.empty(sp.n_ext)
+            while time.perf_counter() < t_end:
+                ks = []
+                for stage in range(4):
+                    us = u if stage == 0 else u + (h if stage == 3 else h / 2) * ks[-1]
+                    ext, m2 = host_request(sp, us)
+                    zt = frg.frg_log_table(None, 0, wl.Z_XMIN, wl.Z_XMAX)
+                    b = frg.frg_batch(sp.n_ext, None if ext is None else ext.ctypes.data,
+                                      m2.ctypes.data, 0.0, zt, out.ctypes.data, err.ctypes.data)
+                    t0 = time.perf_counter()
+                    tk = frg.frg_session_submit(sess, d, b, tid)
+                    frg.frg_session_wait(sess, tk, -1)
+                    t1 = time.perf_counter()
+                    with lock:
+                        trace.append((t0 - t_start, sp.index, t1 - t0))
+                    ks.append(-eta * out)
+                    time.sleep(rnd.expovariate(1.0 / think) if think > 0 else 0.0)
+                    if time.perf_counter() >= t_end:
+                        break
+                if len(ks) == 4:
+                    u = u + h / 6.0 * (ks[0] + 2 * ks[1] + 2 * ks[2] + ks[3])
+
+        ths = [threading.Thread(target=stepper, args=(sp,)) for sp in specs]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        st = frg.frg_session_stats(sess)
+        frg.frg_session_close(sess)
+        idx = np.array([i for _, i, _ in trace])
+        lat = np.array([l for _, _, l in trace])
+        arr = np.array([a for a, _, _ in trace])
+        nodes = req_nodes[idx]
+        span = float((arr + lat).max() - arr.min())
+        # the same arrivals served FIFO, one request at a time, by the plain float64 path
+        free_at = 0.0
+        base_lat = np.empty(len(trace))
+        for k in np.argsort(arr):
+            start = max(arr[k], free_at)
+            free_at = start + svc[idx[k]]
+            base_lat[k] = free_at - arr[k]
+        base_span = free_at - float(arr.min())
+        fam = np.array([specs[i].family for i in idx])
+        f32 = np.array([specs[i].fp32 for i in idx])
+        classes = {}
+        for f in (1, 2, 3):
+            for p32 in (False, True):
+                m = (fam == f) & (f32 == p32)
+                if m.any():
+                    classes[f"{fam_name[f]}_{'fp32' if p32 else 'fp64'}"] = {
+                        "requests": int(m.sum()),
+                        "mean_nodes": round(float(nodes[m].mean())),
+                        "p50_us": pct(lat[m], 50), "p99_us": pct(lat[m], 99),
+                        "baseline_p50_us": pct(base_lat[m], 50),
+                        "baseline_p99_us": pct(base_lat[m], 99)}
+        return {
+            "offered_load": load, "requests": len(trace), "fp32_requests": int(f32.sum()),
+            "gnodes_per_s": round(float(nodes.sum()) / span / 1e9, 2),
+            "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
+            "session_p50_us": round(st.p50_us, 1), "session_p99_us": round(st.p99_us, 1),
+            "launches": int(st.launches),
+            "baseline_fp64_per_batch": {
+                "gnodes_per_s": round(float(nodes.sum()) / base_span / 1e9, 2),
+                "p50_us": pct(base_lat, 50), "p99_us": pct(base_lat, 99)},
+            "per_class": classes,
+        }
+
+    res = {"steppers": n_steppers, "seconds_per_load": seconds}
+    for load in loads:
+        log(f"bench: serving at offered load {load}")
+        res[f"load_{load}"] = run(load)
+    return res
 
 
 def _latency(torch, fn, n=2000):
