@@ -28,6 +28,10 @@ REG_LITIM = 1
 LPA = 1
 TWO_POINT = 2
 THREE_POINT = 3
+LPA_T = 4
+TWO_POINT_T = 5
+BOSONIC = 0
+FERMIONIC = 1
 
 _lock = threading.Lock()
 _lib = None
@@ -65,6 +69,9 @@ def _load():
             lib.frgo_vertex_hyperspherical.argtypes = [I, I, I, I, I, D, D, I, P, P, D, P, I, D, D, P]
             lib.frgo_lpa_flow_rhs.argtypes = [I, I, D, D, I, I, D, P, P, I, P]
             lib.frgo_fd_derivatives.argtypes = [P, P, I, P, P]
+            lib.frgo_matsubara_rule.argtypes = [I, D, D, I, I, P, P]
+            lib.frgo_integrate_ft.argtypes = [I, I, I, D, D, I, I, D, D, I, I, P, P, D, P, I, D, D,
+                                              I, P]
             _lib = lib
     return _lib
 
@@ -162,4 +169,40 @@ def lpa_flow_rhs(rho, u, n_q, q_max, *, d=3, k=1.0, regulator=REG_EXP, n_comp=4,
                                    _ptr(u_a), len(rho_a), _ptr(out))
     if rc != 0:
         raise ValueError("frgo_lpa_flow_rhs rejected the arguments")
+    return out
+
+
+def matsubara_rule(statistics, T, lam, n_tail=0, cap=1 << 16):
+    """Frequency nodes w_j and weights c_j replacing T sum_n f(w_n) (see frg_oracle.h)."""
+    w = np.empty(cap)
+    c = np.empty(cap)
+    n = _load().frgo_matsubara_rule(statistics, T, lam, n_tail, cap, _ptr(w), _ptr(c))
+    if n < 0:
+        raise ValueError(f"frgo_matsubara_rule rejected the arguments (rc={n})")
+    return w[:n].copy(), c[:n].copy()
+
+
+def integrate_ft(family, n_q, q_max, *, T, statistics=BOSONIC, freq_max, freq_scaled=False,
+                 n_tail=0, n_x=0, k=1.0, regulator=REG_EXP, ext=None, m2=None, m2_scalar=0.0,
+                 Z=None, x_min=1e-3, x_max=1e3, n_ext=None):
+    """Finite-temperature integrals I_e, families LPA_T and TWO_POINT_T.
+    ext: family TWO_POINT_T (p[n], p0[n])."""
+    if family == TWO_POINT_T:
+        p, p0 = ext
+        ext_arr = np.concatenate([_f64(p), _f64(p0)])
+        n = len(p)
+    else:
+        ext_arr = None
+        n = None
+    m2a = _f64(m2)
+    if n is None:
+        n = len(m2a) if m2a is not None else int(n_ext)
+    Za = _f64(Z)
+    out = np.empty(n)
+    rc = _load().frgo_integrate_ft(family, n_q, n_x, q_max, k, regulator, statistics, T, freq_max,
+                                   1 if freq_scaled else 0, n_tail, _ptr(ext_arr), _ptr(m2a),
+                                   m2_scalar, _ptr(Za), 0 if Za is None else len(Za), x_min,
+                                   x_max, n, _ptr(out))
+    if rc != 0:
+        raise ValueError(f"frgo_integrate_ft rejected the arguments (rc={rc})")
     return out

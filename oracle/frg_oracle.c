@@ -234,6 +234,108 @@ int frgo_integrate(int family, int d, int n_q, int n_x, int n_phi, double q_max,
 }
 
 /* ---------------------------------------------------------------------------------------- */
+/* Finite temperature: Matsubara frequency rule and the d = 3 + 1 integrals.                 */
+/* ---------------------------------------------------------------------------------------- */
+int frgo_matsubara_rule(int statistics, double T, double lambda, int n_tail, int cap, double *w,
+                        double *c) {
+    if ((statistics != FRGO_BOSONIC && statistics != FRGO_FERMIONIC) || !(T > 0.0) ||
+        !(lambda > 0.0) || n_tail < 0 || w == NULL || c == NULL)
+        return -1;
+    double eta = statistics == FRGO_FERMIONIC ? 0.5 : 0.0;
+    /* largest n >= 0 with 2 pi T (n + eta) <= lambda */
+    double nh = floor(lambda / (2.0 * PI * T) - eta);
+    if (nh < 0.0) return -1;
+    if (nh > 1e6) return -2;
+    int n_hi = (int)nh;
+    int n_lo = statistics == FRGO_FERMIONIC ? -n_hi - 1 : -n_hi; /* symmetric set */
+    int n_exp = n_hi - n_lo + 1;
+    int total = n_exp + 2 * n_tail;
+    if (total > cap) return -2;
+    double Omega = 2.0 * PI * T * ((double)n_hi + eta) + PI * T;
+    static __thread double tn[MAXN], tw[MAXN];
+    if (n_tail > 0) {
+        if (n_tail > MAXN) return -2;
+        frgo_gauss_legendre(n_tail, 0.0, 1.0, tn, tw);
+    }
+    int j = 0;
+    /* negative tail, ascending w = -Omega/t: t ascending */
+    for (int i = 0; i < n_tail; ++i) {
+        w[j] = -Omega / tn[i];
+        c[j] = Omega * tw[i] / (tn[i] * tn[i]) / (2.0 * PI);
+        ++j;
+    }
+    for (int n = n_lo; n <= n_hi; ++n) {
+        w[j] = 2.0 * PI * T * ((double)n + eta);
+        c[j] = T;
+        ++j;
+    }
+    /* positive tail, ascending w = Omega/t: t descending */
+    for (int i = n_tail - 1; i >= 0; --i) {
+        w[j] = Omega / tn[i];
+        c[j] = Omega * tw[i] / (tn[i] * tn[i]) / (2.0 * PI);
+        ++j;
+    }
+    return total;
+}
+
+int frgo_integrate_ft(int family, int n_q, int n_x, double q_max, double k, int regulator,
+                      int statistics, double T, double freq_max, int freq_scaled, int n_tail,
+                      const double *ext, const double *m2, double m2_scalar, const double *Z,
+                      int nZ, double x_min, double x_max, int n_ext, double *out) {
+    if (n_ext < 0 || out == NULL) return -1;
+    if (n_q < 1 || n_q > MAXN || !(q_max > 0.0) || !(k > 0.0)) return -1;
+    if (family != FRGO_LPA_T && family != FRGO_TWO_POINT_T) return -1;
+    if (family == FRGO_TWO_POINT_T && (n_x < 1 || n_x > MAXN || ext == NULL)) return -1;
+    if (Z != NULL && (nZ < 1 || !(x_min > 0.0) || !(x_max > x_min))) return -1;
+    static __thread double qn[MAXN], qw[MAXN], xn[MAXN], xw[MAXN], fw_[MAXN], fc_[MAXN];
+    double lambda = freq_scaled ? freq_max * k : freq_max;
+    int n_f = frgo_matsubara_rule(statistics, T, lambda, n_tail, MAXN, fw_, fc_);
+    if (n_f < 0) return -1;
+    frgo_gauss_legendre(n_q, 0.0, q_max * k, qn, qw);
+    if (family == FRGO_TWO_POINT_T) frgo_gauss_legendre(n_x, -1.0, 1.0, xn, xw);
+    for (int e = 0; e < n_ext; ++e) {
+        double mass = m2 ? m2[e] : m2_scalar;
+        nsum total = {0.0, 0.0};
+        if (family == FRGO_LPA_T) {
+            double pref = 4.0 * PI / pow(2.0 * PI, 3.0);
+            for (int j = 0; j < n_f; ++j) {
+                for (int a = 0; a < n_q; ++a) {
+                    double q = qn[a], q2 = q * q;
+                    double den = fw_[j] * fw_[j] + q2 + frgo_regulator(regulator, q2, k) + mass;
+                    double term = fc_[j] * pref * qw[a] * q2 *
+                                  frgo_regulator_dot(regulator, q2, k) / (den * den);
+                    nsum_add(&total, term);
+                }
+            }
+        } else {
+            double p = ext[e], p0 = ext[n_ext + e];
+            double pref = 2.0 * PI / pow(2.0 * PI, 3.0);
+            for (int j = 0; j < n_f; ++j) {
+                double wq = fw_[j], wl = fw_[j] + p0;
+                for (int a = 0; a < n_q; ++a) {
+                    nsum inner = {0.0, 0.0};
+                    double q = qn[a], q2 = q * q;
+                    for (int b = 0; b < n_x; ++b) {
+                        double l2 = q2 + p * p + 2.0 * q * p * xn[b];
+                        if (l2 < 0.0) l2 = 0.0;
+                        double gq = 1.0 / (wq * wq + frgo_dressing(Z, nZ, x_min, x_max, q2) * q2 +
+                                           frgo_regulator(regulator, q2, k) + mass);
+                        double gl = 1.0 / (wl * wl + frgo_dressing(Z, nZ, x_min, x_max, l2) * l2 +
+                                           frgo_regulator(regulator, l2, k) + mass);
+                        double term = fc_[j] * pref * qw[a] * xw[b] * q2 *
+                                      frgo_regulator_dot(regulator, q2, k) * gq * gq * gl;
+                        nsum_add(&inner, term);
+                    }
+                    nsum_add(&total, nsum_get(&inner));
+                }
+            }
+        }
+        out[e] = nsum_get(&total);
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------------- */
 /* Hyperspherical reference rule (rotation-invariance pin).                                  */
 /* q = |q| (cos t1, sin t1 cos t2, sin t1 sin t2 cos t3, sin t1 sin t2 sin t3),              */
 /* d^4q = q^3 sin^2 t1 sin t2 dq dt1 dt2 dt3.                                                */

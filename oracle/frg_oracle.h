@@ -27,7 +27,7 @@ extern "C" {
 #endif
 
 enum { FRGO_REG_EXP = 0, FRGO_REG_LITIM = 1 };
-enum { FRGO_LPA = 1, FRGO_TWO_POINT = 2, FRGO_THREE_POINT = 3 };
+enum { FRGO_LPA = 1, FRGO_TWO_POINT = 2, FRGO_THREE_POINT = 3, FRGO_LPA_T = 4, FRGO_TWO_POINT_T = 5 };
 
 /* n-point Gauss-Legendre rule on [a, b]; nodes ascending. */
 int frgo_gauss_legendre(int n, double a, double b, double *nodes, double *weights);
@@ -72,6 +72,40 @@ int frgo_vertex_hyperspherical(int n_legs, int n_q, int n_t1, int n_t2, int n_t3
                                double k, int regulator, const double p1[4], const double p2[4],
                                double m2, const double *Z, int nZ, double x_min, double x_max,
                                double *out);
+
+/*
+ * Finite temperature (Sec. 5.3.2, integrator types "Quadratureq0"/"Quadraturex0": the imaginary-
+ * time direction becomes a Matsubara sum; Sec. 3.1: regulators that act on the spatial momentum
+ * only).  Frequencies w_n = 2 pi T (n + eta), eta = 0 (bosonic) or 1/2 (fermionic).
+ *
+ * Frequency rule replacing T sum_{n in Z} f(w_n) by sum_j c_j f(w_j):
+ *   - every Matsubara frequency with |w_n| <= lambda, weight c = T (the bounded frequency domain);
+ *   - n_tail > 0: the frequencies beyond it as an integral, (1/2pi) int_{|w| >= Omega} f(w) dw with
+ *     Omega = (largest explicit |w|) + pi T, the midpoint below the first omitted frequency, each
+ *     side by GL(n_tail) in t on [0, 1] after w = +-Omega/t (dw = Omega dt/t^2).
+ * Nodes ascending in w.  Returns the number of nodes, -1 on invalid arguments (statistics not
+ * 0/1, T or lambda not positive, no explicit frequency, n_tail < 0), -2 if cap is too small.
+ */
+enum { FRGO_BOSONIC = 0, FRGO_FERMIONIC = 1 };
+int frgo_matsubara_rule(int statistics, double T, double lambda, int n_tail, int cap, double *w,
+                        double *c);
+
+/*
+ * Finite-temperature loop integrals in d = 3 + 1 with a spatial regulator R(q^2), q = |spatial q|,
+ * the frequency rule above (lambda = freq_max, or freq_max * k when freq_scaled), radial GL(n_q)
+ * on [0, q_max k] and x GL(n_x) on [-1, 1]:
+ *   family 4 (LPA):       I = sum_j c_j 4pi/(2pi)^3 sum_a w_a q^2 Rdot(q^2) G_j(q)^2
+ *                         G_j(q) = 1/(w_j^2 + q^2 + R(q^2) + m2)                     (Z == 1)
+ *   family 5 (two-point): I = sum_j c_j 2pi/(2pi)^3 sum_ab w_a w_b q^2 Rdot(q^2) G_j(q)^2 H_j(l)
+ *                         G_j(q) = 1/(w_j^2 + Z(q^2) q^2 + R(q^2) + m2),
+ *                         H_j(l) = 1/((w_j + p0)^2 + Z(l^2) l^2 + R(l^2) + m2),  l^2 = q^2 + p^2 + 2 q p x
+ * (int d^3q = 2 pi int q^2 dq int dx; the dressing depends on the spatial momentum).
+ * ext: family 5 p[n_ext] followed by p0[n_ext] (the external frequency); unused for family 4.
+ */
+int frgo_integrate_ft(int family, int n_q, int n_x, double q_max, double k, int regulator,
+                      int statistics, double T, double freq_max, int freq_scaled, int n_tail,
+                      const double *ext, const double *m2, double m2_scalar, const double *Z,
+                      int nZ, double x_min, double x_max, int n_ext, double *out);
 
 /*
  * Right-hand side of the LPA flow of u(rho) = U'(rho) for the O(N) model on a rho grid (Sec. 3.1
