@@ -32,7 +32,7 @@ FP32_PEAK_TFLOPS = 157.3  # packed FP32 (v_pk_fma_f32); unpacked float32 tops ou
 # family: LPA one propagator square and weight; two-point ell^2, log, dressing lerp, expm1 and
 # one single-division propagator plus the accumulation; three-point the same per node (its
 # first leg depends on the outer angle only and is counted once per 16 nodes).
-FLOP_PER_NODE = {1: 15.0, 2: 74.0, 3: 83.0}
+FLOP_PER_NODE = {1: 15.0, 2: 74.0, 3: 83.0, 5: 74.0}
 # Two-point nodes with y = l2/k^2 >= 38 have an exponential below double precision: their exact
 # value needs no expm1 (about 25 of the 74) and a plain reciprocal of Z l2 + m2 instead of the
 # single-division form (about 7 fewer).  The kernel takes that path per wavefront when all its
@@ -50,6 +50,16 @@ def two_point_far_fraction(p, n_q, q_max, n_x):
     l2 = q[None, :, None] ** 2 + P[:, None, None] ** 2 + 2.0 * q[None, :, None] * P[:, None, None] \
         * x[None, None, :]
     return float(np.mean(l2 >= FAR_Y))
+
+
+def ft_frequency_count(T, lam, n_tail, fermionic=False):
+    """Nodes of the Matsubara frequency rule: every |2 pi T (n + eta)| <= lam plus the tail nodes
+    of both sides."""
+    import math
+
+    eta = 0.5 if fermionic else 0.0
+    n_hi = math.floor(lam / (2.0 * math.pi * T) - eta)
+    return 2 * n_hi + (2 if fermionic else 1) + 2 * n_tail
 
 
 def log(msg):
@@ -246,7 +256,7 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=4.0,
                     help="measured seconds of the serving loop per offered load")
     ap.add_argument("--workload", default="two_point_256",
-                    choices=["two_point_256", "three_point_8", "lpa_4096"],
+                    choices=["two_point_256", "three_point_8", "lpa_4096", "two_point_ft_16"],
                     help="workload of the timed line (default: the two-point batch); the others "
                          "exist so that each family's kernel can be profiled on its own")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -285,8 +295,9 @@ def main():
     avg_ms = float(np.mean(ev_ms))
     flops = FLOP_PER_NODE[family] * nodes
     achieved = flops / (avg_ms * 1e-3) / 1e12
+    # the finite-temperature workload has the two-point workload's spatial nodes and momenta
     far = two_point_far_fraction(wl.two_point()[0], wl.TWO_NQ, wl.TWO_QMAX, wl.TWO_NX) \
-        if family == 2 else 0.0
+        if family in (2, 5) else 0.0
     required = FLOP_PER_NODE[family] - FAR_FLOP_SAVED * far
     res = {
         "metric": "integrand Gnodes/s + % FP64/FP32 vector peak; p50/p99 RHS latency",
@@ -353,6 +364,16 @@ def workload_setup(torch, frg, wl, ctx, name):
                   "nodes_per_step": nodes, "rhs_per_step": 8}
         return (lambda: ctx.integrate_multi([d3] * 8, b3), nodes, 3, "frg::multi_kernel<3, 0>",
                 config, (text, tm3, tZ3, o3))
+    if name == "two_point_ft_16":
+        descs, batches, nodes, keep = two_point_ft_setup(torch, frg, wl)
+        config = {"workload": "two-point vertex flow at finite temperature d=3+1: 16 right-hand "
+                              "sides x 256 momenta x (47 Matsubara frequencies (T = 0.1 k, "
+                              "|w| <= 10 k, 8 tail nodes per side) x 64 radial x 32 cos1 GL "
+                              "nodes), per-RHS tabulated Z, m2=0.5, float64, one fused "
+                              "frg_integrate_multi launch",
+                  "nodes_per_step": nodes, "rhs_per_step": 16}
+        return (lambda: ctx.integrate_multi(descs, batches), nodes, 5, "frg::multi_kernel<5, 0>",
+                config, keep)
     rho, u, m2 = wl.lpa_batch()
     tm = _dev(torch, m2.reshape(-1))
     o1 = torch.empty(tm.numel(), dtype=torch.float64, device="cuda")
@@ -363,6 +384,20 @@ def workload_setup(torch, frg, wl, ctx, name):
               "nodes_per_step": nodes, "rhs_per_step": 4096}
     return (lambda: ctx.integrate(d1, o1, m2=tm), nodes, 1, "frg::batch_kernel<1, 0>", config,
             (tm, o1))
+
+
+def two_point_ft_setup(torch, frg, wl, B=16):
+    """The finite-temperature two-point batch, inputs resident in HBM."""
+    p, p0, m2, Z = wl.two_point_ft_batch(B)
+    desc = frg.make_desc(frg.FRG_FAMILY_TWO_POINT_T, wl.FT_NQ, wl.FT_QMAX, n_x=wl.FT_NX,
+                         T=wl.FT_T, freq_max=wl.FT_FREQ_MAX, n_tail=wl.FT_N_TAIL)
+    te, tZ = _dev(torch, np.concatenate([p, p0])), _dev(torch, Z)
+    out = torch.empty((B, p.size), dtype=torch.float64, device="cuda")
+    batches = [frg.make_batch(p.size, out[b], ext=te, m2_scalar=m2, Z=tZ[b], x_min=wl.Z_XMIN,
+                              x_max=wl.Z_XMAX) for b in range(B)]
+    n_f = ft_frequency_count(wl.FT_T, wl.FT_FREQ_MAX, wl.FT_N_TAIL)
+    nodes = B * p.size * n_f * wl.FT_NQ * wl.FT_NX
+    return [desc] * B, batches, nodes, (te, tZ, out)
 
 
 def secondary(torch, frg, wl, ctx, serving_seconds=4.0):
@@ -396,6 +431,18 @@ def secondary(torch, frg, wl, ctx, serving_seconds=4.0):
         "fp64_tflops": round(FLOP_PER_NODE[3] * n3 / (ms3 * 1e-3) / 1e12, 3),
         "frac_fp64_peak": round(FLOP_PER_NODE[3] * n3 / (ms3 * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                                 4)}
+    # finite temperature: the two-point workload with a Matsubara sum (same kernel body, the
+    # frequency folded into the radial index)
+    log("bench: finite-temperature two-point batch")
+    dft, bft, nft, keep_ft = two_point_ft_setup(torch, frg, wl)
+    wall, ev = time_kernel(torch, lambda: ctx.integrate_multi(dft, bft), 5, 1)
+    msft = float(np.mean(ev))
+    ex["two_point_finite_T_batch_16"] = {
+        "gnodes_per_s": round(nft / (msft * 1e-3) / 1e9, 2), "avg_kernel_ms": round(msft, 3),
+        "nodes": nft,
+        "frac_fp64_peak": round(FLOP_PER_NODE[5] * nft / (msft * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                                4)}
+    del keep_ft
     # precision form on the near-pole workload vs float64 on identical inputs
     log("bench: float32 precision form")
 

@@ -69,8 +69,15 @@ typedef enum {
 typedef enum {
     FRG_FAMILY_LPA = 1,         /* radial only, any d >= 1 (local potential approximation) */
     FRG_FAMILY_TWO_POINT = 2,   /* d = 4, one angle (cos1) */
-    FRG_FAMILY_THREE_POINT = 3  /* d = 4, cos1 and phi (third angle trivial: factor 2 pi) */
+    FRG_FAMILY_THREE_POINT = 3, /* d = 4, cos1 and phi (third angle trivial: factor 2 pi) */
+    FRG_FAMILY_LPA_T = 4,       /* finite temperature, d = 3 + 1: Matsubara sum x radial */
+    FRG_FAMILY_TWO_POINT_T = 5  /* finite temperature, d = 3 + 1: Matsubara sum x radial x cos1 */
 } frg_family;
+
+typedef enum {
+    FRG_BOSONIC = 0,   /* Matsubara frequencies w_n = 2 pi n T */
+    FRG_FERMIONIC = 1  /* w_n = 2 pi (n + 1/2) T */
+} frg_statistics;
 
 /*
  * Integral descriptor ("integration kernel" in the paper's App. F terms).
@@ -87,26 +94,57 @@ typedef enum {
  * Rdot = k dR/dk = 2 k^2 y^2 e^y/(e^y - 1)^2 (y = l2/k^2) and the propagator
  * G(l2) = 1/(Z(l2) l2 + R(l2) + m2).  Radial GL(n_q) on [0, q_max*k]; x GL(n_x) on [-1, 1];
  * phi GL(n_phi) on [0, pi].  Momenta squared below zero from rounding are clamped to 0.
+ *
+ * Finite temperature (Sec. 5.3 "Momentum integrations": the "Quadratureq0"/"Quadraturex0"
+ * integrator types, which treat the imaginary-time direction as a Matsubara sum; Sec. 3.1: a
+ * regulator acting on the spatial momentum only).  d must be 4 (three spatial dimensions and the
+ * frequency).  T sum_{n in Z} f(w_n) is evaluated with the frequency rule sum_j c_j f(w_j):
+ *   - every Matsubara frequency with |w_n| <= Lambda, weight T, where Lambda = freq_max
+ *     ("q0": a fixed frequency domain) or freq_max * k ("x0", freq_scaled = 1: the domain scales
+ *     with k);
+ *   - n_tail > 0: the omitted frequencies as the integral (1/2pi) int_{|w| >= Omega} f dw, with
+ *     Omega = (largest explicit |w|) + pi T, by GL(n_tail) in t on [0, 1] after w = +-Omega/t on
+ *     each side (error of the midpoint boundary: O(T^2 f'(Omega)));
+ *   - the frequencies are sorted ascending; radial node a and frequency j form the radial index
+ *     a n_f + j of the sums (contributions are added in that order).
+ *   family 4:  I_e = sum_j c_j 4pi/(2pi)^3 sum_a w_a q_a^2 Rdot(q_a^2) G_j(q_a)^2,
+ *                    G_j(q) = 1/(w_j^2 + q^2 + R(q^2) + m2_e)
+ *   family 5:  I_e = sum_j c_j 2pi/(2pi)^3 sum_ab w_a w_b q_a^2 Rdot(q_a^2) G_j(q_a)^2 H_j(l),
+ *                    G_j(q) = 1/(w_j^2 + Z(q^2) q^2 + R(q^2) + m2_e),
+ *                    H_j(l) = 1/((w_j + p0_e)^2 + Z(l^2) l^2 + R(l^2) + m2_e),
+ *                    l^2 = q_a^2 + p_e^2 + 2 q_a p_e x_b (spatial; Z and R act on spatial momenta)
+ * p0_e is the external frequency: a bosonic 2 pi m T, or for a fermion the paper's
+ * p0f = pi T exp(-k/(pi T)) (App. "Derivation of the four-Fermi system").
+ * Limits: at least one explicit frequency (fermionic: Lambda >= pi T); n_tail <= FRG_MAX_NODES;
+ * n_f = explicit + 2 n_tail <= FRG_MAX_NODES; n_q n_f <= FRG_MAX_FT_NODES.
  */
 typedef struct {
     int family;            /* frg_family */
-    int d;                 /* 1..8 for LPA; must be 4 for families 2 and 3 */
+    int d;                 /* 1..8 for LPA; must be 4 for families 2 to 5 */
     int n_q;               /* radial nodes, 1..FRG_MAX_NODES */
-    int n_x;               /* cos1 nodes (families 2, 3), 1..FRG_MAX_NODES; ignored for LPA */
+    int n_x;               /* cos1 nodes (families 2, 3, 5), 1..FRG_MAX_NODES; ignored for LPA */
     int n_phi;             /* phi nodes (family 3), 1..FRG_MAX_NODES; ignored otherwise */
     int precision;         /* frg_precision */
     double q_max;          /* radial upper limit in units of k, > 0 */
     double k;              /* RG scale, > 0 */
     double near_pole_tau;  /* FP32 form only: a propagator whose denominator D satisfies
                               D < tau (|Z l2 + R| + |m2|) is evaluated in float64; 0 = never */
+    /* families 4 and 5 only (ignored otherwise; zero them) */
+    double T;              /* temperature (same units as k), > 0 */
+    double freq_max;       /* explicit frequencies |w| <= freq_max (or freq_max * k), > 0 */
+    int statistics;        /* frg_statistics */
+    int n_tail;            /* GL nodes per side for the omitted frequencies; 0 = none */
+    int freq_scaled;       /* 0: Lambda = freq_max ("q0"); 1: Lambda = freq_max * k ("x0") */
+    int reserved;          /* zero */
 } frg_integral_desc;
 
 #define FRG_MAX_NODES 1024
+#define FRG_MAX_FT_NODES 65536
 #define FRG_MAX_TABLE 4096
 
 /* Dressing Z tabulated on n points log-uniform in |l| over [x_min, x_max] (device pointer),
  * linear in log|l| between points, constant outside.  values == NULL means Z == 1.
- * Ignored by family 1 (Z == 1 there). */
+ * Ignored by families 1 and 4 (Z == 1 there). */
 typedef struct {
     const double *values;
     int n;                 /* 2..FRG_MAX_TABLE */
@@ -116,8 +154,9 @@ typedef struct {
 /* One batch of n_ext external points sharing one descriptor and one dressing table. */
 typedef struct {
     int n_ext;             /* >= 0; 0 is a valid no-op */
-    const double *ext;     /* device. family 1: unused (may be NULL); family 2: p[n_ext];
-                              family 3: p[n_ext] followed by alpha[n_ext] (2 n_ext values) */
+    const double *ext;     /* device. families 1, 4: unused (may be NULL); family 2: p[n_ext];
+                              family 3: p[n_ext] followed by alpha[n_ext] (2 n_ext values);
+                              family 5: p[n_ext] followed by p0[n_ext] (2 n_ext values) */
     const double *m2;      /* device [n_ext] per-point m^2, or NULL to use m2_scalar */
     double m2_scalar;
     frg_log_table Z;
@@ -154,8 +193,8 @@ frg_status frg_integrate_batch(frg_context *ctx, const frg_integral_desc *desc,
 frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc *descs,
                                const frg_batch *batches, hipStream_t stream);
 
-/* Pick the tile shape (lanes per external point over radial nodes and, for the three-point
- * family, over cos1 nodes; radial chunks per external tile) of frg_integrate_batch and
+/* Pick the tile shape (lanes per external point over radial nodes and over cos1 nodes; radial
+ * chunks per external tile) of frg_integrate_batch and
  * frg_flow_rhs for this descriptor and batch size by timing the candidate shapes on the given
  * batch (its out buffer is overwritten with the integrals), and keep the fastest in the context.
  * If the environment variable FRG_AUTOTUNE_CACHE names a file, tuned shapes are loaded from it
@@ -163,6 +202,8 @@ frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc 
  * "family precision n_q n_x n_phi n_ext target lq_log2 chunks lx_log2" (target = 16 x CUs);
  * if FRG_AUTOTUNE_LOG names a file, every candidate's time is appended to it
  * ("family precision n_q n_x n_phi n_ext lq_log2 chunks lx_log2 us").
+ * Finite-temperature descriptors are keyed as their vacuum counterparts with n_q n_f radial
+ * nodes (family 4 as 1, family 5 as 2) and share their tuned shapes.
  * Results do not depend on the shape, only speed does.  Synchronises `stream`.
  * *best_us (optional) receives the best time per launch. */
 frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const frg_batch *batch,
@@ -178,18 +219,21 @@ frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const f
  *       through three neighbouring grid points (one-sided at the ends), and
  *       du_i/dt = 1/2 [ I(m_s^2) (3 u' + 2 rho u'') + (n_comp - 1) I(m_p^2) u' ]
  *       with t = log(Lambda/k) (Sec. 2.1).  Needs 2 n_ext integrals per call.
- *   families 2 and 3 (vertex expansion): state = m2_e per external point (floored at m2_floor),
- *       grid = the batch's ext array, and dstate_e/dt = coef * I_e.
+ *   family 4: the same at finite temperature (the paper's finite-temperature O(N) example,
+ *       Sec. 3.1), I the family-4 integral.
+ *   families 2, 3 and 5 (vertex expansion): state = m2_e per external point (floored at
+ *       m2_floor), grid = the batch's ext array, and dstate_e/dt = coef * I_e.
  */
 typedef struct {
     int family;
     int n_ext;
     const double *state;   /* device [n_ext] */
-    const double *grid;    /* device: family 1 rho[n_ext]; 2 p[n_ext]; 3 p, alpha [2 n_ext] */
-    frg_log_table Z;       /* families 2, 3 */
-    int n_comp;            /* family 1: N of O(N) (>= 1) */
+    const double *grid;    /* device: families 1, 4 rho[n_ext]; 2 p[n_ext]; 3 p, alpha and
+                              5 p, p0 [2 n_ext] */
+    frg_log_table Z;       /* families 2, 3, 5 */
+    int n_comp;            /* families 1, 4: N of O(N) (>= 1) */
     double m2_floor;       /* mass floor (-0.9 k^2 in the LPA workload) */
-    double coef;           /* families 2, 3: dstate/dt = coef * I */
+    double coef;           /* families 2, 3, 5: dstate/dt = coef * I */
 } frg_flow_state;
 
 /* dstate_dt (device [n_ext]) = RHS(state) for one flow (see frg_flow_state).  The whole chain

@@ -15,10 +15,15 @@ constexpr int kMaxTable = 4096;    // FRG_MAX_TABLE
 // Quadrature rules computed on the device once and cached by the context.
 //  radial (k = 1): q^_a, W^_a = w^_a q^_a^(d-1) Rdot^(q^_a^2), R^_a = R(q^_a^2)
 //  cos1:           x_b, xw_b = w_b sqrt(1 - x_b^2), xs_b = sqrt(1 - x_b^2)      (+ float copies)
+//                  (d = 3 spatial measure: xw_b = w_b)
 //  phi:            fc_c = cos(phi_c), fw_c = w_c sin(phi_c)                      (+ float copies)
+// Finite temperature: one radial rule over the index i = a n_f + j of radial node a and frequency
+// j (d = 3 spatial weights), with the frequency folded in: q^_i = q^_a, R^_i = R^_a + (w_j/k)^2,
+// W^_i = W^_a c_j / k, and w0_i = w_j (null for vacuum rules).
 struct RadialRule {
     const double *q, *W, *R;
     const float *qf, *Wf, *Rf;
+    const double *w0;
 };
 struct AngleRule {
     const double *x, *xw, *xs;
@@ -71,7 +76,13 @@ struct TileDev {
 hipError_t launch_rules(int n_q, double q_max, int d, int n_x, int n_phi, double *q, double *W,
                         double *R, float *qf, float *Wf, float *Rf, double *x, double *xw,
                         double *xs, float *xf, float *xwf, float *xsf, double *fc, double *fw,
-                        float *fcf, float *fwf, hipStream_t s);
+                        float *fcf, float *fwf, hipStream_t s, bool cos1_plain = false);
+// Finite-temperature radial rule (see RadialRule) from a d = 3 vacuum rule `base` of n_q nodes:
+// n_f frequencies, the first and last n_tail of them the tail nodes +-Omega/t (t GL on [0, 1],
+// weight Omega w_t/(2 pi t^2)), the rest 2 pi T (n + eta) for n = n_lo, n_lo + 1, ... (weight T).
+hipError_t launch_ft_rule(int n_q, int n_f, int n_tail, int n_lo, double eta, double T,
+                          double Omega, double k, const RadialRule &base, double *q, double *W,
+                          double *R, float *qf, float *Wf, float *Rf, double *w0, hipStream_t s);
 hipError_t launch_batch(const ReqDev *req_dev_host, const ReqDev *req_dev_ptr, int n_tiles,
                         int lds_bytes, double *contrib, unsigned *counters, hipStream_t s);
 // fam/prec: the family and precision shared by every request of the launch, or -1 (mixed).

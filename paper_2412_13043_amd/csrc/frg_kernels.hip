@@ -88,7 +88,7 @@ __device__ __forceinline__ void exp_pair64_prop(double y, double &e, double &E) 
 __global__ void __launch_bounds__(64) rules_kernel(
     int n_q, double q_max, int d, int n_x, int n_phi, double *q, double *W, double *R, float *qf,
     float *Wf, float *Rf, double *x, double *xw, double *xs, float *xf, float *xwf, float *xsf,
-    double *fc, double *fw, float *fcf, float *fwf) {
+    double *fc, double *fw, float *fcf, float *fwf, int cos1_plain) {
     const double pi = 3.141592653589793238462643383279502884;
     int which = blockIdx.y;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -123,12 +123,14 @@ __global__ void __launch_bounds__(64) rules_kernel(
         gl_root(n_x, i, th, w);
         double xv = cos(th), sv = sin(th);
         int slot = n_x - 1 - i;  // ascending x
+        // d = 4: dx sqrt(1 - x^2) from the second polar angle; d = 3 (cos1_plain): dx alone
+        const double wx = cos1_plain ? w : w * sv;
         x[slot] = xv;
         xs[slot] = sv;
-        xw[slot] = w * sv;
+        xw[slot] = wx;
         xf[slot] = (float)xv;
         xsf[slot] = (float)sv;
-        xwf[slot] = (float)(w * sv);
+        xwf[slot] = (float)wx;
     } else if (which == 2 && i < n_phi) {
         double th, w;
         gl_root(n_phi, i, th, w);
@@ -148,12 +150,62 @@ __global__ void __launch_bounds__(64) rules_kernel(
 hipError_t launch_rules(int n_q, double q_max, int d, int n_x, int n_phi, double *q, double *W,
                         double *R, float *qf, float *Wf, float *Rf, double *x, double *xw,
                         double *xs, float *xf, float *xwf, float *xsf, double *fc, double *fw,
-                        float *fcf, float *fwf, hipStream_t s) {
+                        float *fcf, float *fwf, hipStream_t s, bool cos1_plain) {
     int nmax = n_q > n_x ? n_q : n_x;
     nmax = nmax > n_phi ? nmax : n_phi;
     dim3 grid((nmax + 63) / 64, 3);
     hipLaunchKernelGGL(rules_kernel, grid, dim3(64), 0, s, n_q, q_max, d, n_x, n_phi, q, W, R,
-                       qf, Wf, Rf, x, xw, xs, xf, xwf, xsf, fc, fw, fcf, fwf);
+                       qf, Wf, Rf, x, xw, xs, xf, xwf, xsf, fc, fw, fcf, fwf, cos1_plain ? 1 : 0);
+    return hipGetLastError();
+}
+
+// Finite-temperature radial rule: entry i = a n_f + j of radial node a and frequency j (the
+// frequencies of one radial node adjacent, so that a wavefront's lanes share one spatial node
+// and whole wavefronts take the far-field path together).
+__global__ void __launch_bounds__(64) ft_rule_kernel(
+    int n_q, int n_f, int n_tail, int n_lo, double eta, double T, double Omega, double k,
+    const double *bq, const double *bW, const double *bR, double *q, double *W, double *R,
+    float *qf, float *Wf, float *Rf, double *w0) {
+    const double pi = 3.141592653589793238462643383279502884;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n_q * n_f) return;
+    const int a = (int)(i / n_f);
+    const int j = (int)(i - (long long)a * n_f);
+    double w, c;
+    if (j < n_tail || j >= n_f - n_tail) {
+        // tail node: t_s (ascending) = GL root on [0, 1]; negative side first (w = -Omega/t,
+        // ascending in w for ascending t), positive side mirrored (w = Omega/t, descending t)
+        const int s = j < n_tail ? j : n_f - 1 - j;
+        double th, gw;
+        gl_root(n_tail, n_tail - 1 - s, th, gw);  // root index n-1-s is the s-th smallest
+        const double ch = cos(0.5 * th);
+        const double t = ch * ch;
+        w = (j < n_tail ? -Omega : Omega) / t;
+        c = Omega * (0.5 * gw) / (t * t) / (2.0 * pi);
+    } else {
+        w = 2.0 * pi * T * ((double)(n_lo + (j - n_tail)) + eta);
+        c = T;
+    }
+    const double wh = w / k;
+    const double Ri = fma(wh, wh, bR[a]);
+    const double Wi = bW[a] * (c / k);
+    q[i] = bq[a];
+    R[i] = Ri;
+    W[i] = Wi;
+    qf[i] = (float)bq[a];
+    Rf[i] = (float)Ri;
+    Wf[i] = (float)Wi;
+    w0[i] = w;
+}
+
+hipError_t launch_ft_rule(int n_q, int n_f, int n_tail, int n_lo, double eta, double T,
+                          double Omega, double k, const RadialRule &base, double *q, double *W,
+                          double *R, float *qf, float *Wf, float *Rf, double *w0, hipStream_t s) {
+    const long long n = (long long)n_q * n_f;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ft_rule_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, n_q, n_f,
+                       n_tail, n_lo, eta, T, Omega, k, base.q, base.W, base.R, q, W, R, qf, Wf, Rf,
+                       w0);
     return hipGetLastError();
 }
 
@@ -321,12 +373,15 @@ __device__ __forceinline__ RadialTerm radial64(const ReqDev &r, const Smem &sm, 
     return t;
 }
 
-// Contribution of (e, a) to the two-point integral (without the global prefactor).
+// Contribution of (e, a) to the two-point integral (without the global prefactor).  m2 enters
+// the radial leg, m2x the inner leg: equal in vacuum; at finite temperature the inner leg's mass
+// term carries the shifted frequency, m2x = m2 + (w_j + p0)^2 (the radial leg's w_j^2 is folded
+// into the rule's R).
 __device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm, int a, double p,
-                                                double m2, double inv_k2) {
+                                                double m2, double m2x, double inv_k2) {
     // inner loop in units of k^2: y = l2/k^2 with G(l2) = G^(y)/k^2, G^ = 1/(Z y + R/k^2 + m2/k^2)
     const RadialTerm t = radial64(r, sm, a, p, m2);
-    const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2, m2h = m2 * inv_k2;
+    const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2, m2h = m2x * inv_k2;
     const int nx = r.n_x, nZ = r.nZ;
     const double za = r.za, zb1 = r.zbk + 1.0;
     double inner = 0.0;
@@ -493,9 +548,10 @@ __device__ __forceinline__ Par32 par32(const ReqDev &r, double m2, double inv_k2
 }
 
 __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm, int a, double p,
-                                                double m2, double inv_k2, float &kmax) {
+                                                double m2, double m2x, double inv_k2,
+                                                float &kmax) {
     const RadialTerm t = radial64(r, sm, a, p, m2);
-    const Par32 P = par32(r, m2, inv_k2);
+    const Par32 P = par32(r, m2x, inv_k2);
     const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2;  // y = l2/k^2 > 0 (see FRG_L2_TINY)
     Kahan32 acc{0.0f, 0.0f};
     const int nx = r.n_x;
@@ -527,12 +583,12 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
 // together when lx > 1; act marks the lanes with a point and radial node to evaluate.
 template <int PREC>
 __device__ __forceinline__ double contrib_two(const ReqDev &r, const Smem &sm, int a, double p,
-                                              double m2, double inv_k2, float &kmax, bool act,
-                                              int sx, int lx) {
+                                              double m2, double m2x, double inv_k2, float &kmax,
+                                              bool act, int sx, int lx) {
     if (lx == 1) {
         if (!act) return 0.0;
-        return (PREC == 0) ? contrib_two64(r, sm, a, p, m2, inv_k2)
-                           : contrib_two32(r, sm, a, p, m2, inv_k2, kmax);
+        return (PREC == 0) ? contrib_two64(r, sm, a, p, m2, m2x, inv_k2)
+                           : contrib_two32(r, sm, a, p, m2, m2x, inv_k2, kmax);
     }
     double wg = 0.0, c0 = 0.0, c1 = 0.0;
     Par32 P;
@@ -541,9 +597,9 @@ __device__ __forceinline__ double contrib_two(const ReqDev &r, const Smem &sm, i
         wg = t.wg;
         c0 = t.c0 * inv_k2;
         c1 = t.c1 * inv_k2;
-        if (PREC == 1) P = par32(r, m2, inv_k2);
+        if (PREC == 1) P = par32(r, m2x, inv_k2);
     }
-    const double m2h = m2 * inv_k2, za = r.za, zb1 = r.zbk + 1.0;
+    const double m2h = m2x * inv_k2, za = r.za, zb1 = r.zbk + 1.0;
     const int nx = r.n_x, nZ = r.nZ;
     const int xbase = (int)threadIdx.x & ~(lx - 1);
     const int nblk = nx - nx % FRG_ILP;  // nodes the float32 loop covers in whole blocks
@@ -803,8 +859,17 @@ __device__ __forceinline__ void tile_lpa(const ReqDev &r, int et) {
     if (r.err) r.err[e] = err;
 }
 
-// Vertex families: lanes = (external point, radial sub-lane); contributions to scratch; the last
-// chunk of an external tile adds them in radial order.
+// Value of v in lane l (l the same for every lane of the wavefront).
+__device__ __forceinline__ double readlane64(double v, int l) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Vertex families (FAM 2 two-point, 3 three-point, 5 two-point at finite temperature): lanes =
+// (external point, radial sub-lane, cos1 sub-lane); the point's contributions are added in radial
+// order inside the wavefront, or (radially chunked requests) stored for the finalize kernel.
 template <int FAM, int PREC>
 __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int et, int chunk,
                                             double *__restrict__ contrib,
@@ -828,11 +893,12 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
     // reset by the finalize kernel), then one slot for the dressing table's relative step
     unsigned *kslot = counters + r.ctr_base;
     float kmax = 1.0f;
-    double p = 0.0, m2 = 0.0, ca = 1.0, sa = 0.0;
+    double p = 0.0, m2 = 0.0, ca = 1.0, sa = 0.0, p0 = 0.0;
     if (valid) {
         p = r.ext[e];
         m2 = lane_m2(r, e);
         if (FAM == 3) sincos(r.ext[r.n_ext + e], &sa, &ca);
+        if (FAM == 5) p0 = r.ext[r.n_ext + e];
     }
     // contribution of radial node a (valid in the point's sx == 0 lanes); every lane of the
     // wavefront calls it together, lanes without work pass act = false
@@ -840,7 +906,14 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
         if (FAM == 3)
             return contrib_three<PREC>(r, sm, act ? a : 0, p, ca, sa, m2, inv_k2, kmax, act, sx,
                                        lx);
-        return contrib_two<PREC>(r, sm, act ? a : 0, p, m2, inv_k2, kmax, act, sx, lx);
+        if (FAM == 5) {
+            // radial index a = (frequency j, spatial node): the inner leg's frequency w_j + p0
+            const int ai = act ? a : 0;
+            const double wl = kc(r.rad.w0)[ai] + p0;
+            return contrib_two<PREC>(r, sm, ai, p, m2, fma(wl, wl, m2), inv_k2, kmax, act, sx,
+                                     lx);
+        }
+        return contrib_two<PREC>(r, sm, act ? a : 0, p, m2, m2, inv_k2, kmax, act, sx, lx);
     };
     if (r.chunks == 1) {
         // The wavefront holds every radial node of its points.  The lq radial sub-lanes of a
@@ -855,7 +928,13 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
             const int a = r0 + sq;
             const double v = node(a, valid && a < r.n_q);
             const int nk = min(lq, r.n_q - r0);
-            for (int k = 0; k < nk; ++k) sum += __shfl(v, base + k * lx);
+            if (lpl == 6) {
+                // one point per wavefront: the source lanes are the same for every lane, so the
+                // values are broadcast with scalar reads instead of LDS permutes (same additions)
+                for (int k = 0; k < nk; ++k) sum += readlane64(v, k * lx);
+            } else {
+                for (int k = 0; k < nk; ++k) sum += __shfl(v, base + k * lx);
+            }
         }
         if (PREC == 1) {
             for (int o = 1; o < (1 << lpl); o <<= 1) kmax = fmaxf(kmax, __shfl_xor(kmax, o));
@@ -931,6 +1010,8 @@ hipError_t launch_batch(const ReqDev *req_host, const ReqDev *req_dev_ptr, int n
         if (r.precision == 0) FRG_LAUNCH(1, 0); else FRG_LAUNCH(1, 1);
     } else if (r.family == 2) {
         if (r.precision == 0) FRG_LAUNCH(2, 0); else FRG_LAUNCH(2, 1);
+    } else if (r.family == 5) {
+        if (r.precision == 0) FRG_LAUNCH(5, 0); else FRG_LAUNCH(5, 1);
     } else {
         if (r.precision == 0) FRG_LAUNCH(3, 0); else FRG_LAUNCH(3, 1);
     }
@@ -956,6 +1037,11 @@ __device__ __forceinline__ void multi_tile(const ReqDev &r, Smem &sm, const Tile
             tile_vertex<2, 0>(r, sm, td.et, td.chunk, contrib, counters);
         else
             tile_vertex<2, 1>(r, sm, td.et, td.chunk, contrib, counters);
+    } else if (fam == 5) {
+        if (prec == 0)
+            tile_vertex<5, 0>(r, sm, td.et, td.chunk, contrib, counters);
+        else
+            tile_vertex<5, 1>(r, sm, td.et, td.chunk, contrib, counters);
     } else {
         if (prec == 0)
             tile_vertex<3, 0>(r, sm, td.et, td.chunk, contrib, counters);
@@ -1021,6 +1107,7 @@ static multi_fn multi_variant(int fam, int prec) {
     if (fam == 1) return prec == 0 ? multi_kernel<1, 0> : multi_kernel<1, 1>;
     if (fam == 2) return prec == 0 ? multi_kernel<2, 0> : multi_kernel<2, 1>;
     if (fam == 3) return prec == 0 ? multi_kernel<3, 0> : multi_kernel<3, 1>;
+    if (fam == 5) return prec == 0 ? multi_kernel<5, 0> : multi_kernel<5, 1>;
     return multi_kernel<-1, -1>;
 }
 

@@ -28,13 +28,73 @@ void clear_error() { g_last_error.clear(); }
 
 static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+frg_status freq_rule(const frg_integral_desc &d, FreqRule *out) {
+    if (!finite_pos(d.T) || !finite_pos(d.freq_max) || !finite_pos(d.k)) {
+        set_error("finite temperature needs T, freq_max and k finite and > 0");
+        return FRG_E_INVAL;
+    }
+    if (d.statistics != FRG_BOSONIC && d.statistics != FRG_FERMIONIC) {
+        set_error("statistics must be FRG_BOSONIC or FRG_FERMIONIC, got %d", d.statistics);
+        return FRG_E_INVAL;
+    }
+    if (d.n_tail < 0 || d.n_tail > FRG_MAX_NODES) {
+        set_error("n_tail must be in [0, %d], got %d", FRG_MAX_NODES, d.n_tail);
+        return FRG_E_INVAL;
+    }
+    const double pi = 3.141592653589793238462643383279502884;
+    FreqRule f;
+    f.T = d.T;
+    f.lambda = d.freq_scaled ? d.freq_max * d.k : d.freq_max;
+    f.eta = d.statistics == FRG_FERMIONIC ? 0.5 : 0.0;
+    // largest n >= 0 with 2 pi T (n + eta) <= Lambda
+    const double nh = std::floor(f.lambda / (2.0 * pi * d.T) - f.eta);
+    if (!(nh >= 0.0)) {
+        set_error("no Matsubara frequency inside |w| <= %g at T = %g", f.lambda, d.T);
+        return FRG_E_INVAL;
+    }
+    if (nh > (double)FRG_MAX_NODES) {
+        set_error("more than %d Matsubara frequencies inside |w| <= %g at T = %g", FRG_MAX_NODES,
+                  f.lambda, d.T);
+        return FRG_E_INVAL;
+    }
+    const int n_hi = (int)nh;
+    f.n_lo = d.statistics == FRG_FERMIONIC ? -n_hi - 1 : -n_hi;
+    f.n_exp = n_hi - f.n_lo + 1;
+    f.n_tail = d.n_tail;
+    f.n_f = f.n_exp + 2 * d.n_tail;
+    f.Omega = 2.0 * pi * d.T * ((double)n_hi + f.eta) + pi * d.T;
+    if (f.n_f > FRG_MAX_NODES) {
+        set_error("frequency rule has %d nodes (limit %d)", f.n_f, FRG_MAX_NODES);
+        return FRG_E_INVAL;
+    }
+    *out = f;
+    return FRG_OK;
+}
+
+frg_integral_desc plan_desc(const frg_integral_desc &d) {
+    frg_integral_desc p = d;
+    if (!is_ft(d.family)) return p;
+    FreqRule f;
+    if (freq_rule(d, &f) != FRG_OK) return p;
+    p.family = d.family == FRG_FAMILY_LPA_T ? FRG_FAMILY_LPA : FRG_FAMILY_TWO_POINT;
+    p.n_q = d.n_q * f.n_f;
+    return p;
+}
+
+double nodes_per_point(const frg_integral_desc &d) {
+    const frg_integral_desc p = plan_desc(d);
+    return (double)p.n_q * (is_vertex(p.family) ? p.n_x : 1) *
+           (p.family == FRG_FAMILY_THREE_POINT ? p.n_phi : 1);
+}
+
 frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_ptrs) {
     if (!d || !b) {
         set_error("null descriptor or batch");
         return FRG_E_INVAL;
     }
-    if (d->family < 1 || d->family > 3) {
-        set_error("family must be 1 (LPA), 2 (two-point) or 3 (three-point), got %d", d->family);
+    if (d->family < 1 || d->family > 5) {
+        set_error("family must be 1 (LPA), 2 (two-point), 3 (three-point), 4 (LPA at finite "
+                  "temperature) or 5 (two-point at finite temperature), got %d", d->family);
         return FRG_E_INVAL;
     }
     if (d->precision != FRG_FP64 && d->precision != FRG_FP32_KAHAN) {
@@ -54,7 +114,7 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
         set_error("n_q must be in [1, %d], got %d", FRG_MAX_NODES, d->n_q);
         return FRG_E_INVAL;
     }
-    if (d->family >= 2 && (d->n_x < 1 || d->n_x > FRG_MAX_NODES)) {
+    if (is_vertex(d->family) && (d->n_x < 1 || d->n_x > FRG_MAX_NODES)) {
         set_error("n_x must be in [1, %d], got %d", FRG_MAX_NODES, d->n_x);
         return FRG_E_INVAL;
     }
@@ -70,6 +130,16 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
         set_error("near_pole_tau must be in [0, 1)");
         return FRG_E_INVAL;
     }
+    if (is_ft(d->family)) {
+        FreqRule f;
+        const frg_status fs = freq_rule(*d, &f);
+        if (fs != FRG_OK) return fs;
+        if ((long long)d->n_q * f.n_f > FRG_MAX_FT_NODES) {
+            set_error("n_q * n_frequencies = %lld exceeds %d", (long long)d->n_q * f.n_f,
+                      FRG_MAX_FT_NODES);
+            return FRG_E_INVAL;
+        }
+    }
     if (b->n_ext < 0 || b->n_ext > (1 << 24)) {
         set_error("n_ext must be in [0, 2^24], got %d", b->n_ext);
         return FRG_E_INVAL;
@@ -79,7 +149,7 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
         set_error("out is NULL");
         return FRG_E_INVAL;
     }
-    if (d->family >= 2 && !b->ext) {
+    if (is_vertex(d->family) && !b->ext) {
         set_error("ext is NULL for a vertex family");
         return FRG_E_INVAL;
     }
@@ -87,7 +157,7 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
         set_error("m2_scalar is not finite");
         return FRG_E_INVAL;
     }
-    if (d->family >= 2 && b->Z.values) {
+    if (is_vertex(d->family) && b->Z.values) {
         if (b->Z.n < 2 || b->Z.n > FRG_MAX_TABLE) {
             set_error("dressing table size must be in [2, %d], got %d", FRG_MAX_TABLE, b->Z.n);
             return FRG_E_INVAL;
@@ -97,7 +167,7 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
             return FRG_E_INVAL;
         }
     }
-    if ((double)d->n_q * (double)b->n_ext > 2.0e9) {
+    if ((double)plan_desc(*d).n_q * (double)b->n_ext > 2.0e9) {
         set_error("n_q * n_ext too large for one batch");
         return FRG_E_INVAL;
     }
@@ -117,7 +187,7 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
                 return FRG_E_INVAL;
             }
         }
-        if (d->family >= 2 && b->Z.values) {
+        if (is_vertex(d->family) && b->Z.values) {
             hipPointerAttribute_t attr;
             if (hipPointerGetAttributes(&attr, b->Z.values) != hipSuccess ||
                 (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)) {
@@ -146,15 +216,16 @@ static frg_status get_radial(frg_context *ctx, int n, double q_max, int d, Radia
                                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                    nullptr, ctx->aux));
         FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
-        e->rule = RadialRule{q, W, R, qf, Wf, Rf};
+        e->rule = RadialRule{q, W, R, qf, Wf, Rf, nullptr};
         it = ctx->radial.emplace(key, std::move(e)).first;
     }
     *out = it->second->rule;
     return FRG_OK;
 }
 
-static frg_status get_cos1(frg_context *ctx, int n, AngleRule *out) {
-    auto it = ctx->cos1.find(n);
+static frg_status get_cos1(frg_context *ctx, int n, AngleRule *out, bool plain = false) {
+    const int key = n + (plain ? (1 << 20) : 0);
+    auto it = ctx->cos1.find(key);
     if (it == ctx->cos1.end()) {
         auto e = std::make_unique<AngleEntry>();
         FRG_HIP_CHECK(e->buf.alloc((size_t)n * (3 * sizeof(double) + 3 * sizeof(float)) + 64));
@@ -162,10 +233,34 @@ static frg_status get_cos1(frg_context *ctx, int n, AngleRule *out) {
         float *xf = (float *)(xs + n), *xwf = xf + n, *xsf = xwf + n;
         FRG_HIP_CHECK(launch_rules(0, 1.0, 1, n, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
                                    nullptr, x, xw, xs, xf, xwf, xsf, nullptr, nullptr, nullptr,
-                                   nullptr, ctx->aux));
+                                   nullptr, ctx->aux, plain));
         FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
         e->rule = AngleRule{x, xw, xs, xf, xwf, xsf};
-        it = ctx->cos1.emplace(n, std::move(e)).first;
+        it = ctx->cos1.emplace(key, std::move(e)).first;
+    }
+    *out = it->second->rule;
+    return FRG_OK;
+}
+
+// Finite-temperature radial rule: the frequency rule folded into a d = 3 radial rule.
+static frg_status get_ft_radial(frg_context *ctx, const frg_integral_desc &d, const FreqRule &f,
+                                RadialRule *out) {
+    auto key = std::make_tuple(d.n_q, d.q_max, d.k, d.T, f.lambda, d.statistics, d.n_tail);
+    auto it = ctx->ft_radial.find(key);
+    if (it == ctx->ft_radial.end()) {
+        RadialRule base;
+        frg_status st = get_radial(ctx, d.n_q, d.q_max, 3, &base);
+        if (st != FRG_OK) return st;
+        const size_t n = (size_t)d.n_q * (size_t)f.n_f;
+        auto e = std::make_unique<RadialEntry>();
+        FRG_HIP_CHECK(e->buf.alloc(n * (4 * sizeof(double) + 3 * sizeof(float)) + 64));
+        double *q = (double *)e->buf.ptr, *W = q + n, *R = W + n, *w0 = R + n;
+        float *qf = (float *)(w0 + n), *Wf = qf + n, *Rf = Wf + n;
+        FRG_HIP_CHECK(launch_ft_rule(d.n_q, f.n_f, f.n_tail, f.n_lo, f.eta, f.T, f.Omega, d.k,
+                                     base, q, W, R, qf, Wf, Rf, w0, ctx->aux));
+        FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
+        e->rule = RadialRule{q, W, R, qf, Wf, Rf, w0};
+        it = ctx->ft_radial.emplace(key, std::move(e)).first;
     }
     *out = it->second->rule;
     return FRG_OK;
@@ -198,9 +293,10 @@ static int ilog2(int v) {
     return r;
 }
 
-TileShape heuristic_shape(const frg_integral_desc &d, int n_ext, int target_waves,
+TileShape heuristic_shape(const frg_integral_desc &desc, int n_ext, int target_waves,
                           bool allow_chunks) {
     TileShape s;
+    const frg_integral_desc d = plan_desc(desc);
     if (d.family == 1) return s;
     // external points per wavefront: the smallest power of two >= n_ext, at least 4
     int le = kWave;
@@ -251,8 +347,10 @@ TileShape heuristic_shape(const frg_integral_desc &d, int n_ext, int target_wave
     return s;
 }
 
-TileShape choose_shape(frg_context *ctx, const frg_integral_desc &d, int n_ext, int target_waves,
-                       bool allow_chunks) {
+TileShape choose_shape(frg_context *ctx, const frg_integral_desc &desc, int n_ext,
+                       int target_waves, bool allow_chunks) {
+    // finite-temperature requests share the tuned shapes of their vacuum counterparts
+    const frg_integral_desc d = plan_desc(desc);
     std::vector<int> key = {d.family, d.precision, d.n_q, d.n_x, d.n_phi, n_ext, target_waves};
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end() && (allow_chunks || it->second.chunks == 1)) return it->second;
@@ -286,34 +384,47 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
                         ReqDev *out) {
     ReqDev r;
     std::memset(&r, 0, sizeof r);
-    r.family = d.family;
+    // kernel family: LPA at finite temperature runs the LPA kernel on the frequency-folded rule
+    const bool lpa = is_lpa(d.family), vertex = is_vertex(d.family);
+    FreqRule fr;
+    if (is_ft(d.family)) {
+        const frg_status fs = freq_rule(d, &fr);
+        if (fs != FRG_OK) return fs;
+    }
+    r.family = d.family == FRG_FAMILY_LPA_T ? FRG_FAMILY_LPA : d.family;
     r.d = d.d;
-    r.n_q = d.n_q;
-    r.n_x = d.family >= 2 ? d.n_x : 0;
+    r.n_q = is_ft(d.family) ? d.n_q * fr.n_f : d.n_q;
+    r.n_x = vertex ? d.n_x : 0;
     r.n_phi = d.family == 3 ? d.n_phi : 0;
     r.precision = d.precision;
     r.n_ext = b.n_ext;
-    r.lq_log2 = d.family == 1 ? 0 : shape.lq_log2;
-    r.lx_log2 = d.family >= 2 ? shape.lx_log2 : 0;
-    r.chunks = d.family == 1 ? 1 : shape.chunks;
+    r.lq_log2 = lpa ? 0 : shape.lq_log2;
+    r.lx_log2 = vertex ? shape.lx_log2 : 0;
+    r.chunks = lpa ? 1 : shape.chunks;
     int le = kWave >> (r.lq_log2 + r.lx_log2);
     r.ext_tiles = (b.n_ext + le - 1) / le;
     r.k = d.k;
     r.k2 = d.k * d.k;
     const double pi = 3.141592653589793238462643383279502884;
     double omega;
-    if (d.family == 1)
+    if (d.family == FRG_FAMILY_LPA)
         omega = 2.0 * std::pow(pi, 0.5 * d.d) / std::tgamma(0.5 * d.d) / std::pow(2.0 * pi, d.d);
-    else if (d.family == 2)
+    else if (d.family == FRG_FAMILY_TWO_POINT)
         omega = 4.0 * pi / std::pow(2.0 * pi, 4);
-    else
+    else if (d.family == FRG_FAMILY_THREE_POINT)
         omega = 2.0 * pi / std::pow(2.0 * pi, 4);
+    else if (d.family == FRG_FAMILY_LPA_T)
+        omega = 4.0 * pi / std::pow(2.0 * pi, 3);  // int d^3q/(2pi)^3, radial
+    else
+        omega = 2.0 * pi / std::pow(2.0 * pi, 3);  // int d^3q/(2pi)^3 = 2pi int q^2 dq dx/(2pi)^3
+    // vacuum: k^(d+2) from the k-scaled nodes, weights and Rdot; finite temperature: k^5 from the
+    // spatial part and one k from the frequency weights, which the rule holds as c_j/k
     r.pref = omega * std::pow(d.k, d.d + 2) * coef;
     r.m2_mode = b.m2 ? m2_mode : 0;
     r.m2s = b.m2_scalar;
     r.m2_floor = m2_floor;
     r.tau = d.precision == 1 ? d.near_pole_tau : 0.0;
-    if (d.family >= 2) {
+    if (vertex) {
         // without a dressing table the kernels look up a two-entry table of ones (Z == 1 exactly),
         // which keeps the inner loops free of branches
         const bool has = b.Z.values != nullptr;
@@ -326,10 +437,11 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
         r.zbk = r.zb + r.za * std::log(r.k2);
         r.Z = has ? b.Z.values : (const double *)ctx->ones.ptr;
     }
-    frg_status st = get_radial(ctx, d.n_q, d.q_max, d.d, &r.rad);
+    frg_status st = is_ft(d.family) ? get_ft_radial(ctx, d, fr, &r.rad)
+                                    : get_radial(ctx, d.n_q, d.q_max, d.d, &r.rad);
     if (st != FRG_OK) return st;
-    if (d.family >= 2) {
-        st = get_cos1(ctx, d.n_x, &r.ang);
+    if (vertex) {
+        st = get_cos1(ctx, d.n_x, &r.ang, d.family == FRG_FAMILY_TWO_POINT_T);
         if (st != FRG_OK) return st;
     }
     if (d.family == 3) {
@@ -575,6 +687,7 @@ frg_status frg_context_destroy(frg_context *ctx) {
     (void)hipDeviceSynchronize();
     ctx->graphs.clear();
     ctx->scratch.clear();
+    ctx->ft_radial.clear();
     ctx->radial.clear();
     ctx->cos1.clear();
     ctx->phi.clear();
@@ -613,7 +726,8 @@ frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const f
     }
     frg_status st = validate(desc, batch, true);
     if (st != FRG_OK) return st;
-    if (batch->n_ext == 0 || desc->family == 1) return FRG_OK;  // LPA has a single shape
+    if (batch->n_ext == 0 || is_lpa(desc->family)) return FRG_OK;  // LPA has a single shape
+    const frg_integral_desc pd = plan_desc(*desc);  // finite temperature: n_q n_f radial nodes
     std::lock_guard<std::mutex> lk(ctx->mu);
     FRG_HIP_CHECK(hipSetDevice(ctx->device));
     const int target = 16 * ctx->num_cus;
@@ -621,7 +735,7 @@ frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const f
     for (int lq = 0; lq <= 6; ++lq) {
         const int le = kWave >> lq;
         if (lq > 0 && le / 2 >= batch->n_ext) continue;  // narrower than needed
-        const int max_chunks = (desc->n_q + (1 << lq) - 1) >> lq;
+        const int max_chunks = (pd.n_q + (1 << lq) - 1) >> lq;
         for (int ch = 1; ch <= max_chunks; ch *= 2) cands.push_back(TileShape{lq, ch});
         if ((max_chunks & (max_chunks - 1)) != 0) cands.push_back(TileShape{lq, max_chunks});
         // cos1 nodes shared among lanes as well (single radial chunk)
@@ -659,8 +773,8 @@ frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const f
         if (const char *lp = std::getenv("FRG_AUTOTUNE_LOG")) {
             std::ofstream lf(lp, std::ios::app);
             if (lf)
-                lf << desc->family << ' ' << desc->precision << ' ' << desc->n_q << ' '
-                   << desc->n_x << ' ' << desc->n_phi << ' ' << batch->n_ext << ' ' << c.lq_log2
+                lf << pd.family << ' ' << pd.precision << ' ' << pd.n_q << ' ' << pd.n_x << ' '
+                   << pd.n_phi << ' ' << batch->n_ext << ' ' << c.lq_log2
                    << ' ' << c.chunks << ' ' << c.lx_log2 << ' ' << t_best << '\n';
         }
         if (t_best < best) {
@@ -674,8 +788,8 @@ frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const f
         if (res == FRG_E_DEVICE && g_last_error.empty()) set_error("autotune launch failed");
         return res;
     }
-    std::vector<int> key = {desc->family, desc->precision, desc->n_q, desc->n_x, desc->n_phi,
-                            batch->n_ext, target};
+    std::vector<int> key = {pd.family, pd.precision, pd.n_q, pd.n_x, pd.n_phi, batch->n_ext,
+                            target};
     ctx->tuned[key] = best_shape;
     if (best_us) *best_us = best;
     if (!ctx->tune_path.empty()) {
@@ -722,9 +836,7 @@ frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc 
             set_error("batch %d: %s", i, m.c_str());
             return st;
         }
-        const frg_integral_desc &d = descs[i];
-        double per = (double)d.n_q * (d.family >= 2 ? d.n_x : 1) * (d.family == 3 ? d.n_phi : 1);
-        nodes[i] = per * batches[i].n_ext;
+        nodes[i] = nodes_per_point(descs[i]) * batches[i].n_ext;
         total_nodes += nodes[i];
     }
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -768,12 +880,12 @@ frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
         return FRG_E_INVAL;
     }
     const int n = state->n_ext;
-    if (!state->state || !state->grid || n < (desc->family == 1 ? 3 : 1)) {
-        set_error("flow state needs state and grid pointers and n_ext >= %d",
-                  desc->family == 1 ? 3 : 1);
+    const bool lpa = is_lpa(desc->family);
+    if (!state->state || !state->grid || n < (lpa ? 3 : 1)) {
+        set_error("flow state needs state and grid pointers and n_ext >= %d", lpa ? 3 : 1);
         return FRG_E_INVAL;
     }
-    if (desc->family == 1 && state->n_comp < 1) {
+    if (lpa && state->n_comp < 1) {
         set_error("n_comp must be >= 1");
         return FRG_E_INVAL;
     }
@@ -784,8 +896,8 @@ frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
     // the batch the integrals run on (pointers filled below)
     frg_batch b;
     std::memset(&b, 0, sizeof b);
-    b.n_ext = desc->family == 1 ? 2 * n : n;
-    b.ext = desc->family == 1 ? nullptr : state->grid;
+    b.n_ext = lpa ? 2 * n : n;
+    b.ext = lpa ? nullptr : state->grid;
     b.m2 = state->state;
     b.Z = state->Z;
     b.out = dstate_dt;
@@ -798,8 +910,11 @@ frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
                                   desc->precision, n, state->n_comp, (long long)stream,
                                   (long long)state->state, (long long)state->grid,
                                   (long long)state->Z.values, state->Z.n, (long long)dstate_dt};
-    double dk[7] = {desc->q_max, desc->k, desc->near_pole_tau, state->m2_floor, state->coef,
-                    state->Z.x_min, state->Z.x_max};
+    key.push_back(desc->statistics);
+    key.push_back(desc->n_tail);
+    key.push_back(desc->freq_scaled);
+    double dk[9] = {desc->q_max, desc->k,        desc->near_pole_tau, state->m2_floor, state->coef,
+                    state->Z.x_min, state->Z.x_max, desc->T, desc->freq_max};
     for (double v : dk) {
         long long bits;
         std::memcpy(&bits, &v, sizeof bits);
@@ -810,7 +925,7 @@ frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
         auto g = std::make_unique<FlowGraph>();
         TileShape shape = choose_shape(ctx, *desc, b.n_ext, 16 * ctx->num_cus);
         ReqDev r;
-        if (desc->family == 1) {
+        if (lpa) {
             // the fused kernel takes rules, prefactor and precision from r; masses come from
             // the state inside it
             if ((st = make_request(ctx, *desc, b, shape, 1, 0.0, 1.0, &r)) != FRG_OK) return st;
@@ -828,7 +943,7 @@ frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
         r.contrib_base = 0;
         r.ctr_base = 0;
         g->r = r;
-        g->family = desc->family;
+        g->family = r.family;  // kernel family: 1 for both LPA families
         g->n = n;
         g->n_comp = state->n_comp;
         g->grid = state->grid;

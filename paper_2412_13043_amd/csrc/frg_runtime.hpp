@@ -95,6 +95,33 @@ struct TileShape {
 
 struct FlowGraph;
 
+// Families by what they read: vertex families take external momenta and a dressing table.
+inline bool is_vertex(int fam) {
+    return fam == FRG_FAMILY_TWO_POINT || fam == FRG_FAMILY_THREE_POINT ||
+           fam == FRG_FAMILY_TWO_POINT_T;
+}
+inline bool is_ft(int fam) { return fam == FRG_FAMILY_LPA_T || fam == FRG_FAMILY_TWO_POINT_T; }
+inline bool is_lpa(int fam) { return fam == FRG_FAMILY_LPA || fam == FRG_FAMILY_LPA_T; }
+// doubles of the ext array for n points
+inline long long ext_values(int fam, long long n) {
+    if (fam == FRG_FAMILY_THREE_POINT || fam == FRG_FAMILY_TWO_POINT_T) return 2 * n;
+    return fam == FRG_FAMILY_TWO_POINT ? n : 0;
+}
+
+// Matsubara frequency rule of a finite-temperature descriptor: frequencies 2 pi T (n + eta) for
+// n = n_lo .. n_lo + n_exp - 1 (every |w| <= Lambda), and n_tail tail nodes per side beyond
+// Omega; n_f = n_exp + 2 n_tail.
+struct FreqRule {
+    int n_f = 0, n_exp = 0, n_lo = 0, n_tail = 0;
+    double eta = 0.0, T = 0.0, Omega = 0.0, lambda = 0.0;
+};
+frg_status freq_rule(const frg_integral_desc &d, FreqRule *out);
+// The descriptor as planning sees it: a finite-temperature family as its vacuum counterpart
+// (LPA or two-point) with n_q n_f radial nodes.  Other descriptors are returned unchanged.
+frg_integral_desc plan_desc(const frg_integral_desc &d);
+// Integrand nodes per external point.
+double nodes_per_point(const frg_integral_desc &d);
+
 }  // namespace frg
 
 struct frg_context {
@@ -106,7 +133,11 @@ struct frg_context {
     frg::DeviceBuffer logtab;   // float64 logarithm table (double2[256])
     frg::DeviceBuffer ones;     // {1, 1}: dressing table of requests without one
     std::map<std::tuple<int, double, int>, std::unique_ptr<frg::RadialEntry>> radial;
-    std::map<int, std::unique_ptr<frg::AngleEntry>> cos1;
+    std::map<int, std::unique_ptr<frg::AngleEntry>> cos1;  // key n (+ 1 << 20: d = 3 weights)
+    // finite-temperature radial rules by (n_q, q_max, k, T, Lambda, statistics, n_tail)
+    std::map<std::tuple<int, double, double, double, double, int, int>,
+             std::unique_ptr<frg::RadialEntry>>
+        ft_radial;
     std::map<int, std::unique_ptr<frg::PhiEntry>> phi;
     std::map<hipStream_t, std::unique_ptr<frg::Scratch>> scratch;
     std::map<std::vector<long long>, std::unique_ptr<frg::FlowGraph>> graphs;  // flow RHS plans

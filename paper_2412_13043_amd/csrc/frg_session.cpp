@@ -197,7 +197,7 @@ class HipExecutor : public Executor {
         for (SessReq *r : sl.reqs) {
             frg_batch b = r->host;
             char *blk = base + r->arena_off;
-            b.ext = r->desc.family >= 2 ? (const double *)(blk + r->off_ext) : nullptr;
+            b.ext = is_vertex(r->desc.family) ? (const double *)(blk + r->off_ext) : nullptr;
             b.m2 = r->host.m2 ? (const double *)(blk + r->off_m2) : nullptr;
             b.out = (double *)(blk + r->off_out);
             b.err_out = r->host.err_out ? (double *)(blk + r->off_err) : nullptr;
@@ -258,10 +258,10 @@ class HipExecutor : public Executor {
         for (SessReq *r : sl.reqs) {
             char *dst = h + pos;
             const int n = r->host.n_ext;
-            if (r->desc.family >= 2)
+            if (is_vertex(r->desc.family))
                 std::memcpy(dst + r->off_ext, r->host.ext, (size_t)r->n_ext_vals * 8);
             if (r->host.m2) std::memcpy(dst + r->off_m2, r->host.m2, (size_t)n * 8);
-            if (r->table_id < 0 && r->host.Z.values && r->desc.family >= 2)
+            if (r->table_id < 0 && r->host.Z.values && is_vertex(r->desc.family))
                 std::memcpy(dst + r->off_z, r->host.Z.values, (size_t)r->host.Z.n * 8);
             if (r->in_bytes)
                 FRG_HIP_CHECK(hipMemcpyAsync(base + r->arena_off, dst, r->in_bytes,
@@ -448,13 +448,13 @@ static size_t request_layout(SessReq &r) {
     const frg_integral_desc &d = r.desc;
     const int n = r.host.n_ext;
     size_t off = 0;
-    r.n_ext_vals = d.family == 3 ? 2 * n : (d.family == 2 ? n : 0);
+    r.n_ext_vals = (int)ext_values(d.family, n);
     r.off_ext = off;
     off += (size_t)r.n_ext_vals * 8;
     r.off_m2 = off;
     if (r.host.m2) off += (size_t)n * 8;
     r.off_z = off;
-    if (r.table_id < 0 && r.host.Z.values && d.family >= 2) off += (size_t)r.host.Z.n * 8;
+    if (r.table_id < 0 && r.host.Z.values && is_vertex(d.family)) off += (size_t)r.host.Z.n * 8;
     r.in_bytes = off;
     off = align256(off);
     r.off_out = off;
@@ -462,7 +462,8 @@ static size_t request_layout(SessReq &r) {
     r.off_err = off;
     if (r.host.err_out) off += align256((size_t)n * 8);
     r.off_contrib = off;
-    if (d.family >= 2) off += align256((size_t)d.n_q * n * 8);
+    // contributions of radially chunked requests (n_q n_f radial nodes at finite temperature)
+    if (is_vertex(d.family)) off += align256((size_t)plan_desc(d).n_q * n * 8);
     return align256(off);
 }
 
@@ -572,8 +573,7 @@ frg_status frg_session_submit(frg_session *s, const frg_integral_desc *desc,
         }
     }
     const frg_integral_desc &d = *desc;
-    r->nodes = (uint64_t)batch_host->n_ext * (uint64_t)d.n_q * (d.family >= 2 ? d.n_x : 1) *
-               (d.family == 3 ? d.n_phi : 1);
+    r->nodes = (uint64_t)((double)batch_host->n_ext * nodes_per_point(d));
     r->footprint = request_layout(*r);
     r->t_submit = now_us();
     std::lock_guard<std::mutex> lk(s->mu);

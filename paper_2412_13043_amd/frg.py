@@ -33,7 +33,10 @@ FRG_OK, FRG_E_INVAL, FRG_E_NOMEM, FRG_E_DEVICE, FRG_E_NOTREADY, FRG_E_TIMEOUT, \
     FRG_E_CANCELLED, FRG_E_UNSUPPORTED = range(8)
 FRG_FP64, FRG_FP32_KAHAN = 0, 1
 FRG_FAMILY_LPA, FRG_FAMILY_TWO_POINT, FRG_FAMILY_THREE_POINT = 1, 2, 3
+FRG_FAMILY_LPA_T, FRG_FAMILY_TWO_POINT_T = 4, 5
+FRG_BOSONIC, FRG_FERMIONIC = 0, 1
 FRG_MAX_NODES = 1024
+FRG_MAX_FT_NODES = 65536
 FRG_MAX_TABLE = 4096
 
 STATUS_NAMES = {0: "FRG_OK", 1: "FRG_E_INVAL", 2: "FRG_E_NOMEM", 3: "FRG_E_DEVICE",
@@ -51,7 +54,9 @@ class FrgError(RuntimeError):
 class frg_integral_desc(ctypes.Structure):
     _fields_ = [("family", c_int), ("d", c_int), ("n_q", c_int), ("n_x", c_int),
                 ("n_phi", c_int), ("precision", c_int), ("q_max", c_double), ("k", c_double),
-                ("near_pole_tau", c_double)]
+                ("near_pole_tau", c_double), ("T", c_double), ("freq_max", c_double),
+                ("statistics", c_int), ("n_tail", c_int), ("freq_scaled", c_int),
+                ("reserved", c_int)]
 
 
 class frg_log_table(ctypes.Structure):
@@ -241,10 +246,15 @@ def _stream(stream) -> int:
 
 
 def make_desc(family: int, n_q: int, q_max: float, *, n_x: int = 0, n_phi: int = 0, d: int = 0,
-              k: float = 1.0, precision: int = FRG_FP64, near_pole_tau: float = 0.0):
+              k: float = 1.0, precision: int = FRG_FP64, near_pole_tau: float = 0.0,
+              T: float = 0.0, freq_max: float = 0.0, statistics: int = FRG_BOSONIC,
+              n_tail: int = 0, freq_scaled: bool = False):
+    """Descriptor; T, freq_max, statistics, n_tail and freq_scaled apply to the finite-temperature
+    families (4, 5) only."""
     if d == 0:
         d = 3 if family == FRG_FAMILY_LPA else 4
-    return frg_integral_desc(family, d, n_q, n_x, n_phi, precision, q_max, k, near_pole_tau)
+    return frg_integral_desc(family, d, n_q, n_x, n_phi, precision, q_max, k, near_pole_tau,
+                             T, freq_max, statistics, n_tail, 1 if freq_scaled else 0, 0)
 
 
 def make_batch(n_ext: int, out, *, ext=None, m2=None, m2_scalar: float = 0.0, Z=None,

@@ -154,6 +154,29 @@ def near_pole_batch(B: int = 256, seed_m2_base: int = 400, seed_z_base: int = 10
 
 
 # ------------------------------------------------------------------------------------------
+# Finite temperature (d = 3 + 1, Matsubara sum): the two-point workload's shapes at T = 0.1 k,
+# bosonic frequencies |w| <= 10 k ("q0": fixed domain, the radial range's scale) plus 8 tail
+# nodes per side, GL64 on [0, 10k] x GL32 in cos1; external frequency 0 (bosonic lowest) for
+# half the points and 2 pi T for the other half; per-RHS Z tables; the LPA on the rho grid.
+# ------------------------------------------------------------------------------------------
+FT_T = 0.1
+FT_FREQ_MAX = 10.0
+FT_N_TAIL = 8
+FT_NQ = 64
+FT_NX = 32
+FT_QMAX = 10.0
+
+
+def two_point_ft_batch(B: int = 16, seed_base: int = 1000):
+    """B right-hand sides: p (256 log-spaced) and p0 (0 for even, 2 pi T for odd points),
+    m2 = 0.5, Z tables (seeds 1000+b)."""
+    p = momenta_log()
+    p0 = np.where(np.arange(p.size) % 2 == 1, 2.0 * math.pi * FT_T, 0.0)
+    Z = np.stack([dressing_table(seed_base + b) for b in range(B)])
+    return p, p0, TWO_M2, Z
+
+
+# ------------------------------------------------------------------------------------------
 # Workload 5: serving mix of many concurrent time-steppers
 # ------------------------------------------------------------------------------------------
 @dataclasses.dataclass

@@ -166,3 +166,62 @@ def test_invalid_session_arguments():
     tid = frg.frg_session_register_table(s, Z.ctypes.data, 16, 1e-3, 1e3)
     assert tid == 0
     frg.frg_session_close(s)
+
+
+def _ft_desc(**kw):
+    args = dict(n_x=8, T=0.2, freq_max=5.0, statistics=frg.FRG_BOSONIC, n_tail=4)
+    args.update(kw)
+    return frg.make_desc(frg.FRG_FAMILY_TWO_POINT_T, 16, 6.0, **args)
+
+
+def test_finite_temperature_descriptors_are_validated_at_submit():
+    s = frg.frg_session_open_fake(_cfg(budget=64 << 20), 1.0, 1.0)
+    n = 32
+    ext = np.concatenate([np.linspace(0.1, 3.0, n), np.zeros(n)])  # p then p0
+    out = np.full(n, -1.0)
+    b = frg.frg_batch(n, ext.ctypes.data, None, 0.5, frg.frg_log_table(None, 0, 1e-3, 1e3),
+                      out.ctypes.data, None)
+    t = frg.frg_session_submit(s, _ft_desc(), b, -1)
+    assert frg.frg_session_wait(s, t, 5000) == frg.FRG_OK
+    bad = [dict(T=0.0), dict(T=float("nan")), dict(freq_max=-1.0), dict(statistics=2),
+           dict(n_tail=-1), dict(n_tail=frg.FRG_MAX_NODES + 1),
+           # fermionic with Lambda < pi T: no explicit frequency
+           dict(statistics=frg.FRG_FERMIONIC, T=1.0, freq_max=1.0),
+           # more than FRG_MAX_NODES frequencies
+           dict(T=1e-4, freq_max=10.0),
+           # 16 radial nodes x 2000+ frequencies > FRG_MAX_FT_NODES
+           dict(T=0.01, freq_max=60.0, n_tail=100)]
+    for kw in bad:
+        with pytest.raises(frg.FrgError) as ei:
+            frg.frg_session_submit(s, _ft_desc(**kw), b, -1)
+        assert ei.value.status == frg.FRG_E_INVAL, kw
+    d = _ft_desc()
+    d.family = 6
+    with pytest.raises(frg.FrgError):
+        frg.frg_session_submit(s, d, b, -1)
+    frg.frg_session_close(s)
+
+
+def test_finite_temperature_footprint_counts_every_frequency():
+    # T = 0.2, Lambda = 5: bosonic |2 pi n T| <= 5 gives n = -3..3 (7), plus 2 x 4 tail nodes:
+    # 15 frequencies, so the [n_q n_f][n_ext] contribution block is 15 times the vacuum one
+    n, n_q = 256, 16
+    a = lambda v: (v + 255) // 256 * 256
+    vac = a(a(n * 8) + a(n * 8) + a(n_q * n * 8))
+    ft = a(a(2 * n * 8) + a(n * 8) + a(15 * n_q * n * 8))
+    budget = (vac + ft) // 2  # the vacuum request fits, the finite-temperature one does not
+    s = frg.frg_session_open_fake(_cfg(budget=max(budget, 4096)), 1.0, 1.0)
+    p = np.linspace(0.1, 3.0, n)
+    ext = np.concatenate([p, np.zeros(n)])
+    out = np.empty(n)
+    zt = frg.frg_log_table(None, 0, 1e-3, 1e3)
+    bv = frg.frg_batch(n, p.ctypes.data, None, 0.5, zt, out.ctypes.data, None)
+    bt = frg.frg_batch(n, ext.ctypes.data, None, 0.5, zt, out.ctypes.data, None)
+    t = frg.frg_session_submit(s, frg.make_desc(frg.FRG_FAMILY_TWO_POINT, n_q, 6.0, n_x=8), bv, -1)
+    assert frg.frg_session_wait(s, t, 5000) == frg.FRG_OK
+    with pytest.raises(frg.FrgError) as ei:
+        frg.frg_session_submit(s, _ft_desc(), bt, -1)
+    assert ei.value.status == frg.FRG_E_NOMEM
+    st = frg.frg_session_stats(s)
+    assert st.nodes == n * n_q * 8
+    frg.frg_session_close(s)
