@@ -247,6 +247,60 @@ typedef struct {
 frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
                         const frg_flow_state *state, double *dstate_dt, hipStream_t stream);
 
+/* ---- adaptive flow stepper ------------------------------------------------------------------ */
+
+/*
+ * Integrates a flow dstate/dt = RHS(state; k(t)) in RG time t = log(Lambda/k) (Sec. 2.1), with
+ * k(t) = Lambda exp(-t) and Lambda = desc->k, by the explicit embedded Runge-Kutta pair of
+ * Dormand and Prince, order 5(4), with first-same-as-last stages (the RK45 class of explicit
+ * steppers of Sec. 5.2 "Time-stepping", favoured there for vertex expansions).  RHS is the
+ * right-hand side of frg_flow_rhs for the same descriptor and flow state, re-evaluated at the
+ * stage's k (rules, prefactors, dressing coordinates and, at finite temperature, the frequency
+ * rule follow k; the dressing table and grid stay as given; the mass floor keeps its ratio to
+ * k^2: m2_floor (k/Lambda)^2).
+ *
+ * Step control: err = sqrt(mean_i (e_i / (atol + rtol max(|y_i|, |ynew_i|)))^2) with e the
+ * difference of the fifth- and fourth-order solutions; a step with err <= 1 is accepted; the
+ * next step is h min(fac_max, max(0.2, 0.9 err^(-1/5))), fac_max = 5 (1 right after a
+ * rejection), clipped to [h_min, h_max] and to the end of the interval.  fixed_step = 1 takes
+ * steps of h0 (the last one shortened to end at t_end) without control.
+ *
+ * Everything per step runs on `stream` on the device -- seven stage vectors, six right-hand
+ * sides, the stage combinations and the error norm -- except the accept/reject decision, for
+ * which the host reads one float64 per step.  The state (flow_state.state) is updated in place
+ * on the device; the stepper owns its stage buffers (allocated at creation).
+ */
+typedef struct {
+    double rtol, atol;        /* > 0 */
+    double h0;                /* first step (or the fixed step), > 0 */
+    double h_min, h_max;      /* 0 < h_min <= h_max */
+    int max_steps;            /* attempted steps per frg_stepper_advance call, >= 1 */
+    int fixed_step;           /* 1: steps of exactly h0, no error control */
+} frg_stepper_config;
+
+typedef struct {
+    double t;                 /* RG time reached */
+    double h;                 /* next step size */
+    double last_err;          /* error norm of the last attempted step (0 with fixed_step) */
+    uint64_t accepted, rejected, rhs_evals;  /* totals since creation */
+} frg_stepper_stats;
+
+typedef struct frg_stepper frg_stepper;
+
+/* The stepper starts at t = 0 (k = desc->k).  desc, state and cfg are copied; the device
+ * buffers state->state (evolved in place), state->grid and state->Z.values must stay valid for
+ * the stepper's lifetime.  Families as frg_flow_rhs. */
+frg_status frg_stepper_create(frg_context *ctx, const frg_integral_desc *desc,
+                              const frg_flow_state *state, const frg_stepper_config *cfg,
+                              frg_stepper **out);
+/* Advance to t_end (>= the current t) or until max_steps attempts; synchronises `stream` once
+ * per step.  FRG_E_TIMEOUT if max_steps ran out first (the state is valid at stats->t),
+ * FRG_E_INVAL if the step size fell below h_min or the error norm is not finite (the state is
+ * the last accepted one). */
+frg_status frg_stepper_advance(frg_stepper *st, double t_end, hipStream_t stream,
+                               frg_stepper_stats *stats);
+frg_status frg_stepper_destroy(frg_stepper *st);
+
 /* ---- serving -------------------------------------------------------------------------------- */
 
 typedef struct {

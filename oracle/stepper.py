@@ -1,0 +1,109 @@
+"""Adaptive explicit Runge-Kutta stepper of the oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may use
+this module; the product library never does.  Plain numpy, one stage at a time.
+
+What it computes: the flow dstate/dt = f(t, state) in RG time t = log(Lambda/k) (paper Sec. 2.1)
+advanced by the embedded Runge-Kutta pair of Dormand and Prince, order 5(4), with the last stage
+reused as the next step's first ("first same as last") -- the RK45 class of explicit steppers the
+paper lists for vertex expansions (Sec. 5.2, "Time-stepping").  The tableau is the published one
+(J. R. Dormand, P. J. Prince, J. Comput. Appl. Math. 6 (1980) 19, RK5(4)7M); error norm and
+step-size rule are the standard ones of Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4:
+
+    sc_i = atol + rtol max(|y_i|, |ynew_i|),  err = sqrt(mean_i ((ynew_i - yhat_i)/sc_i)^2),
+    accept if err <= 1,  h_next = h min(facmax, max(0.2, 0.9 err^(-1/5))),
+    facmax = 5, or 1 right after a rejected step; h_next clipped to [h_min, h_max].
+
+A step that would pass t_end ends exactly there.  fixed_step: steps of exactly h0, no control.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction as F
+
+import numpy as np
+
+# Dormand-Prince RK5(4)7M, exact fractions
+C = [F(0), F(1, 5), F(3, 10), F(4, 5), F(8, 9), F(1), F(1)]
+A = [
+    [],
+    [F(1, 5)],
+    [F(3, 40), F(9, 40)],
+    [F(44, 45), F(-56, 15), F(32, 9)],
+    [F(19372, 6561), F(-25360, 2187), F(64448, 6561), F(-212, 729)],
+    [F(9017, 3168), F(-355, 33), F(46732, 5247), F(49, 176), F(-5103, 18656)],
+    [F(35, 384), F(0), F(500, 1113), F(125, 192), F(-2187, 6784), F(11, 84)],
+]
+B = A[6] + [F(0)]  # fifth order
+BHAT = [F(5179, 57600), F(0), F(7571, 16695), F(393, 640), F(-92097, 339200), F(187, 2100),
+        F(1, 40)]  # fourth order (embedded)
+
+
+class Dopri5:
+    """State: t, y, the next step size h, the first stage of the next step (if known)."""
+
+    def __init__(self, f, y0, *, rtol, atol, h0, h_min, h_max, max_steps, fixed_step=False,
+                 t0=0.0):
+        self.f = f
+        self.y = np.array(y0, dtype=np.float64)
+        self.t = float(t0)
+        self.rtol, self.atol = rtol, atol
+        self.h0, self.h_min, self.h_max = h0, h_min, h_max
+        self.h = min(max(h0, h_min), h_max)
+        self.max_steps = max_steps
+        self.fixed = fixed_step
+        self.k0 = None
+        self.rejected_last = False
+        self.accepted = 0
+        self.rejected = 0
+        self.evals = 0
+        self.last_err = 0.0
+
+    def _f(self, t, y):
+        self.evals += 1
+        return np.asarray(self.f(t, y), dtype=np.float64)
+
+    def advance(self, t_end):
+        """Advance to t_end; returns "ok", "max_steps" or "h_min"."""
+        attempts = 0
+        while self.t < t_end:
+            if attempts >= self.max_steps:
+                return "max_steps"
+            attempts += 1
+            h = self.h0 if self.fixed else self.h
+            last = self.t + h >= t_end * (1.0 - 1e-14) - 1e-300
+            if last:
+                h = t_end - self.t
+            if self.k0 is None:
+                self.k0 = self._f(self.t, self.y)
+            K = [self.k0]
+            for s in range(1, 7):
+                incr = sum(float(A[s][j]) * K[j] for j in range(s))
+                K.append(self._f(self.t + float(C[s]) * h, self.y + h * incr))
+            ynew = self.y + h * sum(float(B[j]) * K[j] for j in range(6))
+            if self.fixed:
+                err = 0.0
+            else:
+                est = h * sum(float(B[j] - BHAT[j]) * K[j] for j in range(7))
+                sc = self.atol + self.rtol * np.maximum(np.abs(self.y), np.abs(ynew))
+                err = math.sqrt(float(np.mean((est / sc) ** 2)))
+            self.last_err = err
+            if self.fixed or err <= 1.0:
+                self.y = ynew
+                self.k0 = K[6]
+                self.t = t_end if last else self.t + h
+                self.accepted += 1
+                if self.fixed:
+                    continue
+                fac = 0.9 * err ** -0.2 if err > 0 else 5.0
+                fmax = 1.0 if self.rejected_last else 5.0
+                self.h = min(max(h * min(fmax, max(0.2, fac)), self.h_min), self.h_max)
+                self.rejected_last = False
+            else:
+                self.rejected += 1
+                self.rejected_last = True
+                if h <= self.h_min:
+                    return "h_min"
+                fac = 0.9 * err ** -0.2
+                self.h = min(max(h * min(1.0, max(0.2, fac)), self.h_min), self.h_max)
+        return "ok"

@@ -242,24 +242,42 @@ static frg_status get_cos1(frg_context *ctx, int n, AngleRule *out, bool plain =
     return FRG_OK;
 }
 
-// Finite-temperature radial rule: the frequency rule folded into a d = 3 radial rule.
+size_t ft_rule_bytes(int n_q, int n_f) {
+    return (size_t)n_q * (size_t)n_f * (4 * sizeof(double) + 3 * sizeof(float)) + 64;
+}
+
+frg_status ft_rule_into(frg_context *ctx, const frg_integral_desc &d, void *buf, size_t bytes,
+                        RadialRule *out, hipStream_t s) {
+    FreqRule f;
+    frg_status st = freq_rule(d, &f);
+    if (st != FRG_OK) return st;
+    if (ft_rule_bytes(d.n_q, f.n_f) > bytes) {
+        set_error("finite-temperature rule buffer too small");
+        return FRG_E_INVAL;
+    }
+    RadialRule base;
+    if ((st = get_radial(ctx, d.n_q, d.q_max, 3, &base)) != FRG_OK) return st;
+    const size_t n = (size_t)d.n_q * (size_t)f.n_f;
+    double *q = (double *)buf, *W = q + n, *R = W + n, *w0 = R + n;
+    float *qf = (float *)(w0 + n), *Wf = qf + n, *Rf = Wf + n;
+    FRG_HIP_CHECK(launch_ft_rule(d.n_q, f.n_f, f.n_tail, f.n_lo, f.eta, f.T, f.Omega, d.k, base, q,
+                                 W, R, qf, Wf, Rf, w0, s));
+    *out = RadialRule{q, W, R, qf, Wf, Rf, w0};
+    return FRG_OK;
+}
+
+// Finite-temperature radial rule: the frequency rule folded into a d = 3 radial rule, cached.
 static frg_status get_ft_radial(frg_context *ctx, const frg_integral_desc &d, const FreqRule &f,
                                 RadialRule *out) {
     auto key = std::make_tuple(d.n_q, d.q_max, d.k, d.T, f.lambda, d.statistics, d.n_tail);
     auto it = ctx->ft_radial.find(key);
     if (it == ctx->ft_radial.end()) {
-        RadialRule base;
-        frg_status st = get_radial(ctx, d.n_q, d.q_max, 3, &base);
-        if (st != FRG_OK) return st;
-        const size_t n = (size_t)d.n_q * (size_t)f.n_f;
         auto e = std::make_unique<RadialEntry>();
-        FRG_HIP_CHECK(e->buf.alloc(n * (4 * sizeof(double) + 3 * sizeof(float)) + 64));
-        double *q = (double *)e->buf.ptr, *W = q + n, *R = W + n, *w0 = R + n;
-        float *qf = (float *)(w0 + n), *Wf = qf + n, *Rf = Wf + n;
-        FRG_HIP_CHECK(launch_ft_rule(d.n_q, f.n_f, f.n_tail, f.n_lo, f.eta, f.T, f.Omega, d.k,
-                                     base, q, W, R, qf, Wf, Rf, w0, ctx->aux));
+        const size_t bytes = ft_rule_bytes(d.n_q, f.n_f);
+        FRG_HIP_CHECK(e->buf.alloc(bytes));
+        frg_status st = ft_rule_into(ctx, d, e->buf.ptr, bytes, &e->rule, ctx->aux);
+        if (st != FRG_OK) return st;
         FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
-        e->rule = RadialRule{q, W, R, qf, Wf, Rf, w0};
         it = ctx->ft_radial.emplace(key, std::move(e)).first;
     }
     *out = it->second->rule;
@@ -381,7 +399,7 @@ int lds_bytes_for(const ReqDev &r) {
 
 frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_batch &b,
                         const TileShape &shape, int m2_mode, double m2_floor, double coef,
-                        ReqDev *out) {
+                        ReqDev *out, const RadialRule *rad) {
     ReqDev r;
     std::memset(&r, 0, sizeof r);
     // kernel family: LPA at finite temperature runs the LPA kernel on the frequency-folded rule
@@ -437,8 +455,12 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
         r.zbk = r.zb + r.za * std::log(r.k2);
         r.Z = has ? b.Z.values : (const double *)ctx->ones.ptr;
     }
-    frg_status st = is_ft(d.family) ? get_ft_radial(ctx, d, fr, &r.rad)
-                                    : get_radial(ctx, d.n_q, d.q_max, d.d, &r.rad);
+    frg_status st = FRG_OK;
+    if (rad)
+        r.rad = *rad;
+    else
+        st = is_ft(d.family) ? get_ft_radial(ctx, d, fr, &r.rad)
+                             : get_radial(ctx, d.n_q, d.q_max, d.d, &r.rad);
     if (st != FRG_OK) return st;
     if (vertex) {
         st = get_cos1(ctx, d.n_x, &r.ang, d.family == FRG_FAMILY_TWO_POINT_T);

@@ -151,9 +151,15 @@ namespace frg {
 // Validate a descriptor/batch pair; FRG_E_INVAL with a message on failure.
 frg_status validate(const frg_integral_desc *desc, const frg_batch *batch, bool device_ptrs);
 // Fill a ReqDev for a validated request (rules resolved through the context cache).
+// rad (optional) replaces the cached radial rule (a stepper's own finite-temperature rule).
 frg_status make_request(frg_context *ctx, const frg_integral_desc &desc, const frg_batch &b,
                         const TileShape &shape, int m2_mode, double m2_floor, double coef,
-                        ReqDev *out);
+                        ReqDev *out, const RadialRule *rad = nullptr);
+// Finite-temperature radial rule of d written into buf (n_q n_f (4 doubles + 3 floats)), on
+// stream s; *out points into buf.
+frg_status ft_rule_into(frg_context *ctx, const frg_integral_desc &d, void *buf, size_t bytes,
+                        RadialRule *out, hipStream_t s);
+size_t ft_rule_bytes(int n_q, int n_f);
 // Tile shape for a request: the autotuned one if the context has it, else the heuristic.
 // allow_chunks = false (fused launches) restricts both to single-chunk shapes.
 TileShape choose_shape(frg_context *ctx, const frg_integral_desc &desc, int n_ext,

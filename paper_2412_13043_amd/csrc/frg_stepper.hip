@@ -1,0 +1,364 @@
+// Adaptive explicit stepper for flows dstate/dt = RHS(state; k(t)) in RG time t = log(Lambda/k),
+// k(t) = Lambda exp(-t) (Sec. 2.1): the embedded Runge-Kutta pair of Dormand and Prince,
+// order 5(4), with first-same-as-last stages (the RK45 class of explicit steppers named in
+// Sec. 5.2, "Time-stepping").  The stages, right-hand sides and the error norm run on the
+// device; the host reads one float64 per step to accept or reject it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "frg_runtime.hpp"
+
+namespace frg {
+namespace {
+
+// Dormand & Prince (1980), RK5(4)7FM: nodes c_s, stage coefficients a_sj, and e_j = b_j - bhat_j
+// (fifth- minus fourth-order weights).  The fifth-order weights b are the last stage's row, so
+// the last stage evaluates the right-hand side at the new solution, which is the next step's
+// first stage when the step is accepted.
+constexpr double kC[7] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 4.0 / 5.0, 8.0 / 9.0, 1.0, 1.0};
+constexpr double kA[7][6] = {
+    {0.0, 0.0, 0.0, 0.0, 0.0, 0.0},
+    {1.0 / 5.0, 0.0, 0.0, 0.0, 0.0, 0.0},
+    {3.0 / 40.0, 9.0 / 40.0, 0.0, 0.0, 0.0, 0.0},
+    {44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0.0, 0.0, 0.0},
+    {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0, 0.0, 0.0},
+    {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0, 0.0},
+    {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0}};
+constexpr double kE[7] = {71.0 / 57600.0,      0.0,           -71.0 / 16695.0, 71.0 / 1920.0,
+                          -17253.0 / 339200.0, 22.0 / 525.0, -1.0 / 40.0};
+
+// A linear combination sum_j c_j K_j of up to seven stage vectors.
+struct Combo {
+    const double *K[7];
+    double c[7];
+    int nk;
+};
+
+// out = y + h sum_j c_j K_j (the stage terms in order j = 0, 1, ...).
+__global__ void __launch_bounds__(256) rk_combine_kernel(int n, const double *__restrict__ y,
+                                                         double h, Combo k,
+                                                         double *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int j = 0; j < k.nk; ++j) s = fma(k.c[j], k.K[j][i], s);
+    out[i] = fma(h, s, y[i]);
+}
+
+// One workgroup: err2 = sum_i (h sum_j e_j K_j[i] / (atol + rtol max(|y_i|, |yn_i|)))^2, each
+// thread over a fixed stride, then a fixed tree in LDS (the same bits on every run).
+__global__ void __launch_bounds__(256) rk_error_kernel(int n, const double *__restrict__ y,
+                                                       const double *__restrict__ yn, double h,
+                                                       Combo e, double rtol, double atol,
+                                                       double *__restrict__ err2) {
+    __shared__ double part[256];
+    const int t = (int)threadIdx.x;
+    double acc = 0.0;
+    for (int i = t; i < n; i += 256) {
+        double s = 0.0;
+        for (int j = 0; j < e.nk; ++j) s = fma(e.c[j], e.K[j][i], s);
+        const double sc = atol + rtol * fmax(fabs(y[i]), fabs(yn[i]));
+        const double r = h * s / sc;
+        acc = fma(r, r, acc);
+    }
+    part[t] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) part[t] += part[t + w];
+        __syncthreads();
+    }
+    if (t == 0) err2[0] = part[0];
+}
+
+}  // namespace
+}  // namespace frg
+
+using namespace frg;
+
+struct frg_stepper {
+    frg_context *ctx = nullptr;
+    frg_integral_desc desc{};  // k = Lambda (t = 0)
+    frg_flow_state state{};
+    frg_stepper_config cfg{};
+    TileShape shape;
+    bool lpa = false;
+    int n = 0;
+    DeviceBuffer stages;    // K_0..K_6, the stage input and the new solution: 9 n doubles
+    DeviceBuffer contrib;   // radially chunked right-hand sides
+    DeviceBuffer counters;  // float32 amplification slots (zero at rest)
+    DeviceBuffer ftrule;    // finite temperature: the frequency rule at the stage's k
+    DeviceBuffer err_dev;
+    double *err_host = nullptr;
+    double *K[7] = {};
+    double *ytmp = nullptr, *ynew = nullptr;
+    double t = 0.0, h = 0.0, last_err = 0.0;
+    bool fsal = false;     // K[0] holds RHS(t, state)
+    bool rejected_last = false;
+    uint64_t accepted = 0, rejected = 0, evals = 0;
+    ~frg_stepper() {
+        if (err_host) (void)hipHostFree(err_host);
+    }
+};
+
+namespace {
+
+// RHS at RG time ts of the stage vector y into out, on stream s (caller holds ctx->mu).
+frg_status stepper_rhs(frg_stepper *S, double ts, const double *y, double *out, hipStream_t s) {
+    frg_integral_desc d = S->desc;
+    const double scale = std::exp(-ts);  // k / Lambda
+    d.k = S->desc.k * scale;
+    // the mass floor keeps its ratio to k^2 (the propagator's pole moves with k^2)
+    const double floor = S->state.m2_floor * scale * scale;
+    frg_batch b;
+    std::memset(&b, 0, sizeof b);
+    b.n_ext = S->lpa ? 2 * S->n : S->n;
+    b.ext = S->lpa ? nullptr : S->state.grid;
+    b.m2 = y;
+    b.Z = S->state.Z;
+    b.out = out;
+    RadialRule own;
+    const RadialRule *rp = nullptr;
+    frg_status st;
+    if (is_ft(d.family)) {
+        if ((st = ft_rule_into(S->ctx, d, S->ftrule.ptr, S->ftrule.bytes, &own, s)) != FRG_OK)
+            return st;
+        rp = &own;
+    }
+    ReqDev r;
+    if (S->lpa)
+        st = make_request(S->ctx, d, b, S->shape, 1, 0.0, 1.0, &r, rp);
+    else
+        st = make_request(S->ctx, d, b, S->shape, 2, floor, S->state.coef, &r, rp);
+    if (st != FRG_OK) return st;
+    r.contrib_base = 0;
+    r.ctr_base = 0;
+    if (S->lpa) {
+        FRG_HIP_CHECK(launch_lpa_rhs(r, S->n, S->state.n_comp, S->state.grid, y, floor, out, s));
+    } else {
+        FRG_HIP_CHECK(launch_batch(&r, nullptr, tile_count(r), lds_bytes_for(r),
+                                   (double *)S->contrib.ptr, (unsigned *)S->counters.ptr, s));
+        FRG_HIP_CHECK(launch_finalize(r, (const double *)S->contrib.ptr,
+                                      (unsigned *)S->counters.ptr, s));
+    }
+    ++S->evals;
+    return FRG_OK;
+}
+
+hipError_t combine(int n, const double *y, double h, const double *const *K, const double *c,
+                   int nk, double *out, hipStream_t s) {
+    Combo k;
+    std::memset(&k, 0, sizeof k);
+    for (int j = 0; j < nk; ++j) {
+        k.K[j] = K[j];
+        k.c[j] = c[j];
+    }
+    k.nk = nk;
+    hipLaunchKernelGGL(rk_combine_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, y, h, k, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+frg_status frg_stepper_create(frg_context *ctx, const frg_integral_desc *desc,
+                              const frg_flow_state *state, const frg_stepper_config *cfg,
+                              frg_stepper **out) {
+    clear_error();
+    if (!ctx || !desc || !state || !cfg || !out) {
+        set_error("null argument to frg_stepper_create");
+        return FRG_E_INVAL;
+    }
+    const frg_stepper_config &c = *cfg;
+    if (!(c.rtol > 0.0) || !(c.atol > 0.0) || !(c.h0 > 0.0) || !(c.h_min > 0.0) ||
+        !(c.h_max >= c.h_min) || !std::isfinite(c.h_max) || !std::isfinite(c.rtol) ||
+        !std::isfinite(c.atol) || !std::isfinite(c.h0) || c.max_steps < 1 ||
+        (c.fixed_step != 0 && c.fixed_step != 1)) {
+        set_error("stepper config needs rtol, atol, h0 > 0, 0 < h_min <= h_max (finite), "
+                  "max_steps >= 1, fixed_step 0 or 1");
+        return FRG_E_INVAL;
+    }
+    if (state->family != desc->family) {
+        set_error("flow state family %d does not match descriptor family %d", state->family,
+                  desc->family);
+        return FRG_E_INVAL;
+    }
+    const bool lpa = is_lpa(desc->family);
+    const int n = state->n_ext;
+    if (!state->state || !state->grid || n < (lpa ? 3 : 1)) {
+        set_error("flow state needs state and grid pointers and n_ext >= %d", lpa ? 3 : 1);
+        return FRG_E_INVAL;
+    }
+    if (lpa && state->n_comp < 1) {
+        set_error("n_comp must be >= 1");
+        return FRG_E_INVAL;
+    }
+    if (!std::isfinite(state->m2_floor) || !std::isfinite(state->coef)) {
+        set_error("m2_floor and coef must be finite");
+        return FRG_E_INVAL;
+    }
+    frg_batch b;
+    std::memset(&b, 0, sizeof b);
+    b.n_ext = lpa ? 2 * n : n;
+    b.ext = lpa ? nullptr : state->grid;
+    b.m2 = state->state;
+    b.Z = state->Z;
+    b.out = const_cast<double *>(state->state);  // the state is evolved in place
+    frg_status st = validate(desc, &b, true);
+    if (st != FRG_OK) return st;
+
+    auto S = std::make_unique<frg_stepper>();
+    S->ctx = ctx;
+    S->desc = *desc;
+    S->state = *state;
+    S->cfg = c;
+    S->lpa = lpa;
+    S->n = n;
+    S->h = std::min(std::max(c.h0, c.h_min), c.h_max);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    FRG_HIP_CHECK(hipSetDevice(ctx->device));
+    S->shape = choose_shape(ctx, *desc, b.n_ext, 16 * ctx->num_cus);
+    // work buffers sized at t = 0: at finite temperature with a k-scaled frequency domain the
+    // number of frequencies only falls as k does
+    ReqDev r;
+    if ((st = make_request(ctx, *desc, b, S->shape, lpa ? 1 : 2, state->m2_floor, state->coef,
+                           &r)) != FRG_OK)
+        return st;
+    FRG_HIP_CHECK(S->stages.alloc((size_t)9 * n * sizeof(double)));
+    double *base = (double *)S->stages.ptr;
+    for (int j = 0; j < 7; ++j) S->K[j] = base + (size_t)j * n;
+    S->ytmp = base + (size_t)7 * n;
+    S->ynew = base + (size_t)8 * n;
+    FRG_HIP_CHECK(S->contrib.alloc(std::max<size_t>(contrib_doubles(r), 1) * sizeof(double)));
+    const size_t nc = std::max<size_t>(counter_count(r), 1);
+    FRG_HIP_CHECK(S->counters.alloc(nc * sizeof(unsigned)));
+    FRG_HIP_CHECK(launch_fill_zero_u32((unsigned *)S->counters.ptr, nc, ctx->aux));
+    if (is_ft(desc->family)) {
+        FreqRule f;
+        if ((st = freq_rule(*desc, &f)) != FRG_OK) return st;
+        FRG_HIP_CHECK(S->ftrule.alloc(ft_rule_bytes(desc->n_q, f.n_f)));
+    }
+    FRG_HIP_CHECK(S->err_dev.alloc(sizeof(double)));
+    FRG_HIP_CHECK(hipHostMalloc((void **)&S->err_host, sizeof(double), hipHostMallocDefault));
+    FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
+    *out = S.release();
+    return FRG_OK;
+}
+
+frg_status frg_stepper_advance(frg_stepper *S, double t_end, hipStream_t s,
+                               frg_stepper_stats *stats) {
+    clear_error();
+    if (!S) {
+        set_error("stepper is NULL");
+        return FRG_E_INVAL;
+    }
+    if (!std::isfinite(t_end) || t_end < S->t) {
+        set_error("t_end must be finite and >= the current t = %g", S->t);
+        return FRG_E_INVAL;
+    }
+    const frg_stepper_config &c = S->cfg;
+    const int n = S->n;
+    double *y = const_cast<double *>(S->state.state);
+    frg_status res = FRG_OK;
+    int attempts = 0;
+    {
+        std::lock_guard<std::mutex> lk(S->ctx->mu);
+        FRG_HIP_CHECK(hipSetDevice(S->ctx->device));
+    }
+    while (S->t < t_end) {
+        if (attempts >= c.max_steps) {
+            set_error("max_steps (%d) attempted before t_end", c.max_steps);
+            res = FRG_E_TIMEOUT;
+            break;
+        }
+        ++attempts;
+        double h = c.fixed_step ? c.h0 : S->h;
+        const bool last = S->t + h >= t_end * (1.0 - 1e-14) - 1e-300;
+        if (last) h = t_end - S->t;
+        frg_status st = FRG_OK;
+        {
+            std::lock_guard<std::mutex> lk(S->ctx->mu);
+            if (!S->fsal) {
+                if ((st = stepper_rhs(S, S->t, y, S->K[0], s)) != FRG_OK) return st;
+                S->fsal = true;
+            }
+            for (int st_i = 1; st_i < 7; ++st_i) {
+                double *in = st_i < 6 ? S->ytmp : S->ynew;
+                FRG_HIP_CHECK(combine(n, y, h, (const double *const *)S->K, kA[st_i], st_i, in, s));
+                if ((st = stepper_rhs(S, S->t + kC[st_i] * h, in, S->K[st_i], s)) != FRG_OK)
+                    return st;
+            }
+        }
+        double err = 0.0;
+        if (!c.fixed_step) {
+            Combo e;
+            std::memset(&e, 0, sizeof e);
+            for (int j = 0; j < 7; ++j) {
+                e.K[j] = S->K[j];
+                e.c[j] = kE[j];
+            }
+            e.nk = 7;
+            hipLaunchKernelGGL(rk_error_kernel, dim3(1), dim3(256), 0, s, n, y, S->ynew, h, e,
+                               c.rtol, c.atol, (double *)S->err_dev.ptr);
+            FRG_HIP_CHECK(hipGetLastError());
+            FRG_HIP_CHECK(hipMemcpyAsync(S->err_host, S->err_dev.ptr, sizeof(double),
+                                         hipMemcpyDeviceToHost, s));
+            FRG_HIP_CHECK(hipStreamSynchronize(s));
+            err = std::sqrt(*S->err_host / (double)n);
+            if (!std::isfinite(err)) {
+                set_error("error norm is not finite at t = %g (h = %g)", S->t, h);
+                return FRG_E_INVAL;
+            }
+        }
+        S->last_err = err;
+        if (c.fixed_step || err <= 1.0) {
+            FRG_HIP_CHECK(hipMemcpyAsync(y, S->ynew, (size_t)n * sizeof(double),
+                                         hipMemcpyDeviceToDevice, s));
+            std::swap(S->K[0], S->K[6]);  // the last stage is RHS(t + h, ynew)
+            S->t = last ? t_end : S->t + h;
+            ++S->accepted;
+            if (c.fixed_step) continue;
+            const double fac = err > 0.0 ? 0.9 * std::pow(err, -0.2) : 5.0;
+            const double fac_max = S->rejected_last ? 1.0 : 5.0;
+            S->h = std::min(std::max(h * std::min(fac_max, std::max(0.2, fac)), c.h_min), c.h_max);
+            S->rejected_last = false;
+        } else {
+            ++S->rejected;
+            S->rejected_last = true;
+            if (h <= c.h_min) {
+                set_error("step size at h_min = %g rejected at t = %g (err = %g)", c.h_min, S->t,
+                          err);
+                res = FRG_E_INVAL;
+                break;
+            }
+            const double fac = 0.9 * std::pow(err, -0.2);
+            S->h = std::min(std::max(h * std::min(1.0, std::max(0.2, fac)), c.h_min), c.h_max);
+        }
+    }
+    // the last state copy is queued on s: the state is final when the call returns
+    FRG_HIP_CHECK(hipStreamSynchronize(s));
+    if (stats) {
+        stats->t = S->t;
+        stats->h = S->h;
+        stats->last_err = S->last_err;
+        stats->accepted = S->accepted;
+        stats->rejected = S->rejected;
+        stats->rhs_evals = S->evals;
+    }
+    return res;
+}
+
+frg_status frg_stepper_destroy(frg_stepper *S) {
+    clear_error();
+    if (!S) return FRG_OK;
+    (void)hipSetDevice(S->ctx->device);
+    (void)hipDeviceSynchronize();
+    delete S;
+    return FRG_OK;
+}
+
+}  // extern "C"

@@ -86,6 +86,16 @@ class frg_stats(ctypes.Structure):
                 ("nodes", c_uint64), ("launches", c_uint64)]
 
 
+class frg_stepper_config(ctypes.Structure):
+    _fields_ = [("rtol", c_double), ("atol", c_double), ("h0", c_double), ("h_min", c_double),
+                ("h_max", c_double), ("max_steps", c_int), ("fixed_step", c_int)]
+
+
+class frg_stepper_stats(ctypes.Structure):
+    _fields_ = [("t", c_double), ("h", c_double), ("last_err", c_double),
+                ("accepted", c_uint64), ("rejected", c_uint64), ("rhs_evals", c_uint64)]
+
+
 _P = c_void_p
 _sig = {
     "frg_context_create": ([c_int, c_size_t, POINTER(c_void_p)], c_int),
@@ -106,6 +116,10 @@ _sig = {
     "frg_session_cancel": ([_P, c_uint64], c_int),
     "frg_session_stats": ([_P, POINTER(frg_stats)], c_int),
     "frg_session_close": ([_P], c_int),
+    "frg_stepper_create": ([_P, POINTER(frg_integral_desc), POINTER(frg_flow_state),
+                            POINTER(frg_stepper_config), POINTER(c_void_p)], c_int),
+    "frg_stepper_advance": ([_P, c_double, _P, POINTER(frg_stepper_stats)], c_int),
+    "frg_stepper_destroy": ([_P], c_int),
 }
 EXPORTED = tuple(_sig)
 for _name, (_args, _res) in _sig.items():
@@ -163,6 +177,26 @@ def frg_autotune(ctx: int, desc: frg_integral_desc, batch: frg_batch, stream: in
 def frg_flow_rhs(ctx: int, desc: frg_integral_desc, state: frg_flow_state, dstate_dt: int,
                  stream: int) -> None:
     _check(_lib.frg_flow_rhs(ctx, byref(desc), byref(state), dstate_dt, stream), "frg_flow_rhs")
+
+
+def frg_stepper_create(ctx: int, desc: frg_integral_desc, state: frg_flow_state,
+                       cfg: frg_stepper_config) -> int:
+    h = c_void_p()
+    _check(_lib.frg_stepper_create(ctx, byref(desc), byref(state), byref(cfg), byref(h)),
+           "frg_stepper_create")
+    return h.value
+
+
+def frg_stepper_advance(st: int, t_end: float, stream: int, ok=(FRG_OK,)):
+    """Returns (status, stats); statuses outside `ok` raise."""
+    stats = frg_stepper_stats()
+    rc = _check(_lib.frg_stepper_advance(st, t_end, stream, byref(stats)), "frg_stepper_advance",
+                ok)
+    return rc, stats
+
+
+def frg_stepper_destroy(st: int) -> None:
+    _check(_lib.frg_stepper_destroy(st), "frg_stepper_destroy")
 
 
 def frg_session_open(ctx: int, cfg: frg_session_config) -> int:
@@ -310,3 +344,40 @@ class Context:
                             n_comp, m2_floor, coef)
         frg_flow_rhs(self.handle, desc, st, _dptr(dstate_dt), _stream(stream))
         return dstate_dt
+
+    def stepper(self, desc, state, grid, *, Z=None, x_min=1e-3, x_max=1e3, n_comp=4,
+                m2_floor=-0.9, coef=1.0, rtol=1e-8, atol=1e-10, h0=1e-2, h_min=1e-10,
+                h_max=1.0, max_steps=100000, fixed_step=False):
+        """An adaptive Dormand-Prince 5(4) stepper evolving `state` (device tensor) in place.
+        state, grid and Z must stay alive while the stepper is used."""
+        return Stepper(self, desc, state, grid, Z=Z, x_min=x_min, x_max=x_max, n_comp=n_comp,
+                       m2_floor=m2_floor, coef=coef, rtol=rtol, atol=atol, h0=h0, h_min=h_min,
+                       h_max=h_max, max_steps=max_steps, fixed_step=fixed_step)
+
+
+class Stepper:
+    """frg_stepper: integrates the flow of frg_flow_rhs in RG time t = log(Lambda/k)."""
+
+    def __init__(self, ctx, desc, state, grid, *, Z, x_min, x_max, n_comp, m2_floor, coef, rtol,
+                 atol, h0, h_min, h_max, max_steps, fixed_step):
+        zt = frg_log_table(_dptr(Z), 0 if Z is None else int(Z.numel()), x_min, x_max)
+        fs = frg_flow_state(desc.family, int(state.numel()), _dptr(state), _dptr(grid), zt,
+                            n_comp, m2_floor, coef)
+        cfg = frg_stepper_config(rtol, atol, h0, h_min, h_max, max_steps, 1 if fixed_step else 0)
+        self._keep = (state, grid, Z)
+        self.handle = frg_stepper_create(ctx.handle, desc, fs, cfg)
+
+    def advance(self, t_end, stream=None, ok=(FRG_OK,)):
+        """Advance to t_end; returns (status, frg_stepper_stats)."""
+        return frg_stepper_advance(self.handle, t_end, _stream(stream), ok)
+
+    def close(self):
+        if self.handle:
+            frg_stepper_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover - best effort
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -118,6 +118,24 @@ def test_two_point_ft_parity(env, stat, n_ext, n_q, n_x, T, lam, n_tail, useZ):
     assert _rel(got, ref) <= TOL
 
 
+@pytest.mark.parametrize("stat,k,scaled", [(0, 1.7, True), (1, 0.45, False), (1, 2.3, True)])
+def test_two_point_ft_scale_and_scaled_domain(env, stat, k, scaled):
+    frg = env[0]
+    rng = np.random.default_rng(200 + stat)
+    n = 45
+    p = k * 10 ** rng.uniform(-3, 2, n)
+    p0 = rng.uniform(-1.0, 1.0, n) * k
+    m2 = rng.uniform(-0.4, 1.5, n) * k * k
+    Z = wl.dressing_table(11)
+    kw = dict(T=0.15 * k, statistics=stat, freq_max=5.0 if scaled else 5.0 * k, n_tail=5)
+    desc = frg.make_desc(frg.FRG_FAMILY_TWO_POINT_T, 20, 8.0, n_x=10, k=k, freq_scaled=scaled,
+                         **kw)
+    got = _run(env, desc, n, ext=np.concatenate([p, p0]), m2=m2, Z=Z)
+    ref = oracle.integrate_ft(oracle.TWO_POINT_T, 20, 8.0, n_x=10, k=k, freq_scaled=scaled,
+                              ext=(p, p0), m2=m2, Z=Z, **kw)
+    assert _rel(got, ref) <= TOL
+
+
 @pytest.mark.parametrize("tau", [0.0, 0.1])
 def test_two_point_ft_fp32_within_bound(env, tau):
     frg = env[0]
