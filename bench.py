@@ -235,6 +235,24 @@ def oracle_timings(threads_max=16, seconds=1.5):
         "three_point": (three, P.size, wl.THREE_NQ * wl.THREE_NX * wl.THREE_NPHI,
                         P.size * wl.THREE_NQ * wl.THREE_NX * wl.THREE_NPHI, 64 / P.size),
     }
+    # the O(4) LPA flow of the stepper benchmark, integrated by the oracle's stepper
+    import math
+
+    from oracle import stepper as rk
+
+    rho_s = wl.lpa_rho_grid()
+
+    def flow(t, u):
+        k = math.exp(-t)
+        return oracle.lpa_flow_rhs(rho_s, u, wl.LPA_NQ, wl.LPA_QMAX, k=k, n_comp=4,
+                                   m2_floor=-0.9 * k * k)
+
+    st = rk.Dopri5(flow, 0.3 + rho_s, **STEPPER_CFG)
+    t0 = time.perf_counter()
+    st.advance(STEPPER_T_END["lpa"])
+    res["lpa_flow_stepper"] = {"wall_ms": round((time.perf_counter() - t0) * 1e3, 2),
+                               "accepted": st.accepted, "rejected": st.rejected,
+                               "rhs_evals": st.evals, "threads": 1}
     for name, (call, n_pts, npp, nodes_rhs, single_frac) in cases.items():
         out = {"nodes_per_rhs": nodes_rhs}
         for nt in (1, threads):
@@ -400,6 +418,49 @@ def two_point_ft_setup(torch, frg, wl, B=16):
     return [desc] * B, batches, nodes, (te, tZ, out)
 
 
+STEPPER_CFG = dict(rtol=1e-8, atol=1e-10, h0=0.05, h_min=1e-8, h_max=0.5, max_steps=100000)
+STEPPER_T_END = {"lpa": 3.0, "two_point": 1.0}
+
+
+def stepper_bench(torch, frg, wl, ctx):
+    """Whole flows integrated by the device stepper: the O(4) LPA flow (64 rho points, GL32) from
+    k = Lambda to k = Lambda e^-3, and a two-point vertex flow (256 momenta, 64x32 nodes, state
+    m2 per momentum, dstate/dt = -I) from k = Lambda to Lambda e^-1."""
+    res = {}
+    rho = wl.lpa_rho_grid()
+    grid = _dev(torch, rho)
+    d1 = frg.make_desc(frg.FRG_FAMILY_LPA, wl.LPA_NQ, wl.LPA_QMAX)
+    p, m2, Z = wl.two_point()
+    tp, tZ = _dev(torch, p), _dev(torch, Z)
+    d2 = frg.make_desc(frg.FRG_FAMILY_TWO_POINT, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX)
+
+    def run(kind):
+        if kind == "lpa":
+            state = _dev(torch, 0.3 + rho)
+            st = ctx.stepper(d1, state, grid, n_comp=4, m2_floor=-0.9, **STEPPER_CFG)
+        else:
+            state = torch.full((p.size,), m2, dtype=torch.float64, device="cuda")
+            st = ctx.stepper(d2, state, tp, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
+                             m2_floor=-0.9, coef=-1.0, **STEPPER_CFG)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, s = st.advance(STEPPER_T_END[kind])
+        el = time.perf_counter() - t0
+        st.close()
+        return el, s
+
+    for kind in ("lpa", "two_point"):
+        run(kind)  # plans and rules
+        el, s = run(kind)
+        attempts = s.accepted + s.rejected
+        res[kind] = {"t_end": STEPPER_T_END[kind], "accepted": int(s.accepted),
+                     "rejected": int(s.rejected), "rhs_evals": int(s.rhs_evals),
+                     "wall_ms": round(el * 1e3, 3),
+                     "us_per_step": round(el / max(attempts, 1) * 1e6, 2),
+                     "us_per_rhs": round(el / max(int(s.rhs_evals), 1) * 1e6, 2)}
+    return res
+
+
 def secondary(torch, frg, wl, ctx, serving_seconds=4.0):
     """Other workloads, timed the same way (fewer steps)."""
     ex = {}
@@ -507,6 +568,8 @@ def secondary(torch, frg, wl, ctx, serving_seconds=4.0):
     torch.cuda.synchronize()
     gctx.close()
     ex["rhs_latency_us"] = lat
+    log("bench: flow stepper")
+    ex["flow_stepper"] = stepper_bench(torch, frg, wl, ctx)
     log("bench: serving")
     ex["serving"] = serving(torch, frg, wl, ctx, seconds=serving_seconds)
     return ex
