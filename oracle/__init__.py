@@ -25,6 +25,11 @@ _LIB = os.path.join(_HERE, "libfrg_oracle.so")
 
 REG_EXP = 0
 REG_LITIM = 1
+REG_POLYEXP = 100  # + N: the polynomial-exponential regulator of order N
+
+
+def reg_polyexp(n: int = 8) -> int:
+    return REG_POLYEXP + n
 LPA = 1
 TWO_POINT = 2
 THREE_POINT = 3

@@ -96,10 +96,29 @@ static void exp_pair(double y, double *e, double *E) {
     }
 }
 
+/* polynomial-exponential shape (Sec. 3.1): S = sum_{i=1}^{N} y^i / i and P = sum_{i=1}^{N} y^i,
+ * each term from its own power of y; R = k^2 e^{-S}; at fixed l2, k dy/dk = -2y gives
+ * k dR/dk = 2 k^2 e^{-S} + k^2 e^{-S} (-S'(y)) (-2y) = 2 k^2 e^{-S} (1 + y S'(y)), y S' = P. */
+static void polyexp_sums(int N, double y, double *S, double *P) {
+    double s = 0.0, p = 0.0, yi = 1.0;
+    for (int i = 1; i <= N; ++i) {
+        yi *= y;
+        s += yi / (double)i;
+        p += yi;
+    }
+    *S = s;
+    *P = p;
+}
+
 double frgo_regulator(int kind, double l2, double k) {
     double k2 = k * k;
     if (l2 < 0.0) l2 = 0.0;
     if (kind == FRGO_REG_LITIM) return (l2 < k2) ? (k2 - l2) : 0.0;
+    if (kind > FRGO_REG_POLYEXP && kind <= FRGO_REG_POLYEXP + 64) {
+        double S, P;
+        polyexp_sums(kind - FRGO_REG_POLYEXP, l2 / k2, &S, &P);
+        return k2 * exp(-S);
+    }
     double y = l2 / k2;
     if (y == 0.0) return k2;
     double e, E;
@@ -111,6 +130,11 @@ double frgo_regulator_dot(int kind, double l2, double k) {
     double k2 = k * k;
     if (l2 < 0.0) l2 = 0.0;
     if (kind == FRGO_REG_LITIM) return (l2 < k2) ? 2.0 * k2 : 0.0;
+    if (kind > FRGO_REG_POLYEXP && kind <= FRGO_REG_POLYEXP + 64) {
+        double S, P;
+        polyexp_sums(kind - FRGO_REG_POLYEXP, l2 / k2, &S, &P);
+        return 2.0 * k2 * exp(-S) * (1.0 + P);
+    }
     double y = l2 / k2;
     if (y == 0.0) return 2.0 * k2;
     double e, E;

@@ -26,7 +26,9 @@
 extern "C" {
 #endif
 
-enum { FRGO_REG_EXP = 0, FRGO_REG_LITIM = 1 };
+/* Regulators: exponential, flat (Litim), and the polynomial-exponential shape of Sec. 3.1,
+ * R = k^2 exp(-sum_{i=1}^{N} (l2/k^2)^i / i), selected as FRGO_REG_POLYEXP + N (1 <= N <= 64). */
+enum { FRGO_REG_EXP = 0, FRGO_REG_LITIM = 1, FRGO_REG_POLYEXP = 100 };
 enum { FRGO_LPA = 1, FRGO_TWO_POINT = 2, FRGO_THREE_POINT = 3, FRGO_LPA_T = 4, FRGO_TWO_POINT_T = 5 };
 
 /* n-point Gauss-Legendre rule on [a, b]; nodes ascending. */
