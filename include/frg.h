@@ -75,6 +75,13 @@ typedef enum {
 } frg_family;
 
 typedef enum {
+    FRG_REG_EXPONENTIAL = 0,  /* R = l2/(exp(l2/k^2) - 1) */
+    FRG_REG_POLY_EXP = 1,     /* R = k^2 exp(-sum_{i=1}^{N} y^i/i), y = l2/k^2: the shape s_N of
+                                 Sec. 3.1 (the paper's default regulator, N = 8) */
+    FRG_REG_FLAT = 2          /* R = (k^2 - l2) Theta(k^2 - l2) (Litim), k dR/dk = 2 k^2 Theta */
+} frg_regulator;
+
+typedef enum {
     FRG_BOSONIC = 0,   /* Matsubara frequencies w_n = 2 pi n T */
     FRG_FERMIONIC = 1  /* w_n = 2 pi (n + 1/2) T */
 } frg_statistics;
@@ -90,9 +97,12 @@ typedef enum {
  *                    p1 = p e1, p2 = p (cos(alpha) e1 + sin(alpha) e2):
  *                    l1^2 = q^2 + p^2 + 2 q p x,
  *                    l2^2 = q^2 + p^2 - 2 q p (x cos(alpha) + sqrt(1-x^2) cos(phi) sin(alpha))
- * with the exponential regulator R(l2) = l2/(exp(l2/k^2) - 1), its scale derivative
- * Rdot = k dR/dk = 2 k^2 y^2 e^y/(e^y - 1)^2 (y = l2/k^2) and the propagator
- * G(l2) = 1/(Z(l2) l2 + R(l2) + m2).  Radial GL(n_q) on [0, q_max*k]; x GL(n_x) on [-1, 1];
+ * with the regulator R(l2) (by default the exponential one, R = l2/(exp(l2/k^2) - 1), whose
+ * scale derivative is Rdot = k dR/dk = 2 k^2 y^2 e^y/(e^y - 1)^2, y = l2/k^2; see frg_regulator:
+ * polynomial-exponential Rdot = 2 k^2 exp(-S_N(y)) (1 + sum_{i=1}^{N} y^i), flat
+ * Rdot = 2 k^2 Theta(k^2 - l2)) and the propagator G(l2) = 1/(Z(l2) l2 + R(l2) + m2).
+ * With the flat regulator the integrand has a kink at |q| = k; a radial node within rounding
+ * of it may fall on either side.  Radial GL(n_q) on [0, q_max*k]; x GL(n_x) on [-1, 1];
  * phi GL(n_phi) on [0, pi].  Momenta squared below zero from rounding are clamped to 0.
  *
  * Finite temperature (Sec. 5.3 "Momentum integrations": the "Quadratureq0"/"Quadraturex0"
@@ -135,6 +145,10 @@ typedef struct {
     int statistics;        /* frg_statistics */
     int n_tail;            /* GL nodes per side for the omitted frequencies; 0 = none */
     int freq_scaled;       /* 0: Lambda = freq_max ("q0"); 1: Lambda = freq_max * k ("x0") */
+    /* every family */
+    int regulator;         /* frg_regulator (0, the exponential one, when zeroed); the float32
+                              form supports FRG_REG_EXPONENTIAL only (FRG_E_UNSUPPORTED) */
+    int reg_order;         /* N of FRG_REG_POLY_EXP, 1..16; 0 = 8 */
     int reserved;          /* zero */
 } frg_integral_desc;
 

@@ -13,7 +13,8 @@ constexpr int kMaxRule = 1024;     // FRG_MAX_NODES
 constexpr int kMaxTable = 4096;    // FRG_MAX_TABLE
 
 // Quadrature rules computed on the device once and cached by the context.
-//  radial (k = 1): q^_a, W^_a = w^_a q^_a^(d-1) Rdot^(q^_a^2), R^_a = R(q^_a^2)
+//  radial (k = 1): q^_a, W^_a = w^_a q^_a^(d-1) Rdot^(q^_a^2), R^_a = R(q^_a^2) for the request's
+//                  regulator
 //  cos1:           x_b, xw_b = w_b sqrt(1 - x_b^2), xs_b = sqrt(1 - x_b^2)      (+ float copies)
 //                  (d = 3 spatial measure: xw_b = w_b)
 //  phi:            fc_c = cos(phi_c), fw_c = w_c sin(phi_c)                      (+ float copies)
@@ -44,6 +45,9 @@ struct ReqDev {
     int ext_tiles;    // ceil(n_ext / (64 >> (lq_log2 + lx_log2)))
     int nZ;           // 0 => Z == 1
     int m2_mode;      // 0 scalar, 1 array, 2 array floored at m2_floor (flow states)
+    int reg;          // regulator: 0 exponential, 1 polynomial-exponential, 2 flat
+    int reg_n;        // order N of the polynomial-exponential regulator
+    double far_y;     // y = l2/k^2 beyond which R is exactly 0 in float64 (regulator 1)
     long long ctr_base;      // first counter of this request in the counter array
     long long contrib_base;  // first double of this request's [n_q][n_ext] contribution block
     double k, k2;
@@ -76,7 +80,8 @@ struct TileDev {
 hipError_t launch_rules(int n_q, double q_max, int d, int n_x, int n_phi, double *q, double *W,
                         double *R, float *qf, float *Wf, float *Rf, double *x, double *xw,
                         double *xs, float *xf, float *xwf, float *xsf, double *fc, double *fw,
-                        float *fcf, float *fwf, hipStream_t s, bool cos1_plain = false);
+                        float *fcf, float *fwf, hipStream_t s, bool cos1_plain = false,
+                        int reg = 0, int reg_n = 8);
 // Finite-temperature radial rule (see RadialRule) from a d = 3 vacuum rule `base` of n_q nodes:
 // n_f frequencies, the first and last n_tail of them the tail nodes +-Omega/t (t GL on [0, 1],
 // weight Omega w_t/(2 pi t^2)), the rest 2 pi T (n + eta) for n = n_lo, n_lo + 1, ... (weight T).
@@ -86,9 +91,9 @@ hipError_t launch_ft_rule(int n_q, int n_f, int n_tail, int n_lo, double eta, do
 hipError_t launch_batch(const ReqDev *req_dev_host, const ReqDev *req_dev_ptr, int n_tiles,
                         int lds_bytes, double *contrib, unsigned *counters, hipStream_t s);
 // fam/prec: the family and precision shared by every request of the launch, or -1 (mixed).
-hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, const TileDev *tiles_dev,
-                        int n_tiles, int grid, int lds_bytes, double *contrib,
-                        unsigned *counters, unsigned *work_ctr, hipStream_t s);
+hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg,
+                        const TileDev *tiles_dev, int n_tiles, int grid, int lds_bytes,
+                        double *contrib, unsigned *counters, unsigned *work_ctr, hipStream_t s);
 hipError_t launch_fill_zero_u32(unsigned *p, size_t n, hipStream_t s);
 // radially chunked requests: radial sums after the integrand launch (no-op otherwise)
 hipError_t launch_finalize(const ReqDev &r, const double *contrib, unsigned *counters,
@@ -96,8 +101,8 @@ hipError_t launch_finalize(const ReqDev &r, const double *contrib, unsigned *cou
 hipError_t launch_lpa_rhs(const ReqDev &r, int n, int n_comp, const double *rho, const double *u,
                           double m2_floor, double *dudt, hipStream_t s);
 hipError_t launch_log_table(double2 *out, hipStream_t s);
-int multi_blocks_per_cu(int fam, int prec, int lds_bytes);
-int multi_grid(int n_tiles, int fam, int prec, int lds_bytes, int num_cus);
+int multi_blocks_per_cu(int fam, int prec, int reg, int lds_bytes);
+int multi_grid(int n_tiles, int fam, int prec, int reg, int lds_bytes, int num_cus);
 constexpr int kLogTable = 256;
 
 }  // namespace frg

@@ -88,7 +88,7 @@ __device__ __forceinline__ void exp_pair64_prop(double y, double &e, double &E) 
 __global__ void __launch_bounds__(64) rules_kernel(
     int n_q, double q_max, int d, int n_x, int n_phi, double *q, double *W, double *R, float *qf,
     float *Wf, float *Rf, double *x, double *xw, double *xs, float *xf, float *xwf, float *xsf,
-    double *fc, double *fw, float *fcf, float *fwf, int cos1_plain) {
+    double *fc, double *fw, float *fcf, float *fwf, int cos1_plain, int reg, int reg_n) {
     const double pi = 3.141592653589793238462643383279502884;
     int which = blockIdx.y;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -100,7 +100,21 @@ __global__ void __launch_bounds__(64) rules_kernel(
         double wh = 0.5 * q_max * w;
         double y = qh * qh;          // k = 1
         double Rh, Rd;
-        if (y > 0.0) {
+        if (reg == 1) {
+            // R = exp(-S_N(y)), k dR/dk = 2 exp(-S_N(y)) (1 + y S_N'(y)), y S_N' = sum_i y^i
+            double sn = 1.0 / reg_n, pn = 1.0;
+            for (int j = reg_n - 1; j >= 1; --j) {
+                sn = fma(sn, y, 1.0 / j);
+                pn = fma(pn, y, 1.0);
+            }
+            const double e = exp(-fmin(sn * y, 1000.0));
+            Rh = e;
+            Rd = 2.0 * e * fma(pn, y, 1.0);
+        } else if (reg == 2) {
+            // flat: R = 1 - y, k dR/dk = 2 below y = 1; both 0 from y = 1 on
+            Rh = y < 1.0 ? 1.0 - y : 0.0;
+            Rd = y < 1.0 ? 2.0 : 0.0;
+        } else if (y > 0.0) {
             double e, E;
             exp_pair64(y, e, E);
             Rh = y * e / (-E);
@@ -150,12 +164,14 @@ __global__ void __launch_bounds__(64) rules_kernel(
 hipError_t launch_rules(int n_q, double q_max, int d, int n_x, int n_phi, double *q, double *W,
                         double *R, float *qf, float *Wf, float *Rf, double *x, double *xw,
                         double *xs, float *xf, float *xwf, float *xsf, double *fc, double *fw,
-                        float *fcf, float *fwf, hipStream_t s, bool cos1_plain) {
+                        float *fcf, float *fwf, hipStream_t s, bool cos1_plain, int reg,
+                        int reg_n) {
     int nmax = n_q > n_x ? n_q : n_x;
     nmax = nmax > n_phi ? nmax : n_phi;
     dim3 grid((nmax + 63) / 64, 3);
     hipLaunchKernelGGL(rules_kernel, grid, dim3(64), 0, s, n_q, q_max, d, n_x, n_phi, q, W, R,
-                       qf, Wf, Rf, x, xw, xs, xf, xwf, xsf, fc, fw, fcf, fwf, cos1_plain ? 1 : 0);
+                       qf, Wf, Rf, x, xw, xs, xf, xwf, xsf, fc, fw, fcf, fwf, cos1_plain ? 1 : 0,
+                       reg, reg_n);
     return hipGetLastError();
 }
 
@@ -297,14 +313,35 @@ __device__ __forceinline__ double prop64(double l2, double z, double m2, double 
 // three-point wavefront spans all radial nodes of a point and would only pay for the vote.
 #define FRG_FAR_Y 38.0
 
-template <int W, bool FAR = false>
+// 1/i, i = 1..16: coefficients of the polynomial-exponential regulator's exponent
+__constant__ double kRegInv[17] = {0.0,       1.0,        1.0 / 2.0,  1.0 / 3.0,  1.0 / 4.0,
+                                   1.0 / 5.0, 1.0 / 6.0,  1.0 / 7.0,  1.0 / 8.0,  1.0 / 9.0,
+                                   1.0 / 10.0, 1.0 / 11.0, 1.0 / 12.0, 1.0 / 13.0, 1.0 / 14.0,
+                                   1.0 / 15.0, 1.0 / 16.0};
+
+// S_N(y) = sum_{i=1}^{N} y^i / i (Horner), 1 <= N <= 16.
+__device__ __forceinline__ double poly_s(double y, int n) {
+    double acc = kc(kRegInv)[n];
+    for (int i = n - 1; i >= 1; --i) acc = fma(acc, y, kc(kRegInv)[i]);
+    return acc * y;
+}
+
+// Regulators (REG): 0 exponential, R = l2/(e^y - 1); 1 polynomial-exponential
+// R = k^2 exp(-S_N(y)); 2 flat, R = (k^2 - l2) Theta(k^2 - l2); y = l2/k^2.  For REG 1 and 2
+// the callers pass l2 and m2 in units of k^2 (inv_k2 = 1) and G is 1/(Z y + R/k^2 + m2/k^2);
+// far_y is the y beyond which R/k^2 is exactly 0 in float64 (REG 1), reg_n the order N.
+template <int W, bool FAR = false, int REG = 0>
 __device__ __forceinline__ void propagators64(const double (&l2)[W], double (&G)[W],
                                               const Smem &sm, int nZ, double za, double zb1,
-                                              double m2, double inv_k2) {
-    bool far = FAR;
+                                              double m2, double inv_k2, double far_y = FRG_FAR_Y,
+                                              int reg_n = 8) {
+    // flat regulator: no transcendental to skip
+    constexpr bool kFar = FAR && REG != 2;
+    const double fy = REG == 0 ? FRG_FAR_Y : far_y;
+    bool far = kFar;
 #pragma unroll
-    for (int w = 0; w < W; ++w) far = far && (l2[w] * inv_k2 >= FRG_FAR_Y);
-    if (FAR && __all(far)) {
+    for (int w = 0; w < W; ++w) far = far && (l2[w] * inv_k2 >= fy);
+    if (kFar && __all(far)) {
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             const double zv = dressing64(sm, nZ, za, zb1, l2[w]);
@@ -315,9 +352,17 @@ __device__ __forceinline__ void propagators64(const double (&l2)[W], double (&G)
     double2 t[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) t[w] = sm.logt[(__double2hiint(l2[w]) >> 12) & 0xff];
+    // REG 0: E = expm1(-y); REG 1, 2: E = R/k^2
     double E[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) E[w] = fm::expm1_neg(l2[w] * inv_k2);
+    for (int w = 0; w < W; ++w) {
+        if (REG == 0)
+            E[w] = fm::expm1_neg(l2[w] * inv_k2);
+        else if (REG == 1)
+            E[w] = fm::exp_neg(fmin(poly_s(l2[w], reg_n), 1000.0));
+        else
+            E[w] = fmax(1.0 - l2[w], 0.0);
+    }
     int iz[W];
     double fz[W];
 #pragma unroll
@@ -335,6 +380,14 @@ __device__ __forceinline__ void propagators64(const double (&l2)[W], double (&G)
     double2 z[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) z[w] = sm.Z64[iz[w]];
+    if (REG != 0) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const double zv = fma(fz[w], z[w].y, z[w].x);
+            G[w] = fm::rcp_nr(fma(zv, l2[w], m2) + E[w]);
+        }
+        return;
+    }
     double le[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) le[w] = fma(l2[w], E[w], l2[w]);
@@ -377,6 +430,7 @@ __device__ __forceinline__ RadialTerm radial64(const ReqDev &r, const Smem &sm, 
 // the radial leg, m2x the inner leg: equal in vacuum; at finite temperature the inner leg's mass
 // term carries the shifted frequency, m2x = m2 + (w_j + p0)^2 (the radial leg's w_j^2 is folded
 // into the rule's R).
+template <int REG>
 __device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm, int a, double p,
                                                 double m2, double m2x, double inv_k2) {
     // inner loop in units of k^2: y = l2/k^2 with G(l2) = G^(y)/k^2, G^ = 1/(Z y + R/k^2 + m2/k^2)
@@ -390,13 +444,13 @@ __device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm,
         double l2[FRG_ILP], G[FRG_ILP];
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w) l2[w] = fma(c1, kc(r.ang.x)[b + w], c0);
-        propagators64<FRG_ILP, true>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
+        propagators64<FRG_ILP, true, REG>(l2, G, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w) inner = fma(kc(r.ang.xw)[b + w], G[w], inner);
     }
     for (; b < nx; ++b) {
         double l2[1] = {fma(c1, kc(r.ang.x)[b], c0)}, G[1];
-        propagators64<1, true>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
+        propagators64<1, true, REG>(l2, G, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
         inner = fma(kc(r.ang.xw)[b], G[0], inner);
     }
     return t.wg * (inner * inv_k2);
@@ -406,6 +460,7 @@ __device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm,
 // evaluated once per (a, b); l2^2 = (c0 - c1 x cos a) - c1 sqrt(1-x^2) sin a cos phi.
 // One cos1 node b of the three-point contribution (units of k^2): t = xw_b G^(l1^2) and the phi
 // sum inner = sum_c w_c G^(l2^2).
+template <int REG>
 __device__ __forceinline__ void xterm64(const ReqDev &r, const Smem &sm, int b, double c0,
                                         double c1, double ca, double sa, double m2h, double &t,
                                         double &inner) {
@@ -413,7 +468,7 @@ __device__ __forceinline__ void xterm64(const ReqDev &r, const Smem &sm, int b, 
     const double za = r.za, zb1 = r.zbk + 1.0;
     const double xb = kc(r.ang.x)[b];
     double l1[1] = {fma(c1, xb, c0)}, g1[1];
-    propagators64<1>(l1, g1, sm, nZ, za, zb1, m2h, 1.0);
+    propagators64<1, false, REG>(l1, g1, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
     const double A2 = fma(-c1, xb * ca, c0);
     const double B2 = -c1 * (kc(r.ang.xs)[b] * sa);
     double acc = 0.0;
@@ -423,13 +478,13 @@ __device__ __forceinline__ void xterm64(const ReqDev &r, const Smem &sm, int b, 
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w)
             l2[w] = fmax(fma(B2, kc(r.phi.c)[c + w], A2), FRG_L2_TINY);
-        propagators64<FRG_ILP>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
+        propagators64<FRG_ILP, false, REG>(l2, G, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w) acc = fma(kc(r.phi.w)[c + w], G[w], acc);
     }
     for (; c < nphi; ++c) {
         double l2[1] = {fmax(fma(B2, kc(r.phi.c)[c], A2), FRG_L2_TINY)}, G[1];
-        propagators64<1>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
+        propagators64<1, false, REG>(l2, G, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
         acc = fma(kc(r.phi.w)[c], G[0], acc);
     }
     t = kc(r.ang.xw)[b] * g1[0];
@@ -581,13 +636,13 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
 // loops do (float64: one fused multiply-add per node; float32: the same FRG_ILP-node blocks and
 // compensated additions), so the bits do not depend on lx.  Called by all lanes of a wavefront
 // together when lx > 1; act marks the lanes with a point and radial node to evaluate.
-template <int PREC>
+template <int PREC, int REG>
 __device__ __forceinline__ double contrib_two(const ReqDev &r, const Smem &sm, int a, double p,
                                               double m2, double m2x, double inv_k2, float &kmax,
                                               bool act, int sx, int lx) {
     if (lx == 1) {
         if (!act) return 0.0;
-        return (PREC == 0) ? contrib_two64(r, sm, a, p, m2, m2x, inv_k2)
+        return (PREC == 0) ? contrib_two64<REG>(r, sm, a, p, m2, m2x, inv_k2)
                            : contrib_two32(r, sm, a, p, m2, m2x, inv_k2, kmax);
     }
     double wg = 0.0, c0 = 0.0, c1 = 0.0;
@@ -613,7 +668,7 @@ __device__ __forceinline__ double contrib_two(const ReqDev &r, const Smem &sm, i
         if (act && b < nx) {
             if (PREC == 0) {
                 double l2[1] = {fma(c1, kc(r.ang.x)[b], c0)}, G[1];
-                propagators64<1, true>(l2, G, sm, nZ, za, zb1, m2h, 1.0);
+                propagators64<1, true, REG>(l2, G, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
                 g = G[0];
             } else {
                 float l2[1] = {(float)fma(c1, kc(r.ang.x)[b], c0)}, G[1];
@@ -679,7 +734,7 @@ __device__ __forceinline__ void xterm32(const ReqDev &r, const Smem &sm, const P
 // across lanes and folds them into mid in cos1 order, so mid is the same sequence of fused
 // multiply-adds for every lx.  All lanes of a wavefront call this together when lx > 1 (the
 // cross-lane pulls need them); act marks the lanes with a point and radial node to evaluate.
-template <int PREC>
+template <int PREC, int REG>
 __device__ __forceinline__ double contrib_three(const ReqDev &r, const Smem &sm, int a, double p,
                                                 double ca, double sa, double m2, double inv_k2,
                                                 float &kmax, bool act, int sx, int lx) {
@@ -701,7 +756,7 @@ __device__ __forceinline__ double contrib_three(const ReqDev &r, const Smem &sm,
         double tb = 0.0, ib = 0.0;
         if (act && b < nx) {
             if (PREC == 0)
-                xterm64(r, sm, b, c0, c1, ca, sa, m2h, tb, ib);
+                xterm64<REG>(r, sm, b, c0, c1, ca, sa, m2h, tb, ib);
             else
                 xterm32(r, sm, P, b, c0, c1, ca, sa, kmax, tb, ib);
         }
@@ -870,7 +925,7 @@ __device__ __forceinline__ double readlane64(double v, int l) {
 // Vertex families (FAM 2 two-point, 3 three-point, 5 two-point at finite temperature): lanes =
 // (external point, radial sub-lane, cos1 sub-lane); the point's contributions are added in radial
 // order inside the wavefront, or (radially chunked requests) stored for the finalize kernel.
-template <int FAM, int PREC>
+template <int FAM, int PREC, int REG>
 __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int et, int chunk,
                                             double *__restrict__ contrib,
                                             unsigned *__restrict__ counters) {
@@ -904,16 +959,16 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
     // wavefront calls it together, lanes without work pass act = false
     auto node = [&](int a, bool act) -> double {
         if (FAM == 3)
-            return contrib_three<PREC>(r, sm, act ? a : 0, p, ca, sa, m2, inv_k2, kmax, act, sx,
-                                       lx);
+            return contrib_three<PREC, REG>(r, sm, act ? a : 0, p, ca, sa, m2, inv_k2, kmax, act,
+                                            sx, lx);
         if (FAM == 5) {
             // radial index a = (frequency j, spatial node): the inner leg's frequency w_j + p0
             const int ai = act ? a : 0;
             const double wl = kc(r.rad.w0)[ai] + p0;
-            return contrib_two<PREC>(r, sm, ai, p, m2, fma(wl, wl, m2), inv_k2, kmax, act, sx,
-                                     lx);
+            return contrib_two<PREC, REG>(r, sm, ai, p, m2, fma(wl, wl, m2), inv_k2, kmax, act,
+                                          sx, lx);
         }
-        return contrib_two<PREC>(r, sm, act ? a : 0, p, m2, m2, inv_k2, kmax, act, sx, lx);
+        return contrib_two<PREC, REG>(r, sm, act ? a : 0, p, m2, m2, inv_k2, kmax, act, sx, lx);
     };
     if (r.chunks == 1) {
         // The wavefront holds every radial node of its points.  The lq radial sub-lanes of a
@@ -978,7 +1033,7 @@ __global__ void __launch_bounds__(64) finalize_kernel(ReqDev r, const double *co
 }
 
 // One request: tile = blockIdx.x -> (external tile, chunk).
-template <int FAM, int PREC>
+template <int FAM, int PREC, int REG>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
     FAM == 3 ? FRG_WAVES_PER_EU_MULTI : FRG_WAVES_PER_EU_BATCH)))
 batch_kernel(ReqDev r, double *contrib, unsigned *counters) {
@@ -995,7 +1050,26 @@ batch_kernel(ReqDev r, double *contrib, unsigned *counters) {
     stage_log(sm, r.logt);
     stage_dressing(r, sm);
     __syncthreads();
-    tile_vertex<FAM, PREC>(r, sm, et, chunk, contrib, counters);
+    tile_vertex<FAM, PREC, REG>(r, sm, et, chunk, contrib, counters);
+}
+
+typedef void (*batch_fn)(ReqDev, double *, unsigned *);
+
+// Kernel instance for (family, precision, regulator); the float32 form exists for the
+// exponential regulator only, and the LPA family reads its regulator from the radial rule.
+template <int F>
+static batch_fn batch_for_family(int prec, int reg) {
+    if (prec == 1) return batch_kernel<F, 1, 0>;
+    if (reg == 1) return batch_kernel<F, 0, 1>;
+    if (reg == 2) return batch_kernel<F, 0, 2>;
+    return batch_kernel<F, 0, 0>;
+}
+
+static batch_fn batch_variant(int fam, int prec, int reg) {
+    if (fam == 1) return prec == 0 ? batch_kernel<1, 0, 0> : batch_kernel<1, 1, 0>;
+    if (fam == 2) return batch_for_family<2>(prec, reg);
+    if (fam == 5) return batch_for_family<5>(prec, reg);
+    return batch_for_family<3>(prec, reg);
 }
 
 hipError_t launch_batch(const ReqDev *req_host, const ReqDev *req_dev_ptr, int n_tiles,
@@ -1003,19 +1077,8 @@ hipError_t launch_batch(const ReqDev *req_host, const ReqDev *req_dev_ptr, int n
     (void)req_dev_ptr;
     const ReqDev &r = *req_host;
     if (n_tiles <= 0) return hipSuccess;
-    const dim3 g(n_tiles), b(kWave);
-#define FRG_LAUNCH(F, P) \
-    hipLaunchKernelGGL((batch_kernel<F, P>), g, b, lds_bytes, s, r, contrib, counters)
-    if (r.family == 1) {
-        if (r.precision == 0) FRG_LAUNCH(1, 0); else FRG_LAUNCH(1, 1);
-    } else if (r.family == 2) {
-        if (r.precision == 0) FRG_LAUNCH(2, 0); else FRG_LAUNCH(2, 1);
-    } else if (r.family == 5) {
-        if (r.precision == 0) FRG_LAUNCH(5, 0); else FRG_LAUNCH(5, 1);
-    } else {
-        if (r.precision == 0) FRG_LAUNCH(3, 0); else FRG_LAUNCH(3, 1);
-    }
-#undef FRG_LAUNCH
+    hipLaunchKernelGGL(batch_variant(r.family, r.precision, r.reg), dim3(n_tiles), dim3(kWave),
+                       lds_bytes, s, r, contrib, counters);
     return hipGetLastError();
 }
 
@@ -1024,33 +1087,46 @@ hipError_t launch_batch(const ReqDev *req_host, const ReqDev *req_dev_ptr, int n
 // the list is empty.  A fill kernel ahead of every launch clears the counter (relaunches and
 // graph replays need no memset), so no workgroup has to order its exit against the others with
 // a device-scope fence.
-// FAM = PREC = -1 is the general kernel (any mix of families and precisions); a launch whose
-// requests all share one family and precision uses the instance specialised for them, which
-// carries only that path and so needs fewer registers (more resident waves).
-template <int FAM, int PREC>
-__device__ __forceinline__ void multi_tile(const ReqDev &r, Smem &sm, const TileDev &td,
-                                           double *contrib, unsigned *counters) {
-    const int fam = FAM > 0 ? FAM : r.family;
-    const int prec = PREC >= 0 ? PREC : r.precision;
-    if (fam == 2) {
-        if (prec == 0)
-            tile_vertex<2, 0>(r, sm, td.et, td.chunk, contrib, counters);
-        else
-            tile_vertex<2, 1>(r, sm, td.et, td.chunk, contrib, counters);
-    } else if (fam == 5) {
-        if (prec == 0)
-            tile_vertex<5, 0>(r, sm, td.et, td.chunk, contrib, counters);
-        else
-            tile_vertex<5, 1>(r, sm, td.et, td.chunk, contrib, counters);
-    } else {
-        if (prec == 0)
-            tile_vertex<3, 0>(r, sm, td.et, td.chunk, contrib, counters);
-        else
-            tile_vertex<3, 1>(r, sm, td.et, td.chunk, contrib, counters);
-    }
+// FAM = PREC = REG = -1 is the general kernel (any mix of families, precisions and
+// regulators); a launch whose requests all share one family, precision and regulator uses the
+// instance specialised for them, which carries only that path and so needs fewer registers
+// (more resident waves).
+template <int FAM, int PREC, int REG>
+__device__ __forceinline__ void vertex_tile(const ReqDev &r, Smem &sm, const TileDev &td,
+                                            double *contrib, unsigned *counters) {
+    tile_vertex<FAM, PREC, REG>(r, sm, td.et, td.chunk, contrib, counters);
 }
 
-template <int FAM, int PREC>
+template <int F>
+__device__ __forceinline__ void vertex_tile_any(const ReqDev &r, Smem &sm, const TileDev &td,
+                                                double *contrib, unsigned *counters) {
+    if (r.precision == 1)
+        vertex_tile<F, 1, 0>(r, sm, td, contrib, counters);
+    else if (r.reg == 1)
+        vertex_tile<F, 0, 1>(r, sm, td, contrib, counters);
+    else if (r.reg == 2)
+        vertex_tile<F, 0, 2>(r, sm, td, contrib, counters);
+    else
+        vertex_tile<F, 0, 0>(r, sm, td, contrib, counters);
+}
+
+template <int FAM, int PREC, int REG>
+__device__ __forceinline__ void multi_tile(const ReqDev &r, Smem &sm, const TileDev &td,
+                                           double *contrib, unsigned *counters) {
+    if (FAM > 0) {
+        vertex_tile<(FAM > 0 ? FAM : 2), (PREC > 0 ? PREC : 0), (REG > 0 ? REG : 0)>(
+            r, sm, td, contrib, counters);
+        return;
+    }
+    if (r.family == 2)
+        vertex_tile_any<2>(r, sm, td, contrib, counters);
+    else if (r.family == 5)
+        vertex_tile_any<5>(r, sm, td, contrib, counters);
+    else
+        vertex_tile_any<3>(r, sm, td, contrib, counters);
+}
+
+template <int FAM, int PREC, int REG>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
     (FAM < 0 || FAM == 3) ? FRG_WAVES_PER_EU_MULTI : FRG_WAVES_PER_EU_BATCH)))
 multi_kernel(const ReqDev *__restrict__ reqs, const TileDev *__restrict__ tiles, int n_tiles,
@@ -1094,7 +1170,7 @@ multi_kernel(const ReqDev *__restrict__ reqs, const TileDev *__restrict__ tiles,
                 __syncthreads();
                 staged = td.req;
             }
-            multi_tile<FAM, PREC>(r, sm, td, contrib, counters);
+            multi_tile<FAM, PREC, REG>(r, sm, td, contrib, counters);
             __syncthreads();
         }
     }
@@ -1102,20 +1178,29 @@ multi_kernel(const ReqDev *__restrict__ reqs, const TileDev *__restrict__ tiles,
 
 typedef void (*multi_fn)(const ReqDev *, const TileDev *, int, double *, unsigned *, unsigned *);
 
-static multi_fn multi_variant(int fam, int prec) {
-    // fam/prec < 0: general kernel
-    if (fam == 1) return prec == 0 ? multi_kernel<1, 0> : multi_kernel<1, 1>;
-    if (fam == 2) return prec == 0 ? multi_kernel<2, 0> : multi_kernel<2, 1>;
-    if (fam == 3) return prec == 0 ? multi_kernel<3, 0> : multi_kernel<3, 1>;
-    if (fam == 5) return prec == 0 ? multi_kernel<5, 0> : multi_kernel<5, 1>;
-    return multi_kernel<-1, -1>;
+template <int F>
+static multi_fn multi_for_family(int prec, int reg) {
+    if (prec == 1) return multi_kernel<F, 1, 0>;
+    if (reg == 1) return multi_kernel<F, 0, 1>;
+    if (reg == 2) return multi_kernel<F, 0, 2>;
+    return multi_kernel<F, 0, 0>;
+}
+
+static multi_fn multi_variant(int fam, int prec, int reg) {
+    // any of fam/prec/reg < 0: the general kernel
+    if (fam < 0 || prec < 0 || reg < 0) return multi_kernel<-1, -1, -1>;
+    if (fam == 1) return prec == 0 ? multi_kernel<1, 0, 0> : multi_kernel<1, 1, 0>;
+    if (fam == 2) return multi_for_family<2>(prec, reg);
+    if (fam == 3) return multi_for_family<3>(prec, reg);
+    if (fam == 5) return multi_for_family<5>(prec, reg);
+    return multi_kernel<-1, -1, -1>;
 }
 
 // Workgroups of the fused kernel resident per CU with `lds_bytes` of dynamic LDS (sizes the
 // persistent grid).
-int multi_blocks_per_cu(int fam, int prec, int lds_bytes) {
+int multi_blocks_per_cu(int fam, int prec, int reg, int lds_bytes) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, multi_variant(fam, prec), kWave,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, multi_variant(fam, prec, reg), kWave,
                                                      lds_bytes) != hipSuccess ||
         n < 1)
         n = 4;
@@ -1125,21 +1210,21 @@ int multi_blocks_per_cu(int fam, int prec, int lds_bytes) {
 // Persistent grid: at most the workgroups the CUs hold at once, and no more than the tile list
 // needs in whole rounds -- with R = ceil(tiles / resident) rounds, ceil(tiles / R) workgroups
 // share the tiles evenly instead of leaving a last round mostly idle.
-int multi_grid(int n_tiles, int fam, int prec, int lds_bytes, int num_cus) {
-    const int resident = std::max(1, multi_blocks_per_cu(fam, prec, lds_bytes) * num_cus);
+int multi_grid(int n_tiles, int fam, int prec, int reg, int lds_bytes, int num_cus) {
+    const int resident = std::max(1, multi_blocks_per_cu(fam, prec, reg, lds_bytes) * num_cus);
     if (n_tiles <= resident) return std::max(n_tiles, 1);
     const int rounds = (n_tiles + resident - 1) / resident;
     return (n_tiles + rounds - 1) / rounds;
 }
 
-hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, const TileDev *tiles_dev,
-                        int n_tiles, int grid, int lds_bytes, double *contrib,
-                        unsigned *counters, unsigned *work_ctr, hipStream_t s) {
+hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg,
+                        const TileDev *tiles_dev, int n_tiles, int grid, int lds_bytes,
+                        double *contrib, unsigned *counters, unsigned *work_ctr, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
     const hipError_t e = launch_fill_zero_u32(work_ctr, 2, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(multi_variant(fam, prec), dim3(grid), dim3(kWave), lds_bytes, s, reqs_dev,
-                       tiles_dev, n_tiles, contrib, counters, work_ctr);
+    hipLaunchKernelGGL(multi_variant(fam, prec, reg), dim3(grid), dim3(kWave), lds_bytes, s,
+                       reqs_dev, tiles_dev, n_tiles, contrib, counters, work_ctr);
     return hipGetLastError();
 }
 

@@ -71,6 +71,27 @@ frg_status freq_rule(const frg_integral_desc &d, FreqRule *out) {
     return FRG_OK;
 }
 
+int reg_order(const frg_integral_desc &d) {
+    return d.regulator == FRG_REG_POLY_EXP ? (d.reg_order > 0 ? d.reg_order : 8) : 0;
+}
+
+// Smallest y (to a relative 1e-12) with S_N(y) = sum_{i=1}^{N} y^i/i >= 760: beyond it
+// exp(-S_N) is exactly 0 in float64 (the smallest subnormal is exp(-744.4)), so the
+// polynomial-exponential regulator vanishes exactly there.
+double poly_exp_far_y(int n) {
+    auto S = [n](double y) {
+        double acc = 1.0 / n;
+        for (int i = n - 1; i >= 1; --i) acc = acc * y + 1.0 / i;
+        return acc * y;
+    };
+    double lo = 0.0, hi = 1e4;
+    for (int it = 0; it < 200 && hi - lo > 1e-12 * hi; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        (S(mid) >= 760.0 ? hi : lo) = mid;
+    }
+    return hi;
+}
+
 frg_integral_desc plan_desc(const frg_integral_desc &d) {
     frg_integral_desc p = d;
     if (!is_ft(d.family)) return p;
@@ -100,6 +121,19 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
     if (d->precision != FRG_FP64 && d->precision != FRG_FP32_KAHAN) {
         set_error("precision must be FRG_FP64 or FRG_FP32_KAHAN, got %d", d->precision);
         return FRG_E_INVAL;
+    }
+    if (d->regulator < FRG_REG_EXPONENTIAL || d->regulator > FRG_REG_FLAT) {
+        set_error("regulator must be 0 (exponential), 1 (polynomial-exponential) or 2 (flat), "
+                  "got %d", d->regulator);
+        return FRG_E_INVAL;
+    }
+    if (d->reg_order < 0 || d->reg_order > 16) {
+        set_error("reg_order must be in [0, 16] (0 = 8), got %d", d->reg_order);
+        return FRG_E_INVAL;
+    }
+    if (d->precision == FRG_FP32_KAHAN && d->regulator != FRG_REG_EXPONENTIAL) {
+        set_error("the float32 form is implemented for the exponential regulator only");
+        return FRG_E_UNSUPPORTED;
     }
     if (d->family == FRG_FAMILY_LPA) {
         if (d->d < 1 || d->d > 8) {
@@ -203,8 +237,9 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
 // ---------------------------------------------------------------------------------------------
 // Rule cache
 // ---------------------------------------------------------------------------------------------
-static frg_status get_radial(frg_context *ctx, int n, double q_max, int d, RadialRule *out) {
-    auto key = std::make_tuple(n, q_max, d);
+static frg_status get_radial(frg_context *ctx, int n, double q_max, int d, int reg, int reg_n,
+                             RadialRule *out) {
+    auto key = std::make_tuple(n, q_max, d, reg, reg_n);
     auto it = ctx->radial.find(key);
     if (it == ctx->radial.end()) {
         auto e = std::make_unique<RadialEntry>();
@@ -214,7 +249,7 @@ static frg_status get_radial(frg_context *ctx, int n, double q_max, int d, Radia
         float *qf = (float *)(R + n), *Wf = qf + n, *Rf = Wf + n;
         FRG_HIP_CHECK(launch_rules(n, q_max, d, 0, 0, q, W, R, qf, Wf, Rf, nullptr, nullptr,
                                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                   nullptr, ctx->aux));
+                                   nullptr, ctx->aux, false, reg, reg_n));
         FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
         e->rule = RadialRule{q, W, R, qf, Wf, Rf, nullptr};
         it = ctx->radial.emplace(key, std::move(e)).first;
@@ -256,7 +291,8 @@ frg_status ft_rule_into(frg_context *ctx, const frg_integral_desc &d, void *buf,
         return FRG_E_INVAL;
     }
     RadialRule base;
-    if ((st = get_radial(ctx, d.n_q, d.q_max, 3, &base)) != FRG_OK) return st;
+    if ((st = get_radial(ctx, d.n_q, d.q_max, 3, d.regulator, reg_order(d), &base)) != FRG_OK)
+        return st;
     const size_t n = (size_t)d.n_q * (size_t)f.n_f;
     double *q = (double *)buf, *W = q + n, *R = W + n, *w0 = R + n;
     float *qf = (float *)(w0 + n), *Wf = qf + n, *Rf = Wf + n;
@@ -269,7 +305,8 @@ frg_status ft_rule_into(frg_context *ctx, const frg_integral_desc &d, void *buf,
 // Finite-temperature radial rule: the frequency rule folded into a d = 3 radial rule, cached.
 static frg_status get_ft_radial(frg_context *ctx, const frg_integral_desc &d, const FreqRule &f,
                                 RadialRule *out) {
-    auto key = std::make_tuple(d.n_q, d.q_max, d.k, d.T, f.lambda, d.statistics, d.n_tail);
+    auto key = std::make_tuple(d.n_q, d.q_max, d.k, d.T, f.lambda, d.statistics, d.n_tail,
+                               d.regulator * 32 + reg_order(d));
     auto it = ctx->ft_radial.find(key);
     if (it == ctx->ft_radial.end()) {
         auto e = std::make_unique<RadialEntry>();
@@ -439,6 +476,9 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
     // spatial part and one k from the frequency weights, which the rule holds as c_j/k
     r.pref = omega * std::pow(d.k, d.d + 2) * coef;
     r.m2_mode = b.m2 ? m2_mode : 0;
+    r.reg = d.regulator;
+    r.reg_n = reg_order(d);
+    r.far_y = d.regulator == FRG_REG_POLY_EXP ? poly_exp_far_y(r.reg_n) : 38.0;
     r.m2s = b.m2_scalar;
     r.m2_floor = m2_floor;
     r.tau = d.precision == 1 ? d.near_pole_tau : 0.0;
@@ -460,7 +500,8 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
         r.rad = *rad;
     else
         st = is_ft(d.family) ? get_ft_radial(ctx, d, fr, &r.rad)
-                             : get_radial(ctx, d.n_q, d.q_max, d.d, &r.rad);
+                             : get_radial(ctx, d.n_q, d.q_max, d.d, d.regulator, reg_order(d),
+                                          &r.rad);
     if (st != FRG_OK) return st;
     if (vertex) {
         st = get_cos1(ctx, d.n_x, &r.ang, d.family == FRG_FAMILY_TWO_POINT_T);
@@ -556,14 +597,18 @@ std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out) {
     return sorted;
 }
 
-void common_kind(const std::vector<ReqDev> &reqs, int *fam, int *prec) {
+void common_kind(const std::vector<ReqDev> &reqs, int *fam, int *prec, int *reg) {
+    // the LPA kernel takes its regulator from the radial rule alone
+    auto reg_of = [](const ReqDev &r) { return r.family == 1 ? 0 : r.reg; };
     *fam = reqs.empty() ? -1 : reqs[0].family;
     *prec = reqs.empty() ? -1 : reqs[0].precision;
+    *reg = reqs.empty() ? -1 : reg_of(reqs[0]);
     for (const ReqDev &r : reqs) {
         if (r.family != *fam) *fam = -1;
         if (r.precision != *prec) *prec = -1;
+        if (reg_of(r) != *reg) *reg = -1;
     }
-    if (*fam < 0 || *prec < 0) *fam = *prec = -1;
+    if (*fam < 0 || *prec < 0 || *reg < 0) *fam = *prec = *reg = -1;
 }
 
 frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s, Scratch *sc,
@@ -597,9 +642,9 @@ frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s,
                                  hipMemcpyHostToDevice, s));
     FRG_HIP_CHECK(hipEventRecord(sc->staged, s));
     sc->last_tiles = (int)sorted.size();
-    common_kind(reqs, &sc->last_fam, &sc->last_prec);
-    sc->last_grid = std::min(
-        multi_grid((int)sorted.size(), sc->last_fam, sc->last_prec, lds, ctx->num_cus),
+    common_kind(reqs, &sc->last_fam, &sc->last_prec, &sc->last_reg);
+    sc->last_grid = std::min(multi_grid((int)sorted.size(), sc->last_fam, sc->last_prec,
+                                        sc->last_reg, lds, ctx->num_cus),
         std::max(grid_waves, 1));
     sc->last_lds = lds;
     sc->last_nreqs = (int)reqs.size();
@@ -608,7 +653,7 @@ frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s,
 
 frg_status relaunch_multi(Scratch *sc, hipStream_t s) {
     FRG_HIP_CHECK(launch_multi((const ReqDev *)sc->reqs.ptr, sc->last_fam, sc->last_prec,
-                               (const TileDev *)sc->tiles.ptr, sc->last_tiles, sc->last_grid,
+                               sc->last_reg, (const TileDev *)sc->tiles.ptr, sc->last_tiles, sc->last_grid,
                                sc->last_lds, (double *)sc->contrib.ptr,
                                (unsigned *)sc->counters.ptr, (unsigned *)sc->work.ptr, s));
     return FRG_OK;
@@ -935,6 +980,8 @@ frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
     key.push_back(desc->statistics);
     key.push_back(desc->n_tail);
     key.push_back(desc->freq_scaled);
+    key.push_back(desc->regulator);
+    key.push_back(desc->reg_order);
     double dk[9] = {desc->q_max, desc->k,        desc->near_pole_tau, state->m2_floor, state->coef,
                     state->Z.x_min, state->Z.x_max, desc->T, desc->freq_max};
     for (double v : dk) {

@@ -79,7 +79,8 @@ struct Scratch {
     hipEvent_t staged = nullptr;
     // last fused call on this stream: its argument bytes and launch shape (plan cache)
     std::vector<char> last_key;
-    int last_tiles = 0, last_grid = 0, last_lds = 0, last_nreqs = 0, last_fam = -1, last_prec = -1;
+    int last_tiles = 0, last_grid = 0, last_lds = 0, last_nreqs = 0, last_fam = -1, last_prec = -1,
+        last_reg = -1;
     ~Scratch() {
         if (host_stage) (void)hipHostFree(host_stage);
         if (staged) (void)hipEventDestroy(staged);
@@ -121,6 +122,10 @@ frg_status freq_rule(const frg_integral_desc &d, FreqRule *out);
 frg_integral_desc plan_desc(const frg_integral_desc &d);
 // Integrand nodes per external point.
 double nodes_per_point(const frg_integral_desc &d);
+// Order N of a polynomial-exponential regulator (0 for the other regulators).
+int reg_order(const frg_integral_desc &d);
+// y beyond which the order-n polynomial-exponential regulator is exactly 0 in float64.
+double poly_exp_far_y(int n);
 
 }  // namespace frg
 
@@ -132,10 +137,12 @@ struct frg_context {
     hipStream_t aux = nullptr;  // rule construction and graph capture
     frg::DeviceBuffer logtab;   // float64 logarithm table (double2[256])
     frg::DeviceBuffer ones;     // {1, 1}: dressing table of requests without one
-    std::map<std::tuple<int, double, int>, std::unique_ptr<frg::RadialEntry>> radial;
+    // radial rules by (n, q_max, d, regulator, order)
+    std::map<std::tuple<int, double, int, int, int>, std::unique_ptr<frg::RadialEntry>> radial;
     std::map<int, std::unique_ptr<frg::AngleEntry>> cos1;  // key n (+ 1 << 20: d = 3 weights)
-    // finite-temperature radial rules by (n_q, q_max, k, T, Lambda, statistics, n_tail)
-    std::map<std::tuple<int, double, double, double, double, int, int>,
+    // finite-temperature radial rules by (n_q, q_max, k, T, Lambda, statistics, n_tail,
+    // regulator and order)
+    std::map<std::tuple<int, double, double, double, double, int, int, int>,
              std::unique_ptr<frg::RadialEntry>>
         ft_radial;
     std::map<int, std::unique_ptr<frg::PhiEntry>> phi;
@@ -180,8 +187,8 @@ frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s,
 frg_status relaunch_multi(Scratch *sc, hipStream_t s);
 // Tiles of a fused launch in longest-first order, and the dynamic LDS bytes it needs.
 std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out);
-// Family and precision shared by all requests (each -1 if they differ).
-void common_kind(const std::vector<ReqDev> &reqs, int *fam, int *prec);
+// Family, precision and regulator shared by all requests (all -1 if any differs).
+void common_kind(const std::vector<ReqDev> &reqs, int *fam, int *prec, int *reg);
 int lds_bytes_for(const ReqDev &r);
 
 }  // namespace frg

@@ -271,11 +271,11 @@ class HipExecutor : public Executor {
         FRG_HIP_CHECK(launch_fill_zero_u32((unsigned *)sl.counters.ptr, nctr, sl.stream));
         const ReqDev *reqs_dev = (const ReqDev *)sl.tables.ptr;
         const TileDev *tiles_dev = (const TileDev *)((char *)sl.tables.ptr + tiles_off);
-        int fam, prec;
-        common_kind(rd, &fam, &prec);
-        const int grid = multi_grid((int)tiles.size(), fam, prec, lds, ctx->num_cus);
-        FRG_HIP_CHECK(launch_multi(reqs_dev, fam, prec, tiles_dev, (int)tiles.size(), grid, lds,
-                                   (double *)base, (unsigned *)sl.counters.ptr,
+        int fam, prec, reg;
+        common_kind(rd, &fam, &prec, &reg);
+        const int grid = multi_grid((int)tiles.size(), fam, prec, reg, lds, ctx->num_cus);
+        FRG_HIP_CHECK(launch_multi(reqs_dev, fam, prec, reg, tiles_dev, (int)tiles.size(), grid,
+                                   lds, (double *)base, (unsigned *)sl.counters.ptr,
                                    (unsigned *)sl.work.ptr, sl.stream));
         sl.host_out.clear();
         pos = out_start;

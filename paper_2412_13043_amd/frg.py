@@ -35,6 +35,7 @@ FRG_FP64, FRG_FP32_KAHAN = 0, 1
 FRG_FAMILY_LPA, FRG_FAMILY_TWO_POINT, FRG_FAMILY_THREE_POINT = 1, 2, 3
 FRG_FAMILY_LPA_T, FRG_FAMILY_TWO_POINT_T = 4, 5
 FRG_BOSONIC, FRG_FERMIONIC = 0, 1
+FRG_REG_EXPONENTIAL, FRG_REG_POLY_EXP, FRG_REG_FLAT = 0, 1, 2
 FRG_MAX_NODES = 1024
 FRG_MAX_FT_NODES = 65536
 FRG_MAX_TABLE = 4096
@@ -56,7 +57,7 @@ class frg_integral_desc(ctypes.Structure):
                 ("n_phi", c_int), ("precision", c_int), ("q_max", c_double), ("k", c_double),
                 ("near_pole_tau", c_double), ("T", c_double), ("freq_max", c_double),
                 ("statistics", c_int), ("n_tail", c_int), ("freq_scaled", c_int),
-                ("reserved", c_int)]
+                ("regulator", c_int), ("reg_order", c_int), ("reserved", c_int)]
 
 
 class frg_log_table(ctypes.Structure):
@@ -282,13 +283,15 @@ def _stream(stream) -> int:
 def make_desc(family: int, n_q: int, q_max: float, *, n_x: int = 0, n_phi: int = 0, d: int = 0,
               k: float = 1.0, precision: int = FRG_FP64, near_pole_tau: float = 0.0,
               T: float = 0.0, freq_max: float = 0.0, statistics: int = FRG_BOSONIC,
-              n_tail: int = 0, freq_scaled: bool = False):
+              n_tail: int = 0, freq_scaled: bool = False, regulator: int = FRG_REG_EXPONENTIAL,
+              reg_order: int = 0):
     """Descriptor; T, freq_max, statistics, n_tail and freq_scaled apply to the finite-temperature
-    families (4, 5) only."""
+    families (4, 5) only; regulator and reg_order to every family."""
     if d == 0:
         d = 3 if family == FRG_FAMILY_LPA else 4
     return frg_integral_desc(family, d, n_q, n_x, n_phi, precision, q_max, k, near_pole_tau,
-                             T, freq_max, statistics, n_tail, 1 if freq_scaled else 0, 0)
+                             T, freq_max, statistics, n_tail, 1 if freq_scaled else 0, regulator,
+                             reg_order, 0)
 
 
 def make_batch(n_ext: int, out, *, ext=None, m2=None, m2_scalar: float = 0.0, Z=None,
