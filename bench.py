@@ -119,7 +119,7 @@ def time_kernel(torch, fn, steps, warmup):
     return t1 - t0, [a.elapsed_time(b) / steps]
 
 
-def two_point_batch_setup(torch, frg, B=256, precision=0, seed_m2=None, tau=0.1):
+def two_point_batch_setup(torch, frg, B=256, precision=0, seed_m2=None, tau=0.1, regulator=0):
     from paper_2412_13043_amd import workloads as wl
 
     if seed_m2 is None:
@@ -134,7 +134,7 @@ def two_point_batch_setup(torch, frg, B=256, precision=0, seed_m2=None, tau=0.1)
     out = torch.empty((B, p.size), dtype=torch.float64, device="cuda")
     err = torch.empty((B, p.size), dtype=torch.float64, device="cuda") if precision else None
     desc = frg.make_desc(2, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX, precision=precision,
-                         near_pole_tau=tau if precision else 0.0)
+                         near_pole_tau=tau if precision else 0.0, regulator=regulator)
     batches = [frg.make_batch(p.size, out[b], ext=tp, m2=None if tm is None else tm[b],
                               m2_scalar=m2, Z=tZ[b], x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
                               err_out=None if err is None else err[b]) for b in range(B)]
@@ -504,6 +504,16 @@ def secondary(torch, frg, wl, ctx, serving_seconds=4.0):
         "frac_fp64_peak": round(FLOP_PER_NODE[5] * nft / (msft * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                                 4)}
     del keep_ft
+    # the same two-point batch with the paper's default regulator (polynomial-exponential s_8)
+    # and with the flat one
+    for name, reg in (("two_point_poly_exp_s8_256", 1), ("two_point_flat_256", 2)):
+        log(f"bench: {name}")
+        dr, br, _, _, nr, keep_r = two_point_batch_setup(torch, frg, regulator=reg)
+        wall, ev = time_kernel(torch, lambda: ctx.integrate_multi(dr, br), 5, 1)
+        msr = float(np.mean(ev))
+        ex[name] = {"gnodes_per_s": round(nr / (msr * 1e-3) / 1e9, 2),
+                    "avg_kernel_ms": round(msr, 4)}
+        del keep_r
     # precision form on the near-pole workload vs float64 on identical inputs
     log("bench: float32 precision form")
 
