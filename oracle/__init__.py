@@ -77,6 +77,8 @@ def _load():
             lib.frgo_matsubara_rule.argtypes = [I, D, D, I, I, P, P]
             lib.frgo_integrate_ft.argtypes = [I, I, I, D, D, I, I, D, D, I, I, P, P, D, P, I, D, D,
                                               I, P]
+            lib.frgo_integrate_dm2.argtypes = lib.frgo_integrate.argtypes
+            lib.frgo_integrate_ft_dm2.argtypes = lib.frgo_integrate_ft.argtypes
             _lib = lib
     return _lib
 
@@ -117,7 +119,7 @@ def propagator(l2, m2, k=1.0, Z=None, x_min=1e-3, x_max=1e3, kind=REG_EXP) -> fl
 
 
 def integrate(family, n_q, q_max, *, d=None, n_x=0, n_phi=0, k=1.0, regulator=REG_EXP, ext=None,
-              m2=None, m2_scalar=0.0, Z=None, x_min=1e-3, x_max=1e3, n_ext=None):
+              m2=None, m2_scalar=0.0, Z=None, x_min=1e-3, x_max=1e3, n_ext=None, dm2=False):
     """Loop integrals I_e (see frg_oracle.h).  ext: None | p[n] | (p[n], alpha[n])."""
     if d is None:
         d = 3 if family == LPA else 4
@@ -136,9 +138,9 @@ def integrate(family, n_q, q_max, *, d=None, n_x=0, n_phi=0, k=1.0, regulator=RE
         n = len(m2a) if m2a is not None else int(n_ext)
     Za = _f64(Z)
     out = np.empty(n)
-    rc = _load().frgo_integrate(family, d, n_q, n_x, n_phi, q_max, k, regulator, _ptr(ext_arr),
-                                _ptr(m2a), m2_scalar, _ptr(Za), 0 if Za is None else len(Za),
-                                x_min, x_max, n, _ptr(out))
+    fn = _load().frgo_integrate_dm2 if dm2 else _load().frgo_integrate
+    rc = fn(family, d, n_q, n_x, n_phi, q_max, k, regulator, _ptr(ext_arr), _ptr(m2a), m2_scalar,
+            _ptr(Za), 0 if Za is None else len(Za), x_min, x_max, n, _ptr(out))
     if rc != 0:
         raise ValueError(f"frgo_integrate rejected the arguments (rc={rc})")
     return out
@@ -189,7 +191,7 @@ def matsubara_rule(statistics, T, lam, n_tail=0, cap=1 << 16):
 
 def integrate_ft(family, n_q, q_max, *, T, statistics=BOSONIC, freq_max, freq_scaled=False,
                  n_tail=0, n_x=0, k=1.0, regulator=REG_EXP, ext=None, m2=None, m2_scalar=0.0,
-                 Z=None, x_min=1e-3, x_max=1e3, n_ext=None):
+                 Z=None, x_min=1e-3, x_max=1e3, n_ext=None, dm2=False):
     """Finite-temperature integrals I_e, families LPA_T and TWO_POINT_T.
     ext: family TWO_POINT_T (p[n], p0[n])."""
     if family == TWO_POINT_T:
@@ -204,10 +206,10 @@ def integrate_ft(family, n_q, q_max, *, T, statistics=BOSONIC, freq_max, freq_sc
         n = len(m2a) if m2a is not None else int(n_ext)
     Za = _f64(Z)
     out = np.empty(n)
-    rc = _load().frgo_integrate_ft(family, n_q, n_x, q_max, k, regulator, statistics, T, freq_max,
-                                   1 if freq_scaled else 0, n_tail, _ptr(ext_arr), _ptr(m2a),
-                                   m2_scalar, _ptr(Za), 0 if Za is None else len(Za), x_min,
-                                   x_max, n, _ptr(out))
+    fn = _load().frgo_integrate_ft_dm2 if dm2 else _load().frgo_integrate_ft
+    rc = fn(family, n_q, n_x, q_max, k, regulator, statistics, T, freq_max,
+            1 if freq_scaled else 0, n_tail, _ptr(ext_arr), _ptr(m2a), m2_scalar, _ptr(Za),
+            0 if Za is None else len(Za), x_min, x_max, n, _ptr(out))
     if rc != 0:
         raise ValueError(f"frgo_integrate_ft rejected the arguments (rc={rc})")
     return out

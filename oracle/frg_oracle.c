@@ -177,9 +177,12 @@ static double omega(int d) {
 
 #define MAXN 4096
 
-int frgo_integrate(int family, int d, int n_q, int n_x, int n_phi, double q_max, double k,
-                   int regulator, const double *ext, const double *m2, double m2_scalar,
-                   const double *Z, int nZ, double x_min, double x_max, int n_ext, double *out) {
+/* deriv = 1: the same sums with the product of propagators replaced by its derivative in m2,
+ * each propagator G contributing dG/dm2 = -G^2 (product rule, written out per family). */
+static int integrate_impl(int family, int d, int n_q, int n_x, int n_phi, double q_max, double k,
+                          int regulator, const double *ext, const double *m2, double m2_scalar,
+                          const double *Z, int nZ, double x_min, double x_max, int n_ext,
+                          int deriv, double *out) {
     if (n_ext < 0 || out == NULL) return -1;
     if (n_q < 1 || n_q > MAXN || !(q_max > 0.0) || !(k > 0.0)) return -1;
     if (Z != NULL && (nZ < 1 || !(x_min > 0.0) || !(x_max > x_min))) return -1;
@@ -205,8 +208,10 @@ int frgo_integrate(int family, int d, int n_q, int n_x, int n_phi, double q_max,
             for (int a = 0; a < n_q; ++a) {
                 double q = qn[a], q2 = q * q;
                 double den = q2 + frgo_regulator(regulator, q2, k) + mass;
+                double g = 1.0 / den;
+                double prop = deriv ? -2.0 * g * g * g : g * g;
                 double term = pref * qw[a] * pow(q, (double)(d - 1)) *
-                              frgo_regulator_dot(regulator, q2, k) / (den * den);
+                              frgo_regulator_dot(regulator, q2, k) * prop;
                 nsum_add(&total, term);
             }
         } else if (family == FRGO_TWO_POINT) {
@@ -220,8 +225,10 @@ int frgo_integrate(int family, int d, int n_q, int n_x, int n_phi, double q_max,
                     double l2 = q2 + p * p + 2.0 * q * p * x;
                     double gq = frgo_propagator(regulator, Z, nZ, x_min, x_max, q2, mass, k);
                     double gl = frgo_propagator(regulator, Z, nZ, x_min, x_max, l2, mass, k);
+                    double prop = deriv ? -2.0 * gq * gq * gq * gl - gq * gq * gl * gl
+                                        : gq * gq * gl;
                     double term = pref * qw[a] * xw[b] * sqrt(1.0 - x * x) * q2 * q *
-                                  frgo_regulator_dot(regulator, q2, k) * gq * gq * gl;
+                                  frgo_regulator_dot(regulator, q2, k) * prop;
                     nsum_add(&inner, term);
                 }
                 nsum_add(&total, nsum_get(&inner));
@@ -243,8 +250,11 @@ int frgo_integrate(int family, int d, int n_q, int n_x, int n_phi, double q_max,
                         double gq = frgo_propagator(regulator, Z, nZ, x_min, x_max, q2, mass, k);
                         double g1 = frgo_propagator(regulator, Z, nZ, x_min, x_max, l1, mass, k);
                         double g2 = frgo_propagator(regulator, Z, nZ, x_min, x_max, l2, mass, k);
+                        double prop = deriv ? -2.0 * gq * gq * gq * g1 * g2 -
+                                                  gq * gq * g1 * g1 * g2 - gq * gq * g1 * g2 * g2
+                                            : gq * gq * g1 * g2;
                         double term = pref * qw[a] * xw[b] * fw[c] * sx * sin(phi) * q2 * q *
-                                      frgo_regulator_dot(regulator, q2, k) * gq * gq * g1 * g2;
+                                      frgo_regulator_dot(regulator, q2, k) * prop;
                         nsum_add(&inner, term);
                     }
                     nsum_add(&mid, nsum_get(&inner));
@@ -255,6 +265,21 @@ int frgo_integrate(int family, int d, int n_q, int n_x, int n_phi, double q_max,
         out[e] = nsum_get(&total);
     }
     return 0;
+}
+
+int frgo_integrate(int family, int d, int n_q, int n_x, int n_phi, double q_max, double k,
+                   int regulator, const double *ext, const double *m2, double m2_scalar,
+                   const double *Z, int nZ, double x_min, double x_max, int n_ext, double *out) {
+    return integrate_impl(family, d, n_q, n_x, n_phi, q_max, k, regulator, ext, m2, m2_scalar, Z,
+                          nZ, x_min, x_max, n_ext, 0, out);
+}
+
+int frgo_integrate_dm2(int family, int d, int n_q, int n_x, int n_phi, double q_max, double k,
+                       int regulator, const double *ext, const double *m2, double m2_scalar,
+                       const double *Z, int nZ, double x_min, double x_max, int n_ext,
+                       double *out) {
+    return integrate_impl(family, d, n_q, n_x, n_phi, q_max, k, regulator, ext, m2, m2_scalar, Z,
+                          nZ, x_min, x_max, n_ext, 1, out);
 }
 
 /* ---------------------------------------------------------------------------------------- */
@@ -302,10 +327,11 @@ int frgo_matsubara_rule(int statistics, double T, double lambda, int n_tail, int
     return total;
 }
 
-int frgo_integrate_ft(int family, int n_q, int n_x, double q_max, double k, int regulator,
-                      int statistics, double T, double freq_max, int freq_scaled, int n_tail,
-                      const double *ext, const double *m2, double m2_scalar, const double *Z,
-                      int nZ, double x_min, double x_max, int n_ext, double *out) {
+static int integrate_ft_impl(int family, int n_q, int n_x, double q_max, double k, int regulator,
+                             int statistics, double T, double freq_max, int freq_scaled,
+                             int n_tail, const double *ext, const double *m2, double m2_scalar,
+                             const double *Z, int nZ, double x_min, double x_max, int n_ext,
+                             int deriv, double *out) {
     if (n_ext < 0 || out == NULL) return -1;
     if (n_q < 1 || n_q > MAXN || !(q_max > 0.0) || !(k > 0.0)) return -1;
     if (family != FRGO_LPA_T && family != FRGO_TWO_POINT_T) return -1;
@@ -326,8 +352,10 @@ int frgo_integrate_ft(int family, int n_q, int n_x, double q_max, double k, int 
                 for (int a = 0; a < n_q; ++a) {
                     double q = qn[a], q2 = q * q;
                     double den = fw_[j] * fw_[j] + q2 + frgo_regulator(regulator, q2, k) + mass;
+                    double g = 1.0 / den;
+                    double prop = deriv ? -2.0 * g * g * g : g * g;
                     double term = fc_[j] * pref * qw[a] * q2 *
-                                  frgo_regulator_dot(regulator, q2, k) / (den * den);
+                                  frgo_regulator_dot(regulator, q2, k) * prop;
                     nsum_add(&total, term);
                 }
             }
@@ -346,8 +374,10 @@ int frgo_integrate_ft(int family, int n_q, int n_x, double q_max, double k, int 
                                            frgo_regulator(regulator, q2, k) + mass);
                         double gl = 1.0 / (wl * wl + frgo_dressing(Z, nZ, x_min, x_max, l2) * l2 +
                                            frgo_regulator(regulator, l2, k) + mass);
+                        double prop = deriv ? -2.0 * gq * gq * gq * gl - gq * gq * gl * gl
+                                            : gq * gq * gl;
                         double term = fc_[j] * pref * qw[a] * xw[b] * q2 *
-                                      frgo_regulator_dot(regulator, q2, k) * gq * gq * gl;
+                                      frgo_regulator_dot(regulator, q2, k) * prop;
                         nsum_add(&inner, term);
                     }
                     nsum_add(&total, nsum_get(&inner));
@@ -357,6 +387,24 @@ int frgo_integrate_ft(int family, int n_q, int n_x, double q_max, double k, int 
         out[e] = nsum_get(&total);
     }
     return 0;
+}
+
+int frgo_integrate_ft(int family, int n_q, int n_x, double q_max, double k, int regulator,
+                      int statistics, double T, double freq_max, int freq_scaled, int n_tail,
+                      const double *ext, const double *m2, double m2_scalar, const double *Z,
+                      int nZ, double x_min, double x_max, int n_ext, double *out) {
+    return integrate_ft_impl(family, n_q, n_x, q_max, k, regulator, statistics, T, freq_max,
+                             freq_scaled, n_tail, ext, m2, m2_scalar, Z, nZ, x_min, x_max, n_ext,
+                             0, out);
+}
+
+int frgo_integrate_ft_dm2(int family, int n_q, int n_x, double q_max, double k, int regulator,
+                          int statistics, double T, double freq_max, int freq_scaled, int n_tail,
+                          const double *ext, const double *m2, double m2_scalar, const double *Z,
+                          int nZ, double x_min, double x_max, int n_ext, double *out) {
+    return integrate_ft_impl(family, n_q, n_x, q_max, k, regulator, statistics, T, freq_max,
+                             freq_scaled, n_tail, ext, m2, m2_scalar, Z, nZ, x_min, x_max, n_ext,
+                             1, out);
 }
 
 /* ---------------------------------------------------------------------------------------- */

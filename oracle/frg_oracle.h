@@ -64,6 +64,16 @@ int frgo_integrate(int family, int d, int n_q, int n_x, int n_phi, double q_max,
                    const double *Z, int nZ, double x_min, double x_max, int n_ext, double *out);
 
 /*
+ * dI_e/dm2_e, the derivative of frgo_integrate's integral in the point's mass (the forward-mode
+ * derivative that implicit steppers need, Sec. 5.2 jacobian_variables, App. F "AD"): the same
+ * sums with every propagator's dG/dm2 = -G^2 taken through the product rule.  Same arguments.
+ */
+int frgo_integrate_dm2(int family, int d, int n_q, int n_x, int n_phi, double q_max, double k,
+                       int regulator, const double *ext, const double *m2, double m2_scalar,
+                       const double *Z, int nZ, double x_min, double x_max, int n_ext,
+                       double *out);
+
+/*
  * General d = 4 one-loop integral with explicit external 4-vectors, on a full hyperspherical
  * product rule (GL in the polar angles theta1, theta2 in [0, pi] with the sin^2/sin Jacobian
  * and GL in the azimuth theta3 in [0, 2pi]):
@@ -108,6 +118,12 @@ int frgo_integrate_ft(int family, int n_q, int n_x, double q_max, double k, int 
                       int statistics, double T, double freq_max, int freq_scaled, int n_tail,
                       const double *ext, const double *m2, double m2_scalar, const double *Z,
                       int nZ, double x_min, double x_max, int n_ext, double *out);
+
+/* dI_e/dm2_e of frgo_integrate_ft (see frgo_integrate_dm2).  Same arguments. */
+int frgo_integrate_ft_dm2(int family, int n_q, int n_x, double q_max, double k, int regulator,
+                          int statistics, double T, double freq_max, int freq_scaled, int n_tail,
+                          const double *ext, const double *m2, double m2_scalar, const double *Z,
+                          int nZ, double x_min, double x_max, int n_ext, double *out);
 
 /*
  * Right-hand side of the LPA flow of u(rho) = U'(rho) for the O(N) model on a rho grid (Sec. 3.1
