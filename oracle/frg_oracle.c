@@ -208,10 +208,9 @@ static int integrate_impl(int family, int d, int n_q, int n_x, int n_phi, double
             for (int a = 0; a < n_q; ++a) {
                 double q = qn[a], q2 = q * q;
                 double den = q2 + frgo_regulator(regulator, q2, k) + mass;
-                double g = 1.0 / den;
-                double prop = deriv ? -2.0 * g * g * g : g * g;
                 double term = pref * qw[a] * pow(q, (double)(d - 1)) *
-                              frgo_regulator_dot(regulator, q2, k) * prop;
+                              frgo_regulator_dot(regulator, q2, k) / (den * den);
+                if (deriv) term *= -2.0 / den;
                 nsum_add(&total, term);
             }
         } else if (family == FRGO_TWO_POINT) {
@@ -225,10 +224,12 @@ static int integrate_impl(int family, int d, int n_q, int n_x, int n_phi, double
                     double l2 = q2 + p * p + 2.0 * q * p * x;
                     double gq = frgo_propagator(regulator, Z, nZ, x_min, x_max, q2, mass, k);
                     double gl = frgo_propagator(regulator, Z, nZ, x_min, x_max, l2, mass, k);
-                    double prop = deriv ? -2.0 * gq * gq * gq * gl - gq * gq * gl * gl
-                                        : gq * gq * gl;
                     double term = pref * qw[a] * xw[b] * sqrt(1.0 - x * x) * q2 * q *
-                                  frgo_regulator_dot(regulator, q2, k) * prop;
+                                  frgo_regulator_dot(regulator, q2, k) * gq * gq * gl;
+                    if (deriv)
+                        term = pref * qw[a] * xw[b] * sqrt(1.0 - x * x) * q2 * q *
+                               frgo_regulator_dot(regulator, q2, k) *
+                               (-2.0 * gq * gq * gq * gl - gq * gq * gl * gl);
                     nsum_add(&inner, term);
                 }
                 nsum_add(&total, nsum_get(&inner));
@@ -250,11 +251,13 @@ static int integrate_impl(int family, int d, int n_q, int n_x, int n_phi, double
                         double gq = frgo_propagator(regulator, Z, nZ, x_min, x_max, q2, mass, k);
                         double g1 = frgo_propagator(regulator, Z, nZ, x_min, x_max, l1, mass, k);
                         double g2 = frgo_propagator(regulator, Z, nZ, x_min, x_max, l2, mass, k);
-                        double prop = deriv ? -2.0 * gq * gq * gq * g1 * g2 -
-                                                  gq * gq * g1 * g1 * g2 - gq * gq * g1 * g2 * g2
-                                            : gq * gq * g1 * g2;
                         double term = pref * qw[a] * xw[b] * fw[c] * sx * sin(phi) * q2 * q *
-                                      frgo_regulator_dot(regulator, q2, k) * prop;
+                                      frgo_regulator_dot(regulator, q2, k) * gq * gq * g1 * g2;
+                        if (deriv)
+                            term = pref * qw[a] * xw[b] * fw[c] * sx * sin(phi) * q2 * q *
+                                   frgo_regulator_dot(regulator, q2, k) *
+                                   (-2.0 * gq * gq * gq * g1 * g2 - gq * gq * g1 * g1 * g2 -
+                                    gq * gq * g1 * g2 * g2);
                         nsum_add(&inner, term);
                     }
                     nsum_add(&mid, nsum_get(&inner));
@@ -352,10 +355,9 @@ static int integrate_ft_impl(int family, int n_q, int n_x, double q_max, double 
                 for (int a = 0; a < n_q; ++a) {
                     double q = qn[a], q2 = q * q;
                     double den = fw_[j] * fw_[j] + q2 + frgo_regulator(regulator, q2, k) + mass;
-                    double g = 1.0 / den;
-                    double prop = deriv ? -2.0 * g * g * g : g * g;
                     double term = fc_[j] * pref * qw[a] * q2 *
-                                  frgo_regulator_dot(regulator, q2, k) * prop;
+                                  frgo_regulator_dot(regulator, q2, k) / (den * den);
+                    if (deriv) term *= -2.0 / den;
                     nsum_add(&total, term);
                 }
             }
@@ -374,10 +376,12 @@ static int integrate_ft_impl(int family, int n_q, int n_x, double q_max, double 
                                            frgo_regulator(regulator, q2, k) + mass);
                         double gl = 1.0 / (wl * wl + frgo_dressing(Z, nZ, x_min, x_max, l2) * l2 +
                                            frgo_regulator(regulator, l2, k) + mass);
-                        double prop = deriv ? -2.0 * gq * gq * gq * gl - gq * gq * gl * gl
-                                            : gq * gq * gl;
                         double term = fc_[j] * pref * qw[a] * xw[b] * q2 *
-                                      frgo_regulator_dot(regulator, q2, k) * prop;
+                                      frgo_regulator_dot(regulator, q2, k) * gq * gq * gl;
+                        if (deriv)
+                            term = fc_[j] * pref * qw[a] * xw[b] * q2 *
+                                   frgo_regulator_dot(regulator, q2, k) *
+                                   (-2.0 * gq * gq * gq * gl - gq * gq * gl * gl);
                         nsum_add(&inner, term);
                     }
                     nsum_add(&total, nsum_get(&inner));
