@@ -181,6 +181,12 @@ typedef struct {
                               float32 propagator of that point, L the largest relative step
                               of the dressing table and ds the float32 error bound of the
                               dressing coordinate (0 for FP64) */
+    double *dout_dm2;      /* device [n_ext] or NULL: dI_e/dm2_e, the derivative of each result in
+                              its point's mass, evaluated in the same pass by forward-mode
+                              differentiation through every propagator (dG/dm2 = -G^2; the
+                              Jacobian entries of implicit steppers, Sec. 5.2 and the "AD" option
+                              of App. F); float64 only (FRG_E_UNSUPPORTED otherwise); not taken
+                              by sessions (FRG_E_UNSUPPORTED) */
 } frg_batch;
 
 /* ---- context ------------------------------------------------------------------------------- */

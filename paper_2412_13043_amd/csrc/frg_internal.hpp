@@ -66,6 +66,7 @@ struct ReqDev {
     const double *Z;
     double *out;
     double *err;
+    double *dout;         // dI/dm2 per point, or null
 };
 
 // A unit of work: external tile `et` of request `req`, radial chunk `chunk`.
@@ -91,7 +92,7 @@ hipError_t launch_ft_rule(int n_q, int n_f, int n_tail, int n_lo, double eta, do
 hipError_t launch_batch(const ReqDev *req_dev_host, const ReqDev *req_dev_ptr, int n_tiles,
                         int lds_bytes, double *contrib, unsigned *counters, hipStream_t s);
 // fam/prec: the family and precision shared by every request of the launch, or -1 (mixed).
-hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg,
+hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg, int der,
                         const TileDev *tiles_dev, int n_tiles, int grid, int lds_bytes,
                         double *contrib, unsigned *counters, unsigned *work_ctr, hipStream_t s);
 hipError_t launch_fill_zero_u32(unsigned *p, size_t n, hipStream_t s);
@@ -101,8 +102,8 @@ hipError_t launch_finalize(const ReqDev &r, const double *contrib, unsigned *cou
 hipError_t launch_lpa_rhs(const ReqDev &r, int n, int n_comp, const double *rho, const double *u,
                           double m2_floor, double *dudt, hipStream_t s);
 hipError_t launch_log_table(double2 *out, hipStream_t s);
-int multi_blocks_per_cu(int fam, int prec, int reg, int lds_bytes);
-int multi_grid(int n_tiles, int fam, int prec, int reg, int lds_bytes, int num_cus);
+int multi_blocks_per_cu(int fam, int prec, int reg, int der, int lds_bytes);
+int multi_grid(int n_tiles, int fam, int prec, int reg, int der, int lds_bytes, int num_cus);
 constexpr int kLogTable = 256;
 
 }  // namespace frg

@@ -254,6 +254,9 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *kc(const T
 #endif
 #ifndef FRG_WAVES_PER_EU_MULTI
 #define FRG_WAVES_PER_EU_MULTI 4
+// mass-derivative instances carry a second set of accumulators
+#define FRG_WAVES_PER_EU_DER 4
+#define FRG_WAVES_PER_EU_DER3 3
 #endif
 // Propagators evaluated together per inner-loop step (instruction-level parallelism).
 #ifndef FRG_ILP
@@ -409,7 +412,12 @@ __device__ __forceinline__ double lane_m2(const ReqDev &r, int e) {
 // Radial prologue for (external point, radial node a): W^_a G(q^2)^2 and the angle coefficients
 // c0 = q^2 + p^2, c1 = 2 q p.
 struct RadialTerm {
-    double wg, c0, c1;
+    double wg, c0, c1, g;  // g = G(q^2) itself (for the mass derivative)
+};
+
+// A contribution and (DER) its derivative in the point's m2.
+struct Dual {
+    double v, d;
 };
 
 __device__ __forceinline__ RadialTerm radial64(const ReqDev &r, const Smem &sm, int a, double p,
@@ -423,6 +431,7 @@ __device__ __forceinline__ RadialTerm radial64(const ReqDev &r, const Smem &sm, 
     t.wg = kc(r.rad.W)[a] * (G * G);
     t.c0 = fma(p, p, q2);
     t.c1 = 2.0 * q * p;
+    t.g = G;
     return t;
 }
 
@@ -430,15 +439,25 @@ __device__ __forceinline__ RadialTerm radial64(const ReqDev &r, const Smem &sm, 
 // the radial leg, m2x the inner leg: equal in vacuum; at finite temperature the inner leg's mass
 // term carries the shifted frequency, m2x = m2 + (w_j + p0)^2 (the radial leg's w_j^2 is folded
 // into the rule's R).
-template <int REG>
-__device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm, int a, double p,
-                                                double m2, double m2x, double inv_k2) {
+// d/dm2 of W G(q^2)^2 G(l^2) = W G(q^2)^2 (-2 G(q^2) G(l^2) - G(l^2)^2): the inner sums of G^
+// and G^2 (units of k^2) give both.
+__device__ __forceinline__ Dual two_point_pair(const RadialTerm &t, double inner, double inner2,
+                                               double inv_k2) {
+    Dual out;
+    out.v = t.wg * (inner * inv_k2);
+    out.d = t.wg * (-2.0 * t.g * (inner * inv_k2) - inner2 * (inv_k2 * inv_k2));
+    return out;
+}
+
+template <int REG, bool DER>
+__device__ __forceinline__ Dual contrib_two64(const ReqDev &r, const Smem &sm, int a, double p,
+                                              double m2, double m2x, double inv_k2) {
     // inner loop in units of k^2: y = l2/k^2 with G(l2) = G^(y)/k^2, G^ = 1/(Z y + R/k^2 + m2/k^2)
     const RadialTerm t = radial64(r, sm, a, p, m2);
     const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2, m2h = m2x * inv_k2;
     const int nx = r.n_x, nZ = r.nZ;
     const double za = r.za, zb1 = r.zbk + 1.0;
-    double inner = 0.0;
+    double inner = 0.0, inner2 = 0.0;
     int b = 0;
     for (; b + FRG_ILP <= nx; b += FRG_ILP) {
         double l2[FRG_ILP], G[FRG_ILP];
@@ -446,24 +465,29 @@ __device__ __forceinline__ double contrib_two64(const ReqDev &r, const Smem &sm,
         for (int w = 0; w < FRG_ILP; ++w) l2[w] = fma(c1, kc(r.ang.x)[b + w], c0);
         propagators64<FRG_ILP, true, REG>(l2, G, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
 #pragma unroll
-        for (int w = 0; w < FRG_ILP; ++w) inner = fma(kc(r.ang.xw)[b + w], G[w], inner);
+        for (int w = 0; w < FRG_ILP; ++w) {
+            inner = fma(kc(r.ang.xw)[b + w], G[w], inner);
+            if (DER) inner2 = fma(kc(r.ang.xw)[b + w], G[w] * G[w], inner2);
+        }
     }
     for (; b < nx; ++b) {
         double l2[1] = {fma(c1, kc(r.ang.x)[b], c0)}, G[1];
         propagators64<1, true, REG>(l2, G, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
         inner = fma(kc(r.ang.xw)[b], G[0], inner);
+        if (DER) inner2 = fma(kc(r.ang.xw)[b], G[0] * G[0], inner2);
     }
-    return t.wg * (inner * inv_k2);
+    if (DER) return two_point_pair(t, inner, inner2, inv_k2);
+    return Dual{t.wg * (inner * inv_k2), 0.0};
 }
 
 // Contribution of (e, a) to the three-point integral.  l1 does not depend on phi, so G(l1^2) is
 // evaluated once per (a, b); l2^2 = (c0 - c1 x cos a) - c1 sqrt(1-x^2) sin a cos phi.
 // One cos1 node b of the three-point contribution (units of k^2): t = xw_b G^(l1^2) and the phi
 // sum inner = sum_c w_c G^(l2^2).
-template <int REG>
+template <int REG, bool DER>
 __device__ __forceinline__ void xterm64(const ReqDev &r, const Smem &sm, int b, double c0,
                                         double c1, double ca, double sa, double m2h, double &t,
-                                        double &inner) {
+                                        double &inner, double &g1b, double &inner2) {
     const int nphi = r.n_phi, nZ = r.nZ;
     const double za = r.za, zb1 = r.zbk + 1.0;
     const double xb = kc(r.ang.x)[b];
@@ -471,7 +495,7 @@ __device__ __forceinline__ void xterm64(const ReqDev &r, const Smem &sm, int b, 
     propagators64<1, false, REG>(l1, g1, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
     const double A2 = fma(-c1, xb * ca, c0);
     const double B2 = -c1 * (kc(r.ang.xs)[b] * sa);
-    double acc = 0.0;
+    double acc = 0.0, acc2 = 0.0;
     int c = 0;
     for (; c + FRG_ILP <= nphi; c += FRG_ILP) {
         double l2[FRG_ILP], G[FRG_ILP];
@@ -480,15 +504,21 @@ __device__ __forceinline__ void xterm64(const ReqDev &r, const Smem &sm, int b, 
             l2[w] = fmax(fma(B2, kc(r.phi.c)[c + w], A2), FRG_L2_TINY);
         propagators64<FRG_ILP, false, REG>(l2, G, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
 #pragma unroll
-        for (int w = 0; w < FRG_ILP; ++w) acc = fma(kc(r.phi.w)[c + w], G[w], acc);
+        for (int w = 0; w < FRG_ILP; ++w) {
+            acc = fma(kc(r.phi.w)[c + w], G[w], acc);
+            if (DER) acc2 = fma(kc(r.phi.w)[c + w], G[w] * G[w], acc2);
+        }
     }
     for (; c < nphi; ++c) {
         double l2[1] = {fmax(fma(B2, kc(r.phi.c)[c], A2), FRG_L2_TINY)}, G[1];
         propagators64<1, false, REG>(l2, G, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
         acc = fma(kc(r.phi.w)[c], G[0], acc);
+        if (DER) acc2 = fma(kc(r.phi.w)[c], G[0] * G[0], acc2);
     }
     t = kc(r.ang.xw)[b] * g1[0];
     inner = acc;
+    g1b = g1[0];
+    inner2 = acc2;
 }
 
 // --------------------------------------------------------------------------------------------
@@ -636,20 +666,20 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
 // loops do (float64: one fused multiply-add per node; float32: the same FRG_ILP-node blocks and
 // compensated additions), so the bits do not depend on lx.  Called by all lanes of a wavefront
 // together when lx > 1; act marks the lanes with a point and radial node to evaluate.
-template <int PREC, int REG>
-__device__ __forceinline__ double contrib_two(const ReqDev &r, const Smem &sm, int a, double p,
-                                              double m2, double m2x, double inv_k2, float &kmax,
-                                              bool act, int sx, int lx) {
+template <int PREC, int REG, bool DER>
+__device__ __forceinline__ Dual contrib_two(const ReqDev &r, const Smem &sm, int a, double p,
+                                            double m2, double m2x, double inv_k2, float &kmax,
+                                            bool act, int sx, int lx) {
     if (lx == 1) {
-        if (!act) return 0.0;
-        return (PREC == 0) ? contrib_two64<REG>(r, sm, a, p, m2, m2x, inv_k2)
-                           : contrib_two32(r, sm, a, p, m2, m2x, inv_k2, kmax);
+        if (!act) return Dual{0.0, 0.0};
+        if (PREC == 0) return contrib_two64<REG, DER>(r, sm, a, p, m2, m2x, inv_k2);
+        return Dual{contrib_two32(r, sm, a, p, m2, m2x, inv_k2, kmax), 0.0};
     }
-    double wg = 0.0, c0 = 0.0, c1 = 0.0;
+    RadialTerm t{0.0, 0.0, 0.0, 0.0};
+    double c0 = 0.0, c1 = 0.0;
     Par32 P;
     if (act) {
-        const RadialTerm t = radial64(r, sm, a, p, m2);
-        wg = t.wg;
+        t = radial64(r, sm, a, p, m2);
         c0 = t.c0 * inv_k2;
         c1 = t.c1 * inv_k2;
         if (PREC == 1) P = par32(r, m2x, inv_k2);
@@ -658,7 +688,7 @@ __device__ __forceinline__ double contrib_two(const ReqDev &r, const Smem &sm, i
     const int nx = r.n_x, nZ = r.nZ;
     const int xbase = (int)threadIdx.x & ~(lx - 1);
     const int nblk = nx - nx % FRG_ILP;  // nodes the float32 loop covers in whole blocks
-    double inner = 0.0;
+    double inner = 0.0, inner2 = 0.0;
     Kahan32 acc{0.0f, 0.0f};
     float blk = 0.0f;
     for (int j0 = 0; j0 < nx; j0 += lx) {
@@ -680,7 +710,9 @@ __device__ __forceinline__ double contrib_two(const ReqDev &r, const Smem &sm, i
         for (int k = 0; k < nk; ++k) {
             const int bk = j0 + k;
             if (PREC == 0) {
-                inner = fma(kc(r.ang.xw)[bk], __shfl(g, xbase + k), inner);
+                const double gk = __shfl(g, xbase + k);
+                inner = fma(kc(r.ang.xw)[bk], gk, inner);
+                if (DER) inner2 = fma(kc(r.ang.xw)[bk], gk * gk, inner2);
             } else {
                 const float gk = __shfl(gf, xbase + k);
                 if (bk < nblk) {
@@ -693,8 +725,11 @@ __device__ __forceinline__ double contrib_two(const ReqDev &r, const Smem &sm, i
             }
         }
     }
-    if (PREC == 0) return wg * (inner * inv_k2);
-    return wg * (((double)acc.s - (double)acc.c) * inv_k2);
+    if (PREC == 0) {
+        if (DER) return two_point_pair(t, inner, inner2, inv_k2);
+        return Dual{t.wg * (inner * inv_k2), 0.0};
+    }
+    return Dual{t.wg * (((double)acc.s - (double)acc.c) * inv_k2), 0.0};
 }
 
 __device__ __forceinline__ void xterm32(const ReqDev &r, const Smem &sm, const Par32 &P, int b,
@@ -734,15 +769,18 @@ __device__ __forceinline__ void xterm32(const ReqDev &r, const Smem &sm, const P
 // across lanes and folds them into mid in cos1 order, so mid is the same sequence of fused
 // multiply-adds for every lx.  All lanes of a wavefront call this together when lx > 1 (the
 // cross-lane pulls need them); act marks the lanes with a point and radial node to evaluate.
-template <int PREC, int REG>
-__device__ __forceinline__ double contrib_three(const ReqDev &r, const Smem &sm, int a, double p,
-                                                double ca, double sa, double m2, double inv_k2,
-                                                float &kmax, bool act, int sx, int lx) {
-    double wg = 0.0, c0 = 0.0, c1 = 0.0;
+// DER: d/dm2 of G(q^2)^2 G1 G2 = -2 G(q^2)^3 G1 G2 - G(q^2)^2 (G1^2 G2 + G1 G2^2); per cos1 node
+// the phi sums of G2 and G2^2 and G1 itself give midA = sum xw G1^2 sum G2 and
+// midB = sum xw G1 sum G2^2 next to mid = sum xw G1 sum G2 (units of k^2).
+template <int PREC, int REG, bool DER>
+__device__ __forceinline__ Dual contrib_three(const ReqDev &r, const Smem &sm, int a, double p,
+                                              double ca, double sa, double m2, double inv_k2,
+                                              float &kmax, bool act, int sx, int lx) {
+    RadialTerm t{0.0, 0.0, 0.0, 0.0};
+    double c0 = 0.0, c1 = 0.0;
     Par32 P;
     if (act) {
-        const RadialTerm t = radial64(r, sm, a, p, m2);
-        wg = t.wg;
+        t = radial64(r, sm, a, p, m2);
         c0 = t.c0 * inv_k2;
         c1 = t.c1 * inv_k2;
         if (PREC == 1) P = par32(r, m2, inv_k2);
@@ -750,25 +788,38 @@ __device__ __forceinline__ double contrib_three(const ReqDev &r, const Smem &sm,
     const double m2h = m2 * inv_k2;
     const int nx = r.n_x;
     const int xbase = (int)threadIdx.x & ~(lx - 1);
-    double mid = 0.0;
+    double mid = 0.0, midA = 0.0, midB = 0.0;
     for (int j0 = 0; j0 < nx; j0 += lx) {
         const int b = j0 + sx;
-        double tb = 0.0, ib = 0.0;
+        double tb = 0.0, ib = 0.0, gb = 0.0, i2b = 0.0;
         if (act && b < nx) {
             if (PREC == 0)
-                xterm64<REG>(r, sm, b, c0, c1, ca, sa, m2h, tb, ib);
+                xterm64<REG, DER>(r, sm, b, c0, c1, ca, sa, m2h, tb, ib, gb, i2b);
             else
                 xterm32(r, sm, P, b, c0, c1, ca, sa, kmax, tb, ib);
         }
         if (lx == 1) {
             mid = fma(tb, ib, mid);
+            if (DER) {
+                midA = fma(tb * gb, ib, midA);
+                midB = fma(tb, i2b, midB);
+            }
         } else {
             const int nk = min(lx, nx - j0);
-            for (int k = 0; k < nk; ++k)
-                mid = fma(__shfl(tb, xbase + k), __shfl(ib, xbase + k), mid);
+            for (int k = 0; k < nk; ++k) {
+                const double tk = __shfl(tb, xbase + k), ik = __shfl(ib, xbase + k);
+                mid = fma(tk, ik, mid);
+                if (DER) {
+                    midA = fma(tk * __shfl(gb, xbase + k), ik, midA);
+                    midB = fma(tk, __shfl(i2b, xbase + k), midB);
+                }
+            }
         }
     }
-    return wg * (mid * (inv_k2 * inv_k2));
+    const double i4 = inv_k2 * inv_k2;
+    if (!DER) return Dual{t.wg * (mid * i4), 0.0};
+    return Dual{t.wg * (mid * i4),
+                t.wg * (-2.0 * t.g * (mid * i4) - (midA + midB) * (i4 * inv_k2))};
 }
 
 // float32 form's stated relative error bound per result (u = 2^-24, kappa = largest float32
@@ -869,15 +920,28 @@ __device__ __forceinline__ void bind_smem(Smem &sm, double2 *lds, int nZ, float 
 // LPA: one lane per external point, the whole radial sum in one lane, no scratch.
 // One LPA integral pref * sum_a W_a / (A_a + m2)^2 with A_a = k^2 (q^_a^2 + R^_a); the float32
 // form states (16 + 3 kappa) 2^-24 in err.
+// With r.dout (float64) also dI/dm2 = pref sum_a W_a (-2 G_a^3) into *dv.
 template <int PREC>
-__device__ __forceinline__ double lpa_integral(const ReqDev &r, double m2, double &err) {
+__device__ __forceinline__ double lpa_integral(const ReqDev &r, double m2, double &err,
+                                               double *dv = nullptr) {
     const int nq = r.n_q;
     if (PREC == 0) {
         double acc = 0.0;
-        for (int a = 0; a < nq; ++a) {
-            const double qh = kc(r.rad.q)[a];
-            const double g = fm::rcp_nr(fma(r.k2, fma(qh, qh, kc(r.rad.R)[a]), m2));
-            acc = fma(kc(r.rad.W)[a], g * g, acc);
+        if (dv) {
+            double dacc = 0.0;
+            for (int a = 0; a < nq; ++a) {
+                const double qh = kc(r.rad.q)[a];
+                const double g = fm::rcp_nr(fma(r.k2, fma(qh, qh, kc(r.rad.R)[a]), m2));
+                acc = fma(kc(r.rad.W)[a], g * g, acc);
+                dacc = fma(kc(r.rad.W)[a], g * g * g, dacc);
+            }
+            *dv = r.pref * (-2.0 * dacc);
+        } else {
+            for (int a = 0; a < nq; ++a) {
+                const double qh = kc(r.rad.q)[a];
+                const double g = fm::rcp_nr(fma(r.k2, fma(qh, qh, kc(r.rad.R)[a]), m2));
+                acc = fma(kc(r.rad.W)[a], g * g, acc);
+            }
         }
         err = 0.0;
         return r.pref * acc;
@@ -908,9 +972,10 @@ template <int PREC>
 __device__ __forceinline__ void tile_lpa(const ReqDev &r, int et) {
     const int e = et * kWave + (int)threadIdx.x;
     if (e >= r.n_ext) return;
-    double err;
-    const double v = lpa_integral<PREC>(r, lane_m2(r, e), err);
+    double err, dv = 0.0;
+    const double v = lpa_integral<PREC>(r, lane_m2(r, e), err, r.dout ? &dv : nullptr);
     r.out[e] = v;
+    if (r.dout) r.dout[e] = dv;
     if (r.err) r.err[e] = err;
 }
 
@@ -925,7 +990,7 @@ __device__ __forceinline__ double readlane64(double v, int l) {
 // Vertex families (FAM 2 two-point, 3 three-point, 5 two-point at finite temperature): lanes =
 // (external point, radial sub-lane, cos1 sub-lane); the point's contributions are added in radial
 // order inside the wavefront, or (radially chunked requests) stored for the finalize kernel.
-template <int FAM, int PREC, int REG>
+template <int FAM, int PREC, int REG, bool DER>
 __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int et, int chunk,
                                             double *__restrict__ contrib,
                                             unsigned *__restrict__ counters) {
@@ -957,18 +1022,19 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
     }
     // contribution of radial node a (valid in the point's sx == 0 lanes); every lane of the
     // wavefront calls it together, lanes without work pass act = false
-    auto node = [&](int a, bool act) -> double {
+    auto node = [&](int a, bool act) -> Dual {
         if (FAM == 3)
-            return contrib_three<PREC, REG>(r, sm, act ? a : 0, p, ca, sa, m2, inv_k2, kmax, act,
-                                            sx, lx);
+            return contrib_three<PREC, REG, DER>(r, sm, act ? a : 0, p, ca, sa, m2, inv_k2, kmax,
+                                                 act, sx, lx);
         if (FAM == 5) {
             // radial index a = (frequency j, spatial node): the inner leg's frequency w_j + p0
             const int ai = act ? a : 0;
             const double wl = kc(r.rad.w0)[ai] + p0;
-            return contrib_two<PREC, REG>(r, sm, ai, p, m2, fma(wl, wl, m2), inv_k2, kmax, act,
-                                          sx, lx);
+            return contrib_two<PREC, REG, DER>(r, sm, ai, p, m2, fma(wl, wl, m2), inv_k2, kmax,
+                                               act, sx, lx);
         }
-        return contrib_two<PREC, REG>(r, sm, act ? a : 0, p, m2, m2, inv_k2, kmax, act, sx, lx);
+        return contrib_two<PREC, REG, DER>(r, sm, act ? a : 0, p, m2, m2, inv_k2, kmax, act, sx,
+                                           lx);
     };
     if (r.chunks == 1) {
         // The wavefront holds every radial node of its points.  The lq radial sub-lanes of a
@@ -978,17 +1044,23 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
         // scratch stores, no barrier and no device-scope fence (an L2 writeback and invalidate
         // on a multi-XCD part).
         const int base = lane & ~((1 << lpl) - 1);
-        double sum = 0.0;
+        double sum = 0.0, dsum = 0.0;
         for (int r0 = 0; r0 < r.n_q; r0 += lq) {
             const int a = r0 + sq;
-            const double v = node(a, valid && a < r.n_q);
+            const Dual v = node(a, valid && a < r.n_q);
             const int nk = min(lq, r.n_q - r0);
             if (lpl == 6) {
                 // one point per wavefront: the source lanes are the same for every lane, so the
                 // values are broadcast with scalar reads instead of LDS permutes (same additions)
-                for (int k = 0; k < nk; ++k) sum += readlane64(v, k * lx);
+                for (int k = 0; k < nk; ++k) {
+                    sum += readlane64(v.v, k * lx);
+                    if (DER) dsum += readlane64(v.d, k * lx);
+                }
             } else {
-                for (int k = 0; k < nk; ++k) sum += __shfl(v, base + k * lx);
+                for (int k = 0; k < nk; ++k) {
+                    sum += __shfl(v.v, base + k * lx);
+                    if (DER) dsum += __shfl(v.d, base + k * lx);
+                }
             }
         }
         if (PREC == 1) {
@@ -996,15 +1068,21 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
         }
         if (valid && sub == 0) {
             r.out[e] = r.pref * sum;
+            if (DER && r.dout) r.dout[e] = r.pref * dsum;
             if (r.err) r.err[e] = (PREC == 1) ? fp32_bound(kmax, *sm.zslope, r) : 0.0;
         }
         return;
     }
+    // DER: the derivative contributions follow the values as a second [n_q][n_ext] block
+    const long long dblk = (long long)r.n_q * r.n_ext;
     for (int r0 = a0; r0 < a1; r0 += lq) {
         const int a = r0 + sq;
         const bool act = valid && a < a1;
-        const double v = node(a, act);
-        if (act && sx == 0) blk[(long long)a * r.n_ext + e] = v;
+        const Dual v = node(a, act);
+        if (act && sx == 0) {
+            blk[(long long)a * r.n_ext + e] = v.v;
+            if (DER && r.dout) blk[dblk + (long long)a * r.n_ext + e] = v.d;
+        }
     }
     // the finalize kernel (a later launch on the same stream) adds the chunks in radial order
     if (PREC == 1) {
@@ -1022,6 +1100,10 @@ __global__ void __launch_bounds__(64) finalize_kernel(ReqDev r, const double *co
     if (e >= r.n_ext) return;
     const double s = radial_sum(contrib + r.contrib_base, r.n_q, r.n_ext, e);
     r.out[e] = r.pref * s;
+    if (r.dout) {
+        const double *d = contrib + r.contrib_base + (long long)r.n_q * r.n_ext;
+        r.dout[e] = r.pref * radial_sum(d, r.n_q, r.n_ext, e);
+    }
     if (r.precision == 1) {
         unsigned *kslot = counters + r.ctr_base;
         if (r.err)
@@ -1033,9 +1115,10 @@ __global__ void __launch_bounds__(64) finalize_kernel(ReqDev r, const double *co
 }
 
 // One request: tile = blockIdx.x -> (external tile, chunk).
-template <int FAM, int PREC, int REG>
+template <int FAM, int PREC, int REG, bool DER>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
-    FAM == 3 ? FRG_WAVES_PER_EU_MULTI : FRG_WAVES_PER_EU_BATCH)))
+    DER ? (FAM == 3 ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_DER)
+        : (FAM == 3 ? FRG_WAVES_PER_EU_MULTI : FRG_WAVES_PER_EU_BATCH))))
 batch_kernel(ReqDev r, double *contrib, unsigned *counters) {
     extern __shared__ double2 lds_dyn[];
     if (FAM == 1) {
@@ -1050,26 +1133,32 @@ batch_kernel(ReqDev r, double *contrib, unsigned *counters) {
     stage_log(sm, r.logt);
     stage_dressing(r, sm);
     __syncthreads();
-    tile_vertex<FAM, PREC, REG>(r, sm, et, chunk, contrib, counters);
+    tile_vertex<FAM, PREC, REG, DER>(r, sm, et, chunk, contrib, counters);
 }
 
 typedef void (*batch_fn)(ReqDev, double *, unsigned *);
 
-// Kernel instance for (family, precision, regulator); the float32 form exists for the
-// exponential regulator only, and the LPA family reads its regulator from the radial rule.
-template <int F>
-static batch_fn batch_for_family(int prec, int reg) {
-    if (prec == 1) return batch_kernel<F, 1, 0>;
-    if (reg == 1) return batch_kernel<F, 0, 1>;
-    if (reg == 2) return batch_kernel<F, 0, 2>;
-    return batch_kernel<F, 0, 0>;
+// Kernel instance for (family, precision, regulator, mass derivative); the float32 form exists
+// for the exponential regulator without derivative only, and the LPA kernel reads its regulator
+// from the radial rule and its derivative flag from the request.
+template <int F, bool D>
+static batch_fn batch_for_reg(int reg) {
+    if (reg == 1) return batch_kernel<F, 0, 1, D>;
+    if (reg == 2) return batch_kernel<F, 0, 2, D>;
+    return batch_kernel<F, 0, 0, D>;
 }
 
-static batch_fn batch_variant(int fam, int prec, int reg) {
-    if (fam == 1) return prec == 0 ? batch_kernel<1, 0, 0> : batch_kernel<1, 1, 0>;
-    if (fam == 2) return batch_for_family<2>(prec, reg);
-    if (fam == 5) return batch_for_family<5>(prec, reg);
-    return batch_for_family<3>(prec, reg);
+template <int F>
+static batch_fn batch_for_family(int prec, int reg, bool der) {
+    if (prec == 1) return batch_kernel<F, 1, 0, false>;
+    return der ? batch_for_reg<F, true>(reg) : batch_for_reg<F, false>(reg);
+}
+
+static batch_fn batch_variant(int fam, int prec, int reg, bool der) {
+    if (fam == 1) return prec == 0 ? batch_kernel<1, 0, 0, false> : batch_kernel<1, 1, 0, false>;
+    if (fam == 2) return batch_for_family<2>(prec, reg, der);
+    if (fam == 5) return batch_for_family<5>(prec, reg, der);
+    return batch_for_family<3>(prec, reg, der);
 }
 
 hipError_t launch_batch(const ReqDev *req_host, const ReqDev *req_dev_ptr, int n_tiles,
@@ -1077,8 +1166,8 @@ hipError_t launch_batch(const ReqDev *req_host, const ReqDev *req_dev_ptr, int n
     (void)req_dev_ptr;
     const ReqDev &r = *req_host;
     if (n_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(batch_variant(r.family, r.precision, r.reg), dim3(n_tiles), dim3(kWave),
-                       lds_bytes, s, r, contrib, counters);
+    hipLaunchKernelGGL(batch_variant(r.family, r.precision, r.reg, r.dout != nullptr),
+                       dim3(n_tiles), dim3(kWave), lds_bytes, s, r, contrib, counters);
     return hipGetLastError();
 }
 
@@ -1091,44 +1180,55 @@ hipError_t launch_batch(const ReqDev *req_host, const ReqDev *req_dev_ptr, int n
 // regulators); a launch whose requests all share one family, precision and regulator uses the
 // instance specialised for them, which carries only that path and so needs fewer registers
 // (more resident waves).
-template <int FAM, int PREC, int REG>
+template <int FAM, int PREC, int REG, bool DER>
 __device__ __forceinline__ void vertex_tile(const ReqDev &r, Smem &sm, const TileDev &td,
                                             double *contrib, unsigned *counters) {
-    tile_vertex<FAM, PREC, REG>(r, sm, td.et, td.chunk, contrib, counters);
+    tile_vertex<FAM, PREC, REG, DER>(r, sm, td.et, td.chunk, contrib, counters);
 }
 
-template <int F>
+template <int F, bool D>
+__device__ __forceinline__ void vertex_tile_reg(const ReqDev &r, Smem &sm, const TileDev &td,
+                                                double *contrib, unsigned *counters) {
+    if (r.reg == 1)
+        vertex_tile<F, 0, 1, D>(r, sm, td, contrib, counters);
+    else if (r.reg == 2)
+        vertex_tile<F, 0, 2, D>(r, sm, td, contrib, counters);
+    else
+        vertex_tile<F, 0, 0, D>(r, sm, td, contrib, counters);
+}
+
+// The general kernel comes in two instances: without mass derivatives, and (D) for launches
+// with at least one request that asks for them; there a request without dout runs the same
+// derivative-carrying code (identical values) and skips the derivative stores.
+template <int F, bool D>
 __device__ __forceinline__ void vertex_tile_any(const ReqDev &r, Smem &sm, const TileDev &td,
                                                 double *contrib, unsigned *counters) {
     if (r.precision == 1)
-        vertex_tile<F, 1, 0>(r, sm, td, contrib, counters);
-    else if (r.reg == 1)
-        vertex_tile<F, 0, 1>(r, sm, td, contrib, counters);
-    else if (r.reg == 2)
-        vertex_tile<F, 0, 2>(r, sm, td, contrib, counters);
+        vertex_tile<F, 1, 0, false>(r, sm, td, contrib, counters);
     else
-        vertex_tile<F, 0, 0>(r, sm, td, contrib, counters);
+        vertex_tile_reg<F, D>(r, sm, td, contrib, counters);
 }
 
-template <int FAM, int PREC, int REG>
+template <int FAM, int PREC, int REG, bool DER>
 __device__ __forceinline__ void multi_tile(const ReqDev &r, Smem &sm, const TileDev &td,
                                            double *contrib, unsigned *counters) {
     if (FAM > 0) {
-        vertex_tile<(FAM > 0 ? FAM : 2), (PREC > 0 ? PREC : 0), (REG > 0 ? REG : 0)>(
+        vertex_tile<(FAM > 0 ? FAM : 2), (PREC > 0 ? PREC : 0), (REG > 0 ? REG : 0), DER>(
             r, sm, td, contrib, counters);
         return;
     }
     if (r.family == 2)
-        vertex_tile_any<2>(r, sm, td, contrib, counters);
+        vertex_tile_any<2, DER>(r, sm, td, contrib, counters);
     else if (r.family == 5)
-        vertex_tile_any<5>(r, sm, td, contrib, counters);
+        vertex_tile_any<5, DER>(r, sm, td, contrib, counters);
     else
-        vertex_tile_any<3>(r, sm, td, contrib, counters);
+        vertex_tile_any<3, DER>(r, sm, td, contrib, counters);
 }
 
-template <int FAM, int PREC, int REG>
+template <int FAM, int PREC, int REG, bool DER>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
-    (FAM < 0 || FAM == 3) ? FRG_WAVES_PER_EU_MULTI : FRG_WAVES_PER_EU_BATCH)))
+    DER ? ((FAM < 0 || FAM == 3) ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_DER)
+        : ((FAM < 0 || FAM == 3) ? FRG_WAVES_PER_EU_MULTI : FRG_WAVES_PER_EU_BATCH))))
 multi_kernel(const ReqDev *__restrict__ reqs, const TileDev *__restrict__ tiles, int n_tiles,
              double *contrib, unsigned *counters, unsigned *work) {
     extern __shared__ double2 lds_dyn[];
@@ -1170,7 +1270,7 @@ multi_kernel(const ReqDev *__restrict__ reqs, const TileDev *__restrict__ tiles,
                 __syncthreads();
                 staged = td.req;
             }
-            multi_tile<FAM, PREC, REG>(r, sm, td, contrib, counters);
+            multi_tile<FAM, PREC, REG, DER>(r, sm, td, contrib, counters);
             __syncthreads();
         }
     }
@@ -1178,29 +1278,36 @@ multi_kernel(const ReqDev *__restrict__ reqs, const TileDev *__restrict__ tiles,
 
 typedef void (*multi_fn)(const ReqDev *, const TileDev *, int, double *, unsigned *, unsigned *);
 
-template <int F>
-static multi_fn multi_for_family(int prec, int reg) {
-    if (prec == 1) return multi_kernel<F, 1, 0>;
-    if (reg == 1) return multi_kernel<F, 0, 1>;
-    if (reg == 2) return multi_kernel<F, 0, 2>;
-    return multi_kernel<F, 0, 0>;
+template <int F, bool D>
+static multi_fn multi_for_reg(int reg) {
+    if (reg == 1) return multi_kernel<F, 0, 1, D>;
+    if (reg == 2) return multi_kernel<F, 0, 2, D>;
+    return multi_kernel<F, 0, 0, D>;
 }
 
-static multi_fn multi_variant(int fam, int prec, int reg) {
-    // any of fam/prec/reg < 0: the general kernel
-    if (fam < 0 || prec < 0 || reg < 0) return multi_kernel<-1, -1, -1>;
-    if (fam == 1) return prec == 0 ? multi_kernel<1, 0, 0> : multi_kernel<1, 1, 0>;
-    if (fam == 2) return multi_for_family<2>(prec, reg);
-    if (fam == 3) return multi_for_family<3>(prec, reg);
-    if (fam == 5) return multi_for_family<5>(prec, reg);
-    return multi_kernel<-1, -1, -1>;
+template <int F>
+static multi_fn multi_for_family(int prec, int reg, int der) {
+    if (prec == 1) return multi_kernel<F, 1, 0, false>;
+    return der ? multi_for_reg<F, true>(reg) : multi_for_reg<F, false>(reg);
+}
+
+// (fam, prec, reg) shared by every request of the launch, or -1 (mixed: the general kernel);
+// der = 1 if any request asks for the mass derivative.
+static multi_fn multi_variant(int fam, int prec, int reg, int der) {
+    if (fam < 0 || prec < 0 || reg < 0)
+        return der ? multi_kernel<-1, -1, -1, true> : multi_kernel<-1, -1, -1, false>;
+    if (fam == 1) return prec == 0 ? multi_kernel<1, 0, 0, false> : multi_kernel<1, 1, 0, false>;
+    if (fam == 2) return multi_for_family<2>(prec, reg, der);
+    if (fam == 3) return multi_for_family<3>(prec, reg, der);
+    if (fam == 5) return multi_for_family<5>(prec, reg, der);
+    return der ? multi_kernel<-1, -1, -1, true> : multi_kernel<-1, -1, -1, false>;
 }
 
 // Workgroups of the fused kernel resident per CU with `lds_bytes` of dynamic LDS (sizes the
 // persistent grid).
-int multi_blocks_per_cu(int fam, int prec, int reg, int lds_bytes) {
+int multi_blocks_per_cu(int fam, int prec, int reg, int der, int lds_bytes) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, multi_variant(fam, prec, reg), kWave,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, multi_variant(fam, prec, reg, der), kWave,
                                                      lds_bytes) != hipSuccess ||
         n < 1)
         n = 4;
@@ -1210,20 +1317,21 @@ int multi_blocks_per_cu(int fam, int prec, int reg, int lds_bytes) {
 // Persistent grid: at most the workgroups the CUs hold at once, and no more than the tile list
 // needs in whole rounds -- with R = ceil(tiles / resident) rounds, ceil(tiles / R) workgroups
 // share the tiles evenly instead of leaving a last round mostly idle.
-int multi_grid(int n_tiles, int fam, int prec, int reg, int lds_bytes, int num_cus) {
-    const int resident = std::max(1, multi_blocks_per_cu(fam, prec, reg, lds_bytes) * num_cus);
+int multi_grid(int n_tiles, int fam, int prec, int reg, int der, int lds_bytes, int num_cus) {
+    const int resident =
+        std::max(1, multi_blocks_per_cu(fam, prec, reg, der, lds_bytes) * num_cus);
     if (n_tiles <= resident) return std::max(n_tiles, 1);
     const int rounds = (n_tiles + resident - 1) / resident;
     return (n_tiles + rounds - 1) / rounds;
 }
 
-hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg,
+hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg, int der,
                         const TileDev *tiles_dev, int n_tiles, int grid, int lds_bytes,
                         double *contrib, unsigned *counters, unsigned *work_ctr, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
     const hipError_t e = launch_fill_zero_u32(work_ctr, 2, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(multi_variant(fam, prec, reg), dim3(grid), dim3(kWave), lds_bytes, s,
+    hipLaunchKernelGGL(multi_variant(fam, prec, reg, der), dim3(grid), dim3(kWave), lds_bytes, s,
                        reqs_dev, tiles_dev, n_tiles, contrib, counters, work_ctr);
     return hipGetLastError();
 }

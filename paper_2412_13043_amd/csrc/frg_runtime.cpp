@@ -178,6 +178,10 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
         set_error("n_ext must be in [0, 2^24], got %d", b->n_ext);
         return FRG_E_INVAL;
     }
+    if (b->dout_dm2 && d->precision != FRG_FP64) {
+        set_error("dout_dm2 (the mass derivative) is implemented in float64 only");
+        return FRG_E_UNSUPPORTED;
+    }
     if (b->n_ext == 0) return FRG_OK;
     if (!b->out) {
         set_error("out is NULL");
@@ -207,7 +211,7 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
     }
     if (device_ptrs) {
         // every pointer the kernels dereference must be device-accessible memory
-        const void *ptrs[4] = {b->ext, b->m2, b->out, b->err_out};
+        const void *ptrs[5] = {b->ext, b->m2, b->out, b->err_out, b->dout_dm2};
         for (const void *p : ptrs) {
             if (!p) continue;
             hipPointerAttribute_t attr;
@@ -416,7 +420,8 @@ TileShape choose_shape(frg_context *ctx, const frg_integral_desc &desc, int n_ex
 // reduces its points within the wavefront and needs neither scratch nor counters.
 size_t contrib_doubles(const ReqDev &r) {
     if (r.family == 1 || r.chunks == 1) return 0;
-    return (size_t)r.n_q * (size_t)r.n_ext;  // [n_q][n_ext] contributions
+    // [n_q][n_ext] contributions (and as many derivative contributions)
+    return (size_t)r.n_q * (size_t)r.n_ext * (r.dout ? 2 : 1);
 }
 
 int counter_count(const ReqDev &r) {
@@ -516,6 +521,7 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
     r.m2 = b.m2;
     r.out = b.out;
     r.err = b.err_out;
+    r.dout = b.dout_dm2;
     *out = r;
     return FRG_OK;
 }
@@ -597,16 +603,19 @@ std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out) {
     return sorted;
 }
 
-void common_kind(const std::vector<ReqDev> &reqs, int *fam, int *prec, int *reg) {
-    // the LPA kernel takes its regulator from the radial rule alone
+void common_kind(const std::vector<ReqDev> &reqs, int *fam, int *prec, int *reg, int *der) {
+    // the LPA kernel takes its regulator from the radial rule and its derivative flag from the
+    // request
     auto reg_of = [](const ReqDev &r) { return r.family == 1 ? 0 : r.reg; };
     *fam = reqs.empty() ? -1 : reqs[0].family;
     *prec = reqs.empty() ? -1 : reqs[0].precision;
     *reg = reqs.empty() ? -1 : reg_of(reqs[0]);
+    *der = 0;  // 1 if any vertex request asks for the mass derivative
     for (const ReqDev &r : reqs) {
         if (r.family != *fam) *fam = -1;
         if (r.precision != *prec) *prec = -1;
         if (reg_of(r) != *reg) *reg = -1;
+        if (r.family != 1 && r.dout) *der = 1;
     }
     if (*fam < 0 || *prec < 0 || *reg < 0) *fam = *prec = *reg = -1;
 }
@@ -642,9 +651,9 @@ frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s,
                                  hipMemcpyHostToDevice, s));
     FRG_HIP_CHECK(hipEventRecord(sc->staged, s));
     sc->last_tiles = (int)sorted.size();
-    common_kind(reqs, &sc->last_fam, &sc->last_prec, &sc->last_reg);
+    common_kind(reqs, &sc->last_fam, &sc->last_prec, &sc->last_reg, &sc->last_der);
     sc->last_grid = std::min(multi_grid((int)sorted.size(), sc->last_fam, sc->last_prec,
-                                        sc->last_reg, lds, ctx->num_cus),
+                                        sc->last_reg, sc->last_der, lds, ctx->num_cus),
         std::max(grid_waves, 1));
     sc->last_lds = lds;
     sc->last_nreqs = (int)reqs.size();
@@ -653,7 +662,7 @@ frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s,
 
 frg_status relaunch_multi(Scratch *sc, hipStream_t s) {
     FRG_HIP_CHECK(launch_multi((const ReqDev *)sc->reqs.ptr, sc->last_fam, sc->last_prec,
-                               sc->last_reg, (const TileDev *)sc->tiles.ptr, sc->last_tiles, sc->last_grid,
+                               sc->last_reg, sc->last_der, (const TileDev *)sc->tiles.ptr, sc->last_tiles, sc->last_grid,
                                sc->last_lds, (double *)sc->contrib.ptr,
                                (unsigned *)sc->counters.ptr, (unsigned *)sc->work.ptr, s));
     return FRG_OK;

@@ -80,7 +80,7 @@ struct Scratch {
     // last fused call on this stream: its argument bytes and launch shape (plan cache)
     std::vector<char> last_key;
     int last_tiles = 0, last_grid = 0, last_lds = 0, last_nreqs = 0, last_fam = -1, last_prec = -1,
-        last_reg = -1;
+        last_reg = -1, last_der = -1;
     ~Scratch() {
         if (host_stage) (void)hipHostFree(host_stage);
         if (staged) (void)hipEventDestroy(staged);
@@ -187,8 +187,9 @@ frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s,
 frg_status relaunch_multi(Scratch *sc, hipStream_t s);
 // Tiles of a fused launch in longest-first order, and the dynamic LDS bytes it needs.
 std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out);
-// Family, precision and regulator shared by all requests (all -1 if any differs).
-void common_kind(const std::vector<ReqDev> &reqs, int *fam, int *prec, int *reg);
+// Family, precision and regulator shared by all requests (all -1 if any differs), and whether
+// any request asks for the mass derivative.
+void common_kind(const std::vector<ReqDev> &reqs, int *fam, int *prec, int *reg, int *der);
 int lds_bytes_for(const ReqDev &r);
 
 }  // namespace frg

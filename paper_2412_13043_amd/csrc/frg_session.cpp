@@ -271,11 +271,11 @@ class HipExecutor : public Executor {
         FRG_HIP_CHECK(launch_fill_zero_u32((unsigned *)sl.counters.ptr, nctr, sl.stream));
         const ReqDev *reqs_dev = (const ReqDev *)sl.tables.ptr;
         const TileDev *tiles_dev = (const TileDev *)((char *)sl.tables.ptr + tiles_off);
-        int fam, prec, reg;
-        common_kind(rd, &fam, &prec, &reg);
-        const int grid = multi_grid((int)tiles.size(), fam, prec, reg, lds, ctx->num_cus);
-        FRG_HIP_CHECK(launch_multi(reqs_dev, fam, prec, reg, tiles_dev, (int)tiles.size(), grid,
-                                   lds, (double *)base, (unsigned *)sl.counters.ptr,
+        int fam, prec, reg, der;
+        common_kind(rd, &fam, &prec, &reg, &der);
+        const int grid = multi_grid((int)tiles.size(), fam, prec, reg, der, lds, ctx->num_cus);
+        FRG_HIP_CHECK(launch_multi(reqs_dev, fam, prec, reg, der, tiles_dev, (int)tiles.size(),
+                                   grid, lds, (double *)base, (unsigned *)sl.counters.ptr,
                                    (unsigned *)sl.work.ptr, sl.stream));
         sl.host_out.clear();
         pos = out_start;
@@ -557,6 +557,10 @@ frg_status frg_session_submit(frg_session *s, const frg_integral_desc *desc,
     }
     frg_status st = validate(desc, batch_host, false);
     if (st != FRG_OK) return st;
+    if (batch_host->dout_dm2) {
+        set_error("sessions do not return the mass derivative (dout_dm2 must be NULL)");
+        return FRG_E_UNSUPPORTED;
+    }
     auto r = std::make_unique<SessReq>();
     r->desc = *desc;
     r->host = *batch_host;

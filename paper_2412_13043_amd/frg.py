@@ -66,7 +66,8 @@ class frg_log_table(ctypes.Structure):
 
 class frg_batch(ctypes.Structure):
     _fields_ = [("n_ext", c_int), ("ext", c_void_p), ("m2", c_void_p), ("m2_scalar", c_double),
-                ("Z", frg_log_table), ("out", c_void_p), ("err_out", c_void_p)]
+                ("Z", frg_log_table), ("out", c_void_p), ("err_out", c_void_p),
+                ("dout_dm2", c_void_p)]
 
 
 class frg_flow_state(ctypes.Structure):
@@ -295,9 +296,11 @@ def make_desc(family: int, n_q: int, q_max: float, *, n_x: int = 0, n_phi: int =
 
 
 def make_batch(n_ext: int, out, *, ext=None, m2=None, m2_scalar: float = 0.0, Z=None,
-               x_min: float = 1e-3, x_max: float = 1e3, err_out=None) -> frg_batch:
+               x_min: float = 1e-3, x_max: float = 1e3, err_out=None, dout=None) -> frg_batch:
+    """dout: optional device tensor receiving dI/dm2 per point (float64 descriptors)."""
     zt = frg_log_table(_dptr(Z), 0 if Z is None else int(Z.numel()), x_min, x_max)
-    return frg_batch(n_ext, _dptr(ext), _dptr(m2), m2_scalar, zt, _dptr(out), _dptr(err_out))
+    return frg_batch(n_ext, _dptr(ext), _dptr(m2), m2_scalar, zt, _dptr(out), _dptr(err_out),
+                     _dptr(dout))
 
 
 class Context:
@@ -325,9 +328,9 @@ class Context:
             pass
 
     def integrate(self, desc, out, *, ext=None, m2=None, m2_scalar=0.0, Z=None, x_min=1e-3,
-                  x_max=1e3, err_out=None, stream=None):
+                  x_max=1e3, err_out=None, dout=None, stream=None):
         b = make_batch(int(out.numel()), out, ext=ext, m2=m2, m2_scalar=m2_scalar, Z=Z,
-                       x_min=x_min, x_max=x_max, err_out=err_out)
+                       x_min=x_min, x_max=x_max, err_out=err_out, dout=dout)
         frg_integrate_batch(self.handle, desc, b, _stream(stream))
         return out
 
