@@ -119,7 +119,8 @@ def time_kernel(torch, fn, steps, warmup):
     return t1 - t0, [a.elapsed_time(b) / steps]
 
 
-def two_point_batch_setup(torch, frg, B=256, precision=0, seed_m2=None, tau=0.1, regulator=0):
+def two_point_batch_setup(torch, frg, B=256, precision=0, seed_m2=None, tau=0.1, regulator=0,
+                          dm2=False):
     from paper_2412_13043_amd import workloads as wl
 
     if seed_m2 is None:
@@ -133,12 +134,14 @@ def two_point_batch_setup(torch, frg, B=256, precision=0, seed_m2=None, tau=0.1,
     tm = _dev(torch, m2a) if m2a is not None else None
     out = torch.empty((B, p.size), dtype=torch.float64, device="cuda")
     err = torch.empty((B, p.size), dtype=torch.float64, device="cuda") if precision else None
+    dout = torch.empty((B, p.size), dtype=torch.float64, device="cuda") if dm2 else None
     desc = frg.make_desc(2, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX, precision=precision,
                          near_pole_tau=tau if precision else 0.0, regulator=regulator)
     batches = [frg.make_batch(p.size, out[b], ext=tp, m2=None if tm is None else tm[b],
                               m2_scalar=m2, Z=tZ[b], x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
-                              err_out=None if err is None else err[b]) for b in range(B)]
-    keep = (tp, tZ, tm, out, err)
+                              err_out=None if err is None else err[b],
+                              dout=None if dout is None else dout[b]) for b in range(B)]
+    keep = (tp, tZ, tm, out, err, dout)
     nodes = B * p.size * wl.TWO_NQ * wl.TWO_NX
     return [desc] * B, batches, out, err, nodes, keep
 
@@ -506,9 +509,10 @@ def secondary(torch, frg, wl, ctx, serving_seconds=4.0):
     del keep_ft
     # the same two-point batch with the paper's default regulator (polynomial-exponential s_8)
     # and with the flat one
-    for name, reg in (("two_point_poly_exp_s8_256", 1), ("two_point_flat_256", 2)):
+    for name, reg, dm2 in (("two_point_poly_exp_s8_256", 1, False), ("two_point_flat_256", 2, False),
+                           ("two_point_with_dI_dm2_256", 0, True)):
         log(f"bench: {name}")
-        dr, br, _, _, nr, keep_r = two_point_batch_setup(torch, frg, regulator=reg)
+        dr, br, _, _, nr, keep_r = two_point_batch_setup(torch, frg, regulator=reg, dm2=dm2)
         wall, ev = time_kernel(torch, lambda: ctx.integrate_multi(dr, br), 5, 1)
         msr = float(np.mean(ev))
         ex[name] = {"gnodes_per_s": round(nr / (msr * 1e-3) / 1e9, 2),
