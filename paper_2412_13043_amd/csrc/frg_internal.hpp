@@ -99,6 +99,10 @@ hipError_t launch_fill_zero_u32(unsigned *p, size_t n, hipStream_t s);
 // radially chunked requests: radial sums after the integrand launch (no-op otherwise)
 hipError_t launch_finalize(const ReqDev &r, const double *contrib, unsigned *counters,
                            hipStream_t s);
+// After a fused launch: the radial sums of its chunked requests, one workgroup per (request,
+// block of 64 points) entry of fin (req, et = block).
+hipError_t launch_multi_finalize(const ReqDev *reqs_dev, const TileDev *fin_dev, int n_fin,
+                                 const double *contrib, unsigned *counters, hipStream_t s);
 hipError_t launch_lpa_rhs(const ReqDev &r, int n, int n_comp, const double *rho, const double *u,
                           double m2_floor, double *dudt, hipStream_t s);
 hipError_t launch_log_table(double2 *out, hipStream_t s);

@@ -1094,10 +1094,8 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
 // Radially chunked requests: one thread per external point adds the [n_q][n_ext] contributions
 // in radial order (the same additions as the in-wavefront sum of single-chunk tiles) and states
 // the float32 bound from the amplification slots, which it returns to zero.
-__global__ void __launch_bounds__(64) finalize_kernel(ReqDev r, const double *contrib,
-                                                     unsigned *counters) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= r.n_ext) return;
+__device__ __forceinline__ void finalize_point(const ReqDev &r, int e, const double *contrib,
+                                               unsigned *counters) {
     const double s = radial_sum(contrib + r.contrib_base, r.n_q, r.n_ext, e);
     r.out[e] = r.pref * s;
     if (r.dout) {
@@ -1112,6 +1110,34 @@ __global__ void __launch_bounds__(64) finalize_kernel(ReqDev r, const double *co
     } else if (r.err) {
         r.err[e] = 0.0;
     }
+}
+
+__global__ void __launch_bounds__(64) finalize_kernel(ReqDev r, const double *contrib,
+                                                     unsigned *counters) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= r.n_ext) return;
+    finalize_point(r, e, contrib, counters);
+}
+
+// The radially chunked requests of a fused launch, after it: workgroup b sums the 64 points from
+// 64 fin[b].et of request fin[b].req.
+__global__ void __launch_bounds__(64) multi_finalize_kernel(const ReqDev *__restrict__ reqs,
+                                                           const TileDev *__restrict__ fin,
+                                                           const double *contrib,
+                                                           unsigned *counters) {
+    const TileDev f = fin[blockIdx.x];
+    const ReqDev &r = reqs[f.req];
+    const int e = f.et * kWave + (int)threadIdx.x;
+    if (e >= r.n_ext) return;
+    finalize_point(r, e, contrib, counters);
+}
+
+hipError_t launch_multi_finalize(const ReqDev *reqs_dev, const TileDev *fin_dev, int n_fin,
+                                 const double *contrib, unsigned *counters, hipStream_t s) {
+    if (n_fin <= 0) return hipSuccess;
+    hipLaunchKernelGGL(multi_finalize_kernel, dim3(n_fin), dim3(kWave), 0, s, reqs_dev, fin_dev,
+                       contrib, counters);
+    return hipGetLastError();
 }
 
 // One request: tile = blockIdx.x -> (external tile, chunk).

@@ -407,13 +407,14 @@ TileShape heuristic_shape(const frg_integral_desc &desc, int n_ext, int target_w
 }
 
 TileShape choose_shape(frg_context *ctx, const frg_integral_desc &desc, int n_ext,
-                       int target_waves, bool allow_chunks) {
+                       int target_waves, ShapeUse use) {
     // finite-temperature requests share the tuned shapes of their vacuum counterparts
     const frg_integral_desc d = plan_desc(desc);
     std::vector<int> key = {d.family, d.precision, d.n_q, d.n_x, d.n_phi, n_ext, target_waves};
     auto it = ctx->tuned.find(key);
-    if (it != ctx->tuned.end() && (allow_chunks || it->second.chunks == 1)) return it->second;
-    return heuristic_shape(d, n_ext, target_waves, allow_chunks);
+    if (it != ctx->tuned.end() && (use != ShapeUse::kNoChunks || it->second.chunks == 1))
+        return it->second;
+    return heuristic_shape(d, n_ext, target_waves, use == ShapeUse::kRequest);
 }
 
 // Only radially chunked requests hand contributions between workgroups; a single-chunk tile
@@ -431,6 +432,10 @@ int counter_count(const ReqDev &r) {
 }
 
 int tile_count(const ReqDev &r) { return r.ext_tiles * r.chunks; }
+
+int finalize_blocks(const ReqDev &r) {
+    return (r.family == 1 || r.chunks <= 1) ? 0 : (r.n_ext + kWave - 1) / kWave;
+}
 
 int lds_bytes_for(const ReqDev &r) {
     // logarithm table, float64 dressing pairs, float32 dressing pairs (float32 form)
@@ -632,6 +637,13 @@ frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s,
     int lds = 0;
     std::vector<TileDev> sorted = make_tiles(reqs, &lds);
     if (sorted.empty()) return FRG_OK;
+    // radially chunked requests: (request, block of 64 points) entries of the finalize launch,
+    // stored after the tiles
+    const size_t n_work = sorted.size();
+    for (size_t i = 0; i < reqs.size(); ++i)
+        for (int b = 0; b < finalize_blocks(reqs[i]); ++b)
+            sorted.push_back(TileDev{(int)i, b, 0, 0});
+    const int n_fin = (int)(sorted.size() - n_work);
     size_t rb = reqs.size() * sizeof(ReqDev), tb = sorted.size() * sizeof(TileDev);
     if (!sc->staged) FRG_HIP_CHECK(hipEventCreateWithFlags(&sc->staged, hipEventDisableTiming));
     // the previous upload from the staging area must have finished before it is rewritten
@@ -650,9 +662,10 @@ frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s,
     FRG_HIP_CHECK(hipMemcpyAsync(sc->tiles.ptr, (char *)sc->host_stage + rb, tb,
                                  hipMemcpyHostToDevice, s));
     FRG_HIP_CHECK(hipEventRecord(sc->staged, s));
-    sc->last_tiles = (int)sorted.size();
+    sc->last_tiles = (int)n_work;
+    sc->last_fin = n_fin;
     common_kind(reqs, &sc->last_fam, &sc->last_prec, &sc->last_reg, &sc->last_der);
-    sc->last_grid = std::min(multi_grid((int)sorted.size(), sc->last_fam, sc->last_prec,
+    sc->last_grid = std::min(multi_grid((int)n_work, sc->last_fam, sc->last_prec,
                                         sc->last_reg, sc->last_der, lds, ctx->num_cus),
         std::max(grid_waves, 1));
     sc->last_lds = lds;
@@ -665,6 +678,10 @@ frg_status relaunch_multi(Scratch *sc, hipStream_t s) {
                                sc->last_reg, sc->last_der, (const TileDev *)sc->tiles.ptr, sc->last_tiles, sc->last_grid,
                                sc->last_lds, (double *)sc->contrib.ptr,
                                (unsigned *)sc->counters.ptr, (unsigned *)sc->work.ptr, s));
+    FRG_HIP_CHECK(launch_multi_finalize((const ReqDev *)sc->reqs.ptr,
+                                        (const TileDev *)sc->tiles.ptr + sc->last_tiles,
+                                        sc->last_fin, (const double *)sc->contrib.ptr,
+                                        (unsigned *)sc->counters.ptr, s));
     return FRG_OK;
 }
 
@@ -920,17 +937,22 @@ frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc 
     std::vector<ReqDev> reqs;
     size_t n_contrib = 0, n_ctr = 0, n_tiles = 0;
     const int target_total = 32 * ctx->num_cus;  // about twice the resident waves
+    int n_active = 0;
+    for (int i = 0; i < n; ++i) n_active += batches[i].n_ext > 0;
     for (int i = 0; i < n; ++i) {
         if (batches[i].n_ext == 0) continue;
         int target = std::max(1, (int)std::lround(target_total * nodes[i] / total_nodes));
-        // fused launches take no radial chunks (they would need a finalize pass per request)
-        TileShape shape = choose_shape(ctx, descs[i], batches[i].n_ext, target, false);
+        // radially chunked (tuned) shapes are summed by one finalize launch after the fused one;
+        // a launch of one request is planned as that request alone
+        const ShapeUse use = n_active == 1 ? ShapeUse::kRequest : ShapeUse::kFused;
+        if (n_active == 1) target = 16 * ctx->num_cus;
+        TileShape shape = choose_shape(ctx, descs[i], batches[i].n_ext, target, use);
         ReqDev r;
         if ((st = make_request(ctx, descs[i], batches[i], shape, 1, 0.0, 1.0, &r)) != FRG_OK)
             return st;
         n_contrib += contrib_doubles(r);
         n_ctr += counter_count(r);
-        n_tiles += tile_count(r);
+        n_tiles += tile_count(r) + finalize_blocks(r);
         reqs.push_back(r);
     }
     if (reqs.empty()) return FRG_OK;

@@ -80,7 +80,7 @@ struct Scratch {
     // last fused call on this stream: its argument bytes and launch shape (plan cache)
     std::vector<char> last_key;
     int last_tiles = 0, last_grid = 0, last_lds = 0, last_nreqs = 0, last_fam = -1, last_prec = -1,
-        last_reg = -1, last_der = -1;
+        last_reg = -1, last_der = -1, last_fin = 0;
     ~Scratch() {
         if (host_stage) (void)hipHostFree(host_stage);
         if (staged) (void)hipEventDestroy(staged);
@@ -167,16 +167,22 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &desc, const f
 frg_status ft_rule_into(frg_context *ctx, const frg_integral_desc &d, void *buf, size_t bytes,
                         RadialRule *out, hipStream_t s);
 size_t ft_rule_bytes(int n_q, int n_f);
+// Where a tile shape is used: a request launched alone (radial chunks wherever the heuristic
+// finds them worth a finalize launch), a fused launch (tuned shapes as tuned, the heuristic
+// without radial chunks: measured, the fused launch's larger wave target would trade lanes for
+// chunks at a loss), or a launch with no finalize pass (no chunks at all: sessions).
+enum class ShapeUse { kRequest, kFused, kNoChunks };
 // Tile shape for a request: the autotuned one if the context has it, else the heuristic.
-// allow_chunks = false (fused launches) restricts both to single-chunk shapes.
 TileShape choose_shape(frg_context *ctx, const frg_integral_desc &desc, int n_ext,
-                       int target_waves, bool allow_chunks = true);
+                       int target_waves, ShapeUse use = ShapeUse::kRequest);
 TileShape heuristic_shape(const frg_integral_desc &desc, int n_ext, int target_waves,
                           bool allow_chunks = true);
 // Doubles of contribution scratch and counters a request needs.
 size_t contrib_doubles(const ReqDev &r);
 int counter_count(const ReqDev &r);
 int tile_count(const ReqDev &r);
+// Workgroups of the finalize launch a fused launch needs for this request (0 unless chunked).
+int finalize_blocks(const ReqDev &r);
 // Scratch for a stream, grown to at least the given sizes.
 frg_status get_scratch(frg_context *ctx, hipStream_t s, size_t contrib_doubles, size_t counters,
                        size_t n_reqs, size_t n_tiles, Scratch **out);

@@ -564,3 +564,71 @@ def test_autotune_keeps_results_bitwise(env, tmp_path, monkeypatch):
         assert torch.equal(before, again)
     finally:
         ctx.close()
+
+
+def test_fused_launch_with_radially_chunked_requests(env, tmp_path, monkeypatch):
+    # tuned shapes with radial chunks for some requests of one fused launch (one finalize launch
+    # after it sums them): every result, float32 bound and derivative equal to the request alone
+    frg, _, torch = env
+    target_total = 32 * torch.cuda.get_device_properties(0).multi_processor_count
+    rng = np.random.default_rng(123)
+    n = 70
+    p = 10 ** rng.uniform(-3, 2, n)
+    A = rng.uniform(0, math.pi, n)
+    m2 = rng.uniform(-0.3, 2.0, n)
+    m2n = rng.uniform(-0.95, -0.5, n)
+    Z = wl.dressing_table(9)
+    reqs = [  # (desc, ext, m2, err, dout)
+        (frg.make_desc(2, 13, 10.0, n_x=6), p, m2, False, True),
+        (frg.make_desc(2, 13, 10.0, n_x=6, precision=1, near_pole_tau=0.1), p, m2n, True, False),
+        (frg.make_desc(3, 10, 10.0, n_x=5, n_phi=3), np.concatenate([p, A]), m2, False, False),
+        (frg.make_desc(2, 9, 10.0, n_x=4, regulator=1), p, m2, False, False),
+        (frg.make_desc(1, 32, 6.0), None, m2, False, False),
+    ]
+    nodes = [n * 13 * 6, n * 13 * 6, n * 10 * 5 * 3, n * 9 * 4, n * 32]
+    tot = float(sum(nodes))
+    targets = [max(1, round(target_total * x / tot)) for x in nodes]
+    lines = [f"2 0 13 6 0 {n} {targets[0]} 1 3 0",      # 2 radial lanes, 3 chunks
+             f"2 1 13 6 0 {n} {targets[1]} 0 13 0",     # one radial node per chunk
+             f"3 0 10 5 3 {n} {targets[2]} 2 2 1"]      # radial and cos1 lanes, 2 chunks
+    cache = tmp_path / "fused_chunks.txt"
+    cache.write_text("\n".join(lines) + "\n")
+    monkeypatch.setenv("FRG_AUTOTUNE_CACHE", str(cache))
+    ctx = frg.Context(0)
+    try:
+        tz = _d(torch, Z)
+        alone, outs, errs, douts, batches, keep = [], [], [], [], [], []
+        for d, ext, mm, want_err, want_d in reqs:
+            te = None if ext is None else _d(torch, ext)
+            tm = _d(torch, mm)
+            o = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+            eo = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda") \
+                if want_err else None
+            do = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda") \
+                if want_d else None
+            ctx.integrate(d, o, ext=te, m2=tm, Z=tz, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
+                          err_out=eo, dout=do)
+            torch.cuda.synchronize()
+            alone.append(tuple(None if t is None else t.cpu().numpy() for t in (o, eo, do)))
+            o2, e2, d2 = (torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+                          if t is not None else None for t in (o, eo, do))
+            outs.append(o2)
+            errs.append(e2)
+            douts.append(d2)
+            batches.append(frg.make_batch(n, o2, ext=te, m2=tm, Z=tz, x_min=wl.Z_XMIN,
+                                          x_max=wl.Z_XMAX, err_out=e2, dout=d2))
+            keep += [te, tm]
+        for rep in range(2):  # the second call relaunches the cached plan
+            ctx.integrate_multi([r[0] for r in reqs], batches)
+            torch.cuda.synchronize()
+            for i in range(len(reqs)):
+                assert np.array_equal(outs[i].cpu().numpy(), alone[i][0]), (rep, i)
+                if errs[i] is not None:
+                    assert np.array_equal(errs[i].cpu().numpy(), alone[i][1]), (rep, i)
+                if douts[i] is not None:
+                    assert np.array_equal(douts[i].cpu().numpy(), alone[i][2]), (rep, i)
+        ref = oracle.integrate(2, 13, 10.0, n_x=6, ext=p, m2=m2, Z=Z)
+        assert _rel(alone[0][0], ref) <= TOL
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
