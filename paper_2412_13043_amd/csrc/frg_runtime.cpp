@@ -353,7 +353,7 @@ static int ilog2(int v) {
 }
 
 TileShape heuristic_shape(const frg_integral_desc &desc, int n_ext, int target_waves,
-                          bool allow_chunks) {
+                          bool allow_chunks, bool fused) {
     TileShape s;
     const frg_integral_desc d = plan_desc(desc);
     if (d.family == 1) return s;
@@ -388,9 +388,25 @@ TileShape heuristic_shape(const frg_integral_desc &desc, int n_ext, int target_w
     // with work enough to gain that back (about 15 us of the whole chip).
     const double nodes = (double)n_ext * d.n_q * d.n_x * (d.family == 3 ? d.n_phi : 1);
     if (!allow_chunks || nodes < 8.0e6) return s;
-    // 64 lanes per point and still too few tiles: move radial lanes to cos1 lanes and give the
-    // radial nodes freed that way to further chunks (same lanes per point, twice the tiles)
-    while (le == 1 && ext_tiles * s.chunks < target_waves && s.lq_log2 > 0 &&
+    const int lq_now = 1 << s.lq_log2;
+    if (fused) {
+        // A fused launch shares the chip with other requests: a request whose wavefronts hold
+        // one point each gets radial chunks for about three rounds of the persistent grid
+        // (twice its share of the wave target), so that the tile counter can balance the tail.
+        // Two-point families only (measured: +12 % on the finite-temperature batch; sharing
+        // cos1 nodes among lanes instead costs them 30-40 %).
+        if (le == 1 && d.family != 3) {
+            const int max_chunks = (d.n_q + lq_now - 1) / lq_now;
+            const int want = (2 * target_waves + ext_tiles - 1) / ext_tiles;
+            s.chunks = std::max(1, std::min(max_chunks, want));
+        }
+        return s;
+    }
+    // 64 lanes per point and still too few tiles (three-point): move radial lanes to cos1 lanes
+    // and give the radial nodes freed that way to further chunks (same lanes per point, twice
+    // the tiles).  The two-point families take plain radial chunks below instead (their cos1
+    // sums shared across lanes cost more than they gain).
+    while (d.family == 3 && le == 1 && ext_tiles * s.chunks < target_waves && s.lq_log2 > 0 &&
            (2 << s.lx_log2) <= d.n_x &&
            lane_nodes(s.lq_log2 - 1, s.lx_log2 + 1, s.chunks * 2) >= kMinLaneNodes) {
         --s.lq_log2;
@@ -414,7 +430,8 @@ TileShape choose_shape(frg_context *ctx, const frg_integral_desc &desc, int n_ex
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end() && (use != ShapeUse::kNoChunks || it->second.chunks == 1))
         return it->second;
-    return heuristic_shape(d, n_ext, target_waves, use == ShapeUse::kRequest);
+    return heuristic_shape(d, n_ext, target_waves, use != ShapeUse::kNoChunks,
+                           use == ShapeUse::kFused);
 }
 
 // Only radially chunked requests hand contributions between workgroups; a single-chunk tile
@@ -837,7 +854,7 @@ frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const f
             cands.push_back(TileShape{lq, 1, lx});
         }
     }
-    cands.push_back(heuristic_shape(*desc, batch->n_ext, target, true));
+    cands.push_back(heuristic_shape(*desc, batch->n_ext, target, true, false));
     hipEvent_t e0, e1;
     FRG_HIP_CHECK(hipEventCreate(&e0));
     FRG_HIP_CHECK(hipEventCreate(&e1));

@@ -168,15 +168,15 @@ frg_status ft_rule_into(frg_context *ctx, const frg_integral_desc &d, void *buf,
                         RadialRule *out, hipStream_t s);
 size_t ft_rule_bytes(int n_q, int n_f);
 // Where a tile shape is used: a request launched alone (radial chunks wherever the heuristic
-// finds them worth a finalize launch), a fused launch (tuned shapes as tuned, the heuristic
-// without radial chunks: measured, the fused launch's larger wave target would trade lanes for
-// chunks at a loss), or a launch with no finalize pass (no chunks at all: sessions).
+// finds them worth a finalize launch), a fused launch (tuned shapes as tuned; the heuristic
+// chunks only two-point requests whose wavefronts hold one point each), or a launch with no
+// finalize pass (no chunks at all: sessions).
 enum class ShapeUse { kRequest, kFused, kNoChunks };
 // Tile shape for a request: the autotuned one if the context has it, else the heuristic.
 TileShape choose_shape(frg_context *ctx, const frg_integral_desc &desc, int n_ext,
                        int target_waves, ShapeUse use = ShapeUse::kRequest);
 TileShape heuristic_shape(const frg_integral_desc &desc, int n_ext, int target_waves,
-                          bool allow_chunks = true);
+                          bool allow_chunks = true, bool fused = false);
 // Doubles of contribution scratch and counters a request needs.
 size_t contrib_doubles(const ReqDev &r);
 int counter_count(const ReqDev &r);
