@@ -368,7 +368,7 @@ def workload_setup(torch, frg, wl, ctx, name):
                               "64x32 GL nodes, per-RHS tabulated Z, m2=0.5, float64, one fused "
                               "frg_integrate_multi launch",
                   "nodes_per_step": nodes, "rhs_per_step": 256}
-        return (lambda: ctx.integrate_multi(descs, batches), nodes, 2, "frg::multi_kernel<2, 0>",
+        return (lambda: ctx.integrate_multi(descs, batches), nodes, 2, "frg::multi_kernel<2, 0, 0, false>",
                 config, keep)
     if name == "three_point_8":
         P, A, m3, Z3 = wl.three_point_batch()
@@ -383,7 +383,7 @@ def workload_setup(torch, frg, wl, ctx, name):
                               "pairs x 64x32x16 GL nodes, per-RHS tabulated Z, m2 in U[0.1,2], "
                               "float64, one fused frg_integrate_multi launch",
                   "nodes_per_step": nodes, "rhs_per_step": 8}
-        return (lambda: ctx.integrate_multi([d3] * 8, b3), nodes, 3, "frg::multi_kernel<3, 0>",
+        return (lambda: ctx.integrate_multi([d3] * 8, b3), nodes, 3, "frg::multi_kernel<3, 0, 0, false>",
                 config, (text, tm3, tZ3, o3))
     if name == "two_point_ft_16":
         descs, batches, nodes, keep = two_point_ft_setup(torch, frg, wl)
@@ -393,7 +393,7 @@ def workload_setup(torch, frg, wl, ctx, name):
                               "nodes), per-RHS tabulated Z, m2=0.5, float64, one fused "
                               "frg_integrate_multi launch",
                   "nodes_per_step": nodes, "rhs_per_step": 16}
-        return (lambda: ctx.integrate_multi(descs, batches), nodes, 5, "frg::multi_kernel<5, 0>",
+        return (lambda: ctx.integrate_multi(descs, batches), nodes, 5, "frg::multi_kernel<5, 0, 0, false>",
                 config, keep)
     rho, u, m2 = wl.lpa_batch()
     tm = _dev(torch, m2.reshape(-1))
@@ -403,7 +403,7 @@ def workload_setup(torch, frg, wl, ctx, name):
     config = {"workload": "LPA O(4) d=3: 4096 right-hand sides x 64 rho points x 32 GL nodes, "
                           "float64, one frg_integrate_batch launch",
               "nodes_per_step": nodes, "rhs_per_step": 4096}
-    return (lambda: ctx.integrate(d1, o1, m2=tm), nodes, 1, "frg::batch_kernel<1, 0>", config,
+    return (lambda: ctx.integrate(d1, o1, m2=tm), nodes, 1, "frg::batch_kernel<1, 0, 0, false>", config,
             (tm, o1))
 
 
