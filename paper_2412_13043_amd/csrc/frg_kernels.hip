@@ -896,15 +896,18 @@ __device__ __forceinline__ void stage_dressing(const ReqDev &r, Smem &sm) {
 }
 
 // Radial sum of one point's contributions in radial order, with 8 loads in flight per wait.
+// The point's contributions added in radial order; kInFlight loads are issued before their
+// additions (the finalize runs one thread per point, few wavefronts: load latency bound).
 __device__ __forceinline__ double radial_sum(const double *blk, int n_q, long long stride, int e) {
+    constexpr int kInFlight = 32;
     double s = 0.0;
     int a = 0;
-    for (; a + 8 <= n_q; a += 8) {
-        double v[8];
+    for (; a + kInFlight <= n_q; a += kInFlight) {
+        double v[kInFlight];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = blk[(long long)(a + j) * stride + e];
+        for (int j = 0; j < kInFlight; ++j) v[j] = blk[(long long)(a + j) * stride + e];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) s += v[j];
+        for (int j = 0; j < kInFlight; ++j) s += v[j];
     }
     for (; a < n_q; ++a) s += blk[(long long)a * stride + e];
     return s;
