@@ -322,8 +322,19 @@ __constant__ double kRegInv[17] = {0.0,       1.0,        1.0 / 2.0,  1.0 / 3.0,
                                    1.0 / 10.0, 1.0 / 11.0, 1.0 / 12.0, 1.0 / 13.0, 1.0 / 14.0,
                                    1.0 / 15.0, 1.0 / 16.0};
 
-// S_N(y) = sum_{i=1}^{N} y^i / i (Horner), 1 <= N <= 16.
+// S_N(y) = sum_{i=1}^{N} y^i / i (Horner), 1 <= N <= 16; the paper's N = 8 as a fixed chain
+// (the order is uniform across the wavefront, so the branch is too).
 __device__ __forceinline__ double poly_s(double y, int n) {
+    if (n == 8) {
+        double acc = fma(0.125, y, 1.0 / 7.0);
+        acc = fma(acc, y, 1.0 / 6.0);
+        acc = fma(acc, y, 0.2);
+        acc = fma(acc, y, 0.25);
+        acc = fma(acc, y, 1.0 / 3.0);
+        acc = fma(acc, y, 0.5);
+        acc = fma(acc, y, 1.0);
+        return acc * y;
+    }
     double acc = kc(kRegInv)[n];
     for (int i = n - 1; i >= 1; --i) acc = fma(acc, y, kc(kRegInv)[i]);
     return acc * y;
