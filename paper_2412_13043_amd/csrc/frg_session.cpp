@@ -208,7 +208,7 @@ class HipExecutor : public Executor {
                 b.Z.values = (const double *)(blk + r->off_z);
             }
             int target = std::max(1, (int)std::lround(target_total * (double)r->nodes / total));
-            // fused launch: no radial chunks (they would need a finalize pass per request)
+            // session launches run no finalize pass: single-chunk shapes only
             TileShape shape = choose_shape(ctx, r->desc, b.n_ext, target, ShapeUse::kNoChunks);
             ReqDev q;
             frg_status st = make_request(ctx, r->desc, b, shape, 1, 0.0, 1.0, &q);
