@@ -1016,11 +1016,12 @@ frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
     b.m2 = state->state;
     b.Z = state->Z;
     b.out = dstate_dt;
-    frg_status st = validate(desc, &b, true);
-    if (st != FRG_OK) return st;
+    frg_status st = FRG_OK;
 
     std::lock_guard<std::mutex> lk(ctx->mu);
     FRG_HIP_CHECK(hipSetDevice(ctx->device));
+    // the plan's key holds every descriptor and state field and every pointer: a plan found
+    // under it was validated when it was built
     std::vector<long long> key = {desc->family, desc->d, desc->n_q, desc->n_x, desc->n_phi,
                                   desc->precision, n, state->n_comp, (long long)stream,
                                   (long long)state->state, (long long)state->grid,
@@ -1039,6 +1040,7 @@ frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
     }
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
+        if ((st = validate(desc, &b, true)) != FRG_OK) return st;
         auto g = std::make_unique<FlowGraph>();
         TileShape shape = choose_shape(ctx, *desc, b.n_ext, 16 * ctx->num_cus);
         ReqDev r;
