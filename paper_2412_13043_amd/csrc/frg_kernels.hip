@@ -1265,10 +1265,17 @@ __device__ __forceinline__ void multi_tile(const ReqDev &r, Smem &sm, const Tile
         vertex_tile_any<3, DER>(r, sm, td, contrib, counters);
 }
 
+// Occupancy target of a fused-kernel instance: the three-point family and the general kernel
+// carry more state than the two-point families, the mass derivative a second set of
+// accumulators, and the polynomial-exponential regulator's exponent a few more registers.
+constexpr int multi_waves(int fam, int reg, bool der) {
+    return der ? ((fam < 0 || fam == 3) ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_DER)
+               : ((fam < 0 || fam == 3) ? (reg == 1 ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_MULTI)
+                                        : (reg == 1 ? FRG_WAVES_PER_EU_MULTI : FRG_WAVES_PER_EU_BATCH));
+}
+
 template <int FAM, int PREC, int REG, bool DER>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
-    DER ? ((FAM < 0 || FAM == 3) ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_DER)
-        : ((FAM < 0 || FAM == 3) ? FRG_WAVES_PER_EU_MULTI : FRG_WAVES_PER_EU_BATCH))))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(multi_waves(FAM, REG, DER))))
 multi_kernel(const ReqDev *__restrict__ reqs, const TileDev *__restrict__ tiles, int n_tiles,
              double *contrib, unsigned *counters, unsigned *work) {
     extern __shared__ double2 lds_dyn[];
