@@ -79,6 +79,7 @@ def _load():
                                               I, P]
             lib.frgo_integrate_dm2.argtypes = lib.frgo_integrate.argtypes
             lib.frgo_integrate_ft_dm2.argtypes = lib.frgo_integrate_ft.argtypes
+            lib.frgo_integrate_dz.argtypes = [I, I, I, D, D, I, P, P, D, P, I, D, D, I, P]
             _lib = lib
     return _lib
 
@@ -143,6 +144,19 @@ def integrate(family, n_q, q_max, *, d=None, n_x=0, n_phi=0, k=1.0, regulator=RE
             _ptr(Za), 0 if Za is None else len(Za), x_min, x_max, n, _ptr(out))
     if rc != 0:
         raise ValueError(f"frgo_integrate rejected the arguments (rc={rc})")
+    return out
+
+
+def integrate_dz(n_q, q_max, *, n_x, ext, Z, k=1.0, regulator=REG_EXP, m2=None, m2_scalar=0.0,
+                 x_min=1e-3, x_max=1e3):
+    """dI_e/dZ_i of the two-point integral (see frg_oracle.h): array [n_ext, len(Z)]."""
+    ext_arr, Za, m2a = _f64(ext), _f64(Z), _f64(m2)
+    n = len(ext_arr)
+    out = np.empty((n, len(Za)))
+    rc = _load().frgo_integrate_dz(4, n_q, n_x, q_max, k, regulator, _ptr(ext_arr), _ptr(m2a),
+                                   m2_scalar, _ptr(Za), len(Za), x_min, x_max, n, _ptr(out))
+    if rc != 0:
+        raise ValueError(f"frgo_integrate_dz rejected the arguments (rc={rc})")
     return out
 
 

@@ -285,6 +285,72 @@ int frgo_integrate_dm2(int family, int d, int n_q, int n_x, int n_phi, double q_
                           nZ, x_min, x_max, n_ext, 1, out);
 }
 
+/* Cell and fraction of the dressing's interpolation at l2 (the same clamping as frgo_dressing):
+ * Z(l2) = (1 - f) Z_i + f Z_{i+1} for nZ >= 2; nZ == 1 gives i = 0, f = 0 (Z(l2) = Z_0). */
+static void dressing_cell(int nZ, double x_min, double x_max, double l2, int *i, double *f) {
+    *i = 0;
+    *f = 0.0;
+    if (nZ == 1) return;
+    double u = (l2 > 0.0) ? 0.5 * log(l2) : -INFINITY;
+    double lmin = log(x_min), lmax = log(x_max);
+    double delta = (lmax - lmin) / (double)(nZ - 1);
+    double s = (u - lmin) / delta;
+    if (!(s > 0.0)) s = 0.0;
+    if (s > (double)(nZ - 1)) s = (double)(nZ - 1);
+    int c = (int)floor(s);
+    if (c > nZ - 2) c = nZ - 2;
+    *i = c;
+    *f = s - (double)c;
+}
+
+/* Adds v * dZ(l2)/dZ_i to acc[i] for every table entry i: (1 - f) v to the cell's first entry
+ * and f v to its second. */
+static void add_dressing_weights(nsum *acc, int nZ, int i, double f, double v) {
+    nsum_add(&acc[i], (1.0 - f) * v);
+    if (nZ > 1) nsum_add(&acc[i + 1], f * v);
+}
+
+int frgo_integrate_dz(int d, int n_q, int n_x, double q_max, double k, int regulator,
+                      const double *ext, const double *m2, double m2_scalar, const double *Z,
+                      int nZ, double x_min, double x_max, int n_ext, double *out) {
+    if (n_ext < 0 || out == NULL || ext == NULL || Z == NULL || nZ < 1 || nZ > MAXN) return -1;
+    if (d != 4 || n_q < 1 || n_q > MAXN || n_x < 1 || n_x > MAXN) return -1;
+    if (!(q_max > 0.0) || !(k > 0.0) || !(x_min > 0.0) || !(x_max > x_min)) return -1;
+    static __thread double qn[MAXN], qw[MAXN], xn[MAXN], xw[MAXN];
+    static __thread nsum acc[MAXN];
+    frgo_gauss_legendre(n_q, 0.0, q_max * k, qn, qw);
+    frgo_gauss_legendre(n_x, -1.0, 1.0, xn, xw);
+    double pref = 4.0 * PI / pow(2.0 * PI, 4.0);
+    for (int e = 0; e < n_ext; ++e) {
+        double p = ext[e];
+        double mass = m2 ? m2[e] : m2_scalar;
+        for (int i = 0; i < nZ; ++i) acc[i].s = acc[i].c = 0.0;
+        for (int a = 0; a < n_q; ++a) {
+            double q = qn[a], q2 = q * q;
+            double gq = frgo_propagator(regulator, Z, nZ, x_min, x_max, q2, mass, k);
+            int iq;
+            double fq;
+            dressing_cell(nZ, x_min, x_max, q2, &iq, &fq);
+            for (int b = 0; b < n_x; ++b) {
+                double x = xn[b];
+                double l2 = q2 + p * p + 2.0 * q * p * x;
+                if (l2 < 0.0) l2 = 0.0; /* the propagator's own clamp */
+                double gl = frgo_propagator(regulator, Z, nZ, x_min, x_max, l2, mass, k);
+                double c = pref * qw[a] * xw[b] * sqrt(1.0 - x * x) * q2 * q *
+                           frgo_regulator_dot(regulator, q2, k);
+                /* term = c G(q^2)^2 G(l2); dG(v)/dZ_i = -G(v)^2 v dZ(v)/dZ_i */
+                add_dressing_weights(acc, nZ, iq, fq, -2.0 * c * gq * gq * gq * q2 * gl);
+                int il;
+                double fl;
+                dressing_cell(nZ, x_min, x_max, l2, &il, &fl);
+                add_dressing_weights(acc, nZ, il, fl, -c * gq * gq * gl * gl * l2);
+            }
+        }
+        for (int i = 0; i < nZ; ++i) out[(size_t)e * nZ + i] = nsum_get(&acc[i]);
+    }
+    return 0;
+}
+
 /* ---------------------------------------------------------------------------------------- */
 /* Finite temperature: Matsubara frequency rule and the d = 3 + 1 integrals.                 */
 /* ---------------------------------------------------------------------------------------- */

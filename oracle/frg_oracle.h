@@ -74,6 +74,18 @@ int frgo_integrate_dm2(int family, int d, int n_q, int n_x, int n_phi, double q_
                        double *out);
 
 /*
+ * dI_e/dZ_i, the derivatives of the two-point integral (family 2) in the entries of its dressing
+ * table: out[e * nZ + i], n_ext x nZ row-major.  The integral depends on the entries through the
+ * linear interpolation Z(l2) = (1 - f) Z_j + f Z_{j+1} (cell j, fraction f as in frgo_dressing;
+ * nZ == 1: Z(l2) = Z_0); each propagator contributes dG(v)/dZ_i = -G(v)^2 v dZ(v)/dZ_i through
+ * the product rule, and entries no node reaches get exactly 0.  Z is required.  Arguments as
+ * frgo_integrate (d = 4; ext = p[n_ext]).
+ */
+int frgo_integrate_dz(int d, int n_q, int n_x, double q_max, double k, int regulator,
+                      const double *ext, const double *m2, double m2_scalar, const double *Z,
+                      int nZ, double x_min, double x_max, int n_ext, double *out);
+
+/*
  * General d = 4 one-loop integral with explicit external 4-vectors, on a full hyperspherical
  * product rule (GL in the polar angles theta1, theta2 in [0, pi] with the sin^2/sin Jacobian
  * and GL in the azimuth theta3 in [0, 2pi]):

@@ -1,0 +1,99 @@
+"""Pins of the oracle's derivatives of the two-point integral in its dressing-table entries,
+dI_e/dZ_i (the forward-mode derivatives an implicit stepper of a dressing flow needs; paper
+Sec. 5.2 and App. F), against routes that do not use the derivative code:
+
+* central finite differences of the (separately pinned) integral in each table entry, for every
+  regulator, with momenta that put nodes in the clamped regions below and above the table;
+* the row sums: shifting every entry by c shifts Z(l2) by c, so sum_i dI/dZ_i is the derivative
+  in c, taken by finite differences;
+* a one-entry table (Z(l2) = Z_0 everywhere);
+* the entries no node reaches are exactly 0, and the others are not: the reached cells come
+  from the node momenta directly (brute force over the GL nodes).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+N_Q, N_X, Q_MAX = 9, 7, 10.0
+XMIN, XMAX = 0.05, 20.0
+
+
+def _I(Z, p, m2, reg, n_q=N_Q, n_x=N_X):
+    return oracle.integrate(oracle.TWO_POINT, n_q, Q_MAX, n_x=n_x, ext=p, m2=m2, Z=Z,
+                            x_min=XMIN, x_max=XMAX, regulator=reg)
+
+
+def _J(Z, p, m2, reg, n_q=N_Q, n_x=N_X):
+    return oracle.integrate_dz(n_q, Q_MAX, n_x=n_x, ext=p, m2=m2, Z=Z, x_min=XMIN, x_max=XMAX,
+                               regulator=reg)
+
+
+def _case(seed, nZ=9, n=6):
+    rng = np.random.default_rng(seed)
+    Z = rng.uniform(0.8, 1.4, nZ)
+    p = np.concatenate([[1e-3, 40.0], 10 ** rng.uniform(-1.5, 1.2, n - 2)])
+    m2 = rng.uniform(0.2, 1.5, n)
+    return Z, p, m2
+
+
+@pytest.mark.parametrize("reg", [oracle.REG_EXP, oracle.reg_polyexp(8), oracle.REG_LITIM])
+def test_dz_matches_central_differences(reg):
+    Z, p, m2 = _case(1)
+    J = _J(Z, p, m2, reg)
+    h = 1e-5
+    for i in range(Z.size):
+        Zp, Zm = Z.copy(), Z.copy()
+        Zp[i] += h
+        Zm[i] -= h
+        fd = (_I(Zp, p, m2, reg) - _I(Zm, p, m2, reg)) / (2 * h)
+        # O(h^2) truncation and eps * I / h rounding, relative to the row's scale
+        scale = np.max(np.abs(J), axis=1)
+        assert np.all(np.abs(fd - J[:, i]) <= 1e-7 * scale + 1e-18), i
+
+
+def test_dz_row_sums_are_the_shift_derivative():
+    Z, p, m2 = _case(2, nZ=13)
+    J = _J(Z, p, m2, oracle.REG_EXP)
+    h = 1e-5
+    fd = (_I(Z + h, p, m2, oracle.REG_EXP) - _I(Z - h, p, m2, oracle.REG_EXP)) / (2 * h)
+    assert np.allclose(J.sum(axis=1), fd, rtol=1e-8, atol=0.0)
+
+
+def test_dz_one_entry_table():
+    _, p, m2 = _case(3)
+    Z = np.array([1.2])
+    J = _J(Z, p, m2, oracle.REG_EXP)
+    assert J.shape == (p.size, 1)
+    h = 1e-5
+    fd = (_I(Z + h, p, m2, oracle.REG_EXP) - _I(Z - h, p, m2, oracle.REG_EXP)) / (2 * h)
+    assert np.allclose(J[:, 0], fd, rtol=1e-8, atol=0.0)
+    # every propagator depends on Z_0 with dG/dZ = -G^2 l2 < 0
+    assert np.all(J < 0)
+
+
+def test_dz_zero_exactly_where_no_node_reaches():
+    nZ = 40
+    Z = 1.0 + 0.01 * np.arange(nZ)
+    p = np.array([0.3, 2.5])
+    m2 = np.array([0.5, 0.9])
+    xmin, xmax = 1e-3, 1e4  # the table reaches far beyond every |l|
+    J = oracle.integrate_dz(N_Q, Q_MAX, n_x=N_X, ext=p, m2=m2, Z=Z, x_min=xmin, x_max=xmax)
+    q, _ = oracle.gauss_legendre(N_Q, 0.0, Q_MAX)
+    x, _ = oracle.gauss_legendre(N_X, -1.0, 1.0)
+    delta = (math.log(xmax) - math.log(xmin)) / (nZ - 1)
+    for e in range(p.size):
+        reached = set()
+        for qa in q:
+            l2s = [qa * qa] + [qa * qa + p[e] ** 2 + 2 * qa * p[e] * xb for xb in x]
+            for l2 in l2s:
+                s = min(max((0.5 * math.log(l2) - math.log(xmin)) / delta, 0.0), nZ - 1)
+                i = min(int(math.floor(s)), nZ - 2)
+                reached.update({i, i + 1} if s > i else {i})
+        for i in range(nZ):
+            if i in reached:
+                assert J[e, i] < 0, (e, i)
+            else:
+                assert J[e, i] == 0.0, (e, i)
