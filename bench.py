@@ -551,6 +551,24 @@ def secondary(torch, frg, wl, ctx, serving_seconds=4.0):
         ex[name] = {"gnodes_per_s": round(nr / (msr * 1e-3) / 1e9, 2),
                     "avg_kernel_ms": round(msr, 4)}
         del keep_r
+    # the derivatives in the dressing-table entries (dout_dz) for one right-hand side of the
+    # two-point workload: 256 momenta x 256 entries, after the integral on the same stream
+    log("bench: dressing derivatives")
+    pz, m2z, Zz = wl.two_point()
+    tpz, tZz = _dev(torch, pz), _dev(torch, Zz)
+    oz = torch.empty(pz.size, dtype=torch.float64, device="cuda")
+    jz = torch.empty(pz.size * Zz.size, dtype=torch.float64, device="cuda")
+    dzd = frg.make_desc(2, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX)
+    res_z = {}
+    for name, dz in (("value_only", None), ("value_and_dI_dZ", jz)):
+        fz = lambda: ctx.integrate(dzd, oz, ext=tpz, m2_scalar=m2z, Z=tZz, x_min=wl.Z_XMIN,
+                                   x_max=wl.Z_XMAX, dz=dz)
+        warm_clocks(torch, fz, EXTRA_WARM_S)
+        wall, ev = time_kernel(torch, fz, 200, 5)
+        res_z[name + "_us"] = round(float(np.mean(ev)) * 1e3, 2)
+    res_z["jacobian_entries"] = int(pz.size * Zz.size)
+    res_z["nodes"] = int(pz.size * wl.TWO_NQ * wl.TWO_NX)
+    ex["two_point_dI_dZ_one_rhs"] = res_z
     # precision form on the near-pole workload vs float64 on identical inputs
     log("bench: float32 precision form")
 

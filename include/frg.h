@@ -187,6 +187,20 @@ typedef struct {
                               Jacobian entries of implicit steppers, Sec. 5.2 and the "AD" option
                               of App. F); float64 only (FRG_E_UNSUPPORTED otherwise); not taken
                               by sessions (FRG_E_UNSUPPORTED) */
+    double *dout_dz;       /* device [n_ext * Z.n] or NULL: dI_e/dZ_i, row-major (entry i of point
+                              e at e * Z.n + i), the derivatives of each result in the entries of
+                              its dressing table (the forward-mode derivatives of the "AD" option
+                              of App. F for a flow of the dressing; Sec. 5.2 jacobian_variables).
+                              Z enters through the linear interpolation of every propagator's
+                              dressing, so dG(v)/dZ_i = -G(v)^2 v w_i(v) with w_i(v) the
+                              interpolation weight of entry i at v; entries no node reaches are
+                              exactly 0.  Family 2 in float64 with a dressing table only
+                              (FRG_E_UNSUPPORTED for other families and the float32 form,
+                              FRG_E_INVAL without a table), frg_integrate_batch only
+                              (FRG_E_UNSUPPORTED from frg_integrate_multi and sessions); the
+                              caller owns the buffer.  Computed by a second kernel after the
+                              integral on the same stream; each row's sums have one fixed order
+                              (no atomics), so the values are reproducible bit for bit */
 } frg_batch;
 
 /* ---- context ------------------------------------------------------------------------------- */

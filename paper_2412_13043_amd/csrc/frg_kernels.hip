@@ -1383,6 +1383,153 @@ hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg, int 
     return hipGetLastError();
 }
 
+// --------------------------------------------------------------------------------------------
+// Derivatives of the two-point integral in the dressing-table entries
+// --------------------------------------------------------------------------------------------
+// The integral depends on entry Z_j only through the dressing's linear interpolation at each
+// propagator argument v (q^2 of the radial leg, l2 of the inner leg): dG(v)/dZ_j =
+// -G(v)^2 v w_j(v), with w_j(v) the interpolation weight of entry j at v.  By the product rule,
+//   dI_e/dZ_j = pref sum_a W_a [ -2 G(q_a^2)^3 q_a^2 w_j(q_a^2) sum_b xw_b G(l2_ab)
+//                               - G(q_a^2)^2 sum_b xw_b G(l2_ab)^2 l2_ab w_j(l2_ab) ].
+// One workgroup per external point, in rounds of radial nodes.  A round's node terms, cells and
+// fractions go to LDS; then lane l owns the entries j = l + 64 m and adds, radial node by radial
+// node, the terms of the nodes whose cell touches j.  l2_ab grows with x_b (ascending nodes, p
+// taken as |p|), so for one radial node those nodes form one contiguous run of b, found by
+// binary search.  Every entry's sum has one fixed order and no atomics.
+constexpr int kDzEntries = 1024;  // node terms of one round held in LDS (n_x <= 1024)
+
+// Weight of entry j in the interpolation at padded cell index iz (0 and nZ are the clamped ends,
+// where one entry takes the whole value), fraction f; iz must be j or j + 1.
+__device__ __forceinline__ double dz_weight(int iz, double f, int j, int nZ) {
+    if (iz == 0 || iz == nZ) return 1.0;
+    return iz == j ? f : 1.0 - f;
+}
+
+size_t dz_lds_bytes(int nZ) {
+    return (size_t)(kLogTable + nZ + 1) * sizeof(double2) + (size_t)nZ * sizeof(double) +
+           3 * kDzEntries * sizeof(double) + 7 * kWave * sizeof(double) +
+           kDzEntries * sizeof(int) + kWave * sizeof(int);
+}
+
+template <int REG>
+__global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ jac) {
+    extern __shared__ double2 lds_dyn[];
+    __shared__ float zslope;
+    Smem sm;
+    const int nZ = r.nZ, nx = r.n_x, lane = (int)threadIdx.x, e = (int)blockIdx.x;
+    bind_smem(sm, lds_dyn, nZ, &zslope);
+    // after the padded table: the row's accumulators, the round's node arrays, the round's
+    // radial arrays
+    double *acc = (double *)(lds_dyn + kLogTable + nZ + 1);
+    double *nv = acc + nZ;          // node term  -W G(q^2)^2 xw G^(l2)^2 l2 (units of k^2)
+    double *nf = nv + kDzEntries;   // node cell fraction
+    double *xg = nf + kDzEntries;   // xw G^(l2), for the radial leg's inner sum
+    double *rw = xg + kDzEntries;   // W G(q^2)^2
+    double *rg = rw + kWave;        // G(q^2)
+    double *rc0 = rg + kWave;       // (q^2 + p^2)/k^2
+    double *rc1 = rc0 + kWave;      // 2 q p/k^2
+    double *rq2 = rc1 + kWave;      // q^2
+    double *rv = rq2 + kWave;       // radial-leg term  -2 W G(q^2)^3 q^2 sum_b xw G^(l2)/k^2
+    double *rf = rv + kWave;        // radial-leg cell fraction
+    int *niz = (int *)(rf + kWave); // node padded cell index
+    int *riz = niz + kDzEntries;    // radial-leg padded cell index
+    stage_log(sm, r.logt);
+    stage_dressing(r, sm);
+    for (int j = lane; j < nZ; j += kWave) acc[j] = 0.0;
+    __syncthreads();
+    const double p = fabs(r.ext[e]);
+    const double m2 = lane_m2(r, e);
+    const double inv_k2 = 1.0 / r.k2;
+    const double m2h = m2 * inv_k2;
+    const double zb1 = r.zbk + 1.0;
+    const int R = max(1, min(kWave, kDzEntries / nx));
+    for (int r0 = 0; r0 < r.n_q; r0 += R) {
+        const int nr = min(R, r.n_q - r0);
+        if (lane < nr) {
+            const RadialTerm t = radial64(r, sm, r0 + lane, p, m2);
+            const double q = r.k * kc(r.rad.q)[r0 + lane];
+            const double q2 = q * q;
+            int iz;
+            double f;
+            zcell64(fma(fm::log_tab(fmax(q2, FRG_L2_TINY), sm.logt), r.za, r.zb + 1.0), nZ, iz,
+                    f);
+            rw[lane] = t.wg;
+            rg[lane] = t.g;
+            rc0[lane] = t.c0 * inv_k2;
+            rc1[lane] = t.c1 * inv_k2;
+            rq2[lane] = q2;
+            rf[lane] = f;
+            riz[lane] = iz;
+        }
+        __syncthreads();
+        const int nn = nr * nx;
+        for (int t = lane; t < nn; t += kWave) {
+            const int al = t / nx, b = t - al * nx;
+            double l2[1] = {fma(rc1[al], kc(r.ang.x)[b], rc0[al])}, G[1];
+            propagators64<1, false, REG>(l2, G, sm, nZ, r.za, zb1, m2h, 1.0, r.far_y, r.reg_n);
+            int iz;
+            double f;
+            zcell64(fma(fm::log_tab(l2[0], sm.logt), r.za, zb1), nZ, iz, f);
+            const double xw = kc(r.ang.xw)[b];
+            xg[t] = xw * G[0];
+            nv[t] = -rw[al] * (xw * (G[0] * G[0])) * (l2[0] * inv_k2);
+            nf[t] = f;
+            niz[t] = iz;
+        }
+        __syncthreads();
+        if (lane < nr) {
+            // the radial leg's inner sum in b order; the cells made non-decreasing along b (a
+            // node within rounding of a cell boundary that reads one cell lower than its
+            // predecessor is moved to the boundary: same weights up to that rounding)
+            double inner = 0.0;
+            int prev = 0;
+            for (int b = 0; b < nx; ++b) {
+                const int t = lane * nx + b;
+                inner += xg[t];
+                if (niz[t] < prev) {
+                    niz[t] = prev;
+                    nf[t] = 0.0;
+                } else {
+                    prev = niz[t];
+                }
+            }
+            rv[lane] = -2.0 * rw[lane] * rg[lane] * rq2[lane] * (inner * inv_k2);
+        }
+        __syncthreads();
+        for (int j = lane; j < nZ; j += kWave) {
+            double s = acc[j];
+            for (int al = 0; al < nr; ++al) {
+                const int *row = niz + al * nx;
+                int lo = 0, hi = nx;  // first b with row[b] >= j
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (row[mid] < j)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                for (int b = lo; b < nx && row[b] <= j + 1; ++b)
+                    s = fma(dz_weight(row[b], nf[al * nx + b], j, nZ), nv[al * nx + b], s);
+                const int iq = riz[al];
+                if (iq == j || iq == j + 1) s = fma(dz_weight(iq, rf[al], j, nZ), rv[al], s);
+            }
+            acc[j] = s;
+        }
+        __syncthreads();
+    }
+    for (int j = lane; j < nZ; j += kWave) jac[(long long)e * nZ + j] = r.pref * acc[j];
+}
+
+hipError_t launch_dz(const ReqDev &r, double *jac, hipStream_t s) {
+    if (r.n_ext <= 0) return hipSuccess;
+    if (r.family != 2 || r.precision != 0 || r.nZ < 2 || r.n_x < 1 || r.n_x > kDzEntries)
+        return hipErrorInvalidValue;
+    void (*fn)(ReqDev, double *) =
+        r.reg == 1 ? dz_kernel<1> : (r.reg == 2 ? dz_kernel<2> : dz_kernel<0>);
+    hipLaunchKernelGGL(fn, dim3(r.n_ext), dim3(kWave), dz_lds_bytes(r.nZ), s, r, jac);
+    return hipGetLastError();
+}
+
 // Logarithm table for fm::log_tab: (2 c_j, ln(1/c_j) - ln 2), c_j = 1/(1 + (j + 1/2)/256) rounded
 // to double (2 c_j is exact), ln(1/c_j) - ln 2 to a few ulp of a number below 1 in magnitude.
 __global__ void __launch_bounds__(256) log_table_kernel(double2 *out) {

@@ -182,6 +182,17 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
         set_error("dout_dm2 (the mass derivative) is implemented in float64 only");
         return FRG_E_UNSUPPORTED;
     }
+    if (b->dout_dz) {
+        if (d->family != FRG_FAMILY_TWO_POINT || d->precision != FRG_FP64) {
+            set_error("dout_dz (derivatives in the dressing-table entries) is implemented for "
+                      "the two-point family in float64 only");
+            return FRG_E_UNSUPPORTED;
+        }
+        if (!b->Z.values) {
+            set_error("dout_dz needs a dressing table (Z.values is NULL)");
+            return FRG_E_INVAL;
+        }
+    }
     if (b->n_ext == 0) return FRG_OK;
     if (!b->out) {
         set_error("out is NULL");
@@ -211,7 +222,7 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
     }
     if (device_ptrs) {
         // every pointer the kernels dereference must be device-accessible memory
-        const void *ptrs[5] = {b->ext, b->m2, b->out, b->err_out, b->dout_dm2};
+        const void *ptrs[6] = {b->ext, b->m2, b->out, b->err_out, b->dout_dm2, b->dout_dz};
         for (const void *p : ptrs) {
             if (!p) continue;
             hipPointerAttribute_t attr;
@@ -824,7 +835,9 @@ frg_status frg_integrate_batch(frg_context *ctx, const frg_integral_desc *desc,
     Scratch *sc;
     if ((st = get_scratch(ctx, stream, contrib_doubles(r), counter_count(r), 1, 1, &sc)) != FRG_OK)
         return st;
-    return run_batch(ctx, r, stream, sc);
+    if ((st = run_batch(ctx, r, stream, sc)) != FRG_OK) return st;
+    if (batch->dout_dz) FRG_HIP_CHECK(launch_dz(r, batch->dout_dz, stream));
+    return FRG_OK;
 }
 
 frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const frg_batch *batch,
@@ -945,6 +958,11 @@ frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc 
             std::string m = g_last_error;
             set_error("batch %d: %s", i, m.c_str());
             return st;
+        }
+        if (batches[i].dout_dz) {
+            set_error("batch %d: frg_integrate_multi does not compute dout_dz "
+                      "(frg_integrate_batch does)", i);
+            return FRG_E_UNSUPPORTED;
         }
         nodes[i] = nodes_per_point(descs[i]) * batches[i].n_ext;
         total_nodes += nodes[i];

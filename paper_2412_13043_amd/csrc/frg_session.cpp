@@ -561,6 +561,10 @@ frg_status frg_session_submit(frg_session *s, const frg_integral_desc *desc,
         set_error("sessions do not return the mass derivative (dout_dm2 must be NULL)");
         return FRG_E_UNSUPPORTED;
     }
+    if (batch_host->dout_dz) {
+        set_error("sessions do not return dressing derivatives (dout_dz must be NULL)");
+        return FRG_E_UNSUPPORTED;
+    }
     auto r = std::make_unique<SessReq>();
     r->desc = *desc;
     r->host = *batch_host;

@@ -67,7 +67,7 @@ class frg_log_table(ctypes.Structure):
 class frg_batch(ctypes.Structure):
     _fields_ = [("n_ext", c_int), ("ext", c_void_p), ("m2", c_void_p), ("m2_scalar", c_double),
                 ("Z", frg_log_table), ("out", c_void_p), ("err_out", c_void_p),
-                ("dout_dm2", c_void_p)]
+                ("dout_dm2", c_void_p), ("dout_dz", c_void_p)]
 
 
 class frg_flow_state(ctypes.Structure):
@@ -296,11 +296,20 @@ def make_desc(family: int, n_q: int, q_max: float, *, n_x: int = 0, n_phi: int =
 
 
 def make_batch(n_ext: int, out, *, ext=None, m2=None, m2_scalar: float = 0.0, Z=None,
-               x_min: float = 1e-3, x_max: float = 1e3, err_out=None, dout=None) -> frg_batch:
-    """dout: optional device tensor receiving dI/dm2 per point (float64 descriptors)."""
+               x_min: float = 1e-3, x_max: float = 1e3, err_out=None, dout=None,
+               dz=None) -> frg_batch:
+    """dout: optional device tensor receiving dI/dm2 per point (float64 descriptors).
+    dz: optional contiguous float64 device tensor of n_ext * len(Z) values receiving dI_e/dZ_i
+    row-major (two-point family, frg_integrate_batch only)."""
+    if dz is not None:
+        nz = 0 if Z is None else int(Z.numel())
+        if (dz.numel() != n_ext * nz or not dz.is_contiguous() or not dz.is_cuda or
+                str(dz.dtype) != "torch.float64"):
+            raise ValueError(f"dz must be a contiguous float64 device tensor of n_ext * len(Z) = "
+                             f"{n_ext * nz} values")
     zt = frg_log_table(_dptr(Z), 0 if Z is None else int(Z.numel()), x_min, x_max)
     return frg_batch(n_ext, _dptr(ext), _dptr(m2), m2_scalar, zt, _dptr(out), _dptr(err_out),
-                     _dptr(dout))
+                     _dptr(dout), _dptr(dz))
 
 
 class Context:
@@ -328,9 +337,9 @@ class Context:
             pass
 
     def integrate(self, desc, out, *, ext=None, m2=None, m2_scalar=0.0, Z=None, x_min=1e-3,
-                  x_max=1e3, err_out=None, dout=None, stream=None):
+                  x_max=1e3, err_out=None, dout=None, dz=None, stream=None):
         b = make_batch(int(out.numel()), out, ext=ext, m2=m2, m2_scalar=m2_scalar, Z=Z,
-                       x_min=x_min, x_max=x_max, err_out=err_out, dout=dout)
+                       x_min=x_min, x_max=x_max, err_out=err_out, dout=dout, dz=dz)
         frg_integrate_batch(self.handle, desc, b, _stream(stream))
         return out
 

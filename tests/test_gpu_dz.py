@@ -1,0 +1,145 @@
+"""GPU derivatives of the two-point integral in its dressing-table entries (dout_dz,
+dI_e/dZ_i) against the FP64 oracle, entry by entry.
+
+Every term of an entry's sum has the same sign (W, the weights and G are positive at these
+masses), so each entry is compared at 1e-12 relative, plus 1e-12 of its row's largest entry: the
+interpolation weights f and 1 - f carry the absolute rounding of the dressing coordinate s (a
+few ulp of s, 1e-14 to 1e-13 for tables of hundreds of entries, computed through different
+logarithms on the two sides), which an entry reached only through a small weight feels relative
+to itself but not relative to its row.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_13043_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2412_13043_amd import frg
+
+    ctx = frg.Context(0)
+    yield frg, ctx, torch
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _d(torch, a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), dtype=torch.float64,
+                        device="cuda")
+
+
+def _run(env, n_q, q_max, n_x, p, Z, *, m2=None, m2_scalar=0.0, k=1.0, reg=0, x_min=wl.Z_XMIN,
+         x_max=wl.Z_XMAX):
+    frg, ctx, torch = env
+    n = len(p)
+    out = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    jac = torch.full((n * len(Z),), float("nan"), dtype=torch.float64, device="cuda")
+    desc = frg.make_desc(frg.FRG_FAMILY_TWO_POINT, n_q, q_max, n_x=n_x, k=k, regulator=reg)
+    ctx.integrate(desc, out, ext=_d(torch, p), m2=None if m2 is None else _d(torch, m2),
+                  m2_scalar=m2_scalar, Z=_d(torch, Z), x_min=x_min, x_max=x_max, dz=jac)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), jac.cpu().numpy().reshape(n, len(Z))
+
+
+def _check(got, ref):
+    assert got.shape == ref.shape
+    assert np.all(np.isfinite(got))
+    floor = TOL * np.max(np.abs(ref), axis=1, keepdims=True)
+    assert np.all(np.abs(got - ref) <= TOL * np.abs(ref) + floor)
+
+
+def _okind(reg):
+    return {0: oracle.REG_EXP, 1: oracle.reg_polyexp(8), 2: oracle.REG_LITIM}[reg]
+
+
+@pytest.mark.parametrize("reg", [0, 1, 2])
+@pytest.mark.parametrize("n_ext,n_q,n_x,nZ,k", [(37, 13, 6, 9, 1.0), (40, 64, 40, 57, 1.0),
+                                                 (9, 20, 7, 300, 1.7)])
+def test_dz_matches_oracle(env, reg, n_ext, n_q, n_x, nZ, k):
+    # n_x = 40: 25 radial nodes per round, three rounds; momenta below and above the table
+    rng = np.random.default_rng(n_ext + 3 * reg)
+    p = k * np.concatenate([[0.0, 2e-4, 500.0], 10 ** rng.uniform(-3, 2, n_ext - 3)])
+    m2 = k * k * rng.uniform(0.1, 2.0, n_ext)
+    Z = wl.dressing_table(5 + nZ, nZ)
+    got_v, got = _run(env, n_q, 10.0, n_x, p, Z, m2=m2, k=k, reg=reg)
+    ref = oracle.integrate_dz(n_q, 10.0, n_x=n_x, ext=p, m2=m2, Z=Z, k=k,
+                              regulator=_okind(reg), x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)
+    _check(got, ref)
+    ref_v = oracle.integrate(oracle.TWO_POINT, n_q, 10.0, n_x=n_x, k=k, ext=p, m2=m2, Z=Z,
+                             regulator=_okind(reg))
+    assert np.max(np.abs(got_v - ref_v) / np.abs(ref_v)) <= TOL
+
+
+def test_dz_two_point_workload_full_size(env):
+    # one right-hand side of the two-point workload: 256 momenta x 64 x 32, 256-entry table
+    p, m2, Z = wl.two_point()
+    got_v, got = _run(env, wl.TWO_NQ, wl.TWO_QMAX, wl.TWO_NX, p, Z, m2_scalar=m2)
+    ref = oracle.integrate_dz(wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX, ext=p, m2_scalar=m2, Z=Z,
+                              x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)
+    _check(got, ref)
+
+
+def test_dz_largest_table_and_rule(env):
+    # the largest dressing table (4096 entries, 135 KB of LDS) and the largest cos1 rule (1024
+    # nodes: one radial node per round)
+    Z = 0.8 + 0.7 * (0.5 + 0.5 * np.sin(np.linspace(0, 40, 4096)))
+    p = np.array([0.01, 0.7, 3.0])
+    for n_q, n_x, nz in ((16, 64, 4096), (4, 1024, 64)):
+        got_v, got = _run(env, n_q, 10.0, n_x, p, Z[:nz], m2_scalar=0.3)
+        ref = oracle.integrate_dz(n_q, 10.0, n_x=n_x, ext=p, m2_scalar=0.3, Z=Z[:nz],
+                                  x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)
+        _check(got, ref)
+
+
+def test_dz_reproducible_and_value_unchanged(env):
+    frg, ctx, torch = env
+    p, m2, Z = wl.two_point()
+    v1, j1 = _run(env, 24, 10.0, 12, p, Z, m2_scalar=m2)
+    v2, j2 = _run(env, 24, 10.0, 12, p, Z, m2_scalar=m2)
+    assert np.array_equal(j1, j2)
+    out = torch.empty(p.size, dtype=torch.float64, device="cuda")
+    desc = frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 24, 10.0, n_x=12)
+    ctx.integrate(desc, out, ext=_d(torch, p), m2_scalar=m2, Z=_d(torch, Z), x_min=wl.Z_XMIN,
+                  x_max=wl.Z_XMAX)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), v1)
+
+
+def test_dz_unsupported_and_invalid(env):
+    frg, ctx, torch = env
+    n = 4
+    out = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ext = torch.ones(2 * n, dtype=torch.float64, device="cuda")
+    Z = _d(torch, wl.dressing_table(1, 16))
+    jac = torch.zeros(n * 16, dtype=torch.float64, device="cuda")
+    cases = [(frg.make_desc(frg.FRG_FAMILY_THREE_POINT, 8, 6.0, n_x=4, n_phi=4), frg.FRG_E_UNSUPPORTED),
+             (frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 8, 6.0, n_x=4, precision=1),
+              frg.FRG_E_UNSUPPORTED),
+             (frg.make_desc(frg.FRG_FAMILY_TWO_POINT_T, 8, 6.0, n_x=4, T=0.2, freq_max=3.0),
+              frg.FRG_E_UNSUPPORTED)]
+    for desc, status in cases:
+        with pytest.raises(frg.FrgError) as ei:
+            ctx.integrate(desc, out, ext=ext, m2_scalar=0.5, Z=Z, dz=jac)
+        assert ei.value.status == status
+    d2 = frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 8, 6.0, n_x=4)
+    # no table: a batch built by hand (the binding checks the size against the table)
+    b = frg.make_batch(n, out, ext=ext, m2_scalar=0.5)
+    b.dout_dz = jac.data_ptr()
+    with pytest.raises(frg.FrgError) as ei:
+        frg.frg_integrate_batch(ctx.handle, d2, b, 0)
+    assert ei.value.status == frg.FRG_E_INVAL
+    # the fused call does not compute it
+    b = frg.make_batch(n, out, ext=ext, m2_scalar=0.5, Z=Z, dz=jac)
+    with pytest.raises(frg.FrgError) as ei:
+        ctx.integrate_multi([d2], [b])
+    assert ei.value.status == frg.FRG_E_UNSUPPORTED
+    with pytest.raises(ValueError):
+        frg.make_batch(n, out, ext=ext, m2_scalar=0.5, Z=Z, dz=jac[:-1])
+    torch.cuda.synchronize()
