@@ -1391,12 +1391,16 @@ hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg, int 
 // -G(v)^2 v w_j(v), with w_j(v) the interpolation weight of entry j at v.  By the product rule,
 //   dI_e/dZ_j = pref sum_a W_a [ -2 G(q_a^2)^3 q_a^2 w_j(q_a^2) sum_b xw_b G(l2_ab)
 //                               - G(q_a^2)^2 sum_b xw_b G(l2_ab)^2 l2_ab w_j(l2_ab) ].
-// One workgroup per external point, in rounds of radial nodes.  A round's node terms, cells and
-// fractions go to LDS; then lane l owns the entries j = l + 64 m and adds, radial node by radial
-// node, the terms of the nodes whose cell touches j.  l2_ab grows with x_b (ascending nodes, p
-// taken as |p|), so for one radial node those nodes form one contiguous run of b, found by
-// binary search.  Every entry's sum has one fixed order and no atomics.
-constexpr int kDzEntries = 1024;  // node terms of one round held in LDS (n_x <= 1024)
+// Workgroup (e, slice) computes entries j = 64 slice + lane of point e, one per lane, in rounds
+// of radial nodes.  A round's node terms and cells go to LDS.  l2_ab grows with x_b (ascending
+// nodes, p taken as |p|), so along a radial node's row the cells are non-decreasing: one lane
+// per radial node adds the row, in b order, into one pair of sums per cell (the parts for the
+// cell's lower and upper entry).  The owner of entry j then takes, radial node by radial node,
+// the upper part of the run in cell j and the lower part of the run in cell j + 1 (found by
+// binary search) and the radial leg's term.  Every entry's sum has one fixed order and no
+// atomics.
+// node terms of one round held in LDS: at least 512 and at least one row of n_x
+__host__ __device__ __forceinline__ int dz_entries(int n_x) { return n_x > 512 ? n_x : 512; }
 
 // Weight of entry j in the interpolation at padded cell index iz (0 and nZ are the clamped ends,
 // where one entry takes the whole value), fraction f; iz must be j or j + 1.
@@ -1405,10 +1409,10 @@ __device__ __forceinline__ double dz_weight(int iz, double f, int j, int nZ) {
     return iz == j ? f : 1.0 - f;
 }
 
-size_t dz_lds_bytes(int nZ) {
-    return (size_t)(kLogTable + nZ + 1) * sizeof(double2) + (size_t)nZ * sizeof(double) +
-           3 * kDzEntries * sizeof(double) + 7 * kWave * sizeof(double) +
-           kDzEntries * sizeof(int) + kWave * sizeof(int);
+size_t dz_lds_bytes(int nZ, int n_x) {
+    const size_t E = (size_t)dz_entries(n_x);
+    return (size_t)(kLogTable + nZ + 1) * sizeof(double2) + 3 * E * sizeof(double) +
+           7 * kWave * sizeof(double) + E * sizeof(int) + 2 * kWave * sizeof(int);
 }
 
 template <int REG>
@@ -1417,32 +1421,34 @@ __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ j
     __shared__ float zslope;
     Smem sm;
     const int nZ = r.nZ, nx = r.n_x, lane = (int)threadIdx.x, e = (int)blockIdx.x;
+    const int j = (int)blockIdx.y * kWave + lane;  // the entry this lane owns
+    const int E = dz_entries(nx);
     bind_smem(sm, lds_dyn, nZ, &zslope);
-    // after the padded table: the row's accumulators, the round's node arrays, the round's
-    // radial arrays
-    double *acc = (double *)(lds_dyn + kLogTable + nZ + 1);
-    double *nv = acc + nZ;          // node term  -W G(q^2)^2 xw G^(l2)^2 l2 (units of k^2)
-    double *nf = nv + kDzEntries;   // node cell fraction
-    double *xg = nf + kDzEntries;   // xw G^(l2), for the radial leg's inner sum
-    double *rw = xg + kDzEntries;   // W G(q^2)^2
+    // after the padded table: the round's node arrays (compacted in place into per-cell runs),
+    // then its radial arrays
+    double *nv = (double *)(lds_dyn + kLogTable + nZ + 1);  // node term, then run's lower part
+    double *nf = nv + E;            // node cell fraction, then run's upper part
+    double *xg = nf + E;            // xw G^(l2), for the radial leg's inner sum
+    double *rw = xg + E;            // W G(q^2)^2
     double *rg = rw + kWave;        // G(q^2)
     double *rc0 = rg + kWave;       // (q^2 + p^2)/k^2
     double *rc1 = rc0 + kWave;      // 2 q p/k^2
     double *rq2 = rc1 + kWave;      // q^2
     double *rv = rq2 + kWave;       // radial-leg term  -2 W G(q^2)^3 q^2 sum_b xw G^(l2)/k^2
     double *rf = rv + kWave;        // radial-leg cell fraction
-    int *niz = (int *)(rf + kWave); // node padded cell index
-    int *riz = niz + kDzEntries;    // radial-leg padded cell index
+    int *niz = (int *)(rf + kWave); // node padded cell index, then run's cell
+    int *riz = niz + E;             // radial-leg padded cell index
+    int *nrun = riz + kWave;        // runs per row
     stage_log(sm, r.logt);
     stage_dressing(r, sm);
-    for (int j = lane; j < nZ; j += kWave) acc[j] = 0.0;
     __syncthreads();
     const double p = fabs(r.ext[e]);
     const double m2 = lane_m2(r, e);
     const double inv_k2 = 1.0 / r.k2;
     const double m2h = m2 * inv_k2;
     const double zb1 = r.zbk + 1.0;
-    const int R = max(1, min(kWave, kDzEntries / nx));
+    const int R = max(1, min(kWave, E / nx));
+    double s = 0.0;
     for (int r0 = 0; r0 < r.n_q; r0 += R) {
         const int nr = min(R, r.n_q - r0);
         if (lane < nr) {
@@ -1478,55 +1484,84 @@ __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ j
         }
         __syncthreads();
         if (lane < nr) {
-            // the radial leg's inner sum in b order; the cells made non-decreasing along b (a
-            // node within rounding of a cell boundary that reads one cell lower than its
-            // predecessor is moved to the boundary: same weights up to that rounding)
-            double inner = 0.0;
-            int prev = 0;
+            // the radial leg's inner sum, and the row compacted into runs of equal cell (run k
+            // is written at position k <= b, after position b has been read).  A node within
+            // rounding of a cell boundary that reads one cell below its predecessor is taken at
+            // the boundary (same weights up to that rounding).
+            const int base = lane * nx;
+            double inner = 0.0, lo = 0.0, hi = 0.0;
+            int k = 0, cur = -1, prev = 0;
             for (int b = 0; b < nx; ++b) {
-                const int t = lane * nx + b;
+                const int t = base + b;
                 inner += xg[t];
-                if (niz[t] < prev) {
-                    niz[t] = prev;
-                    nf[t] = 0.0;
+                int iz = niz[t];
+                double f = nf[t];
+                const double v = nv[t];
+                if (iz < prev) {
+                    iz = prev;
+                    f = 0.0;
                 } else {
-                    prev = niz[t];
+                    prev = iz;
+                }
+                if (iz != cur) {
+                    if (cur >= 0) {
+                        nv[base + k] = lo;
+                        nf[base + k] = hi;
+                        niz[base + k] = cur;
+                        ++k;
+                    }
+                    cur = iz;
+                    lo = 0.0;
+                    hi = 0.0;
+                }
+                // cell iz (padded): entry iz - 1 takes (1 - f) v, entry iz takes f v; at the
+                // clamped ends one entry takes all of v
+                if (iz == 0)
+                    hi += v;
+                else if (iz == nZ)
+                    lo += v;
+                else {
+                    lo = fma(1.0 - f, v, lo);
+                    hi = fma(f, v, hi);
                 }
             }
+            nv[base + k] = lo;
+            nf[base + k] = hi;
+            niz[base + k] = cur;
+            nrun[lane] = k + 1;
             rv[lane] = -2.0 * rw[lane] * rg[lane] * rq2[lane] * (inner * inv_k2);
         }
         __syncthreads();
-        for (int j = lane; j < nZ; j += kWave) {
-            double s = acc[j];
+        if (j < nZ) {
             for (int al = 0; al < nr; ++al) {
-                const int *row = niz + al * nx;
-                int lo = 0, hi = nx;  // first b with row[b] >= j
+                const int base = al * nx, n = nrun[al];
+                int lo = 0, hi = n;  // first run with cell >= j
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
-                    if (row[mid] < j)
+                    if (niz[base + mid] < j)
                         lo = mid + 1;
                     else
                         hi = mid;
                 }
-                for (int b = lo; b < nx && row[b] <= j + 1; ++b)
-                    s = fma(dz_weight(row[b], nf[al * nx + b], j, nZ), nv[al * nx + b], s);
+                if (lo < n && niz[base + lo] == j) s += nf[base + lo++];
+                if (lo < n && niz[base + lo] == j + 1) s += nv[base + lo];
                 const int iq = riz[al];
                 if (iq == j || iq == j + 1) s = fma(dz_weight(iq, rf[al], j, nZ), rv[al], s);
             }
-            acc[j] = s;
         }
         __syncthreads();
     }
-    for (int j = lane; j < nZ; j += kWave) jac[(long long)e * nZ + j] = r.pref * acc[j];
+    if (j < nZ) jac[(long long)e * nZ + j] = r.pref * s;
 }
 
 hipError_t launch_dz(const ReqDev &r, double *jac, hipStream_t s) {
     if (r.n_ext <= 0) return hipSuccess;
-    if (r.family != 2 || r.precision != 0 || r.nZ < 2 || r.n_x < 1 || r.n_x > kDzEntries)
-        return hipErrorInvalidValue;
+    if (r.family != 2 || r.precision != 0 || r.nZ < 2 || r.n_x < 1) return hipErrorInvalidValue;
     void (*fn)(ReqDev, double *) =
         r.reg == 1 ? dz_kernel<1> : (r.reg == 2 ? dz_kernel<2> : dz_kernel<0>);
-    hipLaunchKernelGGL(fn, dim3(r.n_ext), dim3(kWave), dz_lds_bytes(r.nZ), s, r, jac);
+    const int slices = (r.nZ + kWave - 1) / kWave;
+    hipLaunchKernelGGL(fn, dim3(r.n_ext, slices), dim3(kWave), dz_lds_bytes(r.nZ, r.n_x), s, r,
+                       jac);
     return hipGetLastError();
 }
 
