@@ -459,6 +459,55 @@ static int integrate_ft_impl(int family, int n_q, int n_x, double q_max, double 
     return 0;
 }
 
+int frgo_integrate_ft_dz(int n_q, int n_x, double q_max, double k, int regulator, int statistics,
+                         double T, double freq_max, int freq_scaled, int n_tail,
+                         const double *ext, const double *m2, double m2_scalar, const double *Z,
+                         int nZ, double x_min, double x_max, int n_ext, double *out) {
+    if (n_ext < 0 || out == NULL || ext == NULL || Z == NULL || nZ < 1 || nZ > MAXN) return -1;
+    if (n_q < 1 || n_q > MAXN || n_x < 1 || n_x > MAXN) return -1;
+    if (!(q_max > 0.0) || !(k > 0.0) || !(x_min > 0.0) || !(x_max > x_min)) return -1;
+    static __thread double qn[MAXN], qw[MAXN], xn[MAXN], xw[MAXN], fw_[MAXN], fc_[MAXN];
+    static __thread nsum acc[MAXN];
+    double lambda = freq_scaled ? freq_max * k : freq_max;
+    int n_f = frgo_matsubara_rule(statistics, T, lambda, n_tail, MAXN, fw_, fc_);
+    if (n_f < 0) return -1;
+    frgo_gauss_legendre(n_q, 0.0, q_max * k, qn, qw);
+    frgo_gauss_legendre(n_x, -1.0, 1.0, xn, xw);
+    double pref = 2.0 * PI / pow(2.0 * PI, 3.0);
+    for (int e = 0; e < n_ext; ++e) {
+        double p = ext[e], p0 = ext[n_ext + e];
+        double mass = m2 ? m2[e] : m2_scalar;
+        for (int i = 0; i < nZ; ++i) acc[i].s = acc[i].c = 0.0;
+        for (int j = 0; j < n_f; ++j) {
+            double wq = fw_[j], wl = fw_[j] + p0;
+            for (int a = 0; a < n_q; ++a) {
+                double q = qn[a], q2 = q * q;
+                int iq;
+                double fq;
+                dressing_cell(nZ, x_min, x_max, q2, &iq, &fq);
+                for (int b = 0; b < n_x; ++b) {
+                    double l2 = q2 + p * p + 2.0 * q * p * xn[b];
+                    if (l2 < 0.0) l2 = 0.0;
+                    double gq = 1.0 / (wq * wq + frgo_dressing(Z, nZ, x_min, x_max, q2) * q2 +
+                                       frgo_regulator(regulator, q2, k) + mass);
+                    double gl = 1.0 / (wl * wl + frgo_dressing(Z, nZ, x_min, x_max, l2) * l2 +
+                                       frgo_regulator(regulator, l2, k) + mass);
+                    double c = fc_[j] * pref * qw[a] * xw[b] * q2 *
+                               frgo_regulator_dot(regulator, q2, k);
+                    /* term = c G(q^2)^2 G(l2): the dressing multiplies the spatial momentum */
+                    add_dressing_weights(acc, nZ, iq, fq, -2.0 * c * gq * gq * gq * q2 * gl);
+                    int il;
+                    double fl;
+                    dressing_cell(nZ, x_min, x_max, l2, &il, &fl);
+                    add_dressing_weights(acc, nZ, il, fl, -c * gq * gq * gl * gl * l2);
+                }
+            }
+        }
+        for (int i = 0; i < nZ; ++i) out[(size_t)e * nZ + i] = nsum_get(&acc[i]);
+    }
+    return 0;
+}
+
 int frgo_integrate_ft(int family, int n_q, int n_x, double q_max, double k, int regulator,
                       int statistics, double T, double freq_max, int freq_scaled, int n_tail,
                       const double *ext, const double *m2, double m2_scalar, const double *Z,

@@ -131,6 +131,14 @@ int frgo_integrate_ft(int family, int n_q, int n_x, double q_max, double k, int 
                       const double *ext, const double *m2, double m2_scalar, const double *Z,
                       int nZ, double x_min, double x_max, int n_ext, double *out);
 
+/* dI_e/dZ_i of the finite-temperature two-point integral (family 5), out[e * nZ + i], as
+ * frgo_integrate_dz: the dressing multiplies the spatial momentum of both legs.  Arguments as
+ * frgo_integrate_ft with family 5 implied; Z is required. */
+int frgo_integrate_ft_dz(int n_q, int n_x, double q_max, double k, int regulator, int statistics,
+                         double T, double freq_max, int freq_scaled, int n_tail,
+                         const double *ext, const double *m2, double m2_scalar, const double *Z,
+                         int nZ, double x_min, double x_max, int n_ext, double *out);
+
 /* dI_e/dm2_e of frgo_integrate_ft (see frgo_integrate_dm2).  Same arguments. */
 int frgo_integrate_ft_dm2(int family, int n_q, int n_x, double q_max, double k, int regulator,
                           int statistics, double T, double freq_max, int freq_scaled, int n_tail,

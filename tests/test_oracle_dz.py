@@ -97,3 +97,29 @@ def test_dz_zero_exactly_where_no_node_reaches():
                 assert J[e, i] < 0, (e, i)
             else:
                 assert J[e, i] == 0.0, (e, i)
+
+
+@pytest.mark.parametrize("stat,scaled", [(oracle.BOSONIC, False), (oracle.FERMIONIC, True)])
+def test_dz_finite_temperature_matches_central_differences(stat, scaled):
+    # the finite-temperature two-point integral (Matsubara sum with tails), each table entry
+    Z, p, m2 = _case(4, nZ=8, n=5)
+    rng = np.random.default_rng(5)
+    p0 = rng.uniform(-1.0, 1.0, p.size)
+    ft = dict(T=0.2, freq_max=3.0, statistics=stat, n_tail=3, freq_scaled=scaled)
+
+    def I(Zv):
+        return oracle.integrate_ft(oracle.TWO_POINT_T, 8, Q_MAX, n_x=6, ext=(p, p0), m2=m2,
+                                   Z=Zv, x_min=XMIN, x_max=XMAX, **ft)
+
+    J = oracle.integrate_ft_dz(8, Q_MAX, n_x=6, ext=(p, p0), m2=m2, Z=Z, x_min=XMIN,
+                               x_max=XMAX, **ft)
+    h = 1e-5
+    scale = np.max(np.abs(J), axis=1)
+    for i in range(Z.size):
+        Zp, Zm = Z.copy(), Z.copy()
+        Zp[i] += h
+        Zm[i] -= h
+        fd = (I(Zp) - I(Zm)) / (2 * h)
+        assert np.all(np.abs(fd - J[:, i]) <= 1e-7 * scale + 1e-18), i
+    fd = (I(Z + h) - I(Z - h)) / (2 * h)
+    assert np.allclose(J.sum(axis=1), fd, rtol=1e-8, atol=0.0)
