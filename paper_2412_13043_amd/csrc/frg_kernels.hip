@@ -1391,6 +1391,9 @@ hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg, int 
 // -G(v)^2 v w_j(v), with w_j(v) the interpolation weight of entry j at v.  By the product rule,
 //   dI_e/dZ_j = pref sum_a W_a [ -2 G(q_a^2)^3 q_a^2 w_j(q_a^2) sum_b xw_b G(l2_ab)
 //                               - G(q_a^2)^2 sum_b xw_b G(l2_ab)^2 l2_ab w_j(l2_ab) ].
+// At finite temperature (FAM 5) a runs over the (spatial node, frequency) radial index; the
+// dressing multiplies the spatial momentum of both legs and the inner leg's mass term carries
+// the frequency, m2 + (w_a + p0)^2, as in the integral.
 // Workgroup (e, slice) computes entries j = 64 slice + lane of point e, one per lane, in rounds
 // of radial nodes.  A round's node terms and cells go to LDS.  l2_ab grows with x_b (ascending
 // nodes, p taken as |p|), so along a radial node's row the cells are non-decreasing: one lane
@@ -1412,10 +1415,10 @@ __device__ __forceinline__ double dz_weight(int iz, double f, int j, int nZ) {
 size_t dz_lds_bytes(int nZ, int n_x) {
     const size_t E = (size_t)dz_entries(n_x);
     return (size_t)(kLogTable + nZ + 1) * sizeof(double2) + 3 * E * sizeof(double) +
-           7 * kWave * sizeof(double) + E * sizeof(int) + 2 * kWave * sizeof(int);
+           8 * kWave * sizeof(double) + E * sizeof(int) + 2 * kWave * sizeof(int);
 }
 
-template <int REG>
+template <int FAM, int REG>
 __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ jac) {
     extern __shared__ double2 lds_dyn[];
     __shared__ float zslope;
@@ -1436,16 +1439,17 @@ __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ j
     double *rq2 = rc1 + kWave;      // q^2
     double *rv = rq2 + kWave;       // radial-leg term  -2 W G(q^2)^3 q^2 sum_b xw G^(l2)/k^2
     double *rf = rv + kWave;        // radial-leg cell fraction
-    int *niz = (int *)(rf + kWave); // node padded cell index, then run's cell
+    double *rm = rf + kWave;        // inner leg's mass term / k^2
+    int *niz = (int *)(rm + kWave); // node padded cell index, then run's cell
     int *riz = niz + E;             // radial-leg padded cell index
     int *nrun = riz + kWave;        // runs per row
     stage_log(sm, r.logt);
     stage_dressing(r, sm);
     __syncthreads();
     const double p = fabs(r.ext[e]);
+    const double p0 = FAM == 5 ? r.ext[r.n_ext + e] : 0.0;
     const double m2 = lane_m2(r, e);
     const double inv_k2 = 1.0 / r.k2;
-    const double m2h = m2 * inv_k2;
     const double zb1 = r.zbk + 1.0;
     const int R = max(1, min(kWave, E / nx));
     double s = 0.0;
@@ -1466,13 +1470,20 @@ __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ j
             rq2[lane] = q2;
             rf[lane] = f;
             riz[lane] = iz;
+            double m2x = m2;
+            if (FAM == 5) {
+                const double wl = kc(r.rad.w0)[r0 + lane] + p0;
+                m2x = fma(wl, wl, m2);
+            }
+            rm[lane] = m2x * inv_k2;
         }
         __syncthreads();
         const int nn = nr * nx;
         for (int t = lane; t < nn; t += kWave) {
             const int al = t / nx, b = t - al * nx;
             double l2[1] = {fma(rc1[al], kc(r.ang.x)[b], rc0[al])}, G[1];
-            propagators64<1, false, REG>(l2, G, sm, nZ, r.za, zb1, m2h, 1.0, r.far_y, r.reg_n);
+            propagators64<1, false, REG>(l2, G, sm, nZ, r.za, zb1, rm[al], 1.0, r.far_y,
+                                         r.reg_n);
             int iz;
             double f;
             zcell64(fma(fm::log_tab(l2[0], sm.logt), r.za, zb1), nZ, iz, f);
@@ -1556,9 +1567,13 @@ __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ j
 
 hipError_t launch_dz(const ReqDev &r, double *jac, hipStream_t s) {
     if (r.n_ext <= 0) return hipSuccess;
-    if (r.family != 2 || r.precision != 0 || r.nZ < 2 || r.n_x < 1) return hipErrorInvalidValue;
-    void (*fn)(ReqDev, double *) =
-        r.reg == 1 ? dz_kernel<1> : (r.reg == 2 ? dz_kernel<2> : dz_kernel<0>);
+    if ((r.family != 2 && r.family != 5) || r.precision != 0 || r.nZ < 2 || r.n_x < 1)
+        return hipErrorInvalidValue;
+    void (*fn)(ReqDev, double *);
+    if (r.family == 5)
+        fn = r.reg == 1 ? dz_kernel<5, 1> : (r.reg == 2 ? dz_kernel<5, 2> : dz_kernel<5, 0>);
+    else
+        fn = r.reg == 1 ? dz_kernel<2, 1> : (r.reg == 2 ? dz_kernel<2, 2> : dz_kernel<2, 0>);
     const int slices = (r.nZ + kWave - 1) / kWave;
     hipLaunchKernelGGL(fn, dim3(r.n_ext, slices), dim3(kWave), dz_lds_bytes(r.nZ, r.n_x), s, r,
                        jac);

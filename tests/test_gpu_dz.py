@@ -1,5 +1,5 @@
-"""GPU derivatives of the two-point integral in its dressing-table entries (dout_dz,
-dI_e/dZ_i) against the FP64 oracle, entry by entry.
+"""GPU derivatives of the two-point integrals (vacuum and finite temperature) in their
+dressing-table entries (dout_dz, dI_e/dZ_i) against the FP64 oracle, entry by entry.
 
 Every term of an entry's sum has the same sign (W, the weights and G are positive at these
 masses), so each entry is compared at 1e-12 relative, plus 1e-12 of its row's largest entry: the
@@ -77,6 +77,31 @@ def test_dz_matches_oracle(env, reg, n_ext, n_q, n_x, nZ, k):
     assert np.max(np.abs(got_v - ref_v) / np.abs(ref_v)) <= TOL
 
 
+@pytest.mark.parametrize("stat,reg,scaled", [(0, 0, False), (1, 1, True), (0, 2, False)])
+def test_dz_finite_temperature_matches_oracle(env, stat, reg, scaled):
+    # the Matsubara sum folded into the radial index; momenta below and above the table
+    frg, ctx, torch = env
+    rng = np.random.default_rng(60 + stat + reg)
+    n, n_q, n_x, nZ = 21, 20, 9, 33
+    p = np.concatenate([[0.0, 3e-4, 400.0], 10 ** rng.uniform(-3, 2, n - 3)])
+    p0 = rng.uniform(-1.0, 1.0, n)
+    m2 = rng.uniform(0.1, 1.5, n)
+    Z = wl.dressing_table(70 + nZ, nZ)
+    ft = dict(T=0.2, freq_max=4.0, statistics=stat, n_tail=3, freq_scaled=scaled)
+    out = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    jac = torch.full((n * nZ,), float("nan"), dtype=torch.float64, device="cuda")
+    desc = frg.make_desc(frg.FRG_FAMILY_TWO_POINT_T, n_q, 10.0, n_x=n_x, regulator=reg, **ft)
+    ctx.integrate(desc, out, ext=_d(torch, np.concatenate([p, p0])), m2=_d(torch, m2),
+                  Z=_d(torch, Z), x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, dz=jac)
+    torch.cuda.synchronize()
+    ref = oracle.integrate_ft_dz(n_q, 10.0, n_x=n_x, ext=(p, p0), m2=m2, Z=Z,
+                                 regulator=_okind(reg), x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, **ft)
+    _check(jac.cpu().numpy().reshape(n, nZ), ref)
+    ref_v = oracle.integrate_ft(oracle.TWO_POINT_T, n_q, 10.0, n_x=n_x, ext=(p, p0), m2=m2,
+                                Z=Z, regulator=_okind(reg), **ft)
+    assert np.max(np.abs(out.cpu().numpy() - ref_v) / np.abs(ref_v)) <= TOL
+
+
 def test_dz_two_point_workload_full_size(env):
     # one right-hand side of the two-point workload: 256 momenta x 64 x 32, 256-entry table
     p, m2, Z = wl.two_point()
@@ -122,8 +147,7 @@ def test_dz_unsupported_and_invalid(env):
     cases = [(frg.make_desc(frg.FRG_FAMILY_THREE_POINT, 8, 6.0, n_x=4, n_phi=4), frg.FRG_E_UNSUPPORTED),
              (frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 8, 6.0, n_x=4, precision=1),
               frg.FRG_E_UNSUPPORTED),
-             (frg.make_desc(frg.FRG_FAMILY_TWO_POINT_T, 8, 6.0, n_x=4, T=0.2, freq_max=3.0),
-              frg.FRG_E_UNSUPPORTED)]
+             (frg.make_desc(frg.FRG_FAMILY_LPA, 8, 6.0), frg.FRG_E_UNSUPPORTED)]
     for desc, status in cases:
         with pytest.raises(frg.FrgError) as ei:
             ctx.integrate(desc, out, ext=ext, m2_scalar=0.5, Z=Z, dz=jac)
