@@ -80,6 +80,7 @@ def _load():
             lib.frgo_integrate_dm2.argtypes = lib.frgo_integrate.argtypes
             lib.frgo_integrate_ft_dm2.argtypes = lib.frgo_integrate_ft.argtypes
             lib.frgo_integrate_dz.argtypes = [I, I, I, D, D, I, P, P, D, P, I, D, D, I, P]
+            lib.frgo_integrate_dz_three.argtypes = [I, I, I, D, D, I, P, P, D, P, I, D, D, I, P]
             lib.frgo_integrate_ft_dz.argtypes = [I, I, D, D, I, I, D, D, I, I, P, P, D, P, I, D,
                                                  D, I, P]
             _lib = lib
@@ -159,6 +160,22 @@ def integrate_dz(n_q, q_max, *, n_x, ext, Z, k=1.0, regulator=REG_EXP, m2=None, 
                                    m2_scalar, _ptr(Za), len(Za), x_min, x_max, n, _ptr(out))
     if rc != 0:
         raise ValueError(f"frgo_integrate_dz rejected the arguments (rc={rc})")
+    return out
+
+
+def integrate_dz_three(n_q, q_max, *, n_x, n_phi, ext, Z, k=1.0, regulator=REG_EXP, m2=None,
+                       m2_scalar=0.0, x_min=1e-3, x_max=1e3):
+    """dI_e/dZ_i of the three-point integral: array [n_ext, len(Z)]; ext = (p[n], alpha[n])."""
+    p, alpha = ext
+    ext_arr = np.concatenate([_f64(p), _f64(alpha)])
+    Za, m2a = _f64(Z), _f64(m2)
+    n = len(p)
+    out = np.empty((n, len(Za)))
+    rc = _load().frgo_integrate_dz_three(n_q, n_x, n_phi, q_max, k, regulator, _ptr(ext_arr),
+                                         _ptr(m2a), m2_scalar, _ptr(Za), len(Za), x_min, x_max,
+                                         n, _ptr(out))
+    if rc != 0:
+        raise ValueError(f"frgo_integrate_dz_three rejected the arguments (rc={rc})")
     return out
 
 

@@ -351,6 +351,60 @@ int frgo_integrate_dz(int d, int n_q, int n_x, double q_max, double k, int regul
     return 0;
 }
 
+int frgo_integrate_dz_three(int n_q, int n_x, int n_phi, double q_max, double k, int regulator,
+                            const double *ext, const double *m2, double m2_scalar,
+                            const double *Z, int nZ, double x_min, double x_max, int n_ext,
+                            double *out) {
+    if (n_ext < 0 || out == NULL || ext == NULL || Z == NULL || nZ < 1 || nZ > MAXN) return -1;
+    if (n_q < 1 || n_q > MAXN || n_x < 1 || n_x > MAXN || n_phi < 1 || n_phi > MAXN) return -1;
+    if (!(q_max > 0.0) || !(k > 0.0) || !(x_min > 0.0) || !(x_max > x_min)) return -1;
+    static __thread double qn[MAXN], qw[MAXN], xn[MAXN], xw[MAXN], fn[MAXN], fw[MAXN];
+    static __thread nsum acc[MAXN];
+    frgo_gauss_legendre(n_q, 0.0, q_max * k, qn, qw);
+    frgo_gauss_legendre(n_x, -1.0, 1.0, xn, xw);
+    frgo_gauss_legendre(n_phi, 0.0, PI, fn, fw);
+    double pref = 2.0 * PI / pow(2.0 * PI, 4.0);
+    for (int e = 0; e < n_ext; ++e) {
+        double p = ext[e], alpha = ext[n_ext + e];
+        double ca = cos(alpha), sa = sin(alpha);
+        double mass = m2 ? m2[e] : m2_scalar;
+        for (int i = 0; i < nZ; ++i) acc[i].s = acc[i].c = 0.0;
+        for (int a = 0; a < n_q; ++a) {
+            double q = qn[a], q2 = q * q;
+            double gq = frgo_propagator(regulator, Z, nZ, x_min, x_max, q2, mass, k);
+            int iq;
+            double fq;
+            dressing_cell(nZ, x_min, x_max, q2, &iq, &fq);
+            for (int b = 0; b < n_x; ++b) {
+                double x = xn[b], sx = sqrt(1.0 - x * x);
+                double l1 = q2 + p * p + 2.0 * q * p * x;
+                if (l1 < 0.0) l1 = 0.0;
+                double g1 = frgo_propagator(regulator, Z, nZ, x_min, x_max, l1, mass, k);
+                int i1;
+                double f1;
+                dressing_cell(nZ, x_min, x_max, l1, &i1, &f1);
+                for (int c = 0; c < n_phi; ++c) {
+                    double phi = fn[c];
+                    double l2 = q2 + p * p - 2.0 * q * p * (x * ca + sx * cos(phi) * sa);
+                    if (l2 < 0.0) l2 = 0.0;
+                    double g2 = frgo_propagator(regulator, Z, nZ, x_min, x_max, l2, mass, k);
+                    double cw = pref * qw[a] * xw[b] * fw[c] * sx * sin(phi) * q2 * q *
+                                frgo_regulator_dot(regulator, q2, k);
+                    /* term = cw G(q^2)^2 G(l1) G(l2) */
+                    add_dressing_weights(acc, nZ, iq, fq, -2.0 * cw * gq * gq * gq * q2 * g1 * g2);
+                    add_dressing_weights(acc, nZ, i1, f1, -cw * gq * gq * g1 * g1 * l1 * g2);
+                    int i2;
+                    double f2;
+                    dressing_cell(nZ, x_min, x_max, l2, &i2, &f2);
+                    add_dressing_weights(acc, nZ, i2, f2, -cw * gq * gq * g1 * g2 * g2 * l2);
+                }
+            }
+        }
+        for (int i = 0; i < nZ; ++i) out[(size_t)e * nZ + i] = nsum_get(&acc[i]);
+    }
+    return 0;
+}
+
 /* ---------------------------------------------------------------------------------------- */
 /* Finite temperature: Matsubara frequency rule and the d = 3 + 1 integrals.                 */
 /* ---------------------------------------------------------------------------------------- */

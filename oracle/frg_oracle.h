@@ -85,6 +85,14 @@ int frgo_integrate_dz(int d, int n_q, int n_x, double q_max, double k, int regul
                       const double *ext, const double *m2, double m2_scalar, const double *Z,
                       int nZ, double x_min, double x_max, int n_ext, double *out);
 
+/* dI_e/dZ_i of the three-point integral (family 3), out[e * nZ + i], as frgo_integrate_dz:
+ * the product rule runs over the radial leg (weight 2) and both inner legs.  ext = p[n_ext]
+ * followed by alpha[n_ext]; Z is required. */
+int frgo_integrate_dz_three(int n_q, int n_x, int n_phi, double q_max, double k, int regulator,
+                            const double *ext, const double *m2, double m2_scalar,
+                            const double *Z, int nZ, double x_min, double x_max, int n_ext,
+                            double *out);
+
 /*
  * General d = 4 one-loop integral with explicit external 4-vectors, on a full hyperspherical
  * product rule (GL in the polar angles theta1, theta2 in [0, pi] with the sin^2/sin Jacobian

@@ -123,3 +123,27 @@ def test_dz_finite_temperature_matches_central_differences(stat, scaled):
         assert np.all(np.abs(fd - J[:, i]) <= 1e-7 * scale + 1e-18), i
     fd = (I(Z + h) - I(Z - h)) / (2 * h)
     assert np.allclose(J.sum(axis=1), fd, rtol=1e-8, atol=0.0)
+
+
+@pytest.mark.parametrize("reg", [oracle.REG_EXP, oracle.reg_polyexp(8), oracle.REG_LITIM])
+def test_dz_three_point_matches_central_differences(reg):
+    # the three-point integral: radial leg, the first inner leg (cos1 only) and the second
+    # (cos1 and phi); angles spanning [0, pi]
+    Z, p, m2 = _case(6, nZ=8, n=5)
+    alpha = np.array([0.0, 0.4, 1.5, 2.6, math.pi])
+    kw = dict(n_x=5, n_phi=4, x_min=XMIN, x_max=XMAX, regulator=reg)
+
+    def I(Zv):
+        return oracle.integrate(oracle.THREE_POINT, 6, Q_MAX, ext=(p, alpha), m2=m2, Z=Zv, **kw)
+
+    J = oracle.integrate_dz_three(6, Q_MAX, ext=(p, alpha), m2=m2, Z=Z, **kw)
+    h = 1e-5
+    scale = np.max(np.abs(J), axis=1)
+    for i in range(Z.size):
+        Zp, Zm = Z.copy(), Z.copy()
+        Zp[i] += h
+        Zm[i] -= h
+        fd = (I(Zp) - I(Zm)) / (2 * h)
+        assert np.all(np.abs(fd - J[:, i]) <= 1e-7 * scale + 1e-18), i
+    fd = (I(Z + h) - I(Z - h)) / (2 * h)
+    assert np.allclose(J.sum(axis=1), fd, rtol=1e-8, atol=0.0)
