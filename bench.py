@@ -569,6 +569,22 @@ def secondary(torch, frg, wl, ctx, serving_seconds=4.0):
     res_z["jacobian_entries"] = int(pz.size * Zz.size)
     res_z["nodes"] = int(pz.size * wl.TWO_NQ * wl.TWO_NX)
     ex["two_point_dI_dZ_one_rhs"] = res_z
+    # the same for one right-hand side of the three-point workload (1024 points x 256 entries)
+    P3, A3, m3z, Z3z = wl.three_point()
+    te3, tm3z, tZ3z = _dev(torch, np.concatenate([P3, A3])), _dev(torch, m3z), _dev(torch, Z3z)
+    o3z = torch.empty(P3.size, dtype=torch.float64, device="cuda")
+    j3z = torch.empty(P3.size * Z3z.size, dtype=torch.float64, device="cuda")
+    d3z = frg.make_desc(3, wl.THREE_NQ, wl.THREE_QMAX, n_x=wl.THREE_NX, n_phi=wl.THREE_NPHI)
+    res_z3 = {}
+    for name, dz in (("value_only", None), ("value_and_dI_dZ", j3z)):
+        fz = lambda: ctx.integrate(d3z, o3z, ext=te3, m2=tm3z, Z=tZ3z, x_min=wl.Z_XMIN,
+                                   x_max=wl.Z_XMAX, dz=dz)
+        warm_clocks(torch, fz, EXTRA_WARM_S)
+        wall, ev = time_kernel(torch, fz, 20, 2)
+        res_z3[name + "_us"] = round(float(np.mean(ev)) * 1e3, 1)
+    res_z3["jacobian_entries"] = int(P3.size * Z3z.size)
+    res_z3["nodes"] = int(P3.size * wl.THREE_NQ * wl.THREE_NX * wl.THREE_NPHI)
+    ex["three_point_dI_dZ_one_rhs"] = res_z3
     # precision form on the near-pole workload vs float64 on identical inputs
     log("bench: float32 precision form")
 

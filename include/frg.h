@@ -194,9 +194,10 @@ typedef struct {
                               Z enters through the linear interpolation of every propagator's
                               dressing, so dG(v)/dZ_i = -G(v)^2 v w_i(v) with w_i(v) the
                               interpolation weight of entry i at v; entries no node reaches are
-                              exactly 0.  Families 2 and 5 (the dressing multiplies the
-                              spatial momentum) in float64 with a dressing table only
-                              (FRG_E_UNSUPPORTED for other families and the float32 form,
+                              exactly 0.  The vertex families 2, 3 and 5 (at finite
+                              temperature the dressing multiplies the spatial momentum) in
+                              float64 with a dressing table only (FRG_E_UNSUPPORTED for the
+                              LPA families and the float32 form,
                               FRG_E_INVAL without a table), frg_integrate_batch only
                               (FRG_E_UNSUPPORTED from frg_integrate_multi and sessions); the
                               caller owns the buffer.  Computed by a second kernel after the

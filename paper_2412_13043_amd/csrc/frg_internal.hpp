@@ -96,7 +96,7 @@ hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg, int 
                         const TileDev *tiles_dev, int n_tiles, int grid, int lds_bytes,
                         double *contrib, unsigned *counters, unsigned *work_ctr, hipStream_t s);
 hipError_t launch_fill_zero_u32(unsigned *p, size_t n, hipStream_t s);
-// Two-point families (2, 5), float64: jac[e * r.nZ + i] = dI_e/dZ_i for every point of r
+// Vertex families (2, 3, 5), float64: jac[e * r.nZ + i] = dI_e/dZ_i for every point of r
 // (workgroups per point and 64-entry slice of the table; r needs a dressing table).
 hipError_t launch_dz(const ReqDev &r, double *jac, hipStream_t s);
 // radially chunked requests: radial sums after the integrand launch (no-op otherwise)

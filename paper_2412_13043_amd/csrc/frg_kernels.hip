@@ -1384,26 +1384,30 @@ hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg, int 
 }
 
 // --------------------------------------------------------------------------------------------
-// Derivatives of the two-point integral in the dressing-table entries
+// Derivatives of the vertex integrals in the dressing-table entries
 // --------------------------------------------------------------------------------------------
 // The integral depends on entry Z_j only through the dressing's linear interpolation at each
-// propagator argument v (q^2 of the radial leg, l2 of the inner leg): dG(v)/dZ_j =
-// -G(v)^2 v w_j(v), with w_j(v) the interpolation weight of entry j at v.  By the product rule,
-//   dI_e/dZ_j = pref sum_a W_a [ -2 G(q_a^2)^3 q_a^2 w_j(q_a^2) sum_b xw_b G(l2_ab)
-//                               - G(q_a^2)^2 sum_b xw_b G(l2_ab)^2 l2_ab w_j(l2_ab) ].
+// propagator argument v: dG(v)/dZ_j = -G(v)^2 v w_j(v), with w_j(v) the interpolation weight of
+// entry j at v.  By the product rule over the legs,
+//   two-point:   dI_e/dZ_j = pref sum_a W_a [ -2 G(q_a^2)^3 q_a^2 w_j(q_a^2) sum_b xw_b G(l2_ab)
+//                                           - G(q_a^2)^2 sum_b xw_b G(l2_ab)^2 l2_ab w_j(l2_ab) ]
+//   three-point: the radial leg (weight 2), the first inner leg G(l1_ab) and the second
+//                G(l2_abc), each with the other propagators as factors.
 // At finite temperature (FAM 5) a runs over the (spatial node, frequency) radial index; the
 // dressing multiplies the spatial momentum of both legs and the inner leg's mass term carries
 // the frequency, m2 + (w_a + p0)^2, as in the integral.
-// Workgroup (e, slice) computes entries j = 64 slice + lane of point e, one per lane, in rounds
-// of radial nodes.  A round's node terms and cells go to LDS.  l2_ab grows with x_b (ascending
-// nodes, p taken as |p|), so along a radial node's row the cells are non-decreasing: one lane
-// per radial node adds the row, in b order, into one pair of sums per cell (the parts for the
-// cell's lower and upper entry).  The owner of entry j then takes, radial node by radial node,
-// the upper part of the run in cell j and the lower part of the run in cell j + 1 (found by
-// binary search) and the radial leg's term.  Every entry's sum has one fixed order and no
-// atomics.
-// node terms of one round held in LDS: at least 512 and at least one row of n_x
-__host__ __device__ __forceinline__ int dz_entries(int n_x) { return n_x > 512 ? n_x : 512; }
+// The sums are organised in rows: a radial node (FAM 2, 5) with its cos1 nodes, or a (radial,
+// cos1) pair (FAM 3) with its phi nodes.  Along a row the innermost propagator's argument grows
+// (ascending x with p taken as |p|; ascending phi with sin(alpha) taken as |sin(alpha)|), so its
+// cells are non-decreasing.  Workgroup (e, slice) computes entries j = 64 slice + lane of point
+// e, one per lane, in rounds of rows: a round's node terms and cells go to LDS, one lane per row
+// adds the row in order into one pair of sums per cell (the parts for the cell's lower and upper
+// entry), and the owner of entry j takes, row by row, the upper part of the run in cell j, the
+// lower part of the run in cell j + 1 (binary search), and the row's single-cell terms (radial
+// leg; FAM 3 also the first inner leg).  Every entry's sum has one fixed order and no atomics.
+
+// node terms of one round held in LDS: at least 512 and at least one row
+__host__ __device__ __forceinline__ int dz_entries(int n_in) { return n_in > 512 ? n_in : 512; }
 
 // Weight of entry j in the interpolation at padded cell index iz (0 and nZ are the clamped ends,
 // where one entry takes the whole value), fraction f; iz must be j or j + 1.
@@ -1412,10 +1416,19 @@ __device__ __forceinline__ double dz_weight(int iz, double f, int j, int nZ) {
     return iz == j ? f : 1.0 - f;
 }
 
-size_t dz_lds_bytes(int nZ, int n_x) {
-    const size_t E = (size_t)dz_entries(n_x);
+constexpr int kDzRowD = 11;  // per-row double arrays
+constexpr int kDzRowI = 3;   // per-row int arrays
+
+size_t dz_lds_bytes(int nZ, int n_in) {
+    const size_t E = (size_t)dz_entries(n_in);
     return (size_t)(kLogTable + nZ + 1) * sizeof(double2) + 3 * E * sizeof(double) +
-           8 * kWave * sizeof(double) + E * sizeof(int) + 2 * kWave * sizeof(int);
+           kDzRowD * kWave * sizeof(double) + E * sizeof(int) + kDzRowI * kWave * sizeof(int);
+}
+
+// Padded cell index and fraction of the dressing coordinate s + 1 = za log(v) + zb1.
+__device__ __forceinline__ void dz_cell(const Smem &sm, int nZ, double za, double zb1, double v,
+                                        int &iz, double &f) {
+    zcell64(fma(fm::log_tab(v, sm.logt), za, zb1), nZ, iz, f);
 }
 
 template <int FAM, int REG>
@@ -1423,87 +1436,125 @@ __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ j
     extern __shared__ double2 lds_dyn[];
     __shared__ float zslope;
     Smem sm;
-    const int nZ = r.nZ, nx = r.n_x, lane = (int)threadIdx.x, e = (int)blockIdx.x;
+    const int nZ = r.nZ, lane = (int)threadIdx.x, e = (int)blockIdx.x;
     const int j = (int)blockIdx.y * kWave + lane;  // the entry this lane owns
-    const int E = dz_entries(nx);
+    const int n_in = FAM == 3 ? r.n_phi : r.n_x;    // nodes per row
+    const long long n_rows = FAM == 3 ? (long long)r.n_q * r.n_x : r.n_q;
+    const int E = dz_entries(n_in);
     bind_smem(sm, lds_dyn, nZ, &zslope);
     // after the padded table: the round's node arrays (compacted in place into per-cell runs),
-    // then its radial arrays
+    // then its per-row arrays
     double *nv = (double *)(lds_dyn + kLogTable + nZ + 1);  // node term, then run's lower part
     double *nf = nv + E;            // node cell fraction, then run's upper part
-    double *xg = nf + E;            // xw G^(l2), for the radial leg's inner sum
-    double *rw = xg + E;            // W G(q^2)^2
-    double *rg = rw + kWave;        // G(q^2)
-    double *rc0 = rg + kWave;       // (q^2 + p^2)/k^2
-    double *rc1 = rc0 + kWave;      // 2 q p/k^2
-    double *rq2 = rc1 + kWave;      // q^2
-    double *rv = rq2 + kWave;       // radial-leg term  -2 W G(q^2)^3 q^2 sum_b xw G^(l2)/k^2
-    double *rf = rv + kWave;        // radial-leg cell fraction
-    double *rm = rf + kWave;        // inner leg's mass term / k^2
-    int *niz = (int *)(rm + kWave); // node padded cell index, then run's cell
+    double *xg = nf + E;            // w G^(node), for the row's inner sum
+    double *rw = xg + E;            // row factor of the node terms
+    double *rwg = rw + kWave;       // W G(q^2)^2
+    double *rg = rwg + kWave;       // G(q^2)
+    double *rq2 = rg + kWave;       // q^2
+    double *rc0 = rq2 + kWave;      // node argument = rc1 * (x or cos phi) + rc0 (units of k^2)
+    double *rc1 = rc0 + kWave;
+    double *rm = rc1 + kWave;       // inner mass term / k^2
+    double *rf = rm + kWave;        // radial-leg cell fraction
+    double *rv = rf + kWave;        // radial-leg term of the row
+    double *r1f = rv + kWave;       // FAM 3: first inner leg's cell fraction
+    double *r1v = r1f + kWave;      // FAM 3: first inner leg's term of the row
+    int *niz = (int *)(r1v + kWave);  // node padded cell index, then run's cell
     int *riz = niz + E;             // radial-leg padded cell index
-    int *nrun = riz + kWave;        // runs per row
+    int *r1iz = riz + kWave;        // FAM 3: first inner leg's padded cell index
+    int *nrun = r1iz + kWave;       // runs per row
     stage_log(sm, r.logt);
     stage_dressing(r, sm);
     __syncthreads();
     const double p = fabs(r.ext[e]);
-    const double p0 = FAM == 5 ? r.ext[r.n_ext + e] : 0.0;
+    double ca = 1.0, sa = 0.0, p0 = 0.0;
+    if (FAM == 3) {
+        sincos(r.ext[r.n_ext + e], &sa, &ca);
+        sa = fabs(sa);
+    }
+    if (FAM == 5) p0 = r.ext[r.n_ext + e];
     const double m2 = lane_m2(r, e);
     const double inv_k2 = 1.0 / r.k2;
+    const double uf = FAM == 3 ? inv_k2 * inv_k2 : inv_k2;  // units of the inner sums
     const double zb1 = r.zbk + 1.0;
-    const int R = max(1, min(kWave, E / nx));
+    const int R = max(1, min(kWave, E / n_in));
     double s = 0.0;
-    for (int r0 = 0; r0 < r.n_q; r0 += R) {
-        const int nr = min(R, r.n_q - r0);
+    for (long long r0 = 0; r0 < n_rows; r0 += R) {
+        const int nr = (int)min((long long)R, n_rows - r0);
         if (lane < nr) {
-            const RadialTerm t = radial64(r, sm, r0 + lane, p, m2);
-            const double q = r.k * kc(r.rad.q)[r0 + lane];
+            const long long row = r0 + lane;
+            const int a = FAM == 3 ? (int)(row / r.n_x) : (int)row;
+            const RadialTerm t = radial64(r, sm, a, p, m2);
+            const double q = r.k * kc(r.rad.q)[a];
             const double q2 = q * q;
             int iz;
             double f;
-            zcell64(fma(fm::log_tab(fmax(q2, FRG_L2_TINY), sm.logt), r.za, r.zb + 1.0), nZ, iz,
-                    f);
-            rw[lane] = t.wg;
+            dz_cell(sm, nZ, r.za, r.zb + 1.0, fmax(q2, FRG_L2_TINY), iz, f);
+            rwg[lane] = t.wg;
             rg[lane] = t.g;
-            rc0[lane] = t.c0 * inv_k2;
-            rc1[lane] = t.c1 * inv_k2;
             rq2[lane] = q2;
             rf[lane] = f;
             riz[lane] = iz;
-            double m2x = m2;
-            if (FAM == 5) {
-                const double wl = kc(r.rad.w0)[r0 + lane] + p0;
-                m2x = fma(wl, wl, m2);
+            const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2;
+            if (FAM == 3) {
+                const int b = (int)(row - (long long)a * r.n_x);
+                const double xb = kc(r.ang.x)[b];
+                const double m2h = m2 * inv_k2;
+                double l1[1] = {fma(c1, xb, c0)}, g1[1];
+                propagators64<1, false, REG>(l1, g1, sm, nZ, r.za, zb1, m2h, 1.0, r.far_y,
+                                             r.reg_n);
+                int i1;
+                double f1;
+                dz_cell(sm, nZ, r.za, zb1, l1[0], i1, f1);
+                const double xwg1 = kc(r.ang.xw)[b] * g1[0];
+                rw[lane] = t.wg * xwg1;
+                rc0[lane] = fma(-c1, xb * ca, c0);
+                rc1[lane] = -c1 * (kc(r.ang.xs)[b] * sa);
+                rm[lane] = m2h;
+                r1f[lane] = f1;
+                r1iz[lane] = i1;
+                // first inner leg, without the phi sum (added with it below)
+                r1v[lane] = -t.wg * (xwg1 * g1[0]) * l1[0];
+            } else {
+                double m2x = m2;
+                if (FAM == 5) {
+                    const double wl = kc(r.rad.w0)[a] + p0;
+                    m2x = fma(wl, wl, m2);
+                }
+                rw[lane] = t.wg;
+                rc0[lane] = c0;
+                rc1[lane] = c1;
+                rm[lane] = m2x * inv_k2;
             }
-            rm[lane] = m2x * inv_k2;
         }
         __syncthreads();
-        const int nn = nr * nx;
+        const int nn = nr * n_in;
         for (int t = lane; t < nn; t += kWave) {
-            const int al = t / nx, b = t - al * nx;
-            double l2[1] = {fma(rc1[al], kc(r.ang.x)[b], rc0[al])}, G[1];
+            const int al = t / n_in, c = t - al * n_in;
+            const double u = FAM == 3 ? kc(r.phi.c)[c] : kc(r.ang.x)[c];
+            const double w = FAM == 3 ? kc(r.phi.w)[c] : kc(r.ang.xw)[c];
+            double l2[1] = {fma(rc1[al], u, rc0[al])}, G[1];
+            if (FAM == 3) l2[0] = fmax(l2[0], FRG_L2_TINY);
             propagators64<1, false, REG>(l2, G, sm, nZ, r.za, zb1, rm[al], 1.0, r.far_y,
                                          r.reg_n);
             int iz;
             double f;
-            zcell64(fma(fm::log_tab(l2[0], sm.logt), r.za, zb1), nZ, iz, f);
-            const double xw = kc(r.ang.xw)[b];
-            xg[t] = xw * G[0];
-            nv[t] = -rw[al] * (xw * (G[0] * G[0])) * (l2[0] * inv_k2);
+            dz_cell(sm, nZ, r.za, zb1, l2[0], iz, f);
+            xg[t] = w * G[0];
+            nv[t] = -rw[al] * (w * (G[0] * G[0])) * (l2[0] * uf);
             nf[t] = f;
             niz[t] = iz;
         }
         __syncthreads();
         if (lane < nr) {
-            // the radial leg's inner sum, and the row compacted into runs of equal cell (run k
-            // is written at position k <= b, after position b has been read).  A node within
+            // the row's inner sum, and the row compacted into runs of equal cell (run k is
+            // written at position k <= c, after position c has been read).  A node within
             // rounding of a cell boundary that reads one cell below its predecessor is taken at
             // the boundary (same weights up to that rounding).
-            const int base = lane * nx;
+            const int base = lane * n_in;
             double inner = 0.0, lo = 0.0, hi = 0.0;
             int k = 0, cur = -1, prev = 0;
-            for (int b = 0; b < nx; ++b) {
-                const int t = base + b;
+            for (int c = 0; c < n_in; ++c) {
+                const int t = base + c;
                 inner += xg[t];
                 int iz = niz[t];
                 double f = nf[t];
@@ -1540,12 +1591,19 @@ __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ j
             nf[base + k] = hi;
             niz[base + k] = cur;
             nrun[lane] = k + 1;
-            rv[lane] = -2.0 * rw[lane] * rg[lane] * rq2[lane] * (inner * inv_k2);
+            if (FAM == 3) {
+                // row = (a, b): radial leg -2 W G(q^2)^3 q^2 xw G^(l1) I_b, first inner leg
+                // -W G(q^2)^2 xw G^(l1)^2 l1 I_b, I_b = sum_c w_c G^(l2) (units k^-4 overall)
+                rv[lane] = -2.0 * rg[lane] * rq2[lane] * rw[lane] * (inner * uf);
+                r1v[lane] *= inner * uf;
+            } else {
+                rv[lane] = -2.0 * rw[lane] * rg[lane] * rq2[lane] * (inner * uf);
+            }
         }
         __syncthreads();
         if (j < nZ) {
             for (int al = 0; al < nr; ++al) {
-                const int base = al * nx, n = nrun[al];
+                const int base = al * n_in, n = nrun[al];
                 int lo = 0, hi = n;  // first run with cell >= j
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
@@ -1558,6 +1616,10 @@ __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ j
                 if (lo < n && niz[base + lo] == j + 1) s += nv[base + lo];
                 const int iq = riz[al];
                 if (iq == j || iq == j + 1) s = fma(dz_weight(iq, rf[al], j, nZ), rv[al], s);
+                if (FAM == 3) {
+                    const int i1 = r1iz[al];
+                    if (i1 == j || i1 == j + 1) s = fma(dz_weight(i1, r1f[al], j, nZ), r1v[al], s);
+                }
             }
         }
         __syncthreads();
@@ -1565,17 +1627,22 @@ __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ j
     if (j < nZ) jac[(long long)e * nZ + j] = r.pref * s;
 }
 
+template <int FAM>
+static void (*dz_for_reg(int reg))(ReqDev, double *) {
+    return reg == 1 ? dz_kernel<FAM, 1> : (reg == 2 ? dz_kernel<FAM, 2> : dz_kernel<FAM, 0>);
+}
+
 hipError_t launch_dz(const ReqDev &r, double *jac, hipStream_t s) {
     if (r.n_ext <= 0) return hipSuccess;
-    if ((r.family != 2 && r.family != 5) || r.precision != 0 || r.nZ < 2 || r.n_x < 1)
+    if ((r.family != 2 && r.family != 3 && r.family != 5) || r.precision != 0 || r.nZ < 2 ||
+        r.n_x < 1 || (r.family == 3 && r.n_phi < 1))
         return hipErrorInvalidValue;
-    void (*fn)(ReqDev, double *);
-    if (r.family == 5)
-        fn = r.reg == 1 ? dz_kernel<5, 1> : (r.reg == 2 ? dz_kernel<5, 2> : dz_kernel<5, 0>);
-    else
-        fn = r.reg == 1 ? dz_kernel<2, 1> : (r.reg == 2 ? dz_kernel<2, 2> : dz_kernel<2, 0>);
+    void (*fn)(ReqDev, double *) = r.family == 3   ? dz_for_reg<3>(r.reg)
+                                   : r.family == 5 ? dz_for_reg<5>(r.reg)
+                                                   : dz_for_reg<2>(r.reg);
     const int slices = (r.nZ + kWave - 1) / kWave;
-    hipLaunchKernelGGL(fn, dim3(r.n_ext, slices), dim3(kWave), dz_lds_bytes(r.nZ, r.n_x), s, r,
+    const int n_in = r.family == 3 ? r.n_phi : r.n_x;
+    hipLaunchKernelGGL(fn, dim3(r.n_ext, slices), dim3(kWave), dz_lds_bytes(r.nZ, n_in), s, r,
                        jac);
     return hipGetLastError();
 }

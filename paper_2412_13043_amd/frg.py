@@ -300,7 +300,7 @@ def make_batch(n_ext: int, out, *, ext=None, m2=None, m2_scalar: float = 0.0, Z=
                dz=None) -> frg_batch:
     """dout: optional device tensor receiving dI/dm2 per point (float64 descriptors).
     dz: optional contiguous float64 device tensor of n_ext * len(Z) values receiving dI_e/dZ_i
-    row-major (two-point family, frg_integrate_batch only)."""
+    row-major (vertex families, frg_integrate_batch only)."""
     if dz is not None:
         nz = 0 if Z is None else int(Z.numel())
         if (dz.numel() != n_ext * nz or not dz.is_contiguous() or not dz.is_cuda or

@@ -1,5 +1,6 @@
-"""GPU derivatives of the two-point integrals (vacuum and finite temperature) in their
-dressing-table entries (dout_dz, dI_e/dZ_i) against the FP64 oracle, entry by entry.
+"""GPU derivatives of the vertex integrals (two-point in vacuum and at finite temperature,
+three-point) in their dressing-table entries (dout_dz, dI_e/dZ_i) against the FP64 oracle,
+entry by entry.
 
 Every term of an entry's sum has the same sign (W, the weights and G are positive at these
 masses), so each entry is compared at 1e-12 relative, plus 1e-12 of its row's largest entry: the
@@ -8,6 +9,8 @@ few ulp of s, 1e-14 to 1e-13 for tables of hundreds of entries, computed through
 logarithms on the two sides), which an entry reached only through a small weight feels relative
 to itself but not relative to its row.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -102,6 +105,32 @@ def test_dz_finite_temperature_matches_oracle(env, stat, reg, scaled):
     assert np.max(np.abs(out.cpu().numpy() - ref_v) / np.abs(ref_v)) <= TOL
 
 
+@pytest.mark.parametrize("reg", [0, 1, 2])
+@pytest.mark.parametrize("n,n_q,n_x,n_phi,nZ", [(13, 9, 5, 7, 11), (6, 12, 40, 600, 48)])
+def test_dz_three_point_matches_oracle(env, reg, n, n_q, n_x, n_phi, nZ):
+    # rows of (radial, cos1) pairs over phi; n_phi = 600: one row per round; angles over
+    # [0, pi] and beyond it (sin(alpha) < 0 reads |sin(alpha)|)
+    frg, ctx, torch = env
+    rng = np.random.default_rng(80 + n + reg)
+    p = np.concatenate([[0.0, 400.0], 10 ** rng.uniform(-3, 2, n - 2)])
+    alpha = np.concatenate([[0.0, math.pi], rng.uniform(0.0, math.pi, n - 3), [4.0]])
+    m2 = rng.uniform(0.1, 1.5, n)
+    Z = wl.dressing_table(90 + nZ, nZ)
+    out = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    jac = torch.full((n * nZ,), float("nan"), dtype=torch.float64, device="cuda")
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT, n_q, 10.0, n_x=n_x, n_phi=n_phi,
+                         regulator=reg)
+    ctx.integrate(desc, out, ext=_d(torch, np.concatenate([p, alpha])), m2=_d(torch, m2),
+                  Z=_d(torch, Z), x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, dz=jac)
+    torch.cuda.synchronize()
+    ref = oracle.integrate_dz_three(n_q, 10.0, n_x=n_x, n_phi=n_phi, ext=(p, alpha), m2=m2, Z=Z,
+                                    regulator=_okind(reg), x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)
+    _check(jac.cpu().numpy().reshape(n, nZ), ref)
+    ref_v = oracle.integrate(oracle.THREE_POINT, n_q, 10.0, n_x=n_x, n_phi=n_phi,
+                             ext=(p, alpha), m2=m2, Z=Z, regulator=_okind(reg))
+    assert np.max(np.abs(out.cpu().numpy() - ref_v) / np.abs(ref_v)) <= TOL
+
+
 def test_dz_two_point_workload_full_size(env):
     # one right-hand side of the two-point workload: 256 momenta x 64 x 32, 256-entry table
     p, m2, Z = wl.two_point()
@@ -144,7 +173,8 @@ def test_dz_unsupported_and_invalid(env):
     ext = torch.ones(2 * n, dtype=torch.float64, device="cuda")
     Z = _d(torch, wl.dressing_table(1, 16))
     jac = torch.zeros(n * 16, dtype=torch.float64, device="cuda")
-    cases = [(frg.make_desc(frg.FRG_FAMILY_THREE_POINT, 8, 6.0, n_x=4, n_phi=4), frg.FRG_E_UNSUPPORTED),
+    cases = [(frg.make_desc(frg.FRG_FAMILY_LPA_T, 8, 6.0, T=0.2, freq_max=3.0),
+              frg.FRG_E_UNSUPPORTED),
              (frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 8, 6.0, n_x=4, precision=1),
               frg.FRG_E_UNSUPPORTED),
              (frg.make_desc(frg.FRG_FAMILY_LPA, 8, 6.0), frg.FRG_E_UNSUPPORTED)]
