@@ -1402,12 +1402,17 @@ hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg, int 
 // cells are non-decreasing.  Workgroup (e, slice) computes entries j = 64 slice + lane of point
 // e, one per lane, in rounds of rows: a round's node terms and cells go to LDS, one lane per row
 // adds the row in order into one pair of sums per cell (the parts for the cell's lower and upper
-// entry), and the owner of entry j takes, row by row, the upper part of the run in cell j, the
-// lower part of the run in cell j + 1 (binary search), and the row's single-cell terms (radial
-// leg; FAM 3 also the first inner leg).  Every entry's sum has one fixed order and no atomics.
+// entry).  A row's runs have distinct cells, so each run's parts land in their own slots of the
+// slice (upper part at entry cell, lower part at entry cell - 1), and the owner of entry j takes,
+// row by row, its upper slot, its lower slot and the row's single-cell terms (radial leg; FAM 3
+// also the first inner leg).  Every entry's sum has one fixed order and no atomics.
 
-// node terms of one round held in LDS: at least 512 and at least one row
-__host__ __device__ __forceinline__ int dz_entries(int n_in) { return n_in > 512 ? n_in : 512; }
+// node terms of one round held in LDS: at least 256 and at least one row; rows per round
+__host__ __device__ __forceinline__ int dz_entries(int n_in) { return n_in > 256 ? n_in : 256; }
+__host__ __device__ __forceinline__ int dz_rows(int n_in) {
+    const int r = dz_entries(n_in) / n_in;
+    return r < 1 ? 1 : (r > kWave ? kWave : r);
+}
 
 // Weight of entry j in the interpolation at padded cell index iz (0 and nZ are the clamped ends,
 // where one entry takes the whole value), fraction f; iz must be j or j + 1.
@@ -1422,7 +1427,8 @@ constexpr int kDzRowI = 3;   // per-row int arrays
 size_t dz_lds_bytes(int nZ, int n_in) {
     const size_t E = (size_t)dz_entries(n_in);
     return (size_t)(kLogTable + nZ + 1) * sizeof(double2) + 3 * E * sizeof(double) +
-           kDzRowD * kWave * sizeof(double) + E * sizeof(int) + kDzRowI * kWave * sizeof(int);
+           kDzRowD * kWave * sizeof(double) + 2 * (size_t)dz_rows(n_in) * kWave * sizeof(double) +
+           E * sizeof(int) + kDzRowI * kWave * sizeof(int);
 }
 
 // Padded cell index and fraction of the dressing coordinate s + 1 = za log(v) + zb1.
@@ -1458,7 +1464,10 @@ __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ j
     double *rv = rf + kWave;        // radial-leg term of the row
     double *r1f = rv + kWave;       // FAM 3: first inner leg's cell fraction
     double *r1v = r1f + kWave;      // FAM 3: first inner leg's term of the row
-    int *niz = (int *)(r1v + kWave);  // node padded cell index, then run's cell
+    const int R = dz_rows(n_in);
+    double *hs = r1v + kWave;       // [R][64] upper parts by entry slot of this slice
+    double *ls = hs + R * kWave;    // [R][64] lower parts by entry slot
+    int *niz = (int *)(ls + R * kWave);  // node padded cell index, then run's cell
     int *riz = niz + E;             // radial-leg padded cell index
     int *r1iz = riz + kWave;        // FAM 3: first inner leg's padded cell index
     int *nrun = r1iz + kWave;       // runs per row
@@ -1476,7 +1485,7 @@ __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ j
     const double inv_k2 = 1.0 / r.k2;
     const double uf = FAM == 3 ? inv_k2 * inv_k2 : inv_k2;  // units of the inner sums
     const double zb1 = r.zbk + 1.0;
-    const int R = max(1, min(kWave, E / n_in));
+    const int j0 = (int)blockIdx.y * kWave;
     double s = 0.0;
     for (long long r0 = 0; r0 < n_rows; r0 += R) {
         const int nr = (int)min((long long)R, n_rows - r0);
@@ -1600,20 +1609,23 @@ __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ j
                 rv[lane] = -2.0 * rw[lane] * rg[lane] * rq2[lane] * (inner * uf);
             }
         }
+        for (int t = lane; t < nr * kWave; t += kWave) {
+            hs[t] = 0.0;
+            ls[t] = 0.0;
+        }
+        __syncthreads();
+        for (int t = lane; t < nn; t += kWave) {
+            const int al = t / n_in, k = t - al * n_in;
+            if (k >= nrun[al]) continue;
+            const int c = niz[t];  // run k of row al (runs are stored from the row's start)
+            if (c >= j0 && c < j0 + kWave) hs[al * kWave + (c - j0)] = nf[t];
+            if (c - 1 >= j0 && c - 1 < j0 + kWave) ls[al * kWave + (c - 1 - j0)] = nv[t];
+        }
         __syncthreads();
         if (j < nZ) {
             for (int al = 0; al < nr; ++al) {
-                const int base = al * n_in, n = nrun[al];
-                int lo = 0, hi = n;  // first run with cell >= j
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (niz[base + mid] < j)
-                        lo = mid + 1;
-                    else
-                        hi = mid;
-                }
-                if (lo < n && niz[base + lo] == j) s += nf[base + lo++];
-                if (lo < n && niz[base + lo] == j + 1) s += nv[base + lo];
+                s += hs[al * kWave + lane];
+                s += ls[al * kWave + lane];
                 const int iq = riz[al];
                 if (iq == j || iq == j + 1) s = fma(dz_weight(iq, rf[al], j, nZ), rv[al], s);
                 if (FAM == 3) {
