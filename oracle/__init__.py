@@ -80,6 +80,8 @@ def _load():
             lib.frgo_integrate_dm2.argtypes = lib.frgo_integrate.argtypes
             lib.frgo_integrate_ft_dm2.argtypes = lib.frgo_integrate_ft.argtypes
             lib.frgo_integrate_dz.argtypes = [I, I, I, D, D, I, P, P, D, P, I, D, D, I, P]
+            lib.frgo_litim_threshold.argtypes = [I, I, D]
+            lib.frgo_litim_threshold.restype = D
             lib.frgo_integrate_dz_three.argtypes = [I, I, I, D, D, I, P, P, D, P, I, D, D, I, P]
             lib.frgo_integrate_ft_dz.argtypes = [I, I, D, D, I, I, D, D, I, I, P, P, D, P, I, D,
                                                  D, I, P]
@@ -161,6 +163,12 @@ def integrate_dz(n_q, q_max, *, n_x, ext, Z, k=1.0, regulator=REG_EXP, m2=None, 
     if rc != 0:
         raise ValueError(f"frgo_integrate_dz rejected the arguments (rc={rc})")
     return out
+
+
+def litim_threshold(d: int, n: int, w) -> np.ndarray:
+    """l_n^d(w) of the flat regulator, elementwise over w (see frg_oracle.h)."""
+    lib = _load()
+    return np.array([lib.frgo_litim_threshold(d, n, float(x)) for x in np.atleast_1d(w)])
 
 
 def integrate_dz_three(n_q, q_max, *, n_x, n_phi, ext, Z, k=1.0, regulator=REG_EXP, m2=None,

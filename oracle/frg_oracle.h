@@ -93,6 +93,11 @@ int frgo_integrate_dz_three(int n_q, int n_x, int n_phi, double q_max, double k,
                             const double *Z, int nZ, double x_min, double x_max, int n_ext,
                             double *out);
 
+/* Threshold function of the flat regulator, l_n^d(w) = (2/d) (n + [n == 0]) / (1 + w)^(n+1): the
+ * closed form of the LPA integral with that regulator, I = Omega_d/(2 pi)^d k^(d-2) l_1^d(m2/k^2)
+ * (and dI/dm2 = -Omega_d/(2 pi)^d k^(d-4) l_2^d). */
+double frgo_litim_threshold(int d, int n, double w);
+
 /*
  * General d = 4 one-loop integral with explicit external 4-vectors, on a full hyperspherical
  * product rule (GL in the polar angles theta1, theta2 in [0, pi] with the sin^2/sin Jacobian
