@@ -205,6 +205,20 @@ typedef struct {
                               (no atomics), so the values are reproducible bit for bit */
 } frg_batch;
 
+/* ---- threshold functions of the flat regulator -------------------------------------------- */
+
+/* out[i] = l_n^d(w[i]) = (2/d) (n + [n == 0]) / (1 + w[i])^(n + 1) for i < count: the threshold
+ * functions of the flat regulator R = (k^2 - q^2) Theta(k^2 - q^2) (Sec. 5, the convenience
+ * functions for standard setups), i.e. the closed form of the LPA loop integral with it,
+ * I(m^2) = Omega_d/(2 pi)^d k^(d-2) l_1^d(m^2/k^2) (family 1 with FRG_REG_FLAT integrates the
+ * same function by quadrature; the two agree to rounding when q_max = 1), with
+ * dI/dm^2 = -Omega_d/(2 pi)^d k^(d-4) l_2^d and, in general, dl_n/dw = -(n + [n == 0]) l_{n+1}.
+ * w and out: device arrays of count doubles, caller-owned; asynchronous on `stream` (no context
+ * needed).  1 <= d <= 16, 0 <= n <= 16, count >= 0 (0: no-op), else FRG_E_INVAL; w <= -1 is no
+ * error (the pole gives inf or a sign flip, as the formula does). */
+frg_status frg_litim_threshold(int d, int n, const double *w, double *out, int count,
+                               hipStream_t stream);
+
 /* ---- context ------------------------------------------------------------------------------- */
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes bounds the library's own device

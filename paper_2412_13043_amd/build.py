@@ -20,6 +20,7 @@ DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-p
 SOURCES = [
     ("frg_kernels.hip", True),
     ("frg_stepper.hip", True),
+    ("frg_threshold.hip", True),
     ("frg_runtime.cpp", False),
     ("frg_session.cpp", False),
 ]

@@ -122,6 +122,7 @@ _sig = {
                             POINTER(frg_stepper_config), POINTER(c_void_p)], c_int),
     "frg_stepper_advance": ([_P, c_double, _P, POINTER(frg_stepper_stats)], c_int),
     "frg_stepper_destroy": ([_P], c_int),
+    "frg_litim_threshold": ([c_int, c_int, _P, _P, c_int, _P], c_int),
 }
 EXPORTED = tuple(_sig)
 for _name, (_args, _res) in _sig.items():
@@ -155,6 +156,18 @@ def frg_context_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
 
 def frg_context_destroy(ctx: int) -> None:
     _check(_lib.frg_context_destroy(ctx), "frg_context_destroy")
+
+
+def frg_litim_threshold(d: int, n: int, w: int, out: int, count: int, stream: int) -> None:
+    _check(_lib.frg_litim_threshold(d, n, w, out, count, stream), "frg_litim_threshold")
+
+
+def litim_threshold(d: int, n: int, w, out, stream=None):
+    """out[i] = l_n^d(w[i]) (float64 device tensors of equal size); returns out."""
+    if w.numel() != out.numel():
+        raise ValueError("w and out must have the same number of values")
+    frg_litim_threshold(d, n, _dptr(w), _dptr(out), int(w.numel()), _stream(stream))
+    return out
 
 
 def frg_integrate_batch(ctx: int, desc: frg_integral_desc, batch: frg_batch, stream: int) -> None:
