@@ -167,11 +167,11 @@ double frgo_propagator(int reg, const double *Z, int nZ, double x_min, double x_
     return 1.0 / (z * l2 + frgo_regulator(reg, l2, k) + m2);
 }
 
-/* Threshold function of the flat regulator: l_n^d(w) = (2/d) (n + [n == 0]) / (1 + w)^(n + 1),
- * the closed form of the LPA loop integral with R = (k^2 - q^2) Theta(k^2 - q^2): the radial
- * integral over [0, k] of q^(d-1) (2 k^2) / (k^2 + m^2)^(n+1) is 2 k^(d+2) / (d (k^2 + m^2)^(n+1)),
- * which in units of k and w = m^2/k^2 gives l_n^d (n = 1 is the squared propagator of the LPA
- * integral; n = 0 the single one). */
+/* Threshold function of the flat regulator: l_n^d(w) = (2/d) (n + [n == 0]) / (1 + w)^(n + 1).
+ * With R = (k^2 - q^2) Theta(k^2 - q^2) the radial integral over [0, k] of
+ * q^(d-1) (2 k^2) / (k^2 + m^2)^m is 2 k^(d+2) / (d (k^2 + m^2)^m), which in units of k and
+ * w = m^2/k^2 is J_m = (2/d) / (1 + w)^m; l_n^d = (n + [n == 0]) J_{n+1} is the conventional
+ * normalisation (dl_n/dw = -(n + [n == 0]) l_{n+1}), and l_1^d is the LPA integral itself. */
 double frgo_litim_threshold(int d, int n, double w) {
     double r = 1.0 / (1.0 + w);
     double p = r;
