@@ -168,6 +168,22 @@ def test_invalid_session_arguments():
     frg.frg_session_close(s)
 
 
+def test_derivative_outputs_are_rejected_at_submit():
+    # sessions return values only: the mass and dressing derivatives are FRG_E_UNSUPPORTED
+    s = frg.frg_session_open_fake(_cfg(), 1.0, 1.0)
+    r = Req()
+    Z = np.ones(16)
+    r.batch.Z = frg.frg_log_table(Z.ctypes.data, 16, 1e-3, 1e3)
+    sink = np.zeros(r.batch.n_ext * 16)
+    for field in ("dout_dm2", "dout_dz"):
+        b = frg.frg_batch.from_buffer_copy(r.batch)
+        setattr(b, field, sink.ctypes.data)
+        with pytest.raises(frg.FrgError) as ei:
+            frg.frg_session_submit(s, r.desc, b, -1)
+        assert ei.value.status == frg.FRG_E_UNSUPPORTED, field
+    frg.frg_session_close(s)
+
+
 def _ft_desc(**kw):
     args = dict(n_x=8, T=0.2, freq_max=5.0, statistics=frg.FRG_BOSONIC, n_tail=4)
     args.update(kw)
