@@ -15,6 +15,8 @@ step-size rule are the standard ones of Hairer, Norsett & Wanner, Solving ODEs I
     facmax = 5, or 1 right after a rejected step; h_next clipped to [h_min, h_max].
 
 A step that would pass t_end ends exactly there.  fixed_step: steps of exactly h0, no control.
+
+Abm4 (below) is the fixed-step Adams-Bashforth-Moulton 4 PECE stepper with an RK4 start.
 """
 from __future__ import annotations
 
@@ -106,4 +108,77 @@ class Dopri5:
                     return "h_min"
                 fac = 0.9 * err ** -0.2
                 self.h = min(max(h * min(1.0, max(0.2, fac)), self.h_min), self.h_max)
+        return "ok"
+
+
+# Adams-Bashforth (order 4) predictor and Adams-Moulton (order 4) corrector weights, exact
+# fractions: y_{n+1} = y_n + h sum_j b_j f_{n-j} (AB4) and y_n + h (m_p f(pred) + sum_j m_j
+# f_{n-j}) (AM4), both from integrating the interpolating cubic of the right-hand side over the
+# step.
+AB4 = [F(55, 24), F(-59, 24), F(37, 24), F(-9, 24)]
+AM4 = [F(9, 24), F(19, 24), F(-5, 24), F(1, 24)]  # f(t_{n+1}, predicted), f_n, f_{n-1}, f_{n-2}
+RK4_C = [F(0), F(1, 2), F(1, 2), F(1)]
+RK4_B = [F(1, 6), F(1, 3), F(1, 3), F(1, 6)]
+
+
+class Abm4:
+    """Fixed-step Adams-Bashforth-Moulton 4 in PECE mode (the multistep class of explicit
+    steppers the paper names for vertex expansions, Sec. 5.2): predict with AB4, evaluate,
+    correct with AM4, evaluate.  The first three steps are classical RK4 steps that build the
+    history f_n, f_{n-1}, f_{n-2}, f_{n-3}.  A step that would pass t_end ends there: if that
+    shortens it (by more than rounding, 1e-9 of h0) it is an RK4 step and the history restarts
+    after it.  Steps of h0; no error control."""
+
+    def __init__(self, f, y0, *, h0, max_steps, t0=0.0):
+        self.f = f
+        self.y = np.array(y0, dtype=np.float64)
+        self.t = float(t0)
+        self.h0 = h0
+        self.max_steps = max_steps
+        self.hist = []  # f_n, f_{n-1}, ... (newest first), all at step h0
+        self.accepted = 0
+        self.evals = 0
+
+    def _f(self, t, y):
+        self.evals += 1
+        return np.asarray(self.f(t, y), dtype=np.float64)
+
+    def _rk4(self, h):
+        k1 = self.hist[0] if self.hist else self._f(self.t, self.y)
+        ks = [k1]
+        for s in range(1, 4):
+            ks.append(self._f(self.t + float(RK4_C[s]) * h, self.y + float(RK4_C[s]) * h * ks[-1]))
+        return self.y + h * sum(float(RK4_B[j]) * ks[j] for j in range(4))
+
+    def advance(self, t_end):
+        """Advance to t_end; returns "ok" or "max_steps"."""
+        attempts = 0
+        while self.t < t_end:
+            if attempts >= self.max_steps:
+                return "max_steps"
+            attempts += 1
+            h = self.h0
+            last = self.t + h >= t_end * (1.0 - 1e-14) - 1e-300
+            if last:
+                h = t_end - self.t
+            if last and h < self.h0 * (1.0 - 1e-9):
+                # shortened final step: RK4, and the history (at step h0) is dropped
+                self.y = self._rk4(h)
+                self.t = t_end
+                self.hist = [self._f(self.t, self.y)]
+                self.accepted += 1
+                continue
+            if len(self.hist) < 4:
+                if not self.hist:
+                    self.hist = [self._f(self.t, self.y)]
+                ynew = self._rk4(h)
+            else:
+                pred = self.y + h * sum(float(AB4[j]) * self.hist[j] for j in range(4))
+                fp = self._f(self.t + h, pred)
+                ynew = self.y + h * (float(AM4[0]) * fp +
+                                     sum(float(AM4[j + 1]) * self.hist[j] for j in range(3)))
+            self.t = t_end if last else self.t + h
+            self.y = ynew
+            self.hist = ([self._f(self.t, self.y)] + self.hist)[:4]
+            self.accepted += 1
         return "ok"

@@ -120,3 +120,43 @@ def test_lpa_flow_matches_scipy_rk45():
     ref = solve_ivp(f, (0.0, 1.5), u0, method="RK45", rtol=1e-11, atol=1e-13)
     assert ref.success
     assert np.max(np.abs(st.y - ref.y[:, -1])) <= 1e-8 * np.max(np.abs(ref.y[:, -1]))
+
+
+def test_abm4_weights_integrate_cubics_exactly():
+    # AB4 over [t_n, t_n + 1] from f at t_n, t_n - 1, t_n - 2, t_n - 3 (unit step), AM4 from
+    # t_n + 1, t_n, t_n - 1, t_n - 2: exact for every cubic (monomials 1, s, s^2, s^3)
+    for k in range(4):
+        exact = F(1, k + 1)  # int_0^1 s^k ds
+        ab = sum(rk.AB4[j] * F(-j) ** k for j in range(4))
+        am = rk.AM4[0] * F(1) ** k + sum(rk.AM4[j + 1] * F(-j) ** k for j in range(3))
+        assert ab == exact and am == exact
+    assert sum(rk.RK4_B) == 1
+
+
+def test_abm4_exact_for_cubic_right_hand_sides():
+    # y' = 1 + 2t - 3t^2 + 4t^3: the RK4 start (Simpson for y-independent f) and AB4/AM4 are
+    # exact, including a shortened last step
+    f = lambda t, y: np.array([1 + 2 * t - 3 * t * t + 4 * t ** 3])
+    st = rk.Abm4(f, [0.5], h0=0.1, max_steps=1000)
+    assert st.advance(1.95) == "ok"
+    T = 1.95
+    assert abs(st.y[0] - (0.5 + T + T * T - T ** 3 + T ** 4)) <= 1e-13
+    assert st.accepted == 20 and st.t == T
+
+
+def _abm_error(h):
+    st = rk.Abm4(lambda t, y: y * math.cos(t), [1.0], h0=h, max_steps=10 ** 6)
+    assert st.advance(2.0) == "ok"
+    return abs(st.y[0] - math.exp(math.sin(2.0)))
+
+
+def test_abm4_global_error_is_fourth_order():
+    e1, e2, e3 = _abm_error(0.1), _abm_error(0.05), _abm_error(0.025)
+    assert 11 < e1 / e2 < 22 and 11 < e2 / e3 < 22
+
+
+def test_abm4_evaluation_count():
+    # three RK4 start steps (the first evaluates f at t0 as well), then two evaluations per step
+    st = rk.Abm4(lambda t, y: -y, [1.0], h0=0.1, max_steps=100)
+    st.advance(1.0)
+    assert st.accepted == 10 and st.evals == 1 + 3 * 4 + 7 * 2
