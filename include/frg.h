@@ -326,6 +326,13 @@ typedef struct {
     double h_min, h_max;      /* 0 < h_min <= h_max */
     int max_steps;            /* attempted steps per frg_stepper_advance call, >= 1 */
     int fixed_step;           /* 1: steps of exactly h0, no error control */
+    int method;               /* 0: Dormand-Prince 5(4) as above; 1: Adams-Bashforth-Moulton 4
+                                 in PECE mode (predict with AB4, evaluate, correct with AM4,
+                                 evaluate; Sec. 5.2 names the ABM class) with steps of exactly
+                                 h0 and no error control (fixed_step, rtol and atol are not
+                                 used, but still checked); the
+                                 first three steps, and a last step shortened to end at t_end
+                                 (after which the history restarts), are classical RK4 steps */
 } frg_stepper_config;
 
 typedef struct {

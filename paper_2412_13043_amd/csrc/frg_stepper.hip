@@ -95,6 +95,10 @@ struct frg_stepper {
     double *err_host = nullptr;
     double *K[7] = {};
     double *ytmp = nullptr, *ynew = nullptr;
+    // Adams-Bashforth-Moulton: f_n, f_{n-1}, f_{n-2}, f_{n-3} (in K[0..3], rotated) and how many
+    // of them are valid
+    double *F[4] = {};
+    int hist = 0;
     double t = 0.0, h = 0.0, last_err = 0.0;
     bool fsal = false;     // K[0] holds RHS(t, state)
     bool rejected_last = false;
@@ -161,6 +165,79 @@ hipError_t combine(int n, const double *y, double h, const double *const *K, con
     return hipGetLastError();
 }
 
+// Adams-Bashforth (order 4) predictor and Adams-Moulton (order 4) corrector weights over the
+// history f_n, f_{n-1}, ... (the corrector's first weight is that of f at the predicted point),
+// and the classical RK4 stage nodes and weights of the start.
+constexpr double kAB4[4] = {55.0 / 24.0, -59.0 / 24.0, 37.0 / 24.0, -9.0 / 24.0};
+constexpr double kAM4[4] = {9.0 / 24.0, 19.0 / 24.0, -5.0 / 24.0, 1.0 / 24.0};
+constexpr double kRK4B[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+
+// One classical RK4 step of size h from (t, y) with k1 = F[0] into ynew (stages in K[4..6]).
+frg_status rk4_step(frg_stepper *S, double h, const double *y, hipStream_t s) {
+    const int n = S->n;
+    const double half = 0.5, one = 1.0;
+    double *k[4] = {S->F[0], S->K[4], S->K[5], S->K[6]};
+    frg_status st;
+    for (int j = 1; j < 4; ++j) {
+        const double *prev[1] = {k[j - 1]};
+        FRG_HIP_CHECK(combine(n, y, h, prev, j < 3 ? &half : &one, 1, S->ytmp, s));
+        if ((st = stepper_rhs(S, S->t + (j < 3 ? 0.5 : 1.0) * h, S->ytmp, k[j], s)) != FRG_OK)
+            return st;
+    }
+    FRG_HIP_CHECK(combine(n, y, h, (const double *const *)k, kRK4B, 4, S->ynew, s));
+    return FRG_OK;
+}
+
+// Fixed-step Adams-Bashforth-Moulton 4 in PECE mode (steps of h0; RK4 start and shortened
+// last step, after which the history restarts).
+frg_status abm_advance(frg_stepper *S, double t_end, hipStream_t s, int *attempts_out) {
+    const frg_stepper_config &c = S->cfg;
+    const int n = S->n;
+    double *y = const_cast<double *>(S->state.state);
+    int attempts = 0;
+    frg_status st;
+    while (S->t < t_end) {
+        if (attempts >= c.max_steps) {
+            set_error("max_steps (%d) attempted before t_end", c.max_steps);
+            *attempts_out = attempts;
+            return FRG_E_TIMEOUT;
+        }
+        ++attempts;
+        double h = c.h0;
+        const bool last = S->t + h >= t_end * (1.0 - 1e-14) - 1e-300;
+        if (last) h = t_end - S->t;
+        const bool shortened = last && h < c.h0 * (1.0 - 1e-9);
+        std::lock_guard<std::mutex> lk(S->ctx->mu);
+        if (S->hist == 0) {
+            if ((st = stepper_rhs(S, S->t, y, S->F[0], s)) != FRG_OK) return st;
+            S->hist = 1;
+        }
+        if (shortened || S->hist < 4) {
+            if ((st = rk4_step(S, h, y, s)) != FRG_OK) return st;
+        } else {
+            FRG_HIP_CHECK(combine(n, y, h, (const double *const *)S->F, kAB4, 4, S->ytmp, s));
+            if ((st = stepper_rhs(S, S->t + h, S->ytmp, S->K[4], s)) != FRG_OK) return st;
+            const double *corr[4] = {S->K[4], S->F[0], S->F[1], S->F[2]};
+            FRG_HIP_CHECK(combine(n, y, h, corr, kAM4, 4, S->ynew, s));
+        }
+        FRG_HIP_CHECK(hipMemcpyAsync(y, S->ynew, (size_t)n * sizeof(double),
+                                     hipMemcpyDeviceToDevice, s));
+        S->t = last ? t_end : S->t + h;
+        if (shortened) {
+            S->hist = 0;  // the history was taken at step h0
+        } else {
+            double *oldest = S->F[3];
+            for (int j = 3; j > 0; --j) S->F[j] = S->F[j - 1];
+            S->F[0] = oldest;
+        }
+        if ((st = stepper_rhs(S, S->t, y, S->F[0], s)) != FRG_OK) return st;
+        S->hist = std::min(S->hist + 1, 4);
+        ++S->accepted;
+    }
+    *attempts_out = attempts;
+    return FRG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -177,9 +254,9 @@ frg_status frg_stepper_create(frg_context *ctx, const frg_integral_desc *desc,
     if (!(c.rtol > 0.0) || !(c.atol > 0.0) || !(c.h0 > 0.0) || !(c.h_min > 0.0) ||
         !(c.h_max >= c.h_min) || !std::isfinite(c.h_max) || !std::isfinite(c.rtol) ||
         !std::isfinite(c.atol) || !std::isfinite(c.h0) || c.max_steps < 1 ||
-        (c.fixed_step != 0 && c.fixed_step != 1)) {
+        (c.fixed_step != 0 && c.fixed_step != 1) || (c.method != 0 && c.method != 1)) {
         set_error("stepper config needs rtol, atol, h0 > 0, 0 < h_min <= h_max (finite), "
-                  "max_steps >= 1, fixed_step 0 or 1");
+                  "max_steps >= 1, fixed_step 0 or 1, method 0 or 1");
         return FRG_E_INVAL;
     }
     if (state->family != desc->family) {
@@ -231,6 +308,7 @@ frg_status frg_stepper_create(frg_context *ctx, const frg_integral_desc *desc,
     FRG_HIP_CHECK(S->stages.alloc((size_t)9 * n * sizeof(double)));
     double *base = (double *)S->stages.ptr;
     for (int j = 0; j < 7; ++j) S->K[j] = base + (size_t)j * n;
+    for (int j = 0; j < 4; ++j) S->F[j] = S->K[j];
     S->ytmp = base + (size_t)7 * n;
     S->ynew = base + (size_t)8 * n;
     FRG_HIP_CHECK(S->contrib.alloc(std::max<size_t>(contrib_doubles(r), 1) * sizeof(double)));
@@ -269,7 +347,8 @@ frg_status frg_stepper_advance(frg_stepper *S, double t_end, hipStream_t s,
         std::lock_guard<std::mutex> lk(S->ctx->mu);
         FRG_HIP_CHECK(hipSetDevice(S->ctx->device));
     }
-    while (S->t < t_end) {
+    if (c.method == 1) res = abm_advance(S, t_end, s, &attempts);
+    while (c.method == 0 && S->t < t_end) {
         if (attempts >= c.max_steps) {
             set_error("max_steps (%d) attempted before t_end", c.max_steps);
             res = FRG_E_TIMEOUT;

@@ -90,7 +90,7 @@ class frg_stats(ctypes.Structure):
 
 class frg_stepper_config(ctypes.Structure):
     _fields_ = [("rtol", c_double), ("atol", c_double), ("h0", c_double), ("h_min", c_double),
-                ("h_max", c_double), ("max_steps", c_int), ("fixed_step", c_int)]
+                ("h_max", c_double), ("max_steps", c_int), ("fixed_step", c_int), ("method", c_int)]
 
 
 class frg_stepper_stats(ctypes.Structure):
@@ -375,23 +375,25 @@ class Context:
 
     def stepper(self, desc, state, grid, *, Z=None, x_min=1e-3, x_max=1e3, n_comp=4,
                 m2_floor=-0.9, coef=1.0, rtol=1e-8, atol=1e-10, h0=1e-2, h_min=1e-10,
-                h_max=1.0, max_steps=100000, fixed_step=False):
-        """An adaptive Dormand-Prince 5(4) stepper evolving `state` (device tensor) in place.
-        state, grid and Z must stay alive while the stepper is used."""
+                h_max=1.0, max_steps=100000, fixed_step=False, method=0):
+        """A flow stepper evolving `state` (device tensor) in place: method 0 the adaptive
+        Dormand-Prince 5(4) (or fixed steps), method 1 the fixed-step Adams-Bashforth-Moulton 4
+        PECE.  state, grid and Z must stay alive while the stepper is used."""
         return Stepper(self, desc, state, grid, Z=Z, x_min=x_min, x_max=x_max, n_comp=n_comp,
                        m2_floor=m2_floor, coef=coef, rtol=rtol, atol=atol, h0=h0, h_min=h_min,
-                       h_max=h_max, max_steps=max_steps, fixed_step=fixed_step)
+                       h_max=h_max, max_steps=max_steps, fixed_step=fixed_step, method=method)
 
 
 class Stepper:
     """frg_stepper: integrates the flow of frg_flow_rhs in RG time t = log(Lambda/k)."""
 
     def __init__(self, ctx, desc, state, grid, *, Z, x_min, x_max, n_comp, m2_floor, coef, rtol,
-                 atol, h0, h_min, h_max, max_steps, fixed_step):
+                 atol, h0, h_min, h_max, max_steps, fixed_step, method=0):
         zt = frg_log_table(_dptr(Z), 0 if Z is None else int(Z.numel()), x_min, x_max)
         fs = frg_flow_state(desc.family, int(state.numel()), _dptr(state), _dptr(grid), zt,
                             n_comp, m2_floor, coef)
-        cfg = frg_stepper_config(rtol, atol, h0, h_min, h_max, max_steps, 1 if fixed_step else 0)
+        cfg = frg_stepper_config(rtol, atol, h0, h_min, h_max, max_steps, 1 if fixed_step else 0,
+                                 method)
         self._keep = (state, grid, Z)
         self.handle = frg_stepper_create(ctx.handle, desc, fs, cfg)
 

@@ -125,6 +125,51 @@ def test_finite_temperature_lpa_stepper_with_k_scaled_frequencies(env):
     st.close()
 
 
+def test_abm4_stepper_matches_oracle(env):
+    # Adams-Bashforth-Moulton 4 PECE, steps of h0: RK4 start, then two right-hand sides per
+    # step; the second call ends with a shortened RK4 step and restarts the history
+    frg, ctx, torch = env
+    rho = wl.lpa_rho_grid()
+    u0 = 0.3 + rho
+    desc = frg.make_desc(frg.FRG_FAMILY_LPA, wl.LPA_NQ, wl.LPA_QMAX, k=1.0)
+    state, grid = _d(torch, u0), _d(torch, rho)
+    st = ctx.stepper(desc, state, grid, n_comp=4, m2_floor=-0.9, h0=0.05, max_steps=10000,
+                     method=1)
+    ref = rk.Abm4(_lpa_rhs(rho, wl.LPA_NQ, wl.LPA_QMAX, 1.0, 4, -0.9), u0, h0=0.05,
+                  max_steps=10000)
+    for t_end in (0.4, 1.23, 1.5):
+        rc, stats = st.advance(t_end)
+        assert ref.advance(t_end) == "ok"
+        assert stats.t == t_end and stats.accepted == ref.accepted
+        assert stats.rhs_evals == ref.evals and stats.rejected == 0
+        assert _close(state.cpu().numpy(), ref.y, 1e-10), t_end
+    st.close()
+    # two-point vertex flow
+    rng = np.random.default_rng(21)
+    p = 10 ** rng.uniform(-2, 1, 40)
+    Z = wl.dressing_table(8)
+    m0 = rng.uniform(0.2, 1.5, 40)
+    d2 = frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 16, 10.0, n_x=8, k=2.0)
+    state, tp, tZ = _d(torch, m0), _d(torch, p), _d(torch, Z)
+    st = ctx.stepper(d2, state, tp, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, m2_floor=-0.5,
+                     coef=-3.0, h0=0.1, max_steps=1000, method=1)
+
+    def f(t, m):
+        k = 2.0 * math.exp(-t)
+        return -3.0 * oracle.integrate(2, 16, 10.0, n_x=8, k=k, ext=p,
+                                       m2=np.maximum(m, -0.5 * (k / 2.0) ** 2), Z=Z)
+
+    ref = rk.Abm4(f, m0, h0=0.1, max_steps=1000)
+    rc, stats = st.advance(0.95)
+    assert ref.advance(0.95) == "ok"
+    assert stats.rhs_evals == ref.evals
+    assert np.max(np.abs(state.cpu().numpy() - ref.y) / np.abs(ref.y)) <= 1e-11
+    st.close()
+    with pytest.raises(frg.FrgError) as ei:
+        ctx.stepper(desc, _d(torch, u0), grid, h0=0.05, method=2)
+    assert ei.value.status == frg.FRG_E_INVAL
+
+
 def test_stepper_limits_and_errors(env):
     frg, ctx, torch = env
     rho = wl.lpa_rho_grid()
