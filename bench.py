@@ -444,12 +444,13 @@ def two_point_ft_setup(torch, frg, wl, B=16):
 
 
 STEPPER_CFG = dict(rtol=1e-8, atol=1e-10, h0=0.05, h_min=1e-8, h_max=0.5, max_steps=100000)
-STEPPER_T_END = {"lpa": 3.0, "two_point": 1.0}
+STEPPER_T_END = {"lpa": 3.0, "lpa_abm4": 3.0, "two_point": 1.0}
 
 
 def stepper_bench(torch, frg, wl, ctx):
     """Whole flows integrated by the device stepper: the O(4) LPA flow (64 rho points, GL32) from
-    k = Lambda to k = Lambda e^-3, and a two-point vertex flow (256 momenta, 64x32 nodes, state
+    k = Lambda to k = Lambda e^-3 (adaptive Dormand-Prince, and fixed-step ABM4 with h = 0.05),
+    and a two-point vertex flow (256 momenta, 64x32 nodes, state
     m2 per momentum, dstate/dt = -I) from k = Lambda to Lambda e^-1."""
     res = {}
     rho = wl.lpa_rho_grid()
@@ -463,6 +464,11 @@ def stepper_bench(torch, frg, wl, ctx):
         if kind == "lpa":
             state = _dev(torch, 0.3 + rho)
             st = ctx.stepper(d1, state, grid, n_comp=4, m2_floor=-0.9, **STEPPER_CFG)
+        elif kind == "lpa_abm4":
+            # the fixed-step Adams-Bashforth-Moulton 4 PECE over the same flow, h = 0.05
+            state = _dev(torch, 0.3 + rho)
+            st = ctx.stepper(d1, state, grid, n_comp=4, m2_floor=-0.9, h0=0.05, max_steps=10000,
+                             method=1)
         else:
             state = torch.full((p.size,), m2, dtype=torch.float64, device="cuda")
             st = ctx.stepper(d2, state, tp, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
@@ -474,7 +480,7 @@ def stepper_bench(torch, frg, wl, ctx):
         st.close()
         return el, s
 
-    for kind in ("lpa", "two_point"):
+    for kind in ("lpa", "lpa_abm4", "two_point"):
         run(kind)  # plans and rules
         el, s = run(kind)
         attempts = s.accepted + s.rejected
