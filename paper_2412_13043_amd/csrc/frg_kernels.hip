@@ -1405,10 +1405,13 @@ hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg, int 
 // entry).  A row's runs have distinct cells, so each run's parts land in their own slots of the
 // slice (upper part at entry cell, lower part at entry cell - 1), and the owner of entry j takes,
 // row by row, its upper slot, its lower slot and the row's single-cell terms (radial leg; FAM 3
-// also the first inner leg).  Every entry's sum has one fixed order and no atomics.
+// also the first inner leg).  A workgroup holds up to kDzWaves wavefronts sharing the staged
+// tables; each takes a contiguous share of the rows, and their sums are combined in wavefront
+// order.  Every entry's sum has one fixed order and no atomics.
 
-// node terms of one round held in LDS: at least 256 and at least one row; rows per round
-__host__ __device__ __forceinline__ int dz_entries(int n_in) { return n_in > 256 ? n_in : 256; }
+// node terms of one wavefront's round held in LDS: at least 128 and at least one row; rows per
+// round
+__host__ __device__ __forceinline__ int dz_entries(int n_in) { return n_in > 128 ? n_in : 128; }
 __host__ __device__ __forceinline__ int dz_rows(int n_in) {
     const int r = dz_entries(n_in) / n_in;
     return r < 1 ? 1 : (r > kWave ? kWave : r);
@@ -1424,11 +1427,17 @@ __device__ __forceinline__ double dz_weight(int iz, double f, int j, int nZ) {
 constexpr int kDzRowD = 11;  // per-row double arrays
 constexpr int kDzRowI = 3;   // per-row int arrays
 
-size_t dz_lds_bytes(int nZ, int n_in) {
-    const size_t E = (size_t)dz_entries(n_in);
-    return (size_t)(kLogTable + nZ + 1) * sizeof(double2) + 3 * E * sizeof(double) +
-           kDzRowD * kWave * sizeof(double) + 2 * (size_t)dz_rows(n_in) * kWave * sizeof(double) +
-           E * sizeof(int) + kDzRowI * kWave * sizeof(int);
+constexpr int kDzWaves = 4;  // wavefronts per workgroup (at most), each with a share of the rows
+
+// LDS of one wavefront's round buffers (16-byte multiple), then of the whole workgroup
+__host__ __device__ __forceinline__ size_t dz_wave_bytes(int n_in) {
+    const size_t E = (size_t)dz_entries(n_in), R = (size_t)dz_rows(n_in);
+    const size_t b = 3 * E * sizeof(double) + kDzRowD * R * sizeof(double) +
+                     2 * R * kWave * sizeof(double) + E * sizeof(int) + kDzRowI * R * sizeof(int);
+    return (b + 15) / 16 * 16;
+}
+size_t dz_lds_bytes(int nZ, int n_in, int waves) {
+    return (size_t)(kLogTable + nZ + 1) * sizeof(double2) + waves * dz_wave_bytes(n_in);
 }
 
 // Padded cell index and fraction of the dressing coordinate s + 1 = za log(v) + zb1.
@@ -1438,41 +1447,46 @@ __device__ __forceinline__ void dz_cell(const Smem &sm, int nZ, double za, doubl
 }
 
 template <int FAM, int REG>
-__global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ jac) {
+__global__ void __launch_bounds__(64 * kDzWaves) dz_kernel(ReqDev r, double *__restrict__ jac) {
     extern __shared__ double2 lds_dyn[];
     __shared__ float zslope;
+    __shared__ double part[kDzWaves][kWave];  // each wavefront's sums, combined in wave order
     Smem sm;
-    const int nZ = r.nZ, lane = (int)threadIdx.x, e = (int)blockIdx.x;
+    const int nZ = r.nZ, e = (int)blockIdx.x;
+    const int lane = (int)threadIdx.x & (kWave - 1), wv = (int)threadIdx.x / kWave;
+    const int nw = (int)blockDim.x / kWave;  // wavefronts of this launch (1..kDzWaves)
     const int j = (int)blockIdx.y * kWave + lane;  // the entry this lane owns
     const int n_in = FAM == 3 ? r.n_phi : r.n_x;    // nodes per row
     const long long n_rows = FAM == 3 ? (long long)r.n_q * r.n_x : r.n_q;
     const int E = dz_entries(n_in);
     bind_smem(sm, lds_dyn, nZ, &zslope);
-    // after the padded table: the round's node arrays (compacted in place into per-cell runs),
-    // then its per-row arrays
-    double *nv = (double *)(lds_dyn + kLogTable + nZ + 1);  // node term, then run's lower part
+    // after the padded table, per wavefront: the round's node arrays (compacted in place into
+    // per-cell runs), then its per-row arrays and the entry slots
+    const int R = dz_rows(n_in);
+    double *nv = (double *)((char *)(lds_dyn + kLogTable + nZ + 1) + wv * dz_wave_bytes(n_in));
     double *nf = nv + E;            // node cell fraction, then run's upper part
     double *xg = nf + E;            // w G^(node), for the row's inner sum
     double *rw = xg + E;            // row factor of the node terms
-    double *rwg = rw + kWave;       // W G(q^2)^2
-    double *rg = rwg + kWave;       // G(q^2)
-    double *rq2 = rg + kWave;       // q^2
-    double *rc0 = rq2 + kWave;      // node argument = rc1 * (x or cos phi) + rc0 (units of k^2)
-    double *rc1 = rc0 + kWave;
-    double *rm = rc1 + kWave;       // inner mass term / k^2
-    double *rf = rm + kWave;        // radial-leg cell fraction
-    double *rv = rf + kWave;        // radial-leg term of the row
-    double *r1f = rv + kWave;       // FAM 3: first inner leg's cell fraction
-    double *r1v = r1f + kWave;      // FAM 3: first inner leg's term of the row
-    const int R = dz_rows(n_in);
-    double *hs = r1v + kWave;       // [R][64] upper parts by entry slot of this slice
+    double *rwg = rw + R;           // W G(q^2)^2
+    double *rg = rwg + R;           // G(q^2)
+    double *rq2 = rg + R;           // q^2
+    double *rc0 = rq2 + R;          // node argument = rc1 * (x or cos phi) + rc0 (units of k^2)
+    double *rc1 = rc0 + R;
+    double *rm = rc1 + R;           // inner mass term / k^2
+    double *rf = rm + R;            // radial-leg cell fraction
+    double *rv = rf + R;            // radial-leg term of the row
+    double *r1f = rv + R;           // FAM 3: first inner leg's cell fraction
+    double *r1v = r1f + R;          // FAM 3: first inner leg's term of the row
+    double *hs = r1v + R;           // [R][64] upper parts by entry slot of this slice
     double *ls = hs + R * kWave;    // [R][64] lower parts by entry slot
     int *niz = (int *)(ls + R * kWave);  // node padded cell index, then run's cell
     int *riz = niz + E;             // radial-leg padded cell index
-    int *r1iz = riz + kWave;        // FAM 3: first inner leg's padded cell index
-    int *nrun = r1iz + kWave;       // runs per row
-    stage_log(sm, r.logt);
-    stage_dressing(r, sm);
+    int *r1iz = riz + R;            // FAM 3: first inner leg's padded cell index
+    int *nrun = r1iz + R;           // runs per row
+    if (wv == 0) {
+        stage_log(sm, r.logt);
+        stage_dressing(r, sm);
+    }
     __syncthreads();
     const double p = fabs(r.ext[e]);
     double ca = 1.0, sa = 0.0, p0 = 0.0;
@@ -1486,9 +1500,15 @@ __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ j
     const double uf = FAM == 3 ? inv_k2 * inv_k2 : inv_k2;  // units of the inner sums
     const double zb1 = r.zbk + 1.0;
     const int j0 = (int)blockIdx.y * kWave;
+    // wavefront wv takes rows [lo, hi); every wavefront runs the same number of rounds (the
+    // barriers are the workgroup's), a finished one with no rows
+    const long long lo = n_rows * wv / nw, hi = n_rows * (wv + 1) / nw;
+    const long long span = (n_rows + nw - 1) / nw;
+    const long long rounds = (span + R - 1) / R;
     double s = 0.0;
-    for (long long r0 = 0; r0 < n_rows; r0 += R) {
-        const int nr = (int)min((long long)R, n_rows - r0);
+    for (long long it = 0; it < rounds; ++it) {
+        const long long r0 = lo + it * R;
+        const int nr = (int)max(0LL, min((long long)R, hi - r0));
         if (lane < nr) {
             const long long row = r0 + lane;
             const int a = FAM == 3 ? (int)(row / r.n_x) : (int)row;
@@ -1636,7 +1656,13 @@ __global__ void __launch_bounds__(64) dz_kernel(ReqDev r, double *__restrict__ j
         }
         __syncthreads();
     }
-    if (j < nZ) jac[(long long)e * nZ + j] = r.pref * s;
+    part[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && j < nZ) {
+        double t = part[0][lane];
+        for (int w = 1; w < nw; ++w) t += part[w][lane];
+        jac[(long long)e * nZ + j] = r.pref * t;
+    }
 }
 
 template <int FAM>
@@ -1654,8 +1680,17 @@ hipError_t launch_dz(const ReqDev &r, double *jac, hipStream_t s) {
                                                    : dz_for_reg<2>(r.reg);
     const int slices = (r.nZ + kWave - 1) / kWave;
     const int n_in = r.family == 3 ? r.n_phi : r.n_x;
-    hipLaunchKernelGGL(fn, dim3(r.n_ext, slices), dim3(kWave), dz_lds_bytes(r.nZ, n_in), s, r,
-                       jac);
+    // as many wavefronts (up to kDzWaves) as the workgroup's LDS allows
+    int dev = 0, max_lds = 65536;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess)
+        return hipGetLastError();
+    int waves = kDzWaves;
+    const size_t fixed = sizeof(double) * kDzWaves * kWave + 16;  // static LDS of the kernel
+    while (waves > 1 && dz_lds_bytes(r.nZ, n_in, waves) + fixed > (size_t)max_lds) --waves;
+    hipLaunchKernelGGL(fn, dim3(r.n_ext, slices), dim3(kWave * waves),
+                       dz_lds_bytes(r.nZ, n_in, waves), s, r, jac);
     return hipGetLastError();
 }
 
