@@ -1427,7 +1427,7 @@ __device__ __forceinline__ double dz_weight(int iz, double f, int j, int nZ) {
 constexpr int kDzRowD = 11;  // per-row double arrays
 constexpr int kDzRowI = 3;   // per-row int arrays
 
-constexpr int kDzWaves = 4;  // wavefronts per workgroup (at most), each with a share of the rows
+constexpr int kDzWaves = 8;  // wavefronts per workgroup (at most), each with a share of the rows
 
 // LDS of one wavefront's round buffers (16-byte multiple), then of the whole workgroup
 __host__ __device__ __forceinline__ size_t dz_wave_bytes(int n_in) {
@@ -1680,13 +1680,14 @@ hipError_t launch_dz(const ReqDev &r, double *jac, hipStream_t s) {
                                                    : dz_for_reg<2>(r.reg);
     const int slices = (r.nZ + kWave - 1) / kWave;
     const int n_in = r.family == 3 ? r.n_phi : r.n_x;
-    // as many wavefronts (up to kDzWaves) as the workgroup's LDS allows
+    // as many wavefronts as the workgroup's LDS allows, up to 8 for the two-point families and 4
+    // for the three-point one (measured: its many short rows gain nothing from more)
     int dev = 0, max_lds = 65536;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
             hipSuccess)
         return hipGetLastError();
-    int waves = kDzWaves;
+    int waves = r.family == 3 ? 4 : kDzWaves;
     const size_t fixed = sizeof(double) * kDzWaves * kWave + 16;  // static LDS of the kernel
     while (waves > 1 && dz_lds_bytes(r.nZ, n_in, waves) + fixed > (size_t)max_lds) --waves;
     hipLaunchKernelGGL(fn, dim3(r.n_ext, slices), dim3(kWave * waves),
