@@ -170,6 +170,25 @@ def test_abm4_stepper_matches_oracle(env):
     assert ei.value.status == frg.FRG_E_INVAL
 
 
+def test_abm4_finite_temperature_lpa_flow(env):
+    # ABM4 on the finite-temperature LPA flow with a k-scaled frequency domain (the frequency
+    # count changes during the run) against the oracle's ABM4 on the oracle's right-hand side
+    frg, ctx, torch = env
+    rho = wl.lpa_rho_grid(32)
+    u0 = 0.4 + 0.8 * rho
+    ft = dict(T=0.12, freq_max=6.0, freq_scaled=True, statistics=0, n_tail=4)
+    desc = frg.make_desc(frg.FRG_FAMILY_LPA_T, 24, 6.0, k=1.0, **ft)
+    state, grid = _d(torch, u0), _d(torch, rho)
+    st = ctx.stepper(desc, state, grid, n_comp=4, m2_floor=-0.9, h0=0.04, max_steps=10000,
+                     method=1)
+    ref = rk.Abm4(_lpa_rhs(rho, 24, 6.0, 1.0, 4, -0.9, ft=ft), u0, h0=0.04, max_steps=10000)
+    rc, stats = st.advance(0.9)
+    assert ref.advance(0.9) == "ok"
+    assert (stats.accepted, stats.rhs_evals) == (ref.accepted, ref.evals)
+    assert _close(state.cpu().numpy(), ref.y, 1e-10)
+    st.close()
+
+
 def test_stepper_limits_and_errors(env):
     frg, ctx, torch = env
     rho = wl.lpa_rho_grid()
