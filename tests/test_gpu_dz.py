@@ -140,6 +140,44 @@ def test_dz_two_point_workload_full_size(env):
     _check(got, ref)
 
 
+def test_dz_full_size_three_point_and_finite_temperature_sampled(env):
+    # one right-hand side of the three-point workload (1024 points x 64 x 32 x 16) and of the
+    # finite-temperature workload (256 momenta x 47 frequencies x 64 x 32), every point on the
+    # GPU, a sample of points through the oracle
+    frg, ctx, torch = env
+    rng = np.random.default_rng(17)
+    P, A, m3, Z3 = wl.three_point()
+    n = P.size
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    jac = torch.full((n * Z3.size,), float("nan"), dtype=torch.float64, device="cuda")
+    d3 = frg.make_desc(frg.FRG_FAMILY_THREE_POINT, wl.THREE_NQ, wl.THREE_QMAX, n_x=wl.THREE_NX,
+                       n_phi=wl.THREE_NPHI)
+    ctx.integrate(d3, out, ext=_d(torch, np.concatenate([P, A])), m2=_d(torch, m3),
+                  Z=_d(torch, Z3), x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, dz=jac)
+    torch.cuda.synchronize()
+    J = jac.cpu().numpy().reshape(n, Z3.size)
+    idx = np.sort(rng.choice(n, 24, replace=False))
+    ref = oracle.integrate_dz_three(wl.THREE_NQ, wl.THREE_QMAX, n_x=wl.THREE_NX,
+                                    n_phi=wl.THREE_NPHI, ext=(P[idx], A[idx]), m2=m3[idx], Z=Z3,
+                                    x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)
+    _check(J[idx], ref)
+    p = wl.momenta_log()
+    p0 = np.where(np.arange(p.size) % 2 == 0, 0.0, 2 * math.pi * wl.FT_T)
+    Z = wl.dressing_table(1000)
+    ft = dict(T=wl.FT_T, freq_max=wl.FT_FREQ_MAX, statistics=0, n_tail=wl.FT_N_TAIL)
+    dft = frg.make_desc(frg.FRG_FAMILY_TWO_POINT_T, wl.FT_NQ, wl.FT_QMAX, n_x=wl.FT_NX, **ft)
+    out = torch.empty(p.size, dtype=torch.float64, device="cuda")
+    jac = torch.full((p.size * Z.size,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.integrate(dft, out, ext=_d(torch, np.concatenate([p, p0])), m2_scalar=0.5,
+                  Z=_d(torch, Z), x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, dz=jac)
+    torch.cuda.synchronize()
+    J = jac.cpu().numpy().reshape(p.size, Z.size)
+    idx = np.sort(rng.choice(p.size, 16, replace=False))
+    ref = oracle.integrate_ft_dz(wl.FT_NQ, wl.FT_QMAX, n_x=wl.FT_NX, ext=(p[idx], p0[idx]),
+                                 m2_scalar=0.5, Z=Z, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, **ft)
+    _check(J[idx], ref)
+
+
 def test_dz_largest_table_and_rule(env):
     # the largest dressing table (4096 entries, 135 KB of LDS) and the largest cos1 rule (1024
     # nodes: one radial node per round)
