@@ -243,6 +243,23 @@ frg_status frg_integrate_batch(frg_context *ctx, const frg_integral_desc *desc,
 frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc *descs,
                                const frg_batch *batches, hipStream_t stream);
 
+/* Static scratch of frg_integrate_batch_noalloc, per device (bytes). */
+#define FRG_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  The same computation, arguments, errors and results
+ * (bit for bit) as frg_integrate_batch, but no device memory is allocated or freed by the call:
+ * the scratch it needs -- the descriptor's quadrature rules if the context has not cached them
+ * yet (an earlier frg_integrate_batch with the same rule parameters caches them), the radial
+ * contributions of radially chunked requests and the float32 form's amplification slots -- lives
+ * in one static device array of FRG_NOALLOC_SCRATCH_BYTES per device, held until the process
+ * ends.  A request needing more returns FRG_E_NOMEM (nothing enqueued).  The array is shared by
+ * every call on the device and keeps the last call's contents (the call clears what must start
+ * at zero): calls whose work may overlap on one device -- different streams, or host threads
+ * without ordering between them -- race on it and must not be issued. */
+frg_status frg_integrate_batch_noalloc(frg_context *ctx, const frg_integral_desc *desc,
+                                       const frg_batch *batch, hipStream_t stream);
+
 /* Pick the tile shape (lanes per external point over radial nodes and over cos1 nodes; radial
  * chunks per external tile) of frg_integrate_batch and
  * frg_flow_rhs for this descriptor and batch size by timing the candidate shapes on the given

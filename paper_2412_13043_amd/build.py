@@ -21,6 +21,7 @@ SOURCES = [
     ("frg_kernels.hip", True),
     ("frg_stepper.hip", True),
     ("frg_threshold.hip", True),
+    ("frg_noalloc.hip", True),
     ("frg_runtime.cpp", False),
     ("frg_session.cpp", False),
 ]

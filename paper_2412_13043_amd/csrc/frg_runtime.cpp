@@ -297,7 +297,7 @@ size_t ft_rule_bytes(int n_q, int n_f) {
 }
 
 frg_status ft_rule_into(frg_context *ctx, const frg_integral_desc &d, void *buf, size_t bytes,
-                        RadialRule *out, hipStream_t s) {
+                        RadialRule *out, hipStream_t s, const RadialRule *base_rule) {
     FreqRule f;
     frg_status st = freq_rule(d, &f);
     if (st != FRG_OK) return st;
@@ -306,7 +306,10 @@ frg_status ft_rule_into(frg_context *ctx, const frg_integral_desc &d, void *buf,
         return FRG_E_INVAL;
     }
     RadialRule base;
-    if ((st = get_radial(ctx, d.n_q, d.q_max, 3, d.regulator, reg_order(d), &base)) != FRG_OK)
+    if (base_rule)
+        base = *base_rule;
+    else if ((st = get_radial(ctx, d.n_q, d.q_max, 3, d.regulator, reg_order(d), &base)) !=
+             FRG_OK)
         return st;
     const size_t n = (size_t)d.n_q * (size_t)f.n_f;
     double *q = (double *)buf, *W = q + n, *R = W + n, *w0 = R + n;
@@ -351,6 +354,107 @@ static frg_status get_phi(frg_context *ctx, int n, PhiRule *out) {
         it = ctx->phi.emplace(n, std::move(e)).first;
     }
     *out = it->second->rule;
+    return FRG_OK;
+}
+
+static size_t radial_rule_bytes(int n) {
+    return (size_t)n * (3 * sizeof(double) + 3 * sizeof(float)) + 64;
+}
+static size_t cos1_rule_bytes(int n) {
+    return (size_t)n * (3 * sizeof(double) + 3 * sizeof(float)) + 64;
+}
+static size_t phi_rule_bytes(int n) {
+    return (size_t)n * (2 * sizeof(double) + 2 * sizeof(float)) + 64;
+}
+static size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool cached_rules(frg_context *ctx, const frg_integral_desc &d, RadialRule *rad, AngleRule *ang,
+                  PhiRule *phi) {
+    if (is_ft(d.family)) {
+        FreqRule f;
+        if (freq_rule(d, &f) != FRG_OK) return false;
+        auto it = ctx->ft_radial.find(std::make_tuple(d.n_q, d.q_max, d.k, d.T, f.lambda,
+                                                      d.statistics, d.n_tail,
+                                                      d.regulator * 32 + reg_order(d)));
+        if (it == ctx->ft_radial.end()) return false;
+        *rad = it->second->rule;
+    } else {
+        auto it = ctx->radial.find(std::make_tuple(d.n_q, d.q_max, d.d, d.regulator,
+                                                   reg_order(d)));
+        if (it == ctx->radial.end()) return false;
+        *rad = it->second->rule;
+    }
+    if (is_vertex(d.family)) {
+        auto it = ctx->cos1.find(d.n_x + (d.family == FRG_FAMILY_TWO_POINT_T ? (1 << 20) : 0));
+        if (it == ctx->cos1.end()) return false;
+        *ang = it->second->rule;
+    }
+    if (d.family == FRG_FAMILY_THREE_POINT) {
+        auto it = ctx->phi.find(d.n_phi);
+        if (it == ctx->phi.end()) return false;
+        *phi = it->second->rule;
+    }
+    return true;
+}
+
+size_t rules_bytes(const frg_integral_desc &d) {
+    size_t b = up256(radial_rule_bytes(d.n_q));  // vacuum rule (finite temperature: its d = 3 base)
+    if (is_ft(d.family)) {
+        FreqRule f;
+        if (freq_rule(d, &f) != FRG_OK) return 0;
+        b += up256(ft_rule_bytes(d.n_q, f.n_f));
+    }
+    if (is_vertex(d.family)) b += up256(cos1_rule_bytes(d.n_x));
+    if (d.family == FRG_FAMILY_THREE_POINT) b += up256(phi_rule_bytes(d.n_phi));
+    return b;
+}
+
+frg_status rules_into(frg_context *ctx, const frg_integral_desc &d, void *buf, size_t bytes,
+                      RadialRule *rad, AngleRule *ang, PhiRule *phi, hipStream_t s) {
+    if (rules_bytes(d) == 0 || rules_bytes(d) > bytes) {
+        set_error("quadrature-rule buffer too small");
+        return FRG_E_INVAL;
+    }
+    char *p = (char *)buf;
+    // the same kernels, arguments and layouts as the context's cache, so the same bits
+    const int n = d.n_q;
+    const int rd = is_ft(d.family) ? 3 : d.d;
+    double *q = (double *)p, *W = q + n, *R = W + n;
+    float *qf = (float *)(R + n), *Wf = qf + n, *Rf = Wf + n;
+    FRG_HIP_CHECK(launch_rules(n, d.q_max, rd, 0, 0, q, W, R, qf, Wf, Rf, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, s, false, d.regulator, reg_order(d)));
+    RadialRule base{q, W, R, qf, Wf, Rf, nullptr};
+    p += up256(radial_rule_bytes(n));
+    if (is_ft(d.family)) {
+        FreqRule f;
+        frg_status st = freq_rule(d, &f);
+        if (st != FRG_OK) return st;
+        const size_t fb = ft_rule_bytes(d.n_q, f.n_f);
+        if ((st = ft_rule_into(ctx, d, p, fb, rad, s, &base)) != FRG_OK) return st;
+        p += up256(fb);
+    } else {
+        *rad = base;
+    }
+    if (is_vertex(d.family)) {
+        const int m = d.n_x;
+        double *x = (double *)p, *xw = x + m, *xs = xw + m;
+        float *xf = (float *)(xs + m), *xwf = xf + m, *xsf = xwf + m;
+        FRG_HIP_CHECK(launch_rules(0, 1.0, 1, m, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   nullptr, x, xw, xs, xf, xwf, xsf, nullptr, nullptr, nullptr,
+                                   nullptr, s, d.family == FRG_FAMILY_TWO_POINT_T));
+        *ang = AngleRule{x, xw, xs, xf, xwf, xsf};
+        p += up256(cos1_rule_bytes(m));
+    }
+    if (d.family == FRG_FAMILY_THREE_POINT) {
+        const int m = d.n_phi;
+        double *c = (double *)p, *w = c + m;
+        float *cf = (float *)(w + m), *wf = cf + m;
+        FRG_HIP_CHECK(launch_rules(0, 1.0, 1, 0, m, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   c, w, cf, wf, s));
+        *phi = PhiRule{c, w, cf, wf};
+    }
     return FRG_OK;
 }
 
@@ -474,7 +578,8 @@ int lds_bytes_for(const ReqDev &r) {
 
 frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_batch &b,
                         const TileShape &shape, int m2_mode, double m2_floor, double coef,
-                        ReqDev *out, const RadialRule *rad) {
+                        ReqDev *out, const RadialRule *rad, const AngleRule *ang,
+                        const PhiRule *phi) {
     ReqDev r;
     std::memset(&r, 0, sizeof r);
     // kernel family: LPA at finite temperature runs the LPA kernel on the frequency-folded rule
@@ -542,11 +647,17 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
                                           &r.rad);
     if (st != FRG_OK) return st;
     if (vertex) {
-        st = get_cos1(ctx, d.n_x, &r.ang, d.family == FRG_FAMILY_TWO_POINT_T);
+        if (ang)
+            r.ang = *ang;
+        else
+            st = get_cos1(ctx, d.n_x, &r.ang, d.family == FRG_FAMILY_TWO_POINT_T);
         if (st != FRG_OK) return st;
     }
     if (d.family == 3) {
-        st = get_phi(ctx, d.n_phi, &r.phi);
+        if (phi)
+            r.phi = *phi;
+        else
+            st = get_phi(ctx, d.n_phi, &r.phi);
         if (st != FRG_OK) return st;
     }
     r.logt = (const double2 *)ctx->logtab.ptr;
@@ -770,6 +881,9 @@ frg_status frg_context_create(int device, size_t hbm_budget_bytes, frg_context *
     FRG_HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
     ctx->hbm_budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
     FRG_HIP_CHECK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    // device address of the no-allocation entry point's static scratch (once per device)
+    frg_status sst = noalloc_scratch_address(device, &ctx->noalloc_scratch);
+    if (sst != FRG_OK) return sst;
     FRG_HIP_CHECK(ctx->logtab.alloc(kLogTable * sizeof(double2)));
     FRG_HIP_CHECK(launch_log_table((double2 *)ctx->logtab.ptr, ctx->aux));
     {

@@ -151,6 +151,7 @@ struct frg_context {
     bool flow_graphs = false;  // replay flow RHS plans as captured HIP graphs (FRG_FLOW_GRAPH=1)
     std::map<std::vector<int>, frg::TileShape> tuned;  // autotuned shapes (loaded/saved on disk)
     std::string tune_path;
+    void *noalloc_scratch = nullptr;  // this device's static scratch (frg_integrate_batch_noalloc)
 };
 
 namespace frg {
@@ -158,15 +159,31 @@ namespace frg {
 // Validate a descriptor/batch pair; FRG_E_INVAL with a message on failure.
 frg_status validate(const frg_integral_desc *desc, const frg_batch *batch, bool device_ptrs);
 // Fill a ReqDev for a validated request (rules resolved through the context cache).
-// rad (optional) replaces the cached radial rule (a stepper's own finite-temperature rule).
+// rad, ang and phi (optional) replace the cached rules (a stepper's own finite-temperature
+// rule; rules built outside the cache).
 frg_status make_request(frg_context *ctx, const frg_integral_desc &desc, const frg_batch &b,
                         const TileShape &shape, int m2_mode, double m2_floor, double coef,
-                        ReqDev *out, const RadialRule *rad = nullptr);
+                        ReqDev *out, const RadialRule *rad = nullptr,
+                        const AngleRule *ang = nullptr, const PhiRule *phi = nullptr);
 // Finite-temperature radial rule of d written into buf (n_q n_f (4 doubles + 3 floats)), on
-// stream s; *out points into buf.
+// stream s; *out points into buf.  base (optional): the d = 3 vacuum rule it is built from
+// (default: the cached one).
 frg_status ft_rule_into(frg_context *ctx, const frg_integral_desc &d, void *buf, size_t bytes,
-                        RadialRule *out, hipStream_t s);
+                        RadialRule *out, hipStream_t s, const RadialRule *base = nullptr);
 size_t ft_rule_bytes(int n_q, int n_f);
+// Every rule of a descriptor from the context's cache, without building or allocating
+// anything: false if one of them is not cached yet.
+bool cached_rules(frg_context *ctx, const frg_integral_desc &d, RadialRule *rad, AngleRule *ang,
+                  PhiRule *phi);
+// Bytes of every rule of a descriptor laid out by rules_into (0 for an invalid descriptor).
+size_t rules_bytes(const frg_integral_desc &d);
+// Build every rule of a descriptor into caller-owned device memory on stream s, with the kernels
+// and layouts of the cache (identical values); nothing is allocated.
+frg_status rules_into(frg_context *ctx, const frg_integral_desc &d, void *buf, size_t bytes,
+                      RadialRule *rad, AngleRule *ang, PhiRule *phi, hipStream_t s);
+// Device address of the no-allocation entry point's static scratch on `device` (looked up once
+// per device, with that device current).
+frg_status noalloc_scratch_address(int device, void **out);
 // Where a tile shape is used: a request launched alone (radial chunks wherever the heuristic
 // finds them worth a finalize launch), a fused launch (tuned shapes as tuned; the heuristic
 // chunks only two-point requests whose wavefronts hold one point each), or a launch with no

@@ -104,6 +104,8 @@ _sig = {
     "frg_context_destroy": ([_P], c_int),
     "frg_last_error": ([], c_char_p),
     "frg_integrate_batch": ([_P, POINTER(frg_integral_desc), POINTER(frg_batch), _P], c_int),
+    "frg_integrate_batch_noalloc": ([_P, POINTER(frg_integral_desc), POINTER(frg_batch), _P],
+                                    c_int),
     "frg_integrate_multi": ([_P, c_int, POINTER(frg_integral_desc), POINTER(frg_batch), _P],
                             c_int),
     "frg_flow_rhs": ([_P, POINTER(frg_integral_desc), POINTER(frg_flow_state), _P, _P], c_int),
@@ -172,6 +174,12 @@ def litim_threshold(d: int, n: int, w, out, stream=None):
 
 def frg_integrate_batch(ctx: int, desc: frg_integral_desc, batch: frg_batch, stream: int) -> None:
     _check(_lib.frg_integrate_batch(ctx, byref(desc), byref(batch), stream), "frg_integrate_batch")
+
+
+def frg_integrate_batch_noalloc(ctx: int, desc: frg_integral_desc, batch: frg_batch,
+                                stream: int) -> None:
+    _check(_lib.frg_integrate_batch_noalloc(ctx, byref(desc), byref(batch), stream),
+           "frg_integrate_batch_noalloc")
 
 
 def frg_integrate_multi(ctx: int, descs, batches, stream: int) -> None:
@@ -354,6 +362,14 @@ class Context:
         b = make_batch(int(out.numel()), out, ext=ext, m2=m2, m2_scalar=m2_scalar, Z=Z,
                        x_min=x_min, x_max=x_max, err_out=err_out, dout=dout, dz=dz)
         frg_integrate_batch(self.handle, desc, b, _stream(stream))
+        return out
+
+    def integrate_noalloc(self, desc, out, *, ext=None, m2=None, m2_scalar=0.0, Z=None,
+                          x_min=1e-3, x_max=1e3, err_out=None, dout=None, dz=None, stream=None):
+        """frg_integrate_batch_noalloc: as integrate, scratch in the library's static array."""
+        b = make_batch(int(out.numel()), out, ext=ext, m2=m2, m2_scalar=m2_scalar, Z=Z,
+                       x_min=x_min, x_max=x_max, err_out=err_out, dout=dout, dz=dz)
+        frg_integrate_batch_noalloc(self.handle, desc, b, _stream(stream))
         return out
 
     def autotune(self, desc, out, *, ext=None, m2=None, m2_scalar=0.0, Z=None, x_min=1e-3,

@@ -65,6 +65,9 @@ def test_null_context_is_rejected_without_device_work():
     assert st == frg.FRG_E_INVAL
     st = frg.raw_status("frg_integrate_multi", None, 1, None, None, None)
     assert st == frg.FRG_E_INVAL
+    st = frg.raw_status("frg_integrate_batch_noalloc", None, ctypes.byref(desc),
+                        ctypes.byref(b), None)
+    assert st == frg.FRG_E_INVAL
 
 
 def test_context_create_rejects_bad_arguments():
