@@ -293,8 +293,12 @@ def main():
                     help="untimed calls for this long before the warmup steps (clock ramp)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
-    ap.add_argument("--serving-seconds", type=float, default=4.0,
-                    help="measured seconds of the serving loop per offered load")
+    ap.add_argument("--serving-seconds", type=float, default=15.0,
+                    help="measured seconds of the serving replay per offered load and path")
+    ap.add_argument("--serving-warm", type=float, default=2.0,
+                    help="seconds of arrivals excluded at the start of each serving replay")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving measurement (after the timed line)")
     ap.add_argument("--workload", default="two_point_256",
                     choices=["two_point_256", "three_point_8", "lpa_4096", "two_point_ft_16"],
                     help="workload of the timed line (default: the two-point batch); the others "
@@ -368,7 +372,12 @@ def main():
     }
     extra = {}
     if not args.no_extra:
-        extra = secondary(torch, frg, wl, ctx, serving_seconds=args.serving_seconds)
+        if args.serving_only:
+            extra = {"serving": serving(torch, frg, wl, ctx, seconds=args.serving_seconds,
+                                        warm=args.serving_warm)}
+        else:
+            extra = secondary(torch, frg, wl, ctx, serving_seconds=args.serving_seconds,
+                              serving_warm=args.serving_warm)
     if extra:
         res["extra"] = extra
     if not args.no_cpu:
@@ -495,7 +504,7 @@ def stepper_bench(torch, frg, wl, ctx):
 EXTRA_WARM_S = 0.1  # clock warming before each secondary timing
 
 
-def secondary(torch, frg, wl, ctx, serving_seconds=4.0):
+def secondary(torch, frg, wl, ctx, serving_seconds=15.0, serving_warm=2.0):
     """Other workloads, timed the same way (fewer steps, shorter clock warming)."""
     ex = {}
     # LPA batch: 4096 right-hand sides x 64 rho points x GL32
@@ -660,159 +669,164 @@ def secondary(torch, frg, wl, ctx, serving_seconds=4.0):
     log("bench: flow stepper")
     ex["flow_stepper"] = stepper_bench(torch, frg, wl, ctx)
     log("bench: serving")
-    ex["serving"] = serving(torch, frg, wl, ctx, seconds=serving_seconds)
+    ex["serving"] = serving(torch, frg, wl, ctx, seconds=serving_seconds, warm=serving_warm)
     return ex
 
 
-def serving(torch, frg, wl, ctx, n_steppers=200, seconds=4.0, loads=(0.5, 0.8, 0.95),
-            seed=12345):
-    """Workload 5: synthetic RK4 time-steppers submitting right-hand-side requests to a session.
+def serving(torch, frg, wl, ctx, n_steppers=200, seconds=15.0, warm=2.0,
+            loads=(0.5, 0.8, 0.95), seed=12345, max_inflight=4):
+    """Workload 5: right-hand-side requests of 200 synthetic RK4 time-steppers, served by a
+    session and, for comparison, by the plain per-batch float64 path, with one client harness.
 
     Each stepper (workloads.stepper_spec) owns a request shape (family, n_ext, nodes per
-    dimension, float64 or float32) and a state; every RK4 stage submits one request built from the
-    stage state, waits for it, and sleeps an exponential think time before the next, so arrivals
-    are close to Poisson.  The think time is set for an offered load of `load` times the
-    capacity implied by the per-shape service times measured beforehand.  Reported per load:
-    requests, Gnodes/s, p50/p99 latency (submit -> result in the host buffer) overall and per
-    family and precision, and the same arrival trace served FIFO on one stream by the plain
-    per-batch float64 path (one frg_integrate_batch per request, service times measured per
-    shape).
+    dimension, float64 or float32), a dressing table (resident in the session; on the device for
+    the plain path) and four RK4 stage inputs.  The C++ replay harness (frg_serving_replay)
+    takes an open-loop arrival trace: Poisson arrivals, each the next stage request of a
+    uniformly drawn stepper, at a rate set for an offered load of `load` times the session's
+    measured saturation capacity.  The same trace is replayed (a) through the session (submit at
+    the arrival time; completions stamped by waiter threads blocked on the tickets) and (b)
+    through the plain path: first in, first out on one stream, each request's inputs copied to
+    the device, one frg_integrate_batch in float64, the result copied back.  The first `warm`
+    seconds of arrivals are excluded; `seconds` are measured.  Every session result is compared
+    bit for bit with the same request computed alone through frg_integrate_batch (float32
+    requests with the float32 form), every plain-path float64 result as well.
     """
-    import random
+    import ctypes
 
     specs = [wl.stepper_spec(i) for i in range(n_steppers)]
     fam_name = {1: "lpa", 2: "two_point", 3: "three_point"}
 
-    def host_request(sp, state):
+    def stage_inputs(sp, stage):
+        u = sp.state0 * (1.0 + 0.01 * stage)
         if sp.family == 1:
-            g = np.gradient(state, sp.ext)
-            m2 = np.maximum(state + 2.0 * sp.ext * g, -0.9)
+            g = np.gradient(u, sp.ext)
+            m2 = np.maximum(u + 2.0 * sp.ext * g, -0.9)
             ext = None
         else:
-            m2 = np.clip(state, 0.05, 4.0)
+            m2 = np.clip(u, 0.05, 4.0)
             ext = np.ascontiguousarray(sp.ext)
         return ext, np.ascontiguousarray(m2)
 
-    def desc_of(sp, fp64=False):
-        prec = 0 if (fp64 or not sp.fp32) else 1
+    def desc_of(sp):
+        prec = 1 if sp.fp32 else 0
         return frg.make_desc(sp.family, sp.n_q, sp.q_max, n_x=sp.n_x, n_phi=sp.n_phi,
                              precision=prec, near_pole_tau=0.1 if prec else 0.0)
 
-    # per-shape service time of the plain float64 path (inputs to HBM, integrate, result back)
-    svc = []
+    cfg = frg.frg_session_config(max_inflight, 4 << 30, 2, 0)  # 4 GiB arena, 2 us polling
+    sess = frg.frg_session_open(ctx.handle, cfg)
+    keep = []
+    kinds, kind_spec, kind_nodes = [], [], []
     for sp in specs:
-        ext, m2 = host_request(sp, sp.state0)
-        d = desc_of(sp, fp64=True)
-        tz = None if sp.Z is None else _dev(torch, sp.Z)
-        best = 1e9
-        for _ in range(2):
-            t0 = time.perf_counter()
-            te = None if ext is None else _dev(torch, ext)
-            tm = _dev(torch, m2)
+        tid, zdev = -1, None
+        if sp.Z is not None:
+            tid = frg.frg_session_register_table(sess, sp.Z.ctypes.data, sp.Z.size, wl.Z_XMIN,
+                                                 wl.Z_XMAX)
+            zdev = _dev(torch, sp.Z)
+            keep.append(zdev)
+        d = desc_of(sp)
+        tz = zdev
+        for stage in range(4):
+            ext, m2 = stage_inputs(sp, stage)
+            # the request alone, as the session must reproduce it
             out = torch.empty(sp.n_ext, dtype=torch.float64, device="cuda")
-            ctx.integrate(d, out, ext=te, m2=tm, Z=tz, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)
-            out.cpu()
-            best = min(best, time.perf_counter() - t0)
-        svc.append(best)
-    svc = np.array(svc)
-    mean_svc = float(svc.mean())
-    req_nodes = np.array([wl.request_nodes(sp) for sp in specs], dtype=np.float64)
+            err = torch.empty(sp.n_ext, dtype=torch.float64, device="cuda") if sp.fp32 else None
+            ctx.integrate(d, out, ext=None if ext is None else _dev(torch, ext),
+                          m2=_dev(torch, m2), Z=tz, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
+                          err_out=err)
+            expect = np.ascontiguousarray(out.cpu().numpy())
+            keep += [ext, m2, expect]
+            kinds.append(frg.frg_replay_kind(
+                d, sp.n_ext, None if ext is None else ext.ctypes.data, m2.ctypes.data, tid,
+                None if zdev is None else zdev.data_ptr(), 0 if sp.Z is None else sp.Z.size,
+                wl.Z_XMIN, wl.Z_XMAX, expect.ctypes.data))
+            kind_spec.append(sp)
+            kind_nodes.append(wl.request_nodes(sp))
+    torch.cuda.synchronize()
+    kind_nodes = np.array(kind_nodes, dtype=np.float64)
+    kfam = np.array([sp.family for sp in kind_spec])
+    k32 = np.array([sp.fp32 for sp in kind_spec])
+    rng = np.random.default_rng(seed)
+
+    def draw_kinds(n):
+        st = rng.integers(0, n_steppers, n)
+        counter = np.zeros(n_steppers, dtype=np.int64)
+        out = np.empty(n, dtype=np.int64)
+        for i, j in enumerate(st):
+            out[i] = 4 * j + counter[j] % 4
+            counter[j] += 1
+        return out
 
     def pct(x, q):
-        return round(float(np.percentile(x, q)) * 1e6, 1)
+        return round(float(np.percentile(x, q)), 1) if len(x) else None
 
-    def run(load):
-        think = max(mean_svc * (n_steppers / load - 1.0), 0.0)
-        cfg = frg.frg_session_config(4, 4 << 30, 20, 0)  # 4 GiB arena
-        sess = frg.frg_session_open(ctx.handle, cfg)
-        tables = {}
-        for sp in specs:
-            if sp.Z is not None:
-                tables[sp.index] = frg.frg_session_register_table(
-                    sess, sp.Z.ctypes.data, sp.Z.size, wl.Z_XMIN, wl.Z_XMAX)
-        trace = []  # (arrival, stepper, latency)
-        lock = threading.Lock()
-        t_start = time.perf_counter()
-        t_end = t_start + seconds
-
-        def stepper(sp):
-            rnd = random.Random(seed + sp.index)
-            u = sp.state0.copy()
-            h, eta = 0.05, 0.02
-            d = desc_of(sp)
-            tid = tables.get(sp.index, -1)
-            out = np.empty(sp.n_ext)
-            err = np.empty(sp.n_ext)
-            while time.perf_counter() < t_end:
-                ks = []
-                for stage in range(4):
-                    us = u if stage == 0 else u + (h if stage == 3 else h / 2) * ks[-1]
-                    ext, m2 = host_request(sp, us)
-                    zt = frg.frg_log_table(None, 0, wl.Z_XMIN, wl.Z_XMAX)
-                    b = frg.frg_batch(sp.n_ext, None if ext is None else ext.ctypes.data,
-                                      m2.ctypes.data, 0.0, zt, out.ctypes.data, err.ctypes.data)
-                    t0 = time.perf_counter()
-                    tk = frg.frg_session_submit(sess, d, b, tid)
-                    frg.frg_session_wait(sess, tk, -1)
-                    t1 = time.perf_counter()
-                    with lock:
-                        trace.append((t0 - t_start, sp.index, t1 - t0))
-                    ks.append(-eta * out)
-                    time.sleep(rnd.expovariate(1.0 / think) if think > 0 else 0.0)
-                    if time.perf_counter() >= t_end:
-                        break
-                if len(ks) == 4:
-                    u = u + h / 6.0 * (ks[0] + 2 * ks[1] + 2 * ks[2] + ks[3])
-
-        ths = [threading.Thread(target=stepper, args=(sp,)) for sp in specs]
-        for t in ths:
-            t.start()
-        for t in ths:
-            t.join()
-        st = frg.frg_session_stats(sess)
-        frg.frg_session_close(sess)
-        idx = np.array([i for _, i, _ in trace])
-        lat = np.array([l for _, _, l in trace])
-        arr = np.array([a for a, _, _ in trace])
-        nodes = req_nodes[idx]
-        span = float((arr + lat).max() - arr.min())
-        # the same arrivals served FIFO, one request at a time, by the plain float64 path
-        free_at = 0.0
-        base_lat = np.empty(len(trace))
-        for k in np.argsort(arr):
-            start = max(arr[k], free_at)
-            free_at = start + svc[idx[k]]
-            base_lat[k] = free_at - arr[k]
-        base_span = free_at - float(arr.min())
-        fam = np.array([specs[i].family for i in idx])
-        f32 = np.array([specs[i].fp32 for i in idx])
+    def summary(lat, status, mism, idx, sel, wall):
+        ok = sel & (status == 0)
+        nodes = kind_nodes[idx]
+        res = {"requests": int(sel.sum()), "failed": int((sel & (status != 0)).sum()),
+               "mismatches": int((sel & (mism != 0)).sum()),
+               "p50_us": pct(lat[ok], 50), "p99_us": pct(lat[ok], 99),
+               "gnodes_per_s_served": round(float(nodes[ok].sum()) / (wall * 1e-6) / 1e9, 2)
+               if wall > 0 else None}
         classes = {}
         for f in (1, 2, 3):
             for p32 in (False, True):
-                m = (fam == f) & (f32 == p32)
+                m = ok & (kfam[idx] == f) & (k32[idx] == p32)
                 if m.any():
                     classes[f"{fam_name[f]}_{'fp32' if p32 else 'fp64'}"] = {
-                        "requests": int(m.sum()),
-                        "mean_nodes": round(float(nodes[m].mean())),
-                        "p50_us": pct(lat[m], 50), "p99_us": pct(lat[m], 99),
-                        "baseline_p50_us": pct(base_lat[m], 50),
-                        "baseline_p99_us": pct(base_lat[m], 99)}
-        return {
-            "offered_load": load, "requests": len(trace), "fp32_requests": int(f32.sum()),
-            "gnodes_per_s": round(float(nodes.sum()) / span / 1e9, 2),
-            "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
-            "session_p50_us": round(st.p50_us, 1), "session_p99_us": round(st.p99_us, 1),
-            "launches": int(st.launches),
-            "baseline_fp64_per_batch": {
-                "gnodes_per_s": round(float(nodes.sum()) / base_span / 1e9, 2),
-                "p50_us": pct(base_lat, 50), "p99_us": pct(base_lat, 99)},
-            "per_class": classes,
-        }
+                        "requests": int(m.sum()), "mean_nodes": round(float(nodes[m].mean())),
+                        "p50_us": pct(lat[m], 50), "p99_us": pct(lat[m], 99)}
+        res["per_class"] = classes
+        return res
 
-    res = {"steppers": n_steppers, "seconds_per_load": seconds}
-    for load in loads:
-        log(f"bench: serving at offered load {load}")
-        res[f"load_{load}"] = run(load)
+    res = {"steppers": n_steppers, "max_inflight": max_inflight, "warm_seconds": warm,
+           "seconds_per_load": seconds, "kinds": len(kinds),
+           "mean_request_nodes": round(float(kind_nodes.mean()))}
+    # saturation capacity: a burst of requests all arriving at once, through both paths
+    n_burst = 1500
+    bidx = draw_kinds(n_burst)
+    btimes = np.zeros(n_burst)
+    cap = {}
+    for name, mode in (("session", 0), ("plain_fp64_per_batch", 1)):
+        log(f"bench: serving capacity, {name}")
+        lat, status, mism, wall = frg.frg_serving_replay(
+            ctx.handle, sess if mode == 0 else None, mode, kinds, btimes, bidx, n_waiters=64)
+        cap[name] = {"gnodes_per_s": round(float(kind_nodes[bidx].sum()) / (wall * 1e-6) / 1e9,
+                                           2),
+                     "requests": n_burst, "wall_ms": round(wall / 1e3, 1),
+                     "failed": int((status != 0).sum()), "mismatches": int((mism != 0).sum())}
+    res["capacity"] = cap
+    c_nodes = cap["session"]["gnodes_per_s"] * 1e9
+    for load in (loads if seconds > 0 else ()):
+        rate = load * c_nodes / float(kind_nodes.mean())  # requests per second
+        n = int(rate * (warm + seconds) * 1.02) + 1
+        gaps = rng.exponential(1.0 / rate, n)
+        times = np.cumsum(gaps) * 1e6
+        times = times[times < (warm + seconds) * 1e6]
+        idx = draw_kinds(times.size)
+        sel = times >= warm * 1e6
+        entry = {"offered_load": load, "arrival_rate_per_s": round(rate, 1),
+                 "offered_gnodes_per_s": round(load * c_nodes / 1e9, 2)}
+        for name, mode in (("session", 0), ("plain_fp64_per_batch", 1)):
+            log(f"bench: serving at offered load {load}, {name}")
+            s0 = frg.frg_session_stats(sess)
+            lat, status, mism, wall = frg.frg_serving_replay(
+                ctx.handle, sess if mode == 0 else None, mode, kinds, times, idx, n_waiters=64)
+            # served rate over the measured arrivals: their nodes over first measured arrival
+            # to last completion
+            t_first = float(times[sel].min()) if sel.any() else 0.0
+            span = float((times[sel] + np.where(status[sel] == 0, lat[sel], 0.0)).max()
+                         - t_first) if sel.any() else 0.0
+            entry[name] = summary(lat, status, mism, idx, sel, span)
+            if mode == 0:
+                s1 = frg.frg_session_stats(sess)
+                entry[name]["launches"] = int(s1.launches - s0.launches)
+        res[f"load_{load}"] = entry
+    st = frg.frg_session_stats(sess)
+    res["session_stats"] = {"p50_us": round(st.p50_us, 1), "p99_us": round(st.p99_us, 1),
+                            "completed": int(st.completed), "failed": int(st.failed),
+                            "launches": int(st.launches), "tickets_held": int(st.tickets_held)}
+    frg.frg_session_close(sess)
+    del keep
     return res
 
 

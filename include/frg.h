@@ -381,29 +381,48 @@ typedef struct {
     int max_inflight;          /* launches in flight at once (>= 1) */
     size_t hbm_budget_bytes;   /* device bytes the session may hold for admitted requests;
                                   0 = the context budget */
-    int poll_us;               /* scheduler sleep when idle */
+    int poll_us;               /* while launches are in flight the scheduler checks them every
+                                  poll_us microseconds, spinning (0 = 2); idle, it sleeps until
+                                  a submission */
     int watchdog_ms;           /* a launch outstanding longer than this fails its tickets */
 } frg_session_config;
 
 typedef struct {
-    double p50_us, p99_us;     /* submit -> result visible on the host, completed requests */
+    double p50_us, p99_us;     /* submit -> result visible on the host, completed requests
+                                  (from a histogram of 0.5 % wide logarithmic bins: the upper
+                                  edge of the bin holding the percentile) */
     double gnodes_per_s;       /* integrand evaluations / busy wall time */
     uint64_t admitted, queued, rejected, completed, failed, cancelled;
     uint64_t nodes;            /* integrand evaluations completed */
     uint64_t launches;         /* fused launches issued */
+    uint64_t tickets_held;     /* tickets the session still keeps (not yet reported, or still
+                                  referenced by a running launch) */
 } frg_stats;
+
+/* Pinned host staging of one launch slot of a session (bytes); a request whose inputs and
+ * outputs need more than this minus the slot's launch tables (about 3 MiB) is rejected with
+ * FRG_E_NOMEM at submit. */
+#define FRG_SESSION_STAGING_BYTES ((size_t)32 << 20)
 
 /* Requests submitted to a session hold HOST pointers (ext, m2, out, err_out); the session
  * stages them into device memory it owns, admitted against the HBM budget, evaluates them in
  * fused launches that new arrivals join while earlier launches run (continuous batching), and
- * copies results back before the ticket completes. */
+ * copies results back before the ticket completes.  A launch holds a bounded amount of work
+ * (about 2e8 integrand nodes); a larger request is evaluated in parts of whole external tiles
+ * over several launches (each result is still bitwise that of frg_integrate_batch).  Requests
+ * are admitted in arrival order, except that requests that fit the budget may go ahead of one
+ * that does not fit yet, a bounded number of times.  Pinned host staging (max_inflight x
+ * FRG_SESSION_STAGING_BYTES) and the launch tables are allocated when the session opens.
+ * A ticket is forgotten once frg_session_wait or frg_session_poll has reported its end (FRG_OK
+ * or its failure status): later calls with it return FRG_E_INVAL. */
 frg_status frg_session_open(frg_context *ctx, const frg_session_config *cfg, frg_session **out);
 /* Copy a dressing table (host values) into device memory for the session's lifetime.
  * A request whose batch.Z.values is NULL and whose table_id >= 0 uses the resident table. */
 frg_status frg_session_register_table(frg_session *s, const double *Z_host, int n, double x_min,
                                       double x_max, int *table_id);
 /* Queue one request; returns immediately with a ticket.  FRG_E_NOMEM if the request alone
- * exceeds the session budget; FRG_E_INVAL on a bad descriptor or batch. */
+ * exceeds the session budget or a slot's host staging; FRG_E_INVAL on a bad descriptor or
+ * batch. */
 frg_status frg_session_submit(frg_session *s, const frg_integral_desc *desc,
                               const frg_batch *batch_host, int table_id, uint64_t *ticket);
 /* *done = 1 when the ticket's results are in the host output buffers.  A ticket that failed

@@ -24,6 +24,7 @@ SOURCES = [
     ("frg_noalloc.hip", True),
     ("frg_runtime.cpp", False),
     ("frg_session.cpp", False),
+    ("frg_replay.cpp", False),
 ]
 
 

@@ -716,7 +716,8 @@ frg_status run_batch(frg_context *ctx, ReqDev &r, hipStream_t s, Scratch *sc) {
     return FRG_OK;
 }
 
-std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out) {
+std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out,
+                                const std::vector<std::pair<int, int>> *et_ranges) {
     std::vector<TileDev> tiles;
     std::vector<double> cost;
     int lds = 0;
@@ -727,7 +728,9 @@ std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out) {
         double inner = r.family == 1 ? 1.0
                                      : std::ceil((double)r.n_x / (1 << r.lx_log2)) *
                                            (r.family == 3 ? r.n_phi : 1);
-        for (int et = 0; et < r.ext_tiles; ++et)
+        const int et0 = et_ranges ? (*et_ranges)[i].first : 0;
+        const int et1 = et_ranges ? (*et_ranges)[i].second : r.ext_tiles;
+        for (int et = et0; et < et1; ++et)
             for (int ch = 0; ch < r.chunks; ++ch) {
                 int a0 = (int)(((long long)r.n_q * ch) / r.chunks);
                 int a1 = (int)(((long long)r.n_q * (ch + 1)) / r.chunks);

@@ -209,7 +209,9 @@ frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s,
                      int grid_waves);
 frg_status relaunch_multi(Scratch *sc, hipStream_t s);
 // Tiles of a fused launch in longest-first order, and the dynamic LDS bytes it needs.
-std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out);
+// et_ranges (optional, one per request): only the external tiles [first, second) of each.
+std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out,
+                                const std::vector<std::pair<int, int>> *et_ranges = nullptr);
 // Family, precision and regulator shared by all requests (all -1 if any differs), and whether
 // any request asks for the mass derivative.
 void common_kind(const std::vector<ReqDev> &reqs, int *fam, int *prec, int *reg, int *der);

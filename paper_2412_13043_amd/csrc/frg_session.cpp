@@ -1,19 +1,33 @@
 // Serving loop: continuous batching of loop-integral requests from many concurrent clients.
 //
-// Requests are queued by frg_session_submit.  A scheduler thread admits queued requests in
-// arrival order while their device footprint (inputs, outputs, contribution scratch) fits in the
-// session's HBM arena, packs every admissible request into one fused persistent launch (the
-// multi-request tile consumer) on a free launch slot, and keeps up to max_inflight such launches
-// on separate streams, so requests that arrive while others run are admitted as memory and slots
-// free up and their work overlaps on the device.  A finished launch's outputs are copied back to
-// the clients' host buffers before their tickets complete.  Each result is computed exactly as
-// frg_integrate_batch would compute it (results do not depend on batch composition).
+// Requests are queued by frg_session_submit.  A scheduler thread admits queued requests while
+// their device footprint (inputs and outputs, 256-byte aligned) fits in the session's HBM arena,
+// packs them into one fused launch of the multi-request tile consumer on a free launch slot, and
+// keeps up to max_inflight such launches on separate streams: requests that arrive while others
+// run are admitted as memory and slots free up, and their work overlaps on the device.
 //
-// Execution goes through an Executor interface: the HIP executor above, and a test double that
-// runs no device work and completes tickets after a delay proportional to their node count, used
-// by CPU-only tests of admission, cancellation, time-outs and accounting.
+// Scheduling rules:
+//   - a launch holds at most kLaunchNodes integrand nodes (a few tenths of a millisecond of the
+//     chip), so small requests never queue behind a long launch for long;
+//   - a request larger than that is cut into parts by external tiles; each part is its own tile
+//     range of one fused launch, the first one stages the request's inputs, the following ones
+//     (at most kPartsInFlight at a time) run once the first has completed; every point is
+//     computed inside one tile, so the result does not depend on the cut;
+//   - arrival order, except that requests that fit may be admitted ahead of an earlier one that
+//     does not fit the arena yet, at most kMaxBypass times per blocked request;
+//   - slots hold pinned host staging and device tables allocated when the session opens; the
+//     launch path allocates nothing.
+// A finished launch's outputs are copied back to the clients' host buffers before their tickets
+// complete.  Each result is computed exactly as frg_integrate_batch would compute it (results do
+// not depend on batch composition or tile shape).
+//
+// Execution goes through an Executor interface: the HIP executor, and a test double that runs
+// no device work and completes a launch after a delay proportional to its node count, used by
+// CPU-only tests of admission, splitting, cancellation, time-outs and accounting.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -33,6 +47,14 @@ static double now_us() {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+constexpr size_t kMaxLaunchReqs = 512;       // requests (or parts) per launch
+constexpr size_t kMaxLaunchTiles = 1 << 17;  // tiles per launch
+constexpr double kLaunchNodes = 2.0e8;       // integrand nodes per launch (~0.35 ms)
+constexpr int kPartsInFlight = 2;            // parts of one request launched at once
+constexpr int kMaxBypass = 64;               // admissions ahead of a request blocked on memory
+constexpr size_t kSlotTables =
+    ((kMaxLaunchReqs * sizeof(ReqDev) + 255) & ~(size_t)255) + kMaxLaunchTiles * sizeof(TileDev);
+
 enum ReqState { RQ_QUEUED = 0, RQ_RUNNING, RQ_DONE, RQ_FAILED, RQ_CANCELLED };
 
 struct SessReq {
@@ -41,16 +63,35 @@ struct SessReq {
     frg_batch host{};    // host pointers from the client
     int table_id = -1;
     int n_ext_vals = 0;  // doubles in ext
-    // device layout inside the request's arena block (byte offsets)
-    size_t off_ext = 0, off_m2 = 0, off_z = 0, off_out = 0, off_err = 0, off_contrib = 0;
+    // device layout inside the request's arena block (byte offsets): inputs, outputs, and for
+    // radially chunked shapes the [n_q][n_ext] contributions and the float32 form's slots
+    size_t off_ext = 0, off_m2 = 0, off_z = 0, off_out = 0, off_err = 0, off_contrib = 0,
+           off_ctr = 0;
     size_t in_bytes = 0;   // ext + m2 + Z, contiguous from offset 0
+    size_t out_bytes = 0;  // out (+ err) staged back to the host
     size_t footprint = 0;  // whole block
-    size_t arena_off = 0;
+    size_t arena_off = (size_t)-1;
     uint64_t nodes = 0;
     double t_submit = 0.0, t_done = 0.0;
     ReqState state = RQ_QUEUED;
     frg_status status = FRG_OK;
     bool timed_out = false;
+    // tile shape (chosen at submit: the one frg_integrate_batch takes for the request alone),
+    // its external tiles and the next one to launch; a request larger than one launch
+    // (split = true) goes in parts of whole external tiles (multiples of align_tiles: 64 points
+    // for chunked shapes, whose radial sums run per block of 64 points), at most
+    // kPartsInFlight at a time once the first has staged the inputs
+    TileShape shape{};
+    bool split = false, chunked = false;
+    int ext_tiles = 0, points_per_tile = 0, align_tiles = 1, next_et = 0, parts_inflight = 0;
+    bool inputs_ready = false;
+    int bypassed = 0;  // admissions ahead of it while it could not be admitted
+    // clients blocked in frg_session_wait on this ticket, and whether one of them (or a poll)
+    // has been told the outcome (the ticket is forgotten once nothing refers to it any more)
+    int waiters = 0;
+    bool reported = false;
+    std::condition_variable cv;
+    bool terminal() const { return state == RQ_DONE || state == RQ_FAILED || state == RQ_CANCELLED; }
 };
 
 // First-fit allocator over a contiguous device range, 256-byte granularity, coalescing frees.
@@ -101,16 +142,24 @@ class Arena {
     std::map<size_t, size_t> free_;
 };
 
+// One request's share of a launch: its external tiles [et0, et1) (all of them unless split).
+struct Part {
+    SessReq *r = nullptr;
+    int et0 = 0, et1 = 0;
+    bool stage_inputs = false;  // this launch copies the request's inputs to the device
+    size_t host_in = 0, host_out = 0;  // staging offsets
+    int p0 = 0, p1 = 0;                // points [p0, p1) whose outputs come back
+    frg_log_table resident{};          // the session-resident dressing table, if the request uses one
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     DeviceBuffer tables;    // ReqDev[] then TileDev[]
-    DeviceBuffer counters;  // zeroed before each launch
     DeviceBuffer work;      // fused-launch tile counter (cleared ahead of each launch)
     void *host = nullptr;   // pinned staging: tables, inputs, outputs
     size_t host_bytes = 0;
-    std::vector<SessReq *> reqs;
-    std::vector<size_t> host_out;  // staging offset of each request's outputs
+    std::vector<Part> parts;
     bool busy = false;
     double t_launch = 0.0;
     double fake_ready = 0.0;  // test double: completion time
@@ -127,15 +176,47 @@ struct ResidentTable {
     double x_min = 0, x_max = 0;
 };
 
+// Latency histogram: logarithmic bins of 0.5 % from 0.1 us to 1e9 us (bounded memory; the
+// percentiles are exact to the bin width).
+class LatencyHist {
+   public:
+    static constexpr int kBins = 4400;
+    static constexpr double kLo = 0.1;
+    static constexpr double kStep = 1.005;
+    void add(double us) {
+        int b = us <= kLo ? 0 : (int)(std::log(us / kLo) / std::log(kStep)) + 1;
+        b = std::min(std::max(b, 0), kBins - 1);
+        ++bins_[b];
+        ++n_;
+    }
+    // upper edge of the bin holding the p-quantile
+    double quantile(double p) const {
+        if (n_ == 0) return 0.0;
+        const uint64_t want = (uint64_t)std::max(1.0, std::ceil(p * (double)n_));
+        uint64_t c = 0;
+        for (int b = 0; b < kBins; ++b) {
+            c += bins_[b];
+            if (c >= want) return kLo * std::pow(kStep, b);
+        }
+        return kLo * std::pow(kStep, kBins - 1);
+    }
 
+   private:
+    uint64_t bins_[kBins] = {};
+    uint64_t n_ = 0;
+};
 
 class Executor {
    public:
     virtual ~Executor() = default;
     virtual frg_status setup(frg_session &) = 0;
+    // enqueue the slot's launch; called without the session lock
     virtual frg_status launch(frg_session &, Slot &) = 0;
     virtual int poll(frg_session &, Slot &) = 0;  // 1 done, 0 running, -1 device error
     virtual void finish(frg_session &, Slot &) = 0;
+    // after a failed launch: wait until nothing queued on the slot's stream can still touch its
+    // staging or the requests' arena blocks
+    virtual void drain(Slot &) = 0;
 };
 
 }  // namespace frg
@@ -145,19 +226,22 @@ struct frg_session {
     frg_session_config cfg{};
     std::unique_ptr<frg::Executor> exec;
     std::mutex mu;
-    std::condition_variable cv;
+    std::condition_variable sched_cv;  // the scheduler: new work, close
     std::thread thr;
     bool stop = false;
-    std::deque<frg::SessReq *> queue;
+    std::deque<frg::SessReq *> queue;  // requests with tiles not yet launched
     std::unordered_map<uint64_t, std::unique_ptr<frg::SessReq>> reqs;
     uint64_t next_ticket = 1;
     frg::Arena arena;
     frg::DeviceBuffer arena_mem;
+    size_t staging_bytes = 0;  // per slot
     std::vector<std::unique_ptr<frg::Slot>> slots;
     std::vector<std::unique_ptr<frg::ResidentTable>> tables;
     double fake_ns_per_node = 0.0, fake_base_us = 0.0;
+    bool fake = false;
+    std::atomic<int> fake_fail{0};  // test double: launches still to fail
     // statistics
-    std::vector<double> lat_us;
+    frg::LatencyHist lat;
     uint64_t admitted = 0, rejected = 0, completed = 0, failed = 0, cancelled = 0, nodes_done = 0,
              launches = 0;
     double t_first = 0.0, t_last = 0.0;
@@ -165,6 +249,12 @@ struct frg_session {
 };
 
 namespace frg {
+
+// Points covered by external tiles [et0, et1) of a request.
+static void part_points(const SessReq &r, int et0, int et1, int *p0, int *p1) {
+    *p0 = std::min(et0 * r.points_per_tile, r.host.n_ext);
+    *p1 = std::min(et1 * r.points_per_tile, r.host.n_ext);
+}
 
 // ---------------------------------------------------------------------------------------------
 // HIP executor
@@ -178,6 +268,9 @@ class HipExecutor : public Executor {
             FRG_HIP_CHECK(hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking));
             FRG_HIP_CHECK(hipEventCreateWithFlags(&sl->done, hipEventDisableTiming));
             FRG_HIP_CHECK(sl->work.alloc(2 * sizeof(unsigned)));
+            FRG_HIP_CHECK(sl->tables.alloc(kSlotTables));
+            FRG_HIP_CHECK(hipHostMalloc(&sl->host, s.staging_bytes, hipHostMallocDefault));
+            sl->host_bytes = s.staging_bytes;
             FRG_HIP_CHECK(launch_fill_zero_u32((unsigned *)sl->work.ptr, 2, sl->stream));
             FRG_HIP_CHECK(hipStreamSynchronize(sl->stream));
         }
@@ -190,11 +283,9 @@ class HipExecutor : public Executor {
         FRG_HIP_CHECK(hipSetDevice(ctx->device));
         char *base = (char *)s.arena_mem.ptr;
         std::vector<ReqDev> rd;
-        double total = 0.0;
-        for (SessReq *r : sl.reqs) total += (double)r->nodes;
-        const int target_total = 32 * ctx->num_cus;
-        long long ctr = 0;
-        for (SessReq *r : sl.reqs) {
+        std::vector<std::pair<int, int>> ranges;
+        for (const Part &pt : sl.parts) {
+            SessReq *r = pt.r;
             frg_batch b = r->host;
             char *blk = base + r->arena_off;
             b.ext = is_vertex(r->desc.family) ? (const double *)(blk + r->off_ext) : nullptr;
@@ -202,61 +293,45 @@ class HipExecutor : public Executor {
             b.out = (double *)(blk + r->off_out);
             b.err_out = r->host.err_out ? (double *)(blk + r->off_err) : nullptr;
             if (r->table_id >= 0) {
-                const ResidentTable &t = *s.tables[r->table_id];
-                b.Z = frg_log_table{(const double *)t.buf.ptr, t.n, t.x_min, t.x_max};
+                b.Z = pt.resident;
             } else if (r->host.Z.values) {
                 b.Z.values = (const double *)(blk + r->off_z);
             }
-            int target = std::max(1, (int)std::lround(target_total * (double)r->nodes / total));
-            // session launches run no finalize pass: single-chunk shapes only
-            TileShape shape = choose_shape(ctx, r->desc, b.n_ext, target, ShapeUse::kNoChunks);
             ReqDev q;
-            frg_status st = make_request(ctx, r->desc, b, shape, 1, 0.0, 1.0, &q);
+            frg_status st = make_request(ctx, r->desc, b, r->shape, 1, 0.0, 1.0, &q);
             if (st != FRG_OK) return st;
+            // contributions and slots inside the request's block, addressed from the arena base
             q.contrib_base = (long long)((r->arena_off + r->off_contrib) / sizeof(double));
-            q.ctr_base = ctr;
-            ctr += counter_count(q);
+            q.ctr_base = (long long)((r->arena_off + r->off_ctr) / sizeof(unsigned));
             rd.push_back(q);
+            ranges.emplace_back(pt.et0, pt.et1);
         }
         int lds = 0;
-        std::vector<TileDev> tiles = make_tiles(rd, &lds);
-        // pinned staging: tables | inputs of each request | outputs of each request
-        size_t tb = align256(rd.size() * sizeof(ReqDev)) + align256(tiles.size() * sizeof(TileDev));
-        size_t need = tb;
-        for (SessReq *r : sl.reqs) need += align256(r->in_bytes);
-        size_t out_start = need;
-        for (SessReq *r : sl.reqs) need += align256((r->host.err_out ? 2 : 1) * r->host.n_ext * 8);
-        if (sl.host_bytes < need) {
-            if (sl.host) FRG_HIP_CHECK(hipHostFree(sl.host));
-            sl.host = nullptr;
-            sl.host_bytes = 0;
-            size_t want = need + need / 2 + 65536;
-            FRG_HIP_CHECK(hipHostMalloc(&sl.host, want, hipHostMallocDefault));
-            sl.host_bytes = want;
+        std::vector<TileDev> tiles = make_tiles(rd, &lds, &ranges);
+        const size_t n_work = tiles.size();
+        // radial sums of the chunked parts: one entry per block of 64 points (parts of chunked
+        // requests start at multiples of 64 points)
+        for (size_t i = 0; i < sl.parts.size(); ++i) {
+            const Part &pt = sl.parts[i];
+            if (!pt.r->chunked) continue;
+            for (int b = pt.p0 / kWave; b * kWave < pt.p1; ++b)
+                tiles.push_back(TileDev{(int)i, b, 0, 0});
         }
-        if (sl.tables.bytes < tb) {
-            FRG_HIP_CHECK(hipStreamSynchronize(sl.stream));
-            if (sl.tables.ptr) FRG_HIP_CHECK(hipFree(sl.tables.ptr));
-            sl.tables.ptr = nullptr;
-            sl.tables.bytes = 0;
-            FRG_HIP_CHECK(sl.tables.alloc(tb + tb / 2 + 4096));
-        }
-        size_t nctr = std::max<long long>(ctr, 1);
-        if (sl.counters.bytes < nctr * sizeof(unsigned)) {
-            FRG_HIP_CHECK(hipStreamSynchronize(sl.stream));
-            if (sl.counters.ptr) FRG_HIP_CHECK(hipFree(sl.counters.ptr));
-            sl.counters.ptr = nullptr;
-            sl.counters.bytes = 0;
-            FRG_HIP_CHECK(sl.counters.alloc(nctr * sizeof(unsigned) * 2));
+        const int n_fin = (int)(tiles.size() - n_work);
+        const size_t tiles_off = align256(rd.size() * sizeof(ReqDev));
+        const size_t tb = tiles_off + tiles.size() * sizeof(TileDev);
+        if (tb > kSlotTables) {
+            set_error("internal: launch tables exceed the slot's preallocated tables");
+            return FRG_E_INVAL;
         }
         char *h = (char *)sl.host;
         std::memcpy(h, rd.data(), rd.size() * sizeof(ReqDev));
-        size_t tiles_off = align256(rd.size() * sizeof(ReqDev));
         std::memcpy(h + tiles_off, tiles.data(), tiles.size() * sizeof(TileDev));
         FRG_HIP_CHECK(hipMemcpyAsync(sl.tables.ptr, h, tb, hipMemcpyHostToDevice, sl.stream));
-        size_t pos = tb;
-        for (SessReq *r : sl.reqs) {
-            char *dst = h + pos;
+        for (const Part &pt : sl.parts) {
+            SessReq *r = pt.r;
+            if (!pt.stage_inputs) continue;
+            char *dst = h + pt.host_in;
             const int n = r->host.n_ext;
             if (is_vertex(r->desc.family))
                 std::memcpy(dst + r->off_ext, r->host.ext, (size_t)r->n_ext_vals * 8);
@@ -266,28 +341,33 @@ class HipExecutor : public Executor {
             if (r->in_bytes)
                 FRG_HIP_CHECK(hipMemcpyAsync(base + r->arena_off, dst, r->in_bytes,
                                              hipMemcpyHostToDevice, sl.stream));
-            pos += align256(r->in_bytes);
+            // the float32 form's amplification slots of a chunked request start at zero (the
+            // radial sums leave them at zero again)
+            if (r->chunked && r->desc.precision == FRG_FP32_KAHAN)
+                FRG_HIP_CHECK(launch_fill_zero_u32((unsigned *)(base + r->arena_off + r->off_ctr),
+                                                   (size_t)n + 1, sl.stream));
         }
-        FRG_HIP_CHECK(launch_fill_zero_u32((unsigned *)sl.counters.ptr, nctr, sl.stream));
         const ReqDev *reqs_dev = (const ReqDev *)sl.tables.ptr;
         const TileDev *tiles_dev = (const TileDev *)((char *)sl.tables.ptr + tiles_off);
         int fam, prec, reg, der;
         common_kind(rd, &fam, &prec, &reg, &der);
-        const int grid = multi_grid((int)tiles.size(), fam, prec, reg, der, lds, ctx->num_cus);
-        FRG_HIP_CHECK(launch_multi(reqs_dev, fam, prec, reg, der, tiles_dev, (int)tiles.size(),
-                                   grid, lds, (double *)base, (unsigned *)sl.counters.ptr,
+        const int grid = multi_grid((int)n_work, fam, prec, reg, der, lds, ctx->num_cus);
+        FRG_HIP_CHECK(launch_multi(reqs_dev, fam, prec, reg, der, tiles_dev, (int)n_work, grid,
+                                   lds, (double *)base, (unsigned *)base,
                                    (unsigned *)sl.work.ptr, sl.stream));
-        sl.host_out.clear();
-        pos = out_start;
-        for (SessReq *r : sl.reqs) {
-            const size_t n = (size_t)r->host.n_ext;
-            sl.host_out.push_back(pos);
-            FRG_HIP_CHECK(hipMemcpyAsync(h + pos, base + r->arena_off + r->off_out, n * 8,
-                                         hipMemcpyDeviceToHost, sl.stream));
+        FRG_HIP_CHECK(launch_multi_finalize(reqs_dev, tiles_dev + n_work, n_fin,
+                                            (const double *)base, (unsigned *)base, sl.stream));
+        for (const Part &pt : sl.parts) {
+            const SessReq *r = pt.r;
+            const size_t n = (size_t)(pt.p1 - pt.p0);
+            if (n == 0) continue;
+            const char *blk = base + r->arena_off;
+            FRG_HIP_CHECK(hipMemcpyAsync(h + pt.host_out, blk + r->off_out + 8 * (size_t)pt.p0,
+                                         n * 8, hipMemcpyDeviceToHost, sl.stream));
             if (r->host.err_out)
-                FRG_HIP_CHECK(hipMemcpyAsync(h + pos + n * 8, base + r->arena_off + r->off_err,
-                                             n * 8, hipMemcpyDeviceToHost, sl.stream));
-            pos += align256((r->host.err_out ? 2 : 1) * n * 8);
+                FRG_HIP_CHECK(hipMemcpyAsync(h + pt.host_out + n * 8,
+                                             blk + r->off_err + 8 * (size_t)pt.p0, n * 8,
+                                             hipMemcpyDeviceToHost, sl.stream));
         }
         FRG_HIP_CHECK(hipEventRecord(sl.done, sl.stream));
         return FRG_OK;
@@ -303,14 +383,16 @@ class HipExecutor : public Executor {
 
     void finish(frg_session &, Slot &sl) override {
         const char *h = (const char *)sl.host;
-        for (size_t i = 0; i < sl.reqs.size(); ++i) {
-            SessReq *r = sl.reqs[i];
-            if (r->timed_out) continue;
-            const size_t n = (size_t)r->host.n_ext;
-            std::memcpy(r->host.out, h + sl.host_out[i], n * 8);
-            if (r->host.err_out) std::memcpy(r->host.err_out, h + sl.host_out[i] + n * 8, n * 8);
+        for (const Part &pt : sl.parts) {
+            const SessReq *r = pt.r;
+            if (r->timed_out || r->state != RQ_RUNNING) continue;
+            const size_t n = (size_t)(pt.p1 - pt.p0);
+            std::memcpy(r->host.out + pt.p0, h + pt.host_out, n * 8);
+            if (r->host.err_out) std::memcpy(r->host.err_out + pt.p0, h + pt.host_out + n * 8, n * 8);
         }
     }
+
+    void drain(Slot &sl) override { (void)hipStreamSynchronize(sl.stream); }
 };
 
 // Test double: no device work; a launch completes after base + ns_per_node * nodes.
@@ -318,79 +400,205 @@ class FakeExecutor : public Executor {
    public:
     frg_status setup(frg_session &) override { return FRG_OK; }
     frg_status launch(frg_session &s, Slot &sl) override {
+        int f = s.fake_fail.load();
+        while (f > 0 && !s.fake_fail.compare_exchange_weak(f, f - 1)) {
+        }
+        if (f > 0) {
+            set_error("test double: launch failure requested");
+            return FRG_E_DEVICE;
+        }
         double nodes = 0.0;
-        for (SessReq *r : sl.reqs) nodes += (double)r->nodes;
+        for (const Part &pt : sl.parts)
+            nodes += (double)(pt.p1 - pt.p0) * nodes_per_point(pt.r->desc);
         sl.fake_ready = now_us() + s.fake_base_us + s.fake_ns_per_node * nodes * 1e-3;
         return FRG_OK;
     }
     int poll(frg_session &, Slot &sl) override { return now_us() >= sl.fake_ready ? 1 : 0; }
     void finish(frg_session &, Slot &) override {}
+    void drain(Slot &) override {}
 };
 
 // ---------------------------------------------------------------------------------------------
-// Scheduler
+// Scheduler (every function below runs with s.mu held)
 // ---------------------------------------------------------------------------------------------
-static void complete_slot(frg_session &s, Slot &sl, bool ok) {
-    double t = now_us();
-    if (ok) s.exec->finish(s, sl);
-    for (SessReq *r : sl.reqs) {
-        s.arena.release(r->arena_off, r->footprint);
-        if (r->timed_out) continue;  // already failed by the watchdog
-        r->t_done = t;
-        if (ok) {
-            r->state = RQ_DONE;
-            r->status = FRG_OK;
-            s.completed++;
-            s.nodes_done += r->nodes;
-            s.lat_us.push_back(t - r->t_submit);
-            s.t_last = t;
-        } else {
-            r->state = RQ_FAILED;
-            r->status = FRG_E_DEVICE;
-            s.failed++;
-        }
+// A ticket whose outcome a client has been told and that nothing refers to any more is dropped.
+static void maybe_forget(frg_session &s, SessReq *r) {
+    if (r->reported && r->waiters == 0 && r->terminal() && r->parts_inflight == 0 &&
+        r->arena_off == Arena::npos && r->state != RQ_QUEUED)
+        s.reqs.erase(r->ticket);
+}
+
+static void remove_from_queue(frg_session &s, SessReq *r) {
+    auto it = std::find(s.queue.begin(), s.queue.end(), r);
+    if (it != s.queue.end()) s.queue.erase(it);
+}
+
+static void end_request(frg_session &s, SessReq *r, ReqState state, frg_status status, double t) {
+    if (r->terminal()) return;
+    r->state = state;
+    r->status = status;
+    r->t_done = t;
+    if (state == RQ_DONE) {
+        s.completed++;
+        s.nodes_done += r->nodes;
+        s.lat.add(t - r->t_submit);
+        s.t_last = t;
+    } else if (state == RQ_FAILED) {
+        s.failed++;
+    } else {
+        s.cancelled++;
     }
-    sl.reqs.clear();
+    r->cv.notify_all();
+}
+
+static void complete_slot(frg_session &s, Slot &sl, bool ok) {
+    const double t = now_us();
+    if (ok) s.exec->finish(s, sl);
+    for (const Part &pt : sl.parts) {
+        SessReq *r = pt.r;
+        r->parts_inflight--;
+        if (ok && pt.stage_inputs) r->inputs_ready = true;
+        if (!ok) {
+            remove_from_queue(s, r);  // no further parts
+            end_request(s, r, RQ_FAILED, FRG_E_DEVICE, t);
+        }
+        const bool all_launched = r->next_et >= r->ext_tiles || r->terminal();
+        if (r->parts_inflight == 0 && all_launched) {
+            if (r->arena_off != Arena::npos) {
+                s.arena.release(r->arena_off, r->footprint);
+                r->arena_off = Arena::npos;
+            }
+            end_request(s, r, RQ_DONE, FRG_OK, t);  // no-op if it already failed or timed out
+        }
+        maybe_forget(s, r);
+    }
+    sl.parts.clear();
     sl.busy = false;
 }
 
-static bool admit_and_launch(frg_session &s) {
-    Slot *free_slot = nullptr;
-    for (auto &sl : s.slots)
-        if (!sl->busy) {
-            free_slot = sl.get();
+// Staging bytes a part takes in a slot: the request's inputs (first part only) and the part's
+// outputs.
+static size_t part_staging(const SessReq &r, int p0, int p1, bool inputs) {
+    const size_t n = (size_t)(p1 - p0);
+    return (inputs ? align256(r.in_bytes) : 0) + align256((r.host.err_out ? 2 : 1) * n * 8);
+}
+
+// Choose the parts of one launch for a free slot; false if there is nothing to launch.
+static bool plan_launch(frg_session &s, Slot &sl) {
+    double nodes = 0.0;
+    size_t tiles = 0;
+    size_t stage = kSlotTables;  // the staging area starts with the launch tables
+    SessReq *blocked = nullptr;  // the earliest request that did not fit the arena
+    std::vector<SessReq *> done_launching, failed;
+    for (size_t qi = 0; qi < s.queue.size() && sl.parts.size() < kMaxLaunchReqs; ++qi) {
+        SessReq *r = s.queue[qi];
+        const bool admitted = r->arena_off != Arena::npos;
+        // a split request whose first part, or enough parts, are still running
+        if (admitted && (!r->inputs_ready || r->parts_inflight >= kPartsInFlight)) continue;
+        const double npp = nodes_per_point(r->desc);
+        const int remaining = r->ext_tiles - r->next_et;
+        const size_t per_tile = (size_t)r->shape.chunks;  // work tiles per external tile
+        int k;
+        if (!r->split) {
+            if (!sl.parts.empty() && nodes + (double)r->nodes > kLaunchNodes) break;
+            k = remaining;
+        } else {
+            // as many whole tiles as the launch has room for, in multiples of align_tiles (at
+            // least one multiple)
+            const double tile_nodes = (double)r->points_per_tile * npp;
+            const int a = r->align_tiles;
+            k = (int)std::floor((kLaunchNodes - nodes) / tile_nodes);
+            k = std::min<long long>(k, (long long)((kMaxLaunchTiles - tiles) / per_tile));
+            k = (k / a) * a;
+            if (k < a) {
+                if (!sl.parts.empty()) break;
+                k = a;
+            }
+            k = std::min(k, remaining);
+        }
+        Part pt;
+        pt.r = r;
+        pt.stage_inputs = r->next_et == 0;
+        pt.et0 = r->next_et;
+        pt.et1 = r->next_et + k;
+        part_points(*r, pt.et0, pt.et1, &pt.p0, &pt.p1);
+        const size_t fin = r->chunked ? (size_t)(pt.p1 - pt.p0 + kWave - 1) / kWave : 0;
+        const size_t pt_tiles = (size_t)k * per_tile + fin;
+        const size_t pst = part_staging(*r, pt.p0, pt.p1, pt.stage_inputs);
+        if (tiles + pt_tiles > kMaxLaunchTiles || stage + pst > s.staging_bytes) {
+            if (sl.parts.empty()) {
+                failed.push_back(r);  // cannot happen for requests accepted at submit
+                continue;
+            }
             break;
         }
-    if (!free_slot || s.queue.empty()) return false;
-    // Arrival order; stop at the first request that does not fit (no overtaking).  A launch
-    // completes as a whole, so it is capped at about half a millisecond of the chip: small
-    // requests are not held back by a large one launched with them, and a request above the
-    // cap runs alone in its slot while the other slots keep serving the rest of the queue.
-    const size_t max_reqs = 512;
-    const double max_nodes = 2.5e8;
-    double nodes = 0.0;
-    std::vector<SessReq *> batch;
-    while (!s.queue.empty() && batch.size() < max_reqs) {
-        SessReq *r = s.queue.front();
-        if (!batch.empty() && nodes + (double)r->nodes > max_nodes) break;
-        size_t off = s.arena.alloc(r->footprint);
-        if (off == Arena::npos) break;
-        r->arena_off = off;
-        r->state = RQ_RUNNING;
-        s.queue.pop_front();
-        batch.push_back(r);
-        nodes += (double)r->nodes;
+        if (!admitted) {
+            // a new admission: after kMaxBypass of them ahead of a request that does not fit
+            // the arena, wait for it (parts of admitted requests still go ahead: they free
+            // the memory it waits for)
+            if (blocked && blocked->bypassed >= kMaxBypass) continue;
+            const size_t off = s.arena.alloc(r->footprint);
+            if (off == Arena::npos) {
+                if (!blocked) blocked = r;
+                continue;
+            }
+            r->arena_off = off;
+            r->state = RQ_RUNNING;
+            s.admitted++;
+            if (blocked) blocked->bypassed++;
+        }
+        if (pt.stage_inputs) {
+            pt.host_in = stage;
+            stage += align256(r->in_bytes);
+        }
+        pt.host_out = stage;
+        stage += align256((r->host.err_out ? 2 : 1) * (size_t)(pt.p1 - pt.p0) * 8);
+        if (r->table_id >= 0) {
+            const ResidentTable &t = *s.tables[r->table_id];
+            pt.resident = frg_log_table{(const double *)t.buf.ptr, t.n, t.x_min, t.x_max};
+        }
+        tiles += pt_tiles;
+        nodes += (double)(pt.p1 - pt.p0) * npp;
+        r->parts_inflight++;
+        r->next_et = pt.et1;
+        if (r->next_et >= r->ext_tiles) done_launching.push_back(r);
+        sl.parts.push_back(pt);
+        if (nodes >= kLaunchNodes) break;
     }
-    if (batch.empty()) return false;
-    free_slot->reqs = batch;
-    free_slot->busy = true;
-    free_slot->t_launch = now_us();
-    s.admitted += batch.size();
+    for (SessReq *r : done_launching) remove_from_queue(s, r);
+    for (SessReq *r : failed) {
+        remove_from_queue(s, r);
+        if (r->arena_off != Arena::npos && r->parts_inflight == 0) {
+            s.arena.release(r->arena_off, r->footprint);
+            r->arena_off = Arena::npos;
+        }
+        end_request(s, r, RQ_FAILED, FRG_E_NOMEM, now_us());
+        maybe_forget(s, r);
+    }
+    return !sl.parts.empty();
+}
+
+static bool admit_and_launch(frg_session &s, std::unique_lock<std::mutex> &lk) {
+    Slot *sl = nullptr;
+    for (auto &x : s.slots)
+        if (!x->busy) {
+            sl = x.get();
+            break;
+        }
+    if (!sl || s.queue.empty()) return false;
+    if (!plan_launch(s, *sl)) return false;
+    sl->busy = true;
+    sl->t_launch = now_us();
     s.launches++;
-    frg_status st = s.exec->launch(s, *free_slot);
+    // the device calls run without the session lock: clients keep submitting and waiting
+    lk.unlock();
+    frg_status st = s.exec->launch(s, *sl);
+    std::string msg = st == FRG_OK ? std::string() : std::string(frg_last_error());
+    if (st != FRG_OK) s.exec->drain(*sl);
+    lk.lock();
     if (st != FRG_OK) {
-        s.fatal = frg_last_error();
-        complete_slot(s, *free_slot, false);
+        s.fatal = msg;
+        complete_slot(s, *sl, false);
     }
     return true;
 }
@@ -412,36 +620,41 @@ static void scheduler(frg_session *sp) {
             }
             busy = true;
             if (s.cfg.watchdog_ms > 0 && now_us() - sl->t_launch > 1e3 * s.cfg.watchdog_ms) {
-                for (SessReq *r : sl->reqs)
-                    if (!r->timed_out) {
-                        r->timed_out = true;
-                        r->state = RQ_FAILED;
-                        r->status = FRG_E_TIMEOUT;
-                        r->t_done = now_us();
-                        s.failed++;
-                        progress = true;
-                    }
+                for (const Part &pt : sl->parts) {
+                    SessReq *r = pt.r;
+                    if (r->timed_out || r->terminal()) continue;
+                    r->timed_out = true;
+                    remove_from_queue(s, r);
+                    end_request(s, r, RQ_FAILED, FRG_E_TIMEOUT, now_us());
+                    progress = true;
+                }
             }
         }
-        while (!s.stop && admit_and_launch(s)) progress = true;
+        while (!s.stop && admit_and_launch(s, lk)) progress = true;
         for (auto &sl : s.slots) busy = busy || sl->busy;
-        if (progress) s.cv.notify_all();
         if (s.stop && !busy) break;
         if (!progress) {
-            if (busy || !s.queue.empty())
-                s.cv.wait_for(lk, std::chrono::microseconds(std::max(1, s.cfg.poll_us)));
-            else
-                s.cv.wait(lk);
+            if (busy) {
+                // launches in flight: poll again after poll_us, spinning with the lock released
+                // (a sleep this short would last the kernel's timer slack, ~50 us, instead)
+                lk.unlock();
+                const double until = now_us() + (double)s.cfg.poll_us;
+                while (now_us() < until) std::this_thread::yield();
+                lk.lock();
+            } else {
+                s.sched_cv.wait(lk);
+            }
         }
     }
-    // queued tickets left at close are cancelled
+    // queued tickets left at close are cancelled (a split request may have launched parts)
     for (SessReq *r : s.queue) {
-        r->state = RQ_CANCELLED;
-        r->status = FRG_E_CANCELLED;
-        s.cancelled++;
+        if (r->arena_off != Arena::npos) {
+            s.arena.release(r->arena_off, r->footprint);
+            r->arena_off = Arena::npos;
+        }
+        end_request(s, r, RQ_CANCELLED, FRG_E_CANCELLED, now_us());
     }
     s.queue.clear();
-    s.cv.notify_all();
 }
 
 static size_t request_layout(SessReq &r) {
@@ -461,9 +674,12 @@ static size_t request_layout(SessReq &r) {
     off += align256((size_t)n * 8);
     r.off_err = off;
     if (r.host.err_out) off += align256((size_t)n * 8);
+    r.out_bytes = (r.host.err_out ? 2 : 1) * (size_t)n * 8;
+    off = align256(off);
     r.off_contrib = off;
-    // contributions of radially chunked requests (n_q n_f radial nodes at finite temperature)
-    if (is_vertex(d.family)) off += align256((size_t)plan_desc(d).n_q * n * 8);
+    if (r.chunked) off += align256((size_t)plan_desc(d).n_q * n * 8);
+    r.off_ctr = off;
+    if (r.chunked && d.precision == FRG_FP32_KAHAN) off += align256(((size_t)n + 1) * 4);
     return align256(off);
 }
 
@@ -481,16 +697,18 @@ static frg_status open_session(frg_context *ctx, const frg_session_config *cfg, 
     auto s = std::make_unique<frg_session>();
     s->ctx = ctx;
     s->cfg = *cfg;
-    if (s->cfg.poll_us == 0) s->cfg.poll_us = 20;
+    if (s->cfg.poll_us == 0) s->cfg.poll_us = 2;
     size_t budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (ctx ? ctx->hbm_budget : 0);
     if (budget < 4096) {
         set_error("session HBM budget must be at least 4096 bytes");
         return FRG_E_INVAL;
     }
     s->arena.init(budget & ~(size_t)255);
+    s->staging_bytes = FRG_SESSION_STAGING_BYTES;
     for (int i = 0; i < cfg->max_inflight; ++i) s->slots.push_back(std::make_unique<Slot>());
     s->fake_ns_per_node = ns_per_node;
     s->fake_base_us = base_us;
+    s->fake = fake;
     if (fake)
         s->exec = std::make_unique<FakeExecutor>();
     else
@@ -522,6 +740,16 @@ frg_status frg_session_open_fake(const frg_session_config *cfg, double ns_per_no
         return FRG_E_INVAL;
     }
     return open_session(nullptr, cfg, true, ns_per_node, base_us, out);
+}
+
+frg_status frg_session_fake_fail_launches(frg_session *s, int n) {
+    clear_error();
+    if (!s || !s->fake || n < 0) {
+        set_error("frg_session_fake_fail_launches needs a fake session and n >= 0");
+        return FRG_E_INVAL;
+    }
+    s->fake_fail.store(n);
+    return FRG_OK;
 }
 
 frg_status frg_session_register_table(frg_session *s, const double *Z_host, int n, double x_min,
@@ -581,7 +809,25 @@ frg_status frg_session_submit(frg_session *s, const frg_integral_desc *desc,
         }
     }
     const frg_integral_desc &d = *desc;
-    r->nodes = (uint64_t)((double)batch_host->n_ext * nodes_per_point(d));
+    const double npp = nodes_per_point(d);
+    const int n = batch_host->n_ext;
+    r->nodes = (uint64_t)((double)n * npp);
+    // the tile shape frg_integrate_batch takes for the request alone (radial chunks included)
+    const int target = 16 * (s->ctx ? s->ctx->num_cus : 256);
+    if (s->ctx) {
+        std::lock_guard<std::mutex> lk(s->ctx->mu);
+        r->shape = choose_shape(s->ctx, d, std::max(n, 1), target, ShapeUse::kRequest);
+    } else {
+        r->shape = heuristic_shape(d, std::max(n, 1), target, true, false);
+    }
+    if (is_lpa(d.family)) r->shape = TileShape{};
+    r->chunked = r->shape.chunks > 1;
+    r->points_per_tile = is_lpa(d.family) ? kWave : (kWave >> (r->shape.lq_log2 + r->shape.lx_log2));
+    r->ext_tiles = (n + r->points_per_tile - 1) / r->points_per_tile;
+    r->align_tiles = r->chunked ? kWave / r->points_per_tile : 1;
+    // parts when the request exceeds one launch's work or a good share of its tile table
+    r->split = n > 0 && ((double)r->nodes > kLaunchNodes ||
+                         (size_t)r->ext_tiles * r->shape.chunks > kMaxLaunchTiles / 2);
     r->footprint = request_layout(*r);
     r->t_submit = now_us();
     std::lock_guard<std::mutex> lk(s->mu);
@@ -591,18 +837,23 @@ frg_status frg_session_submit(frg_session *s, const frg_integral_desc *desc,
                   r->footprint, s->arena.capacity());
         return FRG_E_NOMEM;
     }
+    if (kSlotTables + align256(r->in_bytes) + align256(r->out_bytes) > s->staging_bytes) {
+        s->rejected++;
+        set_error("request needs %zu bytes of host staging, more than the %zu a launch slot has",
+                  kSlotTables + align256(r->in_bytes) + align256(r->out_bytes), s->staging_bytes);
+        return FRG_E_NOMEM;
+    }
     r->ticket = s->next_ticket++;
     *ticket = r->ticket;
     if (s->t_first == 0.0) s->t_first = r->t_submit;
-    if (batch_host->n_ext == 0) {
-        r->state = RQ_DONE;
-        r->t_done = r->t_submit;
-        s->completed++;
-    } else {
-        s->queue.push_back(r.get());
-    }
+    SessReq *raw = r.get();
     s->reqs.emplace(r->ticket, std::move(r));
-    s->cv.notify_all();
+    if (batch_host->n_ext == 0) {
+        end_request(*s, raw, RQ_DONE, FRG_OK, raw->t_submit);
+    } else {
+        s->queue.push_back(raw);
+        s->sched_cv.notify_all();
+    }
     return FRG_OK;
 }
 
@@ -618,13 +869,15 @@ frg_status frg_session_poll(frg_session *s, uint64_t ticket, int *done) {
         set_error("unknown ticket %llu", (unsigned long long)ticket);
         return FRG_E_INVAL;
     }
-    const SessReq &r = *it->second;
-    *done = (r.state == RQ_DONE) ? 1 : 0;
-    if (r.state == RQ_FAILED || r.state == RQ_CANCELLED) {
-        set_error("ticket %llu ended with status %d", (unsigned long long)ticket, r.status);
-        return r.status;
-    }
-    return FRG_OK;
+    SessReq *r = it->second.get();
+    *done = (r->state == RQ_DONE) ? 1 : 0;
+    if (!r->terminal()) return FRG_OK;
+    const frg_status st = r->state == RQ_DONE ? FRG_OK : r->status;
+    if (st != FRG_OK)
+        set_error("ticket %llu ended with status %d", (unsigned long long)ticket, r->status);
+    r->reported = true;
+    maybe_forget(*s, r);
+    return st;
 }
 
 frg_status frg_session_wait(frg_session *s, uint64_t ticket, int timeout_ms) {
@@ -640,19 +893,24 @@ frg_status frg_session_wait(frg_session *s, uint64_t ticket, int timeout_ms) {
         return FRG_E_INVAL;
     }
     SessReq *r = it->second.get();
-    auto terminal = [&] { return r->state == RQ_DONE || r->state == RQ_FAILED ||
-                                 r->state == RQ_CANCELLED; };
+    auto terminal = [&] { return r->terminal(); };
+    r->waiters++;
+    bool ended = true;
     if (timeout_ms < 0)
-        s->cv.wait(lk, terminal);
-    else if (!s->cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), terminal)) {
+        r->cv.wait(lk, terminal);
+    else
+        ended = r->cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), terminal);
+    r->waiters--;
+    if (!ended) {
         set_error("ticket %llu not finished after %d ms", (unsigned long long)ticket, timeout_ms);
         return FRG_E_TIMEOUT;
     }
-    if (r->state != RQ_DONE) {
+    const frg_status st = r->state == RQ_DONE ? FRG_OK : r->status;
+    if (st != FRG_OK)
         set_error("ticket %llu ended with status %d", (unsigned long long)ticket, r->status);
-        return r->status;
-    }
-    return FRG_OK;
+    r->reported = true;
+    maybe_forget(*s, r);
+    return st;
 }
 
 frg_status frg_session_cancel(frg_session *s, uint64_t ticket) {
@@ -672,11 +930,8 @@ frg_status frg_session_cancel(frg_session *s, uint64_t ticket) {
         set_error("ticket %llu is already running or finished", (unsigned long long)ticket);
         return FRG_E_NOTREADY;
     }
-    s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
-    r->state = RQ_CANCELLED;
-    r->status = FRG_E_CANCELLED;
-    s->cancelled++;
-    s->cv.notify_all();
+    remove_from_queue(*s, r);
+    end_request(*s, r, RQ_CANCELLED, FRG_E_CANCELLED, now_us());
     return FRG_OK;
 }
 
@@ -688,26 +943,21 @@ frg_status frg_session_stats(frg_session *s, frg_stats *out) {
     }
     std::lock_guard<std::mutex> lk(s->mu);
     std::memset(out, 0, sizeof *out);
-    std::vector<double> v = s->lat_us;
-    if (!v.empty()) {
-        std::sort(v.begin(), v.end());
-        auto pct = [&](double p) {
-            size_t i = (size_t)std::min<double>(v.size() - 1, std::ceil(p * v.size()) - 1);
-            return v[i];
-        };
-        out->p50_us = pct(0.50);
-        out->p99_us = pct(0.99);
-    }
+    out->p50_us = s->lat.quantile(0.50);
+    out->p99_us = s->lat.quantile(0.99);
     double span = s->t_last - s->t_first;
     out->gnodes_per_s = span > 0 ? (double)s->nodes_done / (span * 1e-6) / 1e9 : 0.0;
     out->admitted = s->admitted;
-    out->queued = s->queue.size();
+    out->queued = 0;
+    for (const SessReq *r : s->queue)
+        if (r->state == RQ_QUEUED) out->queued++;
     out->rejected = s->rejected;
     out->completed = s->completed;
     out->failed = s->failed;
     out->cancelled = s->cancelled;
     out->nodes = s->nodes_done;
     out->launches = s->launches;
+    out->tickets_held = s->reqs.size();
     return FRG_OK;
 }
 
@@ -717,7 +967,7 @@ frg_status frg_session_close(frg_session *s) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
-        s->cv.notify_all();
+        s->sched_cv.notify_all();
     }
     if (s->thr.joinable()) s->thr.join();
     if (s->ctx) (void)hipSetDevice(s->ctx->device);

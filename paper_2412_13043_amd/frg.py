@@ -85,7 +85,7 @@ class frg_stats(ctypes.Structure):
     _fields_ = [("p50_us", c_double), ("p99_us", c_double), ("gnodes_per_s", c_double),
                 ("admitted", c_uint64), ("queued", c_uint64), ("rejected", c_uint64),
                 ("completed", c_uint64), ("failed", c_uint64), ("cancelled", c_uint64),
-                ("nodes", c_uint64), ("launches", c_uint64)]
+                ("nodes", c_uint64), ("launches", c_uint64), ("tickets_held", c_uint64)]
 
 
 class frg_stepper_config(ctypes.Structure):
@@ -135,7 +135,28 @@ for _name, (_args, _res) in _sig.items():
 _lib.frg_session_open_fake.argtypes = [POINTER(frg_session_config), c_double, c_double,
                                        POINTER(c_void_p)]
 _lib.frg_session_open_fake.restype = c_int
-TESTING_EXPORTED = ("frg_session_open_fake",)
+class frg_replay_kind(ctypes.Structure):
+    _fields_ = [("desc", frg_integral_desc), ("n_ext", c_int), ("ext", c_void_p),
+                ("m2", c_void_p), ("table_id", c_int), ("Z_dev", c_void_p), ("nZ", c_int),
+                ("x_min", c_double), ("x_max", c_double), ("expect", c_void_p)]
+
+
+class frg_replay_arrival(ctypes.Structure):
+    _fields_ = [("t_us", c_double), ("kind", c_int)]
+
+
+class frg_replay_result(ctypes.Structure):
+    _fields_ = [("latency_us", c_double), ("status", c_int), ("mismatch", c_int)]
+
+
+_lib.frg_serving_replay.argtypes = [c_void_p, c_void_p, c_int, c_int, POINTER(frg_replay_kind),
+                                    c_int, POINTER(frg_replay_arrival), c_int,
+                                    POINTER(frg_replay_result), POINTER(c_double)]
+_lib.frg_serving_replay.restype = c_int
+_lib.frg_session_fake_fail_launches.argtypes = [c_void_p, c_int]
+_lib.frg_session_fake_fail_launches.restype = c_int
+TESTING_EXPORTED = ("frg_session_open_fake", "frg_session_fake_fail_launches",
+                    "frg_serving_replay")
 
 
 def frg_last_error() -> str:
@@ -233,6 +254,32 @@ def frg_session_open_fake(cfg: frg_session_config, ns_per_node: float, base_us: 
     _check(_lib.frg_session_open_fake(byref(cfg), ns_per_node, base_us, byref(h)),
            "frg_session_open_fake")
     return h.value
+
+
+def frg_serving_replay(ctx, session, mode: int, kinds, times_us, kind_idx, n_waiters: int = 64):
+    """Open-loop replay (include/frg_testing.h): kinds is a list of frg_replay_kind, times_us
+    and kind_idx the arrivals (ascending times).  Returns (latency_us, status, mismatch) numpy
+    arrays and the wall time in microseconds."""
+    import numpy as np
+
+    n = len(times_us)
+    K = (frg_replay_kind * len(kinds))(*kinds)
+    A = (frg_replay_arrival * max(n, 1))()
+    for i in range(n):
+        A[i].t_us = float(times_us[i])
+        A[i].kind = int(kind_idx[i])
+    R = (frg_replay_result * max(n, 1))()
+    wall = c_double()
+    _check(_lib.frg_serving_replay(ctx, session, mode, len(kinds), K, n, A, n_waiters, R,
+                                   byref(wall)), "frg_serving_replay")
+    lat = np.array([R[i].latency_us for i in range(n)])
+    status = np.array([R[i].status for i in range(n)], dtype=np.int32)
+    mism = np.array([R[i].mismatch for i in range(n)], dtype=np.int32)
+    return lat, status, mism, wall.value
+
+
+def frg_session_fake_fail_launches(s: int, n: int) -> None:
+    _check(_lib.frg_session_fake_fail_launches(s, n), "frg_session_fake_fail_launches")
 
 
 def frg_session_register_table(s: int, Z_host_ptr: int, n: int, x_min: float,

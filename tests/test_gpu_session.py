@@ -133,3 +133,94 @@ def test_session_resident_table(env):
     frg.frg_session_close(s)
     ref = oracle.integrate(2, 24, 10.0, n_x=12, ext=p, m2_scalar=0.7, Z=Z)
     assert np.max(np.abs(out - ref) / ref) <= 1e-12
+
+
+def _big_mix(frg):
+    """Requests at the serving workload's sizes: three-point above one launch's node budget
+    (float64 and float32, the latter with 96 nodes per dimension), two-point and LPA requests
+    of 1000+ points, in both precisions, and a few small ones."""
+    rng = np.random.default_rng(4242)
+
+    def three(n_p, n_a, n_q, n_x, n_phi, prec, zseed):
+        p = wl.momenta_log(n_p)
+        alpha = math.pi * np.arange(n_a) / max(1, n_a - 1)
+        ext = np.concatenate([np.repeat(p, n_a), np.tile(alpha, n_p)])
+        n = n_p * n_a
+        return dict(desc=frg.make_desc(3, n_q, 10.0, n_x=n_x, n_phi=n_phi, precision=prec,
+                                       near_pole_tau=0.1),
+                    ext=ext, m2=rng.uniform(0.1, 2.0, n), Z=wl.dressing_table(zseed), n=n, fam=3,
+                    prec=prec, out=np.full(n, np.nan), err=np.full(n, np.nan))
+
+    def two(n, n_q, n_x, prec, zseed):
+        return dict(desc=frg.make_desc(2, n_q, 10.0, n_x=n_x, precision=prec, near_pole_tau=0.1),
+                    ext=wl.momenta_log(n), m2=rng.uniform(0.1, 2.0, n),
+                    Z=wl.dressing_table(zseed), n=n, fam=2, prec=prec, out=np.full(n, np.nan),
+                    err=np.full(n, np.nan))
+
+    def lpa(n, n_q, prec):
+        return dict(desc=frg.make_desc(1, n_q, 6.0, precision=prec, near_pole_tau=0.1), ext=None,
+                    m2=rng.uniform(-0.5, 2.0, n), Z=None, n=n, fam=1, prec=prec,
+                    out=np.full(n, np.nan), err=np.full(n, np.nan))
+
+    return [three(64, 64, 128, 64, 16, 0, 11),   # 4096 pairs, 5.4e8 nodes: three parts
+            two(4096, 128, 128, 0, 12),
+            lpa(4096, 128, 0),
+            three(32, 32, 96, 96, 96, 1, 13),    # 1024 pairs, 9.1e8 nodes, float32
+            two(2000, 100, 96, 1, 14),
+            lpa(1500, 100, 1),
+            two(37, 24, 12, 0, 15),
+            lpa(20, 16, 0),
+            three(3, 5, 16, 12, 8, 1, 16)]
+
+
+def _oracle_points(r, idx):
+    d = r["desc"]
+    n = r["n"]
+    kw = dict(n_x=d.n_x, n_phi=d.n_phi, m2=r["m2"][idx], Z=r["Z"])
+    if r["fam"] == 1:
+        ext = None
+    elif r["fam"] == 2:
+        ext = r["ext"][idx]
+    else:
+        ext = (r["ext"][:n][idx], r["ext"][n:][idx])
+    return oracle.integrate(r["fam"], d.n_q, d.q_max, ext=ext, **kw)
+
+
+def test_session_serving_sizes_mix(env):
+    frg, ctx, torch = env
+    reqs = _big_mix(frg)
+    cfg = frg.frg_session_config(4, 1 << 30, 10, 0)
+    s = frg.frg_session_open(ctx.handle, cfg)
+    tickets = [frg.frg_session_submit(s, r["desc"], _host_batch(frg, r), -1) for r in reqs]
+    for t in tickets:
+        assert frg.frg_session_wait(s, t, 120000) == frg.FRG_OK
+    st = frg.frg_session_stats(s)
+    frg.frg_session_close(s)
+    assert st.completed == len(reqs) and st.failed == 0 and st.tickets_held == 0
+    # the two requests above one launch's budget ran in parts
+    assert st.launches >= 3 + 5
+    rng = np.random.default_rng(99)
+    for r in reqs:
+        # bitwise what frg_integrate_batch gives alone (float32 requests in the float32 form)
+        frg_, ctx_, torch_ = env
+        d = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+        out = torch.empty(r["n"], dtype=torch.float64, device="cuda")
+        err = torch.empty(r["n"], dtype=torch.float64, device="cuda") if r["prec"] else None
+        ctx.integrate(r["desc"], out, ext=None if r["ext"] is None else d(r["ext"]),
+                      m2=d(r["m2"]), Z=None if r["Z"] is None else d(r["Z"]), x_min=wl.Z_XMIN,
+                      x_max=wl.Z_XMAX, err_out=err)
+        torch.cuda.synchronize()
+        assert np.array_equal(r["out"], out.cpu().numpy()), "mix differs from alone"
+        if r["prec"]:
+            assert np.array_equal(r["err"], err.cpu().numpy())
+        # the oracle on a sample that includes the first and last point
+        per_point = r["desc"].n_q * max(r["desc"].n_x, 1) * max(r["desc"].n_phi, 1)
+        k = min(r["n"], max(2, min(24, int(3e6 // per_point))))
+        idx = np.unique(np.concatenate([[0, r["n"] - 1], rng.choice(r["n"], k, replace=False)]))
+        ref = _oracle_points(r, idx)
+        rel = np.abs(r["out"][idx] - ref) / np.abs(ref)
+        if r["prec"] == 0:
+            assert rel.max() <= 1e-12, (r["fam"], r["n"], rel.max())
+        else:
+            assert np.all(rel <= r["err"][idx]), (r["fam"], r["n"], rel.max())
+            assert r["err"].max() < 1e-3

@@ -32,10 +32,11 @@ class Req:
         return self.batch.n_ext * self.desc.n_q * self.desc.n_x
 
     def footprint(self):
-        # inputs, outputs and the [n_q][n_ext] contribution block, 256-byte aligned pieces
+        # inputs (p) and outputs, 256-byte aligned pieces; session launches take no radial
+        # chunks, so no contribution block
         a = lambda v: (v + 255) // 256 * 256
         n = self.batch.n_ext
-        return a(a(n * 8) + a(n * 8) + a(self.desc.n_q * n * 8))
+        return a(a(n * 8) + a(n * 8))
 
 
 def test_fake_session_completes_in_arrival_order_with_one_slot():
@@ -54,10 +55,10 @@ def test_fake_session_completes_in_arrival_order_with_one_slot():
 
 
 def test_admission_waits_for_memory_and_never_fails():
-    r0 = Req(n_ext=64)
+    r0 = Req(n_ext=160)
     budget = 2 * r0.footprint() + 512  # two requests fit at once
     s = frg.frg_session_open_fake(_cfg(inflight=4, budget=budget), 2000.0, 1000.0)
-    reqs = [Req(n_ext=64) for _ in range(10)]
+    reqs = [Req(n_ext=160) for _ in range(10)]
     t0 = time.perf_counter()
     tickets = [frg.frg_session_submit(s, r.desc, r.batch, -1) for r in reqs]
     st = frg.frg_session_stats(s)
@@ -218,26 +219,147 @@ def test_finite_temperature_descriptors_are_validated_at_submit():
     frg.frg_session_close(s)
 
 
-def test_finite_temperature_footprint_counts_every_frequency():
-    # T = 0.2, Lambda = 5: bosonic |2 pi n T| <= 5 gives n = -3..3 (7), plus 2 x 4 tail nodes:
-    # 15 frequencies, so the [n_q n_f][n_ext] contribution block is 15 times the vacuum one
+def test_footprint_is_inputs_and_outputs_only():
+    # a finite-temperature request (p and p0 in, I out) needs a(2n*8) + a(n*8) device bytes and
+    # no contribution scratch: a budget of exactly that admits it, and it runs
     n, n_q = 256, 16
     a = lambda v: (v + 255) // 256 * 256
-    vac = a(a(n * 8) + a(n * 8) + a(n_q * n * 8))
-    ft = a(a(2 * n * 8) + a(n * 8) + a(15 * n_q * n * 8))
-    budget = (vac + ft) // 2  # the vacuum request fits, the finite-temperature one does not
-    s = frg.frg_session_open_fake(_cfg(budget=max(budget, 4096)), 1.0, 1.0)
+    need = a(a(2 * n * 8) + a(n * 8))
+    s = frg.frg_session_open_fake(_cfg(budget=max(need, 4096)), 1.0, 1.0)
     p = np.linspace(0.1, 3.0, n)
     ext = np.concatenate([p, np.zeros(n)])
     out = np.empty(n)
     zt = frg.frg_log_table(None, 0, 1e-3, 1e3)
-    bv = frg.frg_batch(n, p.ctypes.data, None, 0.5, zt, out.ctypes.data, None)
     bt = frg.frg_batch(n, ext.ctypes.data, None, 0.5, zt, out.ctypes.data, None)
-    t = frg.frg_session_submit(s, frg.make_desc(frg.FRG_FAMILY_TWO_POINT, n_q, 6.0, n_x=8), bv, -1)
+    t = frg.frg_session_submit(s, _ft_desc(), bt, -1)
     assert frg.frg_session_wait(s, t, 5000) == frg.FRG_OK
+    # twice the points do not fit
+    ext2 = np.concatenate([np.linspace(0.1, 3.0, 2 * n), np.zeros(2 * n)])
+    out2 = np.empty(2 * n)
+    b2 = frg.frg_batch(2 * n, ext2.ctypes.data, None, 0.5, zt, out2.ctypes.data, None)
     with pytest.raises(frg.FrgError) as ei:
-        frg.frg_session_submit(s, _ft_desc(), bt, -1)
+        frg.frg_session_submit(s, _ft_desc(), b2, -1)
     assert ei.value.status == frg.FRG_E_NOMEM
+    frg.frg_session_close(s)
+
+
+def test_large_request_runs_in_parts_and_small_ones_overtake():
+    # a request of 4096 points x 128 x 64 x 16 nodes (5.4e8) runs in parts of at most 2e8 nodes;
+    # two small requests submitted right after it complete before it, on the other slot
+    s = frg.frg_session_open_fake(_cfg(inflight=2, budget=1 << 30), 1.0, 100.0)  # 1 ns/node
+    n = 4096
+    ext = np.concatenate([np.linspace(0.01, 5.0, n), np.linspace(0.0, 3.0, n)])
+    out = np.full(n, -1.0)
+    big = frg.frg_batch(n, ext.ctypes.data, None, 0.5, frg.frg_log_table(None, 0, 1e-3, 1e3),
+                        out.ctypes.data, None)
+    dbig = frg.make_desc(frg.FRG_FAMILY_THREE_POINT, 128, 10.0, n_x=64, n_phi=16)
+    tb = frg.frg_session_submit(s, dbig, big, -1)
+    small = [Req(n_ext=64) for _ in range(2)]
+    ts = [frg.frg_session_submit(s, r.desc, r.batch, -1) for r in small]
+    for t in ts:
+        assert frg.frg_session_wait(s, t, 5000) == frg.FRG_OK
+    assert frg.frg_session_poll(s, tb) is False  # 0.54 s of fake work, not done yet
+    assert frg.frg_session_wait(s, tb, 10000) == frg.FRG_OK
     st = frg.frg_session_stats(s)
-    assert st.nodes == n * n_q * 8
+    assert st.completed == 3 and st.failed == 0
+    assert st.nodes == n * 128 * 64 * 16 + sum(r.nodes for r in small)
+    # the big request needed at least ceil(5.4e8 / 2e8) = 3 launches (the small ones may join
+    # one of them)
+    assert st.launches >= 3
+    frg.frg_session_close(s)
+
+
+def test_bounded_bypass_of_a_request_blocked_on_memory():
+    # budget for one big request or a few small ones: while small requests hold memory, the big
+    # one waits; small requests behind it may go ahead, but not forever
+    small = Req(n_ext=64)
+    big = Req(n_ext=4096)
+    budget = big.footprint() + 256
+    s = frg.frg_session_open_fake(_cfg(inflight=4, budget=budget), 0.0, 3000.0)  # 3 ms/launch
+    first = [Req(n_ext=64) for _ in range(2)]
+    t_first = [frg.frg_session_submit(s, r.desc, r.batch, -1) for r in first]
+    time.sleep(0.001)
+    tb = frg.frg_session_submit(s, big.desc, big.batch, -1)
+    later = [Req(n_ext=64) for _ in range(200)]
+    t_later = [frg.frg_session_submit(s, r.desc, r.batch, -1) for r in later]
+    for t in t_first + [tb] + t_later:
+        assert frg.frg_session_wait(s, t, 60000) == frg.FRG_OK
+    st = frg.frg_session_stats(s)
+    assert st.completed == 203 and st.failed == 0
+    frg.frg_session_close(s)
+
+
+def test_tickets_are_forgotten_once_reported_and_memory_stays_flat():
+    s = frg.frg_session_open_fake(_cfg(inflight=4, budget=1 << 30), 0.0, 0.0)
+    r = Req(n_ext=16)
+    for _ in range(20):
+        ts = [frg.frg_session_submit(s, r.desc, r.batch, -1) for _ in range(500)]
+        for t in ts:
+            assert frg.frg_session_wait(s, t, 10000) == frg.FRG_OK
+        assert frg.frg_session_stats(s).tickets_held == 0
+    st = frg.frg_session_stats(s)
+    assert st.completed == 10000 and st.p50_us >= 0.0 and st.p99_us >= st.p50_us
+    # a reported ticket is unknown afterwards
+    with pytest.raises(frg.FrgError) as ei:
+        frg.frg_session_poll(s, ts[-1])
+    assert ei.value.status == frg.FRG_E_INVAL
+    frg.frg_session_close(s)
+
+
+def test_latency_percentiles_follow_the_launch_time():
+    # 2 ms per launch, one slot, requests one at a time: no latency below 2 ms (0.5 % bins);
+    # the upper bound is loose, the host may be busy with other tests
+    s = frg.frg_session_open_fake(_cfg(inflight=1, budget=1 << 30, poll_us=20), 0.0, 2000.0)
+    r = Req(n_ext=16)
+    for _ in range(30):
+        t = frg.frg_session_submit(s, r.desc, r.batch, -1)
+        assert frg.frg_session_wait(s, t, 5000) == frg.FRG_OK
+    st = frg.frg_session_stats(s)
+    assert 1990.0 <= st.p50_us <= 20000.0 and st.p50_us <= st.p99_us <= 200000.0
+    frg.frg_session_close(s)
+
+
+def test_failed_launch_fails_its_tickets_and_frees_memory():
+    r = Req(n_ext=300)
+    s = frg.frg_session_open_fake(_cfg(inflight=1, budget=r.footprint() + 256), 0.0, 100.0)
+    frg.frg_session_fake_fail_launches(s, 1)
+    t = frg.frg_session_submit(s, r.desc, r.batch, -1)
+    with pytest.raises(frg.FrgError) as ei:
+        frg.frg_session_wait(s, t, 5000)
+    assert ei.value.status == frg.FRG_E_DEVICE
+    # the budget holds one request: the next one is admitted only if the failed one's block was
+    # released
+    t2 = frg.frg_session_submit(s, r.desc, r.batch, -1)
+    assert frg.frg_session_wait(s, t2, 5000) == frg.FRG_OK
+    st = frg.frg_session_stats(s)
+    assert st.failed == 1 and st.completed == 1 and st.tickets_held == 0
+    frg.frg_session_close(s)
+    with pytest.raises(frg.FrgError):
+        frg.frg_session_fake_fail_launches(0, 1)
+
+
+def test_replay_harness_on_a_fake_session():
+    # open-loop replay: 40 arrivals 1 ms apart on a session whose launches take 0.2 ms; every
+    # request completes, none earlier than its launch time, and the wall time spans the trace
+    s = frg.frg_session_open_fake(_cfg(inflight=2, budget=1 << 30, poll_us=10), 0.0, 200.0)
+    reqs = [Req(n_ext=32), Req(n_ext=48)]
+    kinds = []
+    for r in reqs:
+        kinds.append(frg.frg_replay_kind(r.desc, r.batch.n_ext, r.p.ctypes.data, None, -1, None,
+                                         0, 1e-3, 1e3, None))
+    m2 = [np.full(r.batch.n_ext, 0.5) for r in reqs]
+    for k, v in zip(kinds, m2):
+        k.m2 = v.ctypes.data
+    times = np.arange(40) * 1000.0
+    idx = np.arange(40) % 2
+    lat, status, mism, wall = frg.frg_serving_replay(None, s, 0, kinds, times, idx, n_waiters=4)
+    assert np.all(status == frg.FRG_OK) and np.all(mism == 0)
+    assert np.all(lat >= 200.0) and np.all(lat < 50000.0)
+    assert 39000.0 <= wall <= 39000.0 + 60000.0
+    assert frg.frg_session_stats(s).completed == 40
+    frg.frg_session_close(s)
+    # arrivals out of order are rejected
+    s = frg.frg_session_open_fake(_cfg(), 0.0, 0.0)
+    with pytest.raises(frg.FrgError):
+        frg.frg_serving_replay(None, s, 0, kinds, [5.0, 1.0], [0, 1])
     frg.frg_session_close(s)
