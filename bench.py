@@ -1,17 +1,20 @@
 """Benchmark of the batched loop-integral hot path on one MI355X.
 
-Step = one flow right-hand side batch of the two-point vertex workload: 256 right-hand sides,
-each 256 external momenta p in [1e-3, 1e2] (log-spaced) x (64 radial x 32 cos1 Gauss-Legendre
-nodes) with its own tabulated dressing Z (256-point log grid), m^2 = 0.5, float64 -- evaluated by
-one fused frg_integrate_multi launch (134,217,728 integrand nodes).  Inputs are resident in HBM
-before the timed region.  Before the warmup steps the step runs untimed for --warm-seconds, long
-enough for the GPU's clocks to settle under load; the timed steps then measure the sustained rate.
+Step (default workload) = one flow right-hand-side batch of the three-point vertex workload: 8
+right-hand sides, each 1024 external (|p|, alpha) pairs x (64 radial x 32 cos1 x 16 phi
+Gauss-Legendre nodes) with its own tabulated dressing Z (256-point log grid) and masses m^2 in
+U[0.1, 2], float64 -- evaluated by one fused frg_integrate_multi launch (268,435,456 integrand
+nodes), the largest configuration that fits one GPU.  Inputs are resident in HBM before the
+timed region.  Before the warmup steps the step runs untimed for --warm-seconds, long enough for
+the GPU's clocks to settle under load; the timed steps then measure the sustained rate.
 
 Printed (one JSON line): Gnodes/s, ms per step, the roofline of the dominant kernel (algorithmic
 FP64 FLOPs per node x nodes per launch / average kernel time from HIP events on the launch
-stream, against the MI355X FP64 vector peak), the FP64 oracle timed on the host cores on a
-bounded sample, and secondary figures for the other workloads (LPA batch, three-point batch, the
-float32 precision form, right-hand-side latency percentiles).
+stream, against the MI355X FP64 vector peak, next to the hardware-counted FLOPs of the committed
+profile), the FP64 oracle timed on the host cores on a bounded sample of the same workload, and
+secondary figures for the other workloads (LPA batch, two-point batch, finite temperature, the
+float32 precision form, derivatives, right-hand-side latency, the flow steppers and the serving
+loop against the plain per-batch path).
 """
 from __future__ import annotations
 
@@ -26,20 +29,46 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# The serving measurement keeps up to six launches in flight on six streams; they overlap on
+# the device only on separate hardware queues, and HIP gives a process four by default (shared
+# with torch's and the library's other streams).  Set before anything initialises HIP.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "12")
 
 FP64_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_PEAK_TFLOPS = 157.3  # packed FP32 (v_pk_fma_f32); unpacked float32 tops out at half
-# Algorithmic FP64 work per integrand node (FLOP-equivalents, transcendentals included), per
-# family: LPA one propagator square and weight; two-point ell^2, log, dressing lerp, expm1 and
-# one single-division propagator plus the accumulation; three-point the same per node (its
-# first leg depends on the outer angle only and is counted once per 16 nodes).
-FLOP_PER_NODE = {1: 15.0, 2: 74.0, 3: 83.0, 5: 74.0}
+# Algorithmic FP64 work per integrand node, in FLOPs as the hardware counts them (FMA = 2).
+# The elementary sequences are the counted values of the FLOP-count probe (frg_flop_probe: the
+# FP64 FLOP counter of one dispatch per sequence, less the bare loop, per call; summary and
+# command in profiles/flop_probe.md): table log 12, expm1(-y) 29, Newton reciprocal 5.  Around
+# them each family's node term adds plain arithmetic, counted from its code:
+#   LPA:         the denominator 2 FMAs (4), the reciprocal, its square (1), accumulate (2);
+#   two-point:   l^2 (2), the log, the dressing coordinate (2) and lerp (3), expm1, l^2 e (2),
+#                the single-reciprocal denominator (4), the reciprocal, -E x (1), accumulate
+#                (2) -- 16 + log + expm1 + reciprocal;
+#   three-point: the second leg's l^2 (2), its propagator (the two-point term without l^2 and
+#                accumulation), the product into the sum (2); the first leg (l^2 and a
+#                propagator, 2 + 58) once per (radial, cos1) pair, i.e. 60/n_phi per node plus
+#                4/n_phi of per-pair geometry.
+SEQ_FLOP = {"log": 12.0, "expm1": 29.0, "rcp": 5.0}
+_PROP = SEQ_FLOP["log"] + 2.0 + 3.0 + SEQ_FLOP["expm1"] + 2.0 + 4.0 + SEQ_FLOP["rcp"] + 1.0
+FLOP_LPA = 4.0 + SEQ_FLOP["rcp"] + 1.0 + 2.0
+FLOP_TWO = 2.0 + _PROP + 2.0
+
+
+def flop_three(n_phi):
+    return 2.0 + _PROP + 2.0 + (2.0 + _PROP + 4.0) / n_phi
+
+
+# the standard workloads' three-point rule has 16 phi nodes
+FLOP_PER_NODE = {1: FLOP_LPA, 2: FLOP_TWO, 3: flop_three(16), 5: FLOP_TWO}
+# the survey's FLOP-equivalent estimates (transcendentals as 25/25/10), kept for comparison
+FLOP_PER_NODE_SURVEY = {1: 15.0, 2: 74.0, 3: 147.0, 5: 74.0}
 # Two-point nodes with y = l2/k^2 >= 38 have an exponential below double precision: their exact
-# value needs no expm1 (about 25 of the 74) and a plain reciprocal of Z l2 + m2 instead of the
-# single-division form (about 7 fewer).  The kernel takes that path per wavefront when all its
-# lanes are in that far field.
+# value needs no expm1 and a plain reciprocal of Z l2 + m2 instead of the single-reciprocal form
+# (l^2 e, the outer FMA's extra term and -E x): expm1 + 5 FLOPs fewer.  The kernel takes that
+# path per wavefront when all its lanes are in that far field.
 FAR_Y = 38.0
-FAR_FLOP_SAVED = 32.0
+FAR_FLOP_SAVED = SEQ_FLOP["expm1"] + 5.0
 
 
 def two_point_far_fraction(p, n_q, q_max, n_x):
@@ -83,17 +112,20 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the fused kernel from the committed rocprofv3 counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None when the kernel
+def measured_counters(workload):
+    """Per-launch counter figures of the workload's dominant kernel from the committed rocprofv3
+    summaries (profiles/kernel_counters.json: HBM bytes from FETCH_SIZE + WRITE_SIZE scaled by a
+    plain copy of known size, and the FP64 FLOP counter x 64 lanes), or {} when the kernel
     sources have changed since those counters were taken."""
-    path = os.path.join(ROOT, "profiles", "multi_kernel_traffic.json")
+    path = os.path.join(ROOT, "profiles", "kernel_counters.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
-        return None
-    return d.get("traffic_bytes") if d.get("source_sha256_16") == kernel_source_sha() else None
+        return {}
+    if d.get("source_sha256_16") != kernel_source_sha():
+        return {}
+    return d.get("workloads", {}).get(workload, {})
 
 
 def _dev(torch, a):
@@ -163,35 +195,97 @@ def two_point_batch_setup(torch, frg, B=256, precision=0, seed_m2=None, tau=0.1,
     return [desc] * B, batches, out, err, nodes, keep
 
 
+def host_description():
+    """The host CPU as the oracle timings see it: model, sockets, physical cores, logical CPUs,
+    the CPUs this process may use, and the clock (lscpu's maximum MHz where it reports one,
+    else /proc/cpuinfo's current MHz)."""
+    import platform
+    import subprocess
+
+    d = {"cpu_model": platform.processor() or "unknown", "logical_cpus": os.cpu_count()}
+    try:
+        d["cpus_available"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        d["cpus_available"] = os.cpu_count()
+    phys, sockets, mhz = set(), set(), []
+    try:
+        cur = {}
+        with open("/proc/cpuinfo") as f:
+            for line in list(f) + [""]:
+                if not line.strip():
+                    if "physical id" in cur:
+                        sockets.add(cur["physical id"])
+                        phys.add((cur["physical id"], cur.get("core id", "")))
+                    cur = {}
+                    continue
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                cur[k] = v
+                if k == "model name":
+                    d["cpu_model"] = v
+                elif k == "cpu MHz":
+                    mhz.append(float(v))
+    except OSError:
+        pass
+    d["sockets"] = len(sockets) or None
+    d["physical_cores"] = len(phys) or None
+    d["mhz_current_mean"] = round(float(np.mean(mhz)), 1) if mhz else None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "CPU max MHz":
+                d["mhz_max"] = float(v)
+            elif k == "Socket(s)" and v.isdigit():
+                d["sockets"] = int(v)
+            elif k == "Core(s) per socket" and v.isdigit():
+                d["cores_per_socket"] = int(v)
+            elif k == "Thread(s) per core" and v.isdigit():
+                d["threads_per_core"] = int(v)
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return d
+
+
 def cpu_baseline(target_seconds=12.0):
-    """FP64 oracle on the host cores: disjoint external-point ranges in parallel threads."""
+    """FP64 oracle on the host cores, on a bounded sample of the timed workload (the three-point
+    batch): (p, alpha) pairs of its right-hand sides in order, each with its right-hand side's
+    masses and dressing table, disjoint pair ranges in parallel threads."""
     import oracle
     from paper_2412_13043_amd import workloads as wl
 
-    p, m2, Zs = wl.two_point_batch(64)
-    threads = min(os.cpu_count() or 1, 16)
-    nodes_done = 0
-    rhs_done = 0
+    P, A, m3, Z3 = wl.three_point_batch()
+    threads = min(len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                  else (os.cpu_count() or 1), 16)
+    per_pair = wl.THREE_NQ * wl.THREE_NX * wl.THREE_NPHI
+    block = 8 * threads  # pairs per round: 8 per thread
+    nodes_done = pairs_done = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < target_seconds:
-        Z = Zs[rhs_done % Zs.shape[0]]
-        chunks = np.array_split(np.arange(p.size), threads)
+        b = (pairs_done // P.size) % m3.shape[0]
+        lo = pairs_done % P.size
+        idx = np.arange(lo, min(lo + block, P.size))
+        chunks = np.array_split(idx, threads)
         ths = [threading.Thread(target=oracle.integrate,
-                                args=(oracle.TWO_POINT, wl.TWO_NQ, wl.TWO_QMAX),
-                                kwargs=dict(n_x=wl.TWO_NX, ext=p[c], m2_scalar=m2, Z=Z))
+                                args=(oracle.THREE_POINT, wl.THREE_NQ, wl.THREE_QMAX),
+                                kwargs=dict(n_x=wl.THREE_NX, n_phi=wl.THREE_NPHI,
+                                            ext=(P[c], A[c]), m2=m3[b][c], Z=Z3[b]))
                for c in chunks if c.size]
         for t in ths:
             t.start()
         for t in ths:
             t.join()
-        rhs_done += 1
-        nodes_done += p.size * wl.TWO_NQ * wl.TWO_NX
+        pairs_done += idx.size
+        nodes_done += idx.size * per_pair
     el = time.perf_counter() - t0
+    host = host_description()
     return {"value": round(nodes_done / el / 1e9, 6), "unit": "Gnodes/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{rhs_done} two-point right-hand sides (256 momenta x 64x32 nodes each, "
-                      f"float64, C -O2 libm), {threads} threads over disjoint momentum ranges, "
-                      f"{el:.1f} s"}
+            "sample": f"{pairs_done} (p, alpha) pairs of the three-point batch (64x32x16 nodes "
+                      f"each, float64, C -O2 libm), {threads} threads over disjoint pair ranges, "
+                      f"{el:.1f} s",
+            "host": host}
 
 
 def oracle_timings(threads_max=16, seconds=1.5):
@@ -202,19 +296,8 @@ def oracle_timings(threads_max=16, seconds=1.5):
     import oracle
     from paper_2412_13043_amd import workloads as wl
 
-    model = platform.processor() or "unknown"
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
-    try:
-        avail = len(os.sched_getaffinity(0))
-    except AttributeError:
-        avail = os.cpu_count() or 1
+    host = host_description()
+    avail = host.get("cpus_available") or 1
     threads = min(avail, threads_max)
 
     def rate(call, n_points, nodes_per_point, n_threads):
@@ -233,8 +316,7 @@ def oracle_timings(threads_max=16, seconds=1.5):
             if el >= seconds:
                 return done * nodes_per_point / el  # nodes per second
 
-    res = {"host": {"cpu_model": model, "logical_cpus": os.cpu_count(),
-                    "cpus_available": avail, "threads_used": threads}}
+    res = {"host": dict(host, threads_used=threads)}
     # LPA: 64 rho points x GL32 per right-hand side; the 4096-RHS batch, one point = one integral
     rho, u, m2 = wl.lpa_batch()
     m2f = m2.reshape(-1)
@@ -299,10 +381,21 @@ def main():
                     help="seconds of arrivals excluded at the start of each serving replay")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving measurement (after the timed line)")
-    ap.add_argument("--workload", default="two_point_256",
+    ap.add_argument("--serving-slots", type=int, default=6,
+                    help="launch slots (max_inflight) of the served session")
+    ap.add_argument("--serving-poll-us", type=int, default=2,
+                    help="how often a slot checks its launch for completion (microseconds)")
+    ap.add_argument("--serving-paths", default="both", choices=["both", "session"],
+                    help="serve the traces through the session and the plain path, or the "
+                         "session only")
+    ap.add_argument("--workload", default="three_point_8",
                     choices=["two_point_256", "three_point_8", "lpa_4096", "two_point_ft_16"],
-                    help="workload of the timed line (default: the two-point batch); the others "
-                         "exist so that each family's kernel can be profiled on its own")
+                    help="workload of the timed line (default: the three-point batch, the "
+                         "largest single-GPU configuration); the others exist so that each "
+                         "family's kernel can be timed and profiled on its own")
+    ap.add_argument("--flop-probe", action="store_true",
+                    help="only run the FLOP-count probe kernels (one dispatch per elementary "
+                         "sequence, for a profiler's FP64 FLOP counters)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the "
                          "reference kernel for scaling FETCH_SIZE/WRITE_SIZE counters)")
@@ -314,6 +407,18 @@ def main():
 
     import torch
 
+    if args.flop_probe:
+        from paper_2412_13043_amd import frg
+
+        blocks, iters = 1024, 4096
+        out = torch.empty(blocks * 64, dtype=torch.float64, device="cuda")
+        for seq in range(5):
+            frg.frg_flop_probe(seq, blocks, iters, out)
+        torch.cuda.synchronize()
+        print(json.dumps({"flop_probe": {"sequences": ["loop", "log_tab", "expm1_neg", "exp_neg",
+                                                       "rcp_nr"],
+                                         "evaluations_per_dispatch": blocks * 64 * iters}}))
+        return
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -345,6 +450,9 @@ def main():
     far = two_point_far_fraction(wl.two_point()[0], wl.TWO_NQ, wl.TWO_QMAX, wl.TWO_NX) \
         if family in (2, 5) else 0.0
     required = FLOP_PER_NODE[family] - FAR_FLOP_SAVED * far
+    counters = measured_counters(args.workload)
+    per_s = 1.0 / (avg_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS
+    counted = counters.get("counted_fp64_flop_per_launch")
     res = {
         "metric": "integrand Gnodes/s + % FP64/FP32 vector peak; p50/p99 RHS latency",
         "value": round(value, 3),
@@ -362,19 +470,31 @@ def main():
         "config": config,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                     "traffic": measured_traffic() if args.workload == "two_point_256" else None,
+                     "traffic": counters.get("traffic_bytes"),
                      "kernel": kernel, "avg_kernel_ms": round(avg_ms, 4),
                      "flop_per_node": FLOP_PER_NODE[family],
+                     "flop_per_node_basis": "counted elementary sequences (profiles/"
+                                            "flop_probe.md) + the node term's arithmetic",
+                     # the hardware FP64 FLOP counter of this kernel (committed profile) over
+                     # the time measured here
+                     "frac_counted": round(counted * per_s, 4) if counted else None,
+                     "counted_flop_per_node": round(counted / nodes, 2) if counted else None,
+                     # two-point families: the work the far-field nodes strictly need
                      "far_field_fraction": round(far, 4),
                      "flop_per_node_required": round(required, 2),
-                     "frac_required": round(required * nodes / (avg_ms * 1e-3) / 1e12
-                                            / FP64_PEAK_TFLOPS, 4)},
+                     "frac_required": round(required * nodes * per_s, 4),
+                     # the survey's FLOP-equivalent estimate, for comparison
+                     "flop_per_node_survey": FLOP_PER_NODE_SURVEY[family],
+                     "frac_survey": round(FLOP_PER_NODE_SURVEY[family] * nodes * per_s, 4)},
     }
     extra = {}
     if not args.no_extra:
         if args.serving_only:
             extra = {"serving": serving(torch, frg, wl, ctx, seconds=args.serving_seconds,
-                                        warm=args.serving_warm)}
+                                        warm=args.serving_warm,
+                                        plain=args.serving_paths == "both",
+                                        max_inflight=args.serving_slots,
+                                        poll_us=args.serving_poll_us)}
         else:
             extra = secondary(torch, frg, wl, ctx, serving_seconds=args.serving_seconds,
                               serving_warm=args.serving_warm)
@@ -519,6 +639,22 @@ def secondary(torch, frg, wl, ctx, serving_seconds=15.0, serving_warm=2.0):
     n1 = tm.numel() * wl.LPA_NQ
     ex["lpa_batch_4096"] = {"gnodes_per_s": round(n1 / (np.mean(ev) * 1e-3) / 1e9, 2),
                             "avg_kernel_ms": round(float(np.mean(ev)), 4)}
+    # two-point batch: 256 right-hand sides x 256 momenta x 64x32 (one fused launch)
+    log("bench: two-point batch")
+    descs2, batches2, _, _, n2, keep2 = two_point_batch_setup(torch, frg)
+    f2 = lambda: ctx.integrate_multi(descs2, batches2)
+    warm_clocks(torch, f2, EXTRA_WARM_S)
+    wall, ev = time_kernel(torch, f2, 200, 5)
+    ms2 = float(np.mean(ev))
+    far2 = two_point_far_fraction(wl.two_point()[0], wl.TWO_NQ, wl.TWO_QMAX, wl.TWO_NX)
+    ex["two_point_batch_256"] = {
+        "gnodes_per_s": round(n2 / (ms2 * 1e-3) / 1e9, 2), "avg_kernel_ms": round(ms2, 4),
+        "frac_fp64_peak": round(FLOP_PER_NODE[2] * n2 / (ms2 * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                                4),
+        "frac_required": round((FLOP_PER_NODE[2] - FAR_FLOP_SAVED * far2) * n2 / (ms2 * 1e-3)
+                               / 1e12 / FP64_PEAK_TFLOPS, 4),
+        "far_field_fraction": round(far2, 4)}
+    del keep2
     # three-point batch: 8 right-hand sides x 1024 external pairs x 64x32x16
     log("bench: three-point batch")
     P, A, m3, Z3 = wl.three_point_batch()
@@ -674,7 +810,7 @@ def secondary(torch, frg, wl, ctx, serving_seconds=15.0, serving_warm=2.0):
 
 
 def serving(torch, frg, wl, ctx, n_steppers=200, seconds=15.0, warm=2.0,
-            loads=(0.5, 0.8, 0.95), seed=12345, max_inflight=4):
+            loads=(0.5, 0.8, 0.95), seed=12345, max_inflight=6, plain=True, poll_us=2):
     """Workload 5: right-hand-side requests of 200 synthetic RK4 time-steppers, served by a
     session and, for comparison, by the plain per-batch float64 path, with one client harness.
 
@@ -712,7 +848,7 @@ def serving(torch, frg, wl, ctx, n_steppers=200, seconds=15.0, warm=2.0,
         return frg.make_desc(sp.family, sp.n_q, sp.q_max, n_x=sp.n_x, n_phi=sp.n_phi,
                              precision=prec, near_pole_tau=0.1 if prec else 0.0)
 
-    cfg = frg.frg_session_config(max_inflight, 4 << 30, 2, 0)  # 4 GiB arena, 2 us polling
+    cfg = frg.frg_session_config(max_inflight, 4 << 30, poll_us, 0)  # 4 GiB arena
     sess = frg.frg_session_open(ctx.handle, cfg)
     keep = []
     kinds, kind_spec, kind_nodes = [], [], []
@@ -778,7 +914,8 @@ def serving(torch, frg, wl, ctx, n_steppers=200, seconds=15.0, warm=2.0,
         res["per_class"] = classes
         return res
 
-    res = {"steppers": n_steppers, "max_inflight": max_inflight, "warm_seconds": warm,
+    res = {"steppers": n_steppers, "max_inflight": max_inflight, "poll_us": poll_us,
+           "warm_seconds": warm,
            "seconds_per_load": seconds, "kinds": len(kinds),
            "mean_request_nodes": round(float(kind_nodes.mean()))}
     # saturation capacity: a burst of requests all arriving at once, through both paths
@@ -786,7 +923,8 @@ def serving(torch, frg, wl, ctx, n_steppers=200, seconds=15.0, warm=2.0,
     bidx = draw_kinds(n_burst)
     btimes = np.zeros(n_burst)
     cap = {}
-    for name, mode in (("session", 0), ("plain_fp64_per_batch", 1)):
+    paths = (("session", 0), ("plain_fp64_per_batch", 1)) if plain else (("session", 0),)
+    for name, mode in paths:
         log(f"bench: serving capacity, {name}")
         lat, status, mism, wall = frg.frg_serving_replay(
             ctx.handle, sess if mode == 0 else None, mode, kinds, btimes, bidx, n_waiters=64)
@@ -806,7 +944,7 @@ def serving(torch, frg, wl, ctx, n_steppers=200, seconds=15.0, warm=2.0,
         sel = times >= warm * 1e6
         entry = {"offered_load": load, "arrival_rate_per_s": round(rate, 1),
                  "offered_gnodes_per_s": round(load * c_nodes / 1e9, 2)}
-        for name, mode in (("session", 0), ("plain_fp64_per_batch", 1)):
+        for name, mode in paths:
             log(f"bench: serving at offered load {load}, {name}")
             s0 = frg.frg_session_stats(sess)
             lat, status, mism, wall = frg.frg_serving_replay(
@@ -820,6 +958,11 @@ def serving(torch, frg, wl, ctx, n_steppers=200, seconds=15.0, warm=2.0,
             if mode == 0:
                 s1 = frg.frg_session_stats(sess)
                 entry[name]["launches"] = int(s1.launches - s0.launches)
+                dc = max(int(s1.completed - s0.completed), 1)
+                entry[name]["mean_phase_us"] = {
+                    ph: round((getattr(s1, f"mean_{ph}_us") * s1.completed
+                               - getattr(s0, f"mean_{ph}_us") * s0.completed) / dc, 1)
+                    for ph in ("queue", "launch", "device", "finish")}
         res[f"load_{load}"] = entry
     st = frg.frg_session_stats(sess)
     res["session_stats"] = {"p50_us": round(st.p50_us, 1), "p99_us": round(st.p99_us, 1),

@@ -397,6 +397,10 @@ typedef struct {
     uint64_t launches;         /* fused launches issued */
     uint64_t tickets_held;     /* tickets the session still keeps (not yet reported, or still
                                   referenced by a running launch) */
+    /* means over completed requests of the phases of their last launch: submit -> launch
+       formed, formed -> enqueued on the device, enqueued -> completion seen, completion seen
+       -> results in the client's buffers */
+    double mean_queue_us, mean_launch_us, mean_device_us, mean_finish_us;
 } frg_stats;
 
 /* Pinned host staging of one launch slot of a session (bytes); a request whose inputs and

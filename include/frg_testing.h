@@ -64,6 +64,16 @@ frg_status frg_serving_replay(frg_context *ctx, frg_session *s, int mode, int n_
                               const frg_replay_arrival *arr, int n_waiters,
                               frg_replay_result *res, double *wall_us);
 
+/* ---- FLOP-count probe ------------------------------------------------------------------------ */
+
+/* One kernel dispatch (blocks x 64 lanes, each `iters` evaluations on a varying argument) of the
+ * float64 sequence `seq` the integrand loops use -- 0: none (the bare loop, to subtract), 1: the
+ * table logarithm, 2: expm1(-y) by Cody-Waite reduction, 3: exp(-y) by the same reduction, 4: the
+ * reciprocal seed with one Newton step -- writing one sum per lane to out[blocks * 64] (device).
+ * A profiler's FP64 FLOP counter for the dispatch, less that of seq 0, divided by
+ * blocks * 64 * iters, is the sequence's FLOP count per call.  Synchronises `stream`. */
+frg_status frg_flop_probe(int seq, int blocks, int iters, double *out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,7 @@ SOURCES = [
     ("frg_stepper.hip", True),
     ("frg_threshold.hip", True),
     ("frg_noalloc.hip", True),
+    ("frg_flop_probe.hip", True),
     ("frg_runtime.cpp", False),
     ("frg_session.cpp", False),
     ("frg_replay.cpp", False),
@@ -33,8 +34,9 @@ def _run(cmd):
     subprocess.check_call(cmd)
 
 
-def build(verbose: bool = True, out: str = LIB, defines=()) -> str:
-    """Compile and link libfrg.so; `defines` are extra -D tuning macros for the device code."""
+def build(verbose: bool = True, out: str = LIB, defines=(), csrc: str = CSRC) -> str:
+    """Compile and link libfrg.so; `defines` are extra -D tuning macros for the device code;
+    `csrc` another directory with the same sources (a modified copy, for measurements)."""
     build_dir = BUILD if out == LIB else out + ".build"
     os.makedirs(build_dir, exist_ok=True)
     objs = []
@@ -45,7 +47,7 @@ def build(verbose: bool = True, out: str = LIB, defines=()) -> str:
             cmd += DEVICE + ["-D" + d for d in defines]
         else:
             cmd += ["-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-x", "c++"]
-        cmd += [os.path.join(CSRC, src), "-o", obj]
+        cmd += [os.path.join(csrc, src), "-o", obj]
         _run(cmd)
         objs.append(obj)
     tmp = out + ".tmp"

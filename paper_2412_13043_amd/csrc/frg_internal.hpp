@@ -92,9 +92,12 @@ hipError_t launch_ft_rule(int n_q, int n_f, int n_tail, int n_lo, double eta, do
 hipError_t launch_batch(const ReqDev *req_dev_host, const ReqDev *req_dev_ptr, int n_tiles,
                         int lds_bytes, double *contrib, unsigned *counters, hipStream_t s);
 // fam/prec: the family and precision shared by every request of the launch, or -1 (mixed).
+// clear_work = false: the caller has already zeroed the two tile counters in work_ctr (for
+// instance with the copy that uploads the tile list).
 hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg, int der,
                         const TileDev *tiles_dev, int n_tiles, int grid, int lds_bytes,
-                        double *contrib, unsigned *counters, unsigned *work_ctr, hipStream_t s);
+                        double *contrib, unsigned *counters, unsigned *work_ctr, hipStream_t s,
+                        bool clear_work = true);
 hipError_t launch_fill_zero_u32(unsigned *p, size_t n, hipStream_t s);
 // Vertex families (2, 3, 5), float64: jac[e * r.nZ + i] = dI_e/dZ_i for every point of r
 // (workgroups per point and 64-entry slice of the table; r needs a dressing table).

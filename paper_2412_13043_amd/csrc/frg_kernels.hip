@@ -1374,10 +1374,13 @@ int multi_grid(int n_tiles, int fam, int prec, int reg, int der, int lds_bytes, 
 
 hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg, int der,
                         const TileDev *tiles_dev, int n_tiles, int grid, int lds_bytes,
-                        double *contrib, unsigned *counters, unsigned *work_ctr, hipStream_t s) {
+                        double *contrib, unsigned *counters, unsigned *work_ctr, hipStream_t s,
+                        bool clear_work) {
     if (n_tiles <= 0) return hipSuccess;
-    const hipError_t e = launch_fill_zero_u32(work_ctr, 2, s);
-    if (e != hipSuccess) return e;
+    if (clear_work) {
+        const hipError_t e = launch_fill_zero_u32(work_ctr, 2, s);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(multi_variant(fam, prec, reg, der), dim3(grid), dim3(kWave), lds_bytes, s,
                        reqs_dev, tiles_dev, n_tiles, contrib, counters, work_ctr);
     return hipGetLastError();

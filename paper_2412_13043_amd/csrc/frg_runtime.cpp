@@ -467,11 +467,61 @@ static int ilog2(int v) {
     return r;
 }
 
+// Tile shape of a vertex request launched alone, by a cost estimate over every shape: lanes per
+// point over radial nodes (lq) and cos1 nodes (lx), points per wavefront (le = 64 / (lq lx))
+// and radial chunks (c).  A wavefront runs its lanes in lockstep, so its time is the longest
+// lane's work W = ceil(ceil(n_q / c) / lq) ceil(n_x / lx) n_phi node evaluations (radial and
+// cos1 node counts that are not multiples of the lanes leave lanes idle in the last round); T
+// = ceil(n_ext / le) c wavefronts spread over the SIMDs (target_waves / 4 of them), m =
+// ceil(T / SIMDs) per SIMD, and a SIMD with m wavefronts gets through rate(m) of its issue
+// rate (one wavefront cannot hide its own latencies).  Estimate: m (W + per-tile set-up) /
+// rate(m), plus the radial-sum pass when c > 1; the two-point families pay ~35 % more per node
+// when they share cos1 nodes across lanes (their inner sums are short).
+static TileShape request_shape_search(const frg_integral_desc &d, int n_ext, int target_waves) {
+    const double simds = std::max(1, target_waves / 4);
+    const int nphi = d.family == 3 ? d.n_phi : 1;
+    auto rate = [](double m) { return m >= 4 ? 1.0 : (m >= 3 ? 0.95 : (m >= 2 ? 0.85 : 0.6)); };
+    constexpr double kTileSetup = 20.0;   // node evaluations' worth per tile
+    constexpr double kRadialSums = 40.0;  // the extra launch and contribution round trip
+    TileShape best;
+    double best_t = 1e300;
+    for (int lql = 6; lql >= 0; --lql) {
+        const int lq = 1 << lql;
+        if (lq > d.n_q && lql > 0) continue;
+        for (int lxl = 0; lql + lxl <= 6; ++lxl) {
+            const int lx = 1 << lxl;
+            if (lx > d.n_x && lxl > 0) break;
+            const int le = kWave >> (lql + lxl);
+            const long long et = (n_ext + le - 1) / le;
+            const int max_c = std::max(1, std::min(d.n_q / lq, 64));
+            for (int c = 1; c <= max_c; ++c) {
+                const long long rq = ((d.n_q + c - 1) / c + lq - 1) / lq;
+                const long long rx = (d.n_x + lx - 1) / lx;
+                double W = (double)rq * (double)rx * nphi;
+                if (d.family != 3 && lx > 1) W *= 1.35;
+                const double T = (double)et * c;
+                const double m = std::ceil(T / simds);
+                const double t = m * (W + kTileSetup) / rate(m) + (c > 1 ? kRadialSums : 0.0);
+                // ties: more radial lanes, then fewer chunks
+                if (t < best_t * (1.0 - 1e-9)) {
+                    best_t = t;
+                    best.lq_log2 = lql;
+                    best.lx_log2 = lxl;
+                    best.chunks = c;
+                }
+            }
+        }
+    }
+    return best;
+}
+
 TileShape heuristic_shape(const frg_integral_desc &desc, int n_ext, int target_waves,
                           bool allow_chunks, bool fused) {
     TileShape s;
     const frg_integral_desc d = plan_desc(desc);
     if (d.family == 1) return s;
+    // a request launched alone: the estimate over every shape
+    if (allow_chunks && !fused) return request_shape_search(d, n_ext, target_waves);
     // external points per wavefront: the smallest power of two >= n_ext, at least 4
     int le = kWave;
     while (le > 4 && le / 2 >= n_ext) le /= 2;

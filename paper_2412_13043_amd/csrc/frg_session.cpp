@@ -1,25 +1,36 @@
 // Serving loop: continuous batching of loop-integral requests from many concurrent clients.
 //
-// Requests are queued by frg_session_submit.  A scheduler thread admits queued requests while
-// their device footprint (inputs and outputs, 256-byte aligned) fits in the session's HBM arena,
-// packs them into one fused launch of the multi-request tile consumer on a free launch slot, and
-// keeps up to max_inflight such launches on separate streams: requests that arrive while others
-// run are admitted as memory and slots free up, and their work overlaps on the device.
+// Requests are queued by frg_session_submit.  A scheduler thread packs queued requests into one
+// fused launch of the multi-request tile consumer on a free launch slot, and keeps up to
+// max_inflight such launches on separate streams: requests that arrive while others run join
+// the next launch as slots and memory free up, and their work overlaps on the device.
+//
+// Memory: each launch takes one block of the session's HBM arena (hbm_budget_bytes) holding
+// everything it touches -- the tile counter, the request and tile tables, the requests' inputs,
+// the float32 form's amplification slots, the outputs and, for radially chunked shapes, the
+// [n_q][n_ext] contributions -- so admission is by device footprint: a launch is only formed
+// while its block fits the arena.  One copy uploads the block's first part (tables, inputs, the
+// zeroed counter and slots) from the slot's pinned staging, one copy brings the outputs back:
+// a launch is upload, the fused kernel, the radial sums of chunked requests, download, event.
 //
 // Scheduling rules:
 //   - a launch holds at most kLaunchNodes integrand nodes (a few tenths of a millisecond of the
 //     chip), so small requests never queue behind a long launch for long;
-//   - a request larger than that is cut into parts by external tiles; each part is its own tile
-//     range of one fused launch, the first one stages the request's inputs, the following ones
-//     (at most kPartsInFlight at a time) run once the first has completed; every point is
-//     computed inside one tile, so the result does not depend on the cut;
-//   - arrival order, except that requests that fit may be admitted ahead of an earlier one that
-//     does not fit the arena yet, at most kMaxBypass times per blocked request;
-//   - slots hold pinned host staging and device tables allocated when the session opens; the
-//     launch path allocates nothing.
-// A finished launch's outputs are copied back to the clients' host buffers before their tickets
-// complete.  Each result is computed exactly as frg_integrate_batch would compute it (results do
-// not depend on batch composition or tile shape).
+//   - a larger request is cut into parts of whole external tiles (multiples of 64 points for
+//     chunked shapes, whose radial sums run per block of 64 points), each part a launch share
+//     of its own with its own copy of the request's inputs, at most kPartsInFlight at once;
+//     every point is computed inside one tile, so the result does not depend on the cut;
+//   - every request keeps the tile shape frg_integrate_batch gives it alone;
+//   - small requests (at most kSmallNodes) are launched first, then large ones, each class in
+//     arrival order and in launches of their own; large requests hold at most half the slots
+//     (rounded up), so a small request arriving while large launches run finds a free slot;
+//   - launches run one workgroup per tile (no persistent grid), so concurrent launches share the
+//     CUs tile by tile and a new small launch starts as soon as any running tile ends;
+//   - requests that fit may go ahead of an earlier one that does not fit the arena yet, at most
+//     kMaxBypass times per blocked request;
+//   - pinned staging is allocated when the session opens; launching allocates nothing.
+// Each result is computed exactly as frg_integrate_batch would compute it (results do not depend
+// on batch composition, tile shape or the cut into parts).
 //
 // Execution goes through an Executor interface: the HIP executor, and a test double that runs
 // no device work and completes a launch after a delay proportional to its node count, used by
@@ -48,12 +59,12 @@ static double now_us() {
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 constexpr size_t kMaxLaunchReqs = 512;       // requests (or parts) per launch
-constexpr size_t kMaxLaunchTiles = 1 << 17;  // tiles per launch
+constexpr size_t kMaxLaunchTiles = 1 << 17;  // tiles (and radial-sum blocks) per launch
 constexpr double kLaunchNodes = 2.0e8;       // integrand nodes per launch (~0.35 ms)
 constexpr int kPartsInFlight = 2;            // parts of one request launched at once
 constexpr int kMaxBypass = 64;               // admissions ahead of a request blocked on memory
-constexpr size_t kSlotTables =
-    ((kMaxLaunchReqs * sizeof(ReqDev) + 255) & ~(size_t)255) + kMaxLaunchTiles * sizeof(TileDev);
+constexpr double kSmallNodes = 1.0e8;        // small requests: scheduled first (~0.2 ms alone)
+constexpr size_t kCounterBytes = 256;        // the fused kernel's tile counter, at block start
 
 enum ReqState { RQ_QUEUED = 0, RQ_RUNNING, RQ_DONE, RQ_FAILED, RQ_CANCELLED };
 
@@ -63,28 +74,22 @@ struct SessReq {
     frg_batch host{};    // host pointers from the client
     int table_id = -1;
     int n_ext_vals = 0;  // doubles in ext
-    // device layout inside the request's arena block (byte offsets): inputs, outputs, and for
-    // radially chunked shapes the [n_q][n_ext] contributions and the float32 form's slots
-    size_t off_ext = 0, off_m2 = 0, off_z = 0, off_out = 0, off_err = 0, off_contrib = 0,
-           off_ctr = 0;
-    size_t in_bytes = 0;   // ext + m2 + Z, contiguous from offset 0
-    size_t out_bytes = 0;  // out (+ err) staged back to the host
-    size_t footprint = 0;  // whole block
-    size_t arena_off = (size_t)-1;
+    // inputs as laid out in a launch block (byte offsets from the part's input area): ext, m2,
+    // the request's own dressing table
+    size_t in_ext = 0, in_m2 = 0, in_z = 0, in_bytes = 0;
+    size_t slot_bytes = 0;     // float32 amplification slots of a chunked shape (n_ext + 1)
+    size_t contrib_bytes = 0;  // [n_q][n_ext] contributions of a chunked shape
+    size_t footprint = 0;      // device bytes of the whole request in one launch (no tables)
     uint64_t nodes = 0;
     double t_submit = 0.0, t_done = 0.0;
     ReqState state = RQ_QUEUED;
     frg_status status = FRG_OK;
     bool timed_out = false;
     // tile shape (chosen at submit: the one frg_integrate_batch takes for the request alone),
-    // its external tiles and the next one to launch; a request larger than one launch
-    // (split = true) goes in parts of whole external tiles (multiples of align_tiles: 64 points
-    // for chunked shapes, whose radial sums run per block of 64 points), at most
-    // kPartsInFlight at a time once the first has staged the inputs
+    // its external tiles and the next one to launch; split: more than one launch's work
     TileShape shape{};
     bool split = false, chunked = false;
     int ext_tiles = 0, points_per_tile = 0, align_tiles = 1, next_et = 0, parts_inflight = 0;
-    bool inputs_ready = false;
     int bypassed = 0;  // admissions ahead of it while it could not be admitted
     // clients blocked in frg_session_wait on this ticket, and whether one of them (or a poll)
     // has been told the outcome (the ticket is forgotten once nothing refers to it any more)
@@ -134,6 +139,11 @@ class Arena {
             }
         }
     }
+    size_t largest_free() const {
+        size_t m = 0;
+        for (const auto &f : free_) m = std::max(m, f.second);
+        return m;
+    }
     size_t capacity() const { return cap_; }
     size_t used() const { return used_; }
 
@@ -142,27 +152,34 @@ class Arena {
     std::map<size_t, size_t> free_;
 };
 
-// One request's share of a launch: its external tiles [et0, et1) (all of them unless split).
+// One request's share of a launch: its external tiles [et0, et1), points [p0, p1), and where
+// its inputs, slots, outputs and contributions sit in the launch block (byte offsets).
 struct Part {
     SessReq *r = nullptr;
     int et0 = 0, et1 = 0;
-    bool stage_inputs = false;  // this launch copies the request's inputs to the device
-    size_t host_in = 0, host_out = 0;  // staging offsets
-    int p0 = 0, p1 = 0;                // points [p0, p1) whose outputs come back
-    frg_log_table resident{};          // the session-resident dressing table, if the request uses one
+    int p0 = 0, p1 = 0;
+    size_t in = 0, slots = 0, out = 0, contrib = 0;
+    frg_log_table resident{};  // the session-resident dressing table, if the request uses one
 };
 
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    DeviceBuffer tables;    // ReqDev[] then TileDev[]
-    DeviceBuffer work;      // fused-launch tile counter (cleared ahead of each launch)
-    void *host = nullptr;   // pinned staging: tables, inputs, outputs
+    void *host = nullptr;  // pinned staging of the launch block's uploaded and downloaded parts
     size_t host_bytes = 0;
     std::vector<Part> parts;
-    bool busy = false;
-    double t_launch = 0.0;
+    // the launch block: arena offset and size; its layout (tables, then the parts' inputs and
+    // slots = the upload, then their outputs = the download, then contributions)
+    size_t block_off = (size_t)-1, block_bytes = 0;
+    size_t tables_bytes = 0, upload_bytes = 0, out_begin = 0, out_end = 0;
+    int n_tiles = 0;
+    bool large = false;  // holds a part of a request above kSmallNodes
+    bool busy = false;   // a launch is assigned (planned, running or being completed)
+    bool assigned = false;  // planned, not yet picked up by the slot's worker
+    double t_plan = 0.0, t_launch = 0.0, t_enqueued = 0.0;
     double fake_ready = 0.0;  // test double: completion time
+    std::thread worker;
+    std::condition_variable cv;  // the worker: a launch is assigned, or the session closes
     ~Slot() {
         if (host) (void)hipHostFree(host);
         if (done) (void)hipEventDestroy(done);
@@ -215,7 +232,7 @@ class Executor {
     virtual int poll(frg_session &, Slot &) = 0;  // 1 done, 0 running, -1 device error
     virtual void finish(frg_session &, Slot &) = 0;
     // after a failed launch: wait until nothing queued on the slot's stream can still touch its
-    // staging or the requests' arena blocks
+    // staging or its launch block
     virtual void drain(Slot &) = 0;
 };
 
@@ -244,6 +261,9 @@ struct frg_session {
     frg::LatencyHist lat;
     uint64_t admitted = 0, rejected = 0, completed = 0, failed = 0, cancelled = 0, nodes_done = 0,
              launches = 0;
+    // per completed request: submit -> its last launch planned, planned -> enqueued on the
+    // device, enqueued -> seen complete, seen complete -> result in the client's buffer
+    double sum_queue_us = 0.0, sum_launch_us = 0.0, sum_device_us = 0.0, sum_finish_us = 0.0;
     double t_first = 0.0, t_last = 0.0;
     std::string fatal;
 };
@@ -254,6 +274,14 @@ namespace frg {
 static void part_points(const SessReq &r, int et0, int et1, int *p0, int *p1) {
     *p0 = std::min(et0 * r.points_per_tile, r.host.n_ext);
     *p1 = std::min(et1 * r.points_per_tile, r.host.n_ext);
+}
+
+static size_t part_out_bytes(const SessReq &r, int p0, int p1) {
+    return align256((r.host.err_out ? 2 : 1) * (size_t)(p1 - p0) * sizeof(double));
+}
+
+static size_t tables_bytes(size_t n_parts, size_t n_tiles) {
+    return kCounterBytes + align256(n_parts * sizeof(ReqDev)) + align256(n_tiles * sizeof(TileDev));
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -267,45 +295,45 @@ class HipExecutor : public Executor {
         for (auto &sl : s.slots) {
             FRG_HIP_CHECK(hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking));
             FRG_HIP_CHECK(hipEventCreateWithFlags(&sl->done, hipEventDisableTiming));
-            FRG_HIP_CHECK(sl->work.alloc(2 * sizeof(unsigned)));
-            FRG_HIP_CHECK(sl->tables.alloc(kSlotTables));
             FRG_HIP_CHECK(hipHostMalloc(&sl->host, s.staging_bytes, hipHostMallocDefault));
             sl->host_bytes = s.staging_bytes;
-            FRG_HIP_CHECK(launch_fill_zero_u32((unsigned *)sl->work.ptr, 2, sl->stream));
-            FRG_HIP_CHECK(hipStreamSynchronize(sl->stream));
         }
         return FRG_OK;
     }
 
     frg_status launch(frg_session &s, Slot &sl) override {
         frg_context *ctx = s.ctx;
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        FRG_HIP_CHECK(hipSetDevice(ctx->device));
-        char *base = (char *)s.arena_mem.ptr;
+        char *blk = (char *)s.arena_mem.ptr + sl.block_off;  // device launch block
+        char *h = (char *)sl.host;                           // its staging on the host
         std::vector<ReqDev> rd;
         std::vector<std::pair<int, int>> ranges;
+        // the context lock only for the requests' rules (the cache); the slot's own stream,
+        // staging and block need no lock
+        std::unique_lock<std::mutex> ctx_lk(ctx->mu);
         for (const Part &pt : sl.parts) {
             SessReq *r = pt.r;
             frg_batch b = r->host;
-            char *blk = base + r->arena_off;
-            b.ext = is_vertex(r->desc.family) ? (const double *)(blk + r->off_ext) : nullptr;
-            b.m2 = r->host.m2 ? (const double *)(blk + r->off_m2) : nullptr;
-            b.out = (double *)(blk + r->off_out);
-            b.err_out = r->host.err_out ? (double *)(blk + r->off_err) : nullptr;
-            if (r->table_id >= 0) {
+            const char *in = blk + pt.in;
+            b.ext = is_vertex(r->desc.family) ? (const double *)(in + r->in_ext) : nullptr;
+            b.m2 = r->host.m2 ? (const double *)(in + r->in_m2) : nullptr;
+            // outputs of points [p0, p1) land at the part's output area
+            b.out = (double *)(blk + pt.out) - pt.p0;
+            b.err_out = r->host.err_out ? (double *)(blk + pt.out) + (pt.p1 - pt.p0) - pt.p0
+                                        : nullptr;
+            if (r->table_id >= 0)
                 b.Z = pt.resident;
-            } else if (r->host.Z.values) {
-                b.Z.values = (const double *)(blk + r->off_z);
-            }
+            else if (r->host.Z.values)
+                b.Z.values = (const double *)(in + r->in_z);
             ReqDev q;
             frg_status st = make_request(ctx, r->desc, b, r->shape, 1, 0.0, 1.0, &q);
             if (st != FRG_OK) return st;
-            // contributions and slots inside the request's block, addressed from the arena base
-            q.contrib_base = (long long)((r->arena_off + r->off_contrib) / sizeof(double));
-            q.ctr_base = (long long)((r->arena_off + r->off_ctr) / sizeof(unsigned));
+            // contributions and slots in the block, addressed from the block's start
+            q.contrib_base = (long long)(pt.contrib / sizeof(double));
+            q.ctr_base = (long long)(pt.slots / sizeof(unsigned));
             rd.push_back(q);
             ranges.emplace_back(pt.et0, pt.et1);
         }
+        ctx_lk.unlock();
         int lds = 0;
         std::vector<TileDev> tiles = make_tiles(rd, &lds, &ranges);
         const size_t n_work = tiles.size();
@@ -318,57 +346,43 @@ class HipExecutor : public Executor {
                 tiles.push_back(TileDev{(int)i, b, 0, 0});
         }
         const int n_fin = (int)(tiles.size() - n_work);
-        const size_t tiles_off = align256(rd.size() * sizeof(ReqDev));
-        const size_t tb = tiles_off + tiles.size() * sizeof(TileDev);
-        if (tb > kSlotTables) {
-            set_error("internal: launch tables exceed the slot's preallocated tables");
+        if ((int)tiles.size() != sl.n_tiles) {
+            set_error("internal: launch planned for %d tiles, built %zu", sl.n_tiles, tiles.size());
             return FRG_E_INVAL;
         }
-        char *h = (char *)sl.host;
-        std::memcpy(h, rd.data(), rd.size() * sizeof(ReqDev));
+        // upload area: counter (zero) | request table | tile table | inputs and zeroed slots
+        const size_t reqs_off = kCounterBytes;
+        const size_t tiles_off = reqs_off + align256(rd.size() * sizeof(ReqDev));
+        std::memset(h, 0, kCounterBytes);
+        std::memcpy(h + reqs_off, rd.data(), rd.size() * sizeof(ReqDev));
         std::memcpy(h + tiles_off, tiles.data(), tiles.size() * sizeof(TileDev));
-        FRG_HIP_CHECK(hipMemcpyAsync(sl.tables.ptr, h, tb, hipMemcpyHostToDevice, sl.stream));
         for (const Part &pt : sl.parts) {
             SessReq *r = pt.r;
-            if (!pt.stage_inputs) continue;
-            char *dst = h + pt.host_in;
-            const int n = r->host.n_ext;
+            char *in = h + pt.in;
             if (is_vertex(r->desc.family))
-                std::memcpy(dst + r->off_ext, r->host.ext, (size_t)r->n_ext_vals * 8);
-            if (r->host.m2) std::memcpy(dst + r->off_m2, r->host.m2, (size_t)n * 8);
+                std::memcpy(in + r->in_ext, r->host.ext, (size_t)r->n_ext_vals * 8);
+            if (r->host.m2) std::memcpy(in + r->in_m2, r->host.m2, (size_t)r->host.n_ext * 8);
             if (r->table_id < 0 && r->host.Z.values && is_vertex(r->desc.family))
-                std::memcpy(dst + r->off_z, r->host.Z.values, (size_t)r->host.Z.n * 8);
-            if (r->in_bytes)
-                FRG_HIP_CHECK(hipMemcpyAsync(base + r->arena_off, dst, r->in_bytes,
-                                             hipMemcpyHostToDevice, sl.stream));
-            // the float32 form's amplification slots of a chunked request start at zero (the
-            // radial sums leave them at zero again)
-            if (r->chunked && r->desc.precision == FRG_FP32_KAHAN)
-                FRG_HIP_CHECK(launch_fill_zero_u32((unsigned *)(base + r->arena_off + r->off_ctr),
-                                                   (size_t)n + 1, sl.stream));
+                std::memcpy(in + r->in_z, r->host.Z.values, (size_t)r->host.Z.n * 8);
+            if (r->slot_bytes) std::memset(h + pt.slots, 0, r->slot_bytes);
         }
-        const ReqDev *reqs_dev = (const ReqDev *)sl.tables.ptr;
-        const TileDev *tiles_dev = (const TileDev *)((char *)sl.tables.ptr + tiles_off);
+        FRG_HIP_CHECK(hipMemcpyAsync(blk, h, sl.upload_bytes, hipMemcpyHostToDevice, sl.stream));
+        const ReqDev *reqs_dev = (const ReqDev *)(blk + reqs_off);
+        const TileDev *tiles_dev = (const TileDev *)(blk + tiles_off);
         int fam, prec, reg, der;
         common_kind(rd, &fam, &prec, &reg, &der);
-        const int grid = multi_grid((int)n_work, fam, prec, reg, der, lds, ctx->num_cus);
+        // one workgroup per tile: the launches of the slots interleave on the CUs tile by
+        // tile, so a small launch starts while large ones run (a persistent grid would hold
+        // its CU slots until its whole tile list is done)
+        const int grid = (int)n_work;
         FRG_HIP_CHECK(launch_multi(reqs_dev, fam, prec, reg, der, tiles_dev, (int)n_work, grid,
-                                   lds, (double *)base, (unsigned *)base,
-                                   (unsigned *)sl.work.ptr, sl.stream));
+                                   lds, (double *)blk, (unsigned *)blk, (unsigned *)blk,
+                                   sl.stream, false));
         FRG_HIP_CHECK(launch_multi_finalize(reqs_dev, tiles_dev + n_work, n_fin,
-                                            (const double *)base, (unsigned *)base, sl.stream));
-        for (const Part &pt : sl.parts) {
-            const SessReq *r = pt.r;
-            const size_t n = (size_t)(pt.p1 - pt.p0);
-            if (n == 0) continue;
-            const char *blk = base + r->arena_off;
-            FRG_HIP_CHECK(hipMemcpyAsync(h + pt.host_out, blk + r->off_out + 8 * (size_t)pt.p0,
-                                         n * 8, hipMemcpyDeviceToHost, sl.stream));
-            if (r->host.err_out)
-                FRG_HIP_CHECK(hipMemcpyAsync(h + pt.host_out + n * 8,
-                                             blk + r->off_err + 8 * (size_t)pt.p0, n * 8,
-                                             hipMemcpyDeviceToHost, sl.stream));
-        }
+                                            (const double *)blk, (unsigned *)blk, sl.stream));
+        FRG_HIP_CHECK(hipMemcpyAsync(h + sl.out_begin, blk + sl.out_begin,
+                                     sl.out_end - sl.out_begin, hipMemcpyDeviceToHost,
+                                     sl.stream));
         FRG_HIP_CHECK(hipEventRecord(sl.done, sl.stream));
         return FRG_OK;
     }
@@ -387,8 +401,8 @@ class HipExecutor : public Executor {
             const SessReq *r = pt.r;
             if (r->timed_out || r->state != RQ_RUNNING) continue;
             const size_t n = (size_t)(pt.p1 - pt.p0);
-            std::memcpy(r->host.out + pt.p0, h + pt.host_out, n * 8);
-            if (r->host.err_out) std::memcpy(r->host.err_out + pt.p0, h + pt.host_out + n * 8, n * 8);
+            std::memcpy(r->host.out + pt.p0, h + pt.out, n * 8);
+            if (r->host.err_out) std::memcpy(r->host.err_out + pt.p0, h + pt.out + n * 8, n * 8);
         }
     }
 
@@ -423,8 +437,7 @@ class FakeExecutor : public Executor {
 // ---------------------------------------------------------------------------------------------
 // A ticket whose outcome a client has been told and that nothing refers to any more is dropped.
 static void maybe_forget(frg_session &s, SessReq *r) {
-    if (r->reported && r->waiters == 0 && r->terminal() && r->parts_inflight == 0 &&
-        r->arena_off == Arena::npos && r->state != RQ_QUEUED)
+    if (r->reported && r->waiters == 0 && r->terminal() && r->parts_inflight == 0)
         s.reqs.erase(r->ticket);
 }
 
@@ -451,134 +464,187 @@ static void end_request(frg_session &s, SessReq *r, ReqState state, frg_status s
     r->cv.notify_all();
 }
 
-static void complete_slot(frg_session &s, Slot &sl, bool ok) {
+// Bookkeeping after a launch ended (outputs already copied to the clients' buffers if ok).
+static void complete_slot(frg_session &s, Slot &sl, bool ok, double t_seen) {
     const double t = now_us();
-    if (ok) s.exec->finish(s, sl);
+    if (sl.block_off != Arena::npos) {
+        s.arena.release(sl.block_off, sl.block_bytes);
+        sl.block_off = Arena::npos;
+    }
     for (const Part &pt : sl.parts) {
         SessReq *r = pt.r;
         r->parts_inflight--;
-        if (ok && pt.stage_inputs) r->inputs_ready = true;
         if (!ok) {
             remove_from_queue(s, r);  // no further parts
             end_request(s, r, RQ_FAILED, FRG_E_DEVICE, t);
         }
-        const bool all_launched = r->next_et >= r->ext_tiles || r->terminal();
-        if (r->parts_inflight == 0 && all_launched) {
-            if (r->arena_off != Arena::npos) {
-                s.arena.release(r->arena_off, r->footprint);
-                r->arena_off = Arena::npos;
-            }
-            end_request(s, r, RQ_DONE, FRG_OK, t);  // no-op if it already failed or timed out
+        if (r->parts_inflight == 0 && (r->next_et >= r->ext_tiles || r->terminal()) &&
+            !r->terminal()) {
+            s.sum_queue_us += sl.t_plan - r->t_submit;
+            s.sum_launch_us += sl.t_enqueued - sl.t_plan;
+            s.sum_device_us += t_seen - sl.t_enqueued;
+            s.sum_finish_us += t - t_seen;
+            end_request(s, r, RQ_DONE, FRG_OK, t);
         }
         maybe_forget(s, r);
     }
     sl.parts.clear();
     sl.busy = false;
+    s.sched_cv.notify_all();  // a slot and arena memory are free
 }
 
-// Staging bytes a part takes in a slot: the request's inputs (first part only) and the part's
-// outputs.
-static size_t part_staging(const SessReq &r, int p0, int p1, bool inputs) {
-    const size_t n = (size_t)(p1 - p0);
-    return (inputs ? align256(r.in_bytes) : 0) + align256((r.host.err_out ? 2 : 1) * n * 8);
-}
-
-// Choose the parts of one launch for a free slot; false if there is nothing to launch.
+// Choose the parts of one launch for a free slot and place them in one arena block; false if
+// there is nothing to launch.  Small requests (at most kSmallNodes) go first, in arrival order,
+// and a launch with small requests takes no large ones; large requests hold at most half the
+// slots (rounded up), so a small request that arrives while large launches run finds a slot.
 static bool plan_launch(frg_session &s, Slot &sl) {
+    // room for one launch block: the arena's largest free range and the slot's staging
+    const size_t room = s.arena.largest_free();
+    int large_running = 0;
+    for (const auto &x : s.slots)
+        if (x->busy && x->large) ++large_running;
+    const bool large_ok = large_running < std::max(1, ((int)s.slots.size() + 1) / 2);
     double nodes = 0.0;
-    size_t tiles = 0;
-    size_t stage = kSlotTables;  // the staging area starts with the launch tables
-    SessReq *blocked = nullptr;  // the earliest request that did not fit the arena
-    std::vector<SessReq *> done_launching, failed;
-    for (size_t qi = 0; qi < s.queue.size() && sl.parts.size() < kMaxLaunchReqs; ++qi) {
-        SessReq *r = s.queue[qi];
-        const bool admitted = r->arena_off != Arena::npos;
-        // a split request whose first part, or enough parts, are still running
-        if (admitted && (!r->inputs_ready || r->parts_inflight >= kPartsInFlight)) continue;
-        const double npp = nodes_per_point(r->desc);
-        const int remaining = r->ext_tiles - r->next_et;
-        const size_t per_tile = (size_t)r->shape.chunks;  // work tiles per external tile
-        int k;
-        if (!r->split) {
-            if (!sl.parts.empty() && nodes + (double)r->nodes > kLaunchNodes) break;
-            k = remaining;
-        } else {
-            // as many whole tiles as the launch has room for, in multiples of align_tiles (at
-            // least one multiple)
-            const double tile_nodes = (double)r->points_per_tile * npp;
-            const int a = r->align_tiles;
-            k = (int)std::floor((kLaunchNodes - nodes) / tile_nodes);
-            k = std::min<long long>(k, (long long)((kMaxLaunchTiles - tiles) / per_tile));
-            k = (k / a) * a;
-            if (k < a) {
-                if (!sl.parts.empty()) break;
-                k = a;
+    size_t n_tiles = 0, data = 0, upload_data = 0, out_data = 0;
+    SessReq *blocked = nullptr;  // the earliest request that did not fit
+    bool full = false, large = false;
+    std::vector<SessReq *> done_launching;
+    struct Pick {
+        SessReq *r;
+        int et0, et1, p0, p1;
+    };
+    std::vector<Pick> picks;
+    for (int pass = 0; pass < 2 && !full; ++pass) {
+        // a launch holds small requests or large ones, not both (a small request in a launch
+        // with a large part would wait for the part)
+        if (pass == 1 && (!large_ok || !picks.empty())) break;
+        for (size_t qi = 0; qi < s.queue.size() && !full; ++qi) {
+            if (picks.size() >= kMaxLaunchReqs) {
+                full = true;
+                break;
             }
-            k = std::min(k, remaining);
-        }
-        Part pt;
-        pt.r = r;
-        pt.stage_inputs = r->next_et == 0;
-        pt.et0 = r->next_et;
-        pt.et1 = r->next_et + k;
-        part_points(*r, pt.et0, pt.et1, &pt.p0, &pt.p1);
-        const size_t fin = r->chunked ? (size_t)(pt.p1 - pt.p0 + kWave - 1) / kWave : 0;
-        const size_t pt_tiles = (size_t)k * per_tile + fin;
-        const size_t pst = part_staging(*r, pt.p0, pt.p1, pt.stage_inputs);
-        if (tiles + pt_tiles > kMaxLaunchTiles || stage + pst > s.staging_bytes) {
-            if (sl.parts.empty()) {
-                failed.push_back(r);  // cannot happen for requests accepted at submit
+            SessReq *r = s.queue[qi];
+            if (((double)r->nodes > kSmallNodes) != (pass == 1)) continue;
+            const bool started = r->next_et > 0;
+            if (started && r->parts_inflight >= kPartsInFlight) continue;
+            const double npp = nodes_per_point(r->desc);
+            const int remaining = r->ext_tiles - r->next_et;
+            const size_t per_tile = (size_t)r->shape.chunks;  // work tiles per external tile
+            int k;
+            if (!r->split) {
+                if (!picks.empty() && nodes + (double)r->nodes > kLaunchNodes) {
+                    full = true;
+                    break;
+                }
+                k = remaining;
+            } else {
+                // as many whole tiles as the launch has room for, in multiples of align_tiles
+                // (at least one multiple)
+                const double tile_nodes = (double)r->points_per_tile * npp;
+                const int a = r->align_tiles;
+                k = (int)std::floor((kLaunchNodes - nodes) / tile_nodes);
+                k = (int)std::min<long long>(k,
+                                             (long long)((kMaxLaunchTiles - n_tiles) / per_tile));
+                k = (k / a) * a;
+                if (k < a) {
+                    if (!picks.empty()) {
+                        full = true;
+                        break;
+                    }
+                    k = a;
+                }
+                k = std::min(k, remaining);
+            }
+            int p0, p1;
+            part_points(*r, r->next_et, r->next_et + k, &p0, &p1);
+            const size_t fin = r->chunked ? (size_t)(p1 - p0 + kWave - 1) / kWave : 0;
+            const size_t pt_tiles = (size_t)k * per_tile + fin;
+            const size_t up = align256(r->in_bytes) + align256(r->slot_bytes);
+            const size_t down = part_out_bytes(*r, p0, p1);
+            const size_t tb = tables_bytes(picks.size() + 1, n_tiles + pt_tiles);
+            const size_t need_block = tb + data + up + down + align256(r->contrib_bytes);
+            const size_t need_stage = tb + upload_data + up + out_data + down;
+            if (n_tiles + pt_tiles > kMaxLaunchTiles || need_stage > s.staging_bytes) {
+                if (!picks.empty()) {
+                    full = true;
+                    break;
+                }
+                continue;  // cannot happen for a request accepted at submit
+            }
+            if (need_block > room) {
+                if (!picks.empty()) {
+                    full = true;  // the launch is full
+                    break;
+                }
+                // it does not fit the arena right now: later requests may go ahead of it, a
+                // bounded number of times
+                if (!blocked && !started) blocked = r;
                 continue;
             }
-            break;
-        }
-        if (!admitted) {
-            // a new admission: after kMaxBypass of them ahead of a request that does not fit
-            // the arena, wait for it (parts of admitted requests still go ahead: they free
-            // the memory it waits for)
-            if (blocked && blocked->bypassed >= kMaxBypass) continue;
-            const size_t off = s.arena.alloc(r->footprint);
-            if (off == Arena::npos) {
-                if (!blocked) blocked = r;
-                continue;
+            if (!started) {
+                if (blocked && blocked->bypassed >= kMaxBypass) continue;
+                r->state = RQ_RUNNING;
+                s.admitted++;
+                if (blocked) blocked->bypassed++;
             }
-            r->arena_off = off;
-            r->state = RQ_RUNNING;
-            s.admitted++;
-            if (blocked) blocked->bypassed++;
+            picks.push_back(Pick{r, r->next_et, r->next_et + k, p0, p1});
+            n_tiles += pt_tiles;
+            data += up + down + align256(r->contrib_bytes);
+            upload_data += up;
+            out_data += down;
+            nodes += (double)(p1 - p0) * npp;
+            large = large || pass == 1;
+            r->parts_inflight++;
+            r->next_et += k;
+            if (r->next_et >= r->ext_tiles) done_launching.push_back(r);
+            if (nodes >= kLaunchNodes) full = true;
         }
-        if (pt.stage_inputs) {
-            pt.host_in = stage;
-            stage += align256(r->in_bytes);
-        }
-        pt.host_out = stage;
-        stage += align256((r->host.err_out ? 2 : 1) * (size_t)(pt.p1 - pt.p0) * 8);
-        if (r->table_id >= 0) {
-            const ResidentTable &t = *s.tables[r->table_id];
-            pt.resident = frg_log_table{(const double *)t.buf.ptr, t.n, t.x_min, t.x_max};
-        }
-        tiles += pt_tiles;
-        nodes += (double)(pt.p1 - pt.p0) * npp;
-        r->parts_inflight++;
-        r->next_et = pt.et1;
-        if (r->next_et >= r->ext_tiles) done_launching.push_back(r);
-        sl.parts.push_back(pt);
-        if (nodes >= kLaunchNodes) break;
     }
     for (SessReq *r : done_launching) remove_from_queue(s, r);
-    for (SessReq *r : failed) {
-        remove_from_queue(s, r);
-        if (r->arena_off != Arena::npos && r->parts_inflight == 0) {
-            s.arena.release(r->arena_off, r->footprint);
-            r->arena_off = Arena::npos;
+    if (picks.empty()) return false;
+    sl.large = large;
+    // block layout: tables | inputs and slots of every part (upload) | outputs (download) |
+    // contributions
+    const size_t tb = tables_bytes(picks.size(), n_tiles);
+    size_t pos = tb;
+    sl.parts.clear();
+    for (const Pick &pk : picks) {
+        Part pt;
+        pt.r = pk.r;
+        pt.et0 = pk.et0;
+        pt.et1 = pk.et1;
+        pt.p0 = pk.p0;
+        pt.p1 = pk.p1;
+        pt.in = pos;
+        pos += align256(pk.r->in_bytes);
+        pt.slots = pos;
+        pos += align256(pk.r->slot_bytes);
+        if (pk.r->table_id >= 0) {
+            const ResidentTable &t = *s.tables[pk.r->table_id];
+            pt.resident = frg_log_table{(const double *)t.buf.ptr, t.n, t.x_min, t.x_max};
         }
-        end_request(s, r, RQ_FAILED, FRG_E_NOMEM, now_us());
-        maybe_forget(s, r);
+        sl.parts.push_back(pt);
     }
-    return !sl.parts.empty();
+    sl.upload_bytes = pos;
+    sl.out_begin = pos;
+    for (Part &pt : sl.parts) {
+        pt.out = pos;
+        pos += part_out_bytes(*pt.r, pt.p0, pt.p1);
+    }
+    sl.out_end = pos;
+    for (Part &pt : sl.parts) {
+        pt.contrib = pos;
+        pos += align256(pt.r->contrib_bytes);
+    }
+    sl.tables_bytes = tb;
+    sl.n_tiles = (int)n_tiles;
+    sl.block_bytes = pos;
+    sl.block_off = s.arena.alloc(pos);  // fits: pos <= the largest free range
+    return true;
 }
 
-static bool admit_and_launch(frg_session &s, std::unique_lock<std::mutex> &lk) {
+// Assign the next launch to a free slot; false if no slot is free or nothing can be launched.
+static bool plan_next(frg_session &s) {
     Slot *sl = nullptr;
     for (auto &x : s.slots)
         if (!x->busy) {
@@ -588,99 +654,109 @@ static bool admit_and_launch(frg_session &s, std::unique_lock<std::mutex> &lk) {
     if (!sl || s.queue.empty()) return false;
     if (!plan_launch(s, *sl)) return false;
     sl->busy = true;
-    sl->t_launch = now_us();
+    sl->assigned = true;
+    sl->t_plan = now_us();
     s.launches++;
-    // the device calls run without the session lock: clients keep submitting and waiting
-    lk.unlock();
-    frg_status st = s.exec->launch(s, *sl);
-    std::string msg = st == FRG_OK ? std::string() : std::string(frg_last_error());
-    if (st != FRG_OK) s.exec->drain(*sl);
-    lk.lock();
-    if (st != FRG_OK) {
-        s.fatal = msg;
-        complete_slot(s, *sl, false);
-    }
+    sl->cv.notify_one();
     return true;
 }
 
-static void scheduler(frg_session *sp) {
+// The slot's worker: enqueue each assigned launch (without the session lock, so clients keep
+// submitting and other slots keep launching), wait for it by polling its completion every
+// poll_us (spinning: a sleep this short would last the kernel's timer slack, ~50 us, instead),
+// copy the outputs to the clients' buffers and hand the slot back.
+static void slot_worker(frg_session *sp, Slot *slp) {
     frg_session &s = *sp;
+    Slot &sl = *slp;
     if (s.ctx) (void)hipSetDevice(s.ctx->device);
     std::unique_lock<std::mutex> lk(s.mu);
     for (;;) {
-        bool progress = false;
-        bool busy = false;
-        for (auto &sl : s.slots) {
-            if (!sl->busy) continue;
-            int p = s.exec->poll(s, *sl);
-            if (p != 0) {
-                complete_slot(s, *sl, p > 0);
-                progress = true;
+        sl.cv.wait(lk, [&] { return sl.assigned || (s.stop && !sl.busy); });
+        if (!sl.assigned) return;
+        sl.assigned = false;
+        lk.unlock();
+        frg_status st = s.exec->launch(s, sl);
+        sl.t_enqueued = now_us();
+        std::string msg = st == FRG_OK ? std::string() : std::string(frg_last_error());
+        int p = st == FRG_OK ? 0 : -1;
+        if (st != FRG_OK) s.exec->drain(sl);
+        while (p == 0) {
+            p = s.exec->poll(s, sl);
+            if (p != 0) break;
+            if (s.fake) {  // the test double's launches last milliseconds: no need to spin
+                std::this_thread::sleep_for(std::chrono::microseconds(s.cfg.poll_us));
                 continue;
             }
-            busy = true;
-            if (s.cfg.watchdog_ms > 0 && now_us() - sl->t_launch > 1e3 * s.cfg.watchdog_ms) {
+            const double until = now_us() + (double)s.cfg.poll_us;
+            while (now_us() < until) std::this_thread::yield();
+        }
+        const double t_seen = now_us();
+        if (p < 0 && st == FRG_OK) msg = frg_last_error();
+        // outputs into the clients' buffers (their requests are running: nobody else touches
+        // them); requests the watchdog already failed are skipped inside finish
+        if (p > 0) {
+            lk.lock();
+            s.exec->finish(s, sl);
+            complete_slot(s, sl, true, t_seen);
+        } else {
+            lk.lock();
+            s.fatal = msg;
+            complete_slot(s, sl, false, t_seen);
+        }
+    }
+}
+
+// The scheduler: forms launches whenever a slot is free and work is queued, and runs the
+// watchdog over launches in flight.
+static void scheduler(frg_session *sp) {
+    frg_session &s = *sp;
+    std::unique_lock<std::mutex> lk(s.mu);
+    for (;;) {
+        while (!s.stop && plan_next(s)) {
+        }
+        bool busy = false;
+        for (auto &sl : s.slots) busy = busy || sl->busy;
+        if (s.stop && !busy) break;
+        if (s.cfg.watchdog_ms > 0 && busy) {
+            const double now = now_us();
+            for (auto &sl : s.slots) {
+                if (!sl->busy || now - sl->t_plan <= 1e3 * s.cfg.watchdog_ms) continue;
                 for (const Part &pt : sl->parts) {
                     SessReq *r = pt.r;
                     if (r->timed_out || r->terminal()) continue;
                     r->timed_out = true;
                     remove_from_queue(s, r);
-                    end_request(s, r, RQ_FAILED, FRG_E_TIMEOUT, now_us());
-                    progress = true;
+                    end_request(s, r, RQ_FAILED, FRG_E_TIMEOUT, now);
                 }
             }
-        }
-        while (!s.stop && admit_and_launch(s, lk)) progress = true;
-        for (auto &sl : s.slots) busy = busy || sl->busy;
-        if (s.stop && !busy) break;
-        if (!progress) {
-            if (busy) {
-                // launches in flight: poll again after poll_us, spinning with the lock released
-                // (a sleep this short would last the kernel's timer slack, ~50 us, instead)
-                lk.unlock();
-                const double until = now_us() + (double)s.cfg.poll_us;
-                while (now_us() < until) std::this_thread::yield();
-                lk.lock();
-            } else {
-                s.sched_cv.wait(lk);
-            }
+            s.sched_cv.wait_for(lk, std::chrono::milliseconds(1));
+        } else {
+            s.sched_cv.wait(lk);
         }
     }
     // queued tickets left at close are cancelled (a split request may have launched parts)
-    for (SessReq *r : s.queue) {
-        if (r->arena_off != Arena::npos) {
-            s.arena.release(r->arena_off, r->footprint);
-            r->arena_off = Arena::npos;
-        }
-        end_request(s, r, RQ_CANCELLED, FRG_E_CANCELLED, now_us());
-    }
+    for (SessReq *r : s.queue) end_request(s, r, RQ_CANCELLED, FRG_E_CANCELLED, now_us());
     s.queue.clear();
+    for (auto &sl : s.slots) sl->cv.notify_all();
 }
 
-static size_t request_layout(SessReq &r) {
+// Inputs of a request as one launch block holds them, and its other device needs.
+static void request_layout(SessReq &r) {
     const frg_integral_desc &d = r.desc;
-    const int n = r.host.n_ext;
+    const size_t n = (size_t)r.host.n_ext;
     size_t off = 0;
-    r.n_ext_vals = (int)ext_values(d.family, n);
-    r.off_ext = off;
+    r.n_ext_vals = (int)ext_values(d.family, (long long)n);
+    r.in_ext = off;
     off += (size_t)r.n_ext_vals * 8;
-    r.off_m2 = off;
-    if (r.host.m2) off += (size_t)n * 8;
-    r.off_z = off;
+    r.in_m2 = off;
+    if (r.host.m2) off += n * 8;
+    r.in_z = off;
     if (r.table_id < 0 && r.host.Z.values && is_vertex(d.family)) off += (size_t)r.host.Z.n * 8;
     r.in_bytes = off;
-    off = align256(off);
-    r.off_out = off;
-    off += align256((size_t)n * 8);
-    r.off_err = off;
-    if (r.host.err_out) off += align256((size_t)n * 8);
-    r.out_bytes = (r.host.err_out ? 2 : 1) * (size_t)n * 8;
-    off = align256(off);
-    r.off_contrib = off;
-    if (r.chunked) off += align256((size_t)plan_desc(d).n_q * n * 8);
-    r.off_ctr = off;
-    if (r.chunked && d.precision == FRG_FP32_KAHAN) off += align256(((size_t)n + 1) * 4);
-    return align256(off);
+    r.slot_bytes = (r.chunked && d.precision == FRG_FP32_KAHAN) ? (n + 1) * 4 : 0;
+    r.contrib_bytes = r.chunked ? (size_t)plan_desc(d).n_q * n * 8 : 0;
+    r.footprint = align256(r.in_bytes) + align256(r.slot_bytes) +
+                  align256((r.host.err_out ? 2 : 1) * n * 8) + align256(r.contrib_bytes);
 }
 
 static frg_status open_session(frg_context *ctx, const frg_session_config *cfg, bool fake,
@@ -716,6 +792,7 @@ static frg_status open_session(frg_context *ctx, const frg_session_config *cfg, 
     frg_status st = s->exec->setup(*s);
     if (st != FRG_OK) return st;
     frg_session *raw = s.get();
+    for (auto &sl : s->slots) sl->worker = std::thread(slot_worker, raw, sl.get());
     s->thr = std::thread(scheduler, raw);
     *out = s.release();
     return FRG_OK;
@@ -828,19 +905,26 @@ frg_status frg_session_submit(frg_session *s, const frg_integral_desc *desc,
     // parts when the request exceeds one launch's work or a good share of its tile table
     r->split = n > 0 && ((double)r->nodes > kLaunchNodes ||
                          (size_t)r->ext_tiles * r->shape.chunks > kMaxLaunchTiles / 2);
-    r->footprint = request_layout(*r);
+    request_layout(*r);
+    // a launch of this request alone (its largest part): tables and the request's device bytes
+    const size_t tiles_alone =
+        std::min<size_t>((size_t)r->ext_tiles * r->shape.chunks +
+                             (r->chunked ? ((size_t)n + kWave - 1) / kWave : 0),
+                         kMaxLaunchTiles);
+    const size_t alone = tables_bytes(1, tiles_alone) + r->footprint;
+    const size_t alone_stage = alone - align256(r->contrib_bytes);
     r->t_submit = now_us();
     std::lock_guard<std::mutex> lk(s->mu);
-    if (r->footprint > s->arena.capacity()) {
+    if (alone > s->arena.capacity()) {
         s->rejected++;
-        set_error("request needs %zu device bytes, more than the session budget %zu",
-                  r->footprint, s->arena.capacity());
+        set_error("request needs %zu device bytes, more than the session budget %zu", alone,
+                  s->arena.capacity());
         return FRG_E_NOMEM;
     }
-    if (kSlotTables + align256(r->in_bytes) + align256(r->out_bytes) > s->staging_bytes) {
+    if (alone_stage > s->staging_bytes) {
         s->rejected++;
         set_error("request needs %zu bytes of host staging, more than the %zu a launch slot has",
-                  kSlotTables + align256(r->in_bytes) + align256(r->out_bytes), s->staging_bytes);
+                  alone_stage, s->staging_bytes);
         return FRG_E_NOMEM;
     }
     r->ticket = s->next_ticket++;
@@ -958,6 +1042,13 @@ frg_status frg_session_stats(frg_session *s, frg_stats *out) {
     out->nodes = s->nodes_done;
     out->launches = s->launches;
     out->tickets_held = s->reqs.size();
+    if (s->completed) {
+        const double c = (double)s->completed;
+        out->mean_queue_us = s->sum_queue_us / c;
+        out->mean_launch_us = s->sum_launch_us / c;
+        out->mean_device_us = s->sum_device_us / c;
+        out->mean_finish_us = s->sum_finish_us / c;
+    }
     return FRG_OK;
 }
 
@@ -970,6 +1061,12 @@ frg_status frg_session_close(frg_session *s) {
         s->sched_cv.notify_all();
     }
     if (s->thr.joinable()) s->thr.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto &sl : s->slots) sl->cv.notify_all();
+    }
+    for (auto &sl : s->slots)
+        if (sl->worker.joinable()) sl->worker.join();
     if (s->ctx) (void)hipSetDevice(s->ctx->device);
     delete s;
     return FRG_OK;

@@ -85,7 +85,9 @@ class frg_stats(ctypes.Structure):
     _fields_ = [("p50_us", c_double), ("p99_us", c_double), ("gnodes_per_s", c_double),
                 ("admitted", c_uint64), ("queued", c_uint64), ("rejected", c_uint64),
                 ("completed", c_uint64), ("failed", c_uint64), ("cancelled", c_uint64),
-                ("nodes", c_uint64), ("launches", c_uint64), ("tickets_held", c_uint64)]
+                ("nodes", c_uint64), ("launches", c_uint64), ("tickets_held", c_uint64),
+                ("mean_queue_us", c_double), ("mean_launch_us", c_double),
+                ("mean_device_us", c_double), ("mean_finish_us", c_double)]
 
 
 class frg_stepper_config(ctypes.Structure):
@@ -153,10 +155,12 @@ _lib.frg_serving_replay.argtypes = [c_void_p, c_void_p, c_int, c_int, POINTER(fr
                                     c_int, POINTER(frg_replay_arrival), c_int,
                                     POINTER(frg_replay_result), POINTER(c_double)]
 _lib.frg_serving_replay.restype = c_int
+_lib.frg_flop_probe.argtypes = [c_int, c_int, c_int, c_void_p, c_void_p]
+_lib.frg_flop_probe.restype = c_int
 _lib.frg_session_fake_fail_launches.argtypes = [c_void_p, c_int]
 _lib.frg_session_fake_fail_launches.restype = c_int
 TESTING_EXPORTED = ("frg_session_open_fake", "frg_session_fake_fail_launches",
-                    "frg_serving_replay")
+                    "frg_serving_replay", "frg_flop_probe")
 
 
 def frg_last_error() -> str:
@@ -276,6 +280,14 @@ def frg_serving_replay(ctx, session, mode: int, kinds, times_us, kind_idx, n_wai
     status = np.array([R[i].status for i in range(n)], dtype=np.int32)
     mism = np.array([R[i].mismatch for i in range(n)], dtype=np.int32)
     return lat, status, mism, wall.value
+
+
+def frg_flop_probe(seq: int, blocks: int, iters: int, out, stream=None) -> None:
+    """One dispatch of the FLOP-count probe kernel for sequence `seq` (include/frg_testing.h);
+    out: float64 device tensor of blocks * 64 values."""
+    if out.numel() < blocks * 64:
+        raise ValueError("out needs blocks * 64 values")
+    _check(_lib.frg_flop_probe(seq, blocks, iters, _dptr(out), _stream(stream)), "frg_flop_probe")
 
 
 def frg_session_fake_fail_launches(s: int, n: int) -> None:

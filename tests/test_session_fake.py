@@ -32,8 +32,8 @@ class Req:
         return self.batch.n_ext * self.desc.n_q * self.desc.n_x
 
     def footprint(self):
-        # inputs (p) and outputs, 256-byte aligned pieces; session launches take no radial
-        # chunks, so no contribution block
+        # inputs (p) and outputs, 256-byte aligned pieces (no radial chunks at these sizes, so
+        # no contribution block); a launch also holds its request and tile tables, a few KiB
         a = lambda v: (v + 255) // 256 * 256
         n = self.batch.n_ext
         return a(a(n * 8) + a(n * 8))
@@ -56,7 +56,7 @@ def test_fake_session_completes_in_arrival_order_with_one_slot():
 
 def test_admission_waits_for_memory_and_never_fails():
     r0 = Req(n_ext=160)
-    budget = 2 * r0.footprint() + 512  # two requests fit at once
+    budget = 2 * r0.footprint() + 4096  # at most two requests (and their tables) fit at once
     s = frg.frg_session_open_fake(_cfg(inflight=4, budget=budget), 2000.0, 1000.0)
     reqs = [Req(n_ext=160) for _ in range(10)]
     t0 = time.perf_counter()
@@ -219,13 +219,14 @@ def test_finite_temperature_descriptors_are_validated_at_submit():
     frg.frg_session_close(s)
 
 
-def test_footprint_is_inputs_and_outputs_only():
+def test_footprint_counts_inputs_outputs_and_tables():
     # a finite-temperature request (p and p0 in, I out) needs a(2n*8) + a(n*8) device bytes and
-    # no contribution scratch: a budget of exactly that admits it, and it runs
+    # no contribution scratch, plus its launch's tables (256 tiles: a few KiB): a budget of that
+    # plus 8 KiB admits it, twice the points do not fit
     n, n_q = 256, 16
     a = lambda v: (v + 255) // 256 * 256
-    need = a(a(2 * n * 8) + a(n * 8))
-    s = frg.frg_session_open_fake(_cfg(budget=max(need, 4096)), 1.0, 1.0)
+    need = a(a(2 * n * 8) + a(n * 8)) + 8192
+    s = frg.frg_session_open_fake(_cfg(budget=need), 1.0, 1.0)
     p = np.linspace(0.1, 3.0, n)
     ext = np.concatenate([p, np.zeros(n)])
     out = np.empty(n)
@@ -244,9 +245,10 @@ def test_footprint_is_inputs_and_outputs_only():
 
 
 def test_large_request_runs_in_parts_and_small_ones_overtake():
-    # a request of 4096 points x 128 x 64 x 16 nodes (5.4e8) runs in parts of at most 2e8 nodes;
-    # two small requests submitted right after it complete before it, on the other slot
-    s = frg.frg_session_open_fake(_cfg(inflight=2, budget=1 << 30), 1.0, 100.0)  # 1 ns/node
+    # a request of 4096 points x 128 x 64 x 16 nodes (5.4e8) runs in parts of at most 2e8 nodes,
+    # at most two at a time; two small requests submitted right after it complete before it, on
+    # the third slot
+    s = frg.frg_session_open_fake(_cfg(inflight=3, budget=1 << 30), 1.0, 100.0)  # 1 ns/node
     n = 4096
     ext = np.concatenate([np.linspace(0.01, 5.0, n), np.linspace(0.0, 3.0, n)])
     out = np.full(n, -1.0)
@@ -274,7 +276,7 @@ def test_bounded_bypass_of_a_request_blocked_on_memory():
     # one waits; small requests behind it may go ahead, but not forever
     small = Req(n_ext=64)
     big = Req(n_ext=4096)
-    budget = big.footprint() + 256
+    budget = big.footprint() + 32768  # with its launch tables
     s = frg.frg_session_open_fake(_cfg(inflight=4, budget=budget), 0.0, 3000.0)  # 3 ms/launch
     first = [Req(n_ext=64) for _ in range(2)]
     t_first = [frg.frg_session_submit(s, r.desc, r.batch, -1) for r in first]
@@ -321,7 +323,7 @@ def test_latency_percentiles_follow_the_launch_time():
 
 def test_failed_launch_fails_its_tickets_and_frees_memory():
     r = Req(n_ext=300)
-    s = frg.frg_session_open_fake(_cfg(inflight=1, budget=r.footprint() + 256), 0.0, 100.0)
+    s = frg.frg_session_open_fake(_cfg(inflight=1, budget=r.footprint() + 8192), 0.0, 100.0)
     frg.frg_session_fake_fail_launches(s, 1)
     t = frg.frg_session_submit(s, r.desc, r.batch, -1)
     with pytest.raises(frg.FrgError) as ei:
@@ -362,4 +364,32 @@ def test_replay_harness_on_a_fake_session():
     s = frg.frg_session_open_fake(_cfg(), 0.0, 0.0)
     with pytest.raises(frg.FrgError):
         frg.frg_serving_replay(None, s, 0, kinds, [5.0, 1.0], [0, 1])
+    frg.frg_session_close(s)
+
+
+def test_small_requests_go_first_and_large_ones_leave_a_slot():
+    # two slots; a large request (4096 x 128 x 64 x 16 = 5.4e8 nodes, parts of 2e8 at 1 ns/node)
+    # may hold only one of them, so small requests submitted after it run on the other slot and
+    # finish long before it does
+    s = frg.frg_session_open_fake(_cfg(inflight=2, budget=1 << 30), 1.0, 50.0)
+    n = 4096
+    ext = np.concatenate([np.linspace(0.01, 5.0, n), np.linspace(0.0, 3.0, n)])
+    out = np.full(n, -1.0)
+    big = frg.frg_batch(n, ext.ctypes.data, None, 0.5, frg.frg_log_table(None, 0, 1e-3, 1e3),
+                        out.ctypes.data, None)
+    dbig = frg.make_desc(frg.FRG_FAMILY_THREE_POINT, 128, 10.0, n_x=64, n_phi=16)
+    t0 = time.perf_counter()
+    tb = frg.frg_session_submit(s, dbig, big, -1)
+    small = [Req(n_ext=64) for _ in range(20)]
+    lat = []
+    for r in small:
+        t = frg.frg_session_submit(s, r.desc, r.batch, -1)
+        assert frg.frg_session_wait(s, t, 5000) == frg.FRG_OK
+        lat.append(time.perf_counter() - t0)
+    assert frg.frg_session_wait(s, tb, 10000) == frg.FRG_OK
+    t_big = time.perf_counter() - t0
+    # the large request's three parts take >= 0.54 s one after another on its one slot; all
+    # twenty small ones are done within its first part
+    assert t_big >= 0.5
+    assert max(lat) < 0.2
     frg.frg_session_close(s)
