@@ -82,6 +82,29 @@ def two_point_far_fraction(p, n_q, q_max, n_x):
     return float(np.mean(l2 >= FAR_Y))
 
 
+def three_point_far_fractions(P, A, n_q, q_max, n_x, n_phi):
+    """Fractions of three-point second-leg nodes and first-leg (radial, cos1) pairs (k = 1)
+    whose exponential is below double precision (y = l2/k^2 >= FAR_Y)."""
+    xq, _ = np.polynomial.legendre.leggauss(n_q)
+    q = 0.5 * q_max * (xq + 1.0)
+    x, _ = np.polynomial.legendre.leggauss(n_x)
+    sx = np.sqrt(1.0 - x * x)
+    xp, _ = np.polynomial.legendre.leggauss(n_phi)
+    cph = np.cos(0.5 * np.pi * (xp + 1.0))
+    far2 = far1 = 0.0
+    for i in range(0, P.size, 64):
+        p = P[i:i + 64, None, None, None]
+        a = A[i:i + 64, None, None, None]
+        Q = q[None, :, None, None]
+        c0 = Q * Q + p * p
+        l1 = c0 + 2.0 * Q * p * x[None, None, :, None]
+        l2 = c0 - 2.0 * Q * p * (x[None, None, :, None] * np.cos(a)
+                                 + sx[None, None, :, None] * cph[None, None, None, :] * np.sin(a))
+        far2 += float(np.count_nonzero(l2 >= FAR_Y))
+        far1 += float(np.count_nonzero(l1 >= FAR_Y))
+    return far2 / (P.size * n_q * n_x * n_phi), far1 / (P.size * n_q * n_x)
+
+
 def ft_frequency_count(T, lam, n_tail, fermionic=False):
     """Nodes of the Matsubara frequency rule: every |2 pi T (n + eta)| <= lam plus the tail nodes
     of both sides."""
@@ -450,6 +473,13 @@ def main():
     far = two_point_far_fraction(wl.two_point()[0], wl.TWO_NQ, wl.TWO_QMAX, wl.TWO_NX) \
         if family in (2, 5) else 0.0
     required = FLOP_PER_NODE[family] - FAR_FLOP_SAVED * far
+    if family == 3:
+        # the second leg per node and the first leg per (radial, cos1) pair, each skipping the
+        # exponential in the far field
+        P3, A3 = wl.three_point()[:2]
+        far, far1 = three_point_far_fractions(P3, A3, wl.THREE_NQ, wl.THREE_QMAX, wl.THREE_NX,
+                                              wl.THREE_NPHI)
+        required = FLOP_PER_NODE[3] - FAR_FLOP_SAVED * (far + far1 / wl.THREE_NPHI)
     counters = measured_counters(args.workload)
     per_s = 1.0 / (avg_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS
     counted = counters.get("counted_fp64_flop_per_launch")
@@ -479,7 +509,7 @@ def main():
                      # the time measured here
                      "frac_counted": round(counted * per_s, 4) if counted else None,
                      "counted_flop_per_node": round(counted / nodes, 2) if counted else None,
-                     # two-point families: the work the far-field nodes strictly need
+                     # the work the nodes strictly need (the far-field ones skip expm1)
                      "far_field_fraction": round(far, 4),
                      "flop_per_node_required": round(required, 2),
                      "frac_required": round(required * nodes * per_s, 4),

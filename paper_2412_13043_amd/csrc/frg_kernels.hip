@@ -312,8 +312,11 @@ __device__ __forceinline__ double prop64(double l2, double z, double m2, double 
 // reconstruction), so l2 e = l2 + l2 E = 0 and the propagator below is exactly 1/(Z l2 + m2) --
 // the same bits without evaluating the exponential.  A wavefront takes that path only when all
 // its active lanes are in the far field (a uniform branch).  Used where whole wavefronts often
-// are (two-point tiles group a few neighbouring radial nodes of neighbouring momenta); a
-// three-point wavefront spans all radial nodes of a point and would only pay for the vote.
+// are: two-point tiles group a few neighbouring radial nodes of neighbouring momenta, and fused
+// three-point launches take tiles of 8 points (one |p|, neighbouring angles) x 8 neighbouring
+// radial nodes, whose lanes are all in the far field at about half the steps of the workload
+// (a wavefront over all radial nodes of one point is, at a quarter of them, and pays more for
+// the vote than it saves).
 #define FRG_FAR_Y 38.0
 
 // 1/i, i = 1..16: coefficients of the polynomial-exponential regulator's exponent
@@ -503,7 +506,7 @@ __device__ __forceinline__ void xterm64(const ReqDev &r, const Smem &sm, int b, 
     const double za = r.za, zb1 = r.zbk + 1.0;
     const double xb = kc(r.ang.x)[b];
     double l1[1] = {fma(c1, xb, c0)}, g1[1];
-    propagators64<1, false, REG>(l1, g1, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
+    propagators64<1, true, REG>(l1, g1, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
     const double A2 = fma(-c1, xb * ca, c0);
     const double B2 = -c1 * (kc(r.ang.xs)[b] * sa);
     double acc = 0.0, acc2 = 0.0;
@@ -513,7 +516,7 @@ __device__ __forceinline__ void xterm64(const ReqDev &r, const Smem &sm, int b, 
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w)
             l2[w] = fmax(fma(B2, kc(r.phi.c)[c + w], A2), FRG_L2_TINY);
-        propagators64<FRG_ILP, false, REG>(l2, G, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
+        propagators64<FRG_ILP, true, REG>(l2, G, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w) {
             acc = fma(kc(r.phi.w)[c + w], G[w], acc);
