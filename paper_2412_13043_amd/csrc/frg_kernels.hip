@@ -954,7 +954,22 @@ __device__ __forceinline__ double lpa_integral(const ReqDev &r, double m2, doubl
             }
             *dv = r.pref * (-2.0 * dacc);
         } else {
-            for (int a = 0; a < nq; ++a) {
+            // blocks of 8 radial nodes: the 8 reciprocals are independent and overlap, then
+            // enter the sum in radial order (the same additions as one node at a time)
+            constexpr int U = 8;
+            int a = 0;
+            for (; a + U <= nq; a += U) {
+                double g2[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const double qh = kc(r.rad.q)[a + u];
+                    const double g = fm::rcp_nr(fma(r.k2, fma(qh, qh, kc(r.rad.R)[a + u]), m2));
+                    g2[u] = g * g;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) acc = fma(kc(r.rad.W)[a + u], g2[u], acc);
+            }
+            for (; a < nq; ++a) {
                 const double qh = kc(r.rad.q)[a];
                 const double g = fm::rcp_nr(fma(r.k2, fma(qh, qh, kc(r.rad.R)[a]), m2));
                 acc = fma(kc(r.rad.W)[a], g * g, acc);
