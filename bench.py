@@ -412,7 +412,8 @@ def main():
                     help="serve the traces through the session and the plain path, or the "
                          "session only")
     ap.add_argument("--workload", default="three_point_8",
-                    choices=["two_point_256", "three_point_8", "lpa_4096", "two_point_ft_16"],
+                    choices=["two_point_256", "three_point_8", "lpa_4096", "two_point_ft_16",
+                             "two_point_256_near_pole", "two_point_256_near_pole_fp32"],
                     help="workload of the timed line (default: the three-point batch, the "
                          "largest single-GPU configuration); the others exist so that each "
                          "family's kernel can be timed and profiled on its own")
@@ -495,7 +496,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": config.get("precision", "f64"),
         "data": "synthetic",
         "config": config,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
@@ -551,6 +552,19 @@ def workload_setup(torch, frg, wl, ctx, name):
                   "nodes_per_step": nodes, "rhs_per_step": 256}
         return (lambda: ctx.integrate_multi(descs, batches), nodes, 2, "frg::multi_kernel<2, 0, 0, false>",
                 config, keep)
+    if name in ("two_point_256_near_pole", "two_point_256_near_pole_fp32"):
+        prec = 1 if name.endswith("fp32") else 0
+        descs, batches, out, _, nodes, keep = two_point_batch_setup(torch, frg, precision=prec,
+                                                                    seed_m2=4, tau=0.1)
+        config = {"workload": "two-point vertex flow d=4 near the pole: 256 right-hand sides x "
+                              "256 momenta x 64x32 GL nodes, per-RHS tabulated Z, m2 in "
+                              "U[-0.95,-0.5], " + ("float32 form (tau = 0.1)" if prec else
+                                                   "float64") +
+                              ", one fused frg_integrate_multi launch",
+                  "nodes_per_step": nodes, "rhs_per_step": 256,
+                  "precision": "f32" if prec else "f64"}
+        return (lambda: ctx.integrate_multi(descs, batches), nodes, 2,
+                f"frg::multi_kernel<2, {prec}, 0, false>", config, keep)
     if name == "three_point_8":
         P, A, m3, Z3 = wl.three_point_batch()
         text = _dev(torch, np.concatenate([P, A]))

@@ -176,11 +176,15 @@ typedef struct {
     frg_log_table Z;
     double *out;           /* device [n_ext]: I_e */
     double *err_out;       /* device [n_ext] or NULL: stated relative error bound per result of
-                              the FP32 form, (16 + 3 kappa) u + kappa L ds with u = 2^-24,
-                              kappa the largest amplification (|Z l2 + R| + |m2|)/D of a
-                              float32 propagator of that point, L the largest relative step
-                              of the dressing table and ds the float32 error bound of the
-                              dressing coordinate (0 for FP64) */
+                              the FP32 form (0 for FP64): with u = 2^-24, kappa the largest
+                              amplification (|Z l2 + R| + |m2|)/D among that point's float32
+                              propagators and nG the float32 propagators per integrand term
+                              (two-point 1, three-point 2), (6 + 2 nG) u + nG (eE + er) +
+                              nG kappa K, where eE, er are the measured errors of the float32
+                              exponential and reciprocal and K the per-kappa error of one
+                              propagator, set by the dressing table's largest relative step
+                              and its smallest entry (assumed positive); LPA (7 + 10 kappa) u
+                              + 2 er */
     double *dout_dm2;      /* device [n_ext] or NULL: dI_e/dm2_e, the derivative of each result in
                               its point's mass, evaluated in the same pass by forward-mode
                               differentiation through every propagator (dG/dm2 = -G^2; the

@@ -1,3 +1,4 @@
+// Probes of the elementary sequences the integrand loops use.
 // FP64 FLOP count of the elementary sequences the integrand loops use, for the roofline's
 // per-node work: one kernel per sequence runs it `iters` times per lane on a varying argument,
 // and the hardware FP64 FLOP counter of each dispatch (read by a profiler) divided by the
@@ -5,6 +6,8 @@
 #include "../../include/frg_testing.h"
 #include "frg_internal.hpp"
 #include "frg_math.hpp"
+
+#include <cstring>
 
 namespace frg {
 
@@ -33,9 +36,69 @@ __global__ void __launch_bounds__(64) flop_probe_kernel(double *out, int iters,
     out[gid] = acc;
 }
 
+// Accuracy of the float32 form's elementary operations, over every float32 input of a range
+// (a grid-stride loop; each wavefront's largest error joins a device maximum):
+//  0: |v_log_f32(m) - log2(m)| (absolute) for m in [1/2, 1)  (2^23 inputs);
+//  1: |fm::expm1_neg_f(y) - expm1(-y)| / |expm1(-y)| for normal y in [2^-126, 2^21] (above that the
+//     argument is clamped and the result is -1, off by e^-y);
+//  2: |v_rcp_f32(d) d - 1| for d in [2^-100, 2^100).
+// The references are the float64 log2 and expm1 of the HIP math library.
+__global__ void __launch_bounds__(256) math_probe_kernel(int which, unsigned long long lo,
+                                                         unsigned long long hi,
+                                                         unsigned long long *maxbits) {
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    double worst = 0.0;
+    for (unsigned long long b = lo + blockIdx.x * blockDim.x + threadIdx.x; b < hi; b += stride) {
+        const float x = __uint_as_float((unsigned)b);
+        double err;
+        if (which == 0) {
+            err = fabs((double)__builtin_amdgcn_logf(x) - log2((double)x));
+        } else if (which == 1) {
+            const double E = expm1(-(double)x);
+            err = fabs((double)fm::expm1_neg_f(x) - E) / fabs(E);
+        } else {
+            err = fabs((double)__builtin_amdgcn_rcpf(x) * (double)x - 1.0);
+        }
+        worst = fmax(worst, err);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o));
+    if ((threadIdx.x & (kWave - 1)) == 0)
+        atomicMax(maxbits, (unsigned long long)__double_as_longlong(worst));
+}
+
 }  // namespace frg
 
 using namespace frg;
+
+extern "C" frg_status frg_math_probe(int which, double *max_err, hipStream_t stream) {
+    if (which < 0 || which > 2 || !max_err) return FRG_E_INVAL;
+    // input ranges as float32 bit patterns [lo, hi)
+    const unsigned long long lo[3] = {0x3F000000ull, 0x00800000ull, 0x0D800000ull};
+    const unsigned long long hi[3] = {0x3F800000ull, 0x4A000001ull, 0x71800000ull};
+    unsigned long long *d = nullptr;
+    if (hipMalloc(&d, sizeof(unsigned long long)) != hipSuccess) return FRG_E_DEVICE;
+    hipError_t e = hipMemsetAsync(d, 0, sizeof(unsigned long long), stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(math_probe_kernel, dim3(2048), dim3(256), 0, stream, which, lo[which],
+                           hi[which], d);
+        e = hipGetLastError();
+    }
+    unsigned long long bits = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&bits, d, sizeof(bits), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return FRG_E_DEVICE;
+    std::memcpy(max_err, &bits, sizeof(double));
+    return FRG_OK;
+}
+
+extern "C" void frg_fp32_error_constants(double out[4]) {
+    out[0] = kU32;
+    out[1] = kErrLog2f;
+    out[2] = kErrExpm1f;
+    out[3] = kErrRcpf;
+}
 
 extern "C" frg_status frg_flop_probe(int seq, int blocks, int iters, double *out,
                                      hipStream_t stream) {

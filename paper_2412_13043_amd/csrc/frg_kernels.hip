@@ -266,13 +266,12 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *kc(const T
 // Tables staged in LDS for one request: the logarithm table, then the dressing as n + 1 entries
 // (Z_0, 0), (Z_0, Z_1 - Z_0), ..., (Z_{n-2}, Z_{n-1} - Z_{n-2}), (Z_{n-1}, 0) addressed by
 // s + 1, s = (log|l| - log x_min)/Delta: the constant first and last entries absorb every s
-// outside [0, n-1], so one integer clamp of the cell index replaces clamping s; then
-// (float32 form) the same entries in float32.
+// outside [0, n-1], so one integer clamp of the cell index replaces clamping s (the float32 form
+// reads the same pairs and rounds them to float32 at use).
 struct Smem {
     double2 *logt;
     double2 *Z64;
-    float2 *Z32;
-    float *zslope;  // max_i |Z_{i+1} - Z_i| / min_i |Z_i| of the staged table (float32 form's bound)
+    float *f32c;  // float32 form: [0] K, [1] the fallback's weight (see fp32_constants)
 };
 
 // Cell index and fraction of the padded dressing table for coordinate sp = s + 1.
@@ -557,11 +556,43 @@ struct Kahan32 {
 // (y = l2/k^2, m2/k^2, G^ = k^2 G).
 struct Par32 {
     int nZ;
-    float za2, zb1;   // s + 1 = za2 * log2(y) + zb1
     float m2f, am2f;  // m2/k^2 and its magnitude
     float tau;        // near-pole threshold
-    double m2, za, zb1d;
+    float kfb;        // weight of a float64 fallback's amplification (see fp32_constants)
+    double za2, zb1;  // s + 1 = za2 log2(y) + zb1
+    double m2;        // the float64 fallback's mass
 };
+
+// Dressing cell and fraction at a float32 y.  y = m 2^e exactly (frexp, m in [1/2, 1)), so
+// log2 y = e + log2 m with the hardware v_log_f32 on the mantissa only, whose absolute error
+// there is at most kErrLog2f; e + log2 m and s + 1 = za2 log2 y + zb1 are formed in float64.
+// The coordinate's error is then za2 kErrLog2f (plus float64 rounding), against about
+// 2^-24 (n_Z + |zb1|) had s + 1 been rounded to float32 at its magnitude.
+__device__ __forceinline__ void zcell32(float y, const Par32 &P, int &i, float &f) {
+    const float m = __builtin_amdgcn_frexp_mantf(y);
+    const int e = __builtin_amdgcn_frexp_expf(y);
+    double fd;
+    zcell64(fma((double)__builtin_amdgcn_logf(m) + (double)e, P.za2, P.zb1), P.nZ, i, fd);
+    f = (float)fd;
+}
+
+// Near-pole node of the float32 form: the propagator in float64 at the float32 y, with the
+// float64 dressing entries at the float32 form's cell and fraction, and its amplification
+// kappa = (|Z y + R| + |m2|)/D.  Its float64 arithmetic adds nothing measurable, but y was
+// rounded to float32 and the coordinate carries za2 kErrLog2f plus the fraction's rounding, and
+// kappa amplifies both like every other perturbation: kappa enters kmax scaled by their share
+// kfb of the float32 nodes' per-kappa error K, so that kappa K of the bound covers them.
+__device__ __forceinline__ float prop_fallback(const Par32 &P, float y, double2 zz, float fz,
+                                               float &kmax) {
+    const double l2 = (double)y;
+    const double z = fma((double)fz, zz.y, zz.x);
+    const double E = fm::expm1_neg(l2);
+    const double le = fma(l2, E, l2);
+    const double rd = fm::rcp_nr(fma(-E, fma(z, l2, P.m2), le));
+    const float kap = (float)(fabs(fma(-E, fma(z, l2, fabs(P.m2)), le) * rd) * (double)P.kfb);
+    kmax = __uint_as_float(max(__float_as_uint(kmax), __float_as_uint(kap)));
+    return (float)(-E * rd);
+}
 
 // W float32 propagators; kmax tracks the largest amplification (|Z l2 + R| + |m2|)/D of the
 // float32 evaluations.
@@ -578,17 +609,15 @@ __device__ __forceinline__ void propagators32(const float (&l2)[W], float (&G)[W
     if (FAR && __all(far)) {
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            const float sp = fmaf(__builtin_amdgcn_logf(l2[w]), P.za2, P.zb1);
-            unsigned u;
-            asm("v_cvt_u32_f32 %0, %1" : "=v"(u) : "v"(sp));
-            const float2 z = sm.Z32[(int)min(u, (unsigned)P.nZ)];
-            const float zv = fmaf(__builtin_amdgcn_fractf(sp), z.y, z.x);
+            int iz;
+            float fz;
+            zcell32(l2[w], P, iz, fz);
+            const double2 zz = sm.Z64[iz];
+            const float zv = fmaf(fz, (float)zz.y, (float)zz.x);
             const float den = fmaf(zv, l2[w], P.m2f);
             const float parts = fmaf(zv, l2[w], P.am2f);
             if (den < P.tau * parts) {
-                const double l2d = (double)l2[w];
-                const double zd = dressing64(sm, P.nZ, P.za, P.zb1d, l2d);
-                G[w] = (float)prop64(l2d, zd, P.m2, 1.0);
+                G[w] = prop_fallback(P, l2[w], zz, fz, kmax);
             } else {
                 const float rd = __builtin_amdgcn_rcpf(den);
                 G[w] = rd;
@@ -600,29 +629,21 @@ __device__ __forceinline__ void propagators32(const float (&l2)[W], float (&G)[W
     int iz[W];
     float fz[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-        const float sp = fmaf(__builtin_amdgcn_logf(l2[w]), P.za2, P.zb1);
-        unsigned u;  // saturating conversion: negative and NaN to 0 (see zcell64)
-        asm("v_cvt_u32_f32 %0, %1" : "=v"(u) : "v"(sp));
-        iz[w] = (int)min(u, (unsigned)P.nZ);
-        fz[w] = __builtin_amdgcn_fractf(sp);
-    }
-    float2 z[W];
+    for (int w = 0; w < W; ++w) zcell32(l2[w], P, iz[w], fz[w]);
+    double2 z[W];  // float64 entries, rounded to float32 where the float32 node uses them
 #pragma unroll
-    for (int w = 0; w < W; ++w) z[w] = sm.Z32[iz[w]];
+    for (int w = 0; w < W; ++w) z[w] = sm.Z64[iz[w]];
     float E[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) E[w] = fm::expm1_neg_f(l2[w]);
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-        const float zv = fmaf(fz[w], z[w].y, z[w].x);
+        const float zv = fmaf(fz[w], (float)z[w].y, (float)z[w].x);
         const float le = fmaf(l2[w], E[w], l2[w]);
         const float den = fmaf(-E[w], fmaf(zv, l2[w], P.m2f), le);
         const float parts = fmaf(-E[w], fmaf(zv, l2[w], P.am2f), le);
         if (den < P.tau * parts) {
-            const double l2d = (double)l2[w];
-            const double zd = dressing64(sm, P.nZ, P.za, P.zb1d, l2d);
-            G[w] = (float)prop64(l2d, zd, P.m2, 1.0);
+            G[w] = prop_fallback(P, l2[w], z[w], fz[w], kmax);
         } else {
             const float rd = __builtin_amdgcn_rcpf(den);
             G[w] = -E[w] * rd;
@@ -632,17 +653,17 @@ __device__ __forceinline__ void propagators32(const float (&l2)[W], float (&G)[W
     }
 }
 
-__device__ __forceinline__ Par32 par32(const ReqDev &r, double m2, double inv_k2) {
+__device__ __forceinline__ Par32 par32(const ReqDev &r, const Smem &sm, double m2,
+                                       double inv_k2) {
     Par32 P;
     P.nZ = r.nZ;
-    P.za2 = (float)(r.za * 0.69314718055994530942);
-    P.zb1 = (float)(r.zbk + 1.0);
     P.m2 = m2 * inv_k2;
     P.m2f = (float)P.m2;
     P.am2f = fabsf(P.m2f);
     P.tau = (float)r.tau;
-    P.za = r.za;
-    P.zb1d = r.zbk + 1.0;
+    P.kfb = sm.f32c[1];
+    P.za2 = r.za * 0.69314718055994530942;
+    P.zb1 = r.zbk + 1.0;
     return P;
 }
 
@@ -650,7 +671,7 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
                                                 double m2, double m2x, double inv_k2,
                                                 float &kmax) {
     const RadialTerm t = radial64(r, sm, a, p, m2);
-    const Par32 P = par32(r, m2x, inv_k2);
+    const Par32 P = par32(r, sm, m2x, inv_k2);
     const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2;  // y = l2/k^2 > 0 (see FRG_L2_TINY)
     Kahan32 acc{0.0f, 0.0f};
     const int nx = r.n_x;
@@ -696,7 +717,7 @@ __device__ __forceinline__ Dual contrib_two(const ReqDev &r, const Smem &sm, int
         t = radial64(r, sm, a, p, m2);
         c0 = t.c0 * inv_k2;
         c1 = t.c1 * inv_k2;
-        if (PREC == 1) P = par32(r, m2x, inv_k2);
+        if (PREC == 1) P = par32(r, sm, m2x, inv_k2);
     }
     const double m2h = m2x * inv_k2, za = r.za, zb1 = r.zbk + 1.0;
     const int nx = r.n_x, nZ = r.nZ;
@@ -797,7 +818,7 @@ __device__ __forceinline__ Dual contrib_three(const ReqDev &r, const Smem &sm, i
         t = radial64(r, sm, a, p, m2);
         c0 = t.c0 * inv_k2;
         c1 = t.c1 * inv_k2;
-        if (PREC == 1) P = par32(r, m2, inv_k2);
+        if (PREC == 1) P = par32(r, sm, m2, inv_k2);
     }
     const double m2h = m2 * inv_k2;
     const int nx = r.n_x;
@@ -836,24 +857,44 @@ __device__ __forceinline__ Dual contrib_three(const ReqDev &r, const Smem &sm, i
                 t.wg * (-2.0 * t.g * (mid * i4) - (midA + midB) * (i4 * inv_k2))};
 }
 
-// float32 form's stated relative error bound per result (u = 2^-24, kappa = largest float32
-// amplification (|Z l2 + R| + |m2|)/D of the point, L = largest relative step of the dressing
-// table, ds = bound on the float32 error of the dressing coordinate s):
-//   (16 + 3 kappa) u + kappa L ds
-// 16 u: y = l2/k^2 rounded once to float32, expm1 and its reconstruction, the reciprocal, the
-// weight products, the block sums and their compensated accumulation; 3 kappa u: the rounding of
-// the denominator's three terms, amplified by their cancellation; kappa L ds: the dressing
-// lookup.  ds: s + 1 = fmaf(log2 y, za2, zb1) in float32 -- the rounding of y (1.5 u in log2),
-// v_log_f32 (1 ulp of |log2 y|, at most Lmax = the larger |log2| of the table's end points in
-// units of k^2 while s is inside the table; outside it the end entries are constant), and the
-// rounding of za2, zb1 and the sum (u (2 nZ + 3 |zb1| + 2)).
-__device__ __forceinline__ double fp32_bound(float kmax, float zslope, const ReqDev &r) {
-    const double u = 5.9604644775390625e-8;
-    const double ln2 = 0.69314718055994530942;
-    const double za2 = r.za * ln2, zb1 = fabs(r.zbk + 1.0);
-    const double lmax = fmax(fabs(-r.zbk / r.za), fabs((r.nZ - 1 - r.zbk) / r.za)) / ln2;
-    const double ds = u * (2.0 * (r.nZ + 1) + 3.0 * zb1 + 2.0) + za2 * (2.0 * u * lmax + 1.5 * u);
-    return (16.0 + 3.0 * (double)kmax) * u + (double)kmax * (double)zslope * ds;
+// float32 form's stated relative error bound per result.  u = 2^-24 (float32 unit roundoff);
+// kappa = the largest amplification (|Z y + R| + |m2|)/D among the point's float32 propagators
+// (the fallback's enter scaled, see prop_fallback); nG = float32 propagators per integrand term
+// (two-point 1, three-point 2); eE, er = largest relative errors of fm::expm1_neg_f and of the
+// v_rcp_f32 reciprocal (kErrExpm1f, kErrRcpf, exhaustively measured); K = fp32_constants().
+//   err = (6 + 2 nG) u + nG (eE + er) + nG kappa K
+// Per float32 propagator G~ = fl((-E~) rcp(D~)), D~ = fl((-E~) fl(Z~ y~ + m~) + fl(y~ + y~ E~)):
+//  - not amplified: eE (numerator), er, the product's rounding and D~'s last rounding: 2u + eE + er;
+//  - amplified by kappa (each an absolute error of D relative to its parts (-E)(Z y + |m2|) + y e):
+//    the rounding of y (below), m2 (u), the inner and the le roundings (2u), E~ in (-E)(Z y + m2)
+//    (eE), E~ in le = y (1 + E) (y |E| eE against parts >= y min(1, Z): eE / min(1, Zmin)), and
+//    Z~: float32 entries and fraction and the fma (2u + 1.5 u L) plus the coordinate's error
+//    (L za2 kErrLog2f);
+//  - the rounding of y itself (|dy/y| <= u) moves G by kappa u |y dN/dy| / (|Z y + R| + |m2|) with
+//    N = Z y + R + m2: y Z' / Z <= za L, and |y R'| = R (y/(1 - e^-y) - 1) <= 1.32 R for y <= 2
+//    and <= 0.724 <= (0.362 / Zmin)(Z y + R) beyond: u_y = u (1 + za L + max(1.32, 0.37/Zmin)).
+// Per term: the float32 weight (u), the FRG_ILP-node block sum (2u) and the compensated sum of
+// blocks (2u) -- two-point 6u + 2u + eE + er = (6 + 2) u + ...; three-point: the phi sum's 5u and
+// two propagators, 10u + 2 (eE + er).  Every integrand term is positive, so the bound of a term
+// bounds the integral.  First order in u; kappa is the computed one.
+__device__ __forceinline__ double fp32_bound(float kmax, float K, const ReqDev &r) {
+    const double nG = r.family == 3 ? 2.0 : 1.0;
+    return (6.0 + 2.0 * nG) * kU32 + nG * (kErrExpm1f + kErrRcpf) + nG * (double)kmax * (double)K;
+}
+
+// K = per-kappa relative error of one float32 propagator and the share of it that a float64
+// fallback keeps (see prop_fallback), from the table's largest step L = max|Z_{i+1} - Z_i| /
+// min|Z_i| (per coordinate unit), Zmin = min|Z_i| and the request's coordinate scale za (per
+// unit of ln y); both stored rounded up.
+__device__ __forceinline__ void fp32_constants(const ReqDev &r, float mx, float mn, float *c) {
+    const double L = mn > 0.0f ? (double)mx / (double)mn : 1.0e300;
+    const double zlo = fmin(1.0, (double)mn);
+    const double uy = kU32 * (1.0 + r.za * L + fmax(1.32, 0.37 / zlo));
+    const double us = L * (r.za * 0.69314718055994530942 * kErrLog2f + 1.0e-12);  // coordinate
+    const double K = uy + us + kU32 * (5.0 + 1.5 * L) + kErrExpm1f * (1.0 + 1.0 / zlo);
+    c[0] = K < 1.0e30 ? (float)(K * (1.0 + 1.0 / 1048576.0)) : 3.0e38f;
+    // the fallback: the rounding of y, the coordinate and the fraction's rounding (u/2 of a step)
+    c[1] = (float)((uy + us + 0.5 * kU32 * L) / K * (1.0 + 1.0 / 1048576.0));
 }
 
 // --------------------------------------------------------------------------------------------
@@ -873,11 +914,13 @@ __device__ __forceinline__ void stage_log(Smem &sm, const double2 *logt) {
 }
 
 // Padded dressing of one request: entry j (0..n) is (Z_{j-1}, Z_j - Z_{j-1}) with constant end
-// entries; for the float32 form also its float copy and the table's largest relative step
-// max|Z_{i+1} - Z_i| / min|Z_i| (one wavefront per workgroup).
+// entries; for the float32 form also the bound's constants from the table's largest step
+// max|Z_{i+1} - Z_i| and smallest entry min|Z_i| (one wavefront per workgroup).
+template <int PREC>  // the kernel's precision: 0, 1, or -1 (the request's, at run time)
 __device__ __forceinline__ void stage_dressing(const ReqDev &r, Smem &sm) {
     constexpr int U = 2;  // entries per lane whose loads are in flight together
     const int n = r.nZ;
+    const bool f32 = PREC == 1 || (PREC < 0 && r.precision == 1);
     float mx = 0.0f, mn = 3.0e38f;
     for (int j0 = (int)threadIdx.x; j0 <= n; j0 += U * kWave) {
         double lo[U], hi[U];
@@ -893,19 +936,18 @@ __device__ __forceinline__ void stage_dressing(const ReqDev &r, Smem &sm) {
             if (j > n) break;
             const double dz = (j == 0 || j == n) ? 0.0 : hi[u] - lo[u];
             sm.Z64[j] = make_double2(lo[u], dz);
-            if (r.precision == 1) {
-                sm.Z32[j] = make_float2((float)lo[u], (float)dz);
+            if (f32) {
                 if (j >= 1) mn = fminf(mn, (float)fabs(lo[u]));
                 if (j >= 1 && j < n) mx = fmaxf(mx, (float)fabs(dz));
             }
         }
     }
-    if (r.precision == 1) {
+    if (f32) {
         for (int o = kWave / 2; o > 0; o >>= 1) {
             mx = fmaxf(mx, __shfl_xor(mx, o));
             mn = fminf(mn, __shfl_xor(mn, o));
         }
-        if (threadIdx.x == 0) *sm.zslope = mn > 0.0f ? mx / mn : 3.0e38f;
+        if (threadIdx.x == 0) fp32_constants(r, mx, mn, sm.f32c);
     }
 }
 
@@ -927,16 +969,19 @@ __device__ __forceinline__ double radial_sum(const double *blk, int n_q, long lo
     return s;
 }
 
-__device__ __forceinline__ void bind_smem(Smem &sm, double2 *lds, int nZ, float *zslope) {
+__device__ __forceinline__ void bind_smem(Smem &sm, double2 *lds, int nZ, float *f32c) {
     sm.logt = lds;
     sm.Z64 = lds + kLogTable;
-    sm.Z32 = (float2 *)(lds + kLogTable + nZ + 1);
-    sm.zslope = zslope;
+    sm.f32c = f32c;
 }
 
 // LPA: one lane per external point, the whole radial sum in one lane, no scratch.
-// One LPA integral pref * sum_a W_a / (A_a + m2)^2 with A_a = k^2 (q^_a^2 + R^_a); the float32
-// form states (16 + 3 kappa) 2^-24 in err.
+// One LPA integral pref * sum_a W_a / (A_a + m2)^2 with A_a = k^2 (q^_a^2 + R^_a).  The float32
+// form states (7 + 10 kappa) u + 2 er in err (u = 2^-24, er = kErrRcpf, kappa = the largest
+// (A + |m2|)/(A + m2) of its float32 terms): A from float32 q^, R^ and k^2 carries 5u, so
+// t = A + m2 carries 5 kappa u + u and g^2 = rcp(t)^2 twice that and 2 er; the weight, the
+// two products and the compensated sum add 5u.  Near-pole terms (float64 from the float64
+// nodes) carry only their rounding to float32.
 // With r.dout (float64) also dI/dm2 = pref sum_a W_a (-2 G_a^3) into *dv.
 template <int PREC>
 __device__ __forceinline__ double lpa_integral(const ReqDev &r, double m2, double &err,
@@ -996,7 +1041,7 @@ __device__ __forceinline__ double lpa_integral(const ReqDev &r, double m2, doubl
         }
         acc.add(kc(r.rad.Wf)[a] * (g * g));
     }
-    err = (16.0 + 3.0 * (double)kmax) * 5.9604644775390625e-8;
+    err = (7.0 + 10.0 * (double)kmax) * kU32 + 2.0 * kErrRcpf;
     return r.pref * ((double)acc.s - (double)acc.c);
 }
 
@@ -1101,7 +1146,7 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
         if (valid && sub == 0) {
             r.out[e] = r.pref * sum;
             if (DER && r.dout) r.dout[e] = r.pref * dsum;
-            if (r.err) r.err[e] = (PREC == 1) ? fp32_bound(kmax, *sm.zslope, r) : 0.0;
+            if (r.err) r.err[e] = (PREC == 1) ? fp32_bound(kmax, sm.f32c[0], r) : 0.0;
         }
         return;
     }
@@ -1119,7 +1164,7 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
     // the finalize kernel (a later launch on the same stream) adds the chunks in radial order
     if (PREC == 1) {
         if (valid) atomicMax(&kslot[e], __float_as_uint(kmax));
-        if (lane == 0) kslot[r.n_ext] = __float_as_uint(*sm.zslope);  // same value from every tile
+        if (lane == 0) kslot[r.n_ext] = __float_as_uint(sm.f32c[0]);  // same value from every tile
     }
 }
 
@@ -1176,20 +1221,20 @@ hipError_t launch_multi_finalize(const ReqDev *reqs_dev, const TileDev *fin_dev,
 template <int FAM, int PREC, int REG, bool DER>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
     DER ? (FAM == 3 ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_DER)
-        : (FAM == 3 ? FRG_WAVES_PER_EU_MULTI : FRG_WAVES_PER_EU_BATCH))))
+        : ((FAM == 3 || PREC != 0) ? FRG_WAVES_PER_EU_MULTI : FRG_WAVES_PER_EU_BATCH))))
 batch_kernel(ReqDev r, double *contrib, unsigned *counters) {
     extern __shared__ double2 lds_dyn[];
     if (FAM == 1) {
         tile_lpa<PREC>(r, blockIdx.x);
         return;
     }
-    __shared__ float zslope;
+    __shared__ float f32c[2];
     Smem sm;
-    bind_smem(sm, lds_dyn, r.nZ, &zslope);
+    bind_smem(sm, lds_dyn, r.nZ, f32c);
     const int et = blockIdx.x / r.chunks;
     const int chunk = blockIdx.x - et * r.chunks;
     stage_log(sm, r.logt);
-    stage_dressing(r, sm);
+    stage_dressing<PREC>(r, sm);
     __syncthreads();
     tile_vertex<FAM, PREC, REG, DER>(r, sm, et, chunk, contrib, counters);
 }
@@ -1285,20 +1330,23 @@ __device__ __forceinline__ void multi_tile(const ReqDev &r, Smem &sm, const Tile
 
 // Occupancy target of a fused-kernel instance: the three-point family and the general kernel
 // carry more state than the two-point families, the mass derivative a second set of
-// accumulators, and the polynomial-exponential regulator's exponent a few more registers.
-constexpr int multi_waves(int fam, int reg, bool der) {
+// accumulators, and the polynomial-exponential regulator's exponent a few more registers.  The
+// float32 form of the two-point families holds 4 (its float32 and float64 dressing tables and
+// the logarithm table already hold a CU to 15 workgroups; at 5 it spills).
+constexpr int multi_waves(int fam, int prec, int reg, bool der) {
     return der ? ((fam < 0 || fam == 3) ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_DER)
                : ((fam < 0 || fam == 3) ? (reg == 1 ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_MULTI)
-                                        : (reg == 1 ? FRG_WAVES_PER_EU_MULTI : FRG_WAVES_PER_EU_BATCH));
+                                        : ((reg == 1 || prec != 0) ? FRG_WAVES_PER_EU_MULTI
+                                                                   : FRG_WAVES_PER_EU_BATCH));
 }
 
 template <int FAM, int PREC, int REG, bool DER>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(multi_waves(FAM, REG, DER))))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(multi_waves(FAM, PREC, REG, DER))))
 multi_kernel(const ReqDev *__restrict__ reqs, const TileDev *__restrict__ tiles, int n_tiles,
              double *contrib, unsigned *counters, unsigned *work) {
     extern __shared__ double2 lds_dyn[];
     __shared__ int tile_s;
-    __shared__ float zslope;
+    __shared__ float f32c[2];
     Smem sm;
     int staged = -1;
     bool log_staged = false;
@@ -1326,12 +1374,12 @@ multi_kernel(const ReqDev *__restrict__ reqs, const TileDev *__restrict__ tiles,
             continue;
         }
         if (FAM != 1) {
-            bind_smem(sm, lds_dyn, r.nZ, &zslope);
+            bind_smem(sm, lds_dyn, r.nZ, f32c);
             if (staged != td.req) {
                 // every request of a launch shares the context's logarithm table
                 if (!log_staged) stage_log(sm, r.logt);
                 log_staged = true;
-                stage_dressing(r, sm);
+                stage_dressing<PREC>(r, sm);
                 __syncthreads();
                 staged = td.req;
             }
@@ -1470,7 +1518,7 @@ __device__ __forceinline__ void dz_cell(const Smem &sm, int nZ, double za, doubl
 template <int FAM, int REG>
 __global__ void __launch_bounds__(64 * kDzWaves) dz_kernel(ReqDev r, double *__restrict__ jac) {
     extern __shared__ double2 lds_dyn[];
-    __shared__ float zslope;
+    __shared__ float f32c[2];
     __shared__ double part[kDzWaves][kWave];  // each wavefront's sums, combined in wave order
     Smem sm;
     const int nZ = r.nZ, e = (int)blockIdx.x;
@@ -1480,7 +1528,7 @@ __global__ void __launch_bounds__(64 * kDzWaves) dz_kernel(ReqDev r, double *__r
     const int n_in = FAM == 3 ? r.n_phi : r.n_x;    // nodes per row
     const long long n_rows = FAM == 3 ? (long long)r.n_q * r.n_x : r.n_q;
     const int E = dz_entries(n_in);
-    bind_smem(sm, lds_dyn, nZ, &zslope);
+    bind_smem(sm, lds_dyn, nZ, f32c);
     // after the padded table, per wavefront: the round's node arrays (compacted in place into
     // per-cell runs), then its per-row arrays and the entry slots
     const int R = dz_rows(n_in);
@@ -1506,7 +1554,7 @@ __global__ void __launch_bounds__(64 * kDzWaves) dz_kernel(ReqDev r, double *__r
     int *nrun = r1iz + R;           // runs per row
     if (wv == 0) {
         stage_log(sm, r.logt);
-        stage_dressing(r, sm);
+        stage_dressing<0>(r, sm);
     }
     __syncthreads();
     const double p = fabs(r.ext[e]);

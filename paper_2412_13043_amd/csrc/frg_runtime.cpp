@@ -630,10 +630,9 @@ int finalize_blocks(const ReqDev &r) {
 }
 
 int lds_bytes_for(const ReqDev &r) {
-    // logarithm table, float64 dressing pairs, float32 dressing pairs (float32 form)
+    // logarithm table and dressing pairs (the float32 form rounds the float64 pairs at use)
     if (r.family == 1) return 0;
-    return (kLogTable + r.nZ + 1) * (int)sizeof(double2) +
-           (r.precision == 1 ? (r.nZ + 1) * (int)sizeof(float2) : 0);
+    return (kLogTable + r.nZ + 1) * (int)sizeof(double2);
 }
 
 frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_batch &b,

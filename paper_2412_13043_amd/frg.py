@@ -157,10 +157,15 @@ _lib.frg_serving_replay.argtypes = [c_void_p, c_void_p, c_int, c_int, POINTER(fr
 _lib.frg_serving_replay.restype = c_int
 _lib.frg_flop_probe.argtypes = [c_int, c_int, c_int, c_void_p, c_void_p]
 _lib.frg_flop_probe.restype = c_int
+_lib.frg_math_probe.argtypes = [c_int, POINTER(c_double), c_void_p]
+_lib.frg_math_probe.restype = c_int
+_lib.frg_fp32_error_constants.argtypes = [POINTER(c_double)]
+_lib.frg_fp32_error_constants.restype = None
 _lib.frg_session_fake_fail_launches.argtypes = [c_void_p, c_int]
 _lib.frg_session_fake_fail_launches.restype = c_int
 TESTING_EXPORTED = ("frg_session_open_fake", "frg_session_fake_fail_launches",
-                    "frg_serving_replay", "frg_flop_probe")
+                    "frg_serving_replay", "frg_flop_probe", "frg_math_probe",
+                    "frg_fp32_error_constants")
 
 
 def frg_last_error() -> str:
@@ -288,6 +293,21 @@ def frg_flop_probe(seq: int, blocks: int, iters: int, out, stream=None) -> None:
     if out.numel() < blocks * 64:
         raise ValueError("out needs blocks * 64 values")
     _check(_lib.frg_flop_probe(seq, blocks, iters, _dptr(out), _stream(stream)), "frg_flop_probe")
+
+
+def frg_math_probe(which: int, stream=None) -> float:
+    """Largest error of one float32 elementary operation over its whole input range
+    (include/frg_testing.h): 0 log2 (absolute, on [1/2, 1)), 1 expm1(-y), 2 reciprocal."""
+    v = c_double()
+    _check(_lib.frg_math_probe(which, byref(v), _stream(stream)), "frg_math_probe")
+    return v.value
+
+
+def frg_fp32_error_constants() -> tuple:
+    """(u, log2 error, expm1 error, reciprocal error) the float32 form's bound uses."""
+    a = (c_double * 4)()
+    _lib.frg_fp32_error_constants(a)
+    return tuple(a)
 
 
 def frg_session_fake_fail_launches(s: int, n: int) -> None:

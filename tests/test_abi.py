@@ -98,7 +98,7 @@ def test_binding_loads_a_single_hip_runtime():
 
 def test_library_exports_every_testing_symbol():
     text = open(os.path.join(ROOT, "include", "frg_testing.h")).read()
-    names = sorted(set(re.findall(r"^\s*frg_status\s*(frg_\w+)\s*\(", text, re.M)))
+    names = sorted(set(re.findall(r"^\s*(?:frg_status|void)\s*(frg_\w+)\s*\(", text, re.M)))
     assert "frg_serving_replay" in names and "frg_session_open_fake" in names
     assert sorted(frg.TESTING_EXPORTED) == names
     lib = ctypes.CDLL(frg.LIB_PATH)

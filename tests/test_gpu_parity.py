@@ -250,7 +250,22 @@ def test_fp32_form_within_stated_bound(env, tau):
     print(f"fp32 form tau={tau}: max rel err {rel.max():.3e}, median {np.median(rel):.3e}, "
           f"max stated bound {bound.max():.3e}")
     assert np.all(rel <= bound)
-    assert np.all(bound < 1e-3)
+    # not vacuous: below 1e-4 everywhere, below 1e-5 where the fallback caps kappa at 10
+    assert np.all(bound < 1e-4)
+    if tau >= 0.1:
+        assert np.all(bound < 1e-5)
+
+
+def test_fp32_error_constants_cover_measured(env):
+    """The bound's constants for the float32 log2, expm1 and reciprocal are at least the largest
+    errors over every float32 input of their ranges."""
+    frg, ctx, torch = env
+    u, *consts = frg.frg_fp32_error_constants()
+    assert u == 2.0 ** -24
+    for which, c in enumerate(consts):
+        got = frg.frg_math_probe(which)
+        print(f"float32 probe {which}: largest error {got / u:.4f} u, bound constant {c / u:.4f} u")
+        assert 0.0 < got <= c, (which, got / u, c / u)
 
 
 def test_fp32_form_lpa_and_three_point(env):
