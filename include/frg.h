@@ -189,8 +189,9 @@ typedef struct {
                               its point's mass, evaluated in the same pass by forward-mode
                               differentiation through every propagator (dG/dm2 = -G^2; the
                               Jacobian entries of implicit steppers, Sec. 5.2 and the "AD" option
-                              of App. F); float64 only (FRG_E_UNSUPPORTED otherwise); not taken
-                              by sessions (FRG_E_UNSUPPORTED) */
+                              of App. F); float64 only (FRG_E_UNSUPPORTED otherwise); taken by
+                              frg_integrate_batch, frg_integrate_multi and sessions (there a
+                              host buffer, returned with out) */
     double *dout_dz;       /* device [n_ext * Z.n] or NULL: dI_e/dZ_i, row-major (entry i of point
                               e at e * Z.n + i), the derivatives of each result in the entries of
                               its dressing table (the forward-mode derivatives of the "AD" option
@@ -202,11 +203,14 @@ typedef struct {
                               temperature the dressing multiplies the spatial momentum) in
                               float64 with a dressing table only (FRG_E_UNSUPPORTED for the
                               LPA families and the float32 form,
-                              FRG_E_INVAL without a table), frg_integrate_batch only
-                              (FRG_E_UNSUPPORTED from frg_integrate_multi and sessions); the
-                              caller owns the buffer.  Computed by a second kernel after the
-                              integral on the same stream; each row's sums have one fixed order
-                              (no atomics), so the values are reproducible bit for bit */
+                              FRG_E_INVAL without a table), frg_integrate_batch and
+                              frg_integrate_multi (FRG_E_UNSUPPORTED from sessions); the caller
+                              owns the buffer.  Computed by a second kernel after the
+                              integrals on the same stream.  Each point's parts are rounded to
+                              units of 2^-62 of its largest part and added as integers, so
+                              the values are the same bits for any launch shape or order, and
+                              where every term has one sign each entry errs by at most its
+                              number of parts x 2^-62 of its row's largest entry */
 } frg_batch;
 
 /* ---- threshold functions of the flat regulator -------------------------------------------- */
@@ -412,7 +416,7 @@ typedef struct {
  * FRG_E_NOMEM at submit. */
 #define FRG_SESSION_STAGING_BYTES ((size_t)32 << 20)
 
-/* Requests submitted to a session hold HOST pointers (ext, m2, out, err_out); the session
+/* Requests submitted to a session hold HOST pointers (ext, m2, out, err_out, dout_dm2); the session
  * stages them into device memory it owns, admitted against the HBM budget, evaluates them in
  * fused launches that new arrivals join while earlier launches run (continuous batching), and
  * copies results back before the ticket completes.  A launch holds a bounded amount of work

@@ -17,6 +17,13 @@ step-size rule are the standard ones of Hairer, Norsett & Wanner, Solving ODEs I
 A step that would pass t_end ends exactly there.  fixed_step: steps of exactly h0, no control.
 
 Abm4 (below) is the fixed-step Adams-Bashforth-Moulton 4 PECE stepper with an RK4 start.
+
+Rkf78 (below) is the Runge-Kutta-Fehlberg 7(8) pair (the RK78 class the paper lists next to
+RK45, Sec. 5.2): E. Fehlberg, "Classical fifth-, sixth-, seventh-, and eighth-order Runge-Kutta
+formulas with stepsize control", NASA TR R-287 (1968), the 13-stage 7(8) formulas.  The
+eighth-order solution is kept (local extrapolation); the error estimate is the difference of
+the two solutions, 41/840 h (k_1 + k_11 - k_12 - k_13); the norm and the step rule are those
+above with the exponent -1/8 (the lower order plus one).
 """
 from __future__ import annotations
 
@@ -181,4 +188,115 @@ class Abm4:
             self.y = ynew
             self.hist = ([self._f(self.t, self.y)] + self.hist)[:4]
             self.accepted += 1
+        return "ok"
+
+
+# Fehlberg 7(8), exact fractions: nodes, stage coefficients (row i: a_i0 .. a_i,i-1), seventh-
+# and eighth-order weights
+C78 = [F(0), F(2, 27), F(1, 9), F(1, 6), F(5, 12), F(1, 2), F(5, 6), F(1, 6), F(2, 3), F(1, 3),
+       F(1), F(0), F(1)]
+
+
+def _row(i, entries):
+    r = [F(0)] * i
+    for j, v in entries.items():
+        r[j] = v
+    return r
+
+
+A78 = [
+    [],
+    _row(1, {0: F(2, 27)}),
+    _row(2, {0: F(1, 36), 1: F(1, 12)}),
+    _row(3, {0: F(1, 24), 2: F(1, 8)}),
+    _row(4, {0: F(5, 12), 2: F(-25, 16), 3: F(25, 16)}),
+    _row(5, {0: F(1, 20), 3: F(1, 4), 4: F(1, 5)}),
+    _row(6, {0: F(-25, 108), 3: F(125, 108), 4: F(-65, 27), 5: F(125, 54)}),
+    _row(7, {0: F(31, 300), 4: F(61, 225), 5: F(-2, 9), 6: F(13, 900)}),
+    _row(8, {0: F(2), 3: F(-53, 6), 4: F(704, 45), 5: F(-107, 9), 6: F(67, 90), 7: F(3)}),
+    _row(9, {0: F(-91, 108), 3: F(23, 108), 4: F(-976, 135), 5: F(311, 54), 6: F(-19, 60),
+             7: F(17, 6), 8: F(-1, 12)}),
+    _row(10, {0: F(2383, 4100), 3: F(-341, 164), 4: F(4496, 1025), 5: F(-301, 82),
+              6: F(2133, 4100), 7: F(45, 82), 8: F(45, 164), 9: F(18, 41)}),
+    _row(11, {0: F(3, 205), 5: F(-6, 41), 6: F(-3, 205), 7: F(-3, 41), 8: F(3, 41),
+              9: F(6, 41)}),
+    _row(12, {0: F(-1777, 4100), 3: F(-341, 164), 4: F(4496, 1025), 5: F(-289, 82),
+              6: F(2193, 4100), 7: F(51, 82), 8: F(33, 164), 9: F(12, 41), 11: F(1)}),
+]
+B7 = [F(41, 840), F(0), F(0), F(0), F(0), F(34, 105), F(9, 35), F(9, 35), F(9, 280), F(9, 280),
+      F(41, 840), F(0), F(0)]
+B8 = [F(0), F(0), F(0), F(0), F(0), F(34, 105), F(9, 35), F(9, 35), F(9, 280), F(9, 280), F(0),
+      F(41, 840), F(41, 840)]
+
+
+class Rkf78:
+    """Adaptive Runge-Kutta-Fehlberg 7(8): the eighth-order solution with the difference of the
+    two as its error estimate, the norm and step rule of Dopri5 with exponent -1/8.  Thirteen
+    right-hand sides per attempted step (no stage is shared between steps; a rejected step
+    keeps its first).  fixed_step: steps of exactly h0 without control."""
+
+    def __init__(self, f, y0, *, rtol, atol, h0, h_min, h_max, max_steps, fixed_step=False,
+                 t0=0.0):
+        self.f = f
+        self.y = np.array(y0, dtype=np.float64)
+        self.t = float(t0)
+        self.rtol, self.atol = rtol, atol
+        self.h0, self.h_min, self.h_max = h0, h_min, h_max
+        self.h = min(max(h0, h_min), h_max)
+        self.max_steps = max_steps
+        self.fixed = fixed_step
+        self.k0 = None
+        self.rejected_last = False
+        self.accepted = 0
+        self.rejected = 0
+        self.evals = 0
+        self.last_err = 0.0
+
+    def _f(self, t, y):
+        self.evals += 1
+        return np.asarray(self.f(t, y), dtype=np.float64)
+
+    def advance(self, t_end):
+        """Advance to t_end; returns "ok", "max_steps" or "h_min"."""
+        attempts = 0
+        while self.t < t_end:
+            if attempts >= self.max_steps:
+                return "max_steps"
+            attempts += 1
+            h = self.h0 if self.fixed else self.h
+            last = self.t + h >= t_end * (1.0 - 1e-14) - 1e-300
+            if last:
+                h = t_end - self.t
+            if self.k0 is None:
+                self.k0 = self._f(self.t, self.y)
+            K = [self.k0]
+            for s in range(1, 13):
+                incr = sum(float(A78[s][j]) * K[j] for j in range(s))
+                K.append(self._f(self.t + float(C78[s]) * h, self.y + h * incr))
+            ynew = self.y + h * sum(float(B8[j]) * K[j] for j in range(13))
+            if self.fixed:
+                err = 0.0
+            else:
+                est = h * sum(float(B8[j] - B7[j]) * K[j] for j in range(13))
+                sc = self.atol + self.rtol * np.maximum(np.abs(self.y), np.abs(ynew))
+                err = math.sqrt(float(np.mean((est / sc) ** 2)))
+            self.last_err = err
+            if self.fixed or err <= 1.0:
+                self.y = ynew
+                self.k0 = None
+                self.t = t_end if last else self.t + h
+                self.accepted += 1
+                if self.fixed:
+                    continue
+                fac = 0.9 * err ** -0.125 if err > 0 else 5.0
+                fmax = 1.0 if self.rejected_last else 5.0
+                self.h = min(max(h * min(fmax, max(0.2, fac)), self.h_min), self.h_max)
+                self.rejected_last = False
+            else:
+                self.rejected += 1
+                self.rejected_last = True
+                if h <= self.h_min:
+                    return "h_min"
+                fac = 0.9 * err ** -0.125
+                self.h = min(max(h * min(1.0, max(0.2, fac)), self.h_min), self.h_max)
         return "ok"

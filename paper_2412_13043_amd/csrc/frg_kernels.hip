@@ -1468,45 +1468,46 @@ hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg, int 
 // The sums are organised in rows: a radial node (FAM 2, 5) with its cos1 nodes, or a (radial,
 // cos1) pair (FAM 3) with its phi nodes.  Along a row the innermost propagator's argument grows
 // (ascending x with p taken as |p|; ascending phi with sin(alpha) taken as |sin(alpha)|), so its
-// cells are non-decreasing.  Workgroup (e, slice) computes entries j = 64 slice + lane of point
-// e, one per lane, in rounds of rows: a round's node terms and cells go to LDS, one lane per row
-// adds the row in order into one pair of sums per cell (the parts for the cell's lower and upper
-// entry).  A row's runs have distinct cells, so each run's parts land in their own slots of the
-// slice (upper part at entry cell, lower part at entry cell - 1), and the owner of entry j takes,
-// row by row, its upper slot, its lower slot and the row's single-cell terms (radial leg; FAM 3
-// also the first inner leg).  A workgroup holds up to kDzWaves wavefronts sharing the staged
-// tables; each takes a contiguous share of the rows, and their sums are combined in wavefront
-// order.  Every entry's sum has one fixed order and no atomics.
+// cells are non-decreasing and the row falls into runs of equal cell.  One workgroup takes one
+// point; each lane takes whole rows and adds each run's parts for the cell's lower and upper
+// entry in float64, in row order.  Across lanes the parts are added exactly, as 64-bit integers
+// in units of 2^-S of the point's sum: a first pass over the rows finds the largest part P
+// (2^(E-1) <= P < 2^E) and sets S = 61 - E; the second pass rounds each part to the nearest unit
+// (at most 2^-62 P) and adds it, split into its multiple of 2^32 units and the rest, to two
+// integer accumulators per entry in LDS.  Integer addition is associative, so the result is the
+// same bits for any assignment of rows to lanes and any order of the atomics; each entry errs by
+// at most (its parts) x 2^-62 P, and where every term has one sign (G > 0 throughout) the row's
+// largest entry is at least P, so the error relative to it stays below 2^-62 per part (about
+// 1e-14 for the 10^5 parts of a three-point point).
 
-// node terms of one wavefront's round held in LDS: at least 128 and at least one row; rows per
-// round
-__host__ __device__ __forceinline__ int dz_entries(int n_in) { return n_in > 128 ? n_in : 128; }
-__host__ __device__ __forceinline__ int dz_rows(int n_in) {
-    const int r = dz_entries(n_in) / n_in;
-    return r < 1 ? 1 : (r > kWave ? kWave : r);
-}
-
-// Weight of entry j in the interpolation at padded cell index iz (0 and nZ are the clamped ends,
-// where one entry takes the whole value), fraction f; iz must be j or j + 1.
-__device__ __forceinline__ double dz_weight(int iz, double f, int j, int nZ) {
-    if (iz == 0 || iz == nZ) return 1.0;
-    return iz == j ? f : 1.0 - f;
-}
-
-constexpr int kDzRowD = 11;  // per-row double arrays
-constexpr int kDzRowI = 3;   // per-row int arrays
-
-constexpr int kDzWaves = 8;  // wavefronts per workgroup (at most), each with a share of the rows
-
-// LDS of one wavefront's round buffers (16-byte multiple), then of the whole workgroup
-__host__ __device__ __forceinline__ size_t dz_wave_bytes(int n_in) {
-    const size_t E = (size_t)dz_entries(n_in), R = (size_t)dz_rows(n_in);
-    const size_t b = 3 * E * sizeof(double) + kDzRowD * R * sizeof(double) +
-                     2 * R * kWave * sizeof(double) + E * sizeof(int) + kDzRowI * R * sizeof(int);
-    return (b + 15) / 16 * 16;
-}
-size_t dz_lds_bytes(int nZ, int n_in, int waves) {
-    return (size_t)(kLogTable + nZ + 1) * sizeof(double2) + waves * dz_wave_bytes(n_in);
+// One float64 propagator (the arithmetic of propagators64<1, false, REG>, in units of k^2) with
+// its padded cell and fraction.
+template <int REG>
+__device__ __forceinline__ double prop_cell64(double l2, const Smem &sm, int nZ, double za,
+                                              double zb1, double m2, int reg_n, int &iz,
+                                              double &fz) {
+    const double2 t = sm.logt[(__double2hiint(l2) >> 12) & 0xff];
+    double E;
+    if (REG == 0)
+        E = fm::expm1_neg(l2);
+    else if (REG == 1)
+        E = fm::exp_neg(fmin(poly_s(l2, reg_n), 1000.0));
+    else
+        E = fmax(1.0 - l2, 0.0);
+    const double f = __builtin_amdgcn_frexp_mant(l2);
+    const int k = __builtin_amdgcn_frexp_exp(l2);
+    const double r = fma(f, t.x, -1.0);
+    double p = fma(r, -0.25, 0.3333333333333333);
+    p = fma(r, p, -0.5);
+    p = fma(r, p, 1.0);
+    p = r * p;
+    const double ln = fma((double)k, fm::LN2_HI, t.y + p);
+    zcell64(fma(ln, za, zb1), nZ, iz, fz);
+    const double2 z = sm.Z64[iz];
+    const double zv = fma(fz, z.y, z.x);
+    if (REG != 0) return fm::rcp_nr(fma(zv, l2, m2) + E);
+    const double den = fma(-E, fma(zv, l2, m2), fma(l2, E, l2));
+    return -E * fm::rcp_nr(den);
 }
 
 // Padded cell index and fraction of the dressing coordinate s + 1 = za log(v) + zb1.
@@ -1515,47 +1516,130 @@ __device__ __forceinline__ void dz_cell(const Smem &sm, int nZ, double za, doubl
     zcell64(fma(fm::log_tab(v, sm.logt), za, zb1), nZ, iz, f);
 }
 
+constexpr int kDzMaxWaves = 16;  // wavefronts per workgroup (one point)
+
+// LDS of a workgroup: the logarithm and dressing tables, then the integer accumulators
+size_t dz_lds_bytes(int nZ) {
+    return (size_t)(kLogTable + nZ + 1) * sizeof(double2) +
+           (size_t)nZ * 2 * sizeof(unsigned long long);
+}
+
+// Parts of one row, handed to part(entry, value): the runs of the innermost leg (lower and upper
+// entry of each run's cell), then the row's single-cell terms -- the radial leg and (FAM 3) the
+// first inner leg.  Values in the units of the point's sum before the prefactor.
+template <int FAM, int REG, typename Part>
+__device__ __forceinline__ void dz_row(const ReqDev &r, const Smem &sm, long long row, double p,
+                                       double ca, double sa, double p0, double m2, double inv_k2,
+                                       Part &&part) {
+    const int nZ = r.nZ;
+    const double zb1 = r.zbk + 1.0;
+    const int a = FAM == 3 ? (int)(row / r.n_x) : (int)row;
+    const RadialTerm t = radial64(r, sm, a, p, m2);
+    const double q = r.k * kc(r.rad.q)[a];
+    const double q2 = q * q;
+    const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2;
+    const double uf = FAM == 3 ? inv_k2 * inv_k2 : inv_k2;  // units of the inner sums
+    double rw, A, B, mh, g1 = 0.0, l1 = 0.0, f1 = 0.0, xw = 0.0;
+    int i1 = 0;
+    if (FAM == 3) {
+        const int b = (int)(row - (long long)a * r.n_x);
+        const double xb = kc(r.ang.x)[b];
+        mh = m2 * inv_k2;
+        l1 = fma(c1, xb, c0);
+        g1 = prop_cell64<REG>(l1, sm, nZ, r.za, zb1, mh, r.reg_n, i1, f1);
+        xw = kc(r.ang.xw)[b];
+        rw = t.wg * (xw * g1);
+        A = fma(-c1, xb * ca, c0);
+        B = -c1 * (kc(r.ang.xs)[b] * sa);
+    } else {
+        double m2x = m2;
+        if (FAM == 5) {
+            const double wl = kc(r.rad.w0)[a] + p0;
+            m2x = fma(wl, wl, m2);
+        }
+        rw = t.wg;
+        A = c0;
+        B = c1;
+        mh = m2x * inv_k2;
+    }
+    // cell iz (padded): entry iz - 1 takes (1 - f) v, entry iz takes f v; at the clamped ends
+    // one entry takes all of v
+    auto single = [&](int iz, double f, double v) {
+        if (iz == 0) {
+            part(0, v);
+        } else if (iz == nZ) {
+            part(nZ - 1, v);
+        } else {
+            part(iz - 1, (1.0 - f) * v);
+            part(iz, f * v);
+        }
+    };
+    const int n_in = FAM == 3 ? r.n_phi : r.n_x;
+    double inner = 0.0, lo = 0.0, hi = 0.0;
+    int cur = -1, prev = 0;
+    for (int c = 0; c < n_in; ++c) {
+        const double u = FAM == 3 ? kc(r.phi.c)[c] : kc(r.ang.x)[c];
+        const double w = FAM == 3 ? kc(r.phi.w)[c] : kc(r.ang.xw)[c];
+        double l2 = fma(B, u, A);
+        if (FAM == 3) l2 = fmax(l2, FRG_L2_TINY);
+        int iz;
+        double f;
+        const double G = prop_cell64<REG>(l2, sm, nZ, r.za, zb1, mh, r.reg_n, iz, f);
+        inner += w * G;
+        const double v = -rw * (w * (G * G)) * (l2 * uf);
+        // a node within rounding of a cell boundary that reads one cell below its predecessor
+        // is taken at the boundary (the same weights up to that rounding)
+        if (iz < prev) {
+            iz = prev;
+            f = 0.0;
+        } else {
+            prev = iz;
+        }
+        if (iz != cur) {
+            if (cur > 0) part(cur - 1, lo);
+            if (cur >= 0 && cur < nZ) part(cur, hi);
+            cur = iz;
+            lo = 0.0;
+            hi = 0.0;
+        }
+        if (iz == 0)
+            hi += v;
+        else if (iz == nZ)
+            lo += v;
+        else {
+            lo = fma(1.0 - f, v, lo);
+            hi = fma(f, v, hi);
+        }
+    }
+    if (cur > 0) part(cur - 1, lo);
+    if (cur >= 0 && cur < nZ) part(cur, hi);
+    // radial leg -2 W G(q^2)^3 q^2 [xw G^(l1)] I (FAM 3 per (a, b), I = sum_c w_c G^(l2));
+    // FAM 3 first inner leg -W G(q^2)^2 xw G^(l1)^2 l1 I
+    int iq;
+    double fq;
+    dz_cell(sm, nZ, r.za, r.zb + 1.0, fmax(q2, FRG_L2_TINY), iq, fq);
+    single(iq, fq, -2.0 * t.g * q2 * rw * (inner * uf));
+    if (FAM == 3) single(i1, f1, -t.wg * (xw * (g1 * g1)) * l1 * (inner * uf));
+}
+
 template <int FAM, int REG>
-__global__ void __launch_bounds__(64 * kDzWaves) dz_kernel(ReqDev r, double *__restrict__ jac) {
+__global__ void __launch_bounds__(64 * kDzMaxWaves) dz_kernel(ReqDev r, double *__restrict__ jac) {
     extern __shared__ double2 lds_dyn[];
     __shared__ float f32c[2];
-    __shared__ double part[kDzWaves][kWave];  // each wavefront's sums, combined in wave order
+    __shared__ double wmax[kDzMaxWaves];
     Smem sm;
     const int nZ = r.nZ, e = (int)blockIdx.x;
     const int lane = (int)threadIdx.x & (kWave - 1), wv = (int)threadIdx.x / kWave;
-    const int nw = (int)blockDim.x / kWave;  // wavefronts of this launch (1..kDzWaves)
-    const int j = (int)blockIdx.y * kWave + lane;  // the entry this lane owns
-    const int n_in = FAM == 3 ? r.n_phi : r.n_x;    // nodes per row
+    const int nw = (int)blockDim.x / kWave, nt = (int)blockDim.x;
     const long long n_rows = FAM == 3 ? (long long)r.n_q * r.n_x : r.n_q;
-    const int E = dz_entries(n_in);
     bind_smem(sm, lds_dyn, nZ, f32c);
-    // after the padded table, per wavefront: the round's node arrays (compacted in place into
-    // per-cell runs), then its per-row arrays and the entry slots
-    const int R = dz_rows(n_in);
-    double *nv = (double *)((char *)(lds_dyn + kLogTable + nZ + 1) + wv * dz_wave_bytes(n_in));
-    double *nf = nv + E;            // node cell fraction, then run's upper part
-    double *xg = nf + E;            // w G^(node), for the row's inner sum
-    double *rw = xg + E;            // row factor of the node terms
-    double *rwg = rw + R;           // W G(q^2)^2
-    double *rg = rwg + R;           // G(q^2)
-    double *rq2 = rg + R;           // q^2
-    double *rc0 = rq2 + R;          // node argument = rc1 * (x or cos phi) + rc0 (units of k^2)
-    double *rc1 = rc0 + R;
-    double *rm = rc1 + R;           // inner mass term / k^2
-    double *rf = rm + R;            // radial-leg cell fraction
-    double *rv = rf + R;            // radial-leg term of the row
-    double *r1f = rv + R;           // FAM 3: first inner leg's cell fraction
-    double *r1v = r1f + R;          // FAM 3: first inner leg's term of the row
-    double *hs = r1v + R;           // [R][64] upper parts by entry slot of this slice
-    double *ls = hs + R * kWave;    // [R][64] lower parts by entry slot
-    int *niz = (int *)(ls + R * kWave);  // node padded cell index, then run's cell
-    int *riz = niz + E;             // radial-leg padded cell index
-    int *r1iz = riz + R;            // FAM 3: first inner leg's padded cell index
-    int *nrun = r1iz + R;           // runs per row
+    unsigned long long *acc_hi = (unsigned long long *)(lds_dyn + kLogTable + nZ + 1);
+    unsigned long long *acc_lo = acc_hi + nZ;
     if (wv == 0) {
         stage_log(sm, r.logt);
         stage_dressing<0>(r, sm);
     }
+    for (int j = (int)threadIdx.x; j < 2 * nZ; j += nt) acc_hi[j] = 0ull;
     __syncthreads();
     const double p = fabs(r.ext[e]);
     double ca = 1.0, sa = 0.0, p0 = 0.0;
@@ -1566,171 +1650,44 @@ __global__ void __launch_bounds__(64 * kDzWaves) dz_kernel(ReqDev r, double *__r
     if (FAM == 5) p0 = r.ext[r.n_ext + e];
     const double m2 = lane_m2(r, e);
     const double inv_k2 = 1.0 / r.k2;
-    const double uf = FAM == 3 ? inv_k2 * inv_k2 : inv_k2;  // units of the inner sums
-    const double zb1 = r.zbk + 1.0;
-    const int j0 = (int)blockIdx.y * kWave;
-    // wavefront wv takes rows [lo, hi); every wavefront runs the same number of rounds (the
-    // barriers are the workgroup's), a finished one with no rows
-    const long long lo = n_rows * wv / nw, hi = n_rows * (wv + 1) / nw;
-    const long long span = (n_rows + nw - 1) / nw;
-    const long long rounds = (span + R - 1) / R;
-    double s = 0.0;
-    for (long long it = 0; it < rounds; ++it) {
-        const long long r0 = lo + it * R;
-        const int nr = (int)max(0LL, min((long long)R, hi - r0));
-        if (lane < nr) {
-            const long long row = r0 + lane;
-            const int a = FAM == 3 ? (int)(row / r.n_x) : (int)row;
-            const RadialTerm t = radial64(r, sm, a, p, m2);
-            const double q = r.k * kc(r.rad.q)[a];
-            const double q2 = q * q;
-            int iz;
-            double f;
-            dz_cell(sm, nZ, r.za, r.zb + 1.0, fmax(q2, FRG_L2_TINY), iz, f);
-            rwg[lane] = t.wg;
-            rg[lane] = t.g;
-            rq2[lane] = q2;
-            rf[lane] = f;
-            riz[lane] = iz;
-            const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2;
-            if (FAM == 3) {
-                const int b = (int)(row - (long long)a * r.n_x);
-                const double xb = kc(r.ang.x)[b];
-                const double m2h = m2 * inv_k2;
-                double l1[1] = {fma(c1, xb, c0)}, g1[1];
-                propagators64<1, false, REG>(l1, g1, sm, nZ, r.za, zb1, m2h, 1.0, r.far_y,
-                                             r.reg_n);
-                int i1;
-                double f1;
-                dz_cell(sm, nZ, r.za, zb1, l1[0], i1, f1);
-                const double xwg1 = kc(r.ang.xw)[b] * g1[0];
-                rw[lane] = t.wg * xwg1;
-                rc0[lane] = fma(-c1, xb * ca, c0);
-                rc1[lane] = -c1 * (kc(r.ang.xs)[b] * sa);
-                rm[lane] = m2h;
-                r1f[lane] = f1;
-                r1iz[lane] = i1;
-                // first inner leg, without the phi sum (added with it below)
-                r1v[lane] = -t.wg * (xwg1 * g1[0]) * l1[0];
-            } else {
-                double m2x = m2;
-                if (FAM == 5) {
-                    const double wl = kc(r.rad.w0)[a] + p0;
-                    m2x = fma(wl, wl, m2);
-                }
-                rw[lane] = t.wg;
-                rc0[lane] = c0;
-                rc1[lane] = c1;
-                rm[lane] = m2x * inv_k2;
-            }
-        }
-        __syncthreads();
-        const int nn = nr * n_in;
-        for (int t = lane; t < nn; t += kWave) {
-            const int al = t / n_in, c = t - al * n_in;
-            const double u = FAM == 3 ? kc(r.phi.c)[c] : kc(r.ang.x)[c];
-            const double w = FAM == 3 ? kc(r.phi.w)[c] : kc(r.ang.xw)[c];
-            double l2[1] = {fma(rc1[al], u, rc0[al])}, G[1];
-            if (FAM == 3) l2[0] = fmax(l2[0], FRG_L2_TINY);
-            propagators64<1, false, REG>(l2, G, sm, nZ, r.za, zb1, rm[al], 1.0, r.far_y,
-                                         r.reg_n);
-            int iz;
-            double f;
-            dz_cell(sm, nZ, r.za, zb1, l2[0], iz, f);
-            xg[t] = w * G[0];
-            nv[t] = -rw[al] * (w * (G[0] * G[0])) * (l2[0] * uf);
-            nf[t] = f;
-            niz[t] = iz;
-        }
-        __syncthreads();
-        if (lane < nr) {
-            // the row's inner sum, and the row compacted into runs of equal cell (run k is
-            // written at position k <= c, after position c has been read).  A node within
-            // rounding of a cell boundary that reads one cell below its predecessor is taken at
-            // the boundary (same weights up to that rounding).
-            const int base = lane * n_in;
-            double inner = 0.0, lo = 0.0, hi = 0.0;
-            int k = 0, cur = -1, prev = 0;
-            for (int c = 0; c < n_in; ++c) {
-                const int t = base + c;
-                inner += xg[t];
-                int iz = niz[t];
-                double f = nf[t];
-                const double v = nv[t];
-                if (iz < prev) {
-                    iz = prev;
-                    f = 0.0;
-                } else {
-                    prev = iz;
-                }
-                if (iz != cur) {
-                    if (cur >= 0) {
-                        nv[base + k] = lo;
-                        nf[base + k] = hi;
-                        niz[base + k] = cur;
-                        ++k;
-                    }
-                    cur = iz;
-                    lo = 0.0;
-                    hi = 0.0;
-                }
-                // cell iz (padded): entry iz - 1 takes (1 - f) v, entry iz takes f v; at the
-                // clamped ends one entry takes all of v
-                if (iz == 0)
-                    hi += v;
-                else if (iz == nZ)
-                    lo += v;
-                else {
-                    lo = fma(1.0 - f, v, lo);
-                    hi = fma(f, v, hi);
-                }
-            }
-            nv[base + k] = lo;
-            nf[base + k] = hi;
-            niz[base + k] = cur;
-            nrun[lane] = k + 1;
-            if (FAM == 3) {
-                // row = (a, b): radial leg -2 W G(q^2)^3 q^2 xw G^(l1) I_b, first inner leg
-                // -W G(q^2)^2 xw G^(l1)^2 l1 I_b, I_b = sum_c w_c G^(l2) (units k^-4 overall)
-                rv[lane] = -2.0 * rg[lane] * rq2[lane] * rw[lane] * (inner * uf);
-                r1v[lane] *= inner * uf;
-            } else {
-                rv[lane] = -2.0 * rw[lane] * rg[lane] * rq2[lane] * (inner * uf);
-            }
-        }
-        for (int t = lane; t < nr * kWave; t += kWave) {
-            hs[t] = 0.0;
-            ls[t] = 0.0;
-        }
-        __syncthreads();
-        for (int t = lane; t < nn; t += kWave) {
-            const int al = t / n_in, k = t - al * n_in;
-            if (k >= nrun[al]) continue;
-            const int c = niz[t];  // run k of row al (runs are stored from the row's start)
-            if (c >= j0 && c < j0 + kWave) hs[al * kWave + (c - j0)] = nf[t];
-            if (c - 1 >= j0 && c - 1 < j0 + kWave) ls[al * kWave + (c - 1 - j0)] = nv[t];
-        }
-        __syncthreads();
-        if (j < nZ) {
-            for (int al = 0; al < nr; ++al) {
-                s += hs[al * kWave + lane];
-                s += ls[al * kWave + lane];
-                const int iq = riz[al];
-                if (iq == j || iq == j + 1) s = fma(dz_weight(iq, rf[al], j, nZ), rv[al], s);
-                if (FAM == 3) {
-                    const int i1 = r1iz[al];
-                    if (i1 == j || i1 == j + 1) s = fma(dz_weight(i1, r1f[al], j, nZ), r1v[al], s);
-                }
-            }
-        }
-        __syncthreads();
+    // pass 1: the largest part (a NaN part makes P NaN)
+    double mx = 0.0;
+    for (long long row = threadIdx.x; row < n_rows; row += nt)
+        dz_row<FAM, REG>(r, sm, row, p, ca, sa, p0, m2, inv_k2, [&](int, double v) {
+            const double av = fabs(v);
+            mx = (av > mx || av != av) ? av : mx;
+        });
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const double y = __shfl_xor(mx, o);
+        mx = (y > mx || y != y) ? y : mx;
     }
-    part[wv][lane] = s;
+    if (lane == 0) wmax[wv] = mx;
     __syncthreads();
-    if (wv == 0 && j < nZ) {
-        double t = part[0][lane];
-        for (int w = 1; w < nw; ++w) t += part[w][lane];
-        jac[(long long)e * nZ + j] = r.pref * t;
+    double P = 0.0;
+    for (int w = 0; w < nw; ++w) P = (wmax[w] > P || wmax[w] != wmax[w]) ? wmax[w] : P;
+    const bool exact = P > 0.0 && P <= 1.0e300;  // finite and nonzero
+    // units of 2^-S, S = 61 - E: |part| 2^S < 2^61, so its multiple of 2^32 units fits an int
+    const int Eexp = exact ? __builtin_amdgcn_frexp_exp(P) : 0;
+    const double scale = ldexp(1.0, 61 - Eexp);
+    if (exact) {
+        // pass 2: the parts, exactly
+        for (long long row = threadIdx.x; row < n_rows; row += nt)
+            dz_row<FAM, REG>(r, sm, row, p, ca, sa, p0, m2, inv_k2, [&](int j, double v) {
+                if (v == 0.0) return;
+                const double x = v * scale;
+                const double h = floor(x * 0x1p-32);
+                const double l = rint(fma(-h, 0x1p32, x));  // in [0, 2^32]
+                atomicAdd(&acc_hi[j], (unsigned long long)(long long)(int)h);
+                atomicAdd(&acc_lo[j], (unsigned long long)l);
+            });
+    }
+    __syncthreads();
+    for (int j = (int)threadIdx.x; j < nZ; j += nt) {
+        // no part at all: zero; a non-finite part: that value in every entry of the point
+        const double v =
+            exact ? ldexp(fma((double)(long long)acc_hi[j], 0x1p32, (double)acc_lo[j]), Eexp - 61)
+                  : (P == 0.0 ? 0.0 : P);
+        jac[(long long)e * nZ + j] = r.pref * v;
     }
 }
 
@@ -1747,20 +1704,17 @@ hipError_t launch_dz(const ReqDev &r, double *jac, hipStream_t s) {
     void (*fn)(ReqDev, double *) = r.family == 3   ? dz_for_reg<3>(r.reg)
                                    : r.family == 5 ? dz_for_reg<5>(r.reg)
                                                    : dz_for_reg<2>(r.reg);
-    const int slices = (r.nZ + kWave - 1) / kWave;
-    const int n_in = r.family == 3 ? r.n_phi : r.n_x;
-    // as many wavefronts as the workgroup's LDS allows, up to 8 for the two-point families and 4
-    // for the three-point one (measured: its many short rows gain nothing from more)
-    int dev = 0, max_lds = 65536;
+    // one workgroup per point, a row or more per lane; fewer wavefronts per workgroup when there
+    // are points enough to fill the chip (the result does not depend on the choice)
+    int dev = 0, cus = 256;
     if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
-            hipSuccess)
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return hipGetLastError();
-    int waves = r.family == 3 ? 4 : kDzWaves;
-    const size_t fixed = sizeof(double) * kDzWaves * kWave + 16;  // static LDS of the kernel
-    while (waves > 1 && dz_lds_bytes(r.nZ, n_in, waves) + fixed > (size_t)max_lds) --waves;
-    hipLaunchKernelGGL(fn, dim3(r.n_ext, slices), dim3(kWave * waves),
-                       dz_lds_bytes(r.nZ, n_in, waves), s, r, jac);
+    const long long n_rows = r.family == 3 ? (long long)r.n_q * r.n_x : r.n_q;
+    int waves = (int)std::min<long long>(kDzMaxWaves, (n_rows + kWave - 1) / kWave);
+    while (waves > 4 && (long long)r.n_ext * waves > 16LL * cus) waves /= 2;
+    waves = std::max(1, waves);
+    hipLaunchKernelGGL(fn, dim3(r.n_ext), dim3(kWave * waves), dz_lds_bytes(r.nZ), s, r, jac);
     return hipGetLastError();
 }
 

@@ -758,6 +758,7 @@ frg_status get_scratch(frg_context *ctx, hipStream_t s, size_t n_contrib, size_t
     if ((st = grow(sc->counters, n_counters * sizeof(unsigned), s, true)) != FRG_OK) return st;
     if ((st = grow(sc->work, 2 * sizeof(unsigned), s, true)) != FRG_OK) return st;
     sc->last_key.clear();
+    sc->last_dz.clear();
     if ((st = grow(sc->reqs, n_reqs * sizeof(ReqDev), s, false)) != FRG_OK) return st;
     if ((st = grow(sc->tiles, n_tiles * sizeof(TileDev), s, false)) != FRG_OK) return st;
     *out = sc;
@@ -828,6 +829,7 @@ void common_kind(const std::vector<ReqDev> &reqs, int *fam, int *prec, int *reg,
 
 frg_status run_multi(frg_context *ctx, std::vector<ReqDev> &reqs, hipStream_t s, Scratch *sc,
                      int grid_waves) {
+    sc->last_dz.clear();  // a new plan: its caller adds its derivative blocks
     long long cb = 0, ctr = 0;
     for (ReqDev &r : reqs) {
         r.contrib_base = cb;
@@ -883,6 +885,7 @@ frg_status relaunch_multi(Scratch *sc, hipStream_t s) {
                                         (const TileDev *)sc->tiles.ptr + sc->last_tiles,
                                         sc->last_fin, (const double *)sc->contrib.ptr,
                                         (unsigned *)sc->counters.ptr, s));
+    for (const auto &d : sc->last_dz) FRG_HIP_CHECK(launch_dz(d.first, d.second, s));
     return FRG_OK;
 }
 
@@ -1135,17 +1138,13 @@ frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc 
             set_error("batch %d: %s", i, m.c_str());
             return st;
         }
-        if (batches[i].dout_dz) {
-            set_error("batch %d: frg_integrate_multi does not compute dout_dz "
-                      "(frg_integrate_batch does)", i);
-            return FRG_E_UNSUPPORTED;
-        }
         nodes[i] = nodes_per_point(descs[i]) * batches[i].n_ext;
         total_nodes += nodes[i];
     }
     std::lock_guard<std::mutex> lk(ctx->mu);
     FRG_HIP_CHECK(hipSetDevice(ctx->device));
     std::vector<ReqDev> reqs;
+    std::vector<std::pair<ReqDev, double *>> dz;  // dressing-table derivatives, after the launch
     size_t n_contrib = 0, n_ctr = 0, n_tiles = 0;
     const int target_total = 32 * ctx->num_cus;  // about twice the resident waves
     int n_active = 0;
@@ -1165,6 +1164,7 @@ frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc 
         n_ctr += counter_count(r);
         n_tiles += tile_count(r) + finalize_blocks(r);
         reqs.push_back(r);
+        if (batches[i].dout_dz) dz.emplace_back(r, batches[i].dout_dz);
     }
     if (reqs.empty()) return FRG_OK;
     Scratch *sc;
@@ -1172,6 +1172,8 @@ frg_status frg_integrate_multi(frg_context *ctx, int n, const frg_integral_desc 
         return st;
     sc->last_key.clear();
     if ((st = run_multi(ctx, reqs, stream, sc, 1 << 30)) != FRG_OK) return st;
+    for (const auto &d : dz) FRG_HIP_CHECK(launch_dz(d.first, d.second, stream));
+    sc->last_dz = std::move(dz);
     sc->last_key = std::move(key);
     return FRG_OK;
 }

@@ -81,6 +81,8 @@ struct Scratch {
     std::vector<char> last_key;
     int last_tiles = 0, last_grid = 0, last_lds = 0, last_nreqs = 0, last_fam = -1, last_prec = -1,
         last_reg = -1, last_der = -1, last_fin = 0;
+    // and its dressing-table derivative blocks, launched after the integrals
+    std::vector<std::pair<ReqDev, double *>> last_dz;
     ~Scratch() {
         if (host_stage) (void)hipHostFree(host_stage);
         if (staged) (void)hipEventDestroy(staged);

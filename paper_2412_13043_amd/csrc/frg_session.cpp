@@ -276,8 +276,14 @@ static void part_points(const SessReq &r, int et0, int et1, int *p0, int *p1) {
     *p1 = std::min(et1 * r.points_per_tile, r.host.n_ext);
 }
 
+// Output arrays a request returns: the integrals, then the float32 form's bounds and the mass
+// derivatives if asked for, each [n] doubles in that order.
+static int out_arrays(const SessReq &r) {
+    return 1 + (r.host.err_out ? 1 : 0) + (r.host.dout_dm2 ? 1 : 0);
+}
+
 static size_t part_out_bytes(const SessReq &r, int p0, int p1) {
-    return align256((r.host.err_out ? 2 : 1) * (size_t)(p1 - p0) * sizeof(double));
+    return align256(out_arrays(r) * (size_t)(p1 - p0) * sizeof(double));
 }
 
 static size_t tables_bytes(size_t n_parts, size_t n_tiles) {
@@ -320,6 +326,9 @@ class HipExecutor : public Executor {
             b.out = (double *)(blk + pt.out) - pt.p0;
             b.err_out = r->host.err_out ? (double *)(blk + pt.out) + (pt.p1 - pt.p0) - pt.p0
                                         : nullptr;
+            b.dout_dm2 = r->host.dout_dm2 ? (double *)(blk + pt.out) +
+                                                (out_arrays(*r) - 1) * (pt.p1 - pt.p0) - pt.p0
+                                          : nullptr;
             if (r->table_id >= 0)
                 b.Z = pt.resident;
             else if (r->host.Z.values)
@@ -403,6 +412,9 @@ class HipExecutor : public Executor {
             const size_t n = (size_t)(pt.p1 - pt.p0);
             std::memcpy(r->host.out + pt.p0, h + pt.out, n * 8);
             if (r->host.err_out) std::memcpy(r->host.err_out + pt.p0, h + pt.out + n * 8, n * 8);
+            if (r->host.dout_dm2)
+                std::memcpy(r->host.dout_dm2 + pt.p0, h + pt.out + (out_arrays(*r) - 1) * n * 8,
+                            n * 8);
         }
     }
 
@@ -754,9 +766,10 @@ static void request_layout(SessReq &r) {
     if (r.table_id < 0 && r.host.Z.values && is_vertex(d.family)) off += (size_t)r.host.Z.n * 8;
     r.in_bytes = off;
     r.slot_bytes = (r.chunked && d.precision == FRG_FP32_KAHAN) ? (n + 1) * 4 : 0;
-    r.contrib_bytes = r.chunked ? (size_t)plan_desc(d).n_q * n * 8 : 0;
-    r.footprint = align256(r.in_bytes) + align256(r.slot_bytes) +
-                  align256((r.host.err_out ? 2 : 1) * n * 8) + align256(r.contrib_bytes);
+    // radial contributions of a chunked shape, and as many derivative contributions
+    r.contrib_bytes = r.chunked ? (size_t)plan_desc(d).n_q * n * 8 * (r.host.dout_dm2 ? 2 : 1) : 0;
+    r.footprint = align256(r.in_bytes) + align256(r.slot_bytes) + align256(out_arrays(r) * n * 8) +
+                  align256(r.contrib_bytes);
 }
 
 static frg_status open_session(frg_context *ctx, const frg_session_config *cfg, bool fake,
@@ -862,10 +875,6 @@ frg_status frg_session_submit(frg_session *s, const frg_integral_desc *desc,
     }
     frg_status st = validate(desc, batch_host, false);
     if (st != FRG_OK) return st;
-    if (batch_host->dout_dm2) {
-        set_error("sessions do not return the mass derivative (dout_dm2 must be NULL)");
-        return FRG_E_UNSUPPORTED;
-    }
     if (batch_host->dout_dz) {
         set_error("sessions do not return dressing derivatives (dout_dz must be NULL)");
         return FRG_E_UNSUPPORTED;

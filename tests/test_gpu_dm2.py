@@ -1,7 +1,7 @@
 """GPU mass derivative dI/dm2 (forward mode through every propagator, same pass as I) against
 the oracle's derivative: 1e-12 relative per point in every family, regulator and at finite
 temperature; the value I unchanged bitwise by asking for the derivative; bitwise equal across
-tile shapes and fused launches; FRG_E_UNSUPPORTED for the float32 form and for sessions.
+tile shapes and fused launches and through sessions; FRG_E_UNSUPPORTED for the float32 form.
 """
 import math
 
@@ -152,13 +152,74 @@ def test_dm2_unsupported_combinations(env):
     with pytest.raises(frg.FrgError) as ei:
         ctx.integrate(desc, out, ext=ext, m2_scalar=0.5, dout=dout)
     assert ei.value.status == frg.FRG_E_UNSUPPORTED
+    # sessions: the float32 form with a derivative is refused at submit
     s = frg.frg_session_open(ctx.handle, frg.frg_session_config(1, 1 << 20, 20, 0))
     p = np.ones(4)
     o = np.zeros(4)
+    e = np.zeros(4)
     d = np.zeros(4)
     b = frg.frg_batch(4, p.ctypes.data, None, 0.5, frg.frg_log_table(None, 0, 1e-3, 1e3),
-                      o.ctypes.data, None, d.ctypes.data)
+                      o.ctypes.data, e.ctypes.data, d.ctypes.data)
     with pytest.raises(frg.FrgError) as ei:
-        frg.frg_session_submit(s, frg.make_desc(2, 8, 6.0, n_x=4), b, -1)
+        frg.frg_session_submit(s, desc, b, -1)
     assert ei.value.status == frg.FRG_E_UNSUPPORTED
     frg.frg_session_close(s)
+
+
+def test_dm2_through_sessions(env):
+    """Sessions return dI/dm2 in host buffers: every family, a request above one launch's node
+    budget (split into parts) and a radially chunked one, mixed with requests without it;
+    bitwise what frg_integrate_batch gives alone, and the oracle's derivative on samples."""
+    frg, ctx, torch = env
+    rng = np.random.default_rng(123)
+    P, A, m3, Z3 = wl.three_point()
+    Z = wl.dressing_table(8)
+
+    def req(desc, n, ext, m2, Zt, der):
+        return dict(desc=desc, n=n, ext=ext, m2=m2, Z=Zt, out=np.full(n, np.nan),
+                    dout=np.full(n, np.nan) if der else None)
+
+    p = wl.momenta_log(300)
+    reqs = [
+        req(frg.make_desc(1, 32, 6.0), 500, None, rng.uniform(-0.4, 2.0, 500), None, True),
+        req(frg.make_desc(2, 24, 10.0, n_x=12), 300, p, rng.uniform(0.1, 2.0, 300), Z, True),
+        req(frg.make_desc(2, 20, 10.0, n_x=8), 300, p, rng.uniform(0.1, 2.0, 300), Z, False),
+        # 1024 pairs x 64 x 32 x 16 = 5.4e8 nodes: evaluated in parts
+        req(frg.make_desc(3, wl.THREE_NQ, wl.THREE_QMAX, n_x=wl.THREE_NX, n_phi=wl.THREE_NPHI),
+            P.size, np.concatenate([P, A]), m3, Z3, True),
+        # few points, many radial nodes: a radially chunked shape
+        req(frg.make_desc(2, 256, 10.0, n_x=32), 8, np.ascontiguousarray(p[::40][:8]),
+            rng.uniform(0.1, 2.0, 8), Z, True),
+    ]
+    s = frg.frg_session_open(ctx.handle, frg.frg_session_config(4, 1 << 30, 10, 0))
+    tickets = []
+    for r in reqs:
+        zt = frg.frg_log_table(None if r["Z"] is None else r["Z"].ctypes.data,
+                               0 if r["Z"] is None else r["Z"].size, wl.Z_XMIN, wl.Z_XMAX)
+        b = frg.frg_batch(r["n"], None if r["ext"] is None else r["ext"].ctypes.data,
+                          r["m2"].ctypes.data, 0.0, zt, r["out"].ctypes.data, None,
+                          None if r["dout"] is None else r["dout"].ctypes.data)
+        tickets.append(frg.frg_session_submit(s, r["desc"], b, -1))
+    for t in tickets:
+        assert frg.frg_session_wait(s, t, 120000) == frg.FRG_OK
+    st = frg.frg_session_stats(s)
+    frg.frg_session_close(s)
+    assert st.completed == len(reqs) and st.failed == 0
+    for i, r in enumerate(reqs):
+        val, dv = _run(env, r["desc"], r["n"], ext=r["ext"], m2=r["m2"], Z=r["Z"],
+                       der=r["dout"] is not None)
+        assert np.array_equal(r["out"], val), i
+        if r["dout"] is None:
+            continue
+        assert np.array_equal(r["dout"], dv), i
+        d = r["desc"]
+        idx = np.unique(np.concatenate([[0, r["n"] - 1], rng.choice(r["n"], 6, replace=False)]))
+        if d.family == 1:
+            ref = oracle.integrate(oracle.LPA, d.n_q, d.q_max, m2=r["m2"][idx], dm2=True)
+        elif d.family == 2:
+            ref = oracle.integrate(oracle.TWO_POINT, d.n_q, d.q_max, n_x=d.n_x,
+                                   ext=r["ext"][idx], m2=r["m2"][idx], Z=r["Z"], dm2=True)
+        else:
+            ref = oracle.integrate(oracle.THREE_POINT, d.n_q, d.q_max, n_x=d.n_x, n_phi=d.n_phi,
+                                   ext=(P[idx], A[idx]), m2=r["m2"][idx], Z=r["Z"], dm2=True)
+        assert _rel(r["dout"][idx], ref) <= TOL, i

@@ -204,6 +204,74 @@ def test_dz_reproducible_and_value_unchanged(env):
     assert np.array_equal(out.cpu().numpy(), v1)
 
 
+def test_dz_same_bits_alone_and_in_a_batch(env):
+    """The block is summed exactly across lanes (integer accumulation), so a point's entries
+    are the same bits whether it is launched alone (a workgroup of 16 wavefronts) or among
+    1024 points (4 wavefronts per workgroup)."""
+    frg, ctx, torch = env
+    P, A, m3, Z3 = wl.three_point()
+    d3 = frg.make_desc(frg.FRG_FAMILY_THREE_POINT, 24, wl.THREE_QMAX, n_x=12, n_phi=8)
+
+    def block(idx):
+        n = idx.size
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        jac = torch.full((n * Z3.size,), float("nan"), dtype=torch.float64, device="cuda")
+        ctx.integrate(d3, out, ext=_d(torch, np.concatenate([P[idx], A[idx]])),
+                      m2=_d(torch, m3[idx]), Z=_d(torch, Z3), x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
+                      dz=jac)
+        torch.cuda.synchronize()
+        return jac.cpu().numpy().reshape(n, Z3.size)
+
+    every = block(np.arange(P.size))
+    for i in (0, 517, P.size - 1):
+        assert np.array_equal(block(np.array([i])), every[i:i + 1]), i
+
+
+def test_dz_through_fused_launches(env):
+    """frg_integrate_multi computes each request's block after the fused launch: the same bits
+    as frg_integrate_batch per request, requests without it untouched, and again when the same
+    call is repeated (the plan cache relaunches the blocks too)."""
+    frg, ctx, torch = env
+    P, A, m3, Z3 = wl.three_point()
+    p, m2, Z2 = wl.two_point()
+    sel = np.arange(0, P.size, 7)
+    reqs = [
+        (frg.make_desc(frg.FRG_FAMILY_THREE_POINT, 24, wl.THREE_QMAX, n_x=12, n_phi=8),
+         np.concatenate([P[sel], A[sel]]), m3[sel], Z3, True),
+        (frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 32, wl.TWO_QMAX, n_x=16), p,
+         np.full(p.size, m2), Z2, True),
+        (frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 16, wl.TWO_QMAX, n_x=8), p,
+         np.full(p.size, m2), Z2, False),
+    ]
+    descs, batches, outs, jacs, keep, alone = [], [], [], [], [], []
+    for desc, ext, mm, Z, want in reqs:
+        n = mm.size
+        te, tm, tZ = _d(torch, ext), _d(torch, mm), _d(torch, Z)
+        out = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        jac = torch.full((n * Z.size,), float("nan"), dtype=torch.float64, device="cuda") \
+            if want else None
+        descs.append(desc)
+        batches.append(frg.make_batch(n, out, ext=te, m2=tm, Z=tZ, x_min=wl.Z_XMIN,
+                                      x_max=wl.Z_XMAX, dz=jac))
+        outs.append(out)
+        jacs.append(jac)
+        keep += [te, tm, tZ]
+        o1 = torch.empty(n, dtype=torch.float64, device="cuda")
+        j1 = torch.empty(n * Z.size, dtype=torch.float64, device="cuda") if want else None
+        ctx.integrate(desc, o1, ext=te, m2=tm, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, dz=j1)
+        alone.append((o1, j1))
+    for rep in range(2):
+        for j in jacs:
+            if j is not None:
+                j.fill_(float("nan"))
+        ctx.integrate_multi(descs, batches)
+        torch.cuda.synchronize()
+        for i in range(len(reqs)):
+            assert torch.equal(outs[i], alone[i][0]), (rep, i)
+            if jacs[i] is not None:
+                assert torch.equal(jacs[i], alone[i][1]), (rep, i)
+
+
 def test_dz_unsupported_and_invalid(env):
     frg, ctx, torch = env
     n = 4
@@ -227,11 +295,16 @@ def test_dz_unsupported_and_invalid(env):
     with pytest.raises(frg.FrgError) as ei:
         frg.frg_integrate_batch(ctx.handle, d2, b, 0)
     assert ei.value.status == frg.FRG_E_INVAL
-    # the fused call does not compute it
-    b = frg.make_batch(n, out, ext=ext, m2_scalar=0.5, Z=Z, dz=jac)
+    # sessions do not return it
+    s = frg.frg_session_open(ctx.handle, frg.frg_session_config(1, 1 << 20, 20, 0))
+    hp, ho, hz, hj = np.ones(n), np.zeros(n), wl.dressing_table(1, 16), np.zeros(n * 16)
+    hb = frg.frg_batch(n, hp.ctypes.data, None, 0.5,
+                       frg.frg_log_table(hz.ctypes.data, 16, wl.Z_XMIN, wl.Z_XMAX),
+                       ho.ctypes.data, None, None, hj.ctypes.data)
     with pytest.raises(frg.FrgError) as ei:
-        ctx.integrate_multi([d2], [b])
+        frg.frg_session_submit(s, d2, hb, -1)
     assert ei.value.status == frg.FRG_E_UNSUPPORTED
+    frg.frg_session_close(s)
     with pytest.raises(ValueError):
         frg.make_batch(n, out, ext=ext, m2_scalar=0.5, Z=Z, dz=jac[:-1])
     torch.cuda.synchronize()

@@ -169,19 +169,56 @@ def test_invalid_session_arguments():
     frg.frg_session_close(s)
 
 
-def test_derivative_outputs_are_rejected_at_submit():
-    # sessions return values only: the mass and dressing derivatives are FRG_E_UNSUPPORTED
+def test_derivative_outputs_at_submit():
+    # sessions return the mass derivative (float64) but not the dressing derivatives
     s = frg.frg_session_open_fake(_cfg(), 1.0, 1.0)
     r = Req()
     Z = np.ones(16)
     r.batch.Z = frg.frg_log_table(Z.ctypes.data, 16, 1e-3, 1e3)
     sink = np.zeros(r.batch.n_ext * 16)
-    for field in ("dout_dm2", "dout_dz"):
-        b = frg.frg_batch.from_buffer_copy(r.batch)
-        setattr(b, field, sink.ctypes.data)
-        with pytest.raises(frg.FrgError) as ei:
-            frg.frg_session_submit(s, r.desc, b, -1)
-        assert ei.value.status == frg.FRG_E_UNSUPPORTED, field
+    b = frg.frg_batch.from_buffer_copy(r.batch)
+    b.dout_dz = sink.ctypes.data
+    with pytest.raises(frg.FrgError) as ei:
+        frg.frg_session_submit(s, r.desc, b, -1)
+    assert ei.value.status == frg.FRG_E_UNSUPPORTED
+    # dI/dm2 of the float32 form does not exist
+    err = np.zeros(r.batch.n_ext)
+    b = frg.frg_batch.from_buffer_copy(r.batch)
+    b.dout_dm2 = sink.ctypes.data
+    b.err_out = err.ctypes.data
+    d32 = frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 16, 10.0, n_x=8, precision=1,
+                        near_pole_tau=0.1)
+    with pytest.raises(frg.FrgError) as ei:
+        frg.frg_session_submit(s, d32, b, -1)
+    assert ei.value.status == frg.FRG_E_UNSUPPORTED
+    # float64 with dI/dm2: admitted and completed
+    b = frg.frg_batch.from_buffer_copy(r.batch)
+    b.dout_dm2 = sink.ctypes.data
+    t = frg.frg_session_submit(s, r.desc, b, -1)
+    assert frg.frg_session_wait(s, t, 10000) == frg.FRG_OK
+    frg.frg_session_close(s)
+
+
+def test_mass_derivative_counts_in_the_footprint():
+    # the derivative's output array takes device bytes like the values': with launch tables of
+    # T <= 32 KiB, a budget of footprint + 32 KiB holds the request without it (it needs
+    # footprint + T) but not with it (footprint + 32 KiB + T)
+    r = Req(n_ext=4096, n_q=16, n_x=8)
+    sink = np.zeros(4096)
+    with_d = frg.frg_batch.from_buffer_copy(r.batch)
+    with_d.dout_dm2 = sink.ctypes.data
+    base = r.footprint()
+    extra = 4096 * 8
+    s = frg.frg_session_open_fake(_cfg(budget=base + extra + 32768, inflight=2), 1.0, 1.0)
+    t = frg.frg_session_submit(s, r.desc, with_d, -1)
+    assert frg.frg_session_wait(s, t, 10000) == frg.FRG_OK
+    frg.frg_session_close(s)
+    s = frg.frg_session_open_fake(_cfg(budget=base + 32768, inflight=2), 1.0, 1.0)
+    with pytest.raises(frg.FrgError) as ei:
+        frg.frg_session_submit(s, r.desc, with_d, -1)
+    assert ei.value.status == frg.FRG_E_NOMEM
+    t = frg.frg_session_submit(s, r.desc, r.batch, -1)
+    assert frg.frg_session_wait(s, t, 10000) == frg.FRG_OK
     frg.frg_session_close(s)
 
 
