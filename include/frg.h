@@ -338,12 +338,17 @@ frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
  * difference of the fifth- and fourth-order solutions; a step with err <= 1 is accepted; the
  * next step is h min(fac_max, max(0.2, 0.9 err^(-1/5))), fac_max = 5 (1 right after a
  * rejection), clipped to [h_min, h_max] and to the end of the interval.  fixed_step = 1 takes
- * steps of h0 (the last one shortened to end at t_end) without control.
+ * steps of h0 (the last one shortened to end at t_end) without control.  method = 2 is the
+ * Runge-Kutta-Fehlberg 7(8) pair instead (the RK78 class of the same section; E. Fehlberg,
+ * NASA TR R-287, 1968): 13 right-hand sides per attempted step (a rejected step keeps its
+ * first), the eighth-order solution kept, e = the difference of the eighth- and seventh-order
+ * solutions (41/840 h (k_1 + k_11 - k_12 - k_13) up to sign), the same norm and rule with
+ * exponent -1/8.
  *
- * Everything per step runs on `stream` on the device -- seven stage vectors, six right-hand
- * sides, the stage combinations and the error norm -- except the accept/reject decision, for
- * which the host reads one float64 per step.  The state (flow_state.state) is updated in place
- * on the device; the stepper owns its stage buffers (allocated at creation).
+ * Everything per step runs on `stream` on the device -- the stage vectors (seven; Fehlberg 13),
+ * their right-hand sides, the stage combinations and the error norm -- except the accept/reject
+ * decision, for which the host reads one float64 per step.  The state (flow_state.state) is
+ * updated in place on the device; the stepper owns its stage buffers (allocated at creation).
  */
 typedef struct {
     double rtol, atol;        /* > 0 */
@@ -351,7 +356,8 @@ typedef struct {
     double h_min, h_max;      /* 0 < h_min <= h_max */
     int max_steps;            /* attempted steps per frg_stepper_advance call, >= 1 */
     int fixed_step;           /* 1: steps of exactly h0, no error control */
-    int method;               /* 0: Dormand-Prince 5(4) as above; 1: Adams-Bashforth-Moulton 4
+    int method;               /* 0: Dormand-Prince 5(4) as above; 2: Fehlberg 7(8) as above;
+                                 1: Adams-Bashforth-Moulton 4
                                  in PECE mode (predict with AB4, evaluate, correct with AM4,
                                  evaluate; Sec. 5.2 names the ABM class) with steps of exactly
                                  h0 and no error control (fixed_step, rtol and atol are not

@@ -1,7 +1,8 @@
 // Adaptive explicit stepper for flows dstate/dt = RHS(state; k(t)) in RG time t = log(Lambda/k),
 // k(t) = Lambda exp(-t) (Sec. 2.1): the embedded Runge-Kutta pair of Dormand and Prince,
-// order 5(4), with first-same-as-last stages (the RK45 class of explicit steppers named in
-// Sec. 5.2, "Time-stepping").  The stages, right-hand sides and the error norm run on the
+// order 5(4), with first-same-as-last stages, and the Runge-Kutta-Fehlberg 7(8) pair (the RK45
+// and RK78 classes of explicit steppers named in Sec. 5.2, "Time-stepping"), and the fixed-step
+// Adams-Bashforth-Moulton 4.  The stages, right-hand sides and the error norm run on the
 // device; the host reads one float64 per step to accept or reject it.
 #include <hip/hip_runtime.h>
 
@@ -31,10 +32,42 @@ constexpr double kA[7][6] = {
 constexpr double kE[7] = {71.0 / 57600.0,      0.0,           -71.0 / 16695.0, 71.0 / 1920.0,
                           -17253.0 / 339200.0, 22.0 / 525.0, -1.0 / 40.0};
 
-// A linear combination sum_j c_j K_j of up to seven stage vectors.
+// E. Fehlberg (1968), the 13-stage Runge-Kutta 7(8) formulas: nodes, stage coefficients, the
+// eighth-order weights (the solution kept) and e_j = b8_j - b7_j, nonzero on stages 1, 11, 12
+// and 13 (the error estimate 41/840 h (k_1 + k_11 - k_12 - k_13), up to sign).
+constexpr double kC78[13] = {0.0,       2.0 / 27.0, 1.0 / 9.0, 1.0 / 6.0, 5.0 / 12.0,
+                             1.0 / 2.0, 5.0 / 6.0,  1.0 / 6.0, 2.0 / 3.0, 1.0 / 3.0,
+                             1.0,       0.0,        1.0};
+constexpr double kA78[13][12] = {
+    {},
+    {2.0 / 27.0},
+    {1.0 / 36.0, 1.0 / 12.0},
+    {1.0 / 24.0, 0.0, 1.0 / 8.0},
+    {5.0 / 12.0, 0.0, -25.0 / 16.0, 25.0 / 16.0},
+    {1.0 / 20.0, 0.0, 0.0, 1.0 / 4.0, 1.0 / 5.0},
+    {-25.0 / 108.0, 0.0, 0.0, 125.0 / 108.0, -65.0 / 27.0, 125.0 / 54.0},
+    {31.0 / 300.0, 0.0, 0.0, 0.0, 61.0 / 225.0, -2.0 / 9.0, 13.0 / 900.0},
+    {2.0, 0.0, 0.0, -53.0 / 6.0, 704.0 / 45.0, -107.0 / 9.0, 67.0 / 90.0, 3.0},
+    {-91.0 / 108.0, 0.0, 0.0, 23.0 / 108.0, -976.0 / 135.0, 311.0 / 54.0, -19.0 / 60.0,
+     17.0 / 6.0, -1.0 / 12.0},
+    {2383.0 / 4100.0, 0.0, 0.0, -341.0 / 164.0, 4496.0 / 1025.0, -301.0 / 82.0,
+     2133.0 / 4100.0, 45.0 / 82.0, 45.0 / 164.0, 18.0 / 41.0},
+    {3.0 / 205.0, 0.0, 0.0, 0.0, 0.0, -6.0 / 41.0, -3.0 / 205.0, -3.0 / 41.0, 3.0 / 41.0,
+     6.0 / 41.0},
+    {-1777.0 / 4100.0, 0.0, 0.0, -341.0 / 164.0, 4496.0 / 1025.0, -289.0 / 82.0,
+     2193.0 / 4100.0, 51.0 / 82.0, 33.0 / 164.0, 12.0 / 41.0, 0.0, 1.0}};
+constexpr double kB78[13] = {0.0,         0.0,          0.0,          0.0,         0.0,
+                             34.0 / 105.0, 9.0 / 35.0,  9.0 / 35.0,   9.0 / 280.0, 9.0 / 280.0,
+                             0.0,         41.0 / 840.0, 41.0 / 840.0};
+constexpr double kE78[13] = {-41.0 / 840.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0,
+                             -41.0 / 840.0, 41.0 / 840.0, 41.0 / 840.0};
+
+constexpr int kMaxStages = 13;
+
+// A linear combination sum_j c_j K_j of up to 13 stage vectors.
 struct Combo {
-    const double *K[7];
-    double c[7];
+    const double *K[kMaxStages];
+    double c[kMaxStages];
     int nk;
 };
 
@@ -87,20 +120,20 @@ struct frg_stepper {
     TileShape shape;
     bool lpa = false;
     int n = 0;
-    DeviceBuffer stages;    // K_0..K_6, the stage input and the new solution: 9 n doubles
+    DeviceBuffer stages;    // K_0..K_12, the stage input and the new solution: 15 n doubles
     DeviceBuffer contrib;   // radially chunked right-hand sides
     DeviceBuffer counters;  // float32 amplification slots (zero at rest)
     DeviceBuffer ftrule;    // finite temperature: the frequency rule at the stage's k
     DeviceBuffer err_dev;
     double *err_host = nullptr;
-    double *K[7] = {};
+    double *K[kMaxStages] = {};
     double *ytmp = nullptr, *ynew = nullptr;
     // Adams-Bashforth-Moulton: f_n, f_{n-1}, f_{n-2}, f_{n-3} (in K[0..3], rotated) and how many
     // of them are valid
     double *F[4] = {};
     int hist = 0;
     double t = 0.0, h = 0.0, last_err = 0.0;
-    bool fsal = false;     // K[0] holds RHS(t, state)
+    bool fsal = false;     // K[0] holds RHS(t, state) (after a rejected step too)
     bool rejected_last = false;
     uint64_t accepted = 0, rejected = 0, evals = 0;
     ~frg_stepper() {
@@ -254,9 +287,9 @@ frg_status frg_stepper_create(frg_context *ctx, const frg_integral_desc *desc,
     if (!(c.rtol > 0.0) || !(c.atol > 0.0) || !(c.h0 > 0.0) || !(c.h_min > 0.0) ||
         !(c.h_max >= c.h_min) || !std::isfinite(c.h_max) || !std::isfinite(c.rtol) ||
         !std::isfinite(c.atol) || !std::isfinite(c.h0) || c.max_steps < 1 ||
-        (c.fixed_step != 0 && c.fixed_step != 1) || (c.method != 0 && c.method != 1)) {
+        (c.fixed_step != 0 && c.fixed_step != 1) || c.method < 0 || c.method > 2) {
         set_error("stepper config needs rtol, atol, h0 > 0, 0 < h_min <= h_max (finite), "
-                  "max_steps >= 1, fixed_step 0 or 1, method 0 or 1");
+                  "max_steps >= 1, fixed_step 0 or 1, method 0, 1 or 2");
         return FRG_E_INVAL;
     }
     if (state->family != desc->family) {
@@ -305,12 +338,12 @@ frg_status frg_stepper_create(frg_context *ctx, const frg_integral_desc *desc,
     if ((st = make_request(ctx, *desc, b, S->shape, lpa ? 1 : 2, state->m2_floor, state->coef,
                            &r)) != FRG_OK)
         return st;
-    FRG_HIP_CHECK(S->stages.alloc((size_t)9 * n * sizeof(double)));
+    FRG_HIP_CHECK(S->stages.alloc((size_t)(kMaxStages + 2) * n * sizeof(double)));
     double *base = (double *)S->stages.ptr;
-    for (int j = 0; j < 7; ++j) S->K[j] = base + (size_t)j * n;
+    for (int j = 0; j < kMaxStages; ++j) S->K[j] = base + (size_t)j * n;
     for (int j = 0; j < 4; ++j) S->F[j] = S->K[j];
-    S->ytmp = base + (size_t)7 * n;
-    S->ynew = base + (size_t)8 * n;
+    S->ytmp = base + (size_t)kMaxStages * n;
+    S->ynew = base + (size_t)(kMaxStages + 1) * n;
     FRG_HIP_CHECK(S->contrib.alloc(std::max<size_t>(contrib_doubles(r), 1) * sizeof(double)));
     const size_t nc = std::max<size_t>(counter_count(r), 1);
     FRG_HIP_CHECK(S->counters.alloc(nc * sizeof(unsigned)));
@@ -348,7 +381,13 @@ frg_status frg_stepper_advance(frg_stepper *S, double t_end, hipStream_t s,
         FRG_HIP_CHECK(hipSetDevice(S->ctx->device));
     }
     if (c.method == 1) res = abm_advance(S, t_end, s, &attempts);
-    while (c.method == 0 && S->t < t_end) {
+    // the embedded pairs: Dormand-Prince 5(4) (first same as last) or Fehlberg 7(8)
+    const bool f78 = c.method == 2;
+    const int ns = f78 ? 13 : 7;
+    const double *cn = f78 ? kC78 : kC;
+    const double *er = f78 ? kE78 : kE;
+    const double expo = f78 ? -0.125 : -0.2;  // -1/(lower order + 1)
+    while (c.method != 1 && S->t < t_end) {
         if (attempts >= c.max_steps) {
             set_error("max_steps (%d) attempted before t_end", c.max_steps);
             res = FRG_E_TIMEOUT;
@@ -365,22 +404,27 @@ frg_status frg_stepper_advance(frg_stepper *S, double t_end, hipStream_t s,
                 if ((st = stepper_rhs(S, S->t, y, S->K[0], s)) != FRG_OK) return st;
                 S->fsal = true;
             }
-            for (int st_i = 1; st_i < 7; ++st_i) {
-                double *in = st_i < 6 ? S->ytmp : S->ynew;
-                FRG_HIP_CHECK(combine(n, y, h, (const double *const *)S->K, kA[st_i], st_i, in, s));
-                if ((st = stepper_rhs(S, S->t + kC[st_i] * h, in, S->K[st_i], s)) != FRG_OK)
+            for (int st_i = 1; st_i < ns; ++st_i) {
+                // Dormand-Prince: the last stage's input is the new solution
+                double *in = (!f78 && st_i == 6) ? S->ynew : S->ytmp;
+                const double *a = f78 ? kA78[st_i] : kA[st_i];
+                FRG_HIP_CHECK(combine(n, y, h, (const double *const *)S->K, a, st_i, in, s));
+                if ((st = stepper_rhs(S, S->t + cn[st_i] * h, in, S->K[st_i], s)) != FRG_OK)
                     return st;
             }
+            if (f78)
+                FRG_HIP_CHECK(combine(n, y, h, (const double *const *)S->K, kB78, 13, S->ynew, s));
         }
         double err = 0.0;
         if (!c.fixed_step) {
             Combo e;
             std::memset(&e, 0, sizeof e);
-            for (int j = 0; j < 7; ++j) {
-                e.K[j] = S->K[j];
-                e.c[j] = kE[j];
+            for (int j = 0; j < ns; ++j) {
+                if (er[j] == 0.0) continue;
+                e.K[e.nk] = S->K[j];
+                e.c[e.nk] = er[j];
+                ++e.nk;
             }
-            e.nk = 7;
             hipLaunchKernelGGL(rk_error_kernel, dim3(1), dim3(256), 0, s, n, y, S->ynew, h, e,
                                c.rtol, c.atol, (double *)S->err_dev.ptr);
             FRG_HIP_CHECK(hipGetLastError());
@@ -397,11 +441,14 @@ frg_status frg_stepper_advance(frg_stepper *S, double t_end, hipStream_t s,
         if (c.fixed_step || err <= 1.0) {
             FRG_HIP_CHECK(hipMemcpyAsync(y, S->ynew, (size_t)n * sizeof(double),
                                          hipMemcpyDeviceToDevice, s));
-            std::swap(S->K[0], S->K[6]);  // the last stage is RHS(t + h, ynew)
+            if (f78)
+                S->fsal = false;  // no stage sits at the new solution
+            else
+                std::swap(S->K[0], S->K[6]);  // the last stage is RHS(t + h, ynew)
             S->t = last ? t_end : S->t + h;
             ++S->accepted;
             if (c.fixed_step) continue;
-            const double fac = err > 0.0 ? 0.9 * std::pow(err, -0.2) : 5.0;
+            const double fac = err > 0.0 ? 0.9 * std::pow(err, expo) : 5.0;
             const double fac_max = S->rejected_last ? 1.0 : 5.0;
             S->h = std::min(std::max(h * std::min(fac_max, std::max(0.2, fac)), c.h_min), c.h_max);
             S->rejected_last = false;
@@ -414,7 +461,7 @@ frg_status frg_stepper_advance(frg_stepper *S, double t_end, hipStream_t s,
                 res = FRG_E_INVAL;
                 break;
             }
-            const double fac = 0.9 * std::pow(err, -0.2);
+            const double fac = 0.9 * std::pow(err, expo);
             S->h = std::min(std::max(h * std::min(1.0, std::max(0.2, fac)), c.h_min), c.h_max);
         }
     }
