@@ -357,6 +357,14 @@ typedef struct {
     int max_steps;            /* attempted steps per frg_stepper_advance call, >= 1 */
     int fixed_step;           /* 1: steps of exactly h0, no error control */
     int method;               /* 0: Dormand-Prince 5(4) as above; 2: Fehlberg 7(8) as above;
+                                 3: Adams-Bashforth-Moulton 4 PECE with a variable step:
+                                 Milne's estimate (19/270)(y_c - y_p) of the corrector's error
+                                 in the norm above, err <= 1 accepts, next step h min(fmax,
+                                 max(0.2, 0.9 err^(-1/5))) in [h_min, h_max] with fmax = 1.5 (1
+                                 after a rejection; increases below 10 % not taken); whenever
+                                 the step changes the right-hand-side history is moved onto the
+                                 new spacing by the cubic through its four points; the first
+                                 three steps are RK4 steps of h0; fixed_step not used;
                                  1: Adams-Bashforth-Moulton 4
                                  in PECE mode (predict with AB4, evaluate, correct with AM4,
                                  evaluate; Sec. 5.2 names the ABM class) with steps of exactly

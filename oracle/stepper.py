@@ -18,6 +18,11 @@ A step that would pass t_end ends exactly there.  fixed_step: steps of exactly h
 
 Abm4 (below) is the fixed-step Adams-Bashforth-Moulton 4 PECE stepper with an RK4 start.
 
+Abm4Var (below) is the same PECE pair with a variable step: Milne's estimate of the corrector's
+local error, (19/270)(y_c - y_p) (the AB4 and AM4 error constants 251/720 and -19/720), in the
+norm above; on a change of step the history is moved onto the new spacing by the cubic through
+its four points.
+
 Rkf78 (below) is the Runge-Kutta-Fehlberg 7(8) pair (the RK78 class the paper lists next to
 RK45, Sec. 5.2): E. Fehlberg, "Classical fifth-, sixth-, seventh-, and eighth-order Runge-Kutta
 formulas with stepsize control", NASA TR R-287 (1968), the 13-stage 7(8) formulas.  The
@@ -299,4 +304,119 @@ class Rkf78:
                     return "h_min"
                 fac = 0.9 * err ** -0.125
                 self.h = min(max(h * min(1.0, max(0.2, fac)), self.h_min), self.h_max)
+        return "ok"
+
+
+def respace(hist, ratio):
+    """History f_n, f_{n-1}, f_{n-2}, f_{n-3} (spacing h) moved to spacing ratio * h: the cubic
+    through the four points, p(s) at s = j ratio (s in units of h backwards from t_n), by
+    Lagrange's formula."""
+    out = [hist[0]]
+    for j in range(1, 4):
+        s = j * ratio
+        acc = 0.0
+        for i in range(4):
+            w = 1.0
+            for m in range(4):
+                if m != i:
+                    w *= (s - m) / (i - m)
+            acc = acc + w * hist[i]
+        out.append(acc)
+    return out
+
+
+class Abm4Var:
+    """Adams-Bashforth-Moulton 4 PECE with a variable step.
+
+    The first three steps are classical RK4 steps of h0 (no error estimate) that build the
+    history.  Then each step predicts with AB4, evaluates, corrects with AM4 and estimates the
+    corrector's local error by Milne's device, est = (19/270) (y_c - y_p); err is the RMS of
+    est / (atol + rtol max(|y|, |y_c|)).  err <= 1 accepts (then the right-hand side at the new
+    point joins the history), else the step is repeated smaller.  The next step is
+    h min(fmax, max(0.2, 0.9 err^(-1/5))) clipped to [h_min, h_max], fmax = 1.5 (1 right after
+    a rejection: growth moves the history by extrapolating its cubic, to at most 4.5 old steps
+    back); a change of less than 10 % upwards is not taken.  A step that would pass t_end
+    is shortened to end there.  Whenever the step changes, the history is moved onto the new
+    spacing (respace)."""
+
+    def __init__(self, f, y0, *, rtol, atol, h0, h_min, h_max, max_steps, t0=0.0):
+        self.f = f
+        self.y = np.array(y0, dtype=np.float64)
+        self.t = float(t0)
+        self.rtol, self.atol = rtol, atol
+        self.h0, self.h_min, self.h_max = h0, h_min, h_max
+        self.h = min(max(h0, h_min), h_max)  # the history's spacing once it is full
+        self.max_steps = max_steps
+        self.hist = []
+        self.accepted = 0
+        self.rejected = 0
+        self.evals = 0
+        self.last_err = 0.0
+        self.rejected_last = False
+
+    def _f(self, t, y):
+        self.evals += 1
+        return np.asarray(self.f(t, y), dtype=np.float64)
+
+    def advance(self, t_end):
+        """Advance to t_end; returns "ok", "max_steps" or "h_min"."""
+        attempts = 0
+        while self.t < t_end:
+            if attempts >= self.max_steps:
+                return "max_steps"
+            attempts += 1
+            if not self.hist:
+                self.hist = [self._f(self.t, self.y)]
+            h = self.h
+            last = self.t + h >= t_end * (1.0 - 1e-14) - 1e-300
+            if last:
+                h = t_end - self.t
+            if len(self.hist) < 4:
+                # start: RK4 steps (the last one may be shortened; the history is then
+                # restarted from the new point)
+                k1 = self.hist[0]
+                ks = [k1]
+                for c in (0.5, 0.5, 1.0):
+                    ks.append(self._f(self.t + c * h, self.y + c * h * ks[-1]))
+                self.y = self.y + h * (ks[0] + 2 * ks[1] + 2 * ks[2] + ks[3]) / 6.0
+                self.t = t_end if last else self.t + h
+                fn = self._f(self.t, self.y)
+                self.hist = [fn] if h != self.h else ([fn] + self.hist)[:4]
+                self.accepted += 1
+                continue
+            if h != self.h:
+                self.hist = respace(self.hist, h / self.h)
+            pred = self.y + h * sum(float(AB4[j]) * self.hist[j] for j in range(4))
+            fp = self._f(self.t + h, pred)
+            corr = self.y + h * (float(AM4[0]) * fp +
+                                 sum(float(AM4[j + 1]) * self.hist[j] for j in range(3)))
+            est = (19.0 / 270.0) * (corr - pred)
+            sc = self.atol + self.rtol * np.maximum(np.abs(self.y), np.abs(corr))
+            err = math.sqrt(float(np.mean((est / sc) ** 2)))
+            self.last_err = err
+            if err <= 1.0:
+                self.y = corr
+                self.t = t_end if last else self.t + h
+                self.hist = [self._f(self.t, self.y)] + self.hist[:3]
+                self.accepted += 1
+                fac = 0.9 * err ** -0.2 if err > 0 else 1.5
+                fmax = 1.0 if self.rejected_last else 1.5
+                fac = min(fmax, max(0.2, fac))
+                if 1.0 <= fac < 1.1:
+                    fac = 1.0
+                hn = min(max(h * fac, self.h_min), self.h_max)
+                self.h = h  # the history's spacing
+                if hn != h:
+                    self.hist = respace(self.hist, hn / h)
+                self.h = hn
+                self.rejected_last = False
+            else:
+                self.rejected += 1
+                self.rejected_last = True
+                if h <= self.h_min:
+                    return "h_min"
+                fac = min(1.0, max(0.2, 0.9 * err ** -0.2))
+                hn = min(max(h * fac, self.h_min), self.h_max)
+                self.hist = respace(self.hist, hn / h)
+                self.h = hn
         return "ok"

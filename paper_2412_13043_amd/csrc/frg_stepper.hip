@@ -72,6 +72,7 @@ struct Combo {
 };
 
 // out = y + h sum_j c_j K_j (the stage terms in order j = 0, 1, ...).
+// (y NULL: out = h sum_j c_j K_j.)
 __global__ void __launch_bounds__(256) rk_combine_kernel(int n, const double *__restrict__ y,
                                                          double h, Combo k,
                                                          double *__restrict__ out) {
@@ -79,7 +80,7 @@ __global__ void __launch_bounds__(256) rk_combine_kernel(int n, const double *__
     if (i >= n) return;
     double s = 0.0;
     for (int j = 0; j < k.nk; ++j) s = fma(k.c[j], k.K[j][i], s);
-    out[i] = fma(h, s, y[i]);
+    out[i] = y ? fma(h, s, y[i]) : h * s;
 }
 
 // One workgroup: err2 = sum_i (h sum_j e_j K_j[i] / (atol + rtol max(|y_i|, |yn_i|)))^2, each
@@ -132,7 +133,7 @@ struct frg_stepper {
     // of them are valid
     double *F[4] = {};
     int hist = 0;
-    double t = 0.0, h = 0.0, last_err = 0.0;
+    double t = 0.0, h = 0.0, last_err = 0.0;  // h: the next step (variable ABM: the history's)
     bool fsal = false;     // K[0] holds RHS(t, state) (after a rejected step too)
     bool rejected_last = false;
     uint64_t accepted = 0, rejected = 0, evals = 0;
@@ -271,6 +272,133 @@ frg_status abm_advance(frg_stepper *S, double t_end, hipStream_t s, int *attempt
     return FRG_OK;
 }
 
+// The history f_n, f_{n-1}, f_{n-2}, f_{n-3} (spacing h) moved to spacing ratio h: the cubic
+// through the four points at s = j ratio old steps back (Lagrange), into the spare stage
+// buffers, which then become the history.
+frg_status respace(frg_stepper *S, double ratio, hipStream_t s) {
+    double *spare[3] = {S->K[4], S->K[5], S->K[6]};
+    for (int j = 1; j < 4; ++j) {
+        const double x = j * ratio;
+        double w[4];
+        for (int i = 0; i < 4; ++i) {
+            w[i] = 1.0;
+            for (int m = 0; m < 4; ++m)
+                if (m != i) w[i] *= (x - m) / (double)(i - m);
+        }
+        FRG_HIP_CHECK(combine(S->n, nullptr, 1.0, (const double *const *)S->F, w, 4,
+                              spare[j - 1], s));
+    }
+    for (int j = 1; j < 4; ++j) {
+        double *old = S->F[j];
+        S->F[j] = spare[j - 1];
+        // the freed buffer takes the spare's place among K[4..6]
+        S->K[3 + j] = old;
+    }
+    return FRG_OK;
+}
+
+// Adams-Bashforth-Moulton 4 PECE with a variable step: Milne's estimate (19/270)(y_c - y_p) of
+// the corrector's local error in the norm of the Runge-Kutta pairs, err <= 1 accepts; next step
+// h min(fmax, max(0.2, 0.9 err^(-1/5))) in [h_min, h_max], fmax = 1.5 (1 after a rejection), no
+// increase below 10 %; the history re-spaced by its cubic whenever the step changes; RK4 steps
+// of h0 build the first history.
+frg_status abm_var_advance(frg_stepper *S, double t_end, hipStream_t s, int *attempts_out) {
+    const frg_stepper_config &c = S->cfg;
+    const int n = S->n;
+    double *y = const_cast<double *>(S->state.state);
+    int attempts = 0;
+    frg_status st;
+    const double milne[2] = {19.0 / 270.0, -19.0 / 270.0};
+    while (S->t < t_end) {
+        if (attempts >= c.max_steps) {
+            set_error("max_steps (%d) attempted before t_end", c.max_steps);
+            *attempts_out = attempts;
+            return FRG_E_TIMEOUT;
+        }
+        ++attempts;
+        double h = S->h;
+        const bool last = S->t + h >= t_end * (1.0 - 1e-14) - 1e-300;
+        if (last) h = t_end - S->t;
+        std::unique_lock<std::mutex> lk(S->ctx->mu);
+        if (S->hist == 0) {
+            if ((st = stepper_rhs(S, S->t, y, S->F[0], s)) != FRG_OK) return st;
+            S->hist = 1;
+        }
+        if (S->hist < 4) {
+            // start: RK4 (a shortened last one restarts the history from its end point)
+            if ((st = rk4_step(S, h, y, s)) != FRG_OK) return st;
+            FRG_HIP_CHECK(hipMemcpyAsync(y, S->ynew, (size_t)n * sizeof(double),
+                                         hipMemcpyDeviceToDevice, s));
+            S->t = last ? t_end : S->t + h;
+            const bool keep = h == S->h;
+            double *oldest = S->F[3];
+            for (int j = 3; j > 0; --j) S->F[j] = S->F[j - 1];
+            S->F[0] = oldest;
+            if ((st = stepper_rhs(S, S->t, y, S->F[0], s)) != FRG_OK) return st;
+            S->hist = keep ? std::min(S->hist + 1, 4) : 1;
+            ++S->accepted;
+            continue;
+        }
+        if (h != S->h && (st = respace(S, h / S->h, s)) != FRG_OK) return st;
+        FRG_HIP_CHECK(combine(n, y, h, (const double *const *)S->F, kAB4, 4, S->ytmp, s));
+        if ((st = stepper_rhs(S, S->t + h, S->ytmp, S->K[7], s)) != FRG_OK) return st;
+        const double *corr[4] = {S->K[7], S->F[0], S->F[1], S->F[2]};
+        FRG_HIP_CHECK(combine(n, y, h, corr, kAM4, 4, S->ynew, s));
+        Combo e;
+        std::memset(&e, 0, sizeof e);
+        e.K[0] = S->ynew;
+        e.K[1] = S->ytmp;
+        e.c[0] = milne[0];
+        e.c[1] = milne[1];
+        e.nk = 2;
+        hipLaunchKernelGGL(rk_error_kernel, dim3(1), dim3(256), 0, s, n, y, S->ynew, 1.0, e,
+                           c.rtol, c.atol, (double *)S->err_dev.ptr);
+        FRG_HIP_CHECK(hipGetLastError());
+        FRG_HIP_CHECK(hipMemcpyAsync(S->err_host, S->err_dev.ptr, sizeof(double),
+                                     hipMemcpyDeviceToHost, s));
+        FRG_HIP_CHECK(hipStreamSynchronize(s));
+        const double err = std::sqrt(*S->err_host / (double)n);
+        if (!std::isfinite(err)) {
+            set_error("error norm is not finite at t = %g (h = %g)", S->t, h);
+            return FRG_E_INVAL;
+        }
+        S->last_err = err;
+        if (err <= 1.0) {
+            FRG_HIP_CHECK(hipMemcpyAsync(y, S->ynew, (size_t)n * sizeof(double),
+                                         hipMemcpyDeviceToDevice, s));
+            S->t = last ? t_end : S->t + h;
+            double *oldest = S->F[3];
+            for (int j = 3; j > 0; --j) S->F[j] = S->F[j - 1];
+            S->F[0] = oldest;
+            if ((st = stepper_rhs(S, S->t, y, S->F[0], s)) != FRG_OK) return st;
+            ++S->accepted;
+            double fac = err > 0.0 ? 0.9 * std::pow(err, -0.2) : 1.5;
+            fac = std::min(S->rejected_last ? 1.0 : 1.5, std::max(0.2, fac));
+            if (fac >= 1.0 && fac < 1.1) fac = 1.0;
+            const double hn = std::min(std::max(h * fac, c.h_min), c.h_max);
+            S->h = h;  // the history's spacing
+            if (hn != h && (st = respace(S, hn / h, s)) != FRG_OK) return st;
+            S->h = hn;
+            S->rejected_last = false;
+        } else {
+            ++S->rejected;
+            S->rejected_last = true;
+            if (h <= c.h_min) {
+                set_error("step size at h_min = %g rejected at t = %g (err = %g)", c.h_min, S->t,
+                          err);
+                *attempts_out = attempts;
+                return FRG_E_INVAL;
+            }
+            const double fac = std::min(1.0, std::max(0.2, 0.9 * std::pow(err, -0.2)));
+            const double hn = std::min(std::max(h * fac, c.h_min), c.h_max);
+            if ((st = respace(S, hn / h, s)) != FRG_OK) return st;
+            S->h = hn;
+        }
+    }
+    *attempts_out = attempts;
+    return FRG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -287,9 +415,9 @@ frg_status frg_stepper_create(frg_context *ctx, const frg_integral_desc *desc,
     if (!(c.rtol > 0.0) || !(c.atol > 0.0) || !(c.h0 > 0.0) || !(c.h_min > 0.0) ||
         !(c.h_max >= c.h_min) || !std::isfinite(c.h_max) || !std::isfinite(c.rtol) ||
         !std::isfinite(c.atol) || !std::isfinite(c.h0) || c.max_steps < 1 ||
-        (c.fixed_step != 0 && c.fixed_step != 1) || c.method < 0 || c.method > 2) {
+        (c.fixed_step != 0 && c.fixed_step != 1) || c.method < 0 || c.method > 3) {
         set_error("stepper config needs rtol, atol, h0 > 0, 0 < h_min <= h_max (finite), "
-                  "max_steps >= 1, fixed_step 0 or 1, method 0, 1 or 2");
+                  "max_steps >= 1, fixed_step 0 or 1, method 0 to 3");
         return FRG_E_INVAL;
     }
     if (state->family != desc->family) {
@@ -381,13 +509,14 @@ frg_status frg_stepper_advance(frg_stepper *S, double t_end, hipStream_t s,
         FRG_HIP_CHECK(hipSetDevice(S->ctx->device));
     }
     if (c.method == 1) res = abm_advance(S, t_end, s, &attempts);
+    if (c.method == 3) res = abm_var_advance(S, t_end, s, &attempts);
     // the embedded pairs: Dormand-Prince 5(4) (first same as last) or Fehlberg 7(8)
     const bool f78 = c.method == 2;
     const int ns = f78 ? 13 : 7;
     const double *cn = f78 ? kC78 : kC;
     const double *er = f78 ? kE78 : kE;
     const double expo = f78 ? -0.125 : -0.2;  // -1/(lower order + 1)
-    while (c.method != 1 && S->t < t_end) {
+    while ((c.method == 0 || c.method == 2) && S->t < t_end) {
         if (attempts >= c.max_steps) {
             set_error("max_steps (%d) attempted before t_end", c.max_steps);
             res = FRG_E_TIMEOUT;

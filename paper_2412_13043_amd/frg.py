@@ -473,8 +473,9 @@ class Context:
                 h_max=1.0, max_steps=100000, fixed_step=False, method=0):
         """A flow stepper evolving `state` (device tensor) in place: method 0 the adaptive
         Dormand-Prince 5(4) (or fixed steps), method 1 the fixed-step Adams-Bashforth-Moulton 4
-        PECE, method 2 the adaptive Runge-Kutta-Fehlberg 7(8) (or fixed steps).  state, grid and
-        Z must stay alive while the stepper is used."""
+        PECE, method 2 the adaptive Runge-Kutta-Fehlberg 7(8) (or fixed steps), method 3 the
+        variable-step Adams-Bashforth-Moulton 4 PECE.  state, grid and Z must stay alive while
+        the stepper is used."""
         return Stepper(self, desc, state, grid, Z=Z, x_min=x_min, x_max=x_max, n_comp=n_comp,
                        m2_floor=m2_floor, coef=coef, rtol=rtol, atol=atol, h0=h0, h_min=h_min,
                        h_max=h_max, max_steps=max_steps, fixed_step=fixed_step, method=method)

@@ -1,4 +1,4 @@
-"""GPU flow steppers (Dormand-Prince 5(4), Fehlberg 7(8), ABM4 on the device) against the
+"""GPU flow steppers (Dormand-Prince 5(4), Fehlberg 7(8), fixed- and variable-step ABM4) against the
 oracle's steppers driving the oracle's right-hand sides at k(t) = Lambda exp(-t).
 
 Both sides run the same algorithm; their right-hand sides differ by rounding only (1e-15
@@ -166,8 +166,53 @@ def test_abm4_stepper_matches_oracle(env):
     assert np.max(np.abs(state.cpu().numpy() - ref.y) / np.abs(ref.y)) <= 1e-11
     st.close()
     with pytest.raises(frg.FrgError) as ei:
-        ctx.stepper(desc, _d(torch, u0), grid, h0=0.05, method=3)
+        ctx.stepper(desc, _d(torch, u0), grid, h0=0.05, method=4)
     assert ei.value.status == frg.FRG_E_INVAL
+
+
+def test_variable_abm4_stepper_matches_oracle(env):
+    # variable-step ABM4: RK4 start, Milne's estimate, re-spaced history; the same accepted and
+    # rejected steps and right-hand sides as the oracle's on the LPA flow (two calls, the
+    # second ending with a shortened step) and on a two-point vertex flow
+    frg, ctx, torch = env
+    rho = wl.lpa_rho_grid()
+    u0 = 0.3 + rho
+    desc = frg.make_desc(frg.FRG_FAMILY_LPA, wl.LPA_NQ, wl.LPA_QMAX, k=1.0)
+    state, grid = _d(torch, u0), _d(torch, rho)
+    cfg = dict(rtol=1e-8, atol=1e-10, h0=0.01, h_min=1e-8, h_max=0.5, max_steps=10000)
+    st = ctx.stepper(desc, state, grid, n_comp=4, m2_floor=-0.9, method=3, **cfg)
+    ref = rk.Abm4Var(_lpa_rhs(rho, wl.LPA_NQ, wl.LPA_QMAX, 1.0, 4, -0.9), u0, **cfg)
+    for t_end in (0.5, 2.0):
+        rc, stats = st.advance(t_end)
+        assert ref.advance(t_end) == "ok"
+        assert stats.t == t_end
+        assert (stats.accepted, stats.rejected, stats.rhs_evals) == (ref.accepted,
+                                                                     ref.rejected, ref.evals)
+        assert _close(state.cpu().numpy(), ref.y, 1e-10), t_end
+    assert ref.h > 0.01  # the step grew
+    st.close()
+    rng = np.random.default_rng(41)
+    p = 10 ** rng.uniform(-2, 1, 40)
+    Z = wl.dressing_table(10)
+    m0 = rng.uniform(0.2, 1.5, 40)
+    d2 = frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 16, 10.0, n_x=8, k=2.0)
+    state, tp, tZ = _d(torch, m0), _d(torch, p), _d(torch, Z)
+    cfg = dict(rtol=1e-9, atol=1e-11, h0=0.02, h_min=1e-8, h_max=0.5, max_steps=1000)
+    st = ctx.stepper(d2, state, tp, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, m2_floor=-0.5,
+                     coef=-3.0, method=3, **cfg)
+
+    def f(t, m):
+        k = 2.0 * math.exp(-t)
+        return -3.0 * oracle.integrate(2, 16, 10.0, n_x=8, k=k, ext=p,
+                                       m2=np.maximum(m, -0.5 * (k / 2.0) ** 2), Z=Z)
+
+    ref = rk.Abm4Var(f, m0, **cfg)
+    rc, stats = st.advance(1.0)
+    assert ref.advance(1.0) == "ok"
+    assert (stats.accepted, stats.rejected, stats.rhs_evals) == (ref.accepted, ref.rejected,
+                                                                 ref.evals)
+    assert np.max(np.abs(state.cpu().numpy() - ref.y) / np.abs(ref.y)) <= 1e-10
+    st.close()
 
 
 @pytest.mark.parametrize("fixed", [False, True])

@@ -160,3 +160,43 @@ def test_abm4_evaluation_count():
     st = rk.Abm4(lambda t, y: -y, [1.0], h0=0.1, max_steps=100)
     st.advance(1.0)
     assert st.accepted == 10 and st.evals == 1 + 3 * 4 + 7 * 2
+
+
+def test_respace_is_exact_for_cubic_histories():
+    # the history of f(t) = cubic at spacing h, moved to 0.37 h and 1.5 h, equals the cubic at
+    # the new points
+    cub = lambda t: 2.0 - 3.0 * t + 0.5 * t ** 2 + 0.25 * t ** 3
+    h, tn = 0.3, 1.7
+    hist = [np.array([cub(tn - j * h)]) for j in range(4)]
+    for ratio in (0.37, 1.0, 1.5):
+        got = rk.respace(hist, ratio)
+        want = [cub(tn - j * ratio * h) for j in range(4)]
+        assert np.allclose([g[0] for g in got], want, rtol=0, atol=1e-13), ratio
+
+
+@pytest.mark.parametrize("rtol", [1e-6, 1e-10])
+def test_variable_abm4_reaches_closed_forms(rtol):
+    # a solution whose time scale grows: the step grows with it, accepted steps have err <= 1
+    st = rk.Abm4Var(lambda t, y: np.array([-y[0], y[0] - 2 * y[1]]), [1.0, 0.0], rtol=rtol,
+                    atol=rtol * 1e-2, h0=0.01, h_min=1e-12, h_max=1.0, max_steps=10 ** 5)
+    assert st.advance(6.0) == "ok"
+    exact = np.array([math.exp(-6), math.exp(-6) - math.exp(-12)])
+    assert np.max(np.abs(st.y - exact)) <= 50 * rtol
+    assert st.t == 6.0 and st.last_err <= 1.0
+    assert st.h > 0.01  # it grew from h0
+
+
+def test_variable_abm4_rejects_and_shrinks():
+    # y' = -30 (y - cos t): a first multistep step of 0.1 is far outside the tolerance
+    f = lambda t, y: -30.0 * (y - math.cos(t))
+    st = rk.Abm4Var(f, [1.0], rtol=1e-8, atol=1e-10, h0=0.02, h_min=1e-10, h_max=0.5,
+                    max_steps=10 ** 5)
+    assert st.advance(2.0) == "ok"
+    assert st.rejected >= 1
+    # exact: y = (900 cos t + 30 sin t)/901 + (1 - 900/901) e^{-30 t}
+    exact = (900 * math.cos(2.0) + 30 * math.sin(2.0)) / 901 + (1 / 901) * math.exp(-60.0)
+    assert abs(st.y[0] - exact) <= 1e-6
+    # evaluation count: f at the start point, then 4 per RK4 start step (three stages and the
+    # new point), 2 per accepted multistep step (predicted and new point), 1 per rejection
+    starts = 3
+    assert st.evals == 1 + 4 * starts + 2 * (st.accepted - starts) + st.rejected
