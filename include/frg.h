@@ -146,8 +146,8 @@ typedef struct {
     int n_tail;            /* GL nodes per side for the omitted frequencies; 0 = none */
     int freq_scaled;       /* 0: Lambda = freq_max ("q0"); 1: Lambda = freq_max * k ("x0") */
     /* every family */
-    int regulator;         /* frg_regulator (0, the exponential one, when zeroed); the float32
-                              form supports FRG_REG_EXPONENTIAL only (FRG_E_UNSUPPORTED) */
+    int regulator;         /* frg_regulator (0, the exponential one, when zeroed); every
+                              regulator in both precisions */
     int reg_order;         /* N of FRG_REG_POLY_EXP, 1..16; 0 = 8 */
     int reserved;          /* zero */
 } frg_integral_desc;
@@ -182,9 +182,9 @@ typedef struct {
                               (two-point 1, three-point 2), (6 + 2 nG) u + nG (eE + er) +
                               nG kappa K, where eE, er are the measured errors of the float32
                               exponential and reciprocal and K the per-kappa error of one
-                              propagator, set by the dressing table's largest relative step
-                              and its smallest entry (assumed positive); LPA (7 + 10 kappa) u
-                              + 2 er */
+                              propagator, set by the regulator, the dressing table's largest
+                              relative step and its smallest entry (assumed positive); LPA
+                              (7 + 10 kappa) u + 2 er */
     double *dout_dm2;      /* device [n_ext] or NULL: dI_e/dm2_e, the derivative of each result in
                               its point's mass, evaluated in the same pass by forward-mode
                               differentiation through every propagator (dG/dm2 = -G^2; the

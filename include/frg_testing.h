@@ -79,13 +79,14 @@ frg_status frg_flop_probe(int seq, int blocks, int iters, double *out, hipStream
 /* Largest error, over every float32 input of its range, of one elementary operation of the
  * float32 precision form, into *max_err (host): which = 0: absolute error of the hardware log2
  * (v_log_f32) on [1/2, 1); 1: relative error of the float32 expm1(-y) on normal y <= 2^21;
- * 2: relative error of the hardware reciprocal (v_rcp_f32) on [2^-100, 2^100).  References: the
- * float64 log2 and expm1 of the HIP math library.  Synchronises `stream`. */
+ * 2: relative error of the hardware reciprocal (v_rcp_f32) on [2^-100, 2^100); 3: relative
+ * error of the hardware 2^x (v_exp_f32) on [-126, 0).  References: the float64 log2, expm1 and
+ * exp2 of the HIP math library.  Synchronises `stream`. */
 frg_status frg_math_probe(int which, double *max_err, hipStream_t stream);
 
-/* The constants the float32 form's error bound uses: out[0] = u = 2^-24, out[1..3] = the bounds
- * on the three errors frg_math_probe measures (same order). */
-void frg_fp32_error_constants(double out[4]);
+/* The constants the float32 form's error bound uses: out[0] = u = 2^-24, out[1..4] = the bounds
+ * on the four errors frg_math_probe measures (same order). */
+void frg_fp32_error_constants(double out[5]);
 
 #ifdef __cplusplus
 }

@@ -41,8 +41,9 @@ __global__ void __launch_bounds__(64) flop_probe_kernel(double *out, int iters,
 //  0: |v_log_f32(m) - log2(m)| (absolute) for m in [1/2, 1)  (2^23 inputs);
 //  1: |fm::expm1_neg_f(y) - expm1(-y)| / |expm1(-y)| for normal y in [2^-126, 2^21] (above that the
 //     argument is clamped and the result is -1, off by e^-y);
-//  2: |v_rcp_f32(d) d - 1| for d in [2^-100, 2^100).
-// The references are the float64 log2 and expm1 of the HIP math library.
+//  2: |v_rcp_f32(d) d - 1| for d in [2^-100, 2^100);
+//  3: |v_exp_f32(x) - 2^x| / 2^x for x in [-126, 0) (normal results).
+// The references are the float64 log2, expm1 and exp2 of the HIP math library.
 __global__ void __launch_bounds__(256) math_probe_kernel(int which, unsigned long long lo,
                                                          unsigned long long hi,
                                                          unsigned long long *maxbits) {
@@ -56,8 +57,11 @@ __global__ void __launch_bounds__(256) math_probe_kernel(int which, unsigned lon
         } else if (which == 1) {
             const double E = expm1(-(double)x);
             err = fabs((double)fm::expm1_neg_f(x) - E) / fabs(E);
-        } else {
+        } else if (which == 2) {
             err = fabs((double)__builtin_amdgcn_rcpf(x) * (double)x - 1.0);
+        } else {
+            const double e = exp2((double)x);
+            err = fabs((double)__builtin_amdgcn_exp2f(x) - e) / e;
         }
         worst = fmax(worst, err);
     }
@@ -71,10 +75,10 @@ __global__ void __launch_bounds__(256) math_probe_kernel(int which, unsigned lon
 using namespace frg;
 
 extern "C" frg_status frg_math_probe(int which, double *max_err, hipStream_t stream) {
-    if (which < 0 || which > 2 || !max_err) return FRG_E_INVAL;
-    // input ranges as float32 bit patterns [lo, hi)
-    const unsigned long long lo[3] = {0x3F000000ull, 0x00800000ull, 0x0D800000ull};
-    const unsigned long long hi[3] = {0x3F800000ull, 0x4A000001ull, 0x71800000ull};
+    if (which < 0 || which > 3 || !max_err) return FRG_E_INVAL;
+    // input ranges as float32 bit patterns [lo, hi) (which 3: -0 excluded up to -126 included)
+    const unsigned long long lo[4] = {0x3F000000ull, 0x00800000ull, 0x0D800000ull, 0x80000001ull};
+    const unsigned long long hi[4] = {0x3F800000ull, 0x4A000001ull, 0x71800000ull, 0xC2FC0001ull};
     unsigned long long *d = nullptr;
     if (hipMalloc(&d, sizeof(unsigned long long)) != hipSuccess) return FRG_E_DEVICE;
     hipError_t e = hipMemsetAsync(d, 0, sizeof(unsigned long long), stream);
@@ -93,11 +97,12 @@ extern "C" frg_status frg_math_probe(int which, double *max_err, hipStream_t str
     return FRG_OK;
 }
 
-extern "C" void frg_fp32_error_constants(double out[4]) {
+extern "C" void frg_fp32_error_constants(double out[5]) {
     out[0] = kU32;
     out[1] = kErrLog2f;
     out[2] = kErrExpm1f;
     out[3] = kErrRcpf;
+    out[4] = kErrExp2f;
 }
 
 extern "C" frg_status frg_flop_probe(int seq, int blocks, int iters, double *out,

@@ -117,12 +117,14 @@ int multi_grid(int n_tiles, int fam, int prec, int reg, int der, int lds_bytes, 
 constexpr int kLogTable = 256;
 
 // Float32 form's error constants (relative unless stated): u = 2^-24; the largest absolute error
-// of v_log_f32 (log2) on [1/2, 1), the largest relative error of fm::expm1_neg_f on y >= 0 and
-// of v_rcp_f32 on normal arguments, each rounded up from an exhaustive measurement over every
-// float32 input of its range (frg_math_probe on gfx950: 0.9973 u, 1.4798 u, 1.5348 u).
+// of v_log_f32 (log2) on [1/2, 1), the largest relative errors of fm::expm1_neg_f on y >= 0, of
+// v_rcp_f32 on normal arguments and of v_exp_f32 (2^x) on [-126, 0), each rounded up from an
+// exhaustive measurement over every float32 input of its range (frg_math_probe on gfx950:
+// 0.9973 u, 1.4798 u, 1.5348 u, 1.4234 u).
 constexpr double kU32 = 5.9604644775390625e-8;
 constexpr double kErrLog2f = 1.0 * kU32;
 constexpr double kErrExpm1f = 1.5 * kU32;
 constexpr double kErrRcpf = 1.6 * kU32;
+constexpr double kErrExp2f = 1.5 * kU32;
 
 }  // namespace frg

@@ -342,6 +342,24 @@ __device__ __forceinline__ double poly_s(double y, int n) {
     return acc * y;
 }
 
+// S_N(y) in float32 (the float32 form): the same Horner chain with the coefficients 1/i rounded
+// to float32; y >= 0, so every term is positive and the result carries at most (2N + 1) u.
+__device__ __forceinline__ float poly_s_f(float y, int n) {
+    if (n == 8) {
+        float acc = fmaf(0.125f, y, 1.0f / 7.0f);
+        acc = fmaf(acc, y, 1.0f / 6.0f);
+        acc = fmaf(acc, y, 0.2f);
+        acc = fmaf(acc, y, 0.25f);
+        acc = fmaf(acc, y, 1.0f / 3.0f);
+        acc = fmaf(acc, y, 0.5f);
+        acc = fmaf(acc, y, 1.0f);
+        return acc * y;
+    }
+    float acc = (float)kc(kRegInv)[n];
+    for (int i = n - 1; i >= 1; --i) acc = fmaf(acc, y, (float)kc(kRegInv)[i]);
+    return acc * y;
+}
+
 // Regulators (REG): 0 exponential, R = l2/(e^y - 1); 1 polynomial-exponential
 // R = k^2 exp(-S_N(y)); 2 flat, R = (k^2 - l2) Theta(k^2 - l2); y = l2/k^2.  For REG 1 and 2
 // the callers pass l2 and m2 in units of k^2 (inv_k2 = 1) and G is 1/(Z y + R/k^2 + m2/k^2);
@@ -559,6 +577,7 @@ struct Par32 {
     float m2f, am2f;  // m2/k^2 and its magnitude
     float tau;        // near-pole threshold
     float kfb;        // weight of a float64 fallback's amplification (see fp32_constants)
+    int reg_n;        // order N of the polynomial-exponential regulator
     double za2, zb1;  // s + 1 = za2 log2(y) + zb1
     double m2;        // the float64 fallback's mass
 };
@@ -582,16 +601,28 @@ __device__ __forceinline__ void zcell32(float y, const Par32 &P, int &i, float &
 // rounded to float32 and the coordinate carries za2 kErrLog2f plus the fraction's rounding, and
 // kappa amplifies both like every other perturbation: kappa enters kmax scaled by their share
 // kfb of the float32 nodes' per-kappa error K, so that kappa K of the bound covers them.
+// REG 0: G = (-E)/((-E)(Z y + m2) + y e); REG 1, 2: G = 1/(Z y + m2 + R/k^2).
+template <int REG = 0>
 __device__ __forceinline__ float prop_fallback(const Par32 &P, float y, double2 zz, float fz,
                                                float &kmax) {
     const double l2 = (double)y;
     const double z = fma((double)fz, zz.y, zz.x);
-    const double E = fm::expm1_neg(l2);
-    const double le = fma(l2, E, l2);
-    const double rd = fm::rcp_nr(fma(-E, fma(z, l2, P.m2), le));
-    const float kap = (float)(fabs(fma(-E, fma(z, l2, fabs(P.m2)), le) * rd) * (double)P.kfb);
+    float kap, g;
+    if (REG == 0) {
+        const double E = fm::expm1_neg(l2);
+        const double le = fma(l2, E, l2);
+        const double rd = fm::rcp_nr(fma(-E, fma(z, l2, P.m2), le));
+        kap = (float)(fabs(fma(-E, fma(z, l2, fabs(P.m2)), le) * rd) * (double)P.kfb);
+        g = (float)(-E * rd);
+    } else {
+        const double R = REG == 1 ? fm::exp_neg(fmin(poly_s(l2, P.reg_n), 1000.0))
+                                  : fmax(1.0 - l2, 0.0);
+        const double rd = fm::rcp_nr(fma(z, l2, P.m2) + R);
+        kap = (float)(fabs((fma(z, l2, fabs(P.m2)) + R) * rd) * (double)P.kfb);
+        g = (float)rd;
+    }
     kmax = __uint_as_float(max(__float_as_uint(kmax), __float_as_uint(kap)));
-    return (float)(-E * rd);
+    return g;
 }
 
 // W float32 propagators; kmax tracks the largest amplification (|Z l2 + R| + |m2|)/D of the
@@ -600,9 +631,37 @@ __device__ __forceinline__ float prop_fallback(const Par32 &P, float y, double2 
 // l2 e = 0 and both the denominator and its parts lose the exponential exactly (see FRG_FAR_Y).
 #define FRG_FAR_Y32 18.0f
 
-template <int W, bool FAR = false>
+template <int W, bool FAR = false, int REG = 0>
 __device__ __forceinline__ void propagators32(const float (&l2)[W], float (&G)[W], float &kmax,
                                               const Smem &sm, const Par32 &P) {
+    if (REG != 0) {
+        // polynomial-exponential (R/k^2 = e^-S_N(y)) and flat (R/k^2 = max(1 - y, 0))
+        // regulators: D = Z y + m2 + R/k^2, G = 1/D
+        int iz[W];
+        float fz[W], E[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) zcell32(l2[w], P, iz[w], fz[w]);
+        double2 z[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) z[w] = sm.Z64[iz[w]];
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            E[w] = REG == 1 ? fm::exp_neg_f(poly_s_f(l2[w], P.reg_n)) : fmaxf(1.0f - l2[w], 0.0f);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const float zv = fmaf(fz[w], (float)z[w].y, (float)z[w].x);
+            const float den = fmaf(zv, l2[w], P.m2f) + E[w];
+            const float parts = fmaf(zv, l2[w], P.am2f) + E[w];
+            if (den < P.tau * parts) {
+                G[w] = prop_fallback<REG>(P, l2[w], z[w], fz[w], kmax);
+            } else {
+                const float rd = __builtin_amdgcn_rcpf(den);
+                G[w] = rd;
+                kmax = __uint_as_float(max(__float_as_uint(kmax), __float_as_uint(parts * rd)));
+            }
+        }
+        return;
+    }
     bool far = FAR;
 #pragma unroll
     for (int w = 0; w < W; ++w) far = far && (l2[w] >= FRG_FAR_Y32);
@@ -662,11 +721,13 @@ __device__ __forceinline__ Par32 par32(const ReqDev &r, const Smem &sm, double m
     P.am2f = fabsf(P.m2f);
     P.tau = (float)r.tau;
     P.kfb = sm.f32c[1];
+    P.reg_n = r.reg_n;
     P.za2 = r.za * 0.69314718055994530942;
     P.zb1 = r.zbk + 1.0;
     return P;
 }
 
+template <int REG>
 __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm, int a, double p,
                                                 double m2, double m2x, double inv_k2,
                                                 float &kmax) {
@@ -681,7 +742,7 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w)
             l2[w] = (float)fma(c1, kc(r.ang.x)[b + w], c0);
-        propagators32<FRG_ILP, true>(l2, G, kmax, sm, P);
+        propagators32<FRG_ILP, true, REG>(l2, G, kmax, sm, P);
         float blk = 0.0f;
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w) blk = fmaf(kc(r.ang.xwf)[b + w], G[w], blk);
@@ -689,7 +750,7 @@ __device__ __forceinline__ double contrib_two32(const ReqDev &r, const Smem &sm,
     }
     for (; b < nx; ++b) {
         float l2[1] = {(float)fma(c1, kc(r.ang.x)[b], c0)}, G[1];
-        propagators32<1, true>(l2, G, kmax, sm, P);
+        propagators32<1, true, REG>(l2, G, kmax, sm, P);
         acc.add(kc(r.ang.xwf)[b] * G[0]);
     }
     return t.wg * (((double)acc.s - (double)acc.c) * inv_k2);
@@ -708,7 +769,7 @@ __device__ __forceinline__ Dual contrib_two(const ReqDev &r, const Smem &sm, int
     if (lx == 1) {
         if (!act) return Dual{0.0, 0.0};
         if (PREC == 0) return contrib_two64<REG, DER>(r, sm, a, p, m2, m2x, inv_k2);
-        return Dual{contrib_two32(r, sm, a, p, m2, m2x, inv_k2, kmax), 0.0};
+        return Dual{contrib_two32<REG>(r, sm, a, p, m2, m2x, inv_k2, kmax), 0.0};
     }
     RadialTerm t{0.0, 0.0, 0.0, 0.0};
     double c0 = 0.0, c1 = 0.0;
@@ -737,7 +798,7 @@ __device__ __forceinline__ Dual contrib_two(const ReqDev &r, const Smem &sm, int
                 g = G[0];
             } else {
                 float l2[1] = {(float)fma(c1, kc(r.ang.x)[b], c0)}, G[1];
-                propagators32<1, true>(l2, G, kmax, sm, P);
+                propagators32<1, true, REG>(l2, G, kmax, sm, P);
                 gf = G[0];
             }
         }
@@ -767,13 +828,14 @@ __device__ __forceinline__ Dual contrib_two(const ReqDev &r, const Smem &sm, int
     return Dual{t.wg * (((double)acc.s - (double)acc.c) * inv_k2), 0.0};
 }
 
+template <int REG>
 __device__ __forceinline__ void xterm32(const ReqDev &r, const Smem &sm, const Par32 &P, int b,
                                         double c0, double c1, double ca, double sa, float &kmax,
                                         double &t, double &inner) {
     const int nphi = r.n_phi;
     const double xb = kc(r.ang.x)[b];
     float l1[1] = {(float)fma(c1, xb, c0)}, g1[1];
-    propagators32<1>(l1, g1, kmax, sm, P);
+    propagators32<1, false, REG>(l1, g1, kmax, sm, P);
     const double A2 = fma(-c1, xb * ca, c0);
     const double B2 = -c1 * (kc(r.ang.xs)[b] * sa);
     Kahan32 acc{0.0f, 0.0f};
@@ -783,7 +845,7 @@ __device__ __forceinline__ void xterm32(const ReqDev &r, const Smem &sm, const P
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w)
             l2[w] = (float)fmax(fma(B2, kc(r.phi.c)[c + w], A2), 1e-30);
-        propagators32<FRG_ILP>(l2, G, kmax, sm, P);
+        propagators32<FRG_ILP, false, REG>(l2, G, kmax, sm, P);
         float blk = 0.0f;
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w) blk = fmaf(kc(r.phi.wf)[c + w], G[w], blk);
@@ -791,7 +853,7 @@ __device__ __forceinline__ void xterm32(const ReqDev &r, const Smem &sm, const P
     }
     for (; c < nphi; ++c) {
         float l2[1] = {(float)fmax(fma(B2, kc(r.phi.c)[c], A2), 1e-30)}, G[1];
-        propagators32<1>(l2, G, kmax, sm, P);
+        propagators32<1, false, REG>(l2, G, kmax, sm, P);
         acc.add(kc(r.phi.wf)[c] * G[0]);
     }
     inner = (double)acc.s - (double)acc.c;
@@ -831,7 +893,7 @@ __device__ __forceinline__ Dual contrib_three(const ReqDev &r, const Smem &sm, i
             if (PREC == 0)
                 xterm64<REG, DER>(r, sm, b, c0, c1, ca, sa, m2h, tb, ib, gb, i2b);
             else
-                xterm32(r, sm, P, b, c0, c1, ca, sa, kmax, tb, ib);
+                xterm32<REG>(r, sm, P, b, c0, c1, ca, sa, kmax, tb, ib);
         }
         if (lx == 1) {
             mid = fma(tb, ib, mid);
@@ -885,13 +947,34 @@ __device__ __forceinline__ double fp32_bound(float kmax, float K, const ReqDev &
 // K = per-kappa relative error of one float32 propagator and the share of it that a float64
 // fallback keeps (see prop_fallback), from the table's largest step L = max|Z_{i+1} - Z_i| /
 // min|Z_i| (per coordinate unit), Zmin = min|Z_i| and the request's coordinate scale za (per
-// unit of ln y); both stored rounded up.
+// unit of ln y); both stored rounded up.  Per regulator (each item an absolute error of D
+// relative to its parts, as in fp32_bound):
+//  exponential: see fp32_bound.
+//  polynomial-exponential, D = Z y + m2 + E, E = e^-S, S = S_N(y): E carries E (S eS + eX) with
+//    eS = (2N + 1) u + 1.5 u the exponent's error (Horner of positive terms, the product with
+//    log2(e)) and eX = kErrExp2f, and S E / parts <= cS = max(1, 0.59/Zmin): where S <= 1,
+//    S E / parts <= S E / E = S <= 1; S > 1 needs y > 1 - 1/e for every N, and there
+//    S E <= 1/e while parts >= Z y; the rounding of y moves E by u |y E'| = u E sum y^i
+//    <= u N S E;
+//  flat, E = max(1 - y, 0): E's rounding u, and the rounding of y moves E by u y <= u Z y/Zmin.
+// Common to all: m2 rounded (u), the inner fma (u), the float32 dressing (2u + 1.5 u L), its
+// coordinate (L za2 kErrLog2f) and the rounding of y through Z (u (1 + za L)).
 __device__ __forceinline__ void fp32_constants(const ReqDev &r, float mx, float mn, float *c) {
     const double L = mn > 0.0f ? (double)mx / (double)mn : 1.0e300;
     const double zlo = fmin(1.0, (double)mn);
-    const double uy = kU32 * (1.0 + r.za * L + fmax(1.32, 0.37 / zlo));
     const double us = L * (r.za * 0.69314718055994530942 * kErrLog2f + 1.0e-12);  // coordinate
-    const double K = uy + us + kU32 * (5.0 + 1.5 * L) + kErrExpm1f * (1.0 + 1.0 / zlo);
+    double uy, K;
+    if (r.reg == 1) {
+        const double cs = fmax(1.0, 0.59 / zlo), n = (double)r.reg_n;
+        uy = kU32 * (1.0 + r.za * L + n * cs);
+        K = uy + us + kU32 * (4.0 + 1.5 * L) + cs * (2.0 * n + 2.5) * kU32 + kErrExp2f;
+    } else if (r.reg == 2) {
+        uy = kU32 * (1.0 + r.za * L + 1.0 / zlo);
+        K = uy + us + kU32 * (5.0 + 1.5 * L);
+    } else {
+        uy = kU32 * (1.0 + r.za * L + fmax(1.32, 0.37 / zlo));
+        K = uy + us + kU32 * (5.0 + 1.5 * L) + kErrExpm1f * (1.0 + 1.0 / zlo);
+    }
     c[0] = K < 1.0e30 ? (float)(K * (1.0 + 1.0 / 1048576.0)) : 3.0e38f;
     // the fallback: the rounding of y, the coordinate and the fraction's rounding (u/2 of a step)
     c[1] = (float)((uy + us + 0.5 * kU32 * L) / K * (1.0 + 1.0 / 1048576.0));
@@ -1242,8 +1325,8 @@ batch_kernel(ReqDev r, double *contrib, unsigned *counters) {
 typedef void (*batch_fn)(ReqDev, double *, unsigned *);
 
 // Kernel instance for (family, precision, regulator, mass derivative); the float32 form exists
-// for the exponential regulator without derivative only, and the LPA kernel reads its regulator
-// from the radial rule and its derivative flag from the request.
+// without derivative only, and the LPA kernel reads its regulator from the radial rule and its
+// derivative flag from the request.
 template <int F, bool D>
 static batch_fn batch_for_reg(int reg) {
     if (reg == 1) return batch_kernel<F, 0, 1, D>;
@@ -1253,7 +1336,9 @@ static batch_fn batch_for_reg(int reg) {
 
 template <int F>
 static batch_fn batch_for_family(int prec, int reg, bool der) {
-    if (prec == 1) return batch_kernel<F, 1, 0, false>;
+    if (prec == 1)
+        return reg == 1 ? batch_kernel<F, 1, 1, false>
+                        : (reg == 2 ? batch_kernel<F, 1, 2, false> : batch_kernel<F, 1, 0, false>);
     return der ? batch_for_reg<F, true>(reg) : batch_for_reg<F, false>(reg);
 }
 
@@ -1306,10 +1391,16 @@ __device__ __forceinline__ void vertex_tile_reg(const ReqDev &r, Smem &sm, const
 template <int F, bool D>
 __device__ __forceinline__ void vertex_tile_any(const ReqDev &r, Smem &sm, const TileDev &td,
                                                 double *contrib, unsigned *counters) {
-    if (r.precision == 1)
-        vertex_tile<F, 1, 0, false>(r, sm, td, contrib, counters);
-    else
+    if (r.precision == 1) {
+        if (r.reg == 1)
+            vertex_tile<F, 1, 1, false>(r, sm, td, contrib, counters);
+        else if (r.reg == 2)
+            vertex_tile<F, 1, 2, false>(r, sm, td, contrib, counters);
+        else
+            vertex_tile<F, 1, 0, false>(r, sm, td, contrib, counters);
+    } else {
         vertex_tile_reg<F, D>(r, sm, td, contrib, counters);
+    }
 }
 
 template <int FAM, int PREC, int REG, bool DER>
@@ -1331,8 +1422,7 @@ __device__ __forceinline__ void multi_tile(const ReqDev &r, Smem &sm, const Tile
 // Occupancy target of a fused-kernel instance: the three-point family and the general kernel
 // carry more state than the two-point families, the mass derivative a second set of
 // accumulators, and the polynomial-exponential regulator's exponent a few more registers.  The
-// float32 form of the two-point families holds 4 (its float32 and float64 dressing tables and
-// the logarithm table already hold a CU to 15 workgroups; at 5 it spills).
+// float32 form of the two-point families holds 4 (at 5 it spills).
 constexpr int multi_waves(int fam, int prec, int reg, bool der) {
     return der ? ((fam < 0 || fam == 3) ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_DER)
                : ((fam < 0 || fam == 3) ? (reg == 1 ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_MULTI)
@@ -1400,7 +1490,9 @@ static multi_fn multi_for_reg(int reg) {
 
 template <int F>
 static multi_fn multi_for_family(int prec, int reg, int der) {
-    if (prec == 1) return multi_kernel<F, 1, 0, false>;
+    if (prec == 1)
+        return reg == 1 ? multi_kernel<F, 1, 1, false>
+                        : (reg == 2 ? multi_kernel<F, 1, 2, false> : multi_kernel<F, 1, 0, false>);
     return der ? multi_for_reg<F, true>(reg) : multi_for_reg<F, false>(reg);
 }
 

@@ -131,10 +131,6 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
         set_error("reg_order must be in [0, 16] (0 = 8), got %d", d->reg_order);
         return FRG_E_INVAL;
     }
-    if (d->precision == FRG_FP32_KAHAN && d->regulator != FRG_REG_EXPONENTIAL) {
-        set_error("the float32 form is implemented for the exponential regulator only");
-        return FRG_E_UNSUPPORTED;
-    }
     if (d->family == FRG_FAMILY_LPA) {
         if (d->d < 1 || d->d > 8) {
             set_error("LPA family needs 1 <= d <= 8, got %d", d->d);

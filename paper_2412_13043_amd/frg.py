@@ -297,15 +297,17 @@ def frg_flop_probe(seq: int, blocks: int, iters: int, out, stream=None) -> None:
 
 def frg_math_probe(which: int, stream=None) -> float:
     """Largest error of one float32 elementary operation over its whole input range
-    (include/frg_testing.h): 0 log2 (absolute, on [1/2, 1)), 1 expm1(-y), 2 reciprocal."""
+    (include/frg_testing.h): 0 log2 (absolute, on [1/2, 1)), 1 expm1(-y), 2 reciprocal,
+    3 2^x."""
     v = c_double()
     _check(_lib.frg_math_probe(which, byref(v), _stream(stream)), "frg_math_probe")
     return v.value
 
 
 def frg_fp32_error_constants() -> tuple:
-    """(u, log2 error, expm1 error, reciprocal error) the float32 form's bound uses."""
-    a = (c_double * 4)()
+    """(u, log2 error, expm1 error, reciprocal error, 2^x error) the float32 form's bound
+    uses."""
+    a = (c_double * 5)()
     _lib.frg_fp32_error_constants(a)
     return tuple(a)
 

@@ -40,10 +40,10 @@ def _rel(got, ref):
 
 
 def _run(env, family, n_q, q_max, *, n_x=0, n_phi=0, d=0, k=1.0, ext=None, m2=None,
-         m2_scalar=0.0, Z=None, n_ext=None, precision=0, tau=0.0, err=False):
+         m2_scalar=0.0, Z=None, n_ext=None, precision=0, tau=0.0, err=False, reg=0):
     frg, ctx, torch = env
     desc = frg.make_desc(family, n_q, q_max, n_x=n_x, n_phi=n_phi, d=d, k=k,
-                         precision=precision, near_pole_tau=tau)
+                         precision=precision, near_pole_tau=tau, regulator=reg)
     if n_ext is None:
         n_ext = len(m2) if m2 is not None else (len(ext) if family != 3 else len(ext) // 2)
     out = torch.full((n_ext,), float("nan"), dtype=torch.float64, device="cuda")
@@ -254,6 +254,40 @@ def test_fp32_form_within_stated_bound(env, tau):
     assert np.all(bound < 1e-4)
     if tau >= 0.1:
         assert np.all(bound < 1e-5)
+
+
+@pytest.mark.parametrize("reg", [1, 2])
+def test_fp32_form_other_regulators(env, reg):
+    """The float32 form with the polynomial-exponential (s_8) and the flat regulator: every
+    result within its stated bound against the oracle, the bound not vacuous -- two-point near
+    the pole (tau 0 and 0.1), three-point and LPA samples."""
+    okind = oracle.reg_polyexp(8) if reg == 1 else oracle.REG_LITIM
+    p, m2, Z = wl.near_pole()
+    # Z y + R/k^2 falls to about 0.84 (s_8) and to min Z = 0.8 (flat) with Z >= 0.8, so the
+    # near-pole masses of these regulators are m2 in [-0.75, -0.5] (the exponential's -0.95
+    # would cross their pole)
+    m2 = -0.5 + (m2 + 0.5) * (0.25 / 0.45)
+    ref = oracle.integrate(oracle.TWO_POINT, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX, ext=p, m2=m2,
+                           Z=Z, regulator=okind)
+    for tau in (0.0, 0.1):
+        got, bound = _run(env, 2, wl.TWO_NQ, wl.TWO_QMAX, n_x=wl.TWO_NX, ext=p, m2=m2, Z=Z,
+                          precision=1, tau=tau, err=True, reg=reg)
+        rel = np.abs(got - ref) / ref
+        print(f"fp32 form reg={reg} tau={tau}: max rel err {rel.max():.3e}, "
+              f"max stated bound {bound.max():.3e}")
+        assert np.all(rel <= bound)
+        assert np.all(bound < 1e-4)
+    P, A, m3, Z3 = wl.three_point()
+    sel = np.arange(0, 1024, 41)
+    got, bound = _run(env, 3, 24, 10.0, n_x=12, n_phi=8, ext=np.concatenate([P[sel], A[sel]]),
+                      m2=m3[sel], Z=Z3, precision=1, tau=0.1, err=True, reg=reg)
+    ref = oracle.integrate(oracle.THREE_POINT, 24, 10.0, n_x=12, n_phi=8, ext=(P[sel], A[sel]),
+                           m2=m3[sel], Z=Z3, regulator=okind)
+    assert np.all(np.abs(got - ref) / ref <= bound) and np.all(bound < 1e-4)
+    rho, u, m2l = wl.lpa_potential()
+    got, bound = _run(env, 1, 32, 6.0, m2=m2l, precision=1, tau=0.1, err=True, reg=reg)
+    ref = oracle.integrate(oracle.LPA, 32, 6.0, m2=m2l, regulator=okind)
+    assert np.all(np.abs(got - ref) / ref <= bound) and np.all(bound < 1e-4)
 
 
 def test_fp32_error_constants_cover_measured(env):

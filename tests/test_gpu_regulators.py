@@ -1,7 +1,7 @@
 """GPU parity for the regulator variants -- polynomial-exponential s_N (the paper's default, N = 8,
 and other orders) and flat (Litim) -- in every family, against the FP64 oracle: 1e-12 relative
 per point, bitwise equality across tile shapes and in fused launches mixed with the exponential
-regulator, and FRG_E_UNSUPPORTED for the float32 form.
+regulator, the float32 form of both in fused launches.
 """
 import math
 
@@ -181,10 +181,45 @@ def test_regulator_arguments_checked(env):
     out = torch.zeros(4, dtype=torch.float64, device="cuda")
     ext = torch.ones(4, dtype=torch.float64, device="cuda")
     for kw, status in [(dict(regulator=3), frg.FRG_E_INVAL), (dict(regulator=-1), frg.FRG_E_INVAL),
-                       (dict(regulator=1, reg_order=17), frg.FRG_E_INVAL),
-                       (dict(regulator=1, precision=1), frg.FRG_E_UNSUPPORTED),
-                       (dict(regulator=2, precision=1), frg.FRG_E_UNSUPPORTED)]:
+                       (dict(regulator=1, reg_order=17), frg.FRG_E_INVAL)]:
         desc = frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 8, 6.0, n_x=4, **kw)
         with pytest.raises(frg.FrgError) as ei:
             ctx.integrate(desc, out, ext=ext, m2_scalar=0.5)
         assert ei.value.status == status, kw
+
+
+def test_fp32_regulators_fused_equal_alone(env):
+    # float32 requests with the s_8 and the flat regulator (and one float64 request) in one
+    # fused launch (the general kernel): values and stated bounds bitwise those of the requests
+    # evaluated alone
+    frg, ctx, torch = env
+    p, m2, Z = wl.near_pole()
+    P, A, m3, Z3 = wl.three_point()
+    sel = np.arange(0, 1024, 29)
+    reqs = [(frg.make_desc(2, 24, 10.0, n_x=12, precision=1, near_pole_tau=0.1, regulator=1),
+             p, m2, Z, True),
+            (frg.make_desc(3, 12, 10.0, n_x=6, n_phi=6, precision=1, near_pole_tau=0.1,
+                           regulator=2), np.concatenate([P[sel], A[sel]]), m3[sel], Z3, True),
+            (frg.make_desc(2, 16, 10.0, n_x=8, regulator=1), p, m2 + 1.5, Z, False)]
+    descs, batches, outs, errs, keep, alone = [], [], [], [], [], []
+    for d, ext, mm, Zt, f32 in reqs:
+        n = mm.size
+        te, tm, tZ = _d(torch, ext), _d(torch, mm), _d(torch, Zt)
+        o = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        e = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda") if f32 else None
+        descs.append(d)
+        batches.append(frg.make_batch(n, o, ext=te, m2=tm, Z=tZ, x_min=wl.Z_XMIN,
+                                      x_max=wl.Z_XMAX, err_out=e))
+        outs.append(o)
+        errs.append(e)
+        keep += [te, tm, tZ]
+        o1 = torch.empty(n, dtype=torch.float64, device="cuda")
+        e1 = torch.empty(n, dtype=torch.float64, device="cuda") if f32 else None
+        ctx.integrate(d, o1, ext=te, m2=tm, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, err_out=e1)
+        alone.append((o1, e1))
+    ctx.integrate_multi(descs, batches)
+    torch.cuda.synchronize()
+    for i in range(len(reqs)):
+        assert torch.equal(outs[i], alone[i][0]), i
+        if errs[i] is not None:
+            assert torch.equal(errs[i], alone[i][1]), i
