@@ -617,14 +617,15 @@ def two_point_ft_setup(torch, frg, wl, B=16):
 
 
 STEPPER_CFG = dict(rtol=1e-8, atol=1e-10, h0=0.05, h_min=1e-8, h_max=0.5, max_steps=100000)
-STEPPER_T_END = {"lpa": 3.0, "lpa_abm4": 3.0, "two_point": 1.0}
+STEPPER_T_END = {"lpa": 3.0, "lpa_abm4": 3.0, "lpa_rkf78": 3.0, "lpa_abm4_variable": 3.0,
+                 "two_point": 1.0}
 
 
 def stepper_bench(torch, frg, wl, ctx):
     """Whole flows integrated by the device stepper: the O(4) LPA flow (64 rho points, GL32) from
-    k = Lambda to k = Lambda e^-3 (adaptive Dormand-Prince, and fixed-step ABM4 with h = 0.05),
-    and a two-point vertex flow (256 momenta, 64x32 nodes, state
-    m2 per momentum, dstate/dt = -I) from k = Lambda to Lambda e^-1."""
+    k = Lambda to k = Lambda e^-3 (adaptive Dormand-Prince; fixed-step ABM4 with h = 0.05; the
+    adaptive Fehlberg 7(8) pair; variable-step ABM4), and a two-point vertex flow (256 momenta,
+    64x32 nodes, state m2 per momentum, dstate/dt = -I) from k = Lambda to Lambda e^-1."""
     res = {}
     rho = wl.lpa_rho_grid()
     grid = _dev(torch, rho)
@@ -642,6 +643,13 @@ def stepper_bench(torch, frg, wl, ctx):
             state = _dev(torch, 0.3 + rho)
             st = ctx.stepper(d1, state, grid, n_comp=4, m2_floor=-0.9, h0=0.05, max_steps=10000,
                              method=1)
+        elif kind == "lpa_rkf78":
+            state = _dev(torch, 0.3 + rho)
+            st = ctx.stepper(d1, state, grid, n_comp=4, m2_floor=-0.9, method=2, **STEPPER_CFG)
+        elif kind == "lpa_abm4_variable":
+            state = _dev(torch, 0.3 + rho)
+            st = ctx.stepper(d1, state, grid, n_comp=4, m2_floor=-0.9, method=3,
+                             **dict(STEPPER_CFG, h0=0.01))
         else:
             state = torch.full((p.size,), m2, dtype=torch.float64, device="cuda")
             st = ctx.stepper(d2, state, tp, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
@@ -653,7 +661,7 @@ def stepper_bench(torch, frg, wl, ctx):
         st.close()
         return el, s
 
-    for kind in ("lpa", "lpa_abm4", "two_point"):
+    for kind in ("lpa", "lpa_abm4", "lpa_rkf78", "lpa_abm4_variable", "two_point"):
         run(kind)  # plans and rules
         el, s = run(kind)
         attempts = s.accepted + s.rejected
@@ -783,11 +791,11 @@ def secondary(torch, frg, wl, ctx, serving_seconds=15.0, serving_warm=2.0):
     # precision form on the near-pole workload vs float64 on identical inputs
     log("bench: float32 precision form")
 
-    def fp32_vs_fp64(seed_m2, tau):
+    def fp32_vs_fp64(seed_m2, tau, regulator=0):
         res = {}
         for prec in (0, 1):
             descs, batches, out, err, nodes, keep = two_point_batch_setup(
-                torch, frg, precision=prec, seed_m2=seed_m2, tau=tau)
+                torch, frg, precision=prec, seed_m2=seed_m2, tau=tau, regulator=regulator)
             fp = lambda: ctx.integrate_multi(descs, batches)
             warm_clocks(torch, fp, EXTRA_WARM_S)
             wall, ev = time_kernel(torch, fp, 100, 5)
@@ -813,6 +821,8 @@ def secondary(torch, frg, wl, ctx, serving_seconds=15.0, serving_warm=2.0):
     ex["fp32_form_near_pole_tau_sweep"] = {str(t): fp32_vs_fp64(4, t) for t in (0.0, 0.25)}
     # the two-point workload itself (m2 = 0.5): no propagator falls back to float64
     ex["fp32_form_two_point"] = fp32_vs_fp64(None, 0.1)
+    # the polynomial-exponential s_8 regulator (the paper's default) in both forms
+    ex["fp32_form_two_point_s8"] = fp32_vs_fp64(None, 0.1, regulator=1)
     # right-hand-side latency: one LPA, two-point and three-point RHS per call, the plan's kernels
     # launched directly (default) and replayed as a captured HIP graph (FRG_FLOW_GRAPH=1)
     log("bench: RHS latency")

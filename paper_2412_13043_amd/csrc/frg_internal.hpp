@@ -48,6 +48,7 @@ struct ReqDev {
     int reg;          // regulator: 0 exponential, 1 polynomial-exponential, 2 flat
     int reg_n;        // order N of the polynomial-exponential regulator
     double far_y;     // y = l2/k^2 beyond which R is exactly 0 in float64 (regulator 1)
+    float far_y32;    // y beyond which R/k^2 < e^-24 (regulator 1, float32 form)
     long long ctr_base;      // first counter of this request in the counter array
     long long contrib_base;  // first double of this request's [n_q][n_ext] contribution block
     double k, k2;

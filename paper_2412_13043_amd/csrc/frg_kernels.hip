@@ -578,6 +578,7 @@ struct Par32 {
     float tau;        // near-pole threshold
     float kfb;        // weight of a float64 fallback's amplification (see fp32_constants)
     int reg_n;        // order N of the polynomial-exponential regulator
+    float fary;       // its far field: y beyond which R/k^2 < e^-24
     double za2, zb1;  // s + 1 = za2 log2(y) + zb1
     double m2;        // the float64 fallback's mass
 };
@@ -636,7 +637,9 @@ __device__ __forceinline__ void propagators32(const float (&l2)[W], float (&G)[W
                                               const Smem &sm, const Par32 &P) {
     if (REG != 0) {
         // polynomial-exponential (R/k^2 = e^-S_N(y)) and flat (R/k^2 = max(1 - y, 0))
-        // regulators: D = Z y + m2 + R/k^2, G = 1/D
+        // regulators: D = Z y + m2 + R/k^2, G = 1/D.  Far field of the polynomial-exponential
+        // one (a wave-uniform branch): where every lane has y >= fary, R/k^2 < e^-24 is
+        // dropped (the bound's constant K carries it).
         int iz[W];
         float fz[W], E[W];
 #pragma unroll
@@ -644,9 +647,18 @@ __device__ __forceinline__ void propagators32(const float (&l2)[W], float (&G)[W
         double2 z[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) z[w] = sm.Z64[iz[w]];
+        bool far = FAR && REG == 1;
 #pragma unroll
-        for (int w = 0; w < W; ++w)
-            E[w] = REG == 1 ? fm::exp_neg_f(poly_s_f(l2[w], P.reg_n)) : fmaxf(1.0f - l2[w], 0.0f);
+        for (int w = 0; w < W; ++w) far = far && (l2[w] >= P.fary);
+        if (FAR && REG == 1 && __all(far)) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) E[w] = 0.0f;
+        } else {
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                E[w] = REG == 1 ? fm::exp_neg_f(poly_s_f(l2[w], P.reg_n))
+                                : fmaxf(1.0f - l2[w], 0.0f);
+        }
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             const float zv = fmaf(fz[w], (float)z[w].y, (float)z[w].x);
@@ -722,6 +734,7 @@ __device__ __forceinline__ Par32 par32(const ReqDev &r, const Smem &sm, double m
     P.tau = (float)r.tau;
     P.kfb = sm.f32c[1];
     P.reg_n = r.reg_n;
+    P.fary = r.far_y32;
     P.za2 = r.za * 0.69314718055994530942;
     P.zb1 = r.zbk + 1.0;
     return P;
@@ -950,7 +963,9 @@ __device__ __forceinline__ double fp32_bound(float kmax, float K, const ReqDev &
 // unit of ln y); both stored rounded up.  Per regulator (each item an absolute error of D
 // relative to its parts, as in fp32_bound):
 //  exponential: see fp32_bound.
-//  polynomial-exponential, D = Z y + m2 + E, E = e^-S, S = S_N(y): E carries E (S eS + eX) with
+//  polynomial-exponential, D = Z y + m2 + E, E = e^-S, S = S_N(y): in the far field (y >= fary,
+//    S >= 24) E is dropped, e^-24 = 3.8e-11 against parts >= Zmin fary; else E carries
+//    E (S eS + eX) with
 //    eS = (2N + 1) u + 1.5 u the exponent's error (Horner of positive terms, the product with
 //    log2(e)) and eX = kErrExp2f, and S E / parts <= cS = max(1, 0.59/Zmin): where S <= 1,
 //    S E / parts <= S E / E = S <= 1; S > 1 needs y > 1 - 1/e for every N, and there
@@ -967,7 +982,8 @@ __device__ __forceinline__ void fp32_constants(const ReqDev &r, float mx, float 
     if (r.reg == 1) {
         const double cs = fmax(1.0, 0.59 / zlo), n = (double)r.reg_n;
         uy = kU32 * (1.0 + r.za * L + n * cs);
-        K = uy + us + kU32 * (4.0 + 1.5 * L) + cs * (2.0 * n + 2.5) * kU32 + kErrExp2f;
+        K = uy + us + kU32 * (4.0 + 1.5 * L) + cs * (2.0 * n + 2.5) * kU32 + kErrExp2f +
+            3.8e-11 / (zlo * (double)r.far_y32);  // the far field's dropped e^-S_N < e^-24
     } else if (r.reg == 2) {
         uy = kU32 * (1.0 + r.za * L + 1.0 / zlo);
         K = uy + us + kU32 * (5.0 + 1.5 * L);

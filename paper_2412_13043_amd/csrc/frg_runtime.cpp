@@ -75,10 +75,10 @@ int reg_order(const frg_integral_desc &d) {
     return d.regulator == FRG_REG_POLY_EXP ? (d.reg_order > 0 ? d.reg_order : 8) : 0;
 }
 
-// Smallest y (to a relative 1e-12) with S_N(y) = sum_{i=1}^{N} y^i/i >= 760: beyond it
-// exp(-S_N) is exactly 0 in float64 (the smallest subnormal is exp(-744.4)), so the
+// Smallest y (to a relative 1e-12) with S_N(y) = sum_{i=1}^{N} y^i/i >= s_far; with s_far = 760
+// exp(-S_N) is exactly 0 in float64 beyond it (the smallest subnormal is exp(-744.4)), so the
 // polynomial-exponential regulator vanishes exactly there.
-double poly_exp_far_y(int n) {
+double poly_exp_far_y(int n, double s_far) {
     auto S = [n](double y) {
         double acc = 1.0 / n;
         for (int i = n - 1; i >= 1; --i) acc = acc * y + 1.0 / i;
@@ -87,7 +87,7 @@ double poly_exp_far_y(int n) {
     double lo = 0.0, hi = 1e4;
     for (int it = 0; it < 200 && hi - lo > 1e-12 * hi; ++it) {
         const double mid = 0.5 * (lo + hi);
-        (S(mid) >= 760.0 ? hi : lo) = mid;
+        (S(mid) >= s_far ? hi : lo) = mid;
     }
     return hi;
 }
@@ -676,7 +676,11 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
     r.m2_mode = b.m2 ? m2_mode : 0;
     r.reg = d.regulator;
     r.reg_n = reg_order(d);
-    r.far_y = d.regulator == FRG_REG_POLY_EXP ? poly_exp_far_y(r.reg_n) : 38.0;
+    r.far_y = d.regulator == FRG_REG_POLY_EXP ? poly_exp_far_y(r.reg_n, 760.0) : 38.0;
+    // the float32 form drops e^-S_N below e^-24 (its bound carries that term)
+    r.far_y32 = d.regulator == FRG_REG_POLY_EXP
+                    ? std::nextafter((float)poly_exp_far_y(r.reg_n, 24.0), 3.0e38f)
+                    : 3.0e38f;
     r.m2s = b.m2_scalar;
     r.m2_floor = m2_floor;
     r.tau = d.precision == 1 ? d.near_pole_tau : 0.0;

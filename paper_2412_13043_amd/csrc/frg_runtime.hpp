@@ -127,7 +127,7 @@ double nodes_per_point(const frg_integral_desc &d);
 // Order N of a polynomial-exponential regulator (0 for the other regulators).
 int reg_order(const frg_integral_desc &d);
 // y beyond which the order-n polynomial-exponential regulator is exactly 0 in float64.
-double poly_exp_far_y(int n);
+double poly_exp_far_y(int n, double s_far);
 
 }  // namespace frg
 
