@@ -35,6 +35,7 @@ TWO_POINT = 2
 THREE_POINT = 3
 LPA_T = 4
 TWO_POINT_T = 5
+THREE_POINT_T = 6
 BOSONIC = 0
 FERMIONIC = 1
 
@@ -85,6 +86,10 @@ def _load():
             lib.frgo_integrate_dz_three.argtypes = [I, I, I, D, D, I, P, P, D, P, I, D, D, I, P]
             lib.frgo_integrate_ft_dz.argtypes = [I, I, D, D, I, I, D, D, I, I, P, P, D, P, I, D,
                                                  D, I, P]
+            lib.frgo_integrate_ft_three.argtypes = [I, I, I, D, D, I, I, D, D, I, I, P, P, D, P,
+                                                    I, D, D, I, I, P]
+            lib.frgo_vertex_ft_spherical.argtypes = [I, I, I, D, D, I, I, D, D, I, I, P, P, D, D,
+                                                     D, P, I, D, D, P]
             _lib = lib
     return _lib
 
@@ -249,10 +254,23 @@ def matsubara_rule(statistics, T, lam, n_tail=0, cap=1 << 16):
 
 
 def integrate_ft(family, n_q, q_max, *, T, statistics=BOSONIC, freq_max, freq_scaled=False,
-                 n_tail=0, n_x=0, k=1.0, regulator=REG_EXP, ext=None, m2=None, m2_scalar=0.0,
-                 Z=None, x_min=1e-3, x_max=1e3, n_ext=None, dm2=False):
-    """Finite-temperature integrals I_e, families LPA_T and TWO_POINT_T.
-    ext: family TWO_POINT_T (p[n], p0[n])."""
+                 n_tail=0, n_x=0, n_phi=0, k=1.0, regulator=REG_EXP, ext=None, m2=None,
+                 m2_scalar=0.0, Z=None, x_min=1e-3, x_max=1e3, n_ext=None, dm2=False):
+    """Finite-temperature integrals I_e, families LPA_T, TWO_POINT_T and THREE_POINT_T.
+    ext: family TWO_POINT_T (p[n], p0[n]); THREE_POINT_T (p[n], alpha[n], p01[n], p02[n])."""
+    if family == THREE_POINT_T:
+        ext_arr = np.concatenate([_f64(e) for e in ext])
+        n = len(ext[0])
+        m2a = _f64(m2)
+        Za = _f64(Z)
+        out = np.empty(n)
+        rc = _load().frgo_integrate_ft_three(
+            n_q, n_x, n_phi, q_max, k, regulator, statistics, T, freq_max,
+            1 if freq_scaled else 0, n_tail, _ptr(ext_arr), _ptr(m2a), m2_scalar, _ptr(Za),
+            0 if Za is None else len(Za), x_min, x_max, n, 1 if dm2 else 0, _ptr(out))
+        if rc != 0:
+            raise ValueError(f"frgo_integrate_ft_three rejected the arguments (rc={rc})")
+        return out
     if family == TWO_POINT_T:
         p, p0 = ext
         ext_arr = np.concatenate([_f64(p), _f64(p0)])
@@ -272,3 +290,19 @@ def integrate_ft(family, n_q, q_max, *, T, statistics=BOSONIC, freq_max, freq_sc
     if rc != 0:
         raise ValueError(f"frgo_integrate_ft rejected the arguments (rc={rc})")
     return out
+
+
+def vertex_ft_spherical(n_q, n_t1, n_t2, q_max, p1, p2, p01, p02, m2, *, T, statistics=BOSONIC,
+                        freq_max, freq_scaled=False, n_tail=0, k=1.0, regulator=REG_EXP, Z=None,
+                        x_min=1e-3, x_max=1e3) -> float:
+    """The finite-temperature three-point integral of one point with explicit spatial 3-vectors
+    p1, p2 (frgo_vertex_ft_spherical)."""
+    p1a, p2a, Za = _f64(p1), _f64(p2), _f64(Z)
+    out = np.empty(1)
+    rc = _load().frgo_vertex_ft_spherical(n_q, n_t1, n_t2, q_max, k, regulator, statistics, T,
+                                          freq_max, 1 if freq_scaled else 0, n_tail, _ptr(p1a),
+                                          _ptr(p2a), p01, p02, m2, _ptr(Za),
+                                          0 if Za is None else len(Za), x_min, x_max, _ptr(out))
+    if rc != 0:
+        raise ValueError("frgo_vertex_ft_spherical rejected the arguments")
+    return float(out[0])

@@ -593,6 +593,121 @@ int frgo_integrate_ft_dm2(int family, int n_q, int n_x, double q_max, double k, 
 }
 
 /* ---------------------------------------------------------------------------------------- */
+/* Three-point at finite temperature (family 6).                                            */
+/* ---------------------------------------------------------------------------------------- */
+static double ft_prop(int regulator, const double *Z, int nZ, double x_min, double x_max,
+                      double l2, double w, double m2, double k) {
+    return 1.0 / (w * w + frgo_dressing(Z, nZ, x_min, x_max, l2) * l2 +
+                  frgo_regulator(regulator, l2, k) + m2);
+}
+
+int frgo_integrate_ft_three(int n_q, int n_x, int n_phi, double q_max, double k, int regulator,
+                            int statistics, double T, double freq_max, int freq_scaled,
+                            int n_tail, const double *ext, const double *m2, double m2_scalar,
+                            const double *Z, int nZ, double x_min, double x_max, int n_ext,
+                            int deriv, double *out) {
+    if (n_ext < 0 || out == NULL || ext == NULL) return -1;
+    if (n_q < 1 || n_q > MAXN || n_x < 1 || n_x > MAXN || n_phi < 1 || n_phi > MAXN) return -1;
+    if (!(q_max > 0.0) || !(k > 0.0)) return -1;
+    if (Z != NULL && (nZ < 1 || !(x_min > 0.0) || !(x_max > x_min))) return -1;
+    static __thread double qn[MAXN], qw[MAXN], xn[MAXN], xw[MAXN], fn[MAXN], fw[MAXN],
+        mw[MAXN], mc[MAXN];
+    double lambda = freq_scaled ? freq_max * k : freq_max;
+    int n_f = frgo_matsubara_rule(statistics, T, lambda, n_tail, MAXN, mw, mc);
+    if (n_f < 0) return -1;
+    frgo_gauss_legendre(n_q, 0.0, q_max * k, qn, qw);
+    frgo_gauss_legendre(n_x, -1.0, 1.0, xn, xw);
+    frgo_gauss_legendre(n_phi, 0.0, PI, fn, fw);
+    double pref = 2.0 / pow(2.0 * PI, 3.0);  /* the azimuth folded onto [0, pi] */
+    for (int e = 0; e < n_ext; ++e) {
+        double p = ext[e], alpha = ext[n_ext + e], p01 = ext[2 * n_ext + e],
+               p02 = ext[3 * n_ext + e];
+        double ca = cos(alpha), sa = sin(alpha);
+        double mass = m2 ? m2[e] : m2_scalar;
+        nsum total = {0.0, 0.0};
+        for (int j = 0; j < n_f; ++j) {
+            double w = mw[j];
+            for (int a = 0; a < n_q; ++a) {
+                double q = qn[a], q2 = q * q;
+                double gq = ft_prop(regulator, Z, nZ, x_min, x_max, q2, w, mass, k);
+                double rad = mc[j] * pref * qw[a] * q2 * frgo_regulator_dot(regulator, q2, k);
+                nsum mid = {0.0, 0.0};
+                for (int b = 0; b < n_x; ++b) {
+                    double x = xn[b], sx = sqrt(1.0 - x * x);
+                    double l1 = q2 + p * p + 2.0 * q * p * x;
+                    if (l1 < 0.0) l1 = 0.0;
+                    double g1 = ft_prop(regulator, Z, nZ, x_min, x_max, l1, w + p01, mass, k);
+                    nsum inner = {0.0, 0.0};
+                    for (int c = 0; c < n_phi; ++c) {
+                        double l2 = q2 + p * p - 2.0 * q * p * (x * ca + sx * cos(fn[c]) * sa);
+                        if (l2 < 0.0) l2 = 0.0;
+                        double g2 = ft_prop(regulator, Z, nZ, x_min, x_max, l2, w + p02, mass, k);
+                        double term = rad * xw[b] * fw[c] * gq * gq * g1 * g2;
+                        if (deriv)
+                            term = rad * xw[b] * fw[c] *
+                                   (-2.0 * gq * gq * gq * g1 * g2 - gq * gq * g1 * g1 * g2 -
+                                    gq * gq * g1 * g2 * g2);
+                        nsum_add(&inner, term);
+                    }
+                    nsum_add(&mid, nsum_get(&inner));
+                }
+                nsum_add(&total, nsum_get(&mid));
+            }
+        }
+        out[e] = nsum_get(&total);
+    }
+    return 0;
+}
+
+int frgo_vertex_ft_spherical(int n_q, int n_t1, int n_t2, double q_max, double k, int regulator,
+                             int statistics, double T, double freq_max, int freq_scaled,
+                             int n_tail, const double p1[3], const double p2[3], double p01,
+                             double p02, double m2, const double *Z, int nZ, double x_min,
+                             double x_max, double *out) {
+    if (n_q < 1 || n_t1 < 1 || n_t2 < 1 || n_q > MAXN || n_t1 > MAXN || n_t2 > MAXN) return -1;
+    if (out == NULL || p1 == NULL || p2 == NULL || !(q_max > 0.0) || !(k > 0.0)) return -1;
+    static __thread double qn[MAXN], qw[MAXN], t1n[MAXN], t1w[MAXN], t2n[MAXN], t2w[MAXN],
+        mw[MAXN], mc[MAXN];
+    double lambda = freq_scaled ? freq_max * k : freq_max;
+    int n_f = frgo_matsubara_rule(statistics, T, lambda, n_tail, MAXN, mw, mc);
+    if (n_f < 0) return -1;
+    frgo_gauss_legendre(n_q, 0.0, q_max * k, qn, qw);
+    frgo_gauss_legendre(n_t1, 0.0, PI, t1n, t1w);
+    frgo_gauss_legendre(n_t2, 0.0, 2.0 * PI, t2n, t2w);
+    double pref = 1.0 / pow(2.0 * PI, 3.0);
+    nsum total = {0.0, 0.0};
+    for (int j = 0; j < n_f; ++j) {
+        double w = mw[j];
+        for (int a = 0; a < n_q; ++a) {
+            double q = qn[a], q2 = q * q;
+            double gq = ft_prop(regulator, Z, nZ, x_min, x_max, q2, w, m2, k);
+            double rad = mc[j] * pref * qw[a] * q2 * frgo_regulator_dot(regulator, q2, k) * gq * gq;
+            nsum s1 = {0.0, 0.0};
+            for (int i = 0; i < n_t1; ++i) {
+                double t1 = t1n[i];
+                nsum s2 = {0.0, 0.0};
+                for (int c = 0; c < n_t2; ++c) {
+                    double t2 = t2n[c];
+                    double v[3] = {q * cos(t1), q * sin(t1) * cos(t2), q * sin(t1) * sin(t2)};
+                    double a1 = 0.0, a2 = 0.0;
+                    for (int m = 0; m < 3; ++m) {
+                        a1 += (v[m] + p1[m]) * (v[m] + p1[m]);
+                        a2 += (v[m] - p2[m]) * (v[m] - p2[m]);
+                    }
+                    double g1 = ft_prop(regulator, Z, nZ, x_min, x_max, a1, w + p01, m2, k);
+                    double g2 = ft_prop(regulator, Z, nZ, x_min, x_max, a2, w + p02, m2, k);
+                    nsum_add(&s2, t2w[c] * g1 * g2);
+                }
+                nsum_add(&s1, t1w[i] * sin(t1) * nsum_get(&s2));
+            }
+            nsum_add(&total, rad * nsum_get(&s1));
+        }
+    }
+    out[0] = nsum_get(&total);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------------- */
 /* Hyperspherical reference rule (rotation-invariance pin).                                  */
 /* q = |q| (cos t1, sin t1 cos t2, sin t1 sin t2 cos t3, sin t1 sin t2 sin t3),              */
 /* d^4q = q^3 sin^2 t1 sin t2 dq dt1 dt2 dt3.                                                */

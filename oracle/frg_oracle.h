@@ -29,7 +29,8 @@ extern "C" {
 /* Regulators: exponential, flat (Litim), and the polynomial-exponential shape of Sec. 3.1,
  * R = k^2 exp(-sum_{i=1}^{N} (l2/k^2)^i / i), selected as FRGO_REG_POLYEXP + N (1 <= N <= 64). */
 enum { FRGO_REG_EXP = 0, FRGO_REG_LITIM = 1, FRGO_REG_POLYEXP = 100 };
-enum { FRGO_LPA = 1, FRGO_TWO_POINT = 2, FRGO_THREE_POINT = 3, FRGO_LPA_T = 4, FRGO_TWO_POINT_T = 5 };
+enum { FRGO_LPA = 1, FRGO_TWO_POINT = 2, FRGO_THREE_POINT = 3, FRGO_LPA_T = 4, FRGO_TWO_POINT_T = 5,
+       FRGO_THREE_POINT_T = 6 };
 
 /* n-point Gauss-Legendre rule on [a, b]; nodes ascending. */
 int frgo_gauss_legendre(int n, double a, double b, double *nodes, double *weights);
@@ -143,6 +144,36 @@ int frgo_integrate_ft(int family, int n_q, int n_x, double q_max, double k, int 
                       int statistics, double T, double freq_max, int freq_scaled, int n_tail,
                       const double *ext, const double *m2, double m2_scalar, const double *Z,
                       int nZ, double x_min, double x_max, int n_ext, double *out);
+
+/*
+ * Three-point at finite temperature (family 6), d = 3 + 1: the spatial angles are x = cos theta
+ * (GL(n_x) on [-1, 1]) and the azimuth phi about the first leg, over [0, 2pi) and folded onto
+ * [0, pi] by phi -> 2pi - phi (GL(n_phi) on [0, pi], weight 2; int d^3q = int q^2 dq dx dphi):
+ *   I = sum_j c_j 2/(2pi)^3 sum_abc w_a w_b w_c q^2 Rdot(q^2) G_j(q)^2 H1_j(l1) H2_j(l2)
+ *   G_j(q)  = 1/(w_j^2 + Z(q^2) q^2 + R(q^2) + m2)
+ *   Hi_j(l) = 1/((w_j + p0i)^2 + Z(l^2) l^2 + R(l^2) + m2)
+ *   l1^2 = q^2 + p^2 + 2 q p x,  l2^2 = q^2 + p^2 - 2 q p (x cos(alpha) + sqrt(1 - x^2) cos(phi)
+ *   sin(alpha)) -- the legs q + p1 and q - p2, |p1| = |p2| = p at angle alpha, carrying the loop
+ * frequency shifted by p01 and p02.  ext: p[n_ext], alpha[n_ext], p01[n_ext], p02[n_ext].
+ * deriv = 1: dI/dm2 instead (every propagator's -G^2 by the product rule).
+ */
+int frgo_integrate_ft_three(int n_q, int n_x, int n_phi, double q_max, double k, int regulator,
+                            int statistics, double T, double freq_max, int freq_scaled,
+                            int n_tail, const double *ext, const double *m2, double m2_scalar,
+                            const double *Z, int nZ, double x_min, double x_max, int n_ext,
+                            int deriv, double *out);
+
+/*
+ * The same integral for one point on a product rule in explicit spatial 3-vectors (to pin the
+ * reduced angle form by rotation invariance): q = |q| (cos t1, sin t1 cos t2, sin t1 sin t2),
+ * GL(n_t1) in t1 on [0, pi] with the sin t1 Jacobian and GL(n_t2) in t2 on [0, 2pi]; the legs
+ * are (q + p1, w_j + p01) and (q - p2, w_j + p02) for arbitrary 3-vectors p1, p2.
+ */
+int frgo_vertex_ft_spherical(int n_q, int n_t1, int n_t2, double q_max, double k, int regulator,
+                             int statistics, double T, double freq_max, int freq_scaled,
+                             int n_tail, const double p1[3], const double p2[3], double p01,
+                             double p02, double m2, const double *Z, int nZ, double x_min,
+                             double x_max, double *out);
 
 /* dI_e/dZ_i of the finite-temperature two-point integral (family 5), out[e * nZ + i], as
  * frgo_integrate_dz: the dressing multiplies the spatial momentum of both legs.  Arguments as

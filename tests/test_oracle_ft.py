@@ -26,6 +26,7 @@ import numpy as np
 import pytest
 
 import oracle
+from paper_2412_13043_amd import workloads as wl
 
 PI = math.pi
 
@@ -298,3 +299,102 @@ def test_ft_dimensional_scaling_in_k(family):
     c = oracle.integrate_ft(family, 20, 6.0, k=k, T=T, freq_max=lam / k, freq_scaled=True,
                             ext=ext_k, m2=m2, **zk, **common)
     assert np.array_equal(a, c)
+
+
+# ------------------------------------------------------------------------------------------
+# Three-point at finite temperature
+# ------------------------------------------------------------------------------------------
+def _rotation3(rng):
+    q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+    return q * np.sign(np.diag(r))
+
+
+@pytest.mark.parametrize("alpha", [0.0, 1.1, PI])
+def test_three_point_ft_rotation_invariance(alpha):
+    # the reduced (x, phi) form against explicit spatial 3-vectors on a spherical product rule,
+    # external vectors rotated at random, shifted leg frequencies, a dressing table
+    rng = np.random.default_rng(int(10 * alpha) + 1)
+    Z = wl.dressing_table(3, 32)
+    p, m2, p01, p02 = 0.9, 0.45, 2 * PI * 0.3, -0.7
+    ft = dict(T=0.3, statistics=oracle.FERMIONIC, freq_max=6.0, n_tail=4)
+    reduced = oracle.integrate_ft(oracle.THREE_POINT_T, 24, 6.0, n_x=512, n_phi=48,
+                                  ext=([p], [alpha], [p01], [p02]), m2_scalar=m2, Z=Z, **ft)[0]
+    Q = _rotation3(rng)
+    p1 = Q @ np.array([p, 0.0, 0.0])
+    p2 = Q @ np.array([p * math.cos(alpha), p * math.sin(alpha), 0.0])
+    sph = oracle.vertex_ft_spherical(24, 72, 72, 6.0, p1, p2, p01, p02, m2, Z=Z, **ft)
+    assert abs(sph - reduced) / reduced < 2e-6, (alpha, sph, reduced)
+
+
+@pytest.mark.parametrize("stat,p01,p02", [(oracle.BOSONIC, 2 * PI * 0.3, -4 * PI * 0.3),
+                                          (oracle.FERMIONIC, 0.8, 0.2)])
+def test_three_point_ft_zero_momentum_against_infinite_series(stat, p01, p02):
+    # p = 0, Z = 1: the angles drop out (sum of the x and folded phi weights: 2 x 2 pi = 4 pi)
+    # and per radial node the frequency sum is T sum_n G(w_n)^2 G(w_n + p01) G(w_n + p02),
+    # G(w) = 1/(w^2 + E^2); mpmath sums the two-sided infinite series
+    n_q, q_max, T, lam, n_tail = 6, 5.0, 0.3, 30.0, 40
+    m = 0.35
+    got = oracle.integrate_ft(oracle.THREE_POINT_T, n_q, q_max, T=T, statistics=stat,
+                              freq_max=lam, n_tail=n_tail, n_x=3, n_phi=4,
+                              ext=([0.0], [0.7], [p01], [p02]), m2_scalar=m)[0]
+    xq, wq = np.polynomial.legendre.leggauss(n_q)
+    q = 0.5 * q_max * (xq + 1.0)
+    wq = 0.5 * q_max * wq
+    R, Rd = reg_numpy(q * q)
+    eta = 0.5 if stat == oracle.FERMIONIC else 0.0
+    mp.mp.dps = 30
+    ref = 0.0
+    bound = 0.0
+    Om = omega_of(stat, T, lam)
+    for a in range(n_q):
+        E2 = mp.mpf(q[a] * q[a] + R[a] + m)
+
+        def term(n):
+            w = 2 * mp.pi * T * (n + eta)
+            return 1 / ((w * w + E2) ** 2 * ((w + p01) ** 2 + E2) * ((w + p02) ** 2 + E2))
+
+        s = T * mp.nsum(term, [-mp.inf, mp.inf])
+        ref += float(wq[a] * q[a] ** 2 * Rd[a]) * float(s)
+        # the summand decays like w^-8; bound the boundary term by the k = 4 one at the
+        # smallest of the denominators
+        bound += float(wq[a] * q[a] ** 2 * Rd[a]) * 8.0 * em_bound(
+            4, math.sqrt(max(float(E2), 1e-12)), T, Om - max(abs(p01), abs(p02)))
+    ref *= 4 * PI / (2 * PI) ** 3
+    bound *= 4 * PI / (2 * PI) ** 3
+    assert abs(got - ref) <= bound + 1e-13 * ref, (got, ref, bound)
+
+
+def test_three_point_ft_mass_derivative_against_differences():
+    Z = wl.dressing_table(5, 24)
+    ext = (np.array([0.3, 1.4]), np.array([0.4, 2.5]), np.array([0.6, -1.2]),
+           np.array([0.0, 0.9]))
+    kw = dict(T=0.25, statistics=oracle.BOSONIC, freq_max=8.0, n_tail=6, n_x=8, n_phi=6, Z=Z,
+              ext=ext)
+    m = np.array([0.5, 0.8])
+    d = oracle.integrate_ft(oracle.THREE_POINT_T, 12, 6.0, m2=m, dm2=True, **kw)
+    f = lambda mm: oracle.integrate_ft(oracle.THREE_POINT_T, 12, 6.0, m2=mm, **kw)
+    h = 1e-3
+    d1 = (f(m + h) - f(m - h)) / (2 * h)
+    d2 = (f(m + 2 * h) - f(m - 2 * h)) / (4 * h)
+    rich = (4 * d1 - d2) / 3
+    assert np.max(np.abs(d - rich) / np.abs(d)) < 1e-9
+
+
+def test_three_point_ft_dimensional_scaling_in_k():
+    # I(k; ...) = k^-2 I(1; T/k, m2/k^2, p/k, p0i/k, lambda/k, range/k): one more propagator
+    # than the two-point family
+    k = 1.7
+    rng = np.random.default_rng(4)
+    Z = 1.0 + 0.2 * rng.random(16)
+    T, lam = 0.3, 15.0
+    m2 = np.array([0.2, 1.5])
+    p, al = np.array([0.4, 2.0]), np.array([0.3, 2.9])
+    p01, p02 = np.array([0.5, -1.1]), np.array([-0.2, 0.7])
+    common = dict(statistics=oracle.FERMIONIC, n_tail=12, n_x=6, n_phi=5)
+    a = oracle.integrate_ft(oracle.THREE_POINT_T, 20, 6.0, k=k, T=T, freq_max=lam,
+                            ext=(p, al, p01, p02), m2=m2, Z=Z, x_min=1e-2 * k, x_max=1e2 * k,
+                            **common)
+    b = oracle.integrate_ft(oracle.THREE_POINT_T, 20, 6.0, k=1.0, T=T / k, freq_max=lam / k,
+                            ext=(p / k, al, p01 / k, p02 / k), m2=m2 / k ** 2, Z=Z, x_min=1e-2,
+                            x_max=1e2, **common)
+    assert np.max(np.abs(a - k ** -2 * b) / np.abs(a)) < 1e-12
