@@ -60,9 +60,9 @@ def flop_three(n_phi):
 
 
 # the standard workloads' three-point rule has 16 phi nodes
-FLOP_PER_NODE = {1: FLOP_LPA, 2: FLOP_TWO, 3: flop_three(16), 5: FLOP_TWO}
+FLOP_PER_NODE = {1: FLOP_LPA, 2: FLOP_TWO, 3: flop_three(16), 5: FLOP_TWO, 6: flop_three(16)}
 # the survey's FLOP-equivalent estimates (transcendentals as 25/25/10), kept for comparison
-FLOP_PER_NODE_SURVEY = {1: 15.0, 2: 74.0, 3: 147.0, 5: 74.0}
+FLOP_PER_NODE_SURVEY = {1: 15.0, 2: 74.0, 3: 147.0, 5: 74.0, 6: 147.0}
 # Two-point nodes with y = l2/k^2 >= 38 have an exponential below double precision: their exact
 # value needs no expm1 and a plain reciprocal of Z l2 + m2 instead of the single-reciprocal form
 # (l^2 e, the outer FMA's extra term and -E x): expm1 + 5 FLOPs fewer.  The kernel takes that
@@ -413,7 +413,8 @@ def main():
                          "session only")
     ap.add_argument("--workload", default="three_point_8",
                     choices=["two_point_256", "three_point_8", "lpa_4096", "two_point_ft_16",
-                             "two_point_256_near_pole", "two_point_256_near_pole_fp32"],
+                             "three_point_ft_2", "two_point_256_near_pole",
+                             "two_point_256_near_pole_fp32"],
                     help="workload of the timed line (default: the three-point batch, the "
                          "largest single-GPU configuration); the others exist so that each "
                          "family's kernel can be timed and profiled on its own")
@@ -590,6 +591,17 @@ def workload_setup(torch, frg, wl, ctx, name):
                   "nodes_per_step": nodes, "rhs_per_step": 16}
         return (lambda: ctx.integrate_multi(descs, batches), nodes, 5, "frg::multi_kernel<5, 0, 0, false>",
                 config, keep)
+    if name == "three_point_ft_2":
+        descs, batches, nodes, keep = three_point_ft_setup(torch, frg, wl)
+        config = {"workload": "three-point vertex flow at finite temperature d=3+1: 2 right-hand "
+                              "sides x 1024 external pairs x (47 Matsubara frequencies (T = 0.1 "
+                              "k, |w| <= 10 k, 8 tail nodes per side) x 64 radial x 32 cos1 x "
+                              "16 phi GL nodes), leg frequencies 0 or +-2 pi T, per-RHS "
+                              "tabulated Z and m2 in U[0.1,2], float64, one fused "
+                              "frg_integrate_multi launch",
+                  "nodes_per_step": nodes, "rhs_per_step": len(descs)}
+        return (lambda: ctx.integrate_multi(descs, batches), nodes, 6, "frg::multi_kernel<6, 0, 0, false>",
+                config, keep)
     rho, u, m2 = wl.lpa_batch()
     tm = _dev(torch, m2.reshape(-1))
     o1 = torch.empty(tm.numel(), dtype=torch.float64, device="cuda")
@@ -614,6 +626,21 @@ def two_point_ft_setup(torch, frg, wl, B=16):
     n_f = ft_frequency_count(wl.FT_T, wl.FT_FREQ_MAX, wl.FT_N_TAIL)
     nodes = B * p.size * n_f * wl.FT_NQ * wl.FT_NX
     return [desc] * B, batches, nodes, (te, tZ, out)
+
+
+def three_point_ft_setup(torch, frg, wl, B=2):
+    """The finite-temperature three-point batch, inputs resident in HBM."""
+    P, A, p01, p02, m2, Z = wl.three_point_ft_batch(B)
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, wl.THREE_NQ, wl.THREE_QMAX,
+                         n_x=wl.THREE_NX, n_phi=wl.THREE_NPHI, T=wl.FT_T,
+                         freq_max=wl.FT_FREQ_MAX, n_tail=wl.FT_N_TAIL)
+    te, tm, tZ = _dev(torch, np.concatenate([P, A, p01, p02])), _dev(torch, m2), _dev(torch, Z)
+    out = torch.empty((B, P.size), dtype=torch.float64, device="cuda")
+    batches = [frg.make_batch(P.size, out[b], ext=te, m2=tm[b], Z=tZ[b], x_min=wl.Z_XMIN,
+                              x_max=wl.Z_XMAX) for b in range(B)]
+    n_f = ft_frequency_count(wl.FT_T, wl.FT_FREQ_MAX, wl.FT_N_TAIL)
+    nodes = B * P.size * n_f * wl.THREE_NQ * wl.THREE_NX * wl.THREE_NPHI
+    return [desc] * B, batches, nodes, (te, tm, tZ, out)
 
 
 STEPPER_CFG = dict(rtol=1e-8, atol=1e-10, h0=0.05, h_min=1e-8, h_max=0.5, max_steps=100000)
@@ -741,6 +768,18 @@ def secondary(torch, frg, wl, ctx, serving_seconds=15.0, serving_warm=2.0):
         "frac_fp64_peak": round(FLOP_PER_NODE[5] * nft / (msft * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                                 4)}
     del keep_ft
+    log("bench: finite-temperature three-point batch")
+    d6, b6, n6, keep6 = three_point_ft_setup(torch, frg, wl)
+    f6 = lambda: ctx.integrate_multi(d6, b6)
+    warm_clocks(torch, f6, EXTRA_WARM_S)
+    wall, ev = time_kernel(torch, f6, 20, 2)
+    ms6 = float(np.mean(ev))
+    ex["three_point_finite_T_batch_2"] = {
+        "gnodes_per_s": round(n6 / (ms6 * 1e-3) / 1e9, 2), "avg_kernel_ms": round(ms6, 3),
+        "nodes": n6,
+        "frac_fp64_peak": round(FLOP_PER_NODE[6] * n6 / (ms6 * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                                4)}
+    del keep6
     # the same two-point batch with the paper's default regulator (polynomial-exponential s_8)
     # and with the flat one
     for name, reg, dm2 in (("two_point_poly_exp_s8_256", 1, False), ("two_point_flat_256", 2, False),

@@ -71,7 +71,9 @@ typedef enum {
     FRG_FAMILY_TWO_POINT = 2,   /* d = 4, one angle (cos1) */
     FRG_FAMILY_THREE_POINT = 3, /* d = 4, cos1 and phi (third angle trivial: factor 2 pi) */
     FRG_FAMILY_LPA_T = 4,       /* finite temperature, d = 3 + 1: Matsubara sum x radial */
-    FRG_FAMILY_TWO_POINT_T = 5  /* finite temperature, d = 3 + 1: Matsubara sum x radial x cos1 */
+    FRG_FAMILY_TWO_POINT_T = 5, /* finite temperature, d = 3 + 1: Matsubara sum x radial x cos1 */
+    FRG_FAMILY_THREE_POINT_T = 6 /* finite temperature, d = 3 + 1: Matsubara sum x radial x cos1 x
+                                    phi */
 } frg_family;
 
 typedef enum {
@@ -123,6 +125,16 @@ typedef enum {
  *                    G_j(q) = 1/(w_j^2 + Z(q^2) q^2 + R(q^2) + m2_e),
  *                    H_j(l) = 1/((w_j + p0_e)^2 + Z(l^2) l^2 + R(l^2) + m2_e),
  *                    l^2 = q_a^2 + p_e^2 + 2 q_a p_e x_b (spatial; Z and R act on spatial momenta)
+ *   family 6:  I_e = sum_j c_j 2/(2pi)^3 sum_abc w_a w_b w_c q_a^2 Rdot(q_a^2) G_j(q_a)^2
+ *                    H1_j(l1) H2_j(l2),
+ *                    H1_j(l) = 1/((w_j + p01_e)^2 + Z(l^2) l^2 + R(l^2) + m2_e), H2_j with p02_e,
+ *                    l1^2 = q^2 + p^2 + 2 q p x, l2^2 = q^2 + p^2 - 2 q p (x cos(alpha) +
+ *                    sqrt(1-x^2) cos(phi) sin(alpha)) (spatial, as in family 3 with p1 = p e1,
+ *                    p2 = p (cos(alpha) e1 + sin(alpha) e2)); float64 only (FRG_E_UNSUPPORTED
+ *                    for the FP32 form);
+ *              in three spatial dimensions the cos1 weight is dx alone (no sqrt(1-x^2)) and the
+ *              phi weight dphi alone (no sin(phi)); the azimuth runs over [0, 2pi) and the
+ *              integrand is even in it, so phi GL(n_phi) on [0, pi] carries a factor 2
  * p0_e is the external frequency: a bosonic 2 pi m T, or for a fermion the paper's
  * p0f = pi T exp(-k/(pi T)) (App. "Derivation of the four-Fermi system").
  * Limits: at least one explicit frequency (fermionic: Lambda >= pi T); n_tail <= FRG_MAX_NODES;
@@ -130,16 +142,16 @@ typedef enum {
  */
 typedef struct {
     int family;            /* frg_family */
-    int d;                 /* 1..8 for LPA; must be 4 for families 2 to 5 */
+    int d;                 /* 1..8 for LPA; must be 4 for families 2 to 6 */
     int n_q;               /* radial nodes, 1..FRG_MAX_NODES */
-    int n_x;               /* cos1 nodes (families 2, 3, 5), 1..FRG_MAX_NODES; ignored for LPA */
-    int n_phi;             /* phi nodes (family 3), 1..FRG_MAX_NODES; ignored otherwise */
+    int n_x;               /* cos1 nodes (families 2, 3, 5, 6), 1..FRG_MAX_NODES; ignored for LPA */
+    int n_phi;             /* phi nodes (families 3, 6), 1..FRG_MAX_NODES; ignored otherwise */
     int precision;         /* frg_precision */
     double q_max;          /* radial upper limit in units of k, > 0 */
     double k;              /* RG scale, > 0 */
     double near_pole_tau;  /* FP32 form only: a propagator whose denominator D satisfies
                               D < tau (|Z l2 + R| + |m2|) is evaluated in float64; 0 = never */
-    /* families 4 and 5 only (ignored otherwise; zero them) */
+    /* families 4, 5 and 6 only (ignored otherwise; zero them) */
     double T;              /* temperature (same units as k), > 0 */
     double freq_max;       /* explicit frequencies |w| <= freq_max (or freq_max * k), > 0 */
     int statistics;        /* frg_statistics */
@@ -170,7 +182,10 @@ typedef struct {
     int n_ext;             /* >= 0; 0 is a valid no-op */
     const double *ext;     /* device. families 1, 4: unused (may be NULL); family 2: p[n_ext];
                               family 3: p[n_ext] followed by alpha[n_ext] (2 n_ext values);
-                              family 5: p[n_ext] followed by p0[n_ext] (2 n_ext values) */
+                              family 5: p[n_ext] followed by p0[n_ext] (2 n_ext values);
+                              family 6: p, alpha, p01 and p02, each [n_ext] (4 n_ext values:
+                              the spatial momenta as in family 3, the external frequencies of
+                              the two inner legs) */
     const double *m2;      /* device [n_ext] per-point m^2, or NULL to use m2_scalar */
     double m2_scalar;
     frg_log_table Z;
@@ -202,7 +217,7 @@ typedef struct {
                               exactly 0.  The vertex families 2, 3 and 5 (at finite
                               temperature the dressing multiplies the spatial momentum) in
                               float64 with a dressing table only (FRG_E_UNSUPPORTED for the
-                              LPA families and the float32 form,
+                              LPA families, family 6 and the float32 form,
                               FRG_E_INVAL without a table), frg_integrate_batch and
                               frg_integrate_multi (FRG_E_UNSUPPORTED from sessions); the caller
                               owns the buffer.  Computed by a second kernel after the
@@ -296,7 +311,7 @@ frg_status frg_autotune(frg_context *ctx, const frg_integral_desc *desc, const f
  *       with t = log(Lambda/k) (Sec. 2.1).  Needs 2 n_ext integrals per call.
  *   family 4: the same at finite temperature (the paper's finite-temperature O(N) example,
  *       Sec. 3.1), I the family-4 integral.
- *   families 2, 3 and 5 (vertex expansion): state = m2_e per external point (floored at
+ *   families 2, 3, 5 and 6 (vertex expansion): state = m2_e per external point (floored at
  *       m2_floor), grid = the batch's ext array, and dstate_e/dt = coef * I_e.
  */
 typedef struct {
@@ -304,11 +319,11 @@ typedef struct {
     int n_ext;
     const double *state;   /* device [n_ext] */
     const double *grid;    /* device: families 1, 4 rho[n_ext]; 2 p[n_ext]; 3 p, alpha and
-                              5 p, p0 [2 n_ext] */
-    frg_log_table Z;       /* families 2, 3, 5 */
+                              5 p, p0 [2 n_ext]; 6 p, alpha, p01, p02 [4 n_ext] */
+    frg_log_table Z;       /* families 2, 3, 5, 6 */
     int n_comp;            /* families 1, 4: N of O(N) (>= 1) */
     double m2_floor;       /* mass floor (-0.9 k^2 in the LPA workload) */
-    double coef;           /* families 2, 3, 5: dstate/dt = coef * I */
+    double coef;           /* families 2, 3, 5, 6: dstate/dt = coef * I */
 } frg_flow_state;
 
 /* dstate_dt (device [n_ext]) = RHS(state) for one flow (see frg_flow_state).  The whole chain

@@ -78,12 +78,17 @@ struct TileDev {
     int pad;
 };
 
+// Angular rules of three spatial dimensions (finite temperature), by the `plain` flags of
+// launch_rules: the cos1 weight without sqrt(1 - x^2), the phi weight without sin(phi).
+constexpr int kPlainCos1 = 1;
+constexpr int kPlainPhi = 2;
+
 // Kernel entry points (defined in frg_kernels.hip).
 hipError_t launch_rules(int n_q, double q_max, int d, int n_x, int n_phi, double *q, double *W,
                         double *R, float *qf, float *Wf, float *Rf, double *x, double *xw,
                         double *xs, float *xf, float *xwf, float *xsf, double *fc, double *fw,
-                        float *fcf, float *fwf, hipStream_t s, bool cos1_plain = false,
-                        int reg = 0, int reg_n = 8);
+                        float *fcf, float *fwf, hipStream_t s, int plain = 0, int reg = 0,
+                        int reg_n = 8);
 // Finite-temperature radial rule (see RadialRule) from a d = 3 vacuum rule `base` of n_q nodes:
 // n_f frequencies, the first and last n_tail of them the tail nodes +-Omega/t (t GL on [0, 1],
 // weight Omega w_t/(2 pi t^2)), the rest 2 pi T (n + eta) for n = n_lo, n_lo + 1, ... (weight T).

@@ -88,7 +88,7 @@ __device__ __forceinline__ void exp_pair64_prop(double y, double &e, double &E) 
 __global__ void __launch_bounds__(64) rules_kernel(
     int n_q, double q_max, int d, int n_x, int n_phi, double *q, double *W, double *R, float *qf,
     float *Wf, float *Rf, double *x, double *xw, double *xs, float *xf, float *xwf, float *xsf,
-    double *fc, double *fw, float *fcf, float *fwf, int cos1_plain, int reg, int reg_n) {
+    double *fc, double *fw, float *fcf, float *fwf, int plain, int reg, int reg_n) {
     const double pi = 3.141592653589793238462643383279502884;
     int which = blockIdx.y;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -137,8 +137,8 @@ __global__ void __launch_bounds__(64) rules_kernel(
         gl_root(n_x, i, th, w);
         double xv = cos(th), sv = sin(th);
         int slot = n_x - 1 - i;  // ascending x
-        // d = 4: dx sqrt(1 - x^2) from the second polar angle; d = 3 (cos1_plain): dx alone
-        const double wx = cos1_plain ? w : w * sv;
+        // d = 4: dx sqrt(1 - x^2) from the second polar angle; d = 3 (kPlainCos1): dx alone
+        const double wx = (plain & kPlainCos1) ? w : w * sv;
         x[slot] = xv;
         xs[slot] = sv;
         xw[slot] = wx;
@@ -154,24 +154,24 @@ __global__ void __launch_bounds__(64) rules_kernel(
         int slot = n_phi - 1 - i;
         double sp, cp;
         sincos(ph, &sp, &cp);
+        // d = 4: dphi sin(phi) from the third polar angle; d = 3 (kPlainPhi): the azimuth, dphi
+        const double wf = (plain & kPlainPhi) ? wp : wp * sp;
         fc[slot] = cp;
-        fw[slot] = wp * sp;
+        fw[slot] = wf;
         fcf[slot] = (float)cp;
-        fwf[slot] = (float)(wp * sp);
+        fwf[slot] = (float)wf;
     }
 }
 
 hipError_t launch_rules(int n_q, double q_max, int d, int n_x, int n_phi, double *q, double *W,
                         double *R, float *qf, float *Wf, float *Rf, double *x, double *xw,
                         double *xs, float *xf, float *xwf, float *xsf, double *fc, double *fw,
-                        float *fcf, float *fwf, hipStream_t s, bool cos1_plain, int reg,
-                        int reg_n) {
+                        float *fcf, float *fwf, hipStream_t s, int plain, int reg, int reg_n) {
     int nmax = n_q > n_x ? n_q : n_x;
     nmax = nmax > n_phi ? nmax : n_phi;
     dim3 grid((nmax + 63) / 64, 3);
     hipLaunchKernelGGL(rules_kernel, grid, dim3(64), 0, s, n_q, q_max, d, n_x, n_phi, q, W, R,
-                       qf, Wf, Rf, x, xw, xs, xf, xwf, xsf, fc, fw, fcf, fwf, cos1_plain ? 1 : 0,
-                       reg, reg_n);
+                       qf, Wf, Rf, x, xw, xs, xf, xwf, xsf, fc, fw, fcf, fwf, plain, reg, reg_n);
     return hipGetLastError();
 }
 
@@ -514,16 +514,18 @@ __device__ __forceinline__ Dual contrib_two64(const ReqDev &r, const Smem &sm, i
 // Contribution of (e, a) to the three-point integral.  l1 does not depend on phi, so G(l1^2) is
 // evaluated once per (a, b); l2^2 = (c0 - c1 x cos a) - c1 sqrt(1-x^2) sin a cos phi.
 // One cos1 node b of the three-point contribution (units of k^2): t = xw_b G^(l1^2) and the phi
-// sum inner = sum_c w_c G^(l2^2).
+// sum inner = sum_c w_c G^(l2^2); m2h1 and m2h2 are the mass terms of the two legs (equal in
+// vacuum; at finite temperature each carries its leg's shifted frequency squared).
 template <int REG, bool DER>
 __device__ __forceinline__ void xterm64(const ReqDev &r, const Smem &sm, int b, double c0,
-                                        double c1, double ca, double sa, double m2h, double &t,
-                                        double &inner, double &g1b, double &inner2) {
+                                        double c1, double ca, double sa, double m2h1,
+                                        double m2h2, double &t, double &inner, double &g1b,
+                                        double &inner2) {
     const int nphi = r.n_phi, nZ = r.nZ;
     const double za = r.za, zb1 = r.zbk + 1.0;
     const double xb = kc(r.ang.x)[b];
     double l1[1] = {fma(c1, xb, c0)}, g1[1];
-    propagators64<1, true, REG>(l1, g1, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
+    propagators64<1, true, REG>(l1, g1, sm, nZ, za, zb1, m2h1, 1.0, r.far_y, r.reg_n);
     const double A2 = fma(-c1, xb * ca, c0);
     const double B2 = -c1 * (kc(r.ang.xs)[b] * sa);
     double acc = 0.0, acc2 = 0.0;
@@ -533,7 +535,7 @@ __device__ __forceinline__ void xterm64(const ReqDev &r, const Smem &sm, int b, 
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w)
             l2[w] = fmax(fma(B2, kc(r.phi.c)[c + w], A2), FRG_L2_TINY);
-        propagators64<FRG_ILP, true, REG>(l2, G, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
+        propagators64<FRG_ILP, true, REG>(l2, G, sm, nZ, za, zb1, m2h2, 1.0, r.far_y, r.reg_n);
 #pragma unroll
         for (int w = 0; w < FRG_ILP; ++w) {
             acc = fma(kc(r.phi.w)[c + w], G[w], acc);
@@ -542,7 +544,7 @@ __device__ __forceinline__ void xterm64(const ReqDev &r, const Smem &sm, int b, 
     }
     for (; c < nphi; ++c) {
         double l2[1] = {fmax(fma(B2, kc(r.phi.c)[c], A2), FRG_L2_TINY)}, G[1];
-        propagators64<1, false, REG>(l2, G, sm, nZ, za, zb1, m2h, 1.0, r.far_y, r.reg_n);
+        propagators64<1, false, REG>(l2, G, sm, nZ, za, zb1, m2h2, 1.0, r.far_y, r.reg_n);
         acc = fma(kc(r.phi.w)[c], G[0], acc);
         if (DER) acc2 = fma(kc(r.phi.w)[c], G[0] * G[0], acc2);
     }
@@ -882,10 +884,14 @@ __device__ __forceinline__ void xterm32(const ReqDev &r, const Smem &sm, const P
 // DER: d/dm2 of G(q^2)^2 G1 G2 = -2 G(q^2)^3 G1 G2 - G(q^2)^2 (G1^2 G2 + G1 G2^2); per cos1 node
 // the phi sums of G2 and G2^2 and G1 itself give midA = sum xw G1^2 sum G2 and
 // midB = sum xw G1 sum G2^2 next to mid = sum xw G1 sum G2 (units of k^2).
+// m2 enters the radial leg, m2x1 and m2x2 the legs l1 and l2 (all equal in vacuum; at finite
+// temperature m2x_i = m2 + (w_j + p0i)^2, the radial leg's w_j^2 folded into the rule's R).
+// The float32 form is vacuum-only (m2x1 = m2x2 = m2).
 template <int PREC, int REG, bool DER>
 __device__ __forceinline__ Dual contrib_three(const ReqDev &r, const Smem &sm, int a, double p,
-                                              double ca, double sa, double m2, double inv_k2,
-                                              float &kmax, bool act, int sx, int lx) {
+                                              double ca, double sa, double m2, double m2x1,
+                                              double m2x2, double inv_k2, float &kmax, bool act,
+                                              int sx, int lx) {
     RadialTerm t{0.0, 0.0, 0.0, 0.0};
     double c0 = 0.0, c1 = 0.0;
     Par32 P;
@@ -895,7 +901,7 @@ __device__ __forceinline__ Dual contrib_three(const ReqDev &r, const Smem &sm, i
         c1 = t.c1 * inv_k2;
         if (PREC == 1) P = par32(r, sm, m2, inv_k2);
     }
-    const double m2h = m2 * inv_k2;
+    const double m2h1 = m2x1 * inv_k2, m2h2 = m2x2 * inv_k2;
     const int nx = r.n_x;
     const int xbase = (int)threadIdx.x & ~(lx - 1);
     double mid = 0.0, midA = 0.0, midB = 0.0;
@@ -904,7 +910,7 @@ __device__ __forceinline__ Dual contrib_three(const ReqDev &r, const Smem &sm, i
         double tb = 0.0, ib = 0.0, gb = 0.0, i2b = 0.0;
         if (act && b < nx) {
             if (PREC == 0)
-                xterm64<REG, DER>(r, sm, b, c0, c1, ca, sa, m2h, tb, ib, gb, i2b);
+                xterm64<REG, DER>(r, sm, b, c0, c1, ca, sa, m2h1, m2h2, tb, ib, gb, i2b);
             else
                 xterm32<REG>(r, sm, P, b, c0, c1, ca, sa, kmax, tb, ib);
         }
@@ -1163,7 +1169,8 @@ __device__ __forceinline__ double readlane64(double v, int l) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Vertex families (FAM 2 two-point, 3 three-point, 5 two-point at finite temperature): lanes =
+// Vertex families (FAM 2 two-point, 3 three-point, 5 and 6 two- and three-point at finite
+// temperature): lanes =
 // (external point, radial sub-lane, cos1 sub-lane); the point's contributions are added in radial
 // order inside the wavefront, or (radially chunked requests) stored for the finalize kernel.
 template <int FAM, int PREC, int REG, bool DER>
@@ -1189,19 +1196,31 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
     // reset by the finalize kernel), then one slot for the dressing table's relative step
     unsigned *kslot = counters + r.ctr_base;
     float kmax = 1.0f;
-    double p = 0.0, m2 = 0.0, ca = 1.0, sa = 0.0, p0 = 0.0;
+    double p = 0.0, m2 = 0.0, ca = 1.0, sa = 0.0, p0 = 0.0, p02 = 0.0;
     if (valid) {
         p = r.ext[e];
         m2 = lane_m2(r, e);
-        if (FAM == 3) sincos(r.ext[r.n_ext + e], &sa, &ca);
+        if (FAM == 3 || FAM == 6) sincos(r.ext[r.n_ext + e], &sa, &ca);
         if (FAM == 5) p0 = r.ext[r.n_ext + e];
+        if (FAM == 6) {
+            p0 = r.ext[2 * r.n_ext + e];
+            p02 = r.ext[3 * r.n_ext + e];
+        }
     }
     // contribution of radial node a (valid in the point's sx == 0 lanes); every lane of the
     // wavefront calls it together, lanes without work pass act = false
     auto node = [&](int a, bool act) -> Dual {
         if (FAM == 3)
-            return contrib_three<PREC, REG, DER>(r, sm, act ? a : 0, p, ca, sa, m2, inv_k2, kmax,
-                                                 act, sx, lx);
+            return contrib_three<PREC, REG, DER>(r, sm, act ? a : 0, p, ca, sa, m2, m2, m2, inv_k2,
+                                                 kmax, act, sx, lx);
+        if (FAM == 6) {
+            // radial index a = (spatial node, frequency j): the legs' frequencies w_j + p01 and
+            // w_j + p02
+            const int ai = act ? a : 0;
+            const double w1 = kc(r.rad.w0)[ai] + p0, w2 = kc(r.rad.w0)[ai] + p02;
+            return contrib_three<PREC, REG, DER>(r, sm, ai, p, ca, sa, m2, fma(w1, w1, m2),
+                                                 fma(w2, w2, m2), inv_k2, kmax, act, sx, lx);
+        }
         if (FAM == 5) {
             // radial index a = (frequency j, spatial node): the inner leg's frequency w_j + p0
             const int ai = act ? a : 0;
@@ -1319,8 +1338,9 @@ hipError_t launch_multi_finalize(const ReqDev *reqs_dev, const TileDev *fin_dev,
 // One request: tile = blockIdx.x -> (external tile, chunk).
 template <int FAM, int PREC, int REG, bool DER>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
-    DER ? (FAM == 3 ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_DER)
-        : ((FAM == 3 || PREC != 0) ? FRG_WAVES_PER_EU_MULTI : FRG_WAVES_PER_EU_BATCH))))
+    DER ? ((FAM == 3 || FAM == 6) ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_DER)
+        : ((FAM == 3 || FAM == 6 || PREC != 0) ? FRG_WAVES_PER_EU_MULTI
+                                                : FRG_WAVES_PER_EU_BATCH))))
 batch_kernel(ReqDev r, double *contrib, unsigned *counters) {
     extern __shared__ double2 lds_dyn[];
     if (FAM == 1) {
@@ -1362,6 +1382,7 @@ static batch_fn batch_variant(int fam, int prec, int reg, bool der) {
     if (fam == 1) return prec == 0 ? batch_kernel<1, 0, 0, false> : batch_kernel<1, 1, 0, false>;
     if (fam == 2) return batch_for_family<2>(prec, reg, der);
     if (fam == 5) return batch_for_family<5>(prec, reg, der);
+    if (fam == 6) return der ? batch_for_reg<6, true>(reg) : batch_for_reg<6, false>(reg);
     return batch_for_family<3>(prec, reg, der);
 }
 
@@ -1431,6 +1452,8 @@ __device__ __forceinline__ void multi_tile(const ReqDev &r, Smem &sm, const Tile
         vertex_tile_any<2, DER>(r, sm, td, contrib, counters);
     else if (r.family == 5)
         vertex_tile_any<5, DER>(r, sm, td, contrib, counters);
+    else if (r.family == 6)
+        vertex_tile_reg<6, DER>(r, sm, td, contrib, counters);  // float64 only
     else
         vertex_tile_any<3, DER>(r, sm, td, contrib, counters);
 }
@@ -1440,10 +1463,12 @@ __device__ __forceinline__ void multi_tile(const ReqDev &r, Smem &sm, const Tile
 // accumulators, and the polynomial-exponential regulator's exponent a few more registers.  The
 // float32 form of the two-point families holds 4 (at 5 it spills).
 constexpr int multi_waves(int fam, int prec, int reg, bool der) {
-    return der ? ((fam < 0 || fam == 3) ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_DER)
-               : ((fam < 0 || fam == 3) ? (reg == 1 ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_MULTI)
-                                        : ((reg == 1 || prec != 0) ? FRG_WAVES_PER_EU_MULTI
-                                                                   : FRG_WAVES_PER_EU_BATCH));
+    return der ? ((fam < 0 || fam == 3 || fam == 6) ? FRG_WAVES_PER_EU_DER3
+                                                    : FRG_WAVES_PER_EU_DER)
+               : ((fam < 0 || fam == 3 || fam == 6)
+                      ? (reg == 1 ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_MULTI)
+                      : ((reg == 1 || prec != 0) ? FRG_WAVES_PER_EU_MULTI
+                                                 : FRG_WAVES_PER_EU_BATCH));
 }
 
 template <int FAM, int PREC, int REG, bool DER>
@@ -1521,6 +1546,7 @@ static multi_fn multi_variant(int fam, int prec, int reg, int der) {
     if (fam == 2) return multi_for_family<2>(prec, reg, der);
     if (fam == 3) return multi_for_family<3>(prec, reg, der);
     if (fam == 5) return multi_for_family<5>(prec, reg, der);
+    if (fam == 6) return der ? multi_for_reg<6, true>(reg) : multi_for_reg<6, false>(reg);
     return der ? multi_kernel<-1, -1, -1, true> : multi_kernel<-1, -1, -1, false>;
 }
 

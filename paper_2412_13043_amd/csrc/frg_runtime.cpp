@@ -97,7 +97,10 @@ frg_integral_desc plan_desc(const frg_integral_desc &d) {
     if (!is_ft(d.family)) return p;
     FreqRule f;
     if (freq_rule(d, &f) != FRG_OK) return p;
-    p.family = d.family == FRG_FAMILY_LPA_T ? FRG_FAMILY_LPA : FRG_FAMILY_TWO_POINT;
+    p.family = d.family == FRG_FAMILY_LPA_T
+                   ? FRG_FAMILY_LPA
+                   : (d.family == FRG_FAMILY_THREE_POINT_T ? FRG_FAMILY_THREE_POINT
+                                                           : FRG_FAMILY_TWO_POINT);
     p.n_q = d.n_q * f.n_f;
     return p;
 }
@@ -113,9 +116,10 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
         set_error("null descriptor or batch");
         return FRG_E_INVAL;
     }
-    if (d->family < 1 || d->family > 5) {
+    if (d->family < 1 || d->family > 6) {
         set_error("family must be 1 (LPA), 2 (two-point), 3 (three-point), 4 (LPA at finite "
-                  "temperature) or 5 (two-point at finite temperature), got %d", d->family);
+                  "temperature), 5 (two-point at finite temperature) or 6 (three-point at finite "
+                  "temperature), got %d", d->family);
         return FRG_E_INVAL;
     }
     if (d->precision != FRG_FP64 && d->precision != FRG_FP32_KAHAN) {
@@ -148,7 +152,7 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
         set_error("n_x must be in [1, %d], got %d", FRG_MAX_NODES, d->n_x);
         return FRG_E_INVAL;
     }
-    if (d->family == 3 && (d->n_phi < 1 || d->n_phi > FRG_MAX_NODES)) {
+    if (has_phi(d->family) && (d->n_phi < 1 || d->n_phi > FRG_MAX_NODES)) {
         set_error("n_phi must be in [1, %d], got %d", FRG_MAX_NODES, d->n_phi);
         return FRG_E_INVAL;
     }
@@ -178,10 +182,15 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
         set_error("dout_dm2 (the mass derivative) is implemented in float64 only");
         return FRG_E_UNSUPPORTED;
     }
+    if (d->family == FRG_FAMILY_THREE_POINT_T && d->precision != FRG_FP64) {
+        set_error("family 6 (three-point at finite temperature) is implemented in float64 only");
+        return FRG_E_UNSUPPORTED;
+    }
     if (b->dout_dz) {
-        if (!is_vertex(d->family) || d->precision != FRG_FP64) {
+        if (!is_vertex(d->family) || d->family == FRG_FAMILY_THREE_POINT_T ||
+            d->precision != FRG_FP64) {
             set_error("dout_dz (derivatives in the dressing-table entries) is implemented for "
-                      "the vertex families (2, 3, 5) in float64 only");
+                      "the vertex families 2, 3 and 5 in float64 only");
             return FRG_E_UNSUPPORTED;
         }
         if (!b->Z.values) {
@@ -279,7 +288,7 @@ static frg_status get_cos1(frg_context *ctx, int n, AngleRule *out, bool plain =
         float *xf = (float *)(xs + n), *xwf = xf + n, *xsf = xwf + n;
         FRG_HIP_CHECK(launch_rules(0, 1.0, 1, n, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
                                    nullptr, x, xw, xs, xf, xwf, xsf, nullptr, nullptr, nullptr,
-                                   nullptr, ctx->aux, plain));
+                                   nullptr, ctx->aux, plain ? kPlainCos1 : 0));
         FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
         e->rule = AngleRule{x, xw, xs, xf, xwf, xsf};
         it = ctx->cos1.emplace(key, std::move(e)).first;
@@ -335,8 +344,9 @@ static frg_status get_ft_radial(frg_context *ctx, const frg_integral_desc &d, co
     return FRG_OK;
 }
 
-static frg_status get_phi(frg_context *ctx, int n, PhiRule *out) {
-    auto it = ctx->phi.find(n);
+static frg_status get_phi(frg_context *ctx, int n, PhiRule *out, bool plain = false) {
+    const int key = n + (plain ? (1 << 20) : 0);
+    auto it = ctx->phi.find(key);
     if (it == ctx->phi.end()) {
         auto e = std::make_unique<PhiEntry>();
         FRG_HIP_CHECK(e->buf.alloc((size_t)n * (2 * sizeof(double) + 2 * sizeof(float)) + 64));
@@ -344,10 +354,10 @@ static frg_status get_phi(frg_context *ctx, int n, PhiRule *out) {
         float *cf = (float *)(w + n), *wf = cf + n;
         FRG_HIP_CHECK(launch_rules(0, 1.0, 1, 0, n, nullptr, nullptr, nullptr, nullptr, nullptr,
                                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c,
-                                   w, cf, wf, ctx->aux));
+                                   w, cf, wf, ctx->aux, plain ? kPlainPhi : 0));
         FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
         e->rule = PhiRule{c, w, cf, wf};
-        it = ctx->phi.emplace(n, std::move(e)).first;
+        it = ctx->phi.emplace(key, std::move(e)).first;
     }
     *out = it->second->rule;
     return FRG_OK;
@@ -381,12 +391,12 @@ bool cached_rules(frg_context *ctx, const frg_integral_desc &d, RadialRule *rad,
         *rad = it->second->rule;
     }
     if (is_vertex(d.family)) {
-        auto it = ctx->cos1.find(d.n_x + (d.family == FRG_FAMILY_TWO_POINT_T ? (1 << 20) : 0));
+        auto it = ctx->cos1.find(d.n_x + (is_ft(d.family) ? (1 << 20) : 0));
         if (it == ctx->cos1.end()) return false;
         *ang = it->second->rule;
     }
-    if (d.family == FRG_FAMILY_THREE_POINT) {
-        auto it = ctx->phi.find(d.n_phi);
+    if (has_phi(d.family)) {
+        auto it = ctx->phi.find(d.n_phi + (is_ft(d.family) ? (1 << 20) : 0));
         if (it == ctx->phi.end()) return false;
         *phi = it->second->rule;
     }
@@ -401,7 +411,7 @@ size_t rules_bytes(const frg_integral_desc &d) {
         b += up256(ft_rule_bytes(d.n_q, f.n_f));
     }
     if (is_vertex(d.family)) b += up256(cos1_rule_bytes(d.n_x));
-    if (d.family == FRG_FAMILY_THREE_POINT) b += up256(phi_rule_bytes(d.n_phi));
+    if (has_phi(d.family)) b += up256(phi_rule_bytes(d.n_phi));
     return b;
 }
 
@@ -438,17 +448,17 @@ frg_status rules_into(frg_context *ctx, const frg_integral_desc &d, void *buf, s
         float *xf = (float *)(xs + m), *xwf = xf + m, *xsf = xwf + m;
         FRG_HIP_CHECK(launch_rules(0, 1.0, 1, m, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
                                    nullptr, x, xw, xs, xf, xwf, xsf, nullptr, nullptr, nullptr,
-                                   nullptr, s, d.family == FRG_FAMILY_TWO_POINT_T));
+                                   nullptr, s, is_ft(d.family) ? kPlainCos1 : 0));
         *ang = AngleRule{x, xw, xs, xf, xwf, xsf};
         p += up256(cos1_rule_bytes(m));
     }
-    if (d.family == FRG_FAMILY_THREE_POINT) {
+    if (has_phi(d.family)) {
         const int m = d.n_phi;
         double *c = (double *)p, *w = c + m;
         float *cf = (float *)(w + m), *wf = cf + m;
         FRG_HIP_CHECK(launch_rules(0, 1.0, 1, 0, m, nullptr, nullptr, nullptr, nullptr, nullptr,
                                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                   c, w, cf, wf, s));
+                                   c, w, cf, wf, s, is_ft(d.family) ? kPlainPhi : 0));
         *phi = PhiRule{c, w, cf, wf};
     }
     return FRG_OK;
@@ -648,7 +658,7 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
     r.d = d.d;
     r.n_q = is_ft(d.family) ? d.n_q * fr.n_f : d.n_q;
     r.n_x = vertex ? d.n_x : 0;
-    r.n_phi = d.family == 3 ? d.n_phi : 0;
+    r.n_phi = has_phi(d.family) ? d.n_phi : 0;
     r.precision = d.precision;
     r.n_ext = b.n_ext;
     r.lq_log2 = lpa ? 0 : shape.lq_log2;
@@ -668,8 +678,10 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
         omega = 2.0 * pi / std::pow(2.0 * pi, 4);
     else if (d.family == FRG_FAMILY_LPA_T)
         omega = 4.0 * pi / std::pow(2.0 * pi, 3);  // int d^3q/(2pi)^3, radial
-    else
+    else if (d.family == FRG_FAMILY_TWO_POINT_T)
         omega = 2.0 * pi / std::pow(2.0 * pi, 3);  // int d^3q/(2pi)^3 = 2pi int q^2 dq dx/(2pi)^3
+    else
+        omega = 2.0 / std::pow(2.0 * pi, 3);  // = int q^2 dq dx dphi/(2pi)^3, phi over [0, pi] x 2
     // vacuum: k^(d+2) from the k-scaled nodes, weights and Rdot; finite temperature: k^5 from the
     // spatial part and one k from the frequency weights, which the rule holds as c_j/k
     r.pref = omega * std::pow(d.k, d.d + 2) * coef;
@@ -709,14 +721,14 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
         if (ang)
             r.ang = *ang;
         else
-            st = get_cos1(ctx, d.n_x, &r.ang, d.family == FRG_FAMILY_TWO_POINT_T);
+            st = get_cos1(ctx, d.n_x, &r.ang, is_ft(d.family));
         if (st != FRG_OK) return st;
     }
-    if (d.family == 3) {
+    if (has_phi(d.family)) {
         if (phi)
             r.phi = *phi;
         else
-            st = get_phi(ctx, d.n_phi, &r.phi);
+            st = get_phi(ctx, d.n_phi, &r.phi, is_ft(d.family));
         if (st != FRG_OK) return st;
     }
     r.logt = (const double2 *)ctx->logtab.ptr;
@@ -787,7 +799,7 @@ std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out,
         int lq = 1 << r.lq_log2;
         double inner = r.family == 1 ? 1.0
                                      : std::ceil((double)r.n_x / (1 << r.lx_log2)) *
-                                           (r.family == 3 ? r.n_phi : 1);
+                                           (has_phi(r.family) ? r.n_phi : 1);
         const int et0 = et_ranges ? (*et_ranges)[i].first : 0;
         const int et1 = et_ranges ? (*et_ranges)[i].second : r.ext_tiles;
         for (int et = et0; et < et1; ++et)

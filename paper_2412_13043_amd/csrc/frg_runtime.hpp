@@ -93,7 +93,7 @@ struct Scratch {
 struct TileShape {
     int lq_log2 = 0;  // lanes per point over radial nodes (log2)
     int chunks = 1;   // radial chunks (separate workgroups) per external tile
-    int lx_log2 = 0;  // lanes per point over cos1 nodes (log2; families 2 and 3)
+    int lx_log2 = 0;  // lanes per point over cos1 nodes (log2; vertex families)
 };
 
 struct FlowGraph;
@@ -101,12 +101,20 @@ struct FlowGraph;
 // Families by what they read: vertex families take external momenta and a dressing table.
 inline bool is_vertex(int fam) {
     return fam == FRG_FAMILY_TWO_POINT || fam == FRG_FAMILY_THREE_POINT ||
-           fam == FRG_FAMILY_TWO_POINT_T;
+           fam == FRG_FAMILY_TWO_POINT_T || fam == FRG_FAMILY_THREE_POINT_T;
 }
-inline bool is_ft(int fam) { return fam == FRG_FAMILY_LPA_T || fam == FRG_FAMILY_TWO_POINT_T; }
+inline bool is_ft(int fam) {
+    return fam == FRG_FAMILY_LPA_T || fam == FRG_FAMILY_TWO_POINT_T ||
+           fam == FRG_FAMILY_THREE_POINT_T;
+}
 inline bool is_lpa(int fam) { return fam == FRG_FAMILY_LPA || fam == FRG_FAMILY_LPA_T; }
+// three-point families: a phi rule next to the cos1 rule
+inline bool has_phi(int fam) {
+    return fam == FRG_FAMILY_THREE_POINT || fam == FRG_FAMILY_THREE_POINT_T;
+}
 // doubles of the ext array for n points
 inline long long ext_values(int fam, long long n) {
+    if (fam == FRG_FAMILY_THREE_POINT_T) return 4 * n;
     if (fam == FRG_FAMILY_THREE_POINT || fam == FRG_FAMILY_TWO_POINT_T) return 2 * n;
     return fam == FRG_FAMILY_TWO_POINT ? n : 0;
 }

@@ -33,7 +33,7 @@ FRG_OK, FRG_E_INVAL, FRG_E_NOMEM, FRG_E_DEVICE, FRG_E_NOTREADY, FRG_E_TIMEOUT, \
     FRG_E_CANCELLED, FRG_E_UNSUPPORTED = range(8)
 FRG_FP64, FRG_FP32_KAHAN = 0, 1
 FRG_FAMILY_LPA, FRG_FAMILY_TWO_POINT, FRG_FAMILY_THREE_POINT = 1, 2, 3
-FRG_FAMILY_LPA_T, FRG_FAMILY_TWO_POINT_T = 4, 5
+FRG_FAMILY_LPA_T, FRG_FAMILY_TWO_POINT_T, FRG_FAMILY_THREE_POINT_T = 4, 5, 6
 FRG_BOSONIC, FRG_FERMIONIC = 0, 1
 FRG_REG_EXPONENTIAL, FRG_REG_POLY_EXP, FRG_REG_FLAT = 0, 1, 2
 FRG_MAX_NODES = 1024
@@ -389,7 +389,7 @@ def make_desc(family: int, n_q: int, q_max: float, *, n_x: int = 0, n_phi: int =
               n_tail: int = 0, freq_scaled: bool = False, regulator: int = FRG_REG_EXPONENTIAL,
               reg_order: int = 0):
     """Descriptor; T, freq_max, statistics, n_tail and freq_scaled apply to the finite-temperature
-    families (4, 5) only; regulator and reg_order to every family."""
+    families (4, 5, 6) only; regulator and reg_order to every family."""
     if d == 0:
         d = 3 if family == FRG_FAMILY_LPA else 4
     return frg_integral_desc(family, d, n_q, n_x, n_phi, precision, q_max, k, near_pole_tau,

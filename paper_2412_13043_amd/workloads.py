@@ -176,6 +176,22 @@ def two_point_ft_batch(B: int = 16, seed_base: int = 1000):
     return p, p0, TWO_M2, Z
 
 
+def three_point_ft_batch(B: int = 2, seed_m2_base: int = 500, seed_z_base: int = 1000):
+    """The three-point workload's external pairs at the finite-temperature settings: (p, alpha)
+    as three_point_ext (1024 pairs), leg frequencies p01 = 2 pi T for odd e and 0 otherwise, p02 =
+    -2 pi T for e = 2, 3 mod 4 and 0 otherwise (l1 = q + p1 and l2 = q - p2 with bosonic
+    external frequencies 0 or 2 pi T: every combination), m2 ~ U[0.1, 2] and Z per right-hand
+    side (seeds 500+b, 1000+b)."""
+    P, A = three_point_ext()
+    e = np.arange(P.size)
+    p01 = np.where(e % 2 == 1, 2.0 * math.pi * FT_T, 0.0)
+    p02 = np.where((e // 2) % 2 == 1, -2.0 * math.pi * FT_T, 0.0)
+    m2 = np.stack([np.random.default_rng(seed_m2_base + b).uniform(0.1, 2.0, P.size)
+                   for b in range(B)])
+    Z = np.stack([dressing_table(seed_z_base + b) for b in range(B)])
+    return P, A, p01, p02, m2, Z
+
+
 # ------------------------------------------------------------------------------------------
 # Workload 5: serving mix of many concurrent time-steppers
 # ------------------------------------------------------------------------------------------

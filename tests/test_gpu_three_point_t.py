@@ -1,0 +1,371 @@
+"""GPU parity of the three-point family at finite temperature (family 6: Matsubara sum x radial x
+cos1 x phi in d = 3 + 1, each inner leg with its own external frequency) against the FP64
+oracle, through the C ABI.
+
+Bar as for the other families: 1e-12 relative per external point for the value and its mass
+derivative, bitwise equality across tile shapes, fused launches (the family's own instance and
+the general kernel), flow right-hand sides and sessions; the float32 form and the dressing
+derivatives are refused with FRG_E_UNSUPPORTED.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_13043_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2412_13043_amd import frg
+
+    ctx = frg.Context(0)
+    yield frg, ctx, torch
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _d(torch, a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), dtype=torch.float64,
+                        device="cuda")
+
+
+def _rel(got, ref):
+    return float(np.max(np.abs(got - ref) / np.abs(ref)))
+
+
+def _okind(reg):
+    return {0: oracle.REG_EXP, 1: oracle.reg_polyexp(8), 2: oracle.REG_LITIM}[reg]
+
+
+def _run(env, desc, n, *, ext=None, m2=None, m2_scalar=0.0, Z=None, der=False, ctx=None):
+    frg, ctx0, torch = env
+    out = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    dout = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda") if der else None
+    (ctx or ctx0).integrate(desc, out, ext=None if ext is None else _d(torch, ext),
+                            m2=None if m2 is None else _d(torch, m2), m2_scalar=m2_scalar,
+                            Z=None if Z is None else _d(torch, Z), x_min=wl.Z_XMIN,
+                            x_max=wl.Z_XMAX, dout=dout)
+    torch.cuda.synchronize()
+    if der:
+        return out.cpu().numpy(), dout.cpu().numpy()
+    return out.cpu().numpy()
+
+
+def _points(rng, n, T, stat):
+    """Momenta log-uniform over 5 decades, alpha in [0, pi], and leg frequencies: bosonic
+    2 pi T m (m in -2..2) per leg, fermionic the paper's soft p0f = pi T exp(-1/(pi T)) with a
+    random sign."""
+    p = 10 ** rng.uniform(-3, 2, n)
+    alpha = rng.uniform(0.0, math.pi, n)
+    if stat == 0:
+        p01 = 2 * math.pi * T * rng.integers(-2, 3, n)
+        p02 = 2 * math.pi * T * rng.integers(-2, 3, n)
+    else:
+        soft = math.pi * T * math.exp(-1.0 / (math.pi * T))
+        p01 = soft * rng.choice([-1.0, 1.0], n)
+        p02 = soft * rng.choice([-1.0, 1.0], n)
+    return p, alpha, p01, p02
+
+
+def _oracle(desc, ext, **kw):
+    return oracle.integrate_ft(oracle.THREE_POINT_T, desc.n_q, desc.q_max, n_x=desc.n_x,
+                               n_phi=desc.n_phi, k=desc.k, T=desc.T, statistics=desc.statistics,
+                               freq_max=desc.freq_max, freq_scaled=bool(desc.freq_scaled),
+                               n_tail=desc.n_tail, regulator=_okind(desc.regulator), ext=ext,
+                               **kw)
+
+
+@pytest.mark.parametrize("stat", [0, 1])
+@pytest.mark.parametrize("n_ext,n_q,n_x,n_phi,T,lam,n_tail,useZ,reg", [
+    (37, 9, 6, 5, 0.2, 6.0, 4, True, 0),     # ragged external tile, cos1 and phi rounds
+    (1, 1, 1, 1, 1.0, 7.0, 0, False, 0),     # smallest: one point, one node per dimension
+    (70, 12, 8, 7, 0.05, 2.0, 6, True, 1),   # many frequencies, the polynomial-exponential s_8
+    (64, 16, 9, 4, 0.3, 5.0, 2, True, 2),    # the flat regulator
+])
+def test_three_point_ft_parity(env, stat, n_ext, n_q, n_x, n_phi, T, lam, n_tail, useZ, reg):
+    frg = env[0]
+    rng = np.random.default_rng(300 + n_ext + stat)
+    p, alpha, p01, p02 = _points(rng, n_ext, T, stat)
+    m2 = rng.uniform(-0.4, 2.0, n_ext)
+    Z = wl.dressing_table(9) if useZ else None
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, n_q, 10.0, n_x=n_x, n_phi=n_phi, T=T,
+                         freq_max=lam, statistics=stat, n_tail=n_tail, regulator=reg)
+    got = _run(env, desc, n_ext, ext=np.concatenate([p, alpha, p01, p02]), m2=m2, Z=Z)
+    ref = _oracle(desc, (p, alpha, p01, p02), m2=m2, Z=Z)
+    assert _rel(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("stat,k,scaled", [(0, 1.7, True), (1, 0.45, False)])
+def test_three_point_ft_scale_and_scaled_domain(env, stat, k, scaled):
+    frg = env[0]
+    rng = np.random.default_rng(400 + stat)
+    n = 29
+    T = 0.15 * k
+    p, alpha, p01, p02 = _points(rng, n, T, stat)
+    p = p * k
+    m2 = rng.uniform(-0.3, 1.5, n) * k * k
+    Z = wl.dressing_table(11)
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 14, 8.0, n_x=7, n_phi=6, k=k, T=T,
+                         statistics=stat, freq_max=5.0 if scaled else 5.0 * k, n_tail=5,
+                         freq_scaled=scaled)
+    got = _run(env, desc, n, ext=np.concatenate([p, alpha, p01, p02]), m2=m2, Z=Z)
+    ref = _oracle(desc, (p, alpha, p01, p02), m2=m2, Z=Z)
+    assert _rel(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("reg", [0, 1, 2])
+def test_three_point_ft_mass_derivative(env, reg):
+    frg = env[0]
+    rng = np.random.default_rng(500 + reg)
+    n = 41
+    T = 0.2
+    p, alpha, p01, p02 = _points(rng, n, T, reg % 2)
+    m2 = rng.uniform(-0.3, 1.5, n)
+    Z = wl.dressing_table(8)
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 10, 10.0, n_x=6, n_phi=5, T=T,
+                         freq_max=5.0, statistics=reg % 2, n_tail=3, regulator=reg)
+    ext = np.concatenate([p, alpha, p01, p02])
+    val0 = _run(env, desc, n, ext=ext, m2=m2, Z=Z)
+    val, dv = _run(env, desc, n, ext=ext, m2=m2, Z=Z, der=True)
+    assert np.array_equal(val, val0)  # the value does not change
+    ref = _oracle(desc, (p, alpha, p01, p02), m2=m2, Z=Z, dm2=True)
+    assert _rel(dv, ref) <= TOL
+
+
+def test_three_point_ft_equal_leg_frequencies_and_zero_momentum(env):
+    # p = 0: both inner legs are the radial momentum; with p01 = p02 = 0 the integral is
+    # T sum_j int d^3q/(2pi)^3 Rdot G_j(q)^4, which the oracle gives for any alpha
+    frg = env[0]
+    n = 5
+    alpha = np.linspace(0.0, math.pi, n)
+    p = np.zeros(n)
+    z = np.zeros(n)
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 16, 8.0, n_x=4, n_phi=3, T=0.25,
+                         freq_max=4.0, n_tail=3)
+    got = _run(env, desc, n, ext=np.concatenate([p, alpha, z, z]), m2_scalar=0.3)
+    assert np.all(got == got[0])  # alpha does not enter at p = 0
+    ref = _oracle(desc, (p, alpha, z, z), m2_scalar=0.3)
+    assert _rel(got, ref) <= TOL
+
+
+def test_three_point_ft_tile_shapes_give_identical_bits(env, tmp_path, monkeypatch):
+    # the tile shape is looked up under the vacuum key (family 3, n_q n_f radial nodes)
+    frg, _, torch = env
+    n_q, n_x, n_phi, n = 5, 6, 4, 37
+    kw = dict(T=0.3, freq_max=4.0, statistics=1, n_tail=2)
+    n_f = len(oracle.matsubara_rule(1, 0.3, 4.0, 2)[0])
+    rng = np.random.default_rng(77)
+    p, alpha, p01, p02 = _points(rng, n, 0.3, 1)
+    ext = np.concatenate([p, alpha, p01, p02])
+    m2 = rng.uniform(-0.3, 2.0, n)
+    Z = wl.dressing_table(7)
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, n_q, 10.0, n_x=n_x, n_phi=n_phi, **kw)
+    target = 16 * torch.cuda.get_device_properties(0).multi_processor_count
+    nq_eff = n_q * n_f
+    shapes = [(0, 1, 0), (0, 7, 0), (2, 1, 0), (3, 2, 0), (6, 1, 0), (0, 1, 2), (2, 1, 3),
+              (1, 4, 2)]
+    results = []
+    for lq, ch, lx in shapes:
+        cache = tmp_path / f"ft3_{lq}_{ch}_{lx}.txt"
+        cache.write_text(f"3 0 {nq_eff} {n_x} {n_phi} {n} {target} {lq} {ch} {lx}\n")
+        monkeypatch.setenv("FRG_AUTOTUNE_CACHE", str(cache))
+        ctx = frg.Context(0)
+        try:
+            results.append(_run(env, desc, n, ext=ext, m2=m2, Z=Z, der=True, ctx=ctx))
+        finally:
+            torch.cuda.synchronize()
+            ctx.close()
+    for (o, dv), shape in zip(results[1:], shapes[1:]):
+        assert np.array_equal(o, results[0][0]), shape
+        assert np.array_equal(dv, results[0][1]), shape
+    ref = _oracle(desc, (p, alpha, p01, p02), m2=m2, Z=Z)
+    assert _rel(results[0][0], ref) <= TOL
+
+
+def test_three_point_ft_fused_launches_bitwise(env):
+    """Family 6 in a fused launch of its own (its specialised instance) and mixed with the
+    vacuum three-point, the finite-temperature two-point and an LPA request (the general
+    kernel), with and without the mass derivative: every result the bits of the request
+    evaluated alone."""
+    frg, ctx, torch = env
+    rng = np.random.default_rng(21)
+    n = 50
+    T = 0.2
+    p, alpha, p01, p02 = _points(rng, n, T, 0)
+    Z = wl.dressing_table(4)
+    m2 = rng.uniform(-0.3, 1.5, n)
+    d6 = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 8, 10.0, n_x=6, n_phi=4, T=T, freq_max=6.0,
+                       n_tail=4)
+    d6b = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 6, 10.0, n_x=5, n_phi=3, T=0.1,
+                        freq_max=3.0, statistics=1, n_tail=2, regulator=1)
+    e6 = np.concatenate([p, alpha, p01, p02])
+    mixes = [
+        [(d6, e6, True), (d6b, e6, False)],
+        [(d6, e6, False),
+         (frg.make_desc(frg.FRG_FAMILY_THREE_POINT, 6, 10.0, n_x=4, n_phi=3),
+          np.concatenate([p, alpha]), True),
+         (frg.make_desc(frg.FRG_FAMILY_TWO_POINT_T, 16, 10.0, n_x=8, T=0.2, freq_max=6.0,
+                        n_tail=4), np.concatenate([p, p01]), False),
+         (frg.make_desc(frg.FRG_FAMILY_LPA, 32, 6.0), None, True),
+         (d6b, e6, True)],
+    ]
+    for cases in mixes:
+        alone = [_run(env, d, n, ext=e, m2=m2, Z=Z, der=w) for d, e, w in cases]
+        outs = [torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+                for _ in cases]
+        douts = [torch.full((n,), float("nan"), dtype=torch.float64, device="cuda") if w
+                 else None for _, _, w in cases]
+        keep = [(_d(torch, e) if e is not None else None) for _, e, _ in cases]
+        tm, tz = _d(torch, m2), _d(torch, Z)
+        batches = [frg.make_batch(n, o, ext=k, m2=tm, Z=tz, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
+                                  dout=dd) for o, k, dd in zip(outs, keep, douts)]
+        for rep in range(2):
+            ctx.integrate_multi([d for d, _, _ in cases], batches)
+            torch.cuda.synchronize()
+            for i, (_, _, w) in enumerate(cases):
+                a = alone[i][0] if w else alone[i]
+                assert np.array_equal(outs[i].cpu().numpy(), a), (rep, i)
+                if w:
+                    assert np.array_equal(douts[i].cpu().numpy(), alone[i][1]), (rep, i)
+    ref = _oracle(d6, (p, alpha, p01, p02), m2=m2, Z=Z)
+    assert _rel(_run(env, d6, n, ext=e6, m2=m2, Z=Z), ref) <= TOL
+
+
+def test_three_point_ft_benchmark_batch_sampled(env):
+    # the finite-temperature three-point batch (2 right-hand sides x 1024 pairs x 47 frequencies
+    # x 64 x 32 x 16), sampled points against the oracle
+    frg, ctx, torch = env
+    P, A, p01, p02, m2, Z = wl.three_point_ft_batch()
+    B = Z.shape[0]
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, wl.THREE_NQ, wl.THREE_QMAX,
+                         n_x=wl.THREE_NX, n_phi=wl.THREE_NPHI, T=wl.FT_T,
+                         freq_max=wl.FT_FREQ_MAX, n_tail=wl.FT_N_TAIL)
+    te = _d(torch, np.concatenate([P, A, p01, p02]))
+    tm, tZ = _d(torch, m2), _d(torch, Z)
+    out = torch.full((B, P.size), float("nan"), dtype=torch.float64, device="cuda")
+    batches = [frg.make_batch(P.size, out[b], ext=te, m2=tm[b], Z=tZ[b], x_min=wl.Z_XMIN,
+                              x_max=wl.Z_XMAX) for b in range(B)]
+    ctx.integrate_multi([desc] * B, batches)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert np.all(np.isfinite(got)) and np.all(got > 0)
+    rng = np.random.default_rng(0)
+    for b in range(B):
+        idx = np.sort(rng.choice(P.size, 4, replace=False))
+        idx[0] = 0
+        idx[-1] = P.size - 1
+        ref = _oracle(desc, (P[idx], A[idx], p01[idx], p02[idx]), m2=m2[b, idx], Z=Z[b])
+        assert _rel(got[b, idx], ref) <= TOL
+
+
+def test_flow_rhs_three_point_finite_temperature(env):
+    frg, ctx, torch = env
+    rng = np.random.default_rng(8)
+    n = 40
+    T = 0.2
+    p, alpha, p01, p02 = _points(rng, n, T, 0)
+    grid = np.concatenate([p, alpha, p01, p02])
+    Z = wl.dressing_table(6)
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 8, 10.0, n_x=6, n_phi=4, T=T,
+                         freq_max=5.0, n_tail=3)
+    tgrid, tZ = _d(torch, grid), _d(torch, Z)
+    state = _d(torch, rng.uniform(-1.2, 2.0, n))
+    out = torch.empty_like(state)
+    for rep in range(2):
+        s = state.cpu().numpy()
+        ctx.flow_rhs(desc, state, tgrid, out, Z=tZ, m2_floor=-0.5, coef=0.5)
+        torch.cuda.synchronize()
+        ref = _oracle(desc, (p, alpha, p01, p02), m2=np.maximum(s, -0.5), Z=Z)
+        assert _rel(out.cpu().numpy(), 0.5 * ref) <= TOL
+        state.mul_(0.9).add_(0.05)
+
+
+def test_session_serves_three_point_ft(env):
+    """Family 6 through a session (host buffers): a request above one launch's node budget
+    (split into parts), one with the mass derivative, and vacuum requests beside them; every
+    result the bits of the request evaluated alone."""
+    frg, ctx, torch = env
+    rng = np.random.default_rng(31)
+    P, A, p01, p02, m2b, Zb = wl.three_point_ft_batch(1)
+    # 1024 pairs x 32 radial x 47 frequencies x 16 x 16 = 3.9e8 nodes: evaluated in parts
+    big = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 32, wl.THREE_QMAX, n_x=16, n_phi=16,
+                        T=wl.FT_T, freq_max=wl.FT_FREQ_MAX, n_tail=wl.FT_N_TAIL)
+    small = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 9, 10.0, n_x=6, n_phi=5, T=0.3,
+                          freq_max=4.0, statistics=1, n_tail=2)
+    n = 60
+    ps, als, q1, q2 = _points(rng, n, 0.3, 1)
+    reqs = [
+        dict(desc=big, n=P.size, ext=np.concatenate([P, A, p01, p02]), m2=m2b[0], Z=Zb[0],
+             der=False),
+        dict(desc=small, n=n, ext=np.concatenate([ps, als, q1, q2]),
+             m2=rng.uniform(0.05, 2.0, n), Z=wl.dressing_table(70), der=True),
+        dict(desc=frg.make_desc(frg.FRG_FAMILY_THREE_POINT, 8, 10.0, n_x=5, n_phi=4), n=n,
+             ext=np.concatenate([ps, als]), m2=rng.uniform(0.05, 2.0, n),
+             Z=wl.dressing_table(71), der=False),
+    ]
+    for r in reqs:
+        r["out"] = np.full(r["n"], np.nan)
+        r["dout"] = np.full(r["n"], np.nan) if r["der"] else None
+    s = frg.frg_session_open(ctx.handle, frg.frg_session_config(3, 256 << 20, 20, 0))
+    tickets = []
+    for r in reqs:
+        zt = frg.frg_log_table(r["Z"].ctypes.data, r["Z"].size, wl.Z_XMIN, wl.Z_XMAX)
+        b = frg.frg_batch(r["n"], r["ext"].ctypes.data, r["m2"].ctypes.data, 0.0, zt,
+                          r["out"].ctypes.data, None,
+                          None if r["dout"] is None else r["dout"].ctypes.data)
+        tickets.append(frg.frg_session_submit(s, r["desc"], b, -1))
+    for t in tickets:
+        assert frg.frg_session_wait(s, t, 120000) == frg.FRG_OK
+    frg.frg_session_close(s)
+    for r in reqs:
+        alone = _run(env, r["desc"], r["n"], ext=r["ext"], m2=r["m2"], Z=r["Z"], der=r["der"])
+        if r["der"]:
+            assert np.array_equal(r["out"], alone[0])
+            assert np.array_equal(r["dout"], alone[1])
+        else:
+            assert np.array_equal(r["out"], alone)
+    r = reqs[1]
+    ref = _oracle(small, (ps, als, q1, q2), m2=r["m2"], Z=r["Z"])
+    assert _rel(r["out"], ref) <= TOL
+
+
+def test_three_point_ft_rejections(env):
+    frg, ctx, torch = env
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ext = torch.ones(16, dtype=torch.float64, device="cuda")
+    Z = _d(torch, wl.dressing_table(3))
+    good = dict(n_x=4, n_phi=3, T=0.2, freq_max=3.0, n_tail=2)
+    # the float32 form is not implemented for this family
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 8, 6.0, precision=1, near_pole_tau=0.1,
+                         **good)
+    with pytest.raises(frg.FrgError) as ei:
+        ctx.integrate(desc, out, ext=ext, m2_scalar=0.5)
+    assert ei.value.status == frg.FRG_E_UNSUPPORTED
+    # nor the dressing derivatives
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 8, 6.0, **good)
+    dz = torch.zeros(4 * Z.numel(), dtype=torch.float64, device="cuda")
+    with pytest.raises(frg.FrgError) as ei:
+        ctx.integrate(desc, out, ext=ext, m2_scalar=0.5, Z=Z, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
+                      dz=dz)
+    assert ei.value.status == frg.FRG_E_UNSUPPORTED
+    # n_phi out of range, no ext, a bad frequency rule
+    for kw in [dict(n_phi=0), dict(n_phi=frg.FRG_MAX_NODES + 1), dict(T=0.0)]:
+        args = dict(good)
+        args.update(kw)
+        desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 8, 6.0, **args)
+        with pytest.raises(frg.FrgError) as ei:
+            ctx.integrate(desc, out, ext=ext, m2_scalar=0.5)
+        assert ei.value.status == frg.FRG_E_INVAL, kw
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 8, 6.0, **good)
+    with pytest.raises(frg.FrgError):
+        ctx.integrate(desc, out, m2_scalar=0.5)
+    # n_ext = 0 is a no-op
+    empty = torch.zeros(0, dtype=torch.float64, device="cuda")
+    ctx.integrate(desc, empty, ext=ext, m2_scalar=0.5)
