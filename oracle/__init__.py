@@ -90,6 +90,8 @@ def _load():
                                                     I, D, D, I, I, P]
             lib.frgo_vertex_ft_spherical.argtypes = [I, I, I, D, D, I, I, D, D, I, I, P, P, D, D,
                                                      D, P, I, D, D, P]
+            lib.frgo_integrate_ft_complex.argtypes = [I, I, I, I, D, D, I, I, D, D, I, I, P, P,
+                                                      D, P, I, D, D, I, P]
             _lib = lib
     return _lib
 
@@ -208,6 +210,25 @@ def integrate_ft_dz(n_q, q_max, *, n_x, ext, Z, T, freq_max, statistics=BOSONIC,
     if rc != 0:
         raise ValueError(f"frgo_integrate_ft_dz rejected the arguments (rc={rc})")
     return out
+
+
+def integrate_ft_complex(family, n_q, q_max, *, T, statistics=BOSONIC, freq_max,
+                         freq_scaled=False, n_tail=0, n_x, n_phi=0, k=1.0, regulator=REG_EXP,
+                         ext, m2=None, m2_scalar=0.0, Z=None, x_min=1e-3, x_max=1e3):
+    """Finite-temperature two- and three-point integrals with complex external frequencies of
+    the inner legs; returns complex I_e.  ext: family TWO_POINT_T (p, p0r, p0i); THREE_POINT_T
+    (p, alpha, p01r, p02r, p01i, p02i), each an array of n_ext values."""
+    ext_arr = np.concatenate([_f64(e) for e in ext])
+    n = len(ext[0])
+    m2a, Za = _f64(m2), _f64(Z)
+    out = np.empty(2 * n)
+    rc = _load().frgo_integrate_ft_complex(
+        family, n_q, n_x, n_phi, q_max, k, regulator, statistics, T, freq_max,
+        1 if freq_scaled else 0, n_tail, _ptr(ext_arr), _ptr(m2a), m2_scalar, _ptr(Za),
+        0 if Za is None else len(Za), x_min, x_max, n, _ptr(out))
+    if rc != 0:
+        raise ValueError(f"frgo_integrate_ft_complex rejected the arguments (rc={rc})")
+    return out[:n] + 1j * out[n:]
 
 
 def vertex_hyperspherical(n_legs, n_q, n_t1, n_t2, n_t3, q_max, p1, p2, m2, *, k=1.0,

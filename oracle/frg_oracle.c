@@ -7,6 +7,7 @@
  */
 #include "frg_oracle.h"
 
+#include <complex.h>
 #include <math.h>
 #include <stddef.h>
 
@@ -655,6 +656,91 @@ int frgo_integrate_ft_three(int n_q, int n_x, int n_phi, double q_max, double k,
             }
         }
         out[e] = nsum_get(&total);
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* Complex external frequencies of the inner legs (families 5 and 6).                        */
+/* ---------------------------------------------------------------------------------------- */
+static double complex ft_prop_c(int regulator, const double *Z, int nZ, double x_min,
+                                double x_max, double l2, double complex w, double m2, double k) {
+    return 1.0 / (w * w + frgo_dressing(Z, nZ, x_min, x_max, l2) * l2 +
+                  frgo_regulator(regulator, l2, k) + m2);
+}
+
+int frgo_integrate_ft_complex(int family, int n_q, int n_x, int n_phi, double q_max, double k,
+                              int regulator, int statistics, double T, double freq_max,
+                              int freq_scaled, int n_tail, const double *ext, const double *m2,
+                              double m2_scalar, const double *Z, int nZ, double x_min,
+                              double x_max, int n_ext, double *out) {
+    if (n_ext < 0 || out == NULL || ext == NULL) return -1;
+    if (family != FRGO_TWO_POINT_T && family != FRGO_THREE_POINT_T) return -1;
+    if (n_q < 1 || n_q > MAXN || n_x < 1 || n_x > MAXN) return -1;
+    if (family == FRGO_THREE_POINT_T && (n_phi < 1 || n_phi > MAXN)) return -1;
+    if (!(q_max > 0.0) || !(k > 0.0)) return -1;
+    if (Z != NULL && (nZ < 1 || !(x_min > 0.0) || !(x_max > x_min))) return -1;
+    static __thread double qn[MAXN], qw[MAXN], xn[MAXN], xw[MAXN], fn[MAXN], fw[MAXN],
+        mw[MAXN], mc[MAXN];
+    double lambda = freq_scaled ? freq_max * k : freq_max;
+    int n_f = frgo_matsubara_rule(statistics, T, lambda, n_tail, MAXN, mw, mc);
+    if (n_f < 0) return -1;
+    frgo_gauss_legendre(n_q, 0.0, q_max * k, qn, qw);
+    frgo_gauss_legendre(n_x, -1.0, 1.0, xn, xw);
+    int three = family == FRGO_THREE_POINT_T;
+    if (three) frgo_gauss_legendre(n_phi, 0.0, PI, fn, fw);
+    /* int d^3q/(2pi)^3: 2pi int q^2 dq dx (two-point), 2 int q^2 dq dx dphi, phi on [0, pi] */
+    double pref = (three ? 2.0 : 2.0 * PI) / pow(2.0 * PI, 3.0);
+    for (int e = 0; e < n_ext; ++e) {
+        double p = ext[e];
+        double ca = 1.0, sa = 0.0;
+        double complex s1, s2 = 0.0;
+        if (three) {
+            ca = cos(ext[n_ext + e]);
+            sa = sin(ext[n_ext + e]);
+            s1 = ext[2 * n_ext + e] + ext[4 * n_ext + e] * _Complex_I;
+            s2 = ext[3 * n_ext + e] + ext[5 * n_ext + e] * _Complex_I;
+        } else {
+            s1 = ext[n_ext + e] + ext[2 * n_ext + e] * _Complex_I;
+        }
+        double mass = m2 ? m2[e] : m2_scalar;
+        nsum tre = {0.0, 0.0}, tim = {0.0, 0.0};
+        for (int j = 0; j < n_f; ++j) {
+            double w = mw[j];
+            for (int a = 0; a < n_q; ++a) {
+                double q = qn[a], q2 = q * q;
+                double gq = ft_prop(regulator, Z, nZ, x_min, x_max, q2, w, mass, k);
+                double rad = mc[j] * pref * qw[a] * q2 * frgo_regulator_dot(regulator, q2, k) *
+                             gq * gq;
+                nsum mre = {0.0, 0.0}, mim = {0.0, 0.0};
+                for (int b = 0; b < n_x; ++b) {
+                    double x = xn[b], sx = sqrt(1.0 - x * x);
+                    double l1 = q2 + p * p + 2.0 * q * p * x;
+                    if (l1 < 0.0) l1 = 0.0;
+                    double complex h1 = ft_prop_c(regulator, Z, nZ, x_min, x_max, l1, w + s1,
+                                                  mass, k);
+                    if (!three) {
+                        double complex term = rad * xw[b] * h1;
+                        nsum_add(&mre, creal(term));
+                        nsum_add(&mim, cimag(term));
+                        continue;
+                    }
+                    for (int c = 0; c < n_phi; ++c) {
+                        double l2 = q2 + p * p - 2.0 * q * p * (x * ca + sx * cos(fn[c]) * sa);
+                        if (l2 < 0.0) l2 = 0.0;
+                        double complex h2 = ft_prop_c(regulator, Z, nZ, x_min, x_max, l2,
+                                                      w + s2, mass, k);
+                        double complex term = rad * xw[b] * fw[c] * h1 * h2;
+                        nsum_add(&mre, creal(term));
+                        nsum_add(&mim, cimag(term));
+                    }
+                }
+                nsum_add(&tre, nsum_get(&mre));
+                nsum_add(&tim, nsum_get(&mim));
+            }
+        }
+        out[e] = nsum_get(&tre);
+        out[n_ext + e] = nsum_get(&tim);
     }
     return 0;
 }

@@ -175,6 +175,23 @@ int frgo_vertex_ft_spherical(int n_q, int n_t1, int n_t2, double q_max, double k
                              double p02, double m2, const double *Z, int nZ, double x_min,
                              double x_max, double *out);
 
+/*
+ * Complex external frequencies (families 5 and 6): the external frequency of an inner leg is
+ * p0 = p0r + i p0i, as for the paper's external fermion legs at chemical potential mu, whose
+ * imaginary-time component is p0f - i mu (App. "Derivation of the four-Fermi system",
+ * MakeP0FormRule).  Every inner-leg propagator is continued analytically,
+ *   H(l) = 1/((w_j + p0)^2 + Z(l^2) l^2 + R(l^2) + m2)    (complex),
+ * the radial leg keeps its real frequency w_j; otherwise the integrals are those of
+ * frgo_integrate_ft (family 5) and frgo_integrate_ft_three (family 6).
+ * ext: family 5 p, p0r, p0i; family 6 p, alpha, p01r, p02r, p01i, p02i (each [n_ext]).
+ * out[e] = Re I_e and out[n_ext + e] = Im I_e.
+ */
+int frgo_integrate_ft_complex(int family, int n_q, int n_x, int n_phi, double q_max, double k,
+                              int regulator, int statistics, double T, double freq_max,
+                              int freq_scaled, int n_tail, const double *ext, const double *m2,
+                              double m2_scalar, const double *Z, int nZ, double x_min,
+                              double x_max, int n_ext, double *out);
+
 /* dI_e/dZ_i of the finite-temperature two-point integral (family 5), out[e * nZ + i], as
  * frgo_integrate_dz: the dressing multiplies the spatial momentum of both legs.  Arguments as
  * frgo_integrate_ft with family 5 implied; Z is required. */
