@@ -614,13 +614,16 @@ def workload_setup(torch, frg, wl, ctx, name):
             (tm, o1))
 
 
-def two_point_ft_setup(torch, frg, wl, B=16):
-    """The finite-temperature two-point batch, inputs resident in HBM."""
+def two_point_ft_setup(torch, frg, wl, B=16, mu=None):
+    """The finite-temperature two-point batch, inputs resident in HBM; mu: the inner leg's
+    frequency p0 - i mu (complex results, Re and Im per point)."""
     p, p0, m2, Z = wl.two_point_ft_batch(B)
     desc = frg.make_desc(frg.FRG_FAMILY_TWO_POINT_T, wl.FT_NQ, wl.FT_QMAX, n_x=wl.FT_NX,
-                         T=wl.FT_T, freq_max=wl.FT_FREQ_MAX, n_tail=wl.FT_N_TAIL)
-    te, tZ = _dev(torch, np.concatenate([p, p0])), _dev(torch, Z)
-    out = torch.empty((B, p.size), dtype=torch.float64, device="cuda")
+                         T=wl.FT_T, freq_max=wl.FT_FREQ_MAX, n_tail=wl.FT_N_TAIL,
+                         complex_freq=mu is not None)
+    ext = [p, p0] if mu is None else [p, p0, np.full(p.size, -mu)]
+    te, tZ = _dev(torch, np.concatenate(ext)), _dev(torch, Z)
+    out = torch.empty((B, p.size * (1 if mu is None else 2)), dtype=torch.float64, device="cuda")
     batches = [frg.make_batch(p.size, out[b], ext=te, m2_scalar=m2, Z=tZ[b], x_min=wl.Z_XMIN,
                               x_max=wl.Z_XMAX) for b in range(B)]
     n_f = ft_frequency_count(wl.FT_T, wl.FT_FREQ_MAX, wl.FT_N_TAIL)
@@ -768,6 +771,17 @@ def secondary(torch, frg, wl, ctx, serving_seconds=15.0, serving_warm=2.0):
         "frac_fp64_peak": round(FLOP_PER_NODE[5] * nft / (msft * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                                 4)}
     del keep_ft
+    # the same with the inner leg's frequency p0 - i mu (chemical potential mu = 0.5 k)
+    log("bench: finite-temperature two-point batch at mu = 0.5")
+    dmu, bmu, nmu, keep_mu = two_point_ft_setup(torch, frg, wl, mu=0.5)
+    fmu = lambda: ctx.integrate_multi(dmu, bmu)
+    warm_clocks(torch, fmu, EXTRA_WARM_S)
+    wall, ev = time_kernel(torch, fmu, 100, 5)
+    msmu = float(np.mean(ev))
+    ex["two_point_finite_T_mu_batch_16"] = {
+        "gnodes_per_s": round(nmu / (msmu * 1e-3) / 1e9, 2), "avg_kernel_ms": round(msmu, 3),
+        "nodes": nmu, "mu": 0.5, "vs_real_frequencies": round(msft / msmu, 3)}
+    del keep_mu
     log("bench: finite-temperature three-point batch")
     d6, b6, n6, keep6 = three_point_ft_setup(torch, frg, wl)
     f6 = lambda: ctx.integrate_multi(d6, b6)

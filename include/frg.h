@@ -137,6 +137,15 @@ typedef enum {
  *              integrand is even in it, so phi GL(n_phi) on [0, pi] carries a factor 2
  * p0_e is the external frequency: a bosonic 2 pi m T, or for a fermion the paper's
  * p0f = pi T exp(-k/(pi T)) (App. "Derivation of the four-Fermi system").
+ * Complex external frequencies (complex_freq = 1, families 5 and 6): an inner leg's external
+ * frequency is p0 + i p0i, as for the paper's external fermion legs at chemical potential mu,
+ * whose imaginary-time component is p0f - i mu (same appendix): H continues analytically,
+ * H_j(l) = 1/((w_j + p0 + i p0i)^2 + Z(l^2) l^2 + R(l^2) + m2_e) (the radial leg keeps its real
+ * w_j), and I_e is complex.  The ext array appends the imaginary parts (family 5: p, p0, p0i;
+ * family 6: p, alpha, p01, p02, p01i, p02i) and out holds 2 n_ext values, Re I_e at e and
+ * Im I_e at n_ext + e.  Float64 only, without dout_dm2 and dout_dz (FRG_E_UNSUPPORTED), not
+ * for flows (frg_flow_rhs, steppers: FRG_E_UNSUPPORTED); a continued pole
+ * (w_j + p0 + i p0i)^2 = -(Z l^2 + R + m2) on a node gives inf or nan.
  * Limits: at least one explicit frequency (fermionic: Lambda >= pi T); n_tail <= FRG_MAX_NODES;
  * n_f = explicit + 2 n_tail <= FRG_MAX_NODES; n_q n_f <= FRG_MAX_FT_NODES.
  */
@@ -161,7 +170,8 @@ typedef struct {
     int regulator;         /* frg_regulator (0, the exponential one, when zeroed); every
                               regulator in both precisions */
     int reg_order;         /* N of FRG_REG_POLY_EXP, 1..16; 0 = 8 */
-    int reserved;          /* zero */
+    int complex_freq;      /* families 5 and 6: 1 = complex external frequencies of the inner
+                              legs (see below), 0 = real; must be 0 for the other families */
 } frg_integral_desc;
 
 #define FRG_MAX_NODES 1024
@@ -185,11 +195,12 @@ typedef struct {
                               family 5: p[n_ext] followed by p0[n_ext] (2 n_ext values);
                               family 6: p, alpha, p01 and p02, each [n_ext] (4 n_ext values:
                               the spatial momenta as in family 3, the external frequencies of
-                              the two inner legs) */
+                              the two inner legs); with complex_freq the imaginary parts
+                              follow (families 5 and 6: 3 and 6 n_ext values) */
     const double *m2;      /* device [n_ext] per-point m^2, or NULL to use m2_scalar */
     double m2_scalar;
     frg_log_table Z;
-    double *out;           /* device [n_ext]: I_e */
+    double *out;           /* device [n_ext]: I_e ([2 n_ext], Re then Im, with complex_freq) */
     double *err_out;       /* device [n_ext] or NULL: stated relative error bound per result of
                               the FP32 form (0 for FP64): with u = 2^-24, kappa the largest
                               amplification (|Z l2 + R| + |m2|)/D among that point's float32

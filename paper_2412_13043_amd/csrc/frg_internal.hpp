@@ -36,11 +36,17 @@ struct PhiRule {
 };
 
 // One request ("batch" of external points under one descriptor), as the kernels see it.
+// Kernel families beyond the public ones: the finite-temperature two- and three-point families
+// (5, 6) with complex external frequencies of the inner legs; their requests carry the
+// imaginary part of each result where the others carry dI/dm2 (dout).
+constexpr int kFamTwoPointComplex = 7;
+constexpr int kFamThreePointComplex = 8;
+
 struct ReqDev {
-    int family, d, n_q, n_x, n_phi, precision;
+    int family, d, n_q, n_x, n_phi, precision;  // family: public family or kFam*Complex
     int n_ext;
-    int lq_log2;      // lanes per external point over radial nodes: 1 << lq_log2 (families 2, 3)
-    int lx_log2;      // ... times lanes over cos1 nodes: 1 << lx_log2 (families 2, 3; LPA 0)
+    int lq_log2;      // lanes per external point over radial nodes: 1 << lq_log2 (vertex families)
+    int lx_log2;      // ... times lanes over cos1 nodes: 1 << lx_log2 (vertex families; LPA 0)
     int chunks;       // radial chunks per external tile
     int ext_tiles;    // ceil(n_ext / (64 >> (lq_log2 + lx_log2)))
     int nZ;           // 0 => Z == 1
@@ -67,7 +73,7 @@ struct ReqDev {
     const double *Z;
     double *out;
     double *err;
-    double *dout;         // dI/dm2 per point, or null
+    double *dout;         // dI/dm2 per point (complex families: Im I per point), or null
 };
 
 // A unit of work: external tile `et` of request `req`, radial chunk `chunk`.

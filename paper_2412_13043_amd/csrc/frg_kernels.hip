@@ -938,6 +938,227 @@ __device__ __forceinline__ Dual contrib_three(const ReqDev &r, const Smem &sm, i
                 t.wg * (-2.0 * t.g * (mid * i4) - (midA + midB) * (i4 * inv_k2))};
 }
 
+// --------------------------------------------------------------------------------------------
+// Complex external frequencies (finite temperature, internal families 7 and 8)
+// --------------------------------------------------------------------------------------------
+// An inner leg whose external frequency is p0 + i p0i (the paper's external fermion legs at
+// chemical potential carry p0f - i mu) has the mass term (w_j + p0 + i p0i)^2 + m2 =
+// m2r + i mi with m2r = m2 + (w_j + p0)^2 - p0i^2 and mi = 2 (w_j + p0) p0i, and its
+// propagator is the complex G = 1/(D + i mi) = (D - i mi)/(D^2 + mi^2), D = Z y + R/k^2 + m2r
+// (units of k^2).  The exponential regulator's form D = den/(-E) (den as in propagators64)
+// gives G = (-E)(den + i E mi)/(den^2 + E^2 mi^2); den and E are scaled by 2^-e(E) first (E =
+// m_E 2^e(E), exact), so that neither square underflows as y -> 0, where both vanish like y.
+// One reciprocal per node, as for a real propagator.
+template <int W, bool FAR, int REG>
+__device__ __forceinline__ void propagators64c(const double (&l2)[W], double (&Gr)[W],
+                                               double (&Gi)[W], const Smem &sm, int nZ,
+                                               double za, double zb1, double m2, double mi,
+                                               double far_y, int reg_n) {
+    constexpr bool kFar = FAR && REG != 2;
+    const double fy = REG == 0 ? FRG_FAR_Y : far_y;
+    bool far = kFar;
+#pragma unroll
+    for (int w = 0; w < W; ++w) far = far && (l2[w] >= fy);
+    if (kFar && __all(far)) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const double D = fma(dressing64(sm, nZ, za, zb1, l2[w]), l2[w], m2);
+            const double inv = fm::rcp_nr(fma(D, D, mi * mi));
+            Gr[w] = D * inv;
+            Gi[w] = -mi * inv;
+        }
+        return;
+    }
+    double2 t[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) t[w] = sm.logt[(__double2hiint(l2[w]) >> 12) & 0xff];
+    double E[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        if (REG == 0)
+            E[w] = fm::expm1_neg(l2[w]);
+        else if (REG == 1)
+            E[w] = fm::exp_neg(fmin(poly_s(l2[w], reg_n), 1000.0));
+        else
+            E[w] = fmax(1.0 - l2[w], 0.0);
+    }
+    int iz[W];
+    double fz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const double f = __builtin_amdgcn_frexp_mant(l2[w]);
+        const int k = __builtin_amdgcn_frexp_exp(l2[w]);
+        const double r = fma(f, t[w].x, -1.0);
+        double p = fma(r, -0.25, 0.3333333333333333);
+        p = fma(r, p, -0.5);
+        p = fma(r, p, 1.0);
+        p = r * p;
+        const double ln = fma((double)k, fm::LN2_HI, t[w].y + p);
+        zcell64(fma(ln, za, zb1), nZ, iz[w], fz[w]);
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const double2 z = sm.Z64[iz[w]];
+        const double zv = fma(fz[w], z.y, z.x);
+        if (REG != 0) {
+            const double D = fma(zv, l2[w], m2) + E[w];
+            const double inv = fm::rcp_nr(fma(D, D, mi * mi));
+            Gr[w] = D * inv;
+            Gi[w] = -mi * inv;
+        } else {
+            const double den = fma(-E[w], fma(zv, l2[w], m2), fma(l2[w], E[w], l2[w]));
+            const double mE = __builtin_amdgcn_frexp_mant(E[w]);  // E = mE 2^eE, mE < 0
+            const int eE = __builtin_amdgcn_frexp_exp(E[w]);
+            const double ds = __builtin_amdgcn_ldexp(den, -eE);
+            const double em = mE * mi;
+            const double inv = fm::rcp_nr(fma(ds, ds, em * em));
+            Gr[w] = -mE * ds * inv;
+            Gi[w] = -mE * em * inv;
+        }
+    }
+}
+
+// Two-point contribution of (e, a) with a complex inner-leg mass m2r + i mi (units of k^2
+// after the scaling below): Dual{Re, Im}.  Lanes share cos1 nodes as in contrib_two.
+template <int REG>
+__device__ __forceinline__ Dual contrib_two_c(const ReqDev &r, const Smem &sm, int a, double p,
+                                              double m2, double m2r, double mi, double inv_k2,
+                                              bool act, int sx, int lx) {
+    RadialTerm t{0.0, 0.0, 0.0, 0.0};
+    double c0 = 0.0, c1 = 0.0;
+    if (act) {
+        t = radial64(r, sm, a, p, m2);
+        c0 = t.c0 * inv_k2;
+        c1 = t.c1 * inv_k2;
+    }
+    const double m2h = m2r * inv_k2, mih = mi * inv_k2, za = r.za, zb1 = r.zbk + 1.0;
+    const int nx = r.n_x, nZ = r.nZ;
+    double ir = 0.0, ii = 0.0;
+    if (lx == 1) {
+        if (!act) return Dual{0.0, 0.0};
+        int b = 0;
+        for (; b + FRG_ILP <= nx; b += FRG_ILP) {
+            double l2[FRG_ILP], gr[FRG_ILP], gi[FRG_ILP];
+#pragma unroll
+            for (int w = 0; w < FRG_ILP; ++w) l2[w] = fma(c1, kc(r.ang.x)[b + w], c0);
+            propagators64c<FRG_ILP, true, REG>(l2, gr, gi, sm, nZ, za, zb1, m2h, mih, r.far_y,
+                                               r.reg_n);
+#pragma unroll
+            for (int w = 0; w < FRG_ILP; ++w) {
+                ir = fma(kc(r.ang.xw)[b + w], gr[w], ir);
+                ii = fma(kc(r.ang.xw)[b + w], gi[w], ii);
+            }
+        }
+        for (; b < nx; ++b) {
+            double l2[1] = {fma(c1, kc(r.ang.x)[b], c0)}, gr[1], gi[1];
+            propagators64c<1, true, REG>(l2, gr, gi, sm, nZ, za, zb1, m2h, mih, r.far_y,
+                                         r.reg_n);
+            ir = fma(kc(r.ang.xw)[b], gr[0], ir);
+            ii = fma(kc(r.ang.xw)[b], gi[0], ii);
+        }
+    } else {
+        const int xbase = (int)threadIdx.x & ~(lx - 1);
+        for (int j0 = 0; j0 < nx; j0 += lx) {
+            const int b = j0 + sx;
+            double gr = 0.0, gi = 0.0;
+            if (act && b < nx) {
+                double l2[1] = {fma(c1, kc(r.ang.x)[b], c0)}, Gr[1], Gi[1];
+                propagators64c<1, true, REG>(l2, Gr, Gi, sm, nZ, za, zb1, m2h, mih, r.far_y,
+                                             r.reg_n);
+                gr = Gr[0];
+                gi = Gi[0];
+            }
+            const int nk = min(lx, nx - j0);
+            for (int k = 0; k < nk; ++k) {
+                ir = fma(kc(r.ang.xw)[j0 + k], __shfl(gr, xbase + k), ir);
+                ii = fma(kc(r.ang.xw)[j0 + k], __shfl(gi, xbase + k), ii);
+            }
+        }
+    }
+    return Dual{t.wg * (ir * inv_k2), t.wg * (ii * inv_k2)};
+}
+
+// One cos1 node b of the three-point contribution with complex leg masses (m1r + i m1i on l1,
+// m2r + i m2i on l2; units of k^2): t = xw_b G(l1^2) and the phi sum inner = sum_c w_c G(l2^2),
+// both complex.
+template <int REG>
+__device__ __forceinline__ void xterm64c(const ReqDev &r, const Smem &sm, int b, double c0,
+                                         double c1, double ca, double sa, double m1r,
+                                         double m1i, double m2r, double m2i, double &tr,
+                                         double &ti, double &inr, double &ini) {
+    const int nphi = r.n_phi, nZ = r.nZ;
+    const double za = r.za, zb1 = r.zbk + 1.0;
+    const double xb = kc(r.ang.x)[b];
+    double l1[1] = {fma(c1, xb, c0)}, g1r[1], g1i[1];
+    propagators64c<1, true, REG>(l1, g1r, g1i, sm, nZ, za, zb1, m1r, m1i, r.far_y, r.reg_n);
+    const double A2 = fma(-c1, xb * ca, c0);
+    const double B2 = -c1 * (kc(r.ang.xs)[b] * sa);
+    double ar = 0.0, ai = 0.0;
+    int c = 0;
+    for (; c + FRG_ILP <= nphi; c += FRG_ILP) {
+        double l2[FRG_ILP], gr[FRG_ILP], gi[FRG_ILP];
+#pragma unroll
+        for (int w = 0; w < FRG_ILP; ++w)
+            l2[w] = fmax(fma(B2, kc(r.phi.c)[c + w], A2), FRG_L2_TINY);
+        propagators64c<FRG_ILP, true, REG>(l2, gr, gi, sm, nZ, za, zb1, m2r, m2i, r.far_y,
+                                           r.reg_n);
+#pragma unroll
+        for (int w = 0; w < FRG_ILP; ++w) {
+            ar = fma(kc(r.phi.w)[c + w], gr[w], ar);
+            ai = fma(kc(r.phi.w)[c + w], gi[w], ai);
+        }
+    }
+    for (; c < nphi; ++c) {
+        double l2[1] = {fmax(fma(B2, kc(r.phi.c)[c], A2), FRG_L2_TINY)}, gr[1], gi[1];
+        propagators64c<1, false, REG>(l2, gr, gi, sm, nZ, za, zb1, m2r, m2i, r.far_y, r.reg_n);
+        ar = fma(kc(r.phi.w)[c], gr[0], ar);
+        ai = fma(kc(r.phi.w)[c], gi[0], ai);
+    }
+    tr = kc(r.ang.xw)[b] * g1r[0];
+    ti = kc(r.ang.xw)[b] * g1i[0];
+    inr = ar;
+    ini = ai;
+}
+
+// Three-point contribution of (e, a) with complex leg masses: Dual{Re, Im} of
+// W G(q^2)^2 sum_b t_b inner_b.
+template <int REG>
+__device__ __forceinline__ Dual contrib_three_c(const ReqDev &r, const Smem &sm, int a, double p,
+                                                double ca, double sa, double m2, double m1r,
+                                                double m1i, double m2r, double m2i,
+                                                double inv_k2, bool act, int sx, int lx) {
+    RadialTerm t{0.0, 0.0, 0.0, 0.0};
+    double c0 = 0.0, c1 = 0.0;
+    if (act) {
+        t = radial64(r, sm, a, p, m2);
+        c0 = t.c0 * inv_k2;
+        c1 = t.c1 * inv_k2;
+    }
+    const double h1r = m1r * inv_k2, h1i = m1i * inv_k2, h2r = m2r * inv_k2, h2i = m2i * inv_k2;
+    const int nx = r.n_x;
+    const int xbase = (int)threadIdx.x & ~(lx - 1);
+    double mr = 0.0, mi = 0.0;
+    for (int j0 = 0; j0 < nx; j0 += lx) {
+        const int b = j0 + sx;
+        double tr = 0.0, ti = 0.0, ir = 0.0, ii = 0.0;
+        if (act && b < nx) xterm64c<REG>(r, sm, b, c0, c1, ca, sa, h1r, h1i, h2r, h2i, tr, ti, ir, ii);
+        if (lx == 1) {
+            mr = fma(tr, ir, fma(-ti, ii, mr));
+            mi = fma(tr, ii, fma(ti, ir, mi));
+        } else {
+            const int nk = min(lx, nx - j0);
+            for (int k = 0; k < nk; ++k) {
+                const double tkr = __shfl(tr, xbase + k), tki = __shfl(ti, xbase + k);
+                const double ikr = __shfl(ir, xbase + k), iki = __shfl(ii, xbase + k);
+                mr = fma(tkr, ikr, fma(-tki, iki, mr));
+                mi = fma(tkr, iki, fma(tki, ikr, mi));
+            }
+        }
+    }
+    const double i4 = inv_k2 * inv_k2;
+    return Dual{t.wg * (mr * i4), t.wg * (mi * i4)};
+}
+
 // float32 form's stated relative error bound per result.  u = 2^-24 (float32 unit roundoff);
 // kappa = the largest amplification (|Z y + R| + |m2|)/D among the point's float32 propagators
 // (the fallback's enter scaled, see prop_fallback); nG = float32 propagators per integrand term
@@ -1170,9 +1391,9 @@ __device__ __forceinline__ double readlane64(double v, int l) {
 }
 
 // Vertex families (FAM 2 two-point, 3 three-point, 5 and 6 two- and three-point at finite
-// temperature): lanes =
-// (external point, radial sub-lane, cos1 sub-lane); the point's contributions are added in radial
-// order inside the wavefront, or (radially chunked requests) stored for the finalize kernel.
+// temperature, 7 and 8 the same with complex external frequencies): lanes = (external point,
+// radial sub-lane, cos1 sub-lane); the point's contributions are added in radial order inside
+// the wavefront, or (radially chunked requests) stored for the finalize kernel.
 template <int FAM, int PREC, int REG, bool DER>
 __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int et, int chunk,
                                             double *__restrict__ contrib,
@@ -1196,15 +1417,20 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
     // reset by the finalize kernel), then one slot for the dressing table's relative step
     unsigned *kslot = counters + r.ctr_base;
     float kmax = 1.0f;
-    double p = 0.0, m2 = 0.0, ca = 1.0, sa = 0.0, p0 = 0.0, p02 = 0.0;
+    double p = 0.0, m2 = 0.0, ca = 1.0, sa = 0.0, p0 = 0.0, p02 = 0.0, p0i = 0.0, p02i = 0.0;
     if (valid) {
         p = r.ext[e];
         m2 = lane_m2(r, e);
-        if (FAM == 3 || FAM == 6) sincos(r.ext[r.n_ext + e], &sa, &ca);
-        if (FAM == 5) p0 = r.ext[r.n_ext + e];
-        if (FAM == 6) {
+        if (FAM == 3 || FAM == 6 || FAM == 8) sincos(r.ext[r.n_ext + e], &sa, &ca);
+        if (FAM == 5 || FAM == 7) p0 = r.ext[r.n_ext + e];
+        if (FAM == 7) p0i = r.ext[2 * r.n_ext + e];
+        if (FAM == 6 || FAM == 8) {
             p0 = r.ext[2 * r.n_ext + e];
             p02 = r.ext[3 * r.n_ext + e];
+        }
+        if (FAM == 8) {
+            p0i = r.ext[4 * r.n_ext + e];
+            p02i = r.ext[5 * r.n_ext + e];
         }
     }
     // contribution of radial node a (valid in the point's sx == 0 lanes); every lane of the
@@ -1220,6 +1446,21 @@ __device__ __forceinline__ void tile_vertex(const ReqDev &r, const Smem &sm, int
             const double w1 = kc(r.rad.w0)[ai] + p0, w2 = kc(r.rad.w0)[ai] + p02;
             return contrib_three<PREC, REG, DER>(r, sm, ai, p, ca, sa, m2, fma(w1, w1, m2),
                                                  fma(w2, w2, m2), inv_k2, kmax, act, sx, lx);
+        }
+        if (FAM == 7) {
+            // complex leg frequency w_j + p0 + i p0i: Dual{Re, Im} (the imaginary part takes
+            // the derivative's slot)
+            const int ai = act ? a : 0;
+            const double wl = kc(r.rad.w0)[ai] + p0;
+            return contrib_two_c<REG>(r, sm, ai, p, m2, fma(wl, wl, fma(-p0i, p0i, m2)),
+                                      2.0 * wl * p0i, inv_k2, act, sx, lx);
+        }
+        if (FAM == 8) {
+            const int ai = act ? a : 0;
+            const double w1 = kc(r.rad.w0)[ai] + p0, w2 = kc(r.rad.w0)[ai] + p02;
+            return contrib_three_c<REG>(r, sm, ai, p, ca, sa, m2, fma(w1, w1, fma(-p0i, p0i, m2)),
+                                        2.0 * w1 * p0i, fma(w2, w2, fma(-p02i, p02i, m2)),
+                                        2.0 * w2 * p02i, inv_k2, act, sx, lx);
         }
         if (FAM == 5) {
             // radial index a = (frequency j, spatial node): the inner leg's frequency w_j + p0
@@ -1338,7 +1579,7 @@ hipError_t launch_multi_finalize(const ReqDev *reqs_dev, const TileDev *fin_dev,
 // One request: tile = blockIdx.x -> (external tile, chunk).
 template <int FAM, int PREC, int REG, bool DER>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
-    DER ? ((FAM == 3 || FAM == 6) ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_DER)
+    DER ? ((FAM == 3 || FAM == 6 || FAM == 8) ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_DER)
         : ((FAM == 3 || FAM == 6 || PREC != 0) ? FRG_WAVES_PER_EU_MULTI
                                                 : FRG_WAVES_PER_EU_BATCH))))
 batch_kernel(ReqDev r, double *contrib, unsigned *counters) {
@@ -1383,6 +1624,9 @@ static batch_fn batch_variant(int fam, int prec, int reg, bool der) {
     if (fam == 2) return batch_for_family<2>(prec, reg, der);
     if (fam == 5) return batch_for_family<5>(prec, reg, der);
     if (fam == 6) return der ? batch_for_reg<6, true>(reg) : batch_for_reg<6, false>(reg);
+    // complex frequencies: the imaginary part rides in the derivative's slot
+    if (fam == 7) return batch_for_reg<7, true>(reg);
+    if (fam == 8) return batch_for_reg<8, true>(reg);
     return batch_for_family<3>(prec, reg, der);
 }
 
@@ -1454,8 +1698,15 @@ __device__ __forceinline__ void multi_tile(const ReqDev &r, Smem &sm, const Tile
         vertex_tile_any<5, DER>(r, sm, td, contrib, counters);
     else if (r.family == 6)
         vertex_tile_reg<6, DER>(r, sm, td, contrib, counters);  // float64 only
-    else
+    else if (r.family == 3)
         vertex_tile_any<3, DER>(r, sm, td, contrib, counters);
+    else if constexpr (DER) {
+        // complex frequencies (their requests carry dout, so only this instance sees them)
+        if (r.family == 7)
+            vertex_tile_reg<7, true>(r, sm, td, contrib, counters);
+        else
+            vertex_tile_reg<8, true>(r, sm, td, contrib, counters);
+    }
 }
 
 // Occupancy target of a fused-kernel instance: the three-point family and the general kernel
@@ -1463,8 +1714,8 @@ __device__ __forceinline__ void multi_tile(const ReqDev &r, Smem &sm, const Tile
 // accumulators, and the polynomial-exponential regulator's exponent a few more registers.  The
 // float32 form of the two-point families holds 4 (at 5 it spills).
 constexpr int multi_waves(int fam, int prec, int reg, bool der) {
-    return der ? ((fam < 0 || fam == 3 || fam == 6) ? FRG_WAVES_PER_EU_DER3
-                                                    : FRG_WAVES_PER_EU_DER)
+    return der ? ((fam < 0 || fam == 3 || fam == 6 || fam == 8) ? FRG_WAVES_PER_EU_DER3
+                                                                : FRG_WAVES_PER_EU_DER)
                : ((fam < 0 || fam == 3 || fam == 6)
                       ? (reg == 1 ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_MULTI)
                       : ((reg == 1 || prec != 0) ? FRG_WAVES_PER_EU_MULTI
@@ -1547,6 +1798,8 @@ static multi_fn multi_variant(int fam, int prec, int reg, int der) {
     if (fam == 3) return multi_for_family<3>(prec, reg, der);
     if (fam == 5) return multi_for_family<5>(prec, reg, der);
     if (fam == 6) return der ? multi_for_reg<6, true>(reg) : multi_for_reg<6, false>(reg);
+    if (fam == 7) return multi_for_reg<7, true>(reg);
+    if (fam == 8) return multi_for_reg<8, true>(reg);
     return der ? multi_kernel<-1, -1, -1, true> : multi_kernel<-1, -1, -1, false>;
 }
 

@@ -150,7 +150,7 @@ static frg_status replay_plain(frg_context *ctx, int n_kinds, const frg_replay_k
                                double *wall_us) {
     size_t max_ext = 1, max_n = 1;
     for (int i = 0; i < n_kinds; ++i) {
-        max_ext = std::max(max_ext, (size_t)ext_values(kinds[i].desc.family, kinds[i].n_ext));
+        max_ext = std::max(max_ext, (size_t)ext_values(kinds[i].desc, kinds[i].n_ext));
         max_n = std::max(max_n, (size_t)kinds[i].n_ext);
     }
     FRG_HIP_CHECK(hipSetDevice(ctx->device));
@@ -176,7 +176,7 @@ static frg_status replay_plain(frg_context *ctx, int n_kinds, const frg_replay_k
         const frg_replay_arrival &a = arr[i];
         const frg_replay_kind &k = kinds[a.kind];
         wait_until(t0 + a.t_us);  // first in, first out: no earlier than the previous one ends
-        const size_t ne = (size_t)ext_values(k.desc.family, k.n_ext);
+        const size_t ne = (size_t)ext_values(k.desc, k.n_ext);
         if (ne) std::memcpy(h_ext, k.ext, ne * sizeof(double));
         std::memcpy(h_m2, k.m2, (size_t)k.n_ext * sizeof(double));
         frg_integral_desc d = k.desc;

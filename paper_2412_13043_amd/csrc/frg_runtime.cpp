@@ -182,6 +182,21 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
         set_error("dout_dm2 (the mass derivative) is implemented in float64 only");
         return FRG_E_UNSUPPORTED;
     }
+    if (d->complex_freq != 0 && d->complex_freq != 1) {
+        set_error("complex_freq must be 0 or 1, got %d", d->complex_freq);
+        return FRG_E_INVAL;
+    }
+    if (d->complex_freq) {
+        if (d->family != FRG_FAMILY_TWO_POINT_T && d->family != FRG_FAMILY_THREE_POINT_T) {
+            set_error("complex external frequencies apply to families 5 and 6 only");
+            return FRG_E_INVAL;
+        }
+        if (d->precision != FRG_FP64 || b->dout_dm2 || b->dout_dz) {
+            set_error("complex external frequencies are implemented in float64 without "
+                      "dout_dm2 and dout_dz");
+            return FRG_E_UNSUPPORTED;
+        }
+    }
     if (d->family == FRG_FAMILY_THREE_POINT_T && d->precision != FRG_FP64) {
         set_error("family 6 (three-point at finite temperature) is implemented in float64 only");
         return FRG_E_UNSUPPORTED;
@@ -655,6 +670,9 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
         if (fs != FRG_OK) return fs;
     }
     r.family = d.family == FRG_FAMILY_LPA_T ? FRG_FAMILY_LPA : d.family;
+    if (d.complex_freq)
+        r.family = d.family == FRG_FAMILY_THREE_POINT_T ? kFamThreePointComplex
+                                                        : kFamTwoPointComplex;
     r.d = d.d;
     r.n_q = is_ft(d.family) ? d.n_q * fr.n_f : d.n_q;
     r.n_x = vertex ? d.n_x : 0;
@@ -736,7 +754,8 @@ frg_status make_request(frg_context *ctx, const frg_integral_desc &d, const frg_
     r.m2 = b.m2;
     r.out = b.out;
     r.err = b.err_out;
-    r.dout = b.dout_dm2;
+    // complex frequencies: the imaginary parts take the derivative's place, after the real ones
+    r.dout = d.complex_freq ? b.out + b.n_ext : b.dout_dm2;
     *out = r;
     return FRG_OK;
 }
@@ -799,7 +818,7 @@ std::vector<TileDev> make_tiles(const std::vector<ReqDev> &reqs, int *lds_out,
         int lq = 1 << r.lq_log2;
         double inner = r.family == 1 ? 1.0
                                      : std::ceil((double)r.n_x / (1 << r.lx_log2)) *
-                                           (has_phi(r.family) ? r.n_phi : 1);
+                                           (req_has_phi(r.family) ? r.n_phi : 1);
         const int et0 = et_ranges ? (*et_ranges)[i].first : 0;
         const int et1 = et_ranges ? (*et_ranges)[i].second : r.ext_tiles;
         for (int et = et0; et < et1; ++et)
@@ -1201,6 +1220,10 @@ frg_status frg_flow_rhs(frg_context *ctx, const frg_integral_desc *desc,
         set_error("flow state family %d does not match descriptor family %d", state->family,
                   desc->family);
         return FRG_E_INVAL;
+    }
+    if (desc->complex_freq) {
+        set_error("complex external frequencies give complex integrals: no flow right-hand side");
+        return FRG_E_UNSUPPORTED;
     }
     const int n = state->n_ext;
     const bool lpa = is_lpa(desc->family);

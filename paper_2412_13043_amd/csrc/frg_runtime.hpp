@@ -112,12 +112,23 @@ inline bool is_lpa(int fam) { return fam == FRG_FAMILY_LPA || fam == FRG_FAMILY_
 inline bool has_phi(int fam) {
     return fam == FRG_FAMILY_THREE_POINT || fam == FRG_FAMILY_THREE_POINT_T;
 }
-// doubles of the ext array for n points
+// doubles of the ext array for n points (real external frequencies)
 inline long long ext_values(int fam, long long n) {
     if (fam == FRG_FAMILY_THREE_POINT_T) return 4 * n;
     if (fam == FRG_FAMILY_THREE_POINT || fam == FRG_FAMILY_TWO_POINT_T) return 2 * n;
     return fam == FRG_FAMILY_TWO_POINT ? n : 0;
 }
+// ... of a descriptor: complex external frequencies append their imaginary parts
+inline long long ext_values(const frg_integral_desc &d, long long n) {
+    if (d.complex_freq) return d.family == FRG_FAMILY_THREE_POINT_T ? 6 * n : 3 * n;
+    return ext_values(d.family, n);
+}
+// doubles of the out array for n points (Re then Im with complex frequencies)
+inline long long out_values(const frg_integral_desc &d, long long n) {
+    return d.complex_freq ? 2 * n : n;
+}
+// kernel families (ReqDev::family) with a phi rule
+inline bool req_has_phi(int fam) { return has_phi(fam) || fam == kFamThreePointComplex; }
 
 // Matsubara frequency rule of a finite-temperature descriptor: frequencies 2 pi T (n + eta) for
 // n = n_lo .. n_lo + n_exp - 1 (every |w| <= Lambda), and n_tail tail nodes per side beyond

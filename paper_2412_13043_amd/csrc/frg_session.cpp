@@ -278,8 +278,11 @@ static void part_points(const SessReq &r, int et0, int et1, int *p0, int *p1) {
 
 // Output arrays a request returns: the integrals, then the float32 form's bounds and the mass
 // derivatives if asked for, each [n] doubles in that order.
+// arrays of a part's output area, each of its points: out (Re and Im with complex
+// frequencies), err_out, dout_dm2
 static int out_arrays(const SessReq &r) {
-    return 1 + (r.host.err_out ? 1 : 0) + (r.host.dout_dm2 ? 1 : 0);
+    return 1 + (r.desc.complex_freq ? 1 : 0) + (r.host.err_out ? 1 : 0) +
+           (r.host.dout_dm2 ? 1 : 0);
 }
 
 static size_t part_out_bytes(const SessReq &r, int p0, int p1) {
@@ -324,8 +327,10 @@ class HipExecutor : public Executor {
             b.m2 = r->host.m2 ? (const double *)(in + r->in_m2) : nullptr;
             // outputs of points [p0, p1) land at the part's output area
             b.out = (double *)(blk + pt.out) - pt.p0;
-            b.err_out = r->host.err_out ? (double *)(blk + pt.out) + (pt.p1 - pt.p0) - pt.p0
-                                        : nullptr;
+            const int ncx = r->desc.complex_freq ? 2 : 1;  // Re (and Im) come first
+            b.err_out = r->host.err_out
+                            ? (double *)(blk + pt.out) + ncx * (pt.p1 - pt.p0) - pt.p0
+                            : nullptr;
             b.dout_dm2 = r->host.dout_dm2 ? (double *)(blk + pt.out) +
                                                 (out_arrays(*r) - 1) * (pt.p1 - pt.p0) - pt.p0
                                           : nullptr;
@@ -336,6 +341,8 @@ class HipExecutor : public Executor {
             ReqDev q;
             frg_status st = make_request(ctx, r->desc, b, r->shape, 1, 0.0, 1.0, &q);
             if (st != FRG_OK) return st;
+            // complex frequencies: Im of points [p0, p1) right after their Re in the area
+            if (r->desc.complex_freq) q.dout = (double *)(blk + pt.out) + (pt.p1 - pt.p0) - pt.p0;
             // contributions and slots in the block, addressed from the block's start
             q.contrib_base = (long long)(pt.contrib / sizeof(double));
             q.ctr_base = (long long)(pt.slots / sizeof(unsigned));
@@ -411,7 +418,11 @@ class HipExecutor : public Executor {
             if (r->timed_out || r->state != RQ_RUNNING) continue;
             const size_t n = (size_t)(pt.p1 - pt.p0);
             std::memcpy(r->host.out + pt.p0, h + pt.out, n * 8);
-            if (r->host.err_out) std::memcpy(r->host.err_out + pt.p0, h + pt.out + n * 8, n * 8);
+            const size_t ncx = r->desc.complex_freq ? 2 : 1;
+            if (ncx == 2)
+                std::memcpy(r->host.out + r->host.n_ext + pt.p0, h + pt.out + n * 8, n * 8);
+            if (r->host.err_out)
+                std::memcpy(r->host.err_out + pt.p0, h + pt.out + ncx * n * 8, n * 8);
             if (r->host.dout_dm2)
                 std::memcpy(r->host.dout_dm2 + pt.p0, h + pt.out + (out_arrays(*r) - 1) * n * 8,
                             n * 8);
@@ -757,7 +768,7 @@ static void request_layout(SessReq &r) {
     const frg_integral_desc &d = r.desc;
     const size_t n = (size_t)r.host.n_ext;
     size_t off = 0;
-    r.n_ext_vals = (int)ext_values(d.family, (long long)n);
+    r.n_ext_vals = (int)ext_values(d, (long long)n);
     r.in_ext = off;
     off += (size_t)r.n_ext_vals * 8;
     r.in_m2 = off;
@@ -767,7 +778,9 @@ static void request_layout(SessReq &r) {
     r.in_bytes = off;
     r.slot_bytes = (r.chunked && d.precision == FRG_FP32_KAHAN) ? (n + 1) * 4 : 0;
     // radial contributions of a chunked shape, and as many derivative contributions
-    r.contrib_bytes = r.chunked ? (size_t)plan_desc(d).n_q * n * 8 * (r.host.dout_dm2 ? 2 : 1) : 0;
+    r.contrib_bytes =
+        r.chunked ? (size_t)plan_desc(d).n_q * n * 8 * (r.host.dout_dm2 || d.complex_freq ? 2 : 1)
+                  : 0;
     r.footprint = align256(r.in_bytes) + align256(r.slot_bytes) + align256(out_arrays(r) * n * 8) +
                   align256(r.contrib_bytes);
 }

@@ -425,6 +425,10 @@ frg_status frg_stepper_create(frg_context *ctx, const frg_integral_desc *desc,
                   desc->family);
         return FRG_E_INVAL;
     }
+    if (desc->complex_freq) {
+        set_error("complex external frequencies give complex integrals: no flow to integrate");
+        return FRG_E_UNSUPPORTED;
+    }
     const bool lpa = is_lpa(desc->family);
     const int n = state->n_ext;
     if (!state->state || !state->grid || n < (lpa ? 3 : 1)) {

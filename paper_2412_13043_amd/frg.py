@@ -57,7 +57,7 @@ class frg_integral_desc(ctypes.Structure):
                 ("n_phi", c_int), ("precision", c_int), ("q_max", c_double), ("k", c_double),
                 ("near_pole_tau", c_double), ("T", c_double), ("freq_max", c_double),
                 ("statistics", c_int), ("n_tail", c_int), ("freq_scaled", c_int),
-                ("regulator", c_int), ("reg_order", c_int), ("reserved", c_int)]
+                ("regulator", c_int), ("reg_order", c_int), ("complex_freq", c_int)]
 
 
 class frg_log_table(ctypes.Structure):
@@ -387,14 +387,15 @@ def make_desc(family: int, n_q: int, q_max: float, *, n_x: int = 0, n_phi: int =
               k: float = 1.0, precision: int = FRG_FP64, near_pole_tau: float = 0.0,
               T: float = 0.0, freq_max: float = 0.0, statistics: int = FRG_BOSONIC,
               n_tail: int = 0, freq_scaled: bool = False, regulator: int = FRG_REG_EXPONENTIAL,
-              reg_order: int = 0):
+              reg_order: int = 0, complex_freq: bool = False):
     """Descriptor; T, freq_max, statistics, n_tail and freq_scaled apply to the finite-temperature
-    families (4, 5, 6) only; regulator and reg_order to every family."""
+    families (4, 5, 6) only, complex_freq to families 5 and 6; regulator and reg_order to every
+    family."""
     if d == 0:
         d = 3 if family == FRG_FAMILY_LPA else 4
     return frg_integral_desc(family, d, n_q, n_x, n_phi, precision, q_max, k, near_pole_tau,
                              T, freq_max, statistics, n_tail, 1 if freq_scaled else 0, regulator,
-                             reg_order, 0)
+                             reg_order, 1 if complex_freq else 0)
 
 
 def make_batch(n_ext: int, out, *, ext=None, m2=None, m2_scalar: float = 0.0, Z=None,
@@ -440,7 +441,9 @@ class Context:
 
     def integrate(self, desc, out, *, ext=None, m2=None, m2_scalar=0.0, Z=None, x_min=1e-3,
                   x_max=1e3, err_out=None, dout=None, dz=None, stream=None):
-        b = make_batch(int(out.numel()), out, ext=ext, m2=m2, m2_scalar=m2_scalar, Z=Z,
+        # complex external frequencies: out holds Re then Im of each point
+        n_ext = int(out.numel()) // (2 if desc.complex_freq else 1)
+        b = make_batch(n_ext, out, ext=ext, m2=m2, m2_scalar=m2_scalar, Z=Z,
                        x_min=x_min, x_max=x_max, err_out=err_out, dout=dout, dz=dz)
         frg_integrate_batch(self.handle, desc, b, _stream(stream))
         return out
@@ -448,15 +451,17 @@ class Context:
     def integrate_noalloc(self, desc, out, *, ext=None, m2=None, m2_scalar=0.0, Z=None,
                           x_min=1e-3, x_max=1e3, err_out=None, dout=None, dz=None, stream=None):
         """frg_integrate_batch_noalloc: as integrate, scratch in the library's static array."""
-        b = make_batch(int(out.numel()), out, ext=ext, m2=m2, m2_scalar=m2_scalar, Z=Z,
+        # complex external frequencies: out holds Re then Im of each point
+        n_ext = int(out.numel()) // (2 if desc.complex_freq else 1)
+        b = make_batch(n_ext, out, ext=ext, m2=m2, m2_scalar=m2_scalar, Z=Z,
                        x_min=x_min, x_max=x_max, err_out=err_out, dout=dout, dz=dz)
         frg_integrate_batch_noalloc(self.handle, desc, b, _stream(stream))
         return out
 
     def autotune(self, desc, out, *, ext=None, m2=None, m2_scalar=0.0, Z=None, x_min=1e-3,
                  x_max=1e3, reps=3, stream=None):
-        b = make_batch(int(out.numel()), out, ext=ext, m2=m2, m2_scalar=m2_scalar, Z=Z,
-                       x_min=x_min, x_max=x_max)
+        b = make_batch(int(out.numel()) // (2 if desc.complex_freq else 1), out, ext=ext, m2=m2,
+                       m2_scalar=m2_scalar, Z=Z, x_min=x_min, x_max=x_max)
         return frg_autotune(self.handle, desc, b, _stream(stream), reps)
 
     def integrate_multi(self, descs, batches, stream=None):

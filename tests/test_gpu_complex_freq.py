@@ -1,0 +1,369 @@
+"""GPU parity of the complex external frequencies (finite-temperature two- and three-point
+families with complex_freq = 1: the inner legs' frequencies w_j + p0 + i p0i, the paper's
+external fermion legs at chemical potential p0f - i mu) against the FP64 oracle, through the
+C ABI.
+
+Bar: |I_gpu - I_oracle| <= 1e-12 |I_oracle| per point (complex modulus), bitwise equality across
+tile shapes, fused launches (the families' own instances and the general kernel), sessions and
+the no-allocation entry point; a zero imaginary part gives exactly zero imaginary results.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_13043_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2412_13043_amd import frg
+
+    ctx = frg.Context(0)
+    yield frg, ctx, torch
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _d(torch, a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), dtype=torch.float64,
+                        device="cuda")
+
+
+def _crel(got, ref):
+    return float(np.max(np.abs(got - ref) / np.abs(ref)))
+
+
+def _okind(reg):
+    return {0: oracle.REG_EXP, 1: oracle.reg_polyexp(8), 2: oracle.REG_LITIM}[reg]
+
+
+def _run(env, desc, n, *, ext, m2=None, m2_scalar=0.0, Z=None, ctx=None, noalloc=False,
+         err=False):
+    """Complex results (Re + i Im) of n points."""
+    frg, ctx0, torch = env
+    out = torch.full((2 * n,), float("nan"), dtype=torch.float64, device="cuda")
+    eo = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda") if err else None
+    c = ctx or ctx0
+    f = c.integrate_noalloc if noalloc else c.integrate
+    f(desc, out, ext=_d(torch, ext), m2=None if m2 is None else _d(torch, m2),
+      m2_scalar=m2_scalar, Z=None if Z is None else _d(torch, Z), x_min=wl.Z_XMIN,
+      x_max=wl.Z_XMAX, err_out=eo)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    if err:
+        assert np.all(eo.cpu().numpy() == 0.0)
+    return o[:n] + 1j * o[n:]
+
+
+def _mu_points(rng, n, T, stat, mu):
+    """Momenta over 5 decades, alpha in [0, pi], real leg frequencies as bosonic 2 pi T m or the
+    paper's soft fermionic p0f = pi T exp(-1/(pi T)) with a sign, and imaginary parts -mu or
+    +mu (the two leg orientations)."""
+    p = 10 ** rng.uniform(-3, 2, n)
+    alpha = rng.uniform(0.0, math.pi, n)
+    if stat == 0:
+        r1 = 2 * math.pi * T * rng.integers(-2, 3, n)
+        r2 = 2 * math.pi * T * rng.integers(-2, 3, n)
+    else:
+        soft = math.pi * T * math.exp(-1.0 / (math.pi * T))
+        r1 = soft * rng.choice([-1.0, 1.0], n)
+        r2 = soft * rng.choice([-1.0, 1.0], n)
+    i1 = mu * rng.choice([-1.0, 1.0], n)
+    i2 = mu * rng.choice([-1.0, 1.0], n)
+    return p, alpha, r1, r2, i1, i2
+
+
+def _oracle(desc, ext, **kw):
+    fam = oracle.THREE_POINT_T if desc.family == 6 else oracle.TWO_POINT_T
+    return oracle.integrate_ft_complex(fam, desc.n_q, desc.q_max, n_x=desc.n_x,
+                                       n_phi=desc.n_phi, k=desc.k, T=desc.T,
+                                       statistics=desc.statistics, freq_max=desc.freq_max,
+                                       freq_scaled=bool(desc.freq_scaled), n_tail=desc.n_tail,
+                                       regulator=_okind(desc.regulator), ext=ext, **kw)
+
+
+@pytest.mark.parametrize("stat", [0, 1])
+@pytest.mark.parametrize("n_ext,n_q,n_x,T,lam,n_tail,useZ,reg,mu", [
+    (37, 13, 6, 0.2, 6.0, 4, True, 0, 0.5),     # ragged external tile and cos1 rounds
+    (1, 1, 1, 1.0, 7.0, 0, False, 0, 0.3),      # smallest: one node per dimension
+    (130, 24, 16, 0.05, 2.0, 8, True, 1, 0.8),  # many frequencies, s_8
+    (64, 16, 9, 0.3, 5.0, 2, True, 2, 0.6),     # flat regulator
+])
+def test_two_point_complex_parity(env, stat, n_ext, n_q, n_x, T, lam, n_tail, useZ, reg, mu):
+    frg = env[0]
+    rng = np.random.default_rng(600 + n_ext + stat)
+    p, _, r1, _, i1, _ = _mu_points(rng, n_ext, T, stat, mu)
+    m2 = rng.uniform(-0.3, 2.0, n_ext)
+    Z = wl.dressing_table(9) if useZ else None
+    desc = frg.make_desc(frg.FRG_FAMILY_TWO_POINT_T, n_q, 10.0, n_x=n_x, T=T, freq_max=lam,
+                         statistics=stat, n_tail=n_tail, regulator=reg, complex_freq=True)
+    got = _run(env, desc, n_ext, ext=np.concatenate([p, r1, i1]), m2=m2, Z=Z, err=True)
+    ref = _oracle(desc, (p, r1, i1), m2=m2, Z=Z)
+    assert _crel(got, ref) <= TOL
+    assert np.max(np.abs(got.imag)) > 1e-6 * np.max(np.abs(got.real))  # not vacuous
+
+
+@pytest.mark.parametrize("stat", [0, 1])
+@pytest.mark.parametrize("n_ext,n_q,n_x,n_phi,T,lam,n_tail,useZ,reg,mu", [
+    (37, 9, 6, 5, 0.2, 6.0, 4, True, 0, 0.5),
+    (1, 1, 1, 1, 1.0, 7.0, 0, False, 0, 0.3),
+    (70, 12, 8, 7, 0.05, 2.0, 6, True, 1, 0.7),
+    (64, 16, 9, 4, 0.3, 5.0, 2, True, 2, 0.6),
+])
+def test_three_point_complex_parity(env, stat, n_ext, n_q, n_x, n_phi, T, lam, n_tail, useZ,
+                                    reg, mu):
+    frg = env[0]
+    rng = np.random.default_rng(700 + n_ext + stat)
+    pts = _mu_points(rng, n_ext, T, stat, mu)
+    m2 = rng.uniform(-0.3, 2.0, n_ext)
+    Z = wl.dressing_table(10) if useZ else None
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, n_q, 10.0, n_x=n_x, n_phi=n_phi, T=T,
+                         freq_max=lam, statistics=stat, n_tail=n_tail, regulator=reg,
+                         complex_freq=True)
+    got = _run(env, desc, n_ext, ext=np.concatenate(pts), m2=m2, Z=Z)
+    ref = _oracle(desc, pts, m2=m2, Z=Z)
+    assert _crel(got, ref) <= TOL
+    assert np.max(np.abs(got.imag)) > 1e-6 * np.max(np.abs(got.real))
+
+
+def test_complex_scale_and_scaled_domain(env):
+    frg = env[0]
+    k = 1.6
+    rng = np.random.default_rng(11)
+    n = 29
+    T = 0.15 * k
+    p, al, r1, r2, i1, i2 = _mu_points(rng, n, T, 1, 0.4 * k)
+    p = p * k
+    m2 = rng.uniform(-0.3, 1.5, n) * k * k
+    Z = wl.dressing_table(11)
+    for fam, ext in ((5, (p, r1, i1)), (6, (p, al, r1, r2, i1, i2))):
+        desc = frg.make_desc(fam, 14, 8.0, n_x=7, n_phi=6 if fam == 6 else 0, k=k, T=T,
+                             statistics=1, freq_max=5.0, n_tail=5, freq_scaled=True,
+                             complex_freq=True)
+        got = _run(env, desc, n, ext=np.concatenate(ext), m2=m2, Z=Z)
+        ref = _oracle(desc, ext, m2=m2, Z=Z)
+        assert _crel(got, ref) <= TOL, fam
+
+
+def test_zero_imaginary_part_matches_the_real_families(env):
+    frg = env[0]
+    rng = np.random.default_rng(12)
+    n = 45
+    p, al, r1, r2, _, _ = _mu_points(rng, n, 0.2, 0, 0.0)
+    z = np.zeros(n)
+    m2 = rng.uniform(-0.3, 1.5, n)
+    Z = wl.dressing_table(12)
+    kw = dict(T=0.2, freq_max=5.0, n_tail=3)
+    for fam, ext_c, ext_r in ((5, (p, r1, z), (p, r1)), (6, (p, al, r1, r2, z, z), (p, al, r1, r2))):
+        dc = frg.make_desc(fam, 10, 10.0, n_x=6, n_phi=5 if fam == 6 else 0, complex_freq=True,
+                           **kw)
+        dr = frg.make_desc(fam, 10, 10.0, n_x=6, n_phi=5 if fam == 6 else 0, **kw)
+        got = _run(env, dc, n, ext=np.concatenate(ext_c), m2=m2, Z=Z)
+        frg_, ctx, torch = env
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        ctx.integrate(dr, out, ext=_d(torch, np.concatenate(ext_r)), m2=_d(torch, m2),
+                      Z=_d(torch, Z), x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)
+        torch.cuda.synchronize()
+        real = out.cpu().numpy()
+        assert np.all(got.imag == 0.0), fam
+        assert np.max(np.abs(got.real - real) / real) < 1e-14, fam
+
+
+@pytest.mark.parametrize("fam", [5, 6])
+def test_complex_tile_shapes_give_identical_bits(env, tmp_path, monkeypatch, fam):
+    # the tile shape is looked up under the vacuum key (n_q n_f radial nodes)
+    frg, _, torch = env
+    n_q, n_x, n_phi, n = 5, 6, (4 if fam == 6 else 0), 37
+    kw = dict(T=0.3, freq_max=4.0, statistics=1, n_tail=2)
+    n_f = len(oracle.matsubara_rule(1, 0.3, 4.0, 2)[0])
+    rng = np.random.default_rng(78)
+    p, al, r1, r2, i1, i2 = _mu_points(rng, n, 0.3, 1, 0.5)
+    ext = (p, r1, i1) if fam == 5 else (p, al, r1, r2, i1, i2)
+    m2 = rng.uniform(-0.3, 2.0, n)
+    Z = wl.dressing_table(7)
+    desc = frg.make_desc(fam, n_q, 10.0, n_x=n_x, n_phi=n_phi, complex_freq=True, **kw)
+    target = 16 * torch.cuda.get_device_properties(0).multi_processor_count
+    vac = 2 if fam == 5 else 3
+    shapes = [(0, 1, 0), (0, 7, 0), (2, 1, 0), (3, 2, 0), (6, 1, 0), (0, 1, 2), (2, 1, 3),
+              (1, 4, 2)]
+    results = []
+    for lq, ch, lx in shapes:
+        cache = tmp_path / f"c{fam}_{lq}_{ch}_{lx}.txt"
+        cache.write_text(f"{vac} 0 {n_q * n_f} {n_x} {n_phi} {n} {target} {lq} {ch} {lx}\n")
+        monkeypatch.setenv("FRG_AUTOTUNE_CACHE", str(cache))
+        ctx = frg.Context(0)
+        try:
+            results.append(_run(env, desc, n, ext=np.concatenate(ext), m2=m2, Z=Z, ctx=ctx))
+        finally:
+            torch.cuda.synchronize()
+            ctx.close()
+    for o, shape in zip(results[1:], shapes[1:]):
+        assert np.array_equal(o, results[0]), shape
+    ref = _oracle(desc, ext, m2=m2, Z=Z)
+    assert _crel(results[0], ref) <= TOL
+
+
+def test_complex_fused_launches_and_no_alloc_bitwise(env):
+    """Complex requests in a fused launch of their own (their family instance), mixed with real
+    requests (the general kernel) and through the no-allocation entry point: the bits of each
+    request evaluated alone."""
+    frg, ctx, torch = env
+    rng = np.random.default_rng(22)
+    n = 50
+    p, al, r1, r2, i1, i2 = _mu_points(rng, n, 0.2, 0, 0.5)
+    Z = wl.dressing_table(4)
+    m2 = rng.uniform(-0.3, 1.5, n)
+    c5 = frg.make_desc(5, 16, 10.0, n_x=8, T=0.2, freq_max=6.0, n_tail=4, complex_freq=True)
+    c6 = frg.make_desc(6, 8, 10.0, n_x=6, n_phi=4, T=0.2, freq_max=6.0, n_tail=4,
+                       regulator=1, complex_freq=True)
+    e5 = np.concatenate([p, r1, i1])
+    e6 = np.concatenate([p, al, r1, r2, i1, i2])
+    real = [(frg.make_desc(2, 8, 10.0, n_x=4), p), (frg.make_desc(1, 32, 6.0), None),
+            (frg.make_desc(6, 6, 10.0, n_x=4, n_phi=3, T=0.1, freq_max=3.0, n_tail=2),
+             np.concatenate([p, al, r1, r2]))]
+    alone_c = [_run(env, c5, n, ext=e5, m2=m2, Z=Z), _run(env, c6, n, ext=e6, m2=m2, Z=Z)]
+    for d, e in ((c5, e5), (c6, e6)):
+        a = _run(env, d, n, ext=e, m2=m2, Z=Z, noalloc=True)
+        assert np.array_equal(a, alone_c[0 if d.family == 5 else 1])
+    alone_r = []
+    for d, e in real:
+        o = torch.empty(n, dtype=torch.float64, device="cuda")
+        ctx.integrate(d, o, ext=None if e is None else _d(torch, e), m2=_d(torch, m2),
+                      Z=_d(torch, Z), x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)
+        torch.cuda.synchronize()
+        alone_r.append(o.cpu().numpy())
+    tm, tz = _d(torch, m2), _d(torch, Z)
+    for mix in ([0, 1], [0, 1, 2, 3, 4]):
+        descs = [c5, c6] + [d for d, _ in real]
+        exts = [e5, e6] + [e for _, e in real]
+        sel = [descs[i] for i in mix]
+        keep = [None if exts[i] is None else _d(torch, exts[i]) for i in mix]
+        outs = [torch.full((2 * n if i < 2 else n,), float("nan"), dtype=torch.float64,
+                           device="cuda") for i in mix]
+        bs = [frg.make_batch(n, o, ext=k, m2=tm, Z=tz, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)
+              for o, k in zip(outs, keep)]
+        for rep in range(2):
+            ctx.integrate_multi(sel, bs)
+            torch.cuda.synchronize()
+            for j, i in enumerate(mix):
+                o = outs[j].cpu().numpy()
+                if i < 2:
+                    assert np.array_equal(o[:n] + 1j * o[n:], alone_c[i]), (mix, rep, i)
+                else:
+                    assert np.array_equal(o, alone_r[i - 2]), (mix, rep, i)
+
+
+def test_complex_benchmark_batch_sampled(env):
+    # the finite-temperature two-point batch with the legs' frequencies p0 - i mu (mu = 0.5):
+    # 16 right-hand sides x 256 momenta x 47 frequencies x 64 x 32, sampled against the oracle
+    frg, ctx, torch = env
+    p, p0, m2, Z = wl.two_point_ft_batch()
+    mu = 0.5
+    B = Z.shape[0]
+    desc = frg.make_desc(frg.FRG_FAMILY_TWO_POINT_T, wl.FT_NQ, wl.FT_QMAX, n_x=wl.FT_NX,
+                         T=wl.FT_T, freq_max=wl.FT_FREQ_MAX, n_tail=wl.FT_N_TAIL,
+                         complex_freq=True)
+    te = _d(torch, np.concatenate([p, p0, np.full(p.size, -mu)]))
+    tZ = _d(torch, Z)
+    out = torch.full((B, 2 * p.size), float("nan"), dtype=torch.float64, device="cuda")
+    batches = [frg.make_batch(p.size, out[b], ext=te, m2_scalar=m2, Z=tZ[b], x_min=wl.Z_XMIN,
+                              x_max=wl.Z_XMAX) for b in range(B)]
+    ctx.integrate_multi([desc] * B, batches)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    got = o[:, :p.size] + 1j * o[:, p.size:]
+    assert np.all(np.isfinite(got))
+    rng = np.random.default_rng(0)
+    for b in (0, B - 1):
+        idx = np.sort(rng.choice(p.size, 6, replace=False))
+        idx[0] = 0
+        ref = _oracle(desc, (p[idx], p0[idx], np.full(idx.size, -mu)), m2_scalar=m2, Z=Z[b])
+        assert _crel(got[b, idx], ref) <= TOL
+
+
+def test_session_serves_complex_requests(env):
+    frg, ctx, torch = env
+    rng = np.random.default_rng(32)
+    reqs = []
+    for i in range(6):
+        n = int(rng.integers(5, 90))
+        fam = 5 if i % 2 == 0 else 6
+        T = float(rng.uniform(0.1, 0.4))
+        p, al, r1, r2, i1, i2 = _mu_points(rng, n, T, i % 3 == 0, 0.4)
+        ext = np.concatenate([p, r1, i1] if fam == 5 else [p, al, r1, r2, i1, i2])
+        desc = frg.make_desc(fam, int(rng.integers(4, 16)), 10.0, n_x=int(rng.integers(2, 9)),
+                             n_phi=int(rng.integers(2, 6)) if fam == 6 else 0, T=T,
+                             freq_max=3.0, statistics=int(i % 3 == 0),
+                             n_tail=int(rng.integers(0, 4)), complex_freq=True)
+        reqs.append(dict(desc=desc, n=n, ext=ext, m2=rng.uniform(0.05, 2.0, n),
+                         Z=wl.dressing_table(80 + i), out=np.full(2 * n, np.nan),
+                         err=np.full(n, np.nan)))
+    # a real request beside them
+    pr = 10 ** rng.uniform(-3, 2, 40)
+    reqs.append(dict(desc=frg.make_desc(2, 12, 10.0, n_x=8), n=40, ext=pr,
+                     m2=rng.uniform(0.05, 2.0, 40), Z=wl.dressing_table(90),
+                     out=np.full(40, np.nan), err=np.full(40, np.nan)))
+    s = frg.frg_session_open(ctx.handle, frg.frg_session_config(3, 256 << 20, 20, 0))
+    tickets = []
+    for r in reqs:
+        zt = frg.frg_log_table(r["Z"].ctypes.data, r["Z"].size, wl.Z_XMIN, wl.Z_XMAX)
+        b = frg.frg_batch(r["n"], r["ext"].ctypes.data, r["m2"].ctypes.data, 0.0, zt,
+                          r["out"].ctypes.data, r["err"].ctypes.data)
+        tickets.append(frg.frg_session_submit(s, r["desc"], b, -1))
+    for t in tickets:
+        assert frg.frg_session_wait(s, t, 60000) == frg.FRG_OK
+    frg.frg_session_close(s)
+    for r in reqs[:-1]:
+        n = r["n"]
+        alone = _run(env, r["desc"], n, ext=r["ext"], m2=r["m2"], Z=r["Z"])
+        assert np.array_equal(r["out"][:n] + 1j * r["out"][n:], alone)
+        assert np.all(r["err"] == 0.0)
+    r = reqs[0]
+    n = r["n"]
+    ref = _oracle(r["desc"], (r["ext"][:n], r["ext"][n:2 * n], r["ext"][2 * n:]), m2=r["m2"],
+                  Z=r["Z"])
+    assert _crel(r["out"][:n] + 1j * r["out"][n:], ref) <= TOL
+
+
+def test_complex_rejections(env):
+    frg, ctx, torch = env
+    out = torch.zeros(8, dtype=torch.float64, device="cuda")
+    ext = torch.ones(24, dtype=torch.float64, device="cuda")
+    good = dict(n_x=4, T=0.2, freq_max=3.0, n_tail=2)
+    # float32 form and the derivatives are not implemented for complex frequencies
+    for kw, extra in ((dict(precision=1, near_pole_tau=0.1), {}),
+                      ({}, dict(dout=torch.zeros(4, dtype=torch.float64, device="cuda")))):
+        desc = frg.make_desc(5, 8, 6.0, complex_freq=True, **good, **kw)
+        with pytest.raises(frg.FrgError) as ei:
+            ctx.integrate(desc, out, ext=ext, m2_scalar=0.5, **extra)
+        assert ei.value.status == frg.FRG_E_UNSUPPORTED, kw
+    # the other families have no external frequency
+    for fam in (1, 2, 3, 4):
+        desc = frg.make_desc(fam, 8, 6.0, n_x=4, n_phi=3 if fam == 3 else 0,
+                             T=0.2 if fam == 4 else 0.0, freq_max=3.0 if fam == 4 else 0.0,
+                             complex_freq=True)
+        with pytest.raises(frg.FrgError) as ei:
+            ctx.integrate(desc, out, ext=ext, m2_scalar=0.5)
+        assert ei.value.status == frg.FRG_E_INVAL, fam
+    desc = frg.make_desc(5, 8, 6.0, **good)
+    desc.complex_freq = 2
+    with pytest.raises(frg.FrgError) as ei:
+        ctx.integrate(desc, out, ext=ext, m2_scalar=0.5)
+    assert ei.value.status == frg.FRG_E_INVAL
+    # no flow right-hand side or stepper for complex integrals
+    desc = frg.make_desc(5, 8, 6.0, complex_freq=True, **good)
+    state = torch.zeros(4, dtype=torch.float64, device="cuda")
+    dst = torch.zeros(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(frg.FrgError) as ei:
+        ctx.flow_rhs(desc, state, ext, dst)
+    assert ei.value.status == frg.FRG_E_UNSUPPORTED
+    with pytest.raises(frg.FrgError) as ei:
+        ctx.stepper(desc, state, ext)
+    assert ei.value.status == frg.FRG_E_UNSUPPORTED
