@@ -90,6 +90,8 @@ def _load():
                                                     I, D, D, I, I, P]
             lib.frgo_vertex_ft_spherical.argtypes = [I, I, I, D, D, I, I, D, D, I, I, P, P, D, D,
                                                      D, P, I, D, D, P]
+            lib.frgo_integrate_ft_three_dz.argtypes = [I, I, I, D, D, I, I, D, D, I, I, P, P, D,
+                                                       P, I, D, D, I, P]
             lib.frgo_integrate_ft_complex.argtypes = [I, I, I, I, D, D, I, I, D, D, I, I, P, P,
                                                       D, P, I, D, D, I, P]
             _lib = lib
@@ -209,6 +211,24 @@ def integrate_ft_dz(n_q, q_max, *, n_x, ext, Z, T, freq_max, statistics=BOSONIC,
                                       m2_scalar, _ptr(Za), len(Za), x_min, x_max, n, _ptr(out))
     if rc != 0:
         raise ValueError(f"frgo_integrate_ft_dz rejected the arguments (rc={rc})")
+    return out
+
+
+def integrate_ft_three_dz(n_q, q_max, *, n_x, n_phi, T, statistics=BOSONIC, freq_max,
+                          freq_scaled=False, n_tail=0, k=1.0, regulator=REG_EXP, ext, m2=None,
+                          m2_scalar=0.0, Z, x_min=1e-3, x_max=1e3):
+    """dI_e/dZ_i of the finite-temperature three-point integral: array [n_ext, len(Z)];
+    ext = (p, alpha, p01, p02)."""
+    ext_arr = np.concatenate([_f64(e) for e in ext])
+    n = len(ext[0])
+    Za, m2a = _f64(Z), _f64(m2)
+    out = np.empty((n, len(Za)))
+    rc = _load().frgo_integrate_ft_three_dz(n_q, n_x, n_phi, q_max, k, regulator, statistics, T,
+                                            freq_max, 1 if freq_scaled else 0, n_tail,
+                                            _ptr(ext_arr), _ptr(m2a), m2_scalar, _ptr(Za),
+                                            len(Za), x_min, x_max, n, _ptr(out))
+    if rc != 0:
+        raise ValueError(f"frgo_integrate_ft_three_dz rejected the arguments (rc={rc})")
     return out
 
 

@@ -660,6 +660,69 @@ int frgo_integrate_ft_three(int n_q, int n_x, int n_phi, double q_max, double k,
     return 0;
 }
 
+int frgo_integrate_ft_three_dz(int n_q, int n_x, int n_phi, double q_max, double k,
+                               int regulator, int statistics, double T, double freq_max,
+                               int freq_scaled, int n_tail, const double *ext, const double *m2,
+                               double m2_scalar, const double *Z, int nZ, double x_min,
+                               double x_max, int n_ext, double *out) {
+    if (n_ext < 0 || out == NULL || ext == NULL || Z == NULL || nZ < 1 || nZ > MAXN) return -1;
+    if (n_q < 1 || n_q > MAXN || n_x < 1 || n_x > MAXN || n_phi < 1 || n_phi > MAXN) return -1;
+    if (!(q_max > 0.0) || !(k > 0.0) || !(x_min > 0.0) || !(x_max > x_min)) return -1;
+    static __thread double qn[MAXN], qw[MAXN], xn[MAXN], xw[MAXN], fn[MAXN], fw[MAXN],
+        mw[MAXN], mc[MAXN];
+    static __thread nsum acc[MAXN];
+    double lambda = freq_scaled ? freq_max * k : freq_max;
+    int n_f = frgo_matsubara_rule(statistics, T, lambda, n_tail, MAXN, mw, mc);
+    if (n_f < 0) return -1;
+    frgo_gauss_legendre(n_q, 0.0, q_max * k, qn, qw);
+    frgo_gauss_legendre(n_x, -1.0, 1.0, xn, xw);
+    frgo_gauss_legendre(n_phi, 0.0, PI, fn, fw);
+    double pref = 2.0 / pow(2.0 * PI, 3.0);
+    for (int e = 0; e < n_ext; ++e) {
+        double p = ext[e], alpha = ext[n_ext + e], p01 = ext[2 * n_ext + e],
+               p02 = ext[3 * n_ext + e];
+        double ca = cos(alpha), sa = sin(alpha);
+        double mass = m2 ? m2[e] : m2_scalar;
+        for (int i = 0; i < nZ; ++i) acc[i].s = acc[i].c = 0.0;
+        for (int j = 0; j < n_f; ++j) {
+            double w = mw[j];
+            for (int a = 0; a < n_q; ++a) {
+                double q = qn[a], q2 = q * q;
+                double gq = ft_prop(regulator, Z, nZ, x_min, x_max, q2, w, mass, k);
+                int iq;
+                double fq;
+                dressing_cell(nZ, x_min, x_max, q2, &iq, &fq);
+                for (int b = 0; b < n_x; ++b) {
+                    double x = xn[b], sx = sqrt(1.0 - x * x);
+                    double l1 = q2 + p * p + 2.0 * q * p * x;
+                    if (l1 < 0.0) l1 = 0.0;
+                    double g1 = ft_prop(regulator, Z, nZ, x_min, x_max, l1, w + p01, mass, k);
+                    int i1;
+                    double f1;
+                    dressing_cell(nZ, x_min, x_max, l1, &i1, &f1);
+                    for (int c = 0; c < n_phi; ++c) {
+                        double l2 = q2 + p * p - 2.0 * q * p * (x * ca + sx * cos(fn[c]) * sa);
+                        if (l2 < 0.0) l2 = 0.0;
+                        double g2 = ft_prop(regulator, Z, nZ, x_min, x_max, l2, w + p02, mass, k);
+                        double cw = mc[j] * pref * qw[a] * xw[b] * fw[c] * q2 *
+                                    frgo_regulator_dot(regulator, q2, k);
+                        /* term = cw G(q^2)^2 G(l1) G(l2); dG(v)/dZ_i = -G(v)^2 v w_i(v) */
+                        add_dressing_weights(acc, nZ, iq, fq,
+                                             -2.0 * cw * gq * gq * gq * q2 * g1 * g2);
+                        add_dressing_weights(acc, nZ, i1, f1, -cw * gq * gq * g1 * g1 * l1 * g2);
+                        int i2;
+                        double f2;
+                        dressing_cell(nZ, x_min, x_max, l2, &i2, &f2);
+                        add_dressing_weights(acc, nZ, i2, f2, -cw * gq * gq * g1 * g2 * g2 * l2);
+                    }
+                }
+            }
+        }
+        for (int i = 0; i < nZ; ++i) out[(size_t)e * nZ + i] = nsum_get(&acc[i]);
+    }
+    return 0;
+}
+
 /* ---------------------------------------------------------------------------------------- */
 /* Complex external frequencies of the inner legs (families 5 and 6).                        */
 /* ---------------------------------------------------------------------------------------- */

@@ -175,6 +175,16 @@ int frgo_vertex_ft_spherical(int n_q, int n_t1, int n_t2, double q_max, double k
                              double p02, double m2, const double *Z, int nZ, double x_min,
                              double x_max, double *out);
 
+/* dI_e/dZ_i of the finite-temperature three-point integral (family 6), out[e * nZ + i]: the
+ * radial leg and both inner legs through the interpolation weights of their spatial momenta
+ * (dG(v)/dZ_i = -G(v)^2 v w_i(v)).  Arguments as frgo_integrate_ft_three without deriv; Z is
+ * required. */
+int frgo_integrate_ft_three_dz(int n_q, int n_x, int n_phi, double q_max, double k,
+                               int regulator, int statistics, double T, double freq_max,
+                               int freq_scaled, int n_tail, const double *ext, const double *m2,
+                               double m2_scalar, const double *Z, int nZ, double x_min,
+                               double x_max, int n_ext, double *out);
+
 /*
  * Complex external frequencies (families 5 and 6): the external frequency of an inner leg is
  * p0 = p0r + i p0i, as for the paper's external fermion legs at chemical potential mu, whose

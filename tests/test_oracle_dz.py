@@ -147,3 +147,33 @@ def test_dz_three_point_matches_central_differences(reg):
         assert np.all(np.abs(fd - J[:, i]) <= 1e-7 * scale + 1e-18), i
     fd = (I(Z + h) - I(Z - h)) / (2 * h)
     assert np.allclose(J.sum(axis=1), fd, rtol=1e-8, atol=0.0)
+
+
+@pytest.mark.parametrize("stat,reg", [(oracle.BOSONIC, oracle.REG_EXP),
+                                      (oracle.FERMIONIC, oracle.reg_polyexp(8)),
+                                      (oracle.BOSONIC, oracle.REG_LITIM)])
+def test_dz_three_point_finite_temperature_matches_central_differences(stat, reg):
+    # the finite-temperature three-point integral: radial leg and both inner legs, each with
+    # its own frequency shift
+    Z, p, m2 = _case(7, nZ=8, n=5)
+    alpha = np.array([0.0, 0.4, 1.5, 2.6, math.pi])
+    rng = np.random.default_rng(8)
+    p01, p02 = rng.uniform(-1.0, 1.0, p.size), rng.uniform(-1.0, 1.0, p.size)
+    kw = dict(n_x=5, n_phi=4, T=0.25, freq_max=3.0, statistics=stat, n_tail=2, x_min=XMIN,
+              x_max=XMAX, regulator=reg)
+
+    def I(Zv):
+        return oracle.integrate_ft(oracle.THREE_POINT_T, 6, Q_MAX, ext=(p, alpha, p01, p02),
+                                   m2=m2, Z=Zv, **kw)
+
+    J = oracle.integrate_ft_three_dz(6, Q_MAX, ext=(p, alpha, p01, p02), m2=m2, Z=Z, **kw)
+    h = 1e-5
+    scale = np.max(np.abs(J), axis=1)
+    for i in range(Z.size):
+        Zp, Zm = Z.copy(), Z.copy()
+        Zp[i] += h
+        Zm[i] -= h
+        fd = (I(Zp) - I(Zm)) / (2 * h)
+        assert np.all(np.abs(fd - J[:, i]) <= 1e-7 * scale + 1e-18), i
+    fd = (I(Z + h) - I(Z - h)) / (2 * h)
+    assert np.allclose(J.sum(axis=1), fd, rtol=1e-8, atol=0.0)
