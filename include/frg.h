@@ -130,8 +130,7 @@ typedef enum {
  *                    H1_j(l) = 1/((w_j + p01_e)^2 + Z(l^2) l^2 + R(l^2) + m2_e), H2_j with p02_e,
  *                    l1^2 = q^2 + p^2 + 2 q p x, l2^2 = q^2 + p^2 - 2 q p (x cos(alpha) +
  *                    sqrt(1-x^2) cos(phi) sin(alpha)) (spatial, as in family 3 with p1 = p e1,
- *                    p2 = p (cos(alpha) e1 + sin(alpha) e2)); float64 only (FRG_E_UNSUPPORTED
- *                    for the FP32 form);
+ *                    p2 = p (cos(alpha) e1 + sin(alpha) e2));
  *              in three spatial dimensions the cos1 weight is dx alone (no sqrt(1-x^2)) and the
  *              phi weight dphi alone (no sin(phi)); the azimuth runs over [0, 2pi) and the
  *              integrand is even in it, so phi GL(n_phi) on [0, pi] carries a factor 2
@@ -225,10 +224,10 @@ typedef struct {
                               Z enters through the linear interpolation of every propagator's
                               dressing, so dG(v)/dZ_i = -G(v)^2 v w_i(v) with w_i(v) the
                               interpolation weight of entry i at v; entries no node reaches are
-                              exactly 0.  The vertex families 2, 3 and 5 (at finite
+                              exactly 0.  The vertex families 2, 3, 5 and 6 (at finite
                               temperature the dressing multiplies the spatial momentum) in
                               float64 with a dressing table only (FRG_E_UNSUPPORTED for the
-                              LPA families, family 6 and the float32 form,
+                              LPA families, complex frequencies and the float32 form,
                               FRG_E_INVAL without a table), frg_integrate_batch and
                               frg_integrate_multi (FRG_E_UNSUPPORTED from sessions); the caller
                               owns the buffer.  Computed by a second kernel after the

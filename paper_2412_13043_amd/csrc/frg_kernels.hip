@@ -844,13 +844,14 @@ __device__ __forceinline__ Dual contrib_two(const ReqDev &r, const Smem &sm, int
 }
 
 template <int REG>
-__device__ __forceinline__ void xterm32(const ReqDev &r, const Smem &sm, const Par32 &P, int b,
-                                        double c0, double c1, double ca, double sa, float &kmax,
-                                        double &t, double &inner) {
+// P1 carries the first leg's mass, P the second's (the same in vacuum).
+__device__ __forceinline__ void xterm32(const ReqDev &r, const Smem &sm, const Par32 &P1,
+                                        const Par32 &P, int b, double c0, double c1, double ca,
+                                        double sa, float &kmax, double &t, double &inner) {
     const int nphi = r.n_phi;
     const double xb = kc(r.ang.x)[b];
     float l1[1] = {(float)fma(c1, xb, c0)}, g1[1];
-    propagators32<1, false, REG>(l1, g1, kmax, sm, P);
+    propagators32<1, false, REG>(l1, g1, kmax, sm, P1);
     const double A2 = fma(-c1, xb * ca, c0);
     const double B2 = -c1 * (kc(r.ang.xs)[b] * sa);
     Kahan32 acc{0.0f, 0.0f};
@@ -886,7 +887,6 @@ __device__ __forceinline__ void xterm32(const ReqDev &r, const Smem &sm, const P
 // midB = sum xw G1 sum G2^2 next to mid = sum xw G1 sum G2 (units of k^2).
 // m2 enters the radial leg, m2x1 and m2x2 the legs l1 and l2 (all equal in vacuum; at finite
 // temperature m2x_i = m2 + (w_j + p0i)^2, the radial leg's w_j^2 folded into the rule's R).
-// The float32 form is vacuum-only (m2x1 = m2x2 = m2).
 template <int PREC, int REG, bool DER>
 __device__ __forceinline__ Dual contrib_three(const ReqDev &r, const Smem &sm, int a, double p,
                                               double ca, double sa, double m2, double m2x1,
@@ -894,12 +894,15 @@ __device__ __forceinline__ Dual contrib_three(const ReqDev &r, const Smem &sm, i
                                               int sx, int lx) {
     RadialTerm t{0.0, 0.0, 0.0, 0.0};
     double c0 = 0.0, c1 = 0.0;
-    Par32 P;
+    Par32 P, P1;
     if (act) {
         t = radial64(r, sm, a, p, m2);
         c0 = t.c0 * inv_k2;
         c1 = t.c1 * inv_k2;
-        if (PREC == 1) P = par32(r, sm, m2, inv_k2);
+        if (PREC == 1) {
+            P1 = par32(r, sm, m2x1, inv_k2);
+            P = par32(r, sm, m2x2, inv_k2);
+        }
     }
     const double m2h1 = m2x1 * inv_k2, m2h2 = m2x2 * inv_k2;
     const int nx = r.n_x;
@@ -912,7 +915,7 @@ __device__ __forceinline__ Dual contrib_three(const ReqDev &r, const Smem &sm, i
             if (PREC == 0)
                 xterm64<REG, DER>(r, sm, b, c0, c1, ca, sa, m2h1, m2h2, tb, ib, gb, i2b);
             else
-                xterm32<REG>(r, sm, P, b, c0, c1, ca, sa, kmax, tb, ib);
+                xterm32<REG>(r, sm, P1, P, b, c0, c1, ca, sa, kmax, tb, ib);
         }
         if (lx == 1) {
             mid = fma(tb, ib, mid);
@@ -1180,7 +1183,7 @@ __device__ __forceinline__ Dual contrib_three_c(const ReqDev &r, const Smem &sm,
 // two propagators, 10u + 2 (eE + er).  Every integrand term is positive, so the bound of a term
 // bounds the integral.  First order in u; kappa is the computed one.
 __device__ __forceinline__ double fp32_bound(float kmax, float K, const ReqDev &r) {
-    const double nG = r.family == 3 ? 2.0 : 1.0;
+    const double nG = (r.family == 3 || r.family == 6) ? 2.0 : 1.0;
     return (6.0 + 2.0 * nG) * kU32 + nG * (kErrExpm1f + kErrRcpf) + nG * (double)kmax * (double)K;
 }
 
@@ -1623,7 +1626,7 @@ static batch_fn batch_variant(int fam, int prec, int reg, bool der) {
     if (fam == 1) return prec == 0 ? batch_kernel<1, 0, 0, false> : batch_kernel<1, 1, 0, false>;
     if (fam == 2) return batch_for_family<2>(prec, reg, der);
     if (fam == 5) return batch_for_family<5>(prec, reg, der);
-    if (fam == 6) return der ? batch_for_reg<6, true>(reg) : batch_for_reg<6, false>(reg);
+    if (fam == 6) return batch_for_family<6>(prec, reg, der);
     // complex frequencies: the imaginary part rides in the derivative's slot
     if (fam == 7) return batch_for_reg<7, true>(reg);
     if (fam == 8) return batch_for_reg<8, true>(reg);
@@ -1697,7 +1700,7 @@ __device__ __forceinline__ void multi_tile(const ReqDev &r, Smem &sm, const Tile
     else if (r.family == 5)
         vertex_tile_any<5, DER>(r, sm, td, contrib, counters);
     else if (r.family == 6)
-        vertex_tile_reg<6, DER>(r, sm, td, contrib, counters);  // float64 only
+        vertex_tile_any<6, DER>(r, sm, td, contrib, counters);
     else if (r.family == 3)
         vertex_tile_any<3, DER>(r, sm, td, contrib, counters);
     else if constexpr (DER) {
@@ -1709,15 +1712,17 @@ __device__ __forceinline__ void multi_tile(const ReqDev &r, Smem &sm, const Tile
     }
 }
 
-// Occupancy target of a fused-kernel instance: the three-point family and the general kernel
+// Occupancy target of a fused-kernel instance: the three-point families and the general kernel
 // carry more state than the two-point families, the mass derivative a second set of
 // accumulators, and the polynomial-exponential regulator's exponent a few more registers.  The
-// float32 form of the two-point families holds 4 (at 5 it spills).
+// float32 form of the two-point families holds 4 (at 5 it spills), that of the
+// finite-temperature three-point family (two legs' float32 constants) 3.
 constexpr int multi_waves(int fam, int prec, int reg, bool der) {
     return der ? ((fam < 0 || fam == 3 || fam == 6 || fam == 8) ? FRG_WAVES_PER_EU_DER3
                                                                 : FRG_WAVES_PER_EU_DER)
                : ((fam < 0 || fam == 3 || fam == 6)
-                      ? (reg == 1 ? FRG_WAVES_PER_EU_DER3 : FRG_WAVES_PER_EU_MULTI)
+                      ? ((reg == 1 || (fam == 6 && prec != 0)) ? FRG_WAVES_PER_EU_DER3
+                                                               : FRG_WAVES_PER_EU_MULTI)
                       : ((reg == 1 || prec != 0) ? FRG_WAVES_PER_EU_MULTI
                                                  : FRG_WAVES_PER_EU_BATCH));
 }
@@ -1797,7 +1802,7 @@ static multi_fn multi_variant(int fam, int prec, int reg, int der) {
     if (fam == 2) return multi_for_family<2>(prec, reg, der);
     if (fam == 3) return multi_for_family<3>(prec, reg, der);
     if (fam == 5) return multi_for_family<5>(prec, reg, der);
-    if (fam == 6) return der ? multi_for_reg<6, true>(reg) : multi_for_reg<6, false>(reg);
+    if (fam == 6) return multi_for_family<6>(prec, reg, der);
     if (fam == 7) return multi_for_reg<7, true>(reg);
     if (fam == 8) return multi_for_reg<8, true>(reg);
     return der ? multi_kernel<-1, -1, -1, true> : multi_kernel<-1, -1, -1, false>;
@@ -1912,28 +1917,37 @@ size_t dz_lds_bytes(int nZ) {
 }
 
 // Parts of one row, handed to part(entry, value): the runs of the innermost leg (lower and upper
-// entry of each run's cell), then the row's single-cell terms -- the radial leg and (FAM 3) the
-// first inner leg.  Values in the units of the point's sum before the prefactor.
+// entry of each run's cell), then the row's single-cell terms -- the radial leg and (FAM 3, 6)
+// the first inner leg.  Values in the units of the point's sum before the prefactor.  p0 and p02
+// are the inner legs' external frequencies (FAM 5: p0; FAM 6: p01 and p02).
 template <int FAM, int REG, typename Part>
 __device__ __forceinline__ void dz_row(const ReqDev &r, const Smem &sm, long long row, double p,
-                                       double ca, double sa, double p0, double m2, double inv_k2,
-                                       Part &&part) {
+                                       double ca, double sa, double p0, double p02, double m2,
+                                       double inv_k2, Part &&part) {
+    constexpr bool kThree = FAM == 3 || FAM == 6;
     const int nZ = r.nZ;
     const double zb1 = r.zbk + 1.0;
-    const int a = FAM == 3 ? (int)(row / r.n_x) : (int)row;
+    const int a = kThree ? (int)(row / r.n_x) : (int)row;
     const RadialTerm t = radial64(r, sm, a, p, m2);
     const double q = r.k * kc(r.rad.q)[a];
     const double q2 = q * q;
     const double c0 = t.c0 * inv_k2, c1 = t.c1 * inv_k2;
-    const double uf = FAM == 3 ? inv_k2 * inv_k2 : inv_k2;  // units of the inner sums
+    const double uf = kThree ? inv_k2 * inv_k2 : inv_k2;  // units of the inner sums
     double rw, A, B, mh, g1 = 0.0, l1 = 0.0, f1 = 0.0, xw = 0.0;
     int i1 = 0;
-    if (FAM == 3) {
+    if (kThree) {
         const int b = (int)(row - (long long)a * r.n_x);
         const double xb = kc(r.ang.x)[b];
-        mh = m2 * inv_k2;
+        double mh1 = m2 * inv_k2;
+        mh = mh1;
+        if (FAM == 6) {
+            // radial index a = (spatial node, frequency j): the legs carry w_j + p01, w_j + p02
+            const double w1 = kc(r.rad.w0)[a] + p0, w2 = kc(r.rad.w0)[a] + p02;
+            mh1 = fma(w1, w1, m2) * inv_k2;
+            mh = fma(w2, w2, m2) * inv_k2;
+        }
         l1 = fma(c1, xb, c0);
-        g1 = prop_cell64<REG>(l1, sm, nZ, r.za, zb1, mh, r.reg_n, i1, f1);
+        g1 = prop_cell64<REG>(l1, sm, nZ, r.za, zb1, mh1, r.reg_n, i1, f1);
         xw = kc(r.ang.xw)[b];
         rw = t.wg * (xw * g1);
         A = fma(-c1, xb * ca, c0);
@@ -1961,14 +1975,14 @@ __device__ __forceinline__ void dz_row(const ReqDev &r, const Smem &sm, long lon
             part(iz, f * v);
         }
     };
-    const int n_in = FAM == 3 ? r.n_phi : r.n_x;
+    const int n_in = kThree ? r.n_phi : r.n_x;
     double inner = 0.0, lo = 0.0, hi = 0.0;
     int cur = -1, prev = 0;
     for (int c = 0; c < n_in; ++c) {
-        const double u = FAM == 3 ? kc(r.phi.c)[c] : kc(r.ang.x)[c];
-        const double w = FAM == 3 ? kc(r.phi.w)[c] : kc(r.ang.xw)[c];
+        const double u = kThree ? kc(r.phi.c)[c] : kc(r.ang.x)[c];
+        const double w = kThree ? kc(r.phi.w)[c] : kc(r.ang.xw)[c];
         double l2 = fma(B, u, A);
-        if (FAM == 3) l2 = fmax(l2, FRG_L2_TINY);
+        if (kThree) l2 = fmax(l2, FRG_L2_TINY);
         int iz;
         double f;
         const double G = prop_cell64<REG>(l2, sm, nZ, r.za, zb1, mh, r.reg_n, iz, f);
@@ -2000,13 +2014,13 @@ __device__ __forceinline__ void dz_row(const ReqDev &r, const Smem &sm, long lon
     }
     if (cur > 0) part(cur - 1, lo);
     if (cur >= 0 && cur < nZ) part(cur, hi);
-    // radial leg -2 W G(q^2)^3 q^2 [xw G^(l1)] I (FAM 3 per (a, b), I = sum_c w_c G^(l2));
-    // FAM 3 first inner leg -W G(q^2)^2 xw G^(l1)^2 l1 I
+    // radial leg -2 W G(q^2)^3 q^2 [xw G^(l1)] I (FAM 3, 6 per (a, b), I = sum_c w_c G^(l2));
+    // FAM 3, 6 first inner leg -W G(q^2)^2 xw G^(l1)^2 l1 I
     int iq;
     double fq;
     dz_cell(sm, nZ, r.za, r.zb + 1.0, fmax(q2, FRG_L2_TINY), iq, fq);
     single(iq, fq, -2.0 * t.g * q2 * rw * (inner * uf));
-    if (FAM == 3) single(i1, f1, -t.wg * (xw * (g1 * g1)) * l1 * (inner * uf));
+    if (kThree) single(i1, f1, -t.wg * (xw * (g1 * g1)) * l1 * (inner * uf));
 }
 
 template <int FAM, int REG>
@@ -2018,7 +2032,7 @@ __global__ void __launch_bounds__(64 * kDzMaxWaves) dz_kernel(ReqDev r, double *
     const int nZ = r.nZ, e = (int)blockIdx.x;
     const int lane = (int)threadIdx.x & (kWave - 1), wv = (int)threadIdx.x / kWave;
     const int nw = (int)blockDim.x / kWave, nt = (int)blockDim.x;
-    const long long n_rows = FAM == 3 ? (long long)r.n_q * r.n_x : r.n_q;
+    const long long n_rows = (FAM == 3 || FAM == 6) ? (long long)r.n_q * r.n_x : r.n_q;
     bind_smem(sm, lds_dyn, nZ, f32c);
     unsigned long long *acc_hi = (unsigned long long *)(lds_dyn + kLogTable + nZ + 1);
     unsigned long long *acc_lo = acc_hi + nZ;
@@ -2029,18 +2043,22 @@ __global__ void __launch_bounds__(64 * kDzMaxWaves) dz_kernel(ReqDev r, double *
     for (int j = (int)threadIdx.x; j < 2 * nZ; j += nt) acc_hi[j] = 0ull;
     __syncthreads();
     const double p = fabs(r.ext[e]);
-    double ca = 1.0, sa = 0.0, p0 = 0.0;
-    if (FAM == 3) {
+    double ca = 1.0, sa = 0.0, p0 = 0.0, p02 = 0.0;
+    if (FAM == 3 || FAM == 6) {
         sincos(r.ext[r.n_ext + e], &sa, &ca);
         sa = fabs(sa);
     }
     if (FAM == 5) p0 = r.ext[r.n_ext + e];
+    if (FAM == 6) {
+        p0 = r.ext[2 * r.n_ext + e];
+        p02 = r.ext[3 * r.n_ext + e];
+    }
     const double m2 = lane_m2(r, e);
     const double inv_k2 = 1.0 / r.k2;
     // pass 1: the largest part (a NaN part makes P NaN)
     double mx = 0.0;
     for (long long row = threadIdx.x; row < n_rows; row += nt)
-        dz_row<FAM, REG>(r, sm, row, p, ca, sa, p0, m2, inv_k2, [&](int, double v) {
+        dz_row<FAM, REG>(r, sm, row, p, ca, sa, p0, p02, m2, inv_k2, [&](int, double v) {
             const double av = fabs(v);
             mx = (av > mx || av != av) ? av : mx;
         });
@@ -2059,7 +2077,7 @@ __global__ void __launch_bounds__(64 * kDzMaxWaves) dz_kernel(ReqDev r, double *
     if (exact) {
         // pass 2: the parts, exactly
         for (long long row = threadIdx.x; row < n_rows; row += nt)
-            dz_row<FAM, REG>(r, sm, row, p, ca, sa, p0, m2, inv_k2, [&](int j, double v) {
+            dz_row<FAM, REG>(r, sm, row, p, ca, sa, p0, p02, m2, inv_k2, [&](int j, double v) {
                 if (v == 0.0) return;
                 const double x = v * scale;
                 const double h = floor(x * 0x1p-32);
@@ -2085,10 +2103,12 @@ static void (*dz_for_reg(int reg))(ReqDev, double *) {
 
 hipError_t launch_dz(const ReqDev &r, double *jac, hipStream_t s) {
     if (r.n_ext <= 0) return hipSuccess;
-    if ((r.family != 2 && r.family != 3 && r.family != 5) || r.precision != 0 || r.nZ < 2 ||
-        r.n_x < 1 || (r.family == 3 && r.n_phi < 1))
+    const bool three = r.family == 3 || r.family == 6;
+    if ((r.family != 2 && r.family != 5 && !three) || r.precision != 0 || r.nZ < 2 ||
+        r.n_x < 1 || (three && r.n_phi < 1))
         return hipErrorInvalidValue;
     void (*fn)(ReqDev, double *) = r.family == 3   ? dz_for_reg<3>(r.reg)
+                                   : r.family == 6 ? dz_for_reg<6>(r.reg)
                                    : r.family == 5 ? dz_for_reg<5>(r.reg)
                                                    : dz_for_reg<2>(r.reg);
     // one workgroup per point, a row or more per lane; fewer wavefronts per workgroup when there
@@ -2097,7 +2117,7 @@ hipError_t launch_dz(const ReqDev &r, double *jac, hipStream_t s) {
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return hipGetLastError();
-    const long long n_rows = r.family == 3 ? (long long)r.n_q * r.n_x : r.n_q;
+    const long long n_rows = three ? (long long)r.n_q * r.n_x : r.n_q;
     int waves = (int)std::min<long long>(kDzMaxWaves, (n_rows + kWave - 1) / kWave);
     while (waves > 4 && (long long)r.n_ext * waves > 16LL * cus) waves /= 2;
     waves = std::max(1, waves);

@@ -197,15 +197,10 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
             return FRG_E_UNSUPPORTED;
         }
     }
-    if (d->family == FRG_FAMILY_THREE_POINT_T && d->precision != FRG_FP64) {
-        set_error("family 6 (three-point at finite temperature) is implemented in float64 only");
-        return FRG_E_UNSUPPORTED;
-    }
     if (b->dout_dz) {
-        if (!is_vertex(d->family) || d->family == FRG_FAMILY_THREE_POINT_T ||
-            d->precision != FRG_FP64) {
+        if (!is_vertex(d->family) || d->precision != FRG_FP64) {
             set_error("dout_dz (derivatives in the dressing-table entries) is implemented for "
-                      "the vertex families 2, 3 and 5 in float64 only");
+                      "the vertex families (2, 3, 5, 6) in float64 only");
             return FRG_E_UNSUPPORTED;
         }
         if (!b->Z.values) {

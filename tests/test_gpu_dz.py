@@ -1,5 +1,5 @@
-"""GPU derivatives of the vertex integrals (two-point in vacuum and at finite temperature,
-three-point) in their dressing-table entries (dout_dz, dI_e/dZ_i) against the FP64 oracle,
+"""GPU derivatives of the vertex integrals (two-point and three-point, in vacuum and at finite
+temperature) in their dressing-table entries (dout_dz, dI_e/dZ_i) against the FP64 oracle,
 entry by entry.
 
 Every term of an entry's sum has the same sign (W, the weights and G are positive at these
@@ -129,6 +129,49 @@ def test_dz_three_point_matches_oracle(env, reg, n, n_q, n_x, n_phi, nZ):
     ref_v = oracle.integrate(oracle.THREE_POINT, n_q, 10.0, n_x=n_x, n_phi=n_phi,
                              ext=(p, alpha), m2=m2, Z=Z, regulator=_okind(reg))
     assert np.max(np.abs(out.cpu().numpy() - ref_v) / np.abs(ref_v)) <= TOL
+
+
+@pytest.mark.parametrize("stat,reg", [(0, 0), (1, 1), (0, 2)])
+def test_dz_three_point_finite_temperature_matches_oracle(env, stat, reg):
+    # family 6: the radial index folds the frequencies in; each inner leg with its own shift
+    frg, ctx, torch = env
+    rng = np.random.default_rng(120 + stat + reg)
+    n, n_q, n_x, n_phi, nZ = 11, 8, 6, 5, 23
+    p = np.concatenate([[0.0, 400.0], 10 ** rng.uniform(-3, 2, n - 2)])
+    alpha = np.concatenate([[0.0, math.pi], rng.uniform(0.0, math.pi, n - 2)])
+    p01, p02 = rng.uniform(-1.0, 1.0, n), rng.uniform(-1.0, 1.0, n)
+    m2 = rng.uniform(0.1, 1.5, n)
+    Z = wl.dressing_table(130 + nZ, nZ)
+    ft = dict(T=0.25, freq_max=3.0, statistics=stat, n_tail=2)
+    out = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    jac = torch.full((n * nZ,), float("nan"), dtype=torch.float64, device="cuda")
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, n_q, 10.0, n_x=n_x, n_phi=n_phi,
+                         regulator=reg, **ft)
+    ext = np.concatenate([p, alpha, p01, p02])
+    ctx.integrate(desc, out, ext=_d(torch, ext), m2=_d(torch, m2), Z=_d(torch, Z),
+                  x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, dz=jac)
+    torch.cuda.synchronize()
+    ref = oracle.integrate_ft_three_dz(n_q, 10.0, n_x=n_x, n_phi=n_phi, ext=(p, alpha, p01, p02),
+                                       m2=m2, Z=Z, regulator=_okind(reg), x_min=wl.Z_XMIN,
+                                       x_max=wl.Z_XMAX, **ft)
+    _check(jac.cpu().numpy().reshape(n, nZ), ref)
+    ref_v = oracle.integrate_ft(oracle.THREE_POINT_T, n_q, 10.0, n_x=n_x, n_phi=n_phi,
+                                ext=(p, alpha, p01, p02), m2=m2, Z=Z, regulator=_okind(reg),
+                                **ft)
+    assert np.max(np.abs(out.cpu().numpy() - ref_v) / np.abs(ref_v)) <= TOL
+    # the same block from a fused launch beside a vacuum three-point request
+    out2 = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    jac2 = torch.full((n * nZ,), float("nan"), dtype=torch.float64, device="cuda")
+    o3 = torch.empty(n, dtype=torch.float64, device="cuda")
+    te, tm, tZ = _d(torch, ext), _d(torch, m2), _d(torch, Z)
+    t3 = _d(torch, np.concatenate([p, alpha]))
+    ctx.integrate_multi(
+        [desc, frg.make_desc(frg.FRG_FAMILY_THREE_POINT, 8, 10.0, n_x=6, n_phi=5)],
+        [frg.make_batch(n, out2, ext=te, m2=tm, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
+                        dz=jac2),
+         frg.make_batch(n, o3, ext=t3, m2=tm, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)])
+    torch.cuda.synchronize()
+    assert torch.equal(out2, out) and torch.equal(jac2, jac)
 
 
 def test_dz_two_point_workload_full_size(env):
@@ -283,10 +326,15 @@ def test_dz_unsupported_and_invalid(env):
               frg.FRG_E_UNSUPPORTED),
              (frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 8, 6.0, n_x=4, precision=1),
               frg.FRG_E_UNSUPPORTED),
-             (frg.make_desc(frg.FRG_FAMILY_LPA, 8, 6.0), frg.FRG_E_UNSUPPORTED)]
+             (frg.make_desc(frg.FRG_FAMILY_LPA, 8, 6.0), frg.FRG_E_UNSUPPORTED),
+             (frg.make_desc(frg.FRG_FAMILY_TWO_POINT_T, 8, 6.0, n_x=4, T=0.2, freq_max=3.0,
+                            complex_freq=True), frg.FRG_E_UNSUPPORTED)]
     for desc, status in cases:
+        # complex frequencies: out holds Re and Im of the n points
+        o = torch.zeros(2 * n, dtype=torch.float64, device="cuda") if desc.complex_freq else out
+        e = torch.ones(3 * n, dtype=torch.float64, device="cuda") if desc.complex_freq else ext
         with pytest.raises(frg.FrgError) as ei:
-            ctx.integrate(desc, out, ext=ext, m2_scalar=0.5, Z=Z, dz=jac)
+            ctx.integrate(desc, o, ext=e, m2_scalar=0.5, Z=Z, dz=jac)
         assert ei.value.status == status
     d2 = frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 8, 6.0, n_x=4)
     # no table: a batch built by hand (the binding checks the size against the table)

@@ -4,8 +4,8 @@ oracle, through the C ABI.
 
 Bar as for the other families: 1e-12 relative per external point for the value and its mass
 derivative, bitwise equality across tile shapes, fused launches (the family's own instance and
-the general kernel), flow right-hand sides and sessions; the float32 form and the dressing
-derivatives are refused with FRG_E_UNSUPPORTED.
+the general kernel), flow right-hand sides and sessions; the float32 form within its stated
+bound (the dressing derivatives are tested with the other families' in test_gpu_dz.py).
 """
 import math
 
@@ -336,25 +336,57 @@ def test_session_serves_three_point_ft(env):
     assert _rel(r["out"], ref) <= TOL
 
 
+@pytest.mark.parametrize("tau,reg", [(0.1, 0), (0.0, 0), (0.1, 1), (0.1, 2)])
+def test_three_point_ft_fp32_within_bound(env, tau, reg):
+    """The float32 form: every result within its stated bound of the oracle, masses near the
+    pole at the lowest frequencies (each leg's float32 constants carry its own shifted mass), and
+    the same bits (value and bound) from a fused launch beside a vacuum three-point request."""
+    frg, ctx, torch = env
+    n = 64
+    T = 0.1
+    rng = np.random.default_rng(900 + reg + int(10 * tau))
+    p, alpha, p01, p02 = _points(rng, n, T, 0)
+    lo = -0.9 if reg == 0 else -0.75  # the s_8 and flat poles sit closer
+    m2 = rng.uniform(lo, -0.5, n)
+    Z = wl.dressing_table(3)
+    kw = dict(T=T, freq_max=5.0, statistics=0, n_tail=4, regulator=reg)
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 16, 10.0, n_x=8, n_phi=6, precision=1,
+                         near_pole_tau=tau, **kw)
+    ext = np.concatenate([p, alpha, p01, p02])
+    te, tm, tZ = _d(torch, ext), _d(torch, m2), _d(torch, Z)
+    out = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    err = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.integrate(desc, out, ext=te, m2=tm, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, err_out=err)
+    torch.cuda.synchronize()
+    got, bound = out.cpu().numpy(), err.cpu().numpy()
+    ref = _oracle(desc, (p, alpha, p01, p02), m2=m2, Z=Z)
+    rel = np.abs(got - ref) / np.abs(ref)
+    assert np.all(rel <= bound), (rel / bound).max()
+    assert np.all(bound < 1e-3)
+    # fused beside a float32 vacuum three-point request (the general kernel: mixed families)
+    d3 = frg.make_desc(frg.FRG_FAMILY_THREE_POINT, 8, 10.0, n_x=6, n_phi=4, precision=1,
+                       near_pole_tau=tau, regulator=reg)
+    t3 = _d(torch, np.concatenate([p, alpha]))
+    o2, e2, o3 = (torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+                  for _ in range(3))
+    ctx.integrate_multi([desc, d3], [
+        frg.make_batch(n, o2, ext=te, m2=tm, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, err_out=e2),
+        frg.make_batch(n, o3, ext=t3, m2=tm, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)])
+    torch.cuda.synchronize()
+    assert torch.equal(o2, out) and torch.equal(e2, err)
+    # and in a launch of its own kind (the family's float32 instance)
+    ctx.integrate_multi([desc, desc], [
+        frg.make_batch(n, o2, ext=te, m2=tm, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, err_out=e2),
+        frg.make_batch(n, o3, ext=te, m2=tm, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX)])
+    torch.cuda.synchronize()
+    assert torch.equal(o2, out) and torch.equal(e2, err) and torch.equal(o3, out)
+
+
 def test_three_point_ft_rejections(env):
     frg, ctx, torch = env
     out = torch.zeros(4, dtype=torch.float64, device="cuda")
     ext = torch.ones(16, dtype=torch.float64, device="cuda")
-    Z = _d(torch, wl.dressing_table(3))
     good = dict(n_x=4, n_phi=3, T=0.2, freq_max=3.0, n_tail=2)
-    # the float32 form is not implemented for this family
-    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 8, 6.0, precision=1, near_pole_tau=0.1,
-                         **good)
-    with pytest.raises(frg.FrgError) as ei:
-        ctx.integrate(desc, out, ext=ext, m2_scalar=0.5)
-    assert ei.value.status == frg.FRG_E_UNSUPPORTED
-    # nor the dressing derivatives
-    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 8, 6.0, **good)
-    dz = torch.zeros(4 * Z.numel(), dtype=torch.float64, device="cuda")
-    with pytest.raises(frg.FrgError) as ei:
-        ctx.integrate(desc, out, ext=ext, m2_scalar=0.5, Z=Z, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
-                      dz=dz)
-    assert ei.value.status == frg.FRG_E_UNSUPPORTED
     # n_phi out of range, no ext, a bad frequency rule
     for kw in [dict(n_phi=0), dict(n_phi=frg.FRG_MAX_NODES + 1), dict(T=0.0)]:
         args = dict(good)
