@@ -289,6 +289,9 @@ def test_complex_benchmark_batch_sampled(env):
 
 
 def test_session_serves_complex_requests(env):
+    """Complex requests through a session (host buffers, out of 2 n values): small ones of both
+    families, one split into parts, and a real request beside them; each the bits of the request
+    evaluated alone."""
     frg, ctx, torch = env
     rng = np.random.default_rng(32)
     reqs = []
@@ -305,6 +308,15 @@ def test_session_serves_complex_requests(env):
         reqs.append(dict(desc=desc, n=n, ext=ext, m2=rng.uniform(0.05, 2.0, n),
                          Z=wl.dressing_table(80 + i), out=np.full(2 * n, np.nan),
                          err=np.full(n, np.nan)))
+    # above one launch's node budget: 1024 pairs x 32 radial x 47 frequencies x 16 x 16 =
+    # 3.9e8 nodes, evaluated in parts (each part's imaginary parts at its own offset)
+    P, A, p01, p02, m2b, Zb = wl.three_point_ft_batch(1)
+    nb = P.size
+    big = frg.make_desc(6, 32, wl.THREE_QMAX, n_x=16, n_phi=16, T=wl.FT_T,
+                        freq_max=wl.FT_FREQ_MAX, n_tail=wl.FT_N_TAIL, complex_freq=True)
+    reqs.append(dict(desc=big, n=nb, ext=np.concatenate([P, A, p01, p02, np.full(nb, -0.5),
+                                                         np.full(nb, 0.5)]),
+                     m2=m2b[0], Z=Zb[0], out=np.full(2 * nb, np.nan), err=np.full(nb, np.nan)))
     # a real request beside them
     pr = 10 ** rng.uniform(-3, 2, 40)
     reqs.append(dict(desc=frg.make_desc(2, 12, 10.0, n_x=8), n=40, ext=pr,
