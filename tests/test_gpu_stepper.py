@@ -105,6 +105,43 @@ def test_two_point_flow_stepper_matches_oracle(env):
     st.close()
 
 
+def test_finite_temperature_three_point_flow_stepper_matches_oracle(env):
+    # the three-point vertex flow at finite temperature (state m2 per (p, alpha) point, each
+    # inner leg with its own frequency shift), the frequency rule rebuilt at every stage's k
+    frg, ctx, torch = env
+    rng = np.random.default_rng(14)
+    n = 24
+    p = 10 ** rng.uniform(-2, 1, n)
+    alpha = rng.uniform(0.0, math.pi, n)
+    p01 = 2 * math.pi * 0.2 * rng.integers(-1, 2, n)
+    p02 = 2 * math.pi * 0.2 * rng.integers(-1, 2, n)
+    Z = wl.dressing_table(9)
+    m0 = rng.uniform(0.2, 1.5, n)
+    lam, coef, floor = 1.5, 4.0, -0.5
+    ft = dict(T=0.2, freq_max=4.0, statistics=0, n_tail=3)
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 8, 8.0, n_x=5, n_phi=4, k=lam, **ft)
+    state = _d(torch, m0)
+    grid, tZ = _d(torch, np.concatenate([p, alpha, p01, p02])), _d(torch, Z)
+    cfg = dict(rtol=1e-9, atol=1e-11, h0=0.02, h_min=1e-8, h_max=0.5, max_steps=10000)
+    st = ctx.stepper(desc, state, grid, Z=tZ, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
+                     m2_floor=floor, coef=coef, **cfg)
+
+    def f(t, m):
+        k = lam * math.exp(-t)
+        fl = floor * (k / lam) ** 2
+        return coef * oracle.integrate_ft(oracle.THREE_POINT_T, 8, 8.0, n_x=5, n_phi=4, k=k,
+                                          ext=(p, alpha, p01, p02), m2=np.maximum(m, fl), Z=Z,
+                                          **ft)
+
+    ref = rk.Dopri5(f, m0, **cfg)
+    rc, stats = st.advance(0.6)
+    assert ref.advance(0.6) == "ok"
+    assert (stats.accepted, stats.rejected) == (ref.accepted, ref.rejected)
+    got = state.cpu().numpy()
+    assert np.max(np.abs(got - ref.y) / np.abs(ref.y)) <= 1e-11
+    st.close()
+
+
 def test_finite_temperature_lpa_stepper_with_k_scaled_frequencies(env):
     # x0 frequency domain: Lambda_w = 6 k shrinks with k, so the number of Matsubara
     # frequencies changes during the run
