@@ -415,6 +415,17 @@ def make_batch(n_ext: int, out, *, ext=None, m2=None, m2_scalar: float = 0.0, Z=
                      _dptr(dout), _dptr(dz))
 
 
+def _n_points(desc, out) -> int:
+    """External points of a call whose results go to `out`: with complex external frequencies
+    out holds the real parts followed by the imaginary parts (2 values per point)."""
+    n = int(out.numel())
+    if desc.complex_freq:
+        if n % 2:
+            raise ValueError("with complex frequencies out holds 2 values per point (Re, Im)")
+        return n // 2
+    return n
+
+
 class Context:
     """Owns one frg_context on a HIP device."""
 
@@ -441,8 +452,7 @@ class Context:
 
     def integrate(self, desc, out, *, ext=None, m2=None, m2_scalar=0.0, Z=None, x_min=1e-3,
                   x_max=1e3, err_out=None, dout=None, dz=None, stream=None):
-        # complex external frequencies: out holds Re then Im of each point
-        n_ext = int(out.numel()) // (2 if desc.complex_freq else 1)
+        n_ext = _n_points(desc, out)
         b = make_batch(n_ext, out, ext=ext, m2=m2, m2_scalar=m2_scalar, Z=Z,
                        x_min=x_min, x_max=x_max, err_out=err_out, dout=dout, dz=dz)
         frg_integrate_batch(self.handle, desc, b, _stream(stream))
@@ -451,8 +461,7 @@ class Context:
     def integrate_noalloc(self, desc, out, *, ext=None, m2=None, m2_scalar=0.0, Z=None,
                           x_min=1e-3, x_max=1e3, err_out=None, dout=None, dz=None, stream=None):
         """frg_integrate_batch_noalloc: as integrate, scratch in the library's static array."""
-        # complex external frequencies: out holds Re then Im of each point
-        n_ext = int(out.numel()) // (2 if desc.complex_freq else 1)
+        n_ext = _n_points(desc, out)
         b = make_batch(n_ext, out, ext=ext, m2=m2, m2_scalar=m2_scalar, Z=Z,
                        x_min=x_min, x_max=x_max, err_out=err_out, dout=dout, dz=dz)
         frg_integrate_batch_noalloc(self.handle, desc, b, _stream(stream))
@@ -460,8 +469,8 @@ class Context:
 
     def autotune(self, desc, out, *, ext=None, m2=None, m2_scalar=0.0, Z=None, x_min=1e-3,
                  x_max=1e3, reps=3, stream=None):
-        b = make_batch(int(out.numel()) // (2 if desc.complex_freq else 1), out, ext=ext, m2=m2,
-                       m2_scalar=m2_scalar, Z=Z, x_min=x_min, x_max=x_max)
+        b = make_batch(_n_points(desc, out), out, ext=ext, m2=m2, m2_scalar=m2_scalar, Z=Z,
+                       x_min=x_min, x_max=x_max)
         return frg_autotune(self.handle, desc, b, _stream(stream), reps)
 
     def integrate_multi(self, descs, batches, stream=None):
