@@ -379,3 +379,44 @@ def test_complex_rejections(env):
     with pytest.raises(frg.FrgError) as ei:
         ctx.stepper(desc, state, ext)
     assert ei.value.status == frg.FRG_E_UNSUPPORTED
+
+
+def test_random_shapes_against_oracle(env):
+    """Twenty seeded random requests of both families with complex frequencies and of family 6
+    with real ones (n_ext, node counts, statistics, regulator, temperature, tail, dressing),
+    each at 1e-12 of the oracle: whatever tile shape the heuristics pick for them."""
+    frg = env[0]
+    rng = np.random.default_rng(2024)
+    for case in range(20):
+        fam = 5 if case % 3 == 0 else 6
+        cplx = case % 3 != 2
+        n = int(rng.integers(1, 150))
+        n_q, n_x = int(rng.integers(1, 20)), int(rng.integers(1, 12))
+        n_phi = int(rng.integers(1, 9)) if fam == 6 else 0
+        stat, reg = int(rng.integers(0, 2)), int(rng.integers(0, 3))
+        T = float(rng.uniform(0.05, 0.6))
+        kw = dict(T=T, freq_max=float(rng.uniform(1.0, 6.0)) + 2 * math.pi * T,
+                  statistics=stat, n_tail=int(rng.integers(0, 6)), regulator=reg)
+        p, al, r1, r2, i1, i2 = _mu_points(rng, n, T, stat, 0.5 if cplx else 0.0)
+        m2 = rng.uniform(-0.2, 2.0, n)
+        Z = wl.dressing_table(300 + case) if case % 4 else None
+        desc = frg.make_desc(fam, n_q, 10.0, n_x=n_x, n_phi=n_phi, complex_freq=cplx, **kw)
+        if fam == 5:
+            ext = (p, r1, i1)
+        else:
+            ext = (p, al, r1, r2, i1, i2) if cplx else (p, al, r1, r2)
+        if cplx:
+            got = _run(env, desc, n, ext=np.concatenate(ext), m2=m2, Z=Z)
+            ref = _oracle(desc, ext, m2=m2, Z=Z)
+        else:
+            frg_, ctx, torch = env
+            out = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+            ctx.integrate(desc, out, ext=_d(torch, np.concatenate(ext)), m2=_d(torch, m2),
+                          Z=None if Z is None else _d(torch, Z), x_min=wl.Z_XMIN,
+                          x_max=wl.Z_XMAX)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            ref = oracle.integrate_ft(oracle.THREE_POINT_T, n_q, 10.0, n_x=n_x, n_phi=n_phi,
+                                      ext=ext, m2=m2, Z=Z, regulator=_okind(reg), **{
+                                          k: v for k, v in kw.items() if k != "regulator"})
+        assert _crel(got, ref) <= TOL, (case, fam, cplx, n, n_q, n_x, n_phi)
