@@ -98,7 +98,8 @@ def test_fp32_chunked_slots_then_smaller(env):
                          order=("batch", "noalloc")))
 
 
-@pytest.mark.parametrize("case", ["lpa", "two_point_dm2_dz", "finite_T", "lpa_T"])
+@pytest.mark.parametrize("case", ["lpa", "two_point_dm2_dz", "finite_T", "lpa_T",
+                                  "three_point_T_dm2_dz"])
 def test_families_two_calls(env, case):
     frg, torch = env
     rng = np.random.default_rng(3)
@@ -118,6 +119,14 @@ def test_families_two_calls(env, case):
                                      statistics=1)
                 p0 = np.pi * 0.2 * np.exp(-1.0 / (np.pi * 0.2)) * np.ones(n)
                 res = _both(env, ctx, desc, n, ext=np.concatenate([p, p0]), m2=m2, Z=Z)
+            elif case == "three_point_T_dm2_dz":
+                desc = frg.make_desc(6, nq // 4, 10.0, n_x=nx // 2, n_phi=6, T=0.2,
+                                     freq_max=6.0, n_tail=3)
+                al = rng.uniform(0.0, np.pi, n)
+                p01 = 2 * np.pi * 0.2 * rng.integers(-1, 2, n)
+                p02 = 2 * np.pi * 0.2 * rng.integers(-1, 2, n)
+                res = _both(env, ctx, desc, n, ext=np.concatenate([p, al, p01, p02]), m2=m2,
+                            Z=Z, dm2=True, dz=True)
             else:
                 desc = frg.make_desc(4, nq, 6.0, T=0.1, freq_max=8.0, freq_scaled=True)
                 res = _both(env, ctx, desc, n, m2=m2)
