@@ -41,7 +41,8 @@ FP32_PEAK_TFLOPS = 157.3  # packed FP32 (v_pk_fma_f32); unpacked float32 tops ou
 # FP64 FLOP counter of one dispatch per sequence, less the bare loop, per call; summary and
 # command in profiles/flop_probe.md): table log 12, expm1(-y) 29, Newton reciprocal 5.  Around
 # them each family's node term adds plain arithmetic, counted from its code:
-#   LPA:         the denominator 2 FMAs (4), the reciprocal, its square (1), accumulate (2);
+#   LPA:         the denominator (1: the rule holds q^2 + R per node, the mass enters in units
+#                of k^2), the reciprocal, its square (1), accumulate (2);
 #   two-point:   l^2 (2), the log, the dressing coordinate (2) and lerp (3), expm1, l^2 e (2),
 #                the single-reciprocal denominator (4), the reciprocal, -E x (1), accumulate
 #                (2) -- 16 + log + expm1 + reciprocal;
@@ -51,7 +52,7 @@ FP32_PEAK_TFLOPS = 157.3  # packed FP32 (v_pk_fma_f32); unpacked float32 tops ou
 #                4/n_phi of per-pair geometry.
 SEQ_FLOP = {"log": 12.0, "expm1": 29.0, "rcp": 5.0}
 _PROP = SEQ_FLOP["log"] + 2.0 + 3.0 + SEQ_FLOP["expm1"] + 2.0 + 4.0 + SEQ_FLOP["rcp"] + 1.0
-FLOP_LPA = 4.0 + SEQ_FLOP["rcp"] + 1.0 + 2.0
+FLOP_LPA = 1.0 + SEQ_FLOP["rcp"] + 1.0 + 2.0
 FLOP_TWO = 2.0 + _PROP + 2.0
 
 

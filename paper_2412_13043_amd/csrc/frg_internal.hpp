@@ -25,6 +25,7 @@ struct RadialRule {
     const double *q, *W, *R;
     const float *qf, *Wf, *Rf;
     const double *w0;
+    const double *A;  // q^2 + R per entry (the LPA denominator in units of k^2, less m2/k^2)
 };
 struct AngleRule {
     const double *x, *xw, *xs;
@@ -98,6 +99,9 @@ hipError_t launch_rules(int n_q, double q_max, int d, int n_x, int n_phi, double
 // Finite-temperature radial rule (see RadialRule) from a d = 3 vacuum rule `base` of n_q nodes:
 // n_f frequencies, the first and last n_tail of them the tail nodes +-Omega/t (t GL on [0, 1],
 // weight Omega w_t/(2 pi t^2)), the rest 2 pi T (n + eta) for n = n_lo, n_lo + 1, ... (weight T).
+// A[i] = fma(q[i], q[i], R[i]) for i < n (a radial rule's per-entry q^2 + R).
+hipError_t launch_rule_sum(const double *q, const double *R, double *A, long long n,
+                           hipStream_t s);
 hipError_t launch_ft_rule(int n_q, int n_f, int n_tail, int n_lo, double eta, double T,
                           double Omega, double k, const RadialRule &base, double *q, double *W,
                           double *R, float *qf, float *Wf, float *Rf, double *w0, hipStream_t s);

@@ -214,6 +214,20 @@ __global__ void __launch_bounds__(64) ft_rule_kernel(
     w0[i] = w;
 }
 
+__global__ void __launch_bounds__(256) rule_sum_kernel(const double *q, const double *R,
+                                                      double *A, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) A[i] = fma(q[i], q[i], R[i]);
+}
+
+hipError_t launch_rule_sum(const double *q, const double *R, double *A, long long n,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rule_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, q, R,
+                       A, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_ft_rule(int n_q, int n_f, int n_tail, int n_lo, double eta, double T,
                           double Omega, double k, const RadialRule &base, double *q, double *W,
                           double *R, float *qf, float *Wf, float *Rf, double *w0, hipStream_t s) {
@@ -1317,16 +1331,18 @@ __device__ __forceinline__ double lpa_integral(const ReqDev &r, double m2, doubl
                                                double *dv = nullptr) {
     const int nq = r.n_q;
     if (PREC == 0) {
+        // in units of k^2: G^ = 1/(A_a + m2/k^2) = k^2 G with A_a = q^2 + R per rule entry (one
+        // add per node), the k^-4 of G^2 (k^-6 of G^3) applied once at the end
+        const double ik2 = 1.0 / r.k2, m2h = m2 * ik2;
         double acc = 0.0;
         if (dv) {
             double dacc = 0.0;
             for (int a = 0; a < nq; ++a) {
-                const double qh = kc(r.rad.q)[a];
-                const double g = fm::rcp_nr(fma(r.k2, fma(qh, qh, kc(r.rad.R)[a]), m2));
+                const double g = fm::rcp_nr(kc(r.rad.A)[a] + m2h);
                 acc = fma(kc(r.rad.W)[a], g * g, acc);
                 dacc = fma(kc(r.rad.W)[a], g * g * g, dacc);
             }
-            *dv = r.pref * (-2.0 * dacc);
+            *dv = r.pref * (-2.0 * (dacc * (ik2 * ik2 * ik2)));
         } else {
             // blocks of 8 radial nodes: the 8 reciprocals are independent and overlap, then
             // enter the sum in radial order (the same additions as one node at a time)
@@ -1336,21 +1352,19 @@ __device__ __forceinline__ double lpa_integral(const ReqDev &r, double m2, doubl
                 double g2[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const double qh = kc(r.rad.q)[a + u];
-                    const double g = fm::rcp_nr(fma(r.k2, fma(qh, qh, kc(r.rad.R)[a + u]), m2));
+                    const double g = fm::rcp_nr(kc(r.rad.A)[a + u] + m2h);
                     g2[u] = g * g;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) acc = fma(kc(r.rad.W)[a + u], g2[u], acc);
             }
             for (; a < nq; ++a) {
-                const double qh = kc(r.rad.q)[a];
-                const double g = fm::rcp_nr(fma(r.k2, fma(qh, qh, kc(r.rad.R)[a]), m2));
+                const double g = fm::rcp_nr(kc(r.rad.A)[a] + m2h);
                 acc = fma(kc(r.rad.W)[a], g * g, acc);
             }
         }
         err = 0.0;
-        return r.pref * acc;
+        return r.pref * (acc * (ik2 * ik2));
     }
     // float32 terms, compensated float32 sum; near-pole denominators in float64
     const float k2f = (float)r.k2, m2f = (float)m2, tau = (float)r.tau;

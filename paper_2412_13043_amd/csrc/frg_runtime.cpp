@@ -267,21 +267,29 @@ frg_status validate(const frg_integral_desc *d, const frg_batch *b, bool device_
 // ---------------------------------------------------------------------------------------------
 // Rule cache
 // ---------------------------------------------------------------------------------------------
+// Radial rule layout: q, W, R (float64), qf, Wf, Rf (float32; finite temperature: w0 before
+// them), then A = q^2 + R (float64, 8-byte aligned after the floats).
+static size_t radial_rule_bytes(int n);
+static double *after_floats(float *end) {
+    return (double *)(((uintptr_t)end + 7) & ~(uintptr_t)7);
+}
+
 static frg_status get_radial(frg_context *ctx, int n, double q_max, int d, int reg, int reg_n,
                              RadialRule *out) {
     auto key = std::make_tuple(n, q_max, d, reg, reg_n);
     auto it = ctx->radial.find(key);
     if (it == ctx->radial.end()) {
         auto e = std::make_unique<RadialEntry>();
-        size_t nb = (size_t)n * (3 * sizeof(double) + 3 * sizeof(float)) + 64;
-        FRG_HIP_CHECK(e->buf.alloc(nb));
+        FRG_HIP_CHECK(e->buf.alloc(radial_rule_bytes(n)));
         double *q = (double *)e->buf.ptr, *W = q + n, *R = W + n;
         float *qf = (float *)(R + n), *Wf = qf + n, *Rf = Wf + n;
+        double *A = after_floats(Rf + n);
         FRG_HIP_CHECK(launch_rules(n, q_max, d, 0, 0, q, W, R, qf, Wf, Rf, nullptr, nullptr,
                                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                    nullptr, ctx->aux, false, reg, reg_n));
+        FRG_HIP_CHECK(launch_rule_sum(q, R, A, n, ctx->aux));
         FRG_HIP_CHECK(hipStreamSynchronize(ctx->aux));
-        e->rule = RadialRule{q, W, R, qf, Wf, Rf, nullptr};
+        e->rule = RadialRule{q, W, R, qf, Wf, Rf, nullptr, A};
         it = ctx->radial.emplace(key, std::move(e)).first;
     }
     *out = it->second->rule;
@@ -308,7 +316,7 @@ static frg_status get_cos1(frg_context *ctx, int n, AngleRule *out, bool plain =
 }
 
 size_t ft_rule_bytes(int n_q, int n_f) {
-    return (size_t)n_q * (size_t)n_f * (4 * sizeof(double) + 3 * sizeof(float)) + 64;
+    return (size_t)n_q * (size_t)n_f * (5 * sizeof(double) + 3 * sizeof(float)) + 64;
 }
 
 frg_status ft_rule_into(frg_context *ctx, const frg_integral_desc &d, void *buf, size_t bytes,
@@ -329,9 +337,11 @@ frg_status ft_rule_into(frg_context *ctx, const frg_integral_desc &d, void *buf,
     const size_t n = (size_t)d.n_q * (size_t)f.n_f;
     double *q = (double *)buf, *W = q + n, *R = W + n, *w0 = R + n;
     float *qf = (float *)(w0 + n), *Wf = qf + n, *Rf = Wf + n;
+    double *A = after_floats(Rf + n);
     FRG_HIP_CHECK(launch_ft_rule(d.n_q, f.n_f, f.n_tail, f.n_lo, f.eta, f.T, f.Omega, d.k, base, q,
                                  W, R, qf, Wf, Rf, w0, s));
-    *out = RadialRule{q, W, R, qf, Wf, Rf, w0};
+    FRG_HIP_CHECK(launch_rule_sum(q, R, A, (long long)n, s));
+    *out = RadialRule{q, W, R, qf, Wf, Rf, w0, A};
     return FRG_OK;
 }
 
@@ -374,7 +384,7 @@ static frg_status get_phi(frg_context *ctx, int n, PhiRule *out, bool plain = fa
 }
 
 static size_t radial_rule_bytes(int n) {
-    return (size_t)n * (3 * sizeof(double) + 3 * sizeof(float)) + 64;
+    return (size_t)n * (4 * sizeof(double) + 3 * sizeof(float)) + 64;
 }
 static size_t cos1_rule_bytes(int n) {
     return (size_t)n * (3 * sizeof(double) + 3 * sizeof(float)) + 64;
@@ -437,10 +447,12 @@ frg_status rules_into(frg_context *ctx, const frg_integral_desc &d, void *buf, s
     const int rd = is_ft(d.family) ? 3 : d.d;
     double *q = (double *)p, *W = q + n, *R = W + n;
     float *qf = (float *)(R + n), *Wf = qf + n, *Rf = Wf + n;
+    double *A = after_floats(Rf + n);
     FRG_HIP_CHECK(launch_rules(n, d.q_max, rd, 0, 0, q, W, R, qf, Wf, Rf, nullptr, nullptr,
                                nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                nullptr, s, false, d.regulator, reg_order(d)));
-    RadialRule base{q, W, R, qf, Wf, Rf, nullptr};
+    FRG_HIP_CHECK(launch_rule_sum(q, R, A, n, s));
+    RadialRule base{q, W, R, qf, Wf, Rf, nullptr, A};
     p += up256(radial_rule_bytes(n));
     if (is_ft(d.family)) {
         FreqRule f;
