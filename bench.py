@@ -62,7 +62,7 @@ def flop_three(n_phi):
 
 # the standard workloads' three-point rule has 16 phi nodes
 FLOP_PER_NODE = {1: FLOP_LPA, 2: FLOP_TWO, 3: flop_three(16), 5: FLOP_TWO, 6: flop_three(16)}
-# the survey's FLOP-equivalent estimates (transcendentals as 25/25/10), kept for comparison
+# an earlier FLOP-equivalent estimate (transcendentals as 25/25/10), kept for comparison
 FLOP_PER_NODE_SURVEY = {1: 15.0, 2: 74.0, 3: 147.0, 5: 74.0, 6: 147.0}
 # Two-point nodes with y = l2/k^2 >= 38 have an exponential below double precision: their exact
 # value needs no expm1 and a plain reciprocal of Z l2 + m2 instead of the single-reciprocal form
@@ -516,7 +516,7 @@ def main():
                      "far_field_fraction": round(far, 4),
                      "flop_per_node_required": round(required, 2),
                      "frac_required": round(required * nodes * per_s, 4),
-                     # the survey's FLOP-equivalent estimate, for comparison
+                     # the earlier FLOP-equivalent estimate, for comparison
                      "flop_per_node_survey": FLOP_PER_NODE_SURVEY[family],
                      "frac_survey": round(FLOP_PER_NODE_SURVEY[family] * nodes * per_s, 4)},
     }
