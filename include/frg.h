@@ -228,8 +228,9 @@ typedef struct {
                               temperature the dressing multiplies the spatial momentum) in
                               float64 with a dressing table only (FRG_E_UNSUPPORTED for the
                               LPA families, complex frequencies and the float32 form,
-                              FRG_E_INVAL without a table), frg_integrate_batch and
-                              frg_integrate_multi (FRG_E_UNSUPPORTED from sessions); the caller
+                              FRG_E_INVAL without a table), frg_integrate_batch,
+                              frg_integrate_multi and sessions (there a host buffer, returned
+                              with out; a resident table counts as the table); the caller
                               owns the buffer.  Computed by a second kernel after the
                               integrals on the same stream.  Each point's parts are rounded to
                               units of 2^-62 of its largest part and added as integers, so

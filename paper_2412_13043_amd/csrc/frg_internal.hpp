@@ -115,9 +115,11 @@ hipError_t launch_multi(const ReqDev *reqs_dev, int fam, int prec, int reg, int 
                         double *contrib, unsigned *counters, unsigned *work_ctr, hipStream_t s,
                         bool clear_work = true);
 hipError_t launch_fill_zero_u32(unsigned *p, size_t n, hipStream_t s);
-// Vertex families (2, 3, 5), float64: jac[e * r.nZ + i] = dI_e/dZ_i for every point of r
-// (workgroups per point and 64-entry slice of the table; r needs a dressing table).
+// Vertex families (2, 3, 5, 6), float64: jac[e * r.nZ + i] = dI_e/dZ_i for every point of r
+// (one workgroup per point over every entry; r needs a dressing table).
 hipError_t launch_dz(const ReqDev &r, double *jac, hipStream_t s);
+// The same for points [e0, e0 + n_pts) only, their rows from jac on (row e - e0).
+hipError_t launch_dz_points(const ReqDev &r, double *jac, int e0, int n_pts, hipStream_t s);
 // radially chunked requests: radial sums after the integrand launch (no-op otherwise)
 hipError_t launch_finalize(const ReqDev &r, const double *contrib, unsigned *counters,
                            hipStream_t s);

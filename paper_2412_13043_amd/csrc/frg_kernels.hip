@@ -2037,13 +2037,15 @@ __device__ __forceinline__ void dz_row(const ReqDev &r, const Smem &sm, long lon
     if (kThree) single(i1, f1, -t.wg * (xw * (g1 * g1)) * l1 * (inner * uf));
 }
 
+// Workgroup b takes point e = e0 + b; its row is jac[(e - e0) * nZ ...].
 template <int FAM, int REG>
-__global__ void __launch_bounds__(64 * kDzMaxWaves) dz_kernel(ReqDev r, double *__restrict__ jac) {
+__global__ void __launch_bounds__(64 * kDzMaxWaves) dz_kernel(ReqDev r, double *__restrict__ jac,
+                                                             int e0) {
     extern __shared__ double2 lds_dyn[];
     __shared__ float f32c[2];
     __shared__ double wmax[kDzMaxWaves];
     Smem sm;
-    const int nZ = r.nZ, e = (int)blockIdx.x;
+    const int nZ = r.nZ, e = e0 + (int)blockIdx.x;
     const int lane = (int)threadIdx.x & (kWave - 1), wv = (int)threadIdx.x / kWave;
     const int nw = (int)blockDim.x / kWave, nt = (int)blockDim.x;
     const long long n_rows = (FAM == 3 || FAM == 6) ? (long long)r.n_q * r.n_x : r.n_q;
@@ -2106,22 +2108,27 @@ __global__ void __launch_bounds__(64 * kDzMaxWaves) dz_kernel(ReqDev r, double *
         const double v =
             exact ? ldexp(fma((double)(long long)acc_hi[j], 0x1p32, (double)acc_lo[j]), Eexp - 61)
                   : (P == 0.0 ? 0.0 : P);
-        jac[(long long)e * nZ + j] = r.pref * v;
+        jac[(long long)(e - e0) * nZ + j] = r.pref * v;
     }
 }
 
 template <int FAM>
-static void (*dz_for_reg(int reg))(ReqDev, double *) {
+static void (*dz_for_reg(int reg))(ReqDev, double *, int) {
     return reg == 1 ? dz_kernel<FAM, 1> : (reg == 2 ? dz_kernel<FAM, 2> : dz_kernel<FAM, 0>);
 }
 
 hipError_t launch_dz(const ReqDev &r, double *jac, hipStream_t s) {
-    if (r.n_ext <= 0) return hipSuccess;
+    return launch_dz_points(r, jac, 0, r.n_ext, s);
+}
+
+hipError_t launch_dz_points(const ReqDev &r, double *jac, int e0, int n_pts, hipStream_t s) {
+    if (n_pts <= 0) return hipSuccess;
+    if (e0 < 0 || e0 + n_pts > r.n_ext) return hipErrorInvalidValue;
     const bool three = r.family == 3 || r.family == 6;
     if ((r.family != 2 && r.family != 5 && !three) || r.precision != 0 || r.nZ < 2 ||
         r.n_x < 1 || (three && r.n_phi < 1))
         return hipErrorInvalidValue;
-    void (*fn)(ReqDev, double *) = r.family == 3   ? dz_for_reg<3>(r.reg)
+    void (*fn)(ReqDev, double *, int) = r.family == 3   ? dz_for_reg<3>(r.reg)
                                    : r.family == 6 ? dz_for_reg<6>(r.reg)
                                    : r.family == 5 ? dz_for_reg<5>(r.reg)
                                                    : dz_for_reg<2>(r.reg);
@@ -2133,9 +2140,9 @@ hipError_t launch_dz(const ReqDev &r, double *jac, hipStream_t s) {
         return hipGetLastError();
     const long long n_rows = three ? (long long)r.n_q * r.n_x : r.n_q;
     int waves = (int)std::min<long long>(kDzMaxWaves, (n_rows + kWave - 1) / kWave);
-    while (waves > 4 && (long long)r.n_ext * waves > 16LL * cus) waves /= 2;
+    while (waves > 4 && (long long)n_pts * waves > 16LL * cus) waves /= 2;
     waves = std::max(1, waves);
-    hipLaunchKernelGGL(fn, dim3(r.n_ext), dim3(kWave * waves), dz_lds_bytes(r.nZ), s, r, jac);
+    hipLaunchKernelGGL(fn, dim3(n_pts), dim3(kWave * waves), dz_lds_bytes(r.nZ), s, r, jac, e0);
     return hipGetLastError();
 }
 

@@ -74,6 +74,7 @@ struct SessReq {
     frg_batch host{};    // host pointers from the client
     int table_id = -1;
     int n_ext_vals = 0;  // doubles in ext
+    int dz_n = 0;        // dressing-table entries per point of the dout_dz block (0: none)
     // inputs as laid out in a launch block (byte offsets from the part's input area): ext, m2,
     // the request's own dressing table
     size_t in_ext = 0, in_m2 = 0, in_z = 0, in_bytes = 0;
@@ -285,8 +286,9 @@ static int out_arrays(const SessReq &r) {
            (r.host.dout_dm2 ? 1 : 0);
 }
 
+// a part's output area: the out_arrays arrays of its points, then their dout_dz rows
 static size_t part_out_bytes(const SessReq &r, int p0, int p1) {
-    return align256(out_arrays(r) * (size_t)(p1 - p0) * sizeof(double));
+    return align256((out_arrays(r) + (size_t)r.dz_n) * (size_t)(p1 - p0) * sizeof(double));
 }
 
 static size_t tables_bytes(size_t n_parts, size_t n_tiles) {
@@ -396,6 +398,13 @@ class HipExecutor : public Executor {
                                    sl.stream, false));
         FRG_HIP_CHECK(launch_multi_finalize(reqs_dev, tiles_dev + n_work, n_fin,
                                             (const double *)blk, (unsigned *)blk, sl.stream));
+        // dressing derivatives of the parts that ask for them, rows after the part's outputs
+        for (size_t i = 0; i < sl.parts.size(); ++i) {
+            const Part &pt = sl.parts[i];
+            if (!pt.r->dz_n) continue;
+            double *jac = (double *)(blk + pt.out) + (size_t)out_arrays(*pt.r) * (pt.p1 - pt.p0);
+            FRG_HIP_CHECK(launch_dz_points(rd[i], jac, pt.p0, pt.p1 - pt.p0, sl.stream));
+        }
         FRG_HIP_CHECK(hipMemcpyAsync(h + sl.out_begin, blk + sl.out_begin,
                                      sl.out_end - sl.out_begin, hipMemcpyDeviceToHost,
                                      sl.stream));
@@ -426,6 +435,9 @@ class HipExecutor : public Executor {
             if (r->host.dout_dm2)
                 std::memcpy(r->host.dout_dm2 + pt.p0, h + pt.out + (out_arrays(*r) - 1) * n * 8,
                             n * 8);
+            if (r->dz_n)
+                std::memcpy(r->host.dout_dz + (size_t)pt.p0 * r->dz_n,
+                            h + pt.out + out_arrays(*r) * n * 8, n * (size_t)r->dz_n * 8);
         }
     }
 
@@ -781,8 +793,8 @@ static void request_layout(SessReq &r) {
     r.contrib_bytes =
         r.chunked ? (size_t)plan_desc(d).n_q * n * 8 * (r.host.dout_dm2 || d.complex_freq ? 2 : 1)
                   : 0;
-    r.footprint = align256(r.in_bytes) + align256(r.slot_bytes) + align256(out_arrays(r) * n * 8) +
-                  align256(r.contrib_bytes);
+    r.footprint = align256(r.in_bytes) + align256(r.slot_bytes) +
+                  align256((out_arrays(r) + (size_t)r.dz_n) * n * 8) + align256(r.contrib_bytes);
 }
 
 static frg_status open_session(frg_context *ctx, const frg_session_config *cfg, bool fake,
@@ -886,22 +898,35 @@ frg_status frg_session_submit(frg_session *s, const frg_integral_desc *desc,
         set_error("null session or ticket");
         return FRG_E_INVAL;
     }
-    frg_status st = validate(desc, batch_host, false);
-    if (st != FRG_OK) return st;
-    if (batch_host->dout_dz) {
-        set_error("sessions do not return dressing derivatives (dout_dz must be NULL)");
-        return FRG_E_UNSUPPORTED;
+    if (!desc || !batch_host) {
+        set_error("null descriptor or batch");
+        return FRG_E_INVAL;
     }
-    auto r = std::make_unique<SessReq>();
-    r->desc = *desc;
-    r->host = *batch_host;
-    r->table_id = table_id;
+    // a request on a resident table is checked against that table (dout_dz needs a table)
+    frg_batch vb = *batch_host;
+    int dz_n = batch_host->Z.values ? batch_host->Z.n : 0;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (table_id >= (int)s->tables.size() || table_id < -1) {
             set_error("unknown table id %d", table_id);
             return FRG_E_INVAL;
         }
+        if (table_id >= 0) {
+            // the resident table replaces the batch's (launches use it)
+            const ResidentTable &t = *s->tables[table_id];
+            vb.Z = frg_log_table{(const double *)&t, t.n, t.x_min, t.x_max};  // not read
+            dz_n = t.n;
+        }
+    }
+    frg_status st = validate(desc, &vb, false);
+    if (st != FRG_OK) return st;
+    auto r = std::make_unique<SessReq>();
+    r->desc = *desc;
+    r->host = *batch_host;
+    r->table_id = table_id;
+    r->dz_n = batch_host->dout_dz ? dz_n : 0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) {
             set_error("session is closing");
             return FRG_E_CANCELLED;

@@ -343,16 +343,63 @@ def test_dz_unsupported_and_invalid(env):
     with pytest.raises(frg.FrgError) as ei:
         frg.frg_integrate_batch(ctx.handle, d2, b, 0)
     assert ei.value.status == frg.FRG_E_INVAL
-    # sessions do not return it
-    s = frg.frg_session_open(ctx.handle, frg.frg_session_config(1, 1 << 20, 20, 0))
-    hp, ho, hz, hj = np.ones(n), np.zeros(n), wl.dressing_table(1, 16), np.zeros(n * 16)
-    hb = frg.frg_batch(n, hp.ctypes.data, None, 0.5,
-                       frg.frg_log_table(hz.ctypes.data, 16, wl.Z_XMIN, wl.Z_XMAX),
-                       ho.ctypes.data, None, None, hj.ctypes.data)
-    with pytest.raises(frg.FrgError) as ei:
-        frg.frg_session_submit(s, d2, hb, -1)
-    assert ei.value.status == frg.FRG_E_UNSUPPORTED
-    frg.frg_session_close(s)
     with pytest.raises(ValueError):
         frg.make_batch(n, out, ext=ext, m2_scalar=0.5, Z=Z, dz=jac[:-1])
     torch.cuda.synchronize()
+
+
+def test_dz_through_sessions(env):
+    """Sessions return dI_e/dZ_i in host buffers: a two-point request with its own table, a
+    three-point one on a resident table, a finite-temperature three-point request above one
+    launch's node budget (split into parts, each part's rows after its outputs) and requests
+    without it beside them; values and blocks the bits frg_integrate_batch gives alone."""
+    frg, ctx, torch = env
+    rng = np.random.default_rng(321)
+    p = wl.momenta_log(200)
+    Z2, Z3 = wl.dressing_table(40, 64), wl.dressing_table(41, 48)
+    P, A, p01, p02, m2b, Zb = wl.three_point_ft_batch(1)
+    reqs = [
+        dict(desc=frg.make_desc(2, 24, 10.0, n_x=12), ext=p, m2=rng.uniform(0.1, 2.0, p.size),
+             Z=Z2, resident=False, dz=True),
+        dict(desc=frg.make_desc(3, 10, 10.0, n_x=6, n_phi=5),
+             ext=np.concatenate([p[:90], rng.uniform(0, math.pi, 90)]),
+             m2=rng.uniform(0.1, 2.0, 90), Z=Z3, resident=True, dz=True),
+        dict(desc=frg.make_desc(2, 16, 10.0, n_x=8), ext=p, m2=rng.uniform(0.1, 2.0, p.size),
+             Z=Z2, resident=False, dz=False),
+        # 1024 pairs x 32 radial x 47 frequencies x 16 x 16 = 3.9e8 nodes: in parts
+        dict(desc=frg.make_desc(6, 32, wl.THREE_QMAX, n_x=16, n_phi=16, T=wl.FT_T,
+                                freq_max=wl.FT_FREQ_MAX, n_tail=wl.FT_N_TAIL),
+             ext=np.concatenate([P, A, p01, p02]), m2=m2b[0], Z=Zb[0], resident=False, dz=True),
+    ]
+    s = frg.frg_session_open(ctx.handle, frg.frg_session_config(3, 1 << 30, 20, 0))
+    tickets = []
+    for r in reqs:
+        n = r["m2"].size
+        r["n"] = n
+        r["out"] = np.full(n, np.nan)
+        r["jac"] = np.full(n * r["Z"].size, np.nan) if r["dz"] else None
+        if r["resident"]:
+            tid = frg.frg_session_register_table(s, r["Z"].ctypes.data, r["Z"].size, wl.Z_XMIN,
+                                                 wl.Z_XMAX)
+            zt = frg.frg_log_table(None, 0, wl.Z_XMIN, wl.Z_XMAX)
+        else:
+            tid = -1
+            zt = frg.frg_log_table(r["Z"].ctypes.data, r["Z"].size, wl.Z_XMIN, wl.Z_XMAX)
+        b = frg.frg_batch(n, r["ext"].ctypes.data, r["m2"].ctypes.data, 0.0, zt,
+                          r["out"].ctypes.data, None, None,
+                          None if r["jac"] is None else r["jac"].ctypes.data)
+        tickets.append(frg.frg_session_submit(s, r["desc"], b, tid))
+    for t in tickets:
+        assert frg.frg_session_wait(s, t, 120000) == frg.FRG_OK
+    frg.frg_session_close(s)
+    for i, r in enumerate(reqs):
+        n, nz = r["n"], r["Z"].size
+        out = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        jac = torch.full((n * nz,), float("nan"), dtype=torch.float64, device="cuda") \
+            if r["dz"] else None
+        ctx.integrate(r["desc"], out, ext=_d(torch, r["ext"]), m2=_d(torch, r["m2"]),
+                      Z=_d(torch, r["Z"]), x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, dz=jac)
+        torch.cuda.synchronize()
+        assert np.array_equal(r["out"], out.cpu().numpy()), i
+        if r["dz"]:
+            assert np.array_equal(r["jac"], jac.cpu().numpy()), i

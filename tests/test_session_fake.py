@@ -170,7 +170,8 @@ def test_invalid_session_arguments():
 
 
 def test_derivative_outputs_at_submit():
-    # sessions return the mass derivative (float64) but not the dressing derivatives
+    # sessions return the mass derivative (float64) and the dressing derivatives (float64, with
+    # a table: the batch's or a resident one)
     s = frg.frg_session_open_fake(_cfg(), 1.0, 1.0)
     r = Req()
     Z = np.ones(16)
@@ -178,8 +179,21 @@ def test_derivative_outputs_at_submit():
     sink = np.zeros(r.batch.n_ext * 16)
     b = frg.frg_batch.from_buffer_copy(r.batch)
     b.dout_dz = sink.ctypes.data
+    t = frg.frg_session_submit(s, r.desc, b, -1)
+    assert frg.frg_session_wait(s, t, 10000) == frg.FRG_OK
+    tid = frg.frg_session_register_table(s, Z.ctypes.data, 16, 1e-3, 1e3)
+    b.Z = frg.frg_log_table(None, 0, 1e-3, 1e3)
+    t = frg.frg_session_submit(s, r.desc, b, tid)
+    assert frg.frg_session_wait(s, t, 10000) == frg.FRG_OK
+    # without any table: invalid; the float32 form: not implemented
     with pytest.raises(frg.FrgError) as ei:
         frg.frg_session_submit(s, r.desc, b, -1)
+    assert ei.value.status == frg.FRG_E_INVAL
+    b.Z = frg.frg_log_table(Z.ctypes.data, 16, 1e-3, 1e3)
+    d32 = frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 16, 10.0, n_x=8, precision=1,
+                        near_pole_tau=0.1)
+    with pytest.raises(frg.FrgError) as ei:
+        frg.frg_session_submit(s, d32, b, -1)
     assert ei.value.status == frg.FRG_E_UNSUPPORTED
     # dI/dm2 of the float32 form does not exist
     err = np.zeros(r.batch.n_ext)
