@@ -524,3 +524,71 @@ class Stepper:
             self.close()
         except Exception:
             pass
+
+
+class Session:
+    """A serving session (frg_session_*) with host buffers: submit() queues one request and
+    returns a ticket; its results are in the given numpy arrays once wait() returns FRG_OK.
+    The arrays of a request must stay alive until its ticket has ended.  `fake=(ns_per_node,
+    base_us)` opens the scheduling test double instead (no context, no device work)."""
+
+    def __init__(self, ctx=None, *, max_inflight=4, hbm_budget_bytes=0, poll_us=0,
+                 watchdog_ms=0, fake=None):
+        cfg = frg_session_config(max_inflight, hbm_budget_bytes, poll_us, watchdog_ms)
+        if fake is not None:
+            self.handle = frg_session_open_fake(cfg, float(fake[0]), float(fake[1]))
+        else:
+            self.handle = frg_session_open(ctx.handle, cfg)
+        self._keep = {}
+
+    def register_table(self, Z, x_min, x_max) -> int:
+        """Copies a dressing table (float64 numpy array) to the device for the session's
+        lifetime; returns its id for submit(table_id=...)."""
+        import numpy as np
+
+        z = np.ascontiguousarray(Z, dtype=np.float64)
+        return frg_session_register_table(self.handle, z.ctypes.data, int(z.size), x_min, x_max)
+
+    def submit(self, desc, out, *, ext=None, m2=None, m2_scalar=0.0, Z=None, x_min=1e-3,
+               x_max=1e3, table_id=-1, err_out=None, dout=None, dz=None) -> int:
+        """Queues one request on host arrays (contiguous float64 numpy arrays; out holds the
+        results, 2 values per point with complex frequencies)."""
+        arrs = [a for a in (ext, m2, Z, out, err_out, dout, dz) if a is not None]
+        for a in arrs:
+            if str(a.dtype) != "float64" or not a.flags["C_CONTIGUOUS"]:
+                raise ValueError("session buffers must be contiguous float64 numpy arrays")
+        n = int(out.size) // (2 if desc.complex_freq else 1)
+        ptr = lambda a: None if a is None else a.ctypes.data
+        zt = frg_log_table(ptr(Z), 0 if Z is None else int(Z.size), x_min, x_max)
+        b = frg_batch(n, ptr(ext), ptr(m2), m2_scalar, zt, ptr(out), ptr(err_out), ptr(dout),
+                      ptr(dz))
+        t = frg_session_submit(self.handle, desc, b, table_id)
+        self._keep[t] = arrs
+        return t
+
+    def wait(self, ticket, timeout_ms=-1) -> int:
+        st = frg_session_wait(self.handle, ticket, timeout_ms)
+        if st == FRG_OK:
+            self._keep.pop(ticket, None)
+        return st
+
+    def poll(self, ticket) -> bool:
+        done = frg_session_poll(self.handle, ticket)
+        if done:
+            self._keep.pop(ticket, None)
+        return done
+
+    def stats(self):
+        return frg_session_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            frg_session_close(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -224,3 +224,26 @@ def test_session_serving_sizes_mix(env):
         else:
             assert np.all(rel <= r["err"][idx]), (r["fam"], r["n"], rel.max())
             assert r["err"].max() < 1e-3
+
+
+def test_python_session_class(env):
+    # the Session wrapper on a real context: host arrays in, the bits of frg_integrate_batch out
+    frg, ctx, torch = env
+    rng = np.random.default_rng(77)
+    n = 120
+    p = 10 ** rng.uniform(-3, 2, n)
+    m2 = rng.uniform(0.1, 2.0, n)
+    Z = wl.dressing_table(77)
+    desc = frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 24, 10.0, n_x=12)
+    out = np.full(n, np.nan)
+    dout = np.full(n, np.nan)
+    with frg.Session(ctx, max_inflight=2, hbm_budget_bytes=64 << 20) as s:
+        t = s.submit(desc, out, ext=p, m2=m2, Z=Z, x_min=wl.Z_XMIN, x_max=wl.Z_XMAX, dout=dout)
+        assert s.wait(t, 60000) == frg.FRG_OK
+    o = torch.empty(n, dtype=torch.float64, device="cuda")
+    d = torch.empty(n, dtype=torch.float64, device="cuda")
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    ctx.integrate(desc, o, ext=dev(p), m2=dev(m2), Z=dev(Z), x_min=wl.Z_XMIN, x_max=wl.Z_XMAX,
+                  dout=d)
+    torch.cuda.synchronize()
+    assert np.array_equal(out, o.cpu().numpy()) and np.array_equal(dout, d.cpu().numpy())

@@ -444,3 +444,26 @@ def test_small_requests_go_first_and_large_ones_leave_a_slot():
     assert t_big >= 0.5
     assert max(lat) < 0.2
     frg.frg_session_close(s)
+
+
+def test_python_session_class_on_the_test_double():
+    # the Session wrapper: submit on host arrays, wait, stats, a resident table, context manager
+    import numpy as np
+
+    with frg.Session(max_inflight=2, hbm_budget_bytes=64 << 20, fake=(1.0, 5.0)) as s:
+        desc = frg.make_desc(frg.FRG_FAMILY_TWO_POINT, 8, 10.0, n_x=4)
+        Z = np.ones(16)
+        tid = s.register_table(Z, 1e-3, 1e3)
+        tickets, outs = [], []
+        for i in range(5):
+            n = 10 + i
+            out = np.zeros(n)
+            tickets.append(s.submit(desc, out, ext=np.linspace(0.1, 1.0, n), m2_scalar=0.5,
+                                    table_id=tid if i % 2 else -1, Z=None if i % 2 else Z))
+            outs.append(out)
+        for t in tickets:
+            assert s.wait(t, 10000) == frg.FRG_OK
+        st = s.stats()
+        assert st.completed == 5 and st.failed == 0
+        with pytest.raises(ValueError):
+            s.submit(desc, np.zeros(4, dtype=np.float32), ext=np.ones(4), m2_scalar=0.5)
