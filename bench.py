@@ -354,12 +354,22 @@ def oracle_timings(threads_max=16, seconds=1.5):
     three = lambda lo, hi: oracle.integrate(oracle.THREE_POINT, wl.THREE_NQ, wl.THREE_QMAX,
                                             n_x=wl.THREE_NX, n_phi=wl.THREE_NPHI,
                                             ext=(P[lo:hi], A[lo:hi]), m2=m3[lo:hi], Z=Z3)
+    # finite-temperature three-point: 1024 pairs x 47 frequencies x 64x32x16 per right-hand
+    # side (its first 256 pairs timed; one thread: 16 of them)
+    Pf, Af, f1, f2, mf, Zf = wl.three_point_ft_batch(1)
+    n_f = ft_frequency_count(wl.FT_T, wl.FT_FREQ_MAX, wl.FT_N_TAIL)
+    three_ft = lambda lo, hi: oracle.integrate_ft(
+        oracle.THREE_POINT_T, wl.THREE_NQ, wl.THREE_QMAX, n_x=wl.THREE_NX, n_phi=wl.THREE_NPHI,
+        T=wl.FT_T, freq_max=wl.FT_FREQ_MAX, n_tail=wl.FT_N_TAIL,
+        ext=(Pf[lo:hi], Af[lo:hi], f1[lo:hi], f2[lo:hi]), m2=mf[0][lo:hi], Z=Zf[0])
+    npp_ft = n_f * wl.THREE_NQ * wl.THREE_NX * wl.THREE_NPHI
     cases = {
         "lpa": (lpa, m2f.size, wl.LPA_NQ, wl.LPA_N_RHO * wl.LPA_NQ, 1.0),
         "two_point": (two, p.size, wl.TWO_NQ * wl.TWO_NX, p.size * wl.TWO_NQ * wl.TWO_NX, 1.0),
         # one thread: a 64-pair sample of the right-hand side
         "three_point": (three, P.size, wl.THREE_NQ * wl.THREE_NX * wl.THREE_NPHI,
                         P.size * wl.THREE_NQ * wl.THREE_NX * wl.THREE_NPHI, 64 / P.size),
+        "three_point_finite_T": (three_ft, 256, npp_ft, Pf.size * npp_ft, 16 / 256),
     }
     # the O(4) LPA flow of the stepper benchmark, integrated by the oracle's stepper
     import math
