@@ -401,3 +401,31 @@ def test_three_point_ft_rejections(env):
     # n_ext = 0 is a no-op
     empty = torch.zeros(0, dtype=torch.float64, device="cuda")
     ctx.integrate(desc, empty, ext=ext, m2_scalar=0.5)
+
+
+def test_three_point_ft_maximum_frequency_rule(env):
+    # n_q n_f at the limit FRG_MAX_FT_NODES: 64 radial nodes x 1023 frequencies, real and
+    # complex leg frequencies
+    frg = env[0]
+    T, lam, n_tail = 0.01, 2 * math.pi * 0.01 * 404.5, 107  # 809 explicit + 214 tail = 1023
+    n_f = len(oracle.matsubara_rule(0, T, lam, n_tail)[0])
+    assert n_f == 1023 and 64 * n_f <= frg.FRG_MAX_FT_NODES
+    p, al = np.array([0.3, 4.0]), np.array([0.5, 2.5])
+    f1, f2 = np.array([0.0, 2 * math.pi * T]), np.array([-2 * math.pi * T, 0.0])
+    kw = dict(n_x=2, n_phi=2, T=T, freq_max=lam, n_tail=n_tail)
+    desc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 64, 6.0, **kw)
+    got = _run(env, desc, 2, ext=np.concatenate([p, al, f1, f2]), m2_scalar=0.4)
+    ref = oracle.integrate_ft(oracle.THREE_POINT_T, 64, 6.0, ext=(p, al, f1, f2), m2_scalar=0.4,
+                              **kw)
+    assert _rel(got, ref) <= TOL
+    i1, i2 = np.array([-0.3, 0.3]), np.array([0.3, -0.3])
+    dc = frg.make_desc(frg.FRG_FAMILY_THREE_POINT_T, 64, 6.0, complex_freq=True, **kw)
+    frg_, ctx, torch = env
+    out = torch.full((4,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.integrate(dc, out, ext=_d(torch, np.concatenate([p, al, f1, f2, i1, i2])),
+                  m2_scalar=0.4)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    ref = oracle.integrate_ft_complex(oracle.THREE_POINT_T, 64, 6.0, ext=(p, al, f1, f2, i1, i2),
+                                      m2_scalar=0.4, **kw)
+    assert np.max(np.abs(o[:2] + 1j * o[2:] - ref) / np.abs(ref)) <= TOL
